@@ -1,0 +1,563 @@
+// Reference CPU implementation of the state-space PTA log-likelihood.
+//
+// TEST INFRASTRUCTURE ONLY. This file is the oracle that the GPU library is
+// checked against. Only tests, the smoke check and the CPU-baseline leg of the
+// benchmark may load it; the product path never does. It shares no code,
+// header or table with the HIP library.
+//
+// What it computes (paper: Summary; Statement of Need; Functionality, items
+// "State-space model construction" and "Kalman filter likelihood evaluation"):
+// each noise process is a linear SDE; the processes are stacked into one
+// linear-Gaussian state-space model; the Kalman filter (Kalman 1960) evaluates
+// the likelihood of the timing residuals by the prediction-error decomposition
+//     log L = sum_k -1/2 (ln 2 pi + ln S_k + e_k^2 / S_k).
+// The paper prints no equations, so the concrete model is the reading written
+// out in the design notes (spin random walk, OU red noise, OU common process
+// with Hellings-Downs coupling, EFAC/EQUAD white noise). The code follows the
+// textbook recursion literally: dense F, Q, H; the covariance update in Joseph
+// form with the matrix (I - K H) formed explicitly; symmetrisation afterwards.
+// No structure is exploited, by design.
+//
+// Everything is templated on the scalar type so that the same recursion runs
+// in complex arithmetic for complex-step derivatives (Squire & Trapp 1998).
+//
+// Parity unpinned: whether these model readings are the ones the paper's
+// software uses (the paper states no equations). All arithmetic below is
+// pinned by tests against the dense Gaussian likelihood, closed-form
+// discretisations, Hellings-Downs quadrature and filter invariants.
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+namespace {
+
+using cd = std::complex<double>;
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kLn10 = 2.30258509299404568402;
+constexpr double kYear = 31557600.0;  // Julian year, seconds
+
+enum { M_SPIN = 1, M_PSR4 = 2, M_JOINT = 3 };
+enum { S_NONPD = 1, S_NONFINITE = 2 };
+
+// ---------------------------------------------------------------- scalars
+inline double re(double x) { return x; }
+inline double re(const cd& z) { return z.real(); }
+
+// 10^x, written so that the complex version is analytic and its real part is
+// the double version.
+inline double p10(double x) { return std::pow(10.0, x); }
+inline cd p10(const cd& z) {
+  double r = std::pow(10.0, z.real());
+  double a = z.imag() * kLn10;
+  return cd(r * std::cos(a), r * std::sin(a));
+}
+inline double xexp(double x) { return std::exp(x); }
+inline cd xexp(const cd& z) { return std::exp(z); }
+inline double xlog(double x) { return std::log(x); }
+inline cd xlog(const cd& z) { return std::log(z); }
+// exp(z) - 1 without cancellation; complex version from
+// exp(x+iy) - 1 = (expm1(x) cos y - 2 sin^2(y/2)) + i exp(x) sin y.
+inline double xexpm1(double x) { return std::expm1(x); }
+inline cd xexpm1(const cd& z) {
+  double x = z.real(), y = z.imag();
+  double s = std::sin(0.5 * y);
+  return cd(std::expm1(x) * std::cos(y) - 2.0 * s * s, std::exp(x) * std::sin(y));
+}
+
+// ------------------------------------------------------------ dataset view
+struct DS {
+  int model = 0;
+  int P = 0;
+  const int64_t* off = nullptr;
+  const double* t = nullptr;
+  const double* y = nullptr;
+  const double* sig = nullptr;
+  const double* pos = nullptr;
+  double t_span = 0, s_r = 0, s_f = 0, sigma_s = 0;
+  // merged, time-ordered stream (joint model only)
+  std::vector<int64_t> m_idx;  // global TOA index
+  std::vector<int> m_psr;      // pulsar of each merged TOA
+  std::vector<double> hd;      // P x P Hellings-Downs matrix
+};
+
+int n_canon(const DS& d) { return d.model == M_SPIN ? 2 : 4 * d.P + 2; }
+
+// Hellings & Downs (1983) overlap reduction, earth term plus the pulsar term
+// on the diagonal: G_ab = 3/2 x ln x - x/4 + 1/2 + delta_ab/2,
+// x = (1 - cos zeta_ab)/2, with x ln x = 0 at x = 0.
+void hd_matrix(const double* pos, int P, double* G) {
+  for (int a = 0; a < P; ++a)
+    for (int b = 0; b < P; ++b) {
+      double c = pos[3 * a] * pos[3 * b] + pos[3 * a + 1] * pos[3 * b + 1] +
+                 pos[3 * a + 2] * pos[3 * b + 2];
+      // a pulsar's separation from itself is exactly zero
+      double x = a == b ? 0.0 : 0.5 * (1.0 - c);
+      if (x < 0) x = 0;
+      double xl = x > 0 ? x * std::log(x) : 0.0;
+      G[a * P + b] = 1.5 * xl - 0.25 * x + 0.5 + (a == b ? 0.5 : 0.0);
+    }
+}
+
+// Stationary variance of a one-state OU common process whose variance equals
+// that of the power-law residual spectrum
+//   PSD(f) = A^2 / (12 pi^2) f_yr^(gamma-3) f^(-gamma)
+// integrated from f_low = 1/T_span to infinity.
+template <class T>
+T common_variance(const T& log10A, const T& gam, double t_span) {
+  const double fyr = 1.0 / kYear;
+  T A = p10(log10A);
+  return A * A * xexp((gam - 3.0) * std::log(fyr)) *
+         xexp((gam - 1.0) * std::log(t_span)) /
+         (12.0 * kPi * kPi * (gam - 1.0));
+}
+
+// --------------------------------------------------------- model parameters
+template <class T>
+struct Psr {
+  T vr, gr, efac2, equad2;
+};
+template <class T>
+struct Par {
+  T ss2;  // spin random-walk diffusion, sigma_s^2
+  T vc;   // common OU stationary variance
+  double lam;  // common OU rate 2 pi / T_span
+  std::vector<Psr<T>> psr;
+};
+
+template <class T>
+Par<T> make_par(const DS& d, const T* c) {
+  Par<T> p;
+  p.lam = 2.0 * kPi / d.t_span;
+  if (d.model == M_SPIN) {
+    T ss = p10(c[0]);
+    p.ss2 = ss * ss;
+    p.vc = T(0.0);
+    p.psr.resize(1);
+    p.psr[0] = {T(0.0), T(1.0), c[1] * c[1], T(0.0)};
+    return p;
+  }
+  p.ss2 = T(d.sigma_s * d.sigma_s);
+  p.vc = common_variance(c[4 * d.P], c[4 * d.P + 1], d.t_span);
+  p.psr.resize(d.P);
+  for (int q = 0; q < d.P; ++q) {
+    const T* cq = c + 4 * q;
+    T sr = p10(cq[0]);
+    T gr = p10(cq[1]);
+    T eq = p10(cq[3]);
+    p.psr[q] = {sr * sr / (2.0 * gr), gr, cq[2] * cq[2], eq * eq};
+  }
+  return p;
+}
+
+// ------------------------------------------------------------ dense algebra
+template <class T>
+void mm(int n, const T* A, const T* B, T* C) {  // C = A B
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      T s = T(0.0);
+      for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+      C[i * n + j] = s;
+    }
+}
+template <class T>
+void mmt(int n, const T* A, const T* B, T* C) {  // C = A B^T
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      T s = T(0.0);
+      for (int k = 0; k < n; ++k) s += A[i * n + k] * B[j * n + k];
+      C[i * n + j] = s;
+    }
+}
+
+// Transition and process noise of one pulsar's 4-block [r, f, a, g] (or the
+// 2-block [r, f] of the spin-only model) over an interval dt, written into the
+// n x n matrices F, Q at offset o. Closed forms of Van Loan (1978):
+//   spin (dr = f dt, df = sigma_s dW): F = [[1,dt],[0,1]],
+//        Q = sigma_s^2 [[dt^3/3, dt^2/2],[dt^2/2, dt]];
+//   OU (dz = -g z dt + s dW, v = s^2/2g): F = e^{-g dt}, Q = v (1 - e^{-2 g dt}).
+template <class T>
+void block_fq(const DS& d, const Par<T>& p, int q, double dt, int n, int o,
+              T* F, T* Q) {
+  F[o * n + o] = T(1.0);
+  F[o * n + o + 1] = T(dt);
+  F[(o + 1) * n + o + 1] = T(1.0);
+  Q[o * n + o] = p.ss2 * (dt * dt * dt / 3.0);
+  Q[o * n + o + 1] = p.ss2 * (dt * dt / 2.0);
+  Q[(o + 1) * n + o] = p.ss2 * (dt * dt / 2.0);
+  Q[(o + 1) * n + o + 1] = p.ss2 * dt;
+  if (d.model == M_SPIN) return;
+  const Psr<T>& s = p.psr[q];
+  F[(o + 2) * n + o + 2] = xexp(-s.gr * dt);
+  Q[(o + 2) * n + o + 2] = s.vr * (-xexpm1(-2.0 * s.gr * dt));
+  F[(o + 3) * n + o + 3] = T(std::exp(-p.lam * dt));
+  if (d.model == M_PSR4)
+    Q[(o + 3) * n + o + 3] = p.vc * (-std::expm1(-2.0 * p.lam * dt));
+}
+
+// Full F, Q of the filter that processes pulsar q (per-pulsar models) or the
+// joint state (joint model).
+template <class T>
+void model_fq(const DS& d, const Par<T>& p, int q, double dt, int n, T* F,
+              T* Q) {
+  std::fill(F, F + n * n, T(0.0));
+  std::fill(Q, Q + n * n, T(0.0));
+  if (d.model != M_JOINT) {
+    block_fq(d, p, q, dt, n, 0, F, Q);
+    return;
+  }
+  for (int a = 0; a < d.P; ++a) block_fq(d, p, a, dt, n, 4 * a, F, Q);
+  // common process: process-noise cross-covariance G_ab * q_c(dt)
+  double qc_unit = -std::expm1(-2.0 * p.lam * dt);
+  for (int a = 0; a < d.P; ++a)
+    for (int b = 0; b < d.P; ++b)
+      Q[(4 * a + 3) * n + 4 * b + 3] = p.vc * (d.hd[a * d.P + b] * qc_unit);
+}
+
+template <class T>
+void model_p0(const DS& d, const Par<T>& p, int q, int n, T* P0) {
+  std::fill(P0, P0 + n * n, T(0.0));
+  auto blk = [&](int a, int o) {
+    P0[o * n + o] = T(d.s_r * d.s_r);
+    P0[(o + 1) * n + o + 1] = T(d.s_f * d.s_f);
+    if (d.model == M_SPIN) return;
+    P0[(o + 2) * n + o + 2] = p.psr[a].vr;
+    if (d.model == M_PSR4) P0[(o + 3) * n + o + 3] = p.vc;
+  };
+  if (d.model != M_JOINT) {
+    blk(q, 0);
+    return;
+  }
+  for (int a = 0; a < d.P; ++a) blk(a, 4 * a);
+  for (int a = 0; a < d.P; ++a)
+    for (int b = 0; b < d.P; ++b)
+      P0[(4 * a + 3) * n + 4 * b + 3] = p.vc * d.hd[a * d.P + b];
+}
+
+// Optional per-step record (double runs only): predicted x, P, innovation,
+// its variance and the filtered x, P after each TOA.
+struct Trace {
+  double* e = nullptr;      // [N]
+  double* S = nullptr;      // [N]
+  double* x = nullptr;      // [N*n] filtered
+  double* Pf = nullptr;     // [N*n*n] filtered
+  double* Pp = nullptr;     // [N*n*n] predicted
+};
+
+template <class T>
+void put(double* dst, const T* src, int m) {
+  for (int i = 0; i < m; ++i) dst[i] = re(src[i]);
+}
+
+// The Kalman recursion over one time-ordered stream. Returns the
+// log-likelihood; on failure returns -inf and sets *status.
+// psr_of(k) gives the pulsar of stream element k, idx(k) the TOA index.
+template <class T, class IdxF, class PsrF>
+T kalman(const DS& d, const Par<T>& p, int q_fixed, int64_t N, IdxF idx,
+         PsrF psr_of, int32_t* status, Trace* tr) {
+  const int n = d.model == M_SPIN ? 2 : (d.model == M_PSR4 ? 4 : 4 * d.P);
+  std::vector<T> x(n, T(0.0)), xp(n), P(n * n), Pp(n * n), F(n * n), Q(n * n),
+      tmp(n * n), A(n * n), H(n), u(n), K(n);
+  model_p0(d, p, q_fixed, n, P.data());
+  T ll = T(0.0);
+  double t_prev = 0.0;  // the prior holds at the dataset epoch t0 = 0
+  const double ln2pi = std::log(2.0 * kPi);
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t j = idx(k);
+    const int q = psr_of(k);
+    const double dt = d.t[j] - t_prev;
+    t_prev = d.t[j];
+    // 1. discretise
+    model_fq(d, p, q_fixed, dt, n, F.data(), Q.data());
+    // 2. x- = F x
+    for (int i = 0; i < n; ++i) {
+      T s = T(0.0);
+      for (int m = 0; m < n; ++m) s += F[i * n + m] * x[m];
+      xp[i] = s;
+    }
+    // 3. P- = F P F^T + Q
+    mm(n, F.data(), P.data(), tmp.data());
+    mmt(n, tmp.data(), F.data(), Pp.data());
+    for (int i = 0; i < n * n; ++i) Pp[i] += Q[i];
+    // measurement row: residual = r + a + g of pulsar q
+    std::fill(H.begin(), H.end(), T(0.0));
+    const int o = d.model == M_JOINT ? 4 * q : 0;
+    H[o] = T(1.0);
+    if (d.model != M_SPIN) {
+      H[o + 2] = T(1.0);
+      H[o + 3] = T(1.0);
+    }
+    const Psr<T>& ps = p.psr[d.model == M_JOINT ? q : q_fixed];
+    const double sk = d.sig[j];
+    T R = ps.efac2 * (sk * sk) + ps.equad2;
+    // 4. innovation e = y - H x-
+    T hx = T(0.0);
+    for (int i = 0; i < n; ++i) hx += H[i] * xp[i];
+    T e = d.y[j] - hx;
+    // 5. u = P- H^T
+    for (int i = 0; i < n; ++i) {
+      T s = T(0.0);
+      for (int m = 0; m < n; ++m) s += Pp[i * n + m] * H[m];
+      u[i] = s;
+    }
+    // 6. S = H u + R
+    T S = R;
+    for (int i = 0; i < n; ++i) S += H[i] * u[i];
+    if (!std::isfinite(re(S)) || !std::isfinite(re(e))) {
+      *status = S_NONFINITE;
+      return T(-std::numeric_limits<double>::infinity());
+    }
+    if (!(re(S) > 0.0)) {
+      *status = S_NONPD;
+      return T(-std::numeric_limits<double>::infinity());
+    }
+    // 7. K = u / S ; 8. x = x- + K e
+    for (int i = 0; i < n; ++i) {
+      K[i] = u[i] / S;
+      x[i] = xp[i] + K[i] * e;
+    }
+    // 9. Joseph form: P = (I - K H) P- (I - K H)^T + K R K^T
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m)
+        A[i * n + m] = (i == m ? T(1.0) : T(0.0)) - K[i] * H[m];
+    mm(n, A.data(), Pp.data(), tmp.data());
+    mmt(n, tmp.data(), A.data(), P.data());
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m) P[i * n + m] += K[i] * R * K[m];
+    // 10. symmetrise
+    for (int i = 0; i < n; ++i)
+      for (int m = i + 1; m < n; ++m) {
+        T s = 0.5 * (P[i * n + m] + P[m * n + i]);
+        P[i * n + m] = s;
+        P[m * n + i] = s;
+      }
+    // 11. accumulate the prediction-error decomposition
+    ll += -0.5 * (ln2pi + xlog(S) + e * e / S);
+    if (tr) {
+      tr->e[k] = re(e);
+      tr->S[k] = re(S);
+      put(tr->x + k * n, x.data(), n);
+      put(tr->Pf + k * n * n, P.data(), n * n);
+      put(tr->Pp + k * n * n, Pp.data(), n * n);
+    }
+  }
+  if (!std::isfinite(re(ll))) {
+    *status = S_NONFINITE;
+    return T(-std::numeric_limits<double>::infinity());
+  }
+  return ll;
+}
+
+template <class T>
+bool finite_params(const T* c, int C) {
+  for (int i = 0; i < C; ++i)
+    if (!std::isfinite(re(c[i]))) return false;
+  return true;
+}
+
+// log-likelihood of one pulsar (per-pulsar models)
+template <class T>
+T psr_loglike(const DS& d, const Par<T>& p, int q, int32_t* st, Trace* tr) {
+  const int64_t b = d.off[q], N = d.off[q + 1] - d.off[q];
+  return kalman<T>(d, p, q, N, [b](int64_t k) { return b + k; },
+                   [q](int64_t) { return q; }, st, tr);
+}
+
+template <class T>
+T joint_loglike(const DS& d, const Par<T>& p, int32_t* st, Trace* tr) {
+  const int64_t N = (int64_t)d.m_idx.size();
+  return kalman<T>(d, p, 0, N, [&d](int64_t k) { return d.m_idx[k]; },
+                   [&d](int64_t k) { return d.m_psr[k]; }, st, tr);
+}
+
+// total log-likelihood of one sample (canonical parameter vector c)
+template <class T>
+T sample_loglike(const DS& d, const T* c, int32_t* st, T* per_psr) {
+  *st = 0;
+  if (!finite_params(c, n_canon(d))) {
+    *st = S_NONFINITE;
+    return T(-std::numeric_limits<double>::infinity());
+  }
+  Par<T> p = make_par<T>(d, c);
+  if (d.model == M_JOINT) return joint_loglike<T>(d, p, st, nullptr);
+  T tot = T(0.0);
+  for (int q = 0; q < d.P; ++q) {
+    int32_t s = 0;
+    T l = psr_loglike<T>(d, p, q, &s, nullptr);
+    if (per_psr) per_psr[q] = l;
+    if (s && !*st) *st = s;
+    tot += l;
+  }
+  if (*st) return T(-std::numeric_limits<double>::infinity());
+  return tot;
+}
+
+void build_merged(DS& d) {
+  if (d.model != M_JOINT) return;
+  const int64_t N = d.off[d.P];
+  d.m_idx.resize(N);
+  d.m_psr.resize(N);
+  std::vector<std::pair<int64_t, int>> v;
+  v.reserve(N);
+  for (int q = 0; q < d.P; ++q)
+    for (int64_t j = d.off[q]; j < d.off[q + 1]; ++j) v.push_back({j, q});
+  std::stable_sort(v.begin(), v.end(), [&d](const auto& a, const auto& b) {
+    if (d.t[a.first] != d.t[b.first]) return d.t[a.first] < d.t[b.first];
+    return a.second < b.second;
+  });
+  for (int64_t k = 0; k < N; ++k) {
+    d.m_idx[k] = v[k].first;
+    d.m_psr[k] = v[k].second;
+  }
+  d.hd.resize((size_t)d.P * d.P);
+  hd_matrix(d.pos, d.P, d.hd.data());
+}
+
+template <class F>
+void parallel_for(int64_t S, int nthreads, F f) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > S) nthreads = (int)std::max<int64_t>(S, 1);
+  std::vector<std::thread> th;
+  for (int w = 0; w < nthreads; ++w)
+    th.emplace_back([=]() {
+      for (int64_t s = w; s < S; s += nthreads) f(s);
+    });
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+// ====================================================================== C API
+extern "C" {
+
+// Dataset description. t, y, sigma hold each pulsar's TOAs contiguously
+// (CSR offsets off[P+1]) in ascending time; seconds since the epoch t0 = 0.
+typedef struct {
+  int32_t model;  // 1 spin-only [r,f]; 2 per-pulsar [r,f,a,g]; 3 joint HD
+  int32_t n_psr;
+  const int64_t* off;
+  const double* t;
+  const double* y;
+  const double* sigma;
+  const double* pos;  // [n_psr*3] unit vectors (joint model), may be NULL
+  double t_span;      // seconds
+  double s_r, s_f;    // prior std of the spin offset r (s) and f
+  double sigma_s;     // spin random-walk amplitude (per-pulsar models 2/3)
+} oracle_ds;
+
+static DS make_ds(const oracle_ds* o) {
+  DS d;
+  d.model = o->model;
+  d.P = o->n_psr;
+  d.off = o->off;
+  d.t = o->t;
+  d.y = o->y;
+  d.sig = o->sigma;
+  d.pos = o->pos;
+  d.t_span = o->t_span;
+  d.s_r = o->s_r;
+  d.s_f = o->s_f;
+  d.sigma_s = o->sigma_s;
+  build_merged(d);
+  return d;
+}
+
+int oracle_n_canon(const oracle_ds* o) {
+  return o->model == M_SPIN ? 2 : 4 * o->n_psr + 2;
+}
+
+// logL for S samples of canonical parameters c [S x C]. per_psr (nullable)
+// receives [S x P] per-pulsar terms for the per-pulsar models.
+int oracle_loglike(const oracle_ds* o, const double* c, int64_t S, double* out,
+                   int32_t* status, double* per_psr, int nthreads) {
+  DS d = make_ds(o);
+  const int C = n_canon(d);
+  parallel_for(S, nthreads, [&](int64_t s) {
+    int32_t st = 0;
+    out[s] = sample_loglike<double>(d, c + s * C, &st,
+                                    per_psr ? per_psr + s * d.P : nullptr);
+    if (status) status[s] = st;
+  });
+  return 0;
+}
+
+// Complex-step derivatives d logL / d c_j for the canonical indices which[nw],
+// step h: Im logL(c + i h e_j) / h. Parameters of one pulsar enter only that
+// pulsar's term in the per-pulsar models, so only that term is run.
+int oracle_grad_cs(const oracle_ds* o, const double* c, int64_t S,
+                   const int32_t* which, int nw, double h, double* grad,
+                   int nthreads) {
+  DS d = make_ds(o);
+  const int C = n_canon(d);
+  parallel_for(S, nthreads, [&](int64_t s) {
+    std::vector<cd> cc(C);
+    for (int j = 0; j < nw; ++j) {
+      for (int i = 0; i < C; ++i) cc[i] = cd(c[s * C + i], 0.0);
+      const int w = which[j];
+      cc[w] += cd(0.0, h);
+      int32_t st = 0;
+      cd l;
+      if (d.model == M_PSR4 && w < 4 * d.P) {
+        Par<cd> p = make_par<cd>(d, cc.data());
+        l = psr_loglike<cd>(d, p, w / 4, &st, nullptr);
+      } else {
+        l = sample_loglike<cd>(d, cc.data(), &st, nullptr);
+      }
+      grad[s * nw + j] = st ? 0.0 : l.imag() / h;
+    }
+  });
+  return 0;
+}
+
+// Per-step trace of one filter (pulsar q, or the joint stream when q < 0)
+// for one canonical vector. Arrays sized by the stream length N and the
+// state dimension n of that filter.
+int oracle_trace(const oracle_ds* o, const double* c, int q, double* e,
+                 double* S, double* x, double* Pf, double* Pp, double* ll,
+                 int32_t* status) {
+  DS d = make_ds(o);
+  Par<double> p = make_par<double>(d, c);
+  Trace tr{e, S, x, Pf, Pp};
+  int32_t st = 0;
+  if (d.model == M_JOINT)
+    *ll = joint_loglike<double>(d, p, &st, &tr);
+  else
+    *ll = psr_loglike<double>(d, p, q, &st, &tr);
+  *status = st;
+  return 0;
+}
+
+// Merged stream order of the joint model: global TOA index and pulsar.
+int oracle_merged(const oracle_ds* o, int64_t* idx, int32_t* psr) {
+  DS d = make_ds(o);
+  for (size_t k = 0; k < d.m_idx.size(); ++k) {
+    idx[k] = d.m_idx[k];
+    psr[k] = d.m_psr[k];
+  }
+  return 0;
+}
+
+// F(dt), Q(dt) and the prior P0 of the filter for pulsar q (or joint).
+int oracle_model_mats(const oracle_ds* o, const double* c, int q, double dt,
+                      double* F, double* Q, double* P0) {
+  DS d = make_ds(o);
+  Par<double> p = make_par<double>(d, c);
+  const int n = d.model == M_SPIN ? 2 : (d.model == M_PSR4 ? 4 : 4 * d.P);
+  model_fq(d, p, q, dt, n, F, Q);
+  model_p0(d, p, q, n, P0);
+  return n;
+}
+
+void oracle_hd(const double* pos, int P, double* G) { hd_matrix(pos, P, G); }
+
+double oracle_common_variance(double log10A, double gam, double t_span) {
+  return common_variance<double>(log10A, gam, t_span);
+}
+
+}  // extern "C"
