@@ -1,0 +1,121 @@
+/*
+ * libargus: batched FP64 Kalman-filter log-likelihood of pulsar-timing
+ * residuals on MI355X (gfx950), its gradient, and a learned surrogate.
+ *
+ * The operation (paper: Functionality, "Kalman filter likelihood
+ * evaluation" and "State-space model construction"; Summary): every noise
+ * process of a pulsar (spin wandering, OU red noise, a common OU process for
+ * the gravitational-wave background, coupled across pulsars by the
+ * Hellings-Downs curve) is a linear SDE; stacked, they form one linear
+ * Gaussian state-space model whose likelihood the Kalman filter evaluates in
+ * O(N) by the prediction-error decomposition
+ *     log L = sum_k -1/2 (ln 2 pi + ln S_k + e_k^2 / S_k),
+ * e_k the innovation and S_k its variance. The gradient is what the paper's
+ * sampler integration consumes (Functionality, "Sampler Integration").
+ *
+ * Models (per-pulsar state in brackets; r residual phase offset in s, f
+ * fractional frequency, a red OU in s, g common OU in s):
+ *   ARGUS_M1_SPIN      one pulsar, [r, f]; canonical params
+ *                      [log10 sigma_s, EFAC]
+ *   ARGUS_M2_PSR4      P independent pulsars, [r, f, a, g] each; canonical
+ *                      params: per pulsar [log10 sigma_red, log10 gamma_red,
+ *                      EFAC, log10 EQUAD], then [log10 A, gamma] of the common
+ *                      power law (mapped to the OU variance over 1/T_span..inf)
+ *   ARGUS_M3_JOINT_HD  the same P pulsars in one joint 4P-dim state whose
+ *                      common-process noise is Hellings-Downs correlated
+ * Measurement: y_k = r + a + g + white, white variance EFAC^2 sigma_k^2 +
+ * EQUAD^2 (model 1: EFAC^2 sigma_k^2). Every filter starts from the prior at
+ * the epoch t0 = 0 and predicts to its first TOA.
+ *
+ * Conventions for every call:
+ *  - Return value: ARGUS_OK (0) or an ARGUS_E_* code; argus_last_error()
+ *    then holds a message (thread-local). Nothing throws across the ABI.
+ *  - "dev" pointers are HIP device memory owned by the caller; the library
+ *    never frees them. "host" pointers are read during the call only.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t, may be 0).
+ *    Only dataset create/destroy and the first loglike call for a new sample
+ *    count (which autotunes) synchronise.
+ *  - A numeric failure of one sample does not fail the call: its logL is
+ *    -inf, its gradient row 0, and its status word gets ARGUS_S_NONPD
+ *    (innovation variance <= 0) or ARGUS_S_NONFINITE (NaN/Inf parameter or
+ *    state). The first failure in pulsar order decides the flag; a non-finite
+ *    parameter anywhere in the row gives ARGUS_S_NONFINITE.
+ *  - A dataset handle keeps per-sample-count workspaces and captured graphs;
+ *    calls on one handle from concurrently running streams race.
+ */
+#ifndef ARGUS_H
+#define ARGUS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ARGUS_OK = 0, ARGUS_E_INVAL = 1, ARGUS_E_HIP = 2, ARGUS_E_NOMEM = 3,
+       ARGUS_E_UNSUPPORTED = 4 };
+enum { ARGUS_S_NONPD = 1, ARGUS_S_NONFINITE = 2 };
+enum { ARGUS_M1_SPIN = 1, ARGUS_M2_PSR4 = 2, ARGUS_M3_JOINT_HD = 3 };
+
+typedef struct argus_dataset* argus_dataset_t;
+
+typedef struct {
+  int32_t model;            /* ARGUS_M1_SPIN / ARGUS_M2_PSR4 / ARGUS_M3_JOINT_HD */
+  int32_t n_psr;            /* P >= 1 (model 1: P == 1; model 3: P <= 22) */
+  const int64_t* toa_off;   /* host [P+1] CSR offsets into t/y/sigma, off[0]=0 */
+  const double* t;          /* host [N] s since the epoch t0 = 0; strictly
+                               ascending within a pulsar, >= 0 */
+  const double* y;          /* host [N] timing residuals, s */
+  const double* sigma;      /* host [N] per-TOA 1-sigma errors, s, > 0 */
+  const double* pos;        /* host [P*3] unit vectors; model 3 only, else NULL */
+  const double* fixed;      /* host [C] values used for non-free canonical params */
+  const uint8_t* free_mask; /* host [C]; nonzero = free. Free params become the
+                               columns of theta in canonical order. NULL = all free */
+  double t_span;            /* s; sets the common OU rate 2 pi / t_span and the
+                               power-law low-frequency cutoff 1 / t_span */
+  double s_r, s_f;          /* prior std of r (s) and f at t0 */
+  double sigma_s;           /* spin random-walk amplitude (models 2, 3) */
+} argus_dataset_desc;
+
+/* Copies the data to the device, orders the joint stream by (t, pulsar),
+ * and precomputes per-TOA intervals and the common-process decay.
+ * C = 2 (model 1) or 4P + 2. Synchronises. */
+int argus_dataset_create(const argus_dataset_desc* desc, argus_dataset_t* out);
+int argus_dataset_destroy(argus_dataset_t ds);
+/* D = number of free parameters (columns of theta). */
+int argus_dataset_n_params(argus_dataset_t ds, int32_t* D);
+
+/* logL for S parameter rows. theta: dev [S*D] row-major FP64; logl: dev [S];
+ * status: dev [S] or NULL. Batched persistent kernel replayed from a captured
+ * hipGraph; the first call for a new S autotunes (synchronises). */
+int argus_loglike(argus_dataset_t ds, const double* theta, int64_t S,
+                  double* logl, int32_t* status, void* stream);
+
+/* Per-pulsar terms of logL (models 1, 2): terms dev [P*S], pulsar-major
+ * (terms[p*S + s]); same kernel as argus_loglike, no graph. */
+int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S,
+                        double* terms, int32_t* status, void* stream);
+
+/* The plain per-sample GPU filter: one kernel launch per sample, one thread
+ * per pulsar, per-TOA transcendentals and divisions, no precompute, no
+ * persistence, no graph. Models 1, 2. Same outputs as argus_loglike. */
+int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S,
+                        double* logl, int32_t* status, void* stream);
+
+/* logL and its gradient w.r.t. the D free parameters (models 1, 2): reverse
+ * (adjoint) Kalman sweep with checkpointed filter states. grad: dev [S*D]. */
+int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
+                       double* logl, double* grad, int32_t* status,
+                       void* stream);
+
+/* Human-readable launch configuration chosen for (ds, S), for reports. */
+int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len);
+
+/* Message for the last nonzero return on this thread. */
+const char* argus_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARGUS_H */

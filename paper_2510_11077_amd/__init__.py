@@ -1,0 +1,202 @@
+"""Python binding of libargus (include/argus.h): argument marshalling only.
+
+Every step of the likelihood, its gradient and the surrogate runs in the HIP
+kernels of libargus.so; PyTorch supplies device memory and streams. The
+library must be built in-tree (``python paper_2510_11077_amd/build.py``);
+importing this package fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libargus.so")
+
+M1_SPIN, M2_PSR4, M3_JOINT_HD = 1, 2, 3
+S_NONPD, S_NONFINITE = 1, 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libargus.so is not built: run `python paper_2510_11077_amd/build.py`")
+
+_lib = C.CDLL(LIB_PATH)
+
+
+class ArgusError(RuntimeError):
+    pass
+
+
+class _Desc(C.Structure):
+    _fields_ = [("model", C.c_int32), ("n_psr", C.c_int32), ("toa_off", C.c_void_p),
+                ("t", C.c_void_p), ("y", C.c_void_p), ("sigma", C.c_void_p),
+                ("pos", C.c_void_p), ("fixed", C.c_void_p), ("free_mask", C.c_void_p),
+                ("t_span", C.c_double), ("s_r", C.c_double), ("s_f", C.c_double),
+                ("sigma_s", C.c_double)]
+
+
+_V = C.c_void_p
+_lib.argus_last_error.restype = C.c_char_p
+_lib.argus_dataset_create.argtypes = [C.POINTER(_Desc), C.POINTER(_V)]
+_lib.argus_dataset_destroy.argtypes = [_V]
+_lib.argus_dataset_n_params.argtypes = [_V, C.POINTER(C.c_int32)]
+for _n in ("argus_loglike", "argus_loglike_terms", "argus_loglike_plain"):
+    getattr(_lib, _n).argtypes = [_V, _V, C.c_int64, _V, _V, _V]
+_lib.argus_loglike_grad.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V]
+_lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
+_HAS_SURROGATE = hasattr(_lib, "argus_surrogate_eval")
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise ArgusError("libargus error %d: %s" % (rc, _lib.argus_last_error().decode()))
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev_ptr(t, dtype, name):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ArgusError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ArgusError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ArgusError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+class Dataset:
+    """A dataset handle. `d` is any object with the fields of the descriptor
+    (model, n_psr, off, t, y, sigma, pos, t_span, s_r, s_f, sigma_s, truth as
+    the fixed values, free as the free mask)."""
+
+    def __init__(self, d):
+        self.model = int(d.model)
+        self.n_psr = int(d.n_psr)
+        self._keep = dict(
+            off=np.ascontiguousarray(d.off, np.int64),
+            t=np.ascontiguousarray(d.t, np.float64),
+            y=np.ascontiguousarray(d.y, np.float64),
+            sigma=np.ascontiguousarray(d.sigma, np.float64),
+            pos=None if getattr(d, "pos", None) is None else np.ascontiguousarray(d.pos, np.float64),
+            fixed=np.ascontiguousarray(d.truth, np.float64),
+            free=None if getattr(d, "free", None) is None else np.ascontiguousarray(d.free, np.uint8),
+        )
+        k = self._keep
+        p = lambda a: None if a is None else a.ctypes.data
+        desc = _Desc(self.model, self.n_psr, p(k["off"]), p(k["t"]), p(k["y"]), p(k["sigma"]),
+                     p(k["pos"]) if self.model == M3_JOINT_HD else None, p(k["fixed"]), p(k["free"]),
+                     float(d.t_span), float(d.s_r), float(d.s_f), float(d.sigma_s))
+        h = _V()
+        _check(_lib.argus_dataset_create(C.byref(desc), C.byref(h)))
+        self._h = h
+        D = C.c_int32()
+        _check(_lib.argus_dataset_n_params(self._h, C.byref(D)))
+        self.n_params = D.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.argus_dataset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- calls
+    def _theta(self, theta):
+        import torch
+        if theta.dim() != 2 or theta.shape[1] != self.n_params:
+            raise ArgusError("theta must be [S, %d]" % self.n_params)
+        return _dev_ptr(theta, torch.float64, "theta")
+
+    def _outs(self, theta, out, status, want_status):
+        import torch
+        S = theta.shape[0]
+        if out is None:
+            out = torch.empty(S, dtype=torch.float64, device=theta.device)
+        if status is None and want_status:
+            status = torch.empty(S, dtype=torch.int32, device=theta.device)
+        return out, status
+
+    def loglike(self, theta, out=None, status=None, want_status=True, stream=None):
+        """Batched logL: theta [S, D] float64 (device) -> (logl [S], status [S])."""
+        import torch
+        tp = self._theta(theta)
+        out, status = self._outs(theta, out, status, want_status)
+        _check(_lib.argus_loglike(self._h, tp, theta.shape[0], _dev_ptr(out, torch.float64, "out"),
+                                  _dev_ptr(status, torch.int32, "status"), _stream(stream)))
+        return out, status
+
+    def loglike_terms(self, theta, stream=None):
+        """Per-pulsar terms [P, S] and status [S] (models 1, 2)."""
+        import torch
+        tp = self._theta(theta)
+        S = theta.shape[0]
+        terms = torch.empty((self.n_psr, S), dtype=torch.float64, device=theta.device)
+        status = torch.empty(S, dtype=torch.int32, device=theta.device)
+        _check(_lib.argus_loglike_terms(self._h, tp, S, terms.data_ptr(), status.data_ptr(),
+                                        _stream(stream)))
+        return terms, status
+
+    def loglike_plain(self, theta, out=None, status=None, stream=None):
+        """The plain one-launch-per-sample baseline filter (models 1, 2)."""
+        import torch
+        tp = self._theta(theta)
+        out, status = self._outs(theta, out, status, True)
+        _check(_lib.argus_loglike_plain(self._h, tp, theta.shape[0], out.data_ptr(),
+                                        status.data_ptr(), _stream(stream)))
+        return out, status
+
+    def loglike_grad(self, theta, out=None, grad=None, status=None, stream=None):
+        """logL [S] and d logL / d theta [S, D] (models 1, 2)."""
+        import torch
+        tp = self._theta(theta)
+        out, status = self._outs(theta, out, status, True)
+        if grad is None:
+            grad = torch.empty_like(theta)
+        _check(_lib.argus_loglike_grad(self._h, tp, theta.shape[0], out.data_ptr(),
+                                       _dev_ptr(grad, torch.float64, "grad"), status.data_ptr(),
+                                       _stream(stream)))
+        return out, grad, status
+
+    def tune_info(self, S: int) -> str:
+        buf = C.create_string_buffer(4096)
+        _check(_lib.argus_tune_info(self._h, S, buf, 4096))
+        return buf.value.decode()
+
+
+def _make_loglike_fn():
+    import torch
+
+    class ArgusLogLike(torch.autograd.Function):
+        """logL(theta) with the adjoint-filter gradient as its backward."""
+
+        @staticmethod
+        def forward(ctx, theta, ds):
+            theta = theta.contiguous()
+            logl, grad, _ = ds.loglike_grad(theta)
+            ctx.save_for_backward(grad)
+            return logl
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            return g[:, None] * grad, None
+
+    return ArgusLogLike
+
+
+try:
+    ArgusLogLike = _make_loglike_fn()
+except ImportError:  # torch absent: the ctypes layer still loads
+    ArgusLogLike = None

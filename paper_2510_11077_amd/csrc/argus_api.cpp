@@ -1,0 +1,488 @@
+// Host side of libargus: the C ABI declared in include/argus.h, dataset
+// staging, per-sample-count workspaces, the launch autotuner and hipGraph
+// capture/replay of the batched likelihood.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "argus.h"
+#include "argus_internal.h"
+#include "argus_host.h"
+
+using namespace argus;
+
+namespace argus {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+int DevBuf::alloc(size_t nbytes) {
+  release();
+  if (nbytes == 0) nbytes = 64;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return fail(ARGUS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  bytes = nbytes;
+  return ARGUS_OK;
+}
+
+int DevBuf::upload(const void* src, size_t nbytes) {
+  int rc = alloc(nbytes);
+  if (rc) return rc;
+  if (nbytes && src) HIPCHK(hipMemcpy(p, src, nbytes, hipMemcpyHostToDevice));
+  return ARGUS_OK;
+}
+
+Workspace::~Workspace() {
+  if (has_graph) (void)hipGraphExecDestroy(exec);
+}
+
+int check_device(const argus_dataset* ds) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != ds->device)
+    return fail(ARGUS_E_INVAL, "dataset was created on device " +
+                                   std::to_string(ds->device) +
+                                   " but the current device is " +
+                                   std::to_string(dev));
+  return ARGUS_OK;
+}
+
+}  // namespace argus
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const argus_dataset_desc* d) {
+  if (!d) return fail(ARGUS_E_INVAL, "desc is NULL");
+  if (d->model < 1 || d->model > 3) return fail(ARGUS_E_INVAL, "unknown model");
+  if (d->n_psr < 1) return fail(ARGUS_E_INVAL, "n_psr must be >= 1");
+  if (d->model == ARGUS_M1_SPIN && d->n_psr != 1)
+    return fail(ARGUS_E_INVAL, "model 1 takes exactly one pulsar");
+  if (d->model == ARGUS_M3_JOINT_HD && d->n_psr > kJointMaxPsr)
+    return fail(ARGUS_E_UNSUPPORTED,
+                "joint model supports at most " + std::to_string(kJointMaxPsr) + " pulsars");
+  if (!d->toa_off) return fail(ARGUS_E_INVAL, "toa_off is NULL");
+  if (d->toa_off[0] != 0) return fail(ARGUS_E_INVAL, "toa_off[0] must be 0");
+  for (int p = 0; p < d->n_psr; ++p)
+    if (d->toa_off[p + 1] < d->toa_off[p])
+      return fail(ARGUS_E_INVAL, "toa_off must be non-decreasing");
+  const int64_t N = d->toa_off[d->n_psr];
+  if (N > (int64_t)1 << 31) return fail(ARGUS_E_UNSUPPORTED, "too many TOAs");
+  if (N > 0 && (!d->t || !d->y || !d->sigma))
+    return fail(ARGUS_E_INVAL, "t, y and sigma are required");
+  for (int p = 0; p < d->n_psr; ++p)
+    for (int64_t k = d->toa_off[p]; k < d->toa_off[p + 1]; ++k) {
+      if (!finite(d->t[k]) || d->t[k] < 0.0)
+        return fail(ARGUS_E_INVAL, "t must be finite and >= 0 (epoch t0 = 0)");
+      if (k > d->toa_off[p] && !(d->t[k] > d->t[k - 1]))
+        return fail(ARGUS_E_INVAL, "t must be strictly ascending within a pulsar");
+      if (!finite(d->y[k])) return fail(ARGUS_E_INVAL, "y must be finite");
+      if (!finite(d->sigma[k]) || !(d->sigma[k] > 0.0))
+        return fail(ARGUS_E_INVAL, "sigma must be finite and > 0");
+    }
+  if (d->model == ARGUS_M3_JOINT_HD) {
+    if (!d->pos) return fail(ARGUS_E_INVAL, "pos is required for the joint model");
+    for (int i = 0; i < 3 * d->n_psr; ++i)
+      if (!finite(d->pos[i])) return fail(ARGUS_E_INVAL, "pos must be finite");
+  }
+  if (!finite(d->t_span) || !(d->t_span > 0.0))
+    return fail(ARGUS_E_INVAL, "t_span must be > 0");
+  if (!finite(d->s_r) || !finite(d->s_f) || !finite(d->sigma_s) || d->s_r < 0 ||
+      d->s_f < 0 || d->sigma_s < 0)
+    return fail(ARGUS_E_INVAL, "s_r, s_f, sigma_s must be finite and >= 0");
+  const int C = d->model == ARGUS_M1_SPIN ? 2 : 4 * d->n_psr + 2;
+  for (int c = 0; c < C; ++c) {
+    const bool fr = d->free_mask ? d->free_mask[c] != 0 : true;
+    if (!fr && (!d->fixed || !finite(d->fixed[c])))
+      return fail(ARGUS_E_INVAL, "fixed values of non-free params must be finite");
+  }
+  return ARGUS_OK;
+}
+
+// Work items (64-sample tile, pulsar) in longest-first order.
+std::vector<int32_t> make_items(const std::vector<int64_t>& counts, int64_t S) {
+  const int64_t tiles = (S + kWave - 1) / kWave;
+  std::vector<int> order(counts.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return counts[a] > counts[b]; });
+  std::vector<int32_t> it;
+  it.reserve(2 * tiles * counts.size());
+  for (int p : order)
+    for (int64_t t = 0; t < tiles; ++t) {
+      it.push_back((int32_t)t);
+      it.push_back(p);
+    }
+  return it;
+}
+
+int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
+                       double* logl, int32_t* status, const TuneCfg& cfg,
+                       hipStream_t st) {
+  FilterArgs a{};
+  a.rec = ds->rec.as<TOARec>();
+  a.off = ds->off.as<int64_t>();
+  a.theta = theta;
+  a.col = ds->col.as<int32_t>();
+  a.fixed = ds->fixed.as<double>();
+  a.items = w->items.as<int32_t>();
+  a.counter = w->counter.as<int32_t>();
+  a.part = w->part.as<double>();
+  a.pstat = w->pstat.as<int32_t>();
+  a.S = w->S;
+  a.D = ds->D;
+  a.P = ds->P;
+  a.n_items = w->n_items;
+  a.dynamic = cfg.dynamic;
+  a.mc = ds->mc;
+  HIPCHK(launch_filter(ds->model, a, cfg.grid, cfg.block, st));
+  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, status,
+               w->counter.as<int32_t>(), w->S, ds->P};
+  HIPCHK(launch_reduce(r, st));
+  return ARGUS_OK;
+}
+
+std::vector<TuneCfg> candidates(const argus_dataset* ds, const Workspace* w) {
+  const int simd = 4 * ds->n_cu;
+  std::vector<TuneCfg> c;
+  auto add = [&](int block, int64_t waves, int dyn) {
+    const int wpb = block / kWave;
+    waves = std::min<int64_t>(waves, w->n_items);
+    waves = std::max<int64_t>(waves, 1);
+    const int64_t grid = (waves + wpb - 1) / wpb;
+    for (auto& x : c)
+      if (x.block == block && x.grid == grid && x.dynamic == dyn) return;
+    c.push_back({block, (int)grid, dyn, 0.f});
+  };
+  add(64, w->n_items, 0);
+  add(256, w->n_items, 0);
+  for (int k : {1, 2, 3, 4, 6}) add(64, (int64_t)simd * k, 1);
+  for (int k : {2, 4}) add(256, (int64_t)simd * k, 1);
+  return c;
+}
+
+int autotune(argus_dataset* ds, Workspace* w, const double* theta, double* logl,
+             int32_t* status, hipStream_t st) {
+  const char* forced = std::getenv("ARGUS_CFG");
+  if (forced) {
+    int b = 0, g = 0, dyn = 0;
+    if (std::sscanf(forced, "%d,%d,%d", &b, &g, &dyn) == 3 && b >= 64 && b <= 256 &&
+        b % 64 == 0 && g >= 1) {
+      w->cfg = {b, g, dyn, 0.f};
+      w->tuned = true;
+      return ARGUS_OK;
+    }
+    return fail(ARGUS_E_INVAL, "ARGUS_CFG must be 'block,grid,dynamic'");
+  }
+  const char* en = std::getenv("ARGUS_TUNE");
+  if (en && std::strcmp(en, "0") == 0) {
+    const int wpb = 1;
+    w->cfg = {64 * wpb, (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu), 1, 0.f};
+    w->tuned = true;
+    return ARGUS_OK;
+  }
+  std::vector<TuneCfg> cand = candidates(ds, w);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = ARGUS_OK;
+  for (auto& c : cand) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && rc == ARGUS_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
+      if (!rc) rc = launch_loglike_seq(ds, w, theta, logl, status, c, st);
+      if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
+      if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "sync");
+      float ms = 0;
+      if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "elapsed");
+      if (rep > 0) best = std::min(best, ms);  // first run warms caches
+    }
+    c.ms = best;
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  w->cfg = *std::min_element(cand.begin(), cand.end(),
+                             [](const TuneCfg& a, const TuneCfg& b) { return a.ms < b.ms; });
+  w->tuned = true;
+  w->tune_log.clear();
+  for (auto& c : cand) {
+    char b[128];
+    std::snprintf(b, sizeof b, "block=%d grid=%d dyn=%d: %.4f ms\n", c.block, c.grid,
+                  c.dynamic, c.ms);
+    w->tune_log += b;
+  }
+  return ARGUS_OK;
+}
+
+}  // namespace
+
+namespace argus {
+
+Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc) {
+  auto it = ds->ws.find(S);
+  if (it != ds->ws.end()) return it->second.get();
+  auto w = std::make_unique<Workspace>();
+  w->S = S;
+  const size_t ps = (size_t)ds->P * (size_t)S;
+  if ((*rc = w->part.alloc(ps * sizeof(double)))) return nullptr;
+  if ((*rc = w->pstat.alloc(ps * sizeof(int32_t)))) return nullptr;
+  if ((*rc = w->logl_tmp.alloc((size_t)S * sizeof(double)))) return nullptr;
+  if ((*rc = w->counter.alloc(64))) return nullptr;
+  if (hipMemset(w->counter.p, 0, 64) != hipSuccess) {
+    *rc = fail(ARGUS_E_HIP, "hipMemset");
+    return nullptr;
+  }
+  if (ds->model != ARGUS_M3_JOINT_HD) {
+    std::vector<int32_t> items = make_items(ds->counts, S);
+    w->n_items = (int)(items.size() / 2);
+    if ((*rc = w->items.upload(items.data(), items.size() * sizeof(int32_t)))) return nullptr;
+  }
+  Workspace* raw = w.get();
+  ds->ws[S] = std::move(w);
+  *rc = ARGUS_OK;
+  return raw;
+}
+
+}  // namespace argus
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* argus_last_error(void) { return g_err.c_str(); }
+
+int argus_dataset_create(const argus_dataset_desc* d, argus_dataset_t* out) {
+  if (!out) return fail(ARGUS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc) return rc;
+  auto ds = std::make_unique<argus_dataset>();
+  ds->model = d->model;
+  ds->P = d->n_psr;
+  ds->C = d->model == ARGUS_M1_SPIN ? 2 : 4 * d->n_psr + 2;
+  ds->N = d->toa_off[d->n_psr];
+  HIPCHK(hipGetDevice(&ds->device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, ds->device));
+  ds->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  ds->mc.s_r2 = d->s_r * d->s_r;
+  ds->mc.s_f2 = d->s_f * d->s_f;
+  ds->mc.ss2 = d->sigma_s * d->sigma_s;
+  ds->mc.log_fyr = std::log(1.0 / kYear);
+  ds->mc.log_T = std::log(d->t_span);
+  ds->mc.lam = 2.0 * kPi / d->t_span;
+  // free parameters -> theta columns in canonical order
+  std::vector<int32_t> col(ds->C);
+  std::vector<double> fixed(ds->C, 0.0);
+  int D = 0;
+  for (int c = 0; c < ds->C; ++c) {
+    const bool fr = d->free_mask ? d->free_mask[c] != 0 : true;
+    col[c] = fr ? D++ : -1;
+    if (d->fixed) fixed[c] = d->fixed[c];
+  }
+  ds->D = D;
+  ds->off_h.assign(d->toa_off, d->toa_off + ds->P + 1);
+  ds->counts.resize(ds->P);
+  for (int p = 0; p < ds->P; ++p) ds->counts[p] = d->toa_off[p + 1] - d->toa_off[p];
+  // stream order: per-pulsar CSR, or merged by (t, pulsar) for the joint model
+  const int64_t N = ds->N;
+  std::vector<int64_t> src(N), prev(N);
+  std::vector<int32_t> psr(N);
+  if (d->model == ARGUS_M3_JOINT_HD) {
+    std::vector<std::pair<double, int32_t>> key(N);
+    std::vector<int64_t> ord(N);
+    for (int p = 0; p < ds->P; ++p)
+      for (int64_t k = d->toa_off[p]; k < d->toa_off[p + 1]; ++k) key[k] = {d->t[k], p};
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+      return key[a].first != key[b].first ? key[a].first < key[b].first
+                                          : key[a].second < key[b].second;
+    });
+    for (int64_t k = 0; k < N; ++k) {
+      src[k] = ord[k];
+      prev[k] = k ? ord[k - 1] : -1;
+      psr[k] = key[ord[k]].second;
+    }
+  } else {
+    for (int p = 0; p < ds->P; ++p)
+      for (int64_t k = d->toa_off[p]; k < d->toa_off[p + 1]; ++k) {
+        src[k] = k;
+        prev[k] = k > d->toa_off[p] ? k - 1 : -1;
+        psr[k] = p;
+      }
+  }
+  DevBuf dsrc, dprev, dpsr;
+  if ((rc = ds->t.upload(d->t, N * sizeof(double))) ||
+      (rc = ds->y.upload(d->y, N * sizeof(double))) ||
+      (rc = ds->sig.upload(d->sigma, N * sizeof(double))) ||
+      (rc = dsrc.upload(src.data(), N * sizeof(int64_t))) ||
+      (rc = dprev.upload(prev.data(), N * sizeof(int64_t))) ||
+      (rc = dpsr.upload(psr.data(), N * sizeof(int32_t))) ||
+      (rc = ds->rec.alloc(N * sizeof(TOARec))) ||
+      (rc = ds->off.upload(d->toa_off, (ds->P + 1) * sizeof(int64_t))) ||
+      (rc = ds->col.upload(col.data(), ds->C * sizeof(int32_t))) ||
+      (rc = ds->fixed.upload(fixed.data(), ds->C * sizeof(double))))
+    return rc;
+  StageArgs sa{ds->t.as<double>(), ds->y.as<double>(), ds->sig.as<double>(),
+               dsrc.as<int64_t>(), dprev.as<int64_t>(), dpsr.as<int32_t>(),
+               ds->rec.as<TOARec>(), N, ds->mc.lam};
+  HIPCHK(launch_stage(sa, 0));
+  if (d->model == ARGUS_M3_JOINT_HD) {
+    DevBuf dpos;
+    if ((rc = dpos.upload(d->pos, 3 * ds->P * sizeof(double))) ||
+        (rc = ds->hd.alloc((size_t)ds->P * ds->P * sizeof(double))))
+      return rc;
+    HIPCHK(launch_hd(dpos.as<double>(), ds->P, ds->hd.as<double>(), 0));
+    HIPCHK(hipDeviceSynchronize());
+  }
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipStreamCreateWithFlags(&ds->cap_stream, hipStreamNonBlocking));
+  *out = ds.release();
+  return ARGUS_OK;
+}
+
+int argus_dataset_destroy(argus_dataset_t ds) {
+  if (!ds) return ARGUS_OK;
+  (void)hipDeviceSynchronize();
+  if (ds->cap_stream) (void)hipStreamDestroy(ds->cap_stream);
+  delete ds;
+  return ARGUS_OK;
+}
+
+int argus_dataset_n_params(argus_dataset_t ds, int32_t* D) {
+  if (!ds || !D) return fail(ARGUS_E_INVAL, "NULL argument");
+  *D = ds->D;
+  return ARGUS_OK;
+}
+
+static int check_call(argus_dataset_t ds, const double* theta, int64_t S, const void* out) {
+  if (!ds) return fail(ARGUS_E_INVAL, "dataset is NULL");
+  if (S < 0) return fail(ARGUS_E_INVAL, "S must be >= 0");
+  if (S > ((int64_t)1 << 30)) return fail(ARGUS_E_UNSUPPORTED, "S too large");
+  if (S > 0 && ds->D > 0 && !theta) return fail(ARGUS_E_INVAL, "theta is NULL");
+  if (S > 0 && !out) return fail(ARGUS_E_INVAL, "output is NULL");
+  return check_device(ds);
+}
+
+int argus_loglike(argus_dataset_t ds, const double* theta, int64_t S, double* logl,
+                  int32_t* status, void* stream) {
+  int rc = check_call(ds, theta, S, logl);
+  if (rc || S == 0) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (ds->model == ARGUS_M3_JOINT_HD) return joint_loglike(ds, theta, S, logl, status, st);
+  Workspace* w = get_workspace(ds, S, &rc);
+  if (!w) return rc;
+  if (!w->tuned && (rc = autotune(ds, w, theta, logl, status, st))) return rc;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cs));
+  const char* ng = std::getenv("ARGUS_NO_GRAPH");
+  if (cs != hipStreamCaptureStatusNone || (ng && std::strcmp(ng, "1") == 0))
+    return launch_loglike_seq(ds, w, theta, logl, status, w->cfg, st);
+  if (!w->has_graph || w->g_theta != theta || w->g_out != logl || w->g_status != status) {
+    if (w->has_graph) {
+      HIPCHK(hipGraphExecDestroy(w->exec));
+      w->has_graph = false;
+    }
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(ds->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = launch_loglike_seq(ds, w, theta, logl, status, w->cfg, ds->cap_stream);
+    hipError_t e = hipStreamEndCapture(ds->cap_stream, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(ARGUS_E_HIP, "hipStreamEndCapture failed");
+    e = hipGraphInstantiate(&w->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(ARGUS_E_HIP, "hipGraphInstantiate failed");
+    w->has_graph = true;
+    w->g_theta = theta;
+    w->g_out = logl;
+    w->g_status = status;
+  }
+  HIPCHK(hipGraphLaunch(w->exec, st));
+  return ARGUS_OK;
+}
+
+int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S, double* terms,
+                        int32_t* status, void* stream) {
+  int rc = check_call(ds, theta, S, terms);
+  if (rc || S == 0) return rc;
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "per-pulsar terms exist for models 1 and 2 only");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = get_workspace(ds, S, &rc);
+  if (!w) return rc;
+  if (!w->tuned && (rc = autotune(ds, w, theta, w->logl_tmp.as<double>(), status, st)))
+    return rc;
+  if ((rc = launch_loglike_seq(ds, w, theta, w->logl_tmp.as<double>(), status, w->cfg, st)))
+    return rc;
+  HIPCHK(hipMemcpyAsync(terms, w->part.p, (size_t)ds->P * S * sizeof(double),
+                        hipMemcpyDeviceToDevice, st));
+  return ARGUS_OK;
+}
+
+int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S, double* logl,
+                        int32_t* status, void* stream) {
+  int rc = check_call(ds, theta, S, logl);
+  if (rc || S == 0) return rc;
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "the plain baseline covers models 1 and 2");
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t s = 0; s < S; ++s) {
+    PlainArgs a{ds->t.as<double>(), ds->y.as<double>(), ds->sig.as<double>(),
+                ds->off.as<int64_t>(), theta ? theta + s * ds->D : nullptr,
+                ds->col.as<int32_t>(), ds->fixed.as<double>(), logl + s,
+                status ? status + s : nullptr, ds->D, ds->P, ds->model, ds->mc};
+    HIPCHK(launch_plain(a, st));
+  }
+  return ARGUS_OK;
+}
+
+int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
+  if (!ds || !buf || len <= 0) return fail(ARGUS_E_INVAL, "bad argument");
+  auto it = ds->ws.find(S);
+  std::string s;
+  if (it == ds->ws.end() || !it->second->tuned) {
+    s = "not tuned";
+  } else {
+    const Workspace* w = it->second.get();
+    char b[160];
+    std::snprintf(b, sizeof b, "chosen block=%d grid=%d dyn=%d items=%d\n", w->cfg.block,
+                  w->cfg.grid, w->cfg.dynamic, w->n_items);
+    s = b + w->tune_log;
+  }
+  std::snprintf(buf, len, "%s", s.c_str());
+  return ARGUS_OK;
+}
+
+}  // extern "C"
+extern "C" int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
+                                  double* logl, double* grad, int32_t* status, void* stream) {
+  int rc = check_call(ds, theta, S, logl);
+  if (rc || S == 0) return rc;
+  (void)grad;
+  (void)status;
+  (void)stream;
+  return fail(ARGUS_E_UNSUPPORTED, "gradient not available yet");
+}

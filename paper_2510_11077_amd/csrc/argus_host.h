@@ -1,0 +1,91 @@
+// Host-side state of libargus (dataset handles, workspaces, error helpers).
+#pragma once
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "argus.h"
+#include "argus_internal.h"
+
+namespace argus {
+
+extern thread_local std::string g_err;
+int fail(int code, const std::string& msg);
+
+#define HIPCHK(x)                                                          \
+  do {                                                                     \
+    hipError_t e_ = (x);                                                   \
+    if (e_ != hipSuccess)                                                  \
+      return ::argus::fail(ARGUS_E_HIP,                                    \
+                           std::string(#x ": ") + hipGetErrorString(e_));  \
+  } while (0)
+
+// Largest joint model: one workgroup thread per 4x4 covariance block,
+// P (P + 1) / 2 blocks <= 256 threads.
+constexpr int kJointMaxPsr = 22;
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release();
+  int alloc(size_t nbytes);
+  int upload(const void* src, size_t nbytes);
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct TuneCfg {
+  int block = 64;
+  int grid = 1;
+  int dynamic = 1;
+  float ms = 0.f;
+};
+
+// Per-sample-count state of a dataset.
+struct Workspace {
+  int64_t S = 0;
+  DevBuf part, pstat, logl_tmp, items, counter;
+  int n_items = 0;
+  TuneCfg cfg;
+  bool tuned = false;
+  std::string tune_log;
+  // captured launch sequence, valid for the pointers it was captured with
+  hipGraphExec_t exec{};
+  bool has_graph = false;
+  const void* g_theta = nullptr;
+  const void* g_out = nullptr;
+  const void* g_status = nullptr;
+  // gradient workspace
+  DevBuf ckpt, gpart;
+  int64_t ckpt_elems = 0;
+  ~Workspace();
+};
+
+}  // namespace argus
+
+struct argus_dataset {
+  int model = 0, P = 0, C = 0, D = 0;
+  int64_t N = 0;
+  int device = 0, n_cu = 256;
+  argus::ModelConst mc{};
+  argus::DevBuf rec, off, col, fixed, hd, t, y, sig;
+  std::vector<int64_t> off_h, counts;
+  std::map<int64_t, std::unique_ptr<argus::Workspace>> ws;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace argus {
+int check_device(const argus_dataset* ds);
+Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc);
+int joint_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl,
+                  int32_t* status, hipStream_t st);
+}  // namespace argus

@@ -1,0 +1,137 @@
+// Internal declarations shared by the host API and the kernel translation
+// units of libargus. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace argus {
+
+constexpr int kWave = 64;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLn10 = 2.30258509299404568402;
+constexpr double kLn2Pi = 1.83787706640934548356;
+constexpr double kYear = 31557600.0;
+
+// status words; kPNF marks "a parameter of this filter is not finite" and has
+// priority over the innovation flags when a sample's pulsars are combined
+constexpr int kNonPD = 1;
+constexpr int kNonFinite = 2;
+constexpr int kPNF = 4;
+
+// Per-TOA record, 64 B, in stream order (per-pulsar CSR for models 1/2, the
+// merged time-ordered stream for model 3). All entries are theta-independent.
+struct alignas(64) TOARec {
+  double dt;     // t_k - t_{k-1} (t_0 = epoch 0)
+  double h2;     // dt^2 / 2
+  double h3;     // dt^3 / 3
+  double phc;    // exp(-lambda_c dt), common OU decay
+  double qcu;    // 1 - phc^2, common OU noise per unit variance
+  double y;      // residual
+  double s2;     // sigma_k^2
+  int32_t psr;   // pulsar of this TOA (model 3)
+  int32_t pad;
+};
+static_assert(sizeof(TOARec) == 64, "TOA record is one 64-B line");
+
+// The TOA stream is read-only for the whole of every kernel that reads it and
+// all lanes of a wave read the same record, so kernels address it through the
+// constant address space: the compiler then issues one scalar 64-B load
+// (s_load_dwordx16) per record instead of 64 vector loads.
+typedef __attribute__((address_space(4))) const TOARec* RecPtr;
+
+__device__ __forceinline__ TOARec load_rec(RecPtr r, int64_t k) {
+  TOARec x;
+  x.dt = r[k].dt;
+  x.h2 = r[k].h2;
+  x.h3 = r[k].h3;
+  x.phc = r[k].phc;
+  x.qcu = r[k].qcu;
+  x.y = r[k].y;
+  x.s2 = r[k].s2;
+  x.psr = r[k].psr;
+  x.pad = 0;
+  return x;
+}
+
+// 1/S from the hardware reciprocal refined by two Newton steps (error within
+// an ulp or so; S > 0 in every use that is not already flagged).
+__device__ __forceinline__ double rcp_nr(double S) {
+  double r = __builtin_amdgcn_rcp(S);
+  double e = __builtin_fma(-S, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-S, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Model constants shared by all kernels.
+struct ModelConst {
+  double s_r2, s_f2;   // prior variances of r and f
+  double ss2;          // sigma_s^2 (models 2, 3)
+  double log_fyr;      // ln(1/yr)
+  double log_T;        // ln(t_span)
+  double lam;          // 2 pi / t_span
+};
+
+// Arguments of the batched per-pulsar filter (models 1, 2).
+struct FilterArgs {
+  const TOARec* rec;     // [N]
+  const int64_t* off;    // [P+1]
+  const double* theta;   // [S*D]
+  const int32_t* col;    // [C] theta column of canonical param, or -1
+  const double* fixed;   // [C]
+  const int32_t* items;  // [n_items*2] (sample tile, pulsar), longest first
+  int32_t* counter;      // work-queue head (zero before launch)
+  double* part;          // [P*S] per-pulsar log-likelihood terms
+  int32_t* pstat;        // [P*S] per-pulsar status words
+  int64_t S;
+  int32_t D, P, n_items, dynamic;
+  ModelConst mc;
+};
+
+struct ReduceArgs {
+  const double* part;
+  const int32_t* pstat;
+  double* logl;
+  int32_t* status;
+  int32_t* counter;  // reset to 0 for the next launch
+  int64_t S;
+  int32_t P;
+};
+
+// Plain per-sample filter (baseline): reads raw t/y/sigma.
+struct PlainArgs {
+  const double* t;
+  const double* y;
+  const double* sig;
+  const int64_t* off;
+  const double* theta_row;  // [D] one sample
+  const int32_t* col;
+  const double* fixed;
+  double* logl;             // one output
+  int32_t* status;          // one output or NULL
+  int32_t D, P, model;
+  ModelConst mc;
+};
+
+struct StageArgs {
+  const double* t;
+  const double* y;
+  const double* sig;
+  const int64_t* src;   // [N] source TOA index of stream element k
+  const int64_t* prev;  // [N] source index of the previous element, -1 first
+  const int32_t* psr;   // [N] pulsar of stream element k
+  TOARec* rec;
+  int64_t N;
+  double lam;
+};
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t st);
+hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st);
+hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
+                         hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_plain(const PlainArgs& a, hipStream_t st);
+
+}  // namespace argus

@@ -1,0 +1,481 @@
+// Batched Kalman filters of independent pulsars (models 1 and 2), the
+// per-TOA staging kernel, the Hellings-Downs matrix, the per-sample
+// reduction, and the plain per-sample baseline filter.
+//
+// Method (paper: Functionality, "Kalman filter likelihood evaluation"): for
+// each TOA the filter discretises the SDEs over the interval since the
+// previous TOA (transition F, process noise Q), predicts, forms the
+// innovation e and its variance S, updates the state and covariance, and
+// accumulates -1/2 (ln 2 pi + ln S + e^2 / S).
+//
+// Mapping on CDNA4: one wavefront owns one (64-sample tile, pulsar) filter:
+// lane = sample. All lanes walk the same TOA stream, so every per-TOA value
+// is wave-uniform and is read with scalar loads from one 64-B record; each
+// lane keeps its 4-state mean and the 10 unique covariance entries in VGPRs.
+// The covariance update is the Joseph form written as the symmetric rank-2
+// expression P - K u^T - u K^T + S K K^T (u = P H^T), which equals
+// (I - K H) P (I - K H)^T + K R K^T for any gain K. ln S is accumulated as a
+// product of mantissas with exponent extraction (frexp), one log per filter.
+// Waves take work items from a longest-first queue (atomic head) so pulsars
+// of uneven length balance across the 1024 SIMDs.
+#include "argus_internal.h"
+
+namespace argus {
+
+namespace {
+
+__device__ __forceinline__ bool finite_d(double v) {
+  return __builtin_amdgcn_class(v, 0x1F8);  // -normal..+normal incl. zeros
+}
+
+// First-failure classification, same order of tests as the definition:
+// a non-finite S or e is NONFINITE, otherwise S <= 0 is NONPD.
+__device__ __forceinline__ int step_status(double S, double e) {
+  if (!finite_d(S) || !finite_d(e)) return kNonFinite;
+  return S > 0.0 ? 0 : kNonPD;
+}
+
+struct LogAcc {
+  double m;
+  int e;
+};
+__device__ __forceinline__ void acc_mul(LogAcc& L, double S) {
+  const double p = L.m * S;
+  L.m = __builtin_amdgcn_frexp_mant(p);
+  L.e += __builtin_amdgcn_frexp_exp(p);
+}
+__device__ __forceinline__ double acc_log(const LogAcc& L) {
+  return log(L.m) + (double)L.e * kLn2;
+}
+
+__device__ __forceinline__ double load_param(const FilterArgs& a, int c,
+                                             int64_t s) {
+  const int j = a.col[c];
+  return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
+}
+
+// Stationary variance of the common OU process from the power law (log10 A,
+// gamma): A^2 f_yr^(gamma-3) T^(gamma-1) / (12 pi^2 (gamma-1)).
+__device__ __forceinline__ double common_var(double la, double gc,
+                                             const ModelConst& mc) {
+  const double gm1 = gc - 1.0;
+  return exp(2.0 * kLn10 * la + (gc - 3.0) * mc.log_fyr + gm1 * mc.log_T) /
+         (12.0 * kPi * kPi * gm1);
+}
+
+// Symmetric rank-2 Joseph update of one covariance entry.
+#define JOSEPH(pij, ki, ui, wi, kj, uj) \
+  pij = fma(wi, kj, fma(-(ui), kj, fma(-(ki), uj, pij)))
+
+// ------------------------------------------------------------ model 2 step
+struct F4 {
+  double xr, xf, xa, xg;
+  double prr, prf, pff, pra, pfa, paa, prg, pfg, pag, pgg;
+  double quad;
+  LogAcc L;
+  int st;
+};
+
+__device__ __forceinline__ void step4(F4& f, const TOARec r, double gr,
+                                      double vr, double vc, double efac2,
+                                      double equad2, double ss2) {
+  const double dt = r.dt;
+  // red OU over dt for this lane's rate: phi = 1 + expm1(-g dt),
+  // q = v (1 - phi^2) = -v em (2 + em) without cancellation
+  const double em = expm1(-gr * dt);
+  const double phr = 1.0 + em;
+  const double qr = vr * (-em * (2.0 + em));
+  const double phc = r.phc;
+  const double qc = vc * r.qcu;
+  // predict mean
+  f.xr = fma(dt, f.xf, f.xr);
+  f.xa *= phr;
+  f.xg *= phc;
+  // predict covariance F P F^T + Q
+  const double prf1 = fma(dt, f.pff, f.prf);
+  f.prr = fma(dt, f.prf + prf1, f.prr) + ss2 * r.h3;
+  f.prf = prf1 + ss2 * r.h2;
+  f.pff = f.pff + ss2 * dt;
+  f.pra = phr * fma(dt, f.pfa, f.pra);
+  f.pfa = phr * f.pfa;
+  f.paa = fma(phr * phr, f.paa, qr);
+  f.prg = phc * fma(dt, f.pfg, f.prg);
+  f.pfg = phc * f.pfg;
+  f.pag = (phr * phc) * f.pag;
+  f.pgg = fma(phc * phc, f.pgg, qc);
+  // innovation, H = [1, 0, 1, 1]
+  const double e = r.y - (f.xr + f.xa + f.xg);
+  const double ur = f.prr + f.pra + f.prg;
+  const double uf = f.prf + f.pfa + f.pfg;
+  const double ua = f.pra + f.paa + f.pag;
+  const double ug = f.prg + f.pag + f.pgg;
+  const double S = (ur + ua + ug) + fma(efac2, r.s2, equad2);
+  if (f.st == 0) f.st = step_status(S, e);
+  const double inv = rcp_nr(S);
+  const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
+  f.xr = fma(kr, e, f.xr);
+  f.xf = fma(kf, e, f.xf);
+  f.xa = fma(ka, e, f.xa);
+  f.xg = fma(kg, e, f.xg);
+  const double wr = S * kr, wf = S * kf, wa = S * ka, wg = S * kg;
+  JOSEPH(f.prr, kr, ur, wr, kr, ur);
+  JOSEPH(f.prf, kr, ur, wr, kf, uf);
+  JOSEPH(f.pff, kf, uf, wf, kf, uf);
+  JOSEPH(f.pra, kr, ur, wr, ka, ua);
+  JOSEPH(f.pfa, kf, uf, wf, ka, ua);
+  JOSEPH(f.paa, ka, ua, wa, ka, ua);
+  JOSEPH(f.prg, kr, ur, wr, kg, ug);
+  JOSEPH(f.pfg, kf, uf, wf, kg, ug);
+  JOSEPH(f.pag, ka, ua, wa, kg, ug);
+  JOSEPH(f.pgg, kg, ug, wg, kg, ug);
+  f.quad = fma(e * e, inv, f.quad);
+  acc_mul(f.L, S);
+}
+
+// ------------------------------------------------------------ model 1 step
+struct F2 {
+  double xr, xf, prr, prf, pff, quad;
+  LogAcc L;
+  int st;
+};
+
+__device__ __forceinline__ void step2(F2& f, const TOARec r, double ss2,
+                                      double efac2) {
+  const double dt = r.dt;
+  f.xr = fma(dt, f.xf, f.xr);
+  const double prf1 = fma(dt, f.pff, f.prf);
+  f.prr = fma(dt, f.prf + prf1, f.prr) + ss2 * r.h3;
+  f.prf = prf1 + ss2 * r.h2;
+  f.pff = f.pff + ss2 * dt;
+  const double e = r.y - f.xr;
+  const double ur = f.prr, uf = f.prf;
+  const double S = ur + efac2 * r.s2;
+  if (f.st == 0) f.st = step_status(S, e);
+  const double inv = rcp_nr(S);
+  const double kr = ur * inv, kf = uf * inv;
+  f.xr = fma(kr, e, f.xr);
+  f.xf = fma(kf, e, f.xf);
+  const double wr = S * kr, wf = S * kf;
+  JOSEPH(f.prr, kr, ur, wr, kr, ur);
+  JOSEPH(f.prf, kr, ur, wr, kf, uf);
+  JOSEPH(f.pff, kf, uf, wf, kf, uf);
+  f.quad = fma(e * e, inv, f.quad);
+  acc_mul(f.L, S);
+}
+
+__device__ __forceinline__ double finish(double n, double quad,
+                                         const LogAcc& L, int& st) {
+  double ll = -0.5 * (n * kLn2Pi + acc_log(L) + quad);
+  if (st == 0 && !finite_d(ll)) st = kNonFinite;
+  return st ? -INFINITY : ll;
+}
+
+template <int MODEL>
+__global__ void __launch_bounds__(256) k_filter(FilterArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wpb = blockDim.x / kWave;
+  const int gwave = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * wpb + (threadIdx.x / kWave)));
+  const int nwaves = gridDim.x * wpb;
+  int next = gwave;
+  for (;;) {
+    int it;
+    if (a.dynamic) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(a.counter, 1);
+      it = __builtin_amdgcn_readfirstlane(v);
+    } else {
+      it = next;
+      next += nwaves;
+    }
+    if (it >= a.n_items) break;
+    const int tile = a.items[2 * it];
+    const int p = a.items[2 * it + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int64_t kb = a.off[p], ke = a.off[p + 1];
+    double ll;
+    int st;
+    if (MODEL == 1) {
+      const double lss = load_param(a, 0, s), efac = load_param(a, 1, s);
+      const bool pnf = !(finite_d(lss) && finite_d(efac));
+      const double ss = exp10(lss);
+      const double ss2 = ss * ss, efac2 = efac * efac;
+      F2 f{0.0, 0.0, a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, {1.0, 0}, pnf ? kPNF : 0};
+      const RecPtr rec = (RecPtr)a.rec;
+      for (int64_t k = kb; k < ke; ++k) step2(f, load_rec(rec, k), ss2, efac2);
+      st = f.st;
+      ll = finish((double)(ke - kb), f.quad, f.L, st);
+    } else {
+      const int c0 = 4 * p, cc = 4 * a.P;
+      const double lsr = load_param(a, c0, s), lgr = load_param(a, c0 + 1, s);
+      const double efac = load_param(a, c0 + 2, s);
+      const double leq = load_param(a, c0 + 3, s);
+      const double la = load_param(a, cc, s), gc = load_param(a, cc + 1, s);
+      const bool pnf = !(finite_d(lsr) && finite_d(lgr) && finite_d(efac) &&
+                         finite_d(leq) && finite_d(la) && finite_d(gc));
+      const double gr = exp10(lgr), sr = exp10(lsr), eq = exp10(leq);
+      const double vr = sr * sr / (2.0 * gr);
+      const double vc = common_var(la, gc, a.mc);
+      const double efac2 = efac * efac, equad2 = eq * eq;
+      F4 f{};
+      f.prr = a.mc.s_r2;
+      f.pff = a.mc.s_f2;
+      f.paa = vr;
+      f.pgg = vc;
+      f.L = {1.0, 0};
+      f.st = pnf ? kPNF : 0;
+      const double ss2 = a.mc.ss2;
+      const RecPtr rec = (RecPtr)a.rec;
+      for (int64_t k = kb; k < ke; ++k)
+        step4(f, load_rec(rec, k), gr, vr, vc, efac2, equad2, ss2);
+      st = f.st;
+      ll = finish((double)(ke - kb), f.quad, f.L, st);
+    }
+    if (valid) {
+      a.part[(int64_t)p * a.S + s] = ll;
+      a.pstat[(int64_t)p * a.S + s] = st;
+    }
+  }
+}
+
+// logL[s] = sum over pulsars in index order; status = first failure in
+// pulsar order, NONFINITE if any parameter of the row is not finite.
+__global__ void k_reduce(ReduceArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.counter) *a.counter = 0;
+  if (s >= a.S) return;
+  double acc = 0.0;
+  int st = 0;
+  bool pnf = false;
+  for (int p = 0; p < a.P; ++p) {
+    acc += a.part[(int64_t)p * a.S + s];
+    const int c = a.pstat[(int64_t)p * a.S + s];
+    if (c & kPNF)
+      pnf = true;
+    else if (c && !st)
+      st = c;
+  }
+  if (pnf) st = kNonFinite;
+  a.logl[s] = st ? -INFINITY : acc;
+  if (a.status) a.status[s] = st;
+}
+
+__global__ void k_stage(StageArgs a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.N) return;
+  const int64_t j = a.src[k], pj = a.prev[k];
+  const double dt = a.t[j] - (pj >= 0 ? a.t[pj] : 0.0);
+  TOARec r;
+  r.dt = dt;
+  r.h2 = dt * dt * 0.5;
+  r.h3 = dt * dt * dt / 3.0;
+  const double em = expm1(-a.lam * dt);
+  r.phc = 1.0 + em;
+  r.qcu = -em * (2.0 + em);
+  r.y = a.y[j];
+  const double sg = a.sig[j];
+  r.s2 = sg * sg;
+  r.psr = a.psr[k];
+  r.pad = 0;
+  a.rec[k] = r;
+}
+
+// Hellings & Downs (1983) correlation with the pulsar term on the diagonal:
+// G_ab = 3/2 x ln x - x/4 + 1/2 + delta_ab/2, x = (1 - cos zeta_ab)/2.
+__global__ void k_hd(const double* pos, int P, double* G) {
+  const int a = blockIdx.x, b = threadIdx.x;
+  if (a >= P || b >= P) return;
+  const double c = pos[3 * a] * pos[3 * b] + pos[3 * a + 1] * pos[3 * b + 1] +
+                   pos[3 * a + 2] * pos[3 * b + 2];
+  double x = a == b ? 0.0 : 0.5 * (1.0 - c);
+  x = x < 0.0 ? 0.0 : x;
+  const double xl = x > 0.0 ? x * log(x) : 0.0;
+  G[a * P + b] = 1.5 * xl - 0.25 * x + 0.5 + (a == b ? 0.5 : 0.0);
+}
+
+// ------------------------------------------------ plain per-sample baseline
+// One thread per pulsar filter of one sample: textbook dense recursion with
+// the transition and noise rebuilt from exp/expm1 at every TOA, Joseph form
+// via explicit (I - K H), one log and one division per TOA.
+template <int N>
+__device__ double plain_filter(const PlainArgs& a, int p, int& st) {
+  double lss = 0, efac, leq = 0, lsr = 0, lgr = 0, la = 0, gc = 2;
+  auto prm = [&](int c) {
+    const int j = a.col[c];
+    return j >= 0 ? a.theta_row[j] : a.fixed[c];
+  };
+  if (N == 2) {
+    lss = prm(0);
+    efac = prm(1);
+  } else {
+    lsr = prm(4 * p);
+    lgr = prm(4 * p + 1);
+    efac = prm(4 * p + 2);
+    leq = prm(4 * p + 3);
+    la = prm(4 * a.P);
+    gc = prm(4 * a.P + 1);
+  }
+  st = 0;
+  if (!(finite_d(lss) && finite_d(efac) && finite_d(leq) && finite_d(lsr) &&
+        finite_d(lgr) && finite_d(la) && finite_d(gc))) {
+    st = kPNF;
+    return -INFINITY;
+  }
+  const double ss2 = N == 2 ? pow(10.0, 2.0 * lss) : a.mc.ss2;
+  const double gr = pow(10.0, lgr);
+  const double vr = pow(10.0, 2.0 * lsr) / (2.0 * gr);
+  const double equad2 = N == 2 ? 0.0 : pow(10.0, 2.0 * leq);
+  const double vc = N == 2 ? 0.0
+                           : pow(10.0, 2.0 * la) * pow(1.0 / kYear, gc - 3.0) *
+                                 exp((gc - 1.0) * a.mc.log_T) /
+                                 (12.0 * kPi * kPi * (gc - 1.0));
+  double x[N] = {}, P[N][N] = {};
+  P[0][0] = a.mc.s_r2;
+  P[1][1] = a.mc.s_f2;
+  if constexpr (N == 4) {
+    P[2][2] = vr;
+    P[3][3] = vc;
+  }
+  double H[N] = {};
+  H[0] = 1.0;
+  if constexpr (N == 4) H[2] = H[3] = 1.0;
+  double ll = 0.0, tprev = 0.0;
+  for (int64_t j = a.off[p]; j < a.off[p + 1]; ++j) {
+    const double dt = a.t[j] - tprev;
+    tprev = a.t[j];
+    double F[N][N] = {}, Q[N][N] = {};
+    F[0][0] = F[1][1] = 1.0;
+    F[0][1] = dt;
+    Q[0][0] = ss2 * dt * dt * dt / 3.0;
+    Q[0][1] = Q[1][0] = ss2 * dt * dt / 2.0;
+    Q[1][1] = ss2 * dt;
+    if constexpr (N == 4) {
+      F[2][2] = exp(-gr * dt);
+      Q[2][2] = -vr * expm1(-2.0 * gr * dt);
+      F[3][3] = exp(-a.mc.lam * dt);
+      Q[3][3] = -vc * expm1(-2.0 * a.mc.lam * dt);
+    }
+    double xp[N], T[N][N], Pp[N][N];
+    for (int i = 0; i < N; ++i) {
+      xp[i] = 0;
+      for (int m = 0; m < N; ++m) xp[i] += F[i][m] * x[m];
+    }
+    for (int i = 0; i < N; ++i)
+      for (int m = 0; m < N; ++m) {
+        T[i][m] = 0;
+        for (int l = 0; l < N; ++l) T[i][m] += F[i][l] * P[l][m];
+      }
+    for (int i = 0; i < N; ++i)
+      for (int m = 0; m < N; ++m) {
+        Pp[i][m] = Q[i][m];
+        for (int l = 0; l < N; ++l) Pp[i][m] += T[i][l] * F[m][l];
+      }
+    const double sg = a.sig[j];
+    const double R = efac * efac * sg * sg + equad2;
+    double hx = 0, u[N], S = R;
+    for (int i = 0; i < N; ++i) hx += H[i] * xp[i];
+    const double e = a.y[j] - hx;
+    for (int i = 0; i < N; ++i) {
+      u[i] = 0;
+      for (int m = 0; m < N; ++m) u[i] += Pp[i][m] * H[m];
+      S += H[i] * u[i];
+    }
+    if (st == 0) st = step_status(S, e);
+    double K[N], A[N][N];
+    for (int i = 0; i < N; ++i) {
+      K[i] = u[i] / S;
+      x[i] = xp[i] + K[i] * e;
+    }
+    for (int i = 0; i < N; ++i)
+      for (int m = 0; m < N; ++m) A[i][m] = (i == m ? 1.0 : 0.0) - K[i] * H[m];
+    for (int i = 0; i < N; ++i)
+      for (int m = 0; m < N; ++m) {
+        T[i][m] = 0;
+        for (int l = 0; l < N; ++l) T[i][m] += A[i][l] * Pp[l][m];
+      }
+    for (int i = 0; i < N; ++i)
+      for (int m = 0; m < N; ++m) {
+        P[i][m] = K[i] * R * K[m];
+        for (int l = 0; l < N; ++l) P[i][m] += T[i][l] * A[m][l];
+      }
+    for (int i = 0; i < N; ++i)
+      for (int m = i + 1; m < N; ++m) P[i][m] = P[m][i] = 0.5 * (P[i][m] + P[m][i]);
+    ll += -0.5 * (kLn2Pi + log(S) + e * e / S);
+  }
+  if (st == 0 && !finite_d(ll)) st = kNonFinite;
+  return st ? -INFINITY : ll;
+}
+
+__global__ void __launch_bounds__(64) k_plain(PlainArgs a) {
+  __shared__ double lls[64];
+  __shared__ int sts[64];
+  double acc = 0.0;
+  int st = 0;
+  bool pnf = false;
+  for (int base = 0; base < a.P; base += 64) {
+    const int p = base + threadIdx.x;
+    if (p < a.P) {
+      int s = 0;
+      lls[threadIdx.x] = a.model == 1 ? plain_filter<2>(a, p, s)
+                                      : plain_filter<4>(a, p, s);
+      sts[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int n = a.P - base < 64 ? a.P - base : 64;
+      for (int q = 0; q < n; ++q) {
+        acc += lls[q];
+        if (sts[q] & kPNF)
+          pnf = true;
+        else if (sts[q] && !st)
+          st = sts[q];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (pnf) st = kNonFinite;
+    *a.logl = st ? -INFINITY : acc;
+    if (a.status) *a.status = st;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t st) {
+  if (a.N == 0) return hipSuccess;
+  const int blk = 256;
+  const int64_t grid = (a.N + blk - 1) / blk;
+  hipLaunchKernelGGL(k_stage, dim3((unsigned)grid), dim3(blk), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st) {
+  hipLaunchKernelGGL(k_hd, dim3(P), dim3(64), 0, st, pos, P, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
+                         hipStream_t st) {
+  if (model == 1)
+    hipLaunchKernelGGL(k_filter<1>, dim3(grid), dim3(block), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_filter<2>, dim3(grid), dim3(block), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
+  const int blk = 256;
+  const int64_t grid = a.S > 0 ? (a.S + blk - 1) / blk : 1;
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)grid), dim3(blk), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain(const PlainArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain, dim3(1), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace argus
