@@ -252,6 +252,7 @@ Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc) {
   if ((*rc = w->pstat.alloc(ps * sizeof(int32_t)))) return nullptr;
   if ((*rc = w->logl_tmp.alloc((size_t)S * sizeof(double)))) return nullptr;
   if ((*rc = w->counter.alloc(64))) return nullptr;
+  if ((*rc = w->stat_tmp.alloc((size_t)S * sizeof(int32_t)))) return nullptr;
   if (hipMemset(w->counter.p, 0, 64) != hipSuccess) {
     *rc = fail(ARGUS_E_HIP, "hipMemset");
     return nullptr;
@@ -481,8 +482,8 @@ extern "C" int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64
                                   double* logl, double* grad, int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
-  (void)grad;
-  (void)status;
-  (void)stream;
-  return fail(ARGUS_E_UNSUPPORTED, "gradient not available yet");
+  if (ds->D > 0 && !grad) return fail(ARGUS_E_INVAL, "grad is NULL");
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "the gradient covers models 1 and 2");
+  return grad_loglike(ds, theta, S, logl, grad, status, (hipStream_t)stream);
 }

@@ -64,9 +64,12 @@ struct Workspace {
   const void* g_theta = nullptr;
   const void* g_out = nullptr;
   const void* g_status = nullptr;
-  // gradient workspace
-  DevBuf ckpt, gpart;
-  int64_t ckpt_elems = 0;
+  // gradient workspace: level-1 checkpoints, per-wave level-2 scratch,
+  // per-pulsar gradient parts
+  DevBuf ckpt, scratch, gpart, c1, seg_base, stat_tmp;
+  int64_t tot_seg = 0;
+  int max_sub = 0, grad_waves = 0;
+  bool grad_ready = false;
   ~Workspace();
 };
 
@@ -88,4 +91,6 @@ int check_device(const argus_dataset* ds);
 Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc);
 int joint_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl,
                   int32_t* status, hipStream_t st);
+int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
+                 int32_t* status, hipStream_t st);
 }  // namespace argus

@@ -55,6 +55,38 @@ __device__ __forceinline__ TOARec load_rec(RecPtr r, int64_t k) {
   return x;
 }
 
+// exp(x) - 1 for the OU decays (x = -rate * dt <= 0 in every use). Range
+// reduction x = k ln2 + r, |r| <= ln2/2, with ln 2 split in two parts so that
+// k ln2_hi is exact (Cody & Waite 1980; the split of fdlibm); expm1(r) from
+// its Taylor series to degree 13, whose truncation error r^13/14! < 1.2e-17
+// relative; then expm1(x) = 2^k (expm1(r) + 1) - 1, formed as
+// 2^k expm1(r) + (2^k - 1), which is exact-ish because for k != 0 the result
+// is at least 0.29 in magnitude. 2^k underflows to 0 for x < -745: -1.
+// Taylor coefficients 1/n!, n = 2..13, read from constant memory so that the
+// compiler keeps them in SGPRs (a VOP3 FMA takes one SGPR operand) instead of
+// copying each into the accumulator of a two-address FMA.
+__constant__ double kExpm1Coef[12] = {
+    1.0 / 2.0,        1.0 / 6.0,         1.0 / 24.0,        1.0 / 120.0,
+    1.0 / 720.0,      1.0 / 5040.0,      1.0 / 40320.0,     1.0 / 362880.0,
+    1.0 / 3628800.0,  1.0 / 39916800.0,  1.0 / 479001600.0, 1.0 / 6227020800.0};
+
+__device__ __forceinline__ double expm1_k(double x) {
+  const double kInvLn2 = 1.44269504088896338700;
+  const double kLn2Hi = 6.93147180369123816490e-01;
+  const double kLn2Lo = 1.90821492927058770002e-10;
+  const double kf = __builtin_rint(x * kInvLn2);
+  double r = __builtin_fma(-kf, kLn2Hi, x);
+  r = __builtin_fma(-kf, kLn2Lo, r);
+  // Q(r) = sum_{n=2}^{13} r^(n-2) / n!
+  double q = kExpm1Coef[11];
+#pragma unroll
+  for (int i = 10; i >= 0; --i) q = __builtin_fma(q, r, kExpm1Coef[i]);
+  const double p = __builtin_fma(r * r, q, r);      // expm1(r)
+  const int k = (int)kf;
+  const double t = __builtin_ldexp(1.0, k < -1100 ? -1100 : k);
+  return k == 0 ? p : __builtin_fma(t, p, t - 1.0);
+}
+
 // 1/S from the hardware reciprocal refined by two Newton steps (error within
 // an ulp or so; S > 0 in every use that is not already flagged).
 __device__ __forceinline__ double rcp_nr(double S) {

@@ -1,0 +1,466 @@
+// Gradient of the batched per-pulsar log-likelihood by a hand-written
+// adjoint (reverse-mode) Kalman sweep. The paper's samplers consume the
+// likelihood and its gradient (Functionality, "Sampler Integration"); here
+// the gradient is the exact derivative of the same recursion.
+//
+// Per TOA the forward map is (x, P) -> (x+, P+) with
+//   x- = F x, P- = F P F^T + Q, e = y - h.x-, u = P- h, S = h.u + R,
+//   x+ = x- + u e / S,  P+ = P- - u u^T / S   (the Joseph form evaluated at the
+//   optimal gain; its derivative in K vanishes there, so this is also the
+//   derivative of the Joseph update the forward pass computes),
+//   l += -1/2 (ln S + e^2 / S).
+// With adjoints xb = dL/dx+ and the symmetric Mb = dL/dP+ (Frobenius pairing),
+//   a = xb.u, w = Mb u, b = u.w,
+//   g_e = (a - e)/S, g_S = (b - a e - S/2 + e^2/2)/S^2,
+//   g_u = (e/S) xb - (2/S) w,
+//   xb- = xb - g_e h,  Mb- = Mb + sym(g_u h^T) + g_S h h^T,  Rb = g_S,
+//   Qb = Mb-,  Fb = xb- x^T + 2 Mb- F P,  xb <- F^T xb-,  Mb <- F^T Mb- F,
+// and the parameters enter through F (red-OU decay), Q (red and common OU
+// noise, spin noise), R (EFAC, EQUAD) and the prior P0.
+//
+// Memory: level-1 checkpoints of (x, P) every c1 = ceil(sqrt(N_p)) TOAs
+// (rounded up to a multiple of 4) in HBM; in the reverse sweep each segment
+// is recomputed once to level-2 checkpoints every 4 TOAs (a per-wave scratch
+// area that stays cache-resident), and each 4-TOA piece is reversed from its
+// checkpoint with the state before each TOA recomputed in registers. Work: about 5 forward passes, no per-TOA HBM
+// traffic. Mapping as the forward filter: one wavefront per (64-sample tile,
+// pulsar), lane = sample, TOA records read with scalar loads.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "argus_host.h"
+#include "argus_internal.h"
+
+namespace argus {
+
+namespace {
+
+__device__ __forceinline__ bool finite_d(double v) {
+  return __builtin_amdgcn_class(v, 0x1F8);
+}
+
+struct Cov4 {
+  double rr, rf, ff, ra, fa, aa, rg, fg, ag, gg;
+};
+struct State {
+  double xr, xf, xa, xg;
+  Cov4 P;
+};
+struct LaneP {
+  double gr, vr, vc, efac2, equad2, ss2;
+};
+struct Grad {
+  double gam, v, vc, ef2, eq2, ss2;
+};
+
+constexpr int kFields = 14;  // x (4) + P (10)
+
+struct AdjArgs {
+  const TOARec* rec;
+  const int64_t* off;
+  const double* theta;
+  const int32_t* col;
+  const double* fixed;
+  const int32_t* items;
+  int32_t* counter;
+  const int32_t* c1;        // [P] level-1 stride per pulsar (multiple of 4)
+  const int64_t* seg_base;  // [P] first segment index of each pulsar
+  double* ckpt;             // [tiles * tot_seg * 14 * 64]
+  double* scratch;          // [nwaves * max_sub * 14 * 64]
+  double* part;             // [P*S] log-likelihood terms
+  int32_t* pstat;           // [P*S]
+  double* gpart;            // [P * 6 * S] per-pulsar parameter gradients
+  int64_t S, tot_seg;
+  int32_t D, P, n_items, max_sub, model;
+  ModelConst mc;
+};
+
+__device__ __forceinline__ void put_state(double* base, int lane, const State& s) {
+  const double v[kFields] = {s.xr,   s.xf,   s.xa,   s.xg,   s.P.rr, s.P.rf, s.P.ff,
+                             s.P.ra, s.P.fa, s.P.aa, s.P.rg, s.P.fg, s.P.ag, s.P.gg};
+#pragma unroll
+  for (int f = 0; f < kFields; ++f) base[f * kWave + lane] = v[f];
+}
+__device__ __forceinline__ State get_state(const double* base, int lane) {
+  double v[kFields];
+#pragma unroll
+  for (int f = 0; f < kFields; ++f) v[f] = base[f * kWave + lane];
+  return State{v[0], v[1], v[2], v[3],
+               Cov4{v[4], v[5], v[6], v[7], v[8], v[9], v[10], v[11], v[12], v[13]}};
+}
+
+// Predicted state and covariance over one interval (F P F^T + Q).
+struct Pred {
+  double xr, xf, xa, xg;
+  Cov4 P;
+  double em, ph;
+};
+__device__ __forceinline__ Pred predict(const State& s, const TOARec& r, const LaneP& L) {
+  Pred o;
+  const double dt = r.dt;
+  o.em = expm1_k(-L.gr * dt);
+  o.ph = 1.0 + o.em;
+  const double qr = L.vr * (-o.em * (2.0 + o.em));
+  const double phc = r.phc, qc = L.vc * r.qcu;
+  o.xr = fma(dt, s.xf, s.xr);
+  o.xf = s.xf;
+  o.xa = o.ph * s.xa;
+  o.xg = phc * s.xg;
+  const double prf1 = fma(dt, s.P.ff, s.P.rf);
+  o.P.rr = fma(dt, s.P.rf + prf1, s.P.rr) + L.ss2 * r.h3;
+  o.P.rf = prf1 + L.ss2 * r.h2;
+  o.P.ff = s.P.ff + L.ss2 * dt;
+  o.P.ra = o.ph * fma(dt, s.P.fa, s.P.ra);
+  o.P.fa = o.ph * s.P.fa;
+  o.P.aa = fma(o.ph * o.ph, s.P.aa, qr);
+  o.P.rg = phc * fma(dt, s.P.fg, s.P.rg);
+  o.P.fg = phc * s.P.fg;
+  o.P.ag = (o.ph * phc) * s.P.ag;
+  o.P.gg = fma(phc * phc, s.P.gg, qc);
+  return o;
+}
+
+#define JOSEPH(pij, ki, uj, di, kj) pij = fma(di, kj, fma(-(ki), uj, pij))
+
+// One forward step in place; returns S and e.
+__device__ __forceinline__ void fwd_step(State& s, const TOARec& r, const LaneP& L, double& S,
+                                         double& e, double& inv) {
+  const Pred p = predict(s, r, L);
+  e = r.y - (p.xr + p.xa + p.xg);
+  const double ur = p.P.rr + p.P.ra + p.P.rg;
+  const double uf = p.P.rf + p.P.fa + p.P.fg;
+  const double ua = p.P.ra + p.P.aa + p.P.ag;
+  const double ug = p.P.rg + p.P.ag + p.P.gg;
+  S = (ur + ua + ug) + fma(L.efac2, r.s2, L.equad2);
+  inv = rcp_nr(S);
+  const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
+  s.xr = fma(kr, e, p.xr);
+  s.xf = fma(kf, e, p.xf);
+  s.xa = fma(ka, e, p.xa);
+  s.xg = fma(kg, e, p.xg);
+  const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+  const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug);
+  Cov4 P = p.P;
+  JOSEPH(P.rr, kr, ur, dr, kr);
+  JOSEPH(P.rf, kr, uf, dr, kf);
+  JOSEPH(P.ff, kf, uf, df, kf);
+  JOSEPH(P.ra, kr, ua, dr, ka);
+  JOSEPH(P.fa, kf, ua, df, ka);
+  JOSEPH(P.aa, ka, ua, da, ka);
+  JOSEPH(P.rg, kr, ug, dr, kg);
+  JOSEPH(P.fg, kf, ug, df, kg);
+  JOSEPH(P.ag, ka, ug, da, kg);
+  JOSEPH(P.gg, kg, ug, dg, kg);
+  s.P = P;
+}
+
+__device__ __forceinline__ void fwd_only(State& s, const TOARec& r, const LaneP& L) {
+  double S, e, inv;
+  fwd_step(s, r, L, S, e, inv);
+}
+
+// Reverse of one step. sp = posterior before the step; (xb, Mb) adjoints of
+// the posterior after it, replaced by the adjoints of sp.
+__device__ __forceinline__ void rev_step(const State& sp, const TOARec& r, const LaneP& L,
+                                         double xb[4], Cov4& M, Grad& G) {
+  const Pred p = predict(sp, r, L);
+  const double dt = r.dt, phc = r.phc;
+  const double e = r.y - (p.xr + p.xa + p.xg);
+  const double u[4] = {p.P.rr + p.P.ra + p.P.rg, p.P.rf + p.P.fa + p.P.fg,
+                       p.P.ra + p.P.aa + p.P.ag, p.P.rg + p.P.ag + p.P.gg};
+  const double S = (u[0] + u[2] + u[3]) + fma(L.efac2, r.s2, L.equad2);
+  const double inv = rcp_nr(S);
+  const double a = xb[0] * u[0] + xb[1] * u[1] + xb[2] * u[2] + xb[3] * u[3];
+  const double w[4] = {M.rr * u[0] + M.rf * u[1] + M.ra * u[2] + M.rg * u[3],
+                       M.rf * u[0] + M.ff * u[1] + M.fa * u[2] + M.fg * u[3],
+                       M.ra * u[0] + M.fa * u[1] + M.aa * u[2] + M.ag * u[3],
+                       M.rg * u[0] + M.fg * u[1] + M.ag * u[2] + M.gg * u[3]};
+  const double b = u[0] * w[0] + u[1] * w[1] + u[2] * w[2] + u[3] * w[3];
+  const double ge = (a - e) * inv;
+  const double gS = (b - a * e - 0.5 * S + 0.5 * e * e) * (inv * inv);
+  const double ei = e * inv, ti = 2.0 * inv;
+  double gu[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) gu[i] = ei * xb[i] - ti * w[i];
+  // adjoints of the predicted mean and covariance (h = [1, 0, 1, 1])
+  const double xm[4] = {xb[0] - ge, xb[1], xb[2] - ge, xb[3] - ge};
+  Cov4 Mm;
+  Mm.rr = M.rr + gu[0] + gS;
+  Mm.rf = M.rf + 0.5 * gu[1];
+  Mm.ff = M.ff;
+  Mm.ra = M.ra + 0.5 * (gu[0] + gu[2]) + gS;
+  Mm.fa = M.fa + 0.5 * gu[1];
+  Mm.aa = M.aa + gu[2] + gS;
+  Mm.rg = M.rg + 0.5 * (gu[0] + gu[3]) + gS;
+  Mm.fg = M.fg + 0.5 * gu[1];
+  Mm.ag = M.ag + 0.5 * (gu[2] + gu[3]) + gS;
+  Mm.gg = M.gg + gu[3] + gS;
+  // parameters through R and Q
+  G.ef2 = fma(gS, r.s2, G.ef2);
+  G.eq2 += gS;
+  G.v = fma(Mm.aa, -p.em * (2.0 + p.em), G.v);
+  G.vc = fma(Mm.gg, r.qcu, G.vc);
+  G.ss2 += Mm.rr * r.h3 + 2.0 * Mm.rf * r.h2 + Mm.ff * dt;
+  // through the red-OU decay phi = F_aa: dL/dphi = xm_a x_a + 2 (Mm F P)_aa
+  const double ph = p.ph;
+  const double fpaa = Mm.ra * fma(dt, sp.P.fa, sp.P.ra) + Mm.fa * sp.P.fa +
+                      Mm.aa * (ph * sp.P.aa) + Mm.ag * (phc * sp.P.ag);
+  const double phib = fma(xm[2], sp.xa, 2.0 * fpaa);
+  G.gam = fma(dt * ph, 2.0 * L.vr * ph * Mm.aa - phib, G.gam);
+  // back through F: xb = F^T xm, M = F^T Mm F
+  xb[0] = xm[0];
+  xb[1] = fma(dt, xm[0], xm[1]);
+  xb[2] = ph * xm[2];
+  xb[3] = phc * xm[3];
+  M.rr = Mm.rr;
+  M.rf = fma(dt, Mm.rr, Mm.rf);
+  M.ff = fma(dt, fma(dt, Mm.rr, 2.0 * Mm.rf), Mm.ff);
+  M.ra = ph * Mm.ra;
+  M.fa = ph * fma(dt, Mm.ra, Mm.fa);
+  M.rg = phc * Mm.rg;
+  M.fg = phc * fma(dt, Mm.rg, Mm.fg);
+  M.aa = (ph * ph) * Mm.aa;
+  M.ag = (ph * phc) * Mm.ag;
+  M.gg = (phc * phc) * Mm.gg;
+}
+
+__device__ __forceinline__ double prm(const AdjArgs& a, int c, int64_t s) {
+  const int j = a.col[c];
+  return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
+}
+
+__global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gwave = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  double* scr = a.scratch + (int64_t)gwave * a.max_sub * kFields * kWave;
+  const RecPtr rec = (RecPtr)a.rec;
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int it = __builtin_amdgcn_readfirstlane(v);
+    if (it >= a.n_items) break;
+    const int tile = a.items[2 * it];
+    const int p = a.items[2 * it + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int64_t kb = a.off[p], N = a.off[p + 1] - kb;
+    const int c1 = a.c1[p];
+    double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
+
+    // parameters of this lane's filter
+    LaneP L;
+    double t0, t1, t2, t3, t4 = 0.0, t5 = 2.0;
+    bool pnf;
+    if (a.model == 1) {
+      t0 = prm(a, 0, s);  // log10 sigma_s
+      t1 = prm(a, 1, s);  // EFAC
+      pnf = !(finite_d(t0) && finite_d(t1));
+      const double ss = exp10(t0);
+      L = LaneP{1.0, 0.0, 0.0, t1 * t1, 0.0, ss * ss};
+      t2 = t3 = 0.0;
+    } else {
+      const int c0 = 4 * p, cc = 4 * a.P;
+      t0 = prm(a, c0, s);
+      t1 = prm(a, c0 + 1, s);
+      t2 = prm(a, c0 + 2, s);
+      t3 = prm(a, c0 + 3, s);
+      t4 = prm(a, cc, s);
+      t5 = prm(a, cc + 1, s);
+      pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) && finite_d(t4) &&
+              finite_d(t5));
+      const double gr = exp10(t1), sr = exp10(t0), eq = exp10(t3);
+      const double gm1 = t5 - 1.0;
+      const double vc = exp(2.0 * kLn10 * t4 + (t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+                        (12.0 * kPi * kPi * gm1);
+      L = LaneP{gr, sr * sr / (2.0 * gr), vc, t2 * t2, eq * eq, a.mc.ss2};
+    }
+
+    // ---------------- forward pass: log-likelihood + level-1 checkpoints
+    State st{0.0, 0.0, 0.0, 0.0,
+             Cov4{a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, 0.0, L.vr, 0.0, 0.0, 0.0, L.vc}};
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+    int kc = 0;                 // position within the current segment
+    double* ckw = ck;           // next level-1 checkpoint slot
+    for (int64_t k = 0; k < N; ++k) {
+      if (kc == 0) {
+        put_state(ckw, lane, st);
+        ckw += kFields * kWave;
+      }
+      kc = kc + 1 == c1 ? 0 : kc + 1;
+      double S, e, inv;
+      fwd_step(st, load_rec(rec, kb + k), L, S, e, inv);
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e * e, inv, quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    }
+    double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+    if (stat) ll = -INFINITY;
+
+    // ---------------- reverse sweep
+    double xb[4] = {0.0, 0.0, 0.0, 0.0};
+    Cov4 M{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Grad G{0, 0, 0, 0, 0, 0};
+    const int64_t nseg = (N + c1 - 1) / c1;
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+      const int64_t k0 = sg * c1;
+      const int64_t k1 = k0 + c1 < N ? k0 + c1 : N;
+      const int nsub = (int)((k1 - k0 + 3) / 4);
+      // recompute the segment to level-2 checkpoints every 4 TOAs
+      State cur = get_state(ck + sg * kFields * kWave, lane);
+      for (int t = 0; t < nsub; ++t) {
+        put_state(scr + (int64_t)t * kFields * kWave, lane, cur);
+        if (t + 1 < nsub) {
+          const int64_t kk = kb + k0 + 4 * t;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) fwd_only(cur, load_rec(rec, kk + i), L);
+        }
+      }
+      // reverse each 4-TOA piece, last first: the state before TOA i of the
+      // piece is recomputed from the piece's checkpoint (0..3 steps), so
+      // only two states are live in registers
+      for (int t = nsub - 1; t >= 0; --t) {
+        const int64_t ks = k0 + 4 * t;
+        const int nt = (int)(k1 - ks < 4 ? k1 - ks : 4);
+        const int64_t kk = kb + ks;
+        const State s0 = get_state(scr + (int64_t)t * kFields * kWave, lane);
+        for (int i = nt - 1; i >= 0; --i) {
+          State cur = s0;
+          for (int j = 0; j < i; ++j) fwd_only(cur, load_rec(rec, kk + j), L);
+          rev_step(cur, load_rec(rec, kk + i), L, xb, M, G);
+        }
+      }
+    }
+    // the prior P0 = diag(s_r^2, s_f^2, v_r, v_c)
+    G.v += M.aa;
+    G.vc += M.gg;
+
+    if (valid) {
+      a.part[(int64_t)p * a.S + s] = ll;
+      a.pstat[(int64_t)p * a.S + s] = stat;
+      double* g = a.gpart + (int64_t)p * 6 * a.S + s;
+      if (a.model == 1) {
+        g[0] = G.ss2 * 2.0 * kLn10 * L.ss2;  // log10 sigma_s
+        g[a.S] = G.ef2 * 2.0 * t1;           // EFAC
+      } else {
+        g[0] = G.v * 2.0 * kLn10 * L.vr;                                // log10 sigma_red
+        g[a.S] = kLn10 * (G.gam * L.gr - G.v * L.vr);                   // log10 gamma_red
+        g[2 * a.S] = G.ef2 * 2.0 * t2;                                  // EFAC
+        g[3 * a.S] = G.eq2 * 2.0 * kLn10 * L.equad2;                    // log10 EQUAD
+        g[4 * a.S] = G.vc * 2.0 * kLn10 * L.vc;                         // log10 A
+        g[5 * a.S] = G.vc * L.vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / (t5 - 1.0));  // gamma
+      }
+    }
+  }
+}
+
+// grad[s, col(c)] from the per-pulsar parts: a pulsar's own parameters from
+// its filter, the common ones summed over pulsars in index order; rows of
+// failed samples are zero.
+__global__ void k_grad_reduce(const double* gpart, const int32_t* status, const int32_t* col,
+                              double* grad, int64_t S, int D, int P, int model) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const bool bad = status[s] != 0;
+  double* g = grad + s * D;
+  if (model == 1) {
+    for (int c = 0; c < 2; ++c)
+      if (col[c] >= 0) g[col[c]] = bad ? 0.0 : gpart[(int64_t)c * S + s];
+    return;
+  }
+  for (int p = 0; p < P; ++p)
+    for (int j = 0; j < 4; ++j) {
+      const int cj = col[4 * p + j];
+      if (cj >= 0) g[cj] = bad ? 0.0 : gpart[((int64_t)p * 6 + j) * S + s];
+    }
+  for (int j = 0; j < 2; ++j) {
+    const int cj = col[4 * P + j];
+    if (cj < 0) continue;
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p) acc += gpart[((int64_t)p * 6 + 4 + j) * S + s];
+    g[cj] = bad ? 0.0 : acc;
+  }
+}
+
+}  // namespace
+
+int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
+                 int32_t* status, hipStream_t st) {
+  int rc = ARGUS_OK;
+  Workspace* w = get_workspace(ds, S, &rc);
+  if (!w) return rc;
+  const int64_t tiles = (S + kWave - 1) / kWave;
+  if (!w->grad_ready) {
+    // level-1 strides and segment offsets
+    std::vector<int32_t> c1(ds->P);
+    std::vector<int64_t> base(ds->P);
+    int64_t tot = 0;
+    int cmax = 4;
+    for (int p = 0; p < ds->P; ++p) {
+      const int64_t n = ds->counts[p];
+      int64_t r = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1)));
+      r = ((r + 3) / 4) * 4;
+      c1[p] = (int32_t)r;
+      cmax = std::max<int>(cmax, (int)r);
+      base[p] = tot;
+      tot += (n + r - 1) / r;
+    }
+    w->tot_seg = tot;
+    w->max_sub = cmax / 4;
+    w->grad_waves = (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu);
+    w->grad_waves = ((w->grad_waves + 3) / 4) * 4;
+    if ((rc = w->c1.upload(c1.data(), c1.size() * sizeof(int32_t))) ||
+        (rc = w->seg_base.upload(base.data(), base.size() * sizeof(int64_t))) ||
+        (rc = w->ckpt.alloc((size_t)std::max<int64_t>(tiles * tot, 1) * kFields * kWave *
+                            sizeof(double))) ||
+        (rc = w->scratch.alloc((size_t)w->grad_waves * w->max_sub * kFields * kWave *
+                               sizeof(double))) ||
+        (rc = w->gpart.alloc((size_t)ds->P * 6 * S * sizeof(double))))
+      return rc;
+    w->grad_ready = true;
+  }
+  AdjArgs a{};
+  a.rec = ds->rec.as<TOARec>();
+  a.off = ds->off.as<int64_t>();
+  a.theta = theta;
+  a.col = ds->col.as<int32_t>();
+  a.fixed = ds->fixed.as<double>();
+  a.items = w->items.as<int32_t>();
+  a.counter = w->counter.as<int32_t>();
+  a.c1 = w->c1.as<int32_t>();
+  a.seg_base = w->seg_base.as<int64_t>();
+  a.ckpt = w->ckpt.as<double>();
+  a.scratch = w->scratch.as<double>();
+  a.part = w->part.as<double>();
+  a.pstat = w->pstat.as<int32_t>();
+  a.gpart = w->gpart.as<double>();
+  a.S = S;
+  a.tot_seg = w->tot_seg;
+  a.D = ds->D;
+  a.P = ds->P;
+  a.n_items = w->n_items;
+  a.max_sub = w->max_sub;
+  a.model = ds->model;
+  a.mc = ds->mc;
+  hipLaunchKernelGGL(k_adjoint, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+  HIPCHK(hipGetLastError());
+  int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();
+  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, stat,
+               w->counter.as<int32_t>(), S, ds->P};
+  HIPCHK(launch_reduce(r, st));
+  const int blk = 256;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((S + blk - 1) / blk)), dim3(blk), 0, st,
+                     w->gpart.as<double>(), stat, ds->col.as<int32_t>(), grad, S, ds->D,
+                     ds->P, ds->model);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+}  // namespace argus

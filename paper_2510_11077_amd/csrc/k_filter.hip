@@ -29,10 +29,13 @@ __device__ __forceinline__ bool finite_d(double v) {
 }
 
 // First-failure classification, same order of tests as the definition:
-// a non-finite S or e is NONFINITE, otherwise S <= 0 is NONPD.
-__device__ __forceinline__ int step_status(double S, double e) {
-  if (!finite_d(S) || !finite_d(e)) return kNonFinite;
-  return S > 0.0 ? 0 : kNonPD;
+// a non-finite S or e is NONFINITE, otherwise S <= 0 is NONPD. The common
+// case (S positive and finite, e finite) costs two class tests.
+__device__ __forceinline__ void step_status(int& st, double S, double e) {
+  const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+  if (__builtin_expect(!good, 0)) {
+    if (st == 0) st = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+  }
 }
 
 struct LogAcc {
@@ -63,9 +66,12 @@ __device__ __forceinline__ double common_var(double la, double gc,
          (12.0 * kPi * kPi * gm1);
 }
 
-// Symmetric rank-2 Joseph update of one covariance entry.
-#define JOSEPH(pij, ki, ui, wi, kj, uj) \
-  pij = fma(wi, kj, fma(-(ui), kj, fma(-(ki), uj, pij)))
+// Joseph update of one covariance entry. The symmetric rank-2 form
+// P - K u^T - u K^T + S K K^T is regrouped as P - K u^T + (S K - u) K^T,
+// the same expression for any gain K; d = S K - u is formed with one
+// rounding (fma), so the small residual of the optimal gain is not lost to
+// cancellation.
+#define JOSEPH(pij, ki, uj, di, kj) pij = fma(di, kj, fma(-(ki), uj, pij))
 
 // ------------------------------------------------------------ model 2 step
 struct F4 {
@@ -82,7 +88,7 @@ __device__ __forceinline__ void step4(F4& f, const TOARec r, double gr,
   const double dt = r.dt;
   // red OU over dt for this lane's rate: phi = 1 + expm1(-g dt),
   // q = v (1 - phi^2) = -v em (2 + em) without cancellation
-  const double em = expm1(-gr * dt);
+  const double em = expm1_k(-gr * dt);
   const double phr = 1.0 + em;
   const double qr = vr * (-em * (2.0 + em));
   const double phc = r.phc;
@@ -110,24 +116,25 @@ __device__ __forceinline__ void step4(F4& f, const TOARec r, double gr,
   const double ua = f.pra + f.paa + f.pag;
   const double ug = f.prg + f.pag + f.pgg;
   const double S = (ur + ua + ug) + fma(efac2, r.s2, equad2);
-  if (f.st == 0) f.st = step_status(S, e);
+  step_status(f.st, S, e);
   const double inv = rcp_nr(S);
   const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
   f.xr = fma(kr, e, f.xr);
   f.xf = fma(kf, e, f.xf);
   f.xa = fma(ka, e, f.xa);
   f.xg = fma(kg, e, f.xg);
-  const double wr = S * kr, wf = S * kf, wa = S * ka, wg = S * kg;
-  JOSEPH(f.prr, kr, ur, wr, kr, ur);
-  JOSEPH(f.prf, kr, ur, wr, kf, uf);
-  JOSEPH(f.pff, kf, uf, wf, kf, uf);
-  JOSEPH(f.pra, kr, ur, wr, ka, ua);
-  JOSEPH(f.pfa, kf, uf, wf, ka, ua);
-  JOSEPH(f.paa, ka, ua, wa, ka, ua);
-  JOSEPH(f.prg, kr, ur, wr, kg, ug);
-  JOSEPH(f.pfg, kf, uf, wf, kg, ug);
-  JOSEPH(f.pag, ka, ua, wa, kg, ug);
-  JOSEPH(f.pgg, kg, ug, wg, kg, ug);
+  const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+  const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug);
+  JOSEPH(f.prr, kr, ur, dr, kr);
+  JOSEPH(f.prf, kr, uf, dr, kf);
+  JOSEPH(f.pff, kf, uf, df, kf);
+  JOSEPH(f.pra, kr, ua, dr, ka);
+  JOSEPH(f.pfa, kf, ua, df, ka);
+  JOSEPH(f.paa, ka, ua, da, ka);
+  JOSEPH(f.prg, kr, ug, dr, kg);
+  JOSEPH(f.pfg, kf, ug, df, kg);
+  JOSEPH(f.pag, ka, ug, da, kg);
+  JOSEPH(f.pgg, kg, ug, dg, kg);
   f.quad = fma(e * e, inv, f.quad);
   acc_mul(f.L, S);
 }
@@ -150,15 +157,15 @@ __device__ __forceinline__ void step2(F2& f, const TOARec r, double ss2,
   const double e = r.y - f.xr;
   const double ur = f.prr, uf = f.prf;
   const double S = ur + efac2 * r.s2;
-  if (f.st == 0) f.st = step_status(S, e);
+  step_status(f.st, S, e);
   const double inv = rcp_nr(S);
   const double kr = ur * inv, kf = uf * inv;
   f.xr = fma(kr, e, f.xr);
   f.xf = fma(kf, e, f.xf);
-  const double wr = S * kr, wf = S * kf;
-  JOSEPH(f.prr, kr, ur, wr, kr, ur);
-  JOSEPH(f.prf, kr, ur, wr, kf, uf);
-  JOSEPH(f.pff, kf, uf, wf, kf, uf);
+  const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+  JOSEPH(f.prr, kr, ur, dr, kr);
+  JOSEPH(f.prf, kr, uf, dr, kf);
+  JOSEPH(f.pff, kf, uf, df, kf);
   f.quad = fma(e * e, inv, f.quad);
   acc_mul(f.L, S);
 }
@@ -382,7 +389,7 @@ __device__ double plain_filter(const PlainArgs& a, int p, int& st) {
       for (int m = 0; m < N; ++m) u[i] += Pp[i][m] * H[m];
       S += H[i] * u[i];
     }
-    if (st == 0) st = step_status(S, e);
+    step_status(st, S, e);
     double K[N], A[N][N];
     for (int i = 0; i < N; ++i) {
       K[i] = u[i] / S;

@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxP = kJointMaxPsr;
+constexpr int kChunk = 64;  // TOAs per decay table / ledger fold
 
 __device__ __forceinline__ bool finite_d(double v) {
   return __builtin_amdgcn_class(v, 0x1F8);
@@ -54,7 +55,11 @@ __device__ __forceinline__ double prm(const JointArgs& a, int c, int64_t s) {
 }
 
 __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
-  __shared__ double s_phr[2][kMaxP], s_qr[2][kMaxP];
+  // red-OU decay and noise of every pulsar for the next kChunk TOAs
+  __shared__ double s_ph[kChunk][kMaxP], s_q[kChunk][kMaxP];
+  // (S, e) of each TOA of the chunk, folded into the likelihood by wave 0
+  __shared__ double s_led[kChunk][2];
+  __shared__ double s_rec[kChunk][8];
   __shared__ double s_u[2][4 * kMaxP];
   __shared__ double s_e[2];
   __shared__ double s_vr[kMaxP], s_gr[kMaxP], s_ef2[kMaxP], s_eq2[kMaxP];
@@ -62,6 +67,7 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   __shared__ int s_pnf;
 
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
   const int64_t s = blockIdx.x;
   const int P = a.P;
   const int nb = P * (P + 1) / 2;
@@ -78,9 +84,6 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   }
   const bool owner = tid < nb;
   const bool diag = owner && ba == bb;
-  // threads that evaluate per-pulsar red-OU decays: the last P threads
-  const int q_phi = tid - (kThreads - P);
-  const bool phi_thr = q_phi >= 0;
 
   if (tid == 0) {
     const double la = prm(a, 4 * P, s), gc = prm(a, 4 * P + 1, s);
@@ -90,30 +93,23 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
     s_pnf = (finite_d(la) && finite_d(gc)) ? 0 : 1;
   }
   __syncthreads();
-  double gr_q = 0.0, vr_q = 0.0;
-  if (phi_thr) {
-    const int q = q_phi;
+  if (tid < P) {
+    const int q = tid;
     const double lsr = prm(a, 4 * q, s), lgr = prm(a, 4 * q + 1, s);
     const double ef = prm(a, 4 * q + 2, s), leq = prm(a, 4 * q + 3, s);
     if (!(finite_d(lsr) && finite_d(lgr) && finite_d(ef) && finite_d(leq)))
       atomicOr(&s_pnf, 1);
-    gr_q = exp10(lgr);
+    const double gr = exp10(lgr);
     const double sr = exp10(lsr), eq = exp10(leq);
-    vr_q = sr * sr / (2.0 * gr_q);
-    s_vr[q] = vr_q;
-    s_gr[q] = gr_q;
+    s_vr[q] = sr * sr / (2.0 * gr);
+    s_gr[q] = gr;
     s_ef2[q] = ef * ef;
     s_eq2[q] = eq * eq;
-    if (a.N > 0) {
-      const double em = expm1(-gr_q * a.rec[0].dt);
-      s_phr[0][q] = 1.0 + em;
-      s_qr[0][q] = vr_q * (-em * (2.0 + em));
-    }
   }
   __syncthreads();
   const double vc = s_vc;
   const double gvc = owner ? a.hd[ba * P + bb] * vc : 0.0;  // G_ab v_c
-  // covariance block P[i][j] = Cov(state i of pulsar ba, state j of pulsar bb)
+  // covariance block B[i][j] = Cov(state i of pulsar ba, state j of pulsar bb)
   double B[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -127,102 +123,161 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   B[3][3] = gvc;
   double x[4] = {0.0, 0.0, 0.0, 0.0};  // mean of pulsar ba (diagonal owners)
   const double ss2 = a.mc.ss2;
+  // per-lane ledger of wave 0: lane l folds TOAs k = l mod kChunk
   double quad = 0.0, lm = 1.0;
-  int le = 0, st = s_pnf ? kPNF : 0;
+  int le = 0, fail_code = 0;
+  int64_t fail_k = INT64_MAX;
 
-  const RecPtr rec = (RecPtr)a.rec;
-  for (int64_t k = 0; k < a.N; ++k) {
-    const int buf = (int)(k & 1);
-    const TOARec r = load_rec(rec, k);
-    const int p = r.psr;
-    const double dt = r.dt, phc = r.phc;
-    if (owner) {
-      const double pa = s_phr[buf][ba], pb = s_phr[buf][bb];
-      // rows: F_a B
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        B[0][j] = fma(dt, B[1][j], B[0][j]);
-        B[2][j] *= pa;
-        B[3][j] *= phc;
-      }
-      // columns: (F_a B) F_b^T
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        B[i][0] = fma(dt, B[i][1], B[i][0]);
-        B[i][2] *= pb;
-        B[i][3] *= phc;
-      }
-      B[3][3] = fma(gvc, r.qcu, B[3][3]);
-      if (diag) {
-        B[0][0] += ss2 * r.h3;
-        B[0][1] += ss2 * r.h2;
-        B[1][0] += ss2 * r.h2;
-        B[1][1] += ss2 * dt;
-        B[2][2] += s_qr[buf][ba];
-        x[0] = fma(dt, x[1], x[0]);
-        x[2] *= pa;
-        x[3] *= phc;
-        if (ba == p) s_e[buf] = r.y - (x[0] + x[2] + x[3]);
-      }
-      // u = P H^T for the pulsar paired with p in this block
-      if (bb == p) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s_u[buf][4 * ba + i] = B[i][0] + B[i][2] + B[i][3];
-      } else if (ba == p) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) s_u[buf][4 * bb + j] = B[0][j] + B[2][j] + B[3][j];
-      }
-    }
-    if (phi_thr && k + 1 < a.N) {
-      const double em = expm1(-gr_q * rec[k + 1].dt);
-      s_phr[buf ^ 1][q_phi] = 1.0 + em;
-      s_qr[buf ^ 1][q_phi] = vr_q * (-em * (2.0 + em));
+  for (int64_t k0 = 0; k0 < a.N; k0 += kChunk) {
+    const int n = (int)(a.N - k0 < kChunk ? a.N - k0 : kChunk);
+    // stage the chunk's TOA records in LDS (8 doubles each; the last slot
+    // carries the pulsar index) and build its decay table, (TOA j, pulsar q)
+    // spread over all threads
+    for (int idx = tid; idx < n * 8; idx += kThreads)
+      s_rec[idx >> 3][idx & 7] = reinterpret_cast<const double*>(a.rec + k0)[idx];
+    for (int idx = tid; idx < n * P; idx += kThreads) {
+      const int q = idx / n, j = idx - q * n;
+      const double em = expm1_k(-s_gr[q] * a.rec[k0 + j].dt);
+      s_ph[j][q] = 1.0 + em;
+      s_q[j][q] = s_vr[q] * (-em * (2.0 + em));
     }
     __syncthreads();
-    const double* u = s_u[buf];
-    const double S =
-        (u[4 * p] + u[4 * p + 2] + u[4 * p + 3]) + fma(s_ef2[p], r.s2, s_eq2[p]);
-    const double inv = rcp_nr(S);
-    const double e = s_e[buf];
-    if (owner) {
-      double ua[4], ub[4], ka[4], kb[4], wa[4];
+    // values of TOA j used before the barrier; those of j + 1 are read from
+    // LDS during the update phase of j, off the critical path
+    double r_dt = s_rec[0][0], r_h2 = s_rec[0][1], r_h3 = s_rec[0][2];
+    double r_phc = s_rec[0][3], r_qcu = s_rec[0][4], r_y = s_rec[0][5];
+    double r_s2 = s_rec[0][6];
+    int r_p = __double_as_longlong(s_rec[0][7]) & 0xffffffff;
+    double pa = s_ph[0][ba], pb = s_ph[0][bb], qa = s_q[0][ba];
+    for (int j = 0; j < n; ++j) {
+      const int64_t k = k0 + j;
+      const int buf = (int)(k & 1);
+      const int p = __builtin_amdgcn_readfirstlane(r_p);
+      const double dt = r_dt, phc = r_phc;
+      if (owner) {
+        // rows: F_a B
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ua[i] = u[4 * ba + i];
-        ub[i] = u[4 * bb + i];
-        ka[i] = ua[i] * inv;
-        kb[i] = ub[i] * inv;
-        wa[i] = S * ka[i];
+        for (int c = 0; c < 4; ++c) {
+          B[0][c] = fma(dt, B[1][c], B[0][c]);
+          B[2][c] *= pa;
+          B[3][c] *= phc;
+        }
+        // columns: (F_a B) F_b^T
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          B[i][0] = fma(dt, B[i][1], B[i][0]);
+          B[i][2] *= pb;
+          B[i][3] *= phc;
+        }
+        B[3][3] = fma(gvc, r_qcu, B[3][3]);
+        if (diag) {
+          B[0][0] += ss2 * r_h3;
+          B[0][1] += ss2 * r_h2;
+          B[1][0] += ss2 * r_h2;
+          B[1][1] += ss2 * dt;
+          B[2][2] += qa;
+          x[0] = fma(dt, x[1], x[0]);
+          x[2] *= pa;
+          x[3] *= phc;
+          if (ba == p) s_e[buf] = r_y - (x[0] + x[2] + x[3]);
+        }
+        // u = P H^T for the pulsar paired with p in this block
+        if (bb == p) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s_u[buf][4 * ba + i] = B[i][0] + B[i][2] + B[i][3];
+        } else if (ba == p) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s_u[buf][4 * bb + c] = B[0][c] + B[2][c] + B[3][c];
+        }
       }
+      __syncthreads();
+      const double s2 = r_s2;
+      if (j + 1 < n) {
+        r_dt = s_rec[j + 1][0];
+        r_h2 = s_rec[j + 1][1];
+        r_h3 = s_rec[j + 1][2];
+        r_phc = s_rec[j + 1][3];
+        r_qcu = s_rec[j + 1][4];
+        r_y = s_rec[j + 1][5];
+        r_s2 = s_rec[j + 1][6];
+        r_p = __double_as_longlong(s_rec[j + 1][7]) & 0xffffffff;
+        pa = s_ph[j + 1][ba];
+        pb = s_ph[j + 1][bb];
+        qa = s_q[j + 1][ba];
+      }
+      const double* u = s_u[buf];
+      const double S =
+          (u[4 * p] + u[4 * p + 2] + u[4 * p + 3]) + fma(s_ef2[p], s2, s_eq2[p]);
+      const double inv = rcp_nr(S);
+      if (owner) {
+        double ua[4], ub[4], ka[4], kb[4], da[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
+          ua[i] = u[4 * ba + i];
+          ub[i] = u[4 * bb + i];
+          ka[i] = ua[i] * inv;
+          kb[i] = ub[i] * inv;
+          da[i] = fma(S, ka[i], -ua[i]);
+        }
+        // Joseph form P - K u^T - u K^T + S K K^T = P - K u^T + (S K - u) K^T
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          B[i][j] = fma(wa[i], kb[j], fma(-ua[i], kb[j], fma(-ka[i], ub[j], B[i][j])));
-      if (diag) {
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = fma(ka[i], e, x[i]);
+          for (int c = 0; c < 4; ++c) B[i][c] = fma(da[i], kb[c], fma(-ka[i], ub[c], B[i][c]));
+        if (diag) {
+          const double e = s_e[buf];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[i] = fma(ka[i], e, x[i]);
+        }
+      }
+      if (tid == 0) {
+        s_led[j][0] = S;
+        s_led[j][1] = s_e[buf];
       }
     }
-    if (tid == 0) {
-      if (st == 0) {
-        if (!finite_d(S) || !finite_d(e))
-          st = kNonFinite;
-        else if (!(S > 0.0))
-          st = kNonPD;
+    // wave 0 folds the chunk's innovations into its per-lane ledger
+    if (tid < kWave && lane < n) {
+      const double S = s_led[lane][0], e = s_led[lane][1];
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && fail_code == 0) {
+        fail_code = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+        fail_k = k0 + lane;
       }
-      quad = fma(e * e, inv, quad);
+      quad = fma(e * e, rcp_nr(S), quad);
       const double pm = lm * S;
       lm = __builtin_amdgcn_frexp_mant(pm);
       le += __builtin_amdgcn_frexp_exp(pm);
     }
   }
-  if (tid == 0) {
-    if (st & kPNF) st = kNonFinite;
-    double ll = -0.5 * ((double)a.N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
-    if (st == 0 && !finite_d(ll)) st = kNonFinite;
-    a.logl[s] = st ? -INFINITY : ll;
-    if (a.status) a.status[s] = st;
+  // wave 0: combine the lanes in lane order; first failure = smallest TOA
+  if (tid < kWave) {
+    __shared__ double s_fold[kWave][2];
+    __shared__ int64_t s_fk[kWave];
+    __shared__ int s_fc[kWave];
+    s_fold[lane][0] = quad;
+    s_fold[lane][1] = log(lm) + (double)le * kLn2;
+    s_fk[lane] = fail_k;
+    s_fc[lane] = fail_code;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      double qs = 0.0, ls = 0.0;
+      int64_t fk = INT64_MAX;
+      int st = 0;
+      for (int l = 0; l < kWave; ++l) {
+        qs += s_fold[l][0];
+        ls += s_fold[l][1];
+        if (s_fk[l] < fk) {
+          fk = s_fk[l];
+          st = s_fc[l];
+        }
+      }
+      if (s_pnf) st = kNonFinite;
+      double ll = -0.5 * ((double)a.N * kLn2Pi + ls + qs);
+      if (st == 0 && !finite_d(ll)) st = kNonFinite;
+      a.logl[s] = st ? -INFINITY : ll;
+      if (a.status) a.status[s] = st;
+    }
   }
 }
 
