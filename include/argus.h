@@ -108,6 +108,78 @@ int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
                        double* logl, double* grad, int32_t* status,
                        void* stream);
 
+/* ---------------------------------------------------------------------
+ * Learned surrogate of logL (an MLP d -> w -> w -> w -> 1, SiLU hidden
+ * layers) and delayed-acceptance screening with the exact filter as judge
+ * (Christen & Fox 2005), for the paper's sampler integration (Functionality,
+ * "Sampler Integration"). Hidden layers run on BF16 matrix cores with FP32
+ * accumulation; biases, output layer, gradients and Adam state are FP32.
+ *
+ * Packed FP32 parameter block ("master"), weights row-major output-by-input:
+ *   W1 [w x d] | b1 [w] | W2 [w x w] | b2 [w] | W3 [w x w] | b3 [w] |
+ *   W4 [w] | b4 [1]          (n = w d + 2 w^2 + 4 w + 1)
+ * The caller owns the master block and the Adam moments (device FP32); the
+ * handle owns the BF16 copies and activation workspaces. Inputs are mapped
+ * from the box [in_lo, in_hi] to [-1, 1]; the network predicts the
+ * standardised target (logL - out_mu) / out_sd.
+ * ------------------------------------------------------------------- */
+typedef struct argus_mlp* argus_mlp_t;
+
+/* d_in in [1, 32]; width a multiple of 64 in [64, 1024]; max_batch (largest
+ * training batch) a multiple of 64. Allocates; synchronises. */
+int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t* out);
+int argus_mlp_destroy(argus_mlp_t h);
+int argus_mlp_n_params(argus_mlp_t h, int64_t* n);
+
+/* Takes the weights from master (dev [n]) into the handle's BF16/FP32
+ * copies and sets the input box (host [d_in]) and target standardisation. */
+int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo,
+                   const double* in_hi, double out_mu, double out_sd, void* stream);
+
+/* logl_hat (dev [Q]) for parameter rows theta (dev [Q*d_in] FP64), any Q. */
+int argus_surrogate_eval(argus_mlp_t h, const double* theta, int64_t Q,
+                         double* logl_hat, void* stream);
+
+/* Loss (dev [1]) = mean over the batch of (net(theta) - (target - mu)/sd)^2
+ * and its gradient w.r.t. the packed parameters (grad_out dev [n], or NULL
+ * to keep it internal). B a multiple of 64, <= max_batch. */
+int argus_mlp_grad(argus_mlp_t h, const double* theta, const double* target,
+                   int64_t B, float* grad_out, float* loss_out, void* stream);
+
+/* One training step: argus_mlp_grad, then Adam (beta 0.9, 0.999, eps 1e-8,
+ * bias-corrected with step >= 1) on master/adam_m/adam_v in place, then the
+ * handle's copies refreshed from the new master. */
+int argus_surrogate_train_step(argus_mlp_t h, float* master, float* adam_m,
+                               float* adam_v, const double* theta,
+                               const double* target, int64_t B, float lr,
+                               int64_t step, float* loss_out, void* stream);
+
+/* Delayed acceptance, stage 1 for Q chains with symmetric proposals: chain i
+ * survives when theta_prop[i] lies in [lo, hi] (dev [d]) and
+ * logu1[i] < lh_prop[i] - lh_cur[i] (surrogate values). Survivor indices go
+ * to idx (dev [Q]) in increasing order, their number to count (dev [1]).
+ * work: dev int32 [argus_da_work_size(Q)]; work[0..Q) then holds the
+ * stage-1 decisions. */
+int argus_da_stage1(const double* theta_prop, const double* lo, const double* hi,
+                    const double* lh_cur, const double* lh_prop, const double* logu1,
+                    int64_t Q, int32_t d, int32_t* idx, int32_t* count, int32_t* work,
+                    void* stream);
+int64_t argus_da_work_size(int64_t Q);
+
+/* dst[j] = src[idx[j]] (rows of d doubles) for j < cap; rows past *count
+ * repeat the last survivor, so a fixed-size exact evaluation can follow. */
+int argus_gather_rows(const double* src, const int32_t* idx, const int32_t* count,
+                      int64_t cap, int32_t d, double* dst, void* stream);
+
+/* Stage 2 for the survivors j < *count (chain i = idx[j]): accept when
+ * logu2[i] < (ll_prop[j] - ll_cur[i]) - (lh_prop[i] - lh_cur[i]); an accepted
+ * chain copies theta_prop[i] into theta_cur[i], updates ll_cur/lh_cur and
+ * increments acc[i]. ll_prop: exact logL of the gathered survivors. */
+int argus_da_stage2(const int32_t* idx, const int32_t* count, int64_t cap,
+                    const double* ll_prop, const double* lh_prop, const double* logu2,
+                    const double* theta_prop, double* theta_cur, double* ll_cur,
+                    double* lh_cur, int32_t* acc, int32_t d, void* stream);
+
 /* Human-readable launch configuration chosen for (ds, S), for reports. */
 int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len);
 

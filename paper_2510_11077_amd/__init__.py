@@ -45,7 +45,19 @@ for _n in ("argus_loglike", "argus_loglike_terms", "argus_loglike_plain"):
     getattr(_lib, _n).argtypes = [_V, _V, C.c_int64, _V, _V, _V]
 _lib.argus_loglike_grad.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V]
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
-_HAS_SURROGATE = hasattr(_lib, "argus_surrogate_eval")
+_lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)]
+_lib.argus_mlp_destroy.argtypes = [_V]
+_lib.argus_mlp_n_params.argtypes = [_V, C.POINTER(C.c_int64)]
+_lib.argus_mlp_load.argtypes = [_V, _V, _V, _V, C.c_double, C.c_double, _V]
+_lib.argus_surrogate_eval.argtypes = [_V, _V, C.c_int64, _V, _V]
+_lib.argus_mlp_grad.argtypes = [_V, _V, _V, C.c_int64, _V, _V, _V]
+_lib.argus_surrogate_train_step.argtypes = [_V, _V, _V, _V, _V, _V, C.c_int64, C.c_float,
+                                            C.c_int64, _V, _V]
+_lib.argus_da_stage1.argtypes = [_V, _V, _V, _V, _V, _V, C.c_int64, C.c_int32, _V, _V, _V, _V]
+_lib.argus_da_work_size.argtypes = [C.c_int64]
+_lib.argus_da_work_size.restype = C.c_int64
+_lib.argus_gather_rows.argtypes = [_V, _V, _V, C.c_int64, C.c_int32, _V, _V]
+_lib.argus_da_stage2.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V, _V, _V, _V, _V, C.c_int32, _V]
 
 
 def _check(rc: int):
@@ -173,6 +185,165 @@ class Dataset:
         buf = C.create_string_buffer(4096)
         _check(_lib.argus_tune_info(self._h, S, buf, 4096))
         return buf.value.decode()
+
+
+class MLP:
+    """Surrogate network handle (argus_mlp_*). The packed FP32 master weights
+    and Adam moments are torch tensors owned by this object."""
+
+    def __init__(self, d_in, width=256, max_batch=4096, device="cuda"):
+        import torch
+        h = _V()
+        _check(_lib.argus_mlp_create(d_in, width, max_batch, C.byref(h)))
+        self._h = h
+        n = C.c_int64()
+        _check(_lib.argus_mlp_n_params(self._h, C.byref(n)))
+        self.n_params, self.d_in, self.width, self.max_batch = n.value, d_in, width, max_batch
+        self.master = torch.zeros(self.n_params, dtype=torch.float32, device=device)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.argus_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, master, in_lo, in_hi, out_mu, out_sd, stream=None):
+        """Set the weights (packed FP32, any device tensor or array) and the
+        input box / target standardisation."""
+        import torch
+        self.master.copy_(torch.as_tensor(master, dtype=torch.float32))
+        self.m.zero_()
+        self.v.zero_()
+        self.step = 0
+        self.in_lo = np.ascontiguousarray(in_lo, np.float64)
+        self.in_hi = np.ascontiguousarray(in_hi, np.float64)
+        self.out_mu, self.out_sd = float(out_mu), float(out_sd)
+        _check(_lib.argus_mlp_load(self._h, self.master.data_ptr(), self.in_lo.ctypes.data,
+                                   self.in_hi.ctypes.data, self.out_mu, self.out_sd,
+                                   _stream(stream)))
+
+    def eval(self, theta, out=None, stream=None):
+        import torch
+        theta = theta.contiguous()
+        if out is None:
+            out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+        _check(_lib.argus_surrogate_eval(self._h, _dev_ptr(theta, torch.float64, "theta"),
+                                         theta.shape[0], out.data_ptr(), _stream(stream)))
+        return out
+
+    def grad(self, theta, target, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=theta.device)
+        _check(_lib.argus_mlp_grad(self._h, _dev_ptr(theta, torch.float64, "theta"),
+                                   _dev_ptr(target, torch.float64, "target"), theta.shape[0],
+                                   g.data_ptr(), self.loss.data_ptr(), _stream(stream)))
+        return g, self.loss
+
+    def train_step(self, theta, target, lr, stream=None):
+        import torch
+        self.step += 1
+        _check(_lib.argus_surrogate_train_step(
+            self._h, self.master.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+            _dev_ptr(theta, torch.float64, "theta"), _dev_ptr(target, torch.float64, "target"),
+            theta.shape[0], float(lr), self.step, self.loss.data_ptr(), _stream(stream)))
+        return self.loss
+
+
+def da_stage1(theta_prop, lo, hi, lh_cur, lh_prop, logu1, idx, count, work, stream=None):
+    Q, d = theta_prop.shape
+    _check(_lib.argus_da_stage1(theta_prop.data_ptr(), lo.data_ptr(), hi.data_ptr(),
+                                lh_cur.data_ptr(), lh_prop.data_ptr(), logu1.data_ptr(), Q, d,
+                                idx.data_ptr(), count.data_ptr(), work.data_ptr(),
+                                _stream(stream)))
+
+
+def da_work_size(Q: int) -> int:
+    return int(_lib.argus_da_work_size(Q))
+
+
+def gather_rows(src, idx, count, cap, dst, stream=None):
+    _check(_lib.argus_gather_rows(src.data_ptr(), idx.data_ptr(), count.data_ptr(), cap,
+                                  src.shape[1], dst.data_ptr(), _stream(stream)))
+
+
+def da_stage2(idx, count, cap, ll_prop, lh_prop, logu2, theta_prop, theta_cur, ll_cur, lh_cur,
+              acc, stream=None):
+    _check(_lib.argus_da_stage2(idx.data_ptr(), count.data_ptr(), cap, ll_prop.data_ptr(),
+                                lh_prop.data_ptr(), logu2.data_ptr(), theta_prop.data_ptr(),
+                                theta_cur.data_ptr(), ll_cur.data_ptr(), lh_cur.data_ptr(),
+                                acc.data_ptr(), theta_cur.shape[1], _stream(stream)))
+
+
+class DelayedAcceptance:
+    """Q parallel random-walk chains screened by the surrogate (stage 1) and
+    judged by the exact filter (stage 2); every step runs in libargus
+    kernels, this class only sequences them. Random numbers are drawn with
+    torch and passed in. The survivor count is the only value read back per
+    iteration (to size the exact evaluation)."""
+
+    def __init__(self, ds, net, theta0, lo, hi, step_scale, seed=0):
+        import torch
+        self.ds, self.net = ds, net
+        self.theta = theta0.clone().contiguous()
+        self.Q, self.d = self.theta.shape
+        dev = self.theta.device
+        self.lo = torch.as_tensor(lo, dtype=torch.float64, device=dev)
+        self.hi = torch.as_tensor(hi, dtype=torch.float64, device=dev)
+        self.scale = torch.as_tensor(step_scale, dtype=torch.float64, device=dev)
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+        self.ll, _ = ds.loglike(self.theta)
+        self.ll = self.ll.clone()
+        self.lh = net.eval(self.theta).clone()
+        self.idx = torch.empty(self.Q, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.work = torch.empty(da_work_size(self.Q), dtype=torch.int32, device=dev)
+        self.acc = torch.zeros(self.Q, dtype=torch.int32, device=dev)
+        self.n_exact = 0
+        self.n_prop = 0
+
+    def draws(self):
+        import torch
+        eps = torch.randn(self.theta.shape, dtype=torch.float64, device=self.theta.device,
+                          generator=self.gen) * self.scale
+        u = torch.rand((2, self.Q), dtype=torch.float64, device=self.theta.device,
+                       generator=self.gen)
+        return eps, torch.log(u[0]), torch.log(u[1])
+
+    def step(self, eps=None, logu1=None, logu2=None, record=None):
+        import torch
+        if eps is None:
+            eps, logu1, logu2 = self.draws()
+        prop = (self.theta + eps).contiguous()
+        lh_prop = self.net.eval(prop)
+        da_stage1(prop, self.lo, self.hi, self.lh, lh_prop, logu1, self.idx, self.count,
+                  self.work)
+        n = int(self.count.item())
+        self.n_prop += self.Q
+        if record is not None:
+            record.append(dict(prop=prop.clone(), lh_prop=lh_prop.clone(), lh_cur=self.lh.clone(),
+                               ll_cur=self.ll.clone(), logu1=logu1.clone(), logu2=logu2.clone(),
+                               theta=self.theta.clone(), n=n))
+        if n == 0:
+            return 0
+        cap = max(64, 1 << (n - 1).bit_length())  # fixed sizes keep tuned workspaces
+        cap = min(cap, self.Q)
+        sub = torch.empty((cap, self.d), dtype=torch.float64, device=prop.device)
+        gather_rows(prop, self.idx, self.count, cap, sub)
+        ll_prop, _ = self.ds.loglike(sub, want_status=False)
+        self.n_exact += n
+        da_stage2(self.idx, self.count, cap, ll_prop, lh_prop, logu2, prop, self.theta, self.ll,
+                  self.lh, self.acc)
+        return n
 
 
 def _make_loglike_fn():

@@ -1,0 +1,711 @@
+// Learned surrogate of the log-likelihood: an MLP d -> w -> w -> w -> 1 with
+// SiLU hidden layers, inference and training (forward, backward, Adam), and
+// the delayed-acceptance screening kernels that use it. (The paper's
+// inference integrates the likelihood with samplers, Functionality,
+// "Sampler Integration"; the surrogate screens proposals so that the exact
+// filter runs only on stage-1 survivors, Christen & Fox 2005.)
+//
+// Arithmetic: hidden-layer weights, inputs and activations in BF16, products
+// on the matrix cores (v_mfma_f32_32x32x16_bf16) with FP32 accumulation;
+// biases, the 1-unit output layer, gradients and Adam state in FP32.
+//
+// Every GEMM is written C[m][n] = sum_k X[m][k] Y[n][k] with both operands
+// K-contiguous, so each lane feeds the MFMA with one 16-B load per operand:
+//   forward   Z_l  = A_{l-1} W_l^T       X = A_{l-1} [B x in],  Y = W_l [out x in]
+//   backward  dA   = dZ_l W_l            X = dZ_l [B x out],    Y = W_l^T [in x out]
+//   weights   dW_l = dZ_l^T A_{l-1}      X = dZ_l^T [out x B],  Y = A_{l-1}^T [in x B]
+// so the forward and backward epilogues also write transposed copies.
+// MFMA 32x32x16 lane layout (checked on the device): A row l%32, k
+// 8(l/32)..+7; B column l%32, same k; accumulator r of lane l is row
+// 8(r/4) + 4(l/32) + r%4, column l%32.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "argus_host.h"
+#include "argus_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace argus {
+
+namespace {
+
+enum { EPI_FWD = 0, EPI_BWD = 1, EPI_WGRAD = 2 };
+
+struct GemmArgs {
+  const __bf16* X;
+  const __bf16* Y;
+  int ldx, ldy, M, N, K;
+  const float* bias;  // FWD [N]
+  float* zout;        // FWD [M x N] pre-activation, nullable
+  __bf16* out;        // FWD/BWD [M x ldo], nullable
+  __bf16* outT;       // FWD/BWD [N x ldoT], nullable
+  int ldo, ldoT;
+  const float* zin;   // BWD [M x N] pre-activation of the layer being entered
+  float* C;           // WGRAD [M x ldc]
+  int ldc;
+};
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 64 + (w >> 1) * 32;
+  const int n0 = blockIdx.y * 64 + (w & 1) * 32;
+  // rows/columns past the edge are clamped for the loads, never stored
+  const int mr = min(m0 + (l & 31), g.M - 1);
+  const int nr = min(n0 + (l & 31), g.N - 1);
+  const int kk = (l >> 5) * 8;
+  const __bf16* xp = g.X + (size_t)mr * g.ldx + kk;
+  const __bf16* yp = g.Y + (size_t)nr * g.ldy + kk;
+  f32x16 acc = {};
+  for (int k = 0; k < g.K; k += 16) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(xp + k);
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(yp + k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int col = n0 + (l & 31);
+  if (col >= g.N) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    if (row >= g.M) continue;
+    const float v = acc[r];
+    if (EPI == EPI_WGRAD) {
+      g.C[(size_t)row * g.ldc + col] = v;
+    } else {
+      float o;
+      if (EPI == EPI_FWD) {
+        const float z = v + g.bias[col];
+        if (g.zout) g.zout[(size_t)row * g.N + col] = z;
+        o = z * sigm(z);  // SiLU
+      } else {
+        const float z = g.zin[(size_t)row * g.N + col];
+        const float s = sigm(z);
+        o = v * (s * (1.0f + z * (1.0f - s)));  // dA * SiLU'(z)
+      }
+      const __bf16 ob = (__bf16)o;
+      if (g.out) g.out[(size_t)row * g.ldo + col] = ob;
+      if (g.outT) g.outT[(size_t)col * g.ldoT + row] = ob;
+    }
+  }
+}
+
+// Inputs mapped from the prior box to [-1, 1], rounded to BF16, padded with
+// zero columns to kKin; optional transposed copy and standardised targets.
+constexpr int kKin = 32;
+
+__global__ void k_prep(const double* theta, int64_t B, int d_in, const double* lo,
+                       const double* hi, __bf16* x0, __bf16* x0T, int ldT,
+                       const double* target, double mu, double sd, float* t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * kKin) return;
+  const int64_t m = i / kKin;
+  const int k = (int)(i - m * kKin);
+  float v = 0.0f;
+  if (k < d_in) {
+    const double u = 2.0 * (theta[m * d_in + k] - lo[k]) / (hi[k] - lo[k]) - 1.0;
+    v = (float)u;
+  }
+  const __bf16 b = (__bf16)v;
+  x0[m * kKin + k] = b;
+  if (x0T) x0T[(int64_t)k * ldT + m] = b;
+  if (t && k == 0) t[m] = (float)((target[m] - mu) / sd);
+}
+
+// Output layer in FP32: o = sum_n a3[m][n] W4[n] + b4 (index order).
+__device__ __forceinline__ float out_row(const __bf16* a3, int width, const float* W4,
+                                         float b4) {
+  float acc = 0.0f;
+  for (int n = 0; n < width; n += 8) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(a3 + n);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = fmaf((float)v[j], W4[n + j], acc);
+  }
+  return acc + b4;
+}
+
+__global__ void k_out_eval(const __bf16* a3, int64_t Q, int width, const float* W4,
+                           const float* b4, double mu, double sd, double* out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= Q) return;
+  const float o = out_row(a3 + m * width, width, W4, b4[0]);
+  out[m] = (double)o * sd + mu;
+}
+
+// Training head: o, residual, dout = 2 (o - t) / B, squared residual.
+__global__ void k_out_train(const __bf16* a3, int64_t B, int width, const float* W4,
+                            const float* b4, const float* t, float* dout, float* sq) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= B) return;
+  const float o = out_row(a3 + m * width, width, W4, b4[0]);
+  const float d = o - t[m];
+  dout[m] = 2.0f * d / (float)B;
+  sq[m] = d * d;
+}
+
+// dZ3[m][n] = bf16(dout[m] W4[n] SiLU'(z3[m][n])), both layouts.
+__global__ void k_dz_last(const float* dout, const float* W4, const float* z3, int64_t B,
+                          int width, __bf16* dz, __bf16* dzT, int ldT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * width) return;
+  const int64_t m = i / width;
+  const int n = (int)(i - m * width);
+  const float z = z3[i];
+  const float s = sigm(z);
+  const __bf16 b = (__bf16)(dout[m] * W4[n] * (s * (1.0f + z * (1.0f - s))));
+  dz[i] = b;
+  dzT[(int64_t)n * ldT + m] = b;
+}
+
+// Row sums of a [rows x ld] bf16 matrix over its first B columns (the bias
+// gradients, from the transposed dZ), in index order.
+__global__ void k_rowsum_bf16(const __bf16* a, int rows, int64_t B, int64_t ld, float* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float acc = 0.0f;
+  const __bf16* p = a + r * ld;
+  for (int64_t m = 0; m < B; ++m) acc += (float)p[m];
+  out[r] = acc;
+}
+
+// Output-layer gradients and the loss: gW4[n] = sum_m dout[m] a3T[n][m],
+// gb4 = sum_m dout[m], loss = sum_m sq[m] / B; one block, index order.
+__global__ void k_head_grad(const float* dout, const float* sq, const __bf16* a3T, int64_t ldT,
+                            int64_t B, int width, float* gW4, float* gb4, float* loss) {
+  for (int n = threadIdx.x; n < width; n += blockDim.x) {
+    float acc = 0.0f;
+    const __bf16* p = a3T + n * ldT;
+    for (int64_t m = 0; m < B; ++m) acc = fmaf(dout[m], (float)p[m], acc);
+    gW4[n] = acc;
+  }
+  if (threadIdx.x == 0) {
+    float a = 0.0f, s = 0.0f;
+    for (int64_t m = 0; m < B; ++m) {
+      a += dout[m];
+      s += sq[m];
+    }
+    *gb4 = a;
+    *loss = s / (float)B;
+  }
+}
+
+struct AdamArgs {
+  float* master;
+  float* m;
+  float* v;
+  const float* g;
+  float* p32;             // the handle's FP32 copy (biases, output layer)
+  __bf16 *w1, *w2, *w3;   // BF16 hidden weights [w x kKin], [w x w], [w x w]
+  __bf16 *w2T, *w3T;      // transposed copies
+  int64_t n;
+  int d_in, width;
+  float lr, b1, b2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+  int do_update;                  // 0: only refresh the copies from master
+};
+
+__device__ __forceinline__ void scatter_copy(const AdamArgs& a, int64_t i, float w) {
+  a.p32[i] = w;
+  const int64_t dW = a.width, o1 = 0, o2 = (int64_t)dW * a.d_in + dW,
+                o3 = o2 + dW * dW + dW;
+  const __bf16 b = (__bf16)w;
+  if (i < o1 + dW * a.d_in) {
+    const int64_t n = (i - o1) / a.d_in, k = (i - o1) % a.d_in;
+    a.w1[n * kKin + k] = b;
+  } else if (i >= o2 && i < o2 + dW * dW) {
+    const int64_t n = (i - o2) / dW, k = (i - o2) % dW;
+    a.w2[n * dW + k] = b;
+    a.w2T[k * dW + n] = b;
+  } else if (i >= o3 && i < o3 + dW * dW) {
+    const int64_t n = (i - o3) / dW, k = (i - o3) % dW;
+    a.w3[n * dW + k] = b;
+    a.w3T[k * dW + n] = b;
+  }
+}
+
+__global__ void k_adam(AdamArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  float w = a.master[i];
+  if (a.do_update) {
+    const float g = a.g[i];
+    const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    w -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+    a.master[i] = w;
+  }
+  scatter_copy(a, i, w);
+}
+
+// ------------------------------------------------- delayed acceptance
+// Stage 1 for chain i: a proposal outside the prior box is rejected; else
+// accepted when log u1 < lhat_prop - lhat_cur. Accepted chain indices are
+// compacted in increasing order (per-block counts, one-block scan, then
+// per-block ordered writes).
+constexpr int kScanBlock = 256;
+
+__device__ __forceinline__ bool stage1_ok(int64_t i, const double* theta_prop, int d,
+                                          const double* lo, const double* hi,
+                                          const double* lh_cur, const double* lh_prop,
+                                          const double* logu1) {
+  const double* t = theta_prop + i * d;
+  for (int k = 0; k < d; ++k)
+    if (!(t[k] >= lo[k] && t[k] <= hi[k])) return false;
+  return logu1[i] < lh_prop[i] - lh_cur[i];
+}
+
+struct DA1Args {
+  const double *theta_prop, *lo, *hi, *lh_cur, *lh_prop, *logu1;
+  int64_t Q;
+  int d;
+  int32_t* block_cnt;   // [nblocks]
+  int32_t* block_off;   // [nblocks]
+  int32_t* idx;         // [Q] compacted survivors
+  int32_t* count;       // [1]
+  int32_t* flag1;       // [Q] stage-1 decision
+};
+
+__global__ void k_da1_count(DA1Args a) {
+  __shared__ int s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  int ok = 0;
+  if (i < a.Q) {
+    ok = stage1_ok(i, a.theta_prop, a.d, a.lo, a.hi, a.lh_cur, a.lh_prop, a.logu1);
+    a.flag1[i] = ok;
+  }
+  if (ok) atomicAdd(&s_cnt, 1);  // integer count: order-independent
+  __syncthreads();
+  if (threadIdx.x == 0) a.block_cnt[blockIdx.x] = s_cnt;
+}
+
+__global__ void k_da1_scan(DA1Args a, int nblocks) {
+  if (threadIdx.x != 0) return;
+  int acc = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    a.block_off[b] = acc;
+    acc += a.block_cnt[b];
+  }
+  *a.count = acc;
+}
+
+__global__ void k_da1_write(DA1Args a) {
+  __shared__ int s_flag[kScanBlock];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  s_flag[threadIdx.x] = i < a.Q ? a.flag1[i] : 0;
+  __syncthreads();
+  if (i >= a.Q || !s_flag[threadIdx.x]) return;
+  int before = 0;
+  for (int j = 0; j < (int)threadIdx.x; ++j) before += s_flag[j];
+  a.idx[a.block_off[blockIdx.x] + before] = (int32_t)i;
+}
+
+__global__ void k_gather_rows(const double* src, const int32_t* idx, const int32_t* count,
+                              int64_t cap, int d, double* dst) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = *count;
+  if (j >= cap * d) return;
+  const int64_t r = j / d, k = j - r * d;
+  // rows past the survivor count repeat the last survivor (padding)
+  const int64_t rr = n > 0 ? (r < n ? r : n - 1) : 0;
+  dst[j] = n > 0 ? src[(int64_t)idx[rr] * d + k] : 0.0;
+}
+
+struct DA2Args {
+  const int32_t* idx;
+  const int32_t* count;
+  const double* ll_prop;   // [>= count] exact logL of the gathered survivors
+  const double* lh_prop;   // [Q]
+  const double* logu2;     // [Q]
+  const double* theta_prop;
+  double* theta_cur;       // [Q x d] updated in place
+  double* ll_cur;          // [Q]
+  double* lh_cur;          // [Q]
+  int32_t* acc;            // [Q] accepted-move counters
+  int d;
+};
+
+__global__ void k_da2(DA2Args a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= *a.count) return;
+  const int64_t i = a.idx[j];
+  const double la = (a.ll_prop[j] - a.ll_cur[i]) - (a.lh_prop[i] - a.lh_cur[i]);
+  if (a.logu2[i] < la) {
+    for (int k = 0; k < a.d; ++k) a.theta_cur[i * a.d + k] = a.theta_prop[i * a.d + k];
+    a.ll_cur[i] = a.ll_prop[j];
+    a.lh_cur[i] = a.lh_prop[i];
+    a.acc[i] += 1;
+  }
+}
+
+}  // namespace
+}  // namespace argus
+
+// ================================================================ host side
+struct argus_mlp {
+  int d_in = 0, width = 0;
+  int64_t n = 0, max_batch = 0;
+  int device = 0;
+  argus::DevBuf p32, w1, w2, w3, w2T, w3T, lo, hi;
+  double mu = 0.0, sd = 1.0;
+  bool loaded = false;
+  // inference buffers (grown on demand)
+  argus::DevBuf e_x0, e_a, e_b;
+  int64_t e_cap = 0;
+  // training buffers
+  argus::DevBuf x0, x0T, z[3], a[3], aT[3], dz[3], dzT[3], t, dout, sq, g;
+};
+
+namespace argus {
+namespace {
+
+int64_t mlp_params(int d, int w) { return (int64_t)w * d + 2LL * w * w + 4LL * w + 1; }
+
+int launch_gemm(int epi, const GemmArgs& g, hipStream_t st) {
+  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
+  if (epi == EPI_FWD)
+    hipLaunchKernelGGL(k_gemm<EPI_FWD>, grid, dim3(256), 0, st, g);
+  else if (epi == EPI_BWD)
+    hipLaunchKernelGGL(k_gemm<EPI_BWD>, grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL(k_gemm<EPI_WGRAD>, grid, dim3(256), 0, st, g);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+GemmArgs gemm(const __bf16* X, int ldx, const __bf16* Y, int ldy, int M, int N, int K) {
+  GemmArgs g{};
+  g.X = X;
+  g.Y = Y;
+  g.ldx = ldx;
+  g.ldy = ldy;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  return g;
+}
+
+unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Forward of the three hidden layers for B rows from standardised inputs x0.
+// train = store pre-activations and transposed activations.
+int hidden_forward(argus_mlp* h, const __bf16* x0, int64_t B, __bf16* a1, __bf16* a2, __bf16* a3,
+                   bool train, hipStream_t st) {
+  const int w = h->width;
+  const float* p = h->p32.as<float>();
+  const float* b[3] = {p + (int64_t)w * h->d_in, p + (int64_t)w * h->d_in + w + (int64_t)w * w,
+                       p + (int64_t)w * h->d_in + 2 * (w + (int64_t)w * w)};
+  const __bf16* Ws[3] = {h->w1.as<__bf16>(), h->w2.as<__bf16>(), h->w3.as<__bf16>()};
+  const __bf16* in[3] = {x0, a1, a2};
+  __bf16* outs[3] = {a1, a2, a3};
+  for (int l = 0; l < 3; ++l) {
+    const int K = l == 0 ? kKin : w;
+    GemmArgs g = gemm(in[l], K, Ws[l], K, (int)B, w, K);
+    g.bias = b[l];
+    g.out = outs[l];
+    g.ldo = w;
+    if (train) {
+      g.zout = h->z[l].as<float>();
+      g.outT = h->aT[l].as<__bf16>();
+      g.ldoT = (int)h->max_batch;
+    }
+    int rc = launch_gemm(EPI_FWD, g, st);
+    if (rc) return rc;
+  }
+  return ARGUS_OK;
+}
+
+int check_mlp(const argus_mlp* h) {
+  if (!h) return fail(ARGUS_E_INVAL, "mlp handle is NULL");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != h->device) return fail(ARGUS_E_INVAL, "mlp handle belongs to another device");
+  return ARGUS_OK;
+}
+
+// forward + backward into h->g (packed FP32 gradient) and loss_out
+int mlp_backprop(argus_mlp* h, const double* theta, const double* target, int64_t B,
+                 float* loss_out, hipStream_t st) {
+  const int w = h->width, d = h->d_in;
+  const int64_t ldT = h->max_batch;
+  hipLaunchKernelGGL(k_prep, dim3(blocks(B * kKin, 256)), dim3(256), 0, st, theta, B, d,
+                     h->lo.as<double>(), h->hi.as<double>(), h->x0.as<__bf16>(),
+                     h->x0T.as<__bf16>(), (int)ldT, target, h->mu, h->sd, h->t.as<float>());
+  HIPCHK(hipGetLastError());
+  __bf16* A[3] = {h->a[0].as<__bf16>(), h->a[1].as<__bf16>(), h->a[2].as<__bf16>()};
+  int rc = hidden_forward(h, h->x0.as<__bf16>(), B, A[0], A[1], A[2], true, st);
+  if (rc) return rc;
+  const float* p = h->p32.as<float>();
+  const int64_t oW2 = (int64_t)w * d + w, oW3 = oW2 + (int64_t)w * w + w,
+                oW4 = oW3 + (int64_t)w * w + w;
+  float* g = h->g.as<float>();
+  hipLaunchKernelGGL(k_out_train, dim3(blocks(B, 256)), dim3(256), 0, st, A[2], B, w, p + oW4,
+                     p + oW4 + w, h->t.as<float>(), h->dout.as<float>(), h->sq.as<float>());
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_head_grad, dim3(1), dim3(256), 0, st, h->dout.as<float>(),
+                     h->sq.as<float>(), h->aT[2].as<__bf16>(), ldT, B, w, g + oW4, g + oW4 + w,
+                     loss_out);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_dz_last, dim3(blocks(B * w, 256)), dim3(256), 0, st, h->dout.as<float>(),
+                     p + oW4, h->z[2].as<float>(), B, w, h->dz[2].as<__bf16>(),
+                     h->dzT[2].as<__bf16>(), (int)ldT);
+  HIPCHK(hipGetLastError());
+  const int64_t oW[3] = {0, oW2, oW3};
+  const __bf16* WT[3] = {nullptr, h->w2T.as<__bf16>(), h->w3T.as<__bf16>()};
+  for (int l = 2; l >= 0; --l) {
+    // weight gradient dW_l = dZ_l^T A_{l-1}
+    const int K_in = l == 0 ? kKin : w;
+    const __bf16* AinT = l == 0 ? h->x0T.as<__bf16>() : h->aT[l - 1].as<__bf16>();
+    GemmArgs gw = gemm(h->dzT[l].as<__bf16>(), (int)ldT, AinT, (int)ldT, w,
+                       l == 0 ? d : w, (int)B);
+    gw.C = g + oW[l];
+    gw.ldc = l == 0 ? d : w;
+    (void)K_in;
+    if ((rc = launch_gemm(EPI_WGRAD, gw, st))) return rc;
+    hipLaunchKernelGGL(k_rowsum_bf16, dim3(blocks(w, 256)), dim3(256), 0, st,
+                       h->dzT[l].as<__bf16>(), w, B, ldT, g + oW[l] + (int64_t)w * (l == 0 ? d : w));
+    HIPCHK(hipGetLastError());
+    if (l > 0) {
+      // dZ_{l-1} = (dZ_l W_l) * SiLU'(Z_{l-1})
+      GemmArgs gb = gemm(h->dz[l].as<__bf16>(), w, WT[l], w, (int)B, w, w);
+      gb.zin = h->z[l - 1].as<float>();
+      gb.out = h->dz[l - 1].as<__bf16>();
+      gb.ldo = w;
+      gb.outT = h->dzT[l - 1].as<__bf16>();
+      gb.ldoT = (int)ldT;
+      if ((rc = launch_gemm(EPI_BWD, gb, st))) return rc;
+    }
+  }
+  return ARGUS_OK;
+}
+
+int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float lr,
+            int64_t step, hipStream_t st) {
+  AdamArgs a{};
+  a.master = master;
+  a.m = m;
+  a.v = v;
+  a.g = h->g.as<float>();
+  a.p32 = h->p32.as<float>();
+  a.w1 = h->w1.as<__bf16>();
+  a.w2 = h->w2.as<__bf16>();
+  a.w3 = h->w3.as<__bf16>();
+  a.w2T = h->w2T.as<__bf16>();
+  a.w3T = h->w3T.as<__bf16>();
+  a.n = h->n;
+  a.d_in = h->d_in;
+  a.width = h->width;
+  a.lr = lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.c1 = update ? (float)(1.0 / (1.0 - std::pow(0.9, (double)step))) : 1.0f;
+  a.c2 = update ? (float)(1.0 / (1.0 - std::pow(0.999, (double)step))) : 1.0f;
+  a.do_update = update ? 1 : 0;
+  hipLaunchKernelGGL(k_adam, dim3(blocks(h->n, 256)), dim3(256), 0, st, a);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+}  // namespace
+}  // namespace argus
+
+using namespace argus;
+
+extern "C" {
+
+int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t* out) {
+  if (!out) return fail(ARGUS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (d_in < 1 || d_in > kKin) return fail(ARGUS_E_UNSUPPORTED, "d_in must be in [1, 32]");
+  if (width < 64 || width > 1024 || width % 64)
+    return fail(ARGUS_E_UNSUPPORTED, "width must be a multiple of 64 in [64, 1024]");
+  if (max_batch < 64 || max_batch % 64 || max_batch > (1LL << 24))
+    return fail(ARGUS_E_UNSUPPORTED, "max_batch must be a multiple of 64 in [64, 2^24]");
+  auto h = std::make_unique<argus_mlp>();
+  h->d_in = d_in;
+  h->width = width;
+  h->n = mlp_params(d_in, width);
+  h->max_batch = max_batch;
+  HIPCHK(hipGetDevice(&h->device));
+  const int64_t w = width, B = max_batch;
+  int rc;
+  if ((rc = h->p32.alloc(h->n * 4)) || (rc = h->w1.alloc(w * kKin * 2)) ||
+      (rc = h->w2.alloc(w * w * 2)) || (rc = h->w3.alloc(w * w * 2)) ||
+      (rc = h->w2T.alloc(w * w * 2)) || (rc = h->w3T.alloc(w * w * 2)) ||
+      (rc = h->lo.alloc(kKin * 8)) || (rc = h->hi.alloc(kKin * 8)) ||
+      (rc = h->x0.alloc(B * kKin * 2)) || (rc = h->x0T.alloc(B * kKin * 2)) ||
+      (rc = h->t.alloc(B * 4)) || (rc = h->dout.alloc(B * 4)) || (rc = h->sq.alloc(B * 4)) ||
+      (rc = h->g.alloc(h->n * 4)))
+    return rc;
+  for (int l = 0; l < 3; ++l)
+    if ((rc = h->z[l].alloc(B * w * 4)) || (rc = h->a[l].alloc(B * w * 2)) ||
+        (rc = h->aT[l].alloc(B * w * 2)) || (rc = h->dz[l].alloc(B * w * 2)) ||
+        (rc = h->dzT[l].alloc(B * w * 2)))
+      return rc;
+  // zero padding columns of W1 and unused tails once
+  HIPCHK(hipMemset(h->w1.p, 0, w * kKin * 2));
+  HIPCHK(hipMemset(h->g.p, 0, h->n * 4));
+  HIPCHK(hipDeviceSynchronize());
+  *out = h.release();
+  return ARGUS_OK;
+}
+
+int argus_mlp_destroy(argus_mlp_t h) {
+  if (!h) return ARGUS_OK;
+  (void)hipDeviceSynchronize();
+  delete h;
+  return ARGUS_OK;
+}
+
+int argus_mlp_n_params(argus_mlp_t h, int64_t* n) {
+  if (!h || !n) return fail(ARGUS_E_INVAL, "NULL argument");
+  *n = h->n;
+  return ARGUS_OK;
+}
+
+int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo, const double* in_hi,
+                   double out_mu, double out_sd, void* stream) {
+  int rc = check_mlp(h);
+  if (rc) return rc;
+  if (!master || !in_lo || !in_hi) return fail(ARGUS_E_INVAL, "NULL argument");
+  if (!(out_sd > 0.0) || !std::isfinite(out_mu)) return fail(ARGUS_E_INVAL, "bad standardisation");
+  for (int k = 0; k < h->d_in; ++k)
+    if (!(in_hi[k] > in_lo[k])) return fail(ARGUS_E_INVAL, "input box must have hi > lo");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(h->lo.p, in_lo, h->d_in * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->hi.p, in_hi, h->d_in * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  h->mu = out_mu;
+  h->sd = out_sd;
+  if ((rc = refresh(h, const_cast<float*>(master), nullptr, nullptr, false, 0.f, 0, st)))
+    return rc;
+  h->loaded = true;
+  return ARGUS_OK;
+}
+
+int argus_surrogate_eval(argus_mlp_t h, const double* theta, int64_t Q, double* logl_hat,
+                         void* stream) {
+  int rc = check_mlp(h);
+  if (rc) return rc;
+  if (!h->loaded) return fail(ARGUS_E_INVAL, "weights not loaded");
+  if (Q < 0) return fail(ARGUS_E_INVAL, "Q must be >= 0");
+  if (Q == 0) return ARGUS_OK;
+  if (!theta || !logl_hat) return fail(ARGUS_E_INVAL, "NULL argument");
+  if (Q > h->e_cap) {
+    const int64_t cap = ((Q + 63) / 64) * 64;
+    if ((rc = h->e_x0.alloc(cap * kKin * 2)) || (rc = h->e_a.alloc(cap * h->width * 2)) ||
+        (rc = h->e_b.alloc(cap * h->width * 2)))
+      return rc;
+    h->e_cap = cap;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_prep, dim3(blocks(Q * kKin, 256)), dim3(256), 0, st, theta, Q, h->d_in,
+                     h->lo.as<double>(), h->hi.as<double>(), h->e_x0.as<__bf16>(), nullptr, 0,
+                     nullptr, 0.0, 1.0, nullptr);
+  HIPCHK(hipGetLastError());
+  __bf16* A = h->e_a.as<__bf16>();
+  __bf16* Bb = h->e_b.as<__bf16>();
+  // a1 -> A, a2 -> B, a3 -> A
+  if ((rc = hidden_forward(h, h->e_x0.as<__bf16>(), Q, A, Bb, A, false, st))) return rc;
+  const int w = h->width;
+  const float* p = h->p32.as<float>();
+  const int64_t oW4 = (int64_t)w * h->d_in + w + 2 * ((int64_t)w * w + w);
+  hipLaunchKernelGGL(k_out_eval, dim3(blocks(Q, 256)), dim3(256), 0, st, A, Q, w, p + oW4,
+                     p + oW4 + w, h->mu, h->sd, logl_hat);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+int argus_mlp_grad(argus_mlp_t h, const double* theta, const double* target, int64_t B,
+                   float* grad_out, float* loss_out, void* stream) {
+  int rc = check_mlp(h);
+  if (rc) return rc;
+  if (!h->loaded) return fail(ARGUS_E_INVAL, "weights not loaded");
+  if (B < 64 || B % 64 || B > h->max_batch)
+    return fail(ARGUS_E_INVAL, "batch must be a multiple of 64 and <= max_batch");
+  if (!theta || !target || !loss_out) return fail(ARGUS_E_INVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = mlp_backprop(h, theta, target, B, loss_out, st))) return rc;
+  if (grad_out)
+    HIPCHK(hipMemcpyAsync(grad_out, h->g.p, h->n * 4, hipMemcpyDeviceToDevice, st));
+  return ARGUS_OK;
+}
+
+int argus_surrogate_train_step(argus_mlp_t h, float* master, float* adam_m, float* adam_v,
+                               const double* theta, const double* target, int64_t B, float lr,
+                               int64_t step, float* loss_out, void* stream) {
+  int rc = check_mlp(h);
+  if (rc) return rc;
+  if (!master || !adam_m || !adam_v) return fail(ARGUS_E_INVAL, "NULL argument");
+  if (step < 1) return fail(ARGUS_E_INVAL, "step counts from 1");
+  if ((rc = argus_mlp_grad(h, theta, target, B, nullptr, loss_out, stream))) return rc;
+  return refresh(h, master, adam_m, adam_v, true, lr, step, (hipStream_t)stream);
+}
+
+int argus_da_stage1(const double* theta_prop, const double* lo, const double* hi,
+                    const double* lh_cur, const double* lh_prop, const double* logu1, int64_t Q,
+                    int32_t d, int32_t* idx, int32_t* count, int32_t* work, void* stream) {
+  if (Q < 0 || d < 1) return fail(ARGUS_E_INVAL, "bad sizes");
+  if (!count) return fail(ARGUS_E_INVAL, "count is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = (int)blocks(Q, kScanBlock);
+  if (Q == 0) {
+    hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(64), 0, st,
+                       DA1Args{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d,
+                               nullptr, nullptr, nullptr, count, nullptr},
+                       0);
+    HIPCHK(hipGetLastError());
+    return ARGUS_OK;
+  }
+  if (!theta_prop || !lo || !hi || !lh_cur || !lh_prop || !logu1 || !idx || !work)
+    return fail(ARGUS_E_INVAL, "NULL argument");
+  // work = [stage-1 flags (Q) | per-block counts (nb) | per-block offsets (nb)]
+  DA1Args a{theta_prop, lo, hi, lh_cur, lh_prop, logu1, Q, d,
+            work + Q, work + Q + nb, idx, count, work};
+  hipLaunchKernelGGL(k_da1_count, dim3(nb), dim3(kScanBlock), 0, st, a);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(64), 0, st, a, nb);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_da1_write, dim3(nb), dim3(kScanBlock), 0, st, a);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+int64_t argus_da_work_size(int64_t Q) {
+  return Q <= 0 ? 0 : Q + 2 * ((Q + kScanBlock - 1) / kScanBlock);
+}
+
+int argus_gather_rows(const double* src, const int32_t* idx, const int32_t* count, int64_t cap,
+                      int32_t d, double* dst, void* stream) {
+  if (cap < 0 || d < 1) return fail(ARGUS_E_INVAL, "bad sizes");
+  if (cap == 0) return ARGUS_OK;
+  if (!src || !idx || !count || !dst) return fail(ARGUS_E_INVAL, "NULL argument");
+  hipLaunchKernelGGL(k_gather_rows, dim3(blocks(cap * d, 256)), dim3(256), 0,
+                     (hipStream_t)stream, src, idx, count, cap, d, dst);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+int argus_da_stage2(const int32_t* idx, const int32_t* count, int64_t cap, const double* ll_prop,
+                    const double* lh_prop, const double* logu2, const double* theta_prop,
+                    double* theta_cur, double* ll_cur, double* lh_cur, int32_t* acc, int32_t d,
+                    void* stream) {
+  if (cap < 0 || d < 1) return fail(ARGUS_E_INVAL, "bad sizes");
+  if (cap == 0) return ARGUS_OK;
+  if (!idx || !count || !ll_prop || !lh_prop || !logu2 || !theta_prop || !theta_cur || !ll_cur ||
+      !lh_cur || !acc)
+    return fail(ARGUS_E_INVAL, "NULL argument");
+  DA2Args a{idx, count, ll_prop, lh_prop, logu2, theta_prop, theta_cur, ll_cur, lh_cur, acc, d};
+  hipLaunchKernelGGL(k_da2, dim3(blocks(cap, 256)), dim3(256), 0, (hipStream_t)stream, a);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+"""Surrogate MLP kernels (BF16 MFMA, FP32 accumulation) against the FP64
+oracle that emulates the BF16 roundings, and delayed acceptance against a
+decision-by-decision replay.
+
+Tolerances. Forward: |y - y_ref| <= 1e-2 * (sum_n |a3_n W4_n| + |b4|) in
+standardised units: both sides round the same values to BF16, but FP32
+accumulation can move a value across a BF16 rounding boundary (2^-8
+relative), which then propagates. Gradients: per block, |g - g_ref| <=
+2e-2 max|g_ref| + 1e-2 |g_ref|. Adam: FP32 vs FP64, 1e-5 relative."""
+import numpy as np
+import pytest
+
+import pta_inputs as pi
+
+pytestmark = pytest.mark.gpu
+D, W = 10, 256
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2510_11077_amd as A
+    return A
+
+
+def dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype or torch.float64, device="cuda")
+
+
+def rand_net(seed):
+    from oracle import mlp
+    flat = mlp.init(D, W, seed)
+    rng = np.random.default_rng(seed + 1)
+    p = mlp.unpack(flat, D, W)
+    for b in ("b1", "b2", "b3"):
+        p[b] = rng.normal(size=W).astype(np.float32).astype(np.float64) * 0.1
+    p["b4"] = np.array([0.3])
+    return mlp.pack(p, D, W).astype(np.float32).astype(np.float64)
+
+
+def make(A, flat, lo, hi, mu=0.0, sd=1.0, max_batch=512):
+    net = A.MLP(D, W, max_batch)
+    net.load(flat, lo, hi, mu, sd)
+    return net
+
+
+@pytest.mark.parametrize("Q", [1, 63, 1000])
+def test_forward_matches_oracle(A, Q):
+    from oracle import mlp
+    flat = rand_net(1)
+    lo, hi = np.full(D, -2.0), np.linspace(1.0, 3.0, D)
+    th = np.random.default_rng(2).uniform(lo, hi, size=(Q, D))
+    mu, sd = 1234.5, 17.0
+    net = make(A, flat, lo, hi, mu, sd)
+    y = net.eval(dev(th)).cpu().numpy()
+    x = mlp.standardise_inputs(th, lo, hi)
+    ref, cache = mlp.forward(flat, x, D, W, emulate=True)
+    p = mlp.unpack(flat, D, W)
+    scale = np.abs(cache["a3"] * p["W4"]).sum(1) + abs(p["b4"][0])
+    err = np.abs((y - mu) / sd - ref)
+    assert (err <= 1e-2 * scale).all(), (err / scale).max()
+    assert np.median(err / scale) < 1e-3
+
+
+def test_gradient_matches_oracle(A):
+    from oracle import mlp
+    flat = rand_net(3)
+    lo, hi = np.zeros(D), np.ones(D)
+    rng = np.random.default_rng(4)
+    B = 128
+    th = rng.uniform(0, 1, size=(B, D))
+    mu, sd = 10.0, 2.0
+    target = mu + sd * rng.normal(size=B)
+    net = make(A, flat, lo, hi, mu, sd)
+    g, loss = net.grad(dev(th), dev(target))
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = mlp.loss_and_grad(flat, mlp.standardise_inputs(th, lo, hi), (target - mu) / sd,
+                                   D, W, emulate=True)
+    assert abs(loss.item() - lref) <= 1e-2 * lref
+    o = 0
+    for name, shape in mlp.layout(D, W):
+        n = int(np.prod(shape))
+        a, b = g[o:o + n], gref[o:o + n]
+        assert (np.abs(a - b) <= 2e-2 * np.abs(b).max() + 1e-2 * np.abs(b)).all(), name
+        o += n
+
+
+def test_adam_step_matches_oracle(A):
+    import torch
+    from oracle import mlp
+    flat = rand_net(5)
+    lo, hi = np.zeros(D), np.ones(D)
+    rng = np.random.default_rng(6)
+    B = 256
+    th, target = rng.uniform(0, 1, size=(B, D)), rng.normal(size=B)
+    net = make(A, flat, lo, hi)
+    w, m, v = flat.copy(), np.zeros_like(flat), np.zeros_like(flat)
+    for step in range(1, 4):
+        g, _ = net.grad(dev(th), dev(target))  # the gradient this step will use
+        g = g.cpu().numpy().astype(np.float64)
+        net.train_step(dev(th), dev(target), 1e-3)
+        torch.cuda.synchronize()
+        w, m, v = mlp.adam(w, g, m, v, step, 1e-3)
+        got = net.master.cpu().numpy().astype(np.float64)
+        assert np.allclose(got, w, rtol=1e-5, atol=1e-7), step
+        assert np.allclose(net.m.cpu().numpy(), m, rtol=1e-5, atol=1e-10)
+        assert np.allclose(net.v.cpu().numpy(), v, rtol=1e-4, atol=1e-14)
+
+
+def test_training_lowers_the_loss(A):
+    """A smooth function of 10 inputs: 150 Adam steps on batches of 512."""
+    rng = np.random.default_rng(7)
+    lo, hi = np.zeros(D), np.ones(D)
+    f = lambda t: 50.0 * np.sin(3 * t[:, 0]) + 30.0 * t[:, 1] * t[:, 2] - 20 * t[:, 3] ** 2
+    from oracle import mlp
+    net = make(A, mlp.init(D, W, 8), lo, hi, 0.0, 40.0)
+    th_all = rng.uniform(0, 1, size=(512 * 150, D))
+    y_all = f(th_all)
+    first = None
+    for i in range(150):
+        th = dev(th_all[i * 512:(i + 1) * 512])
+        loss = net.train_step(th, dev(y_all[i * 512:(i + 1) * 512]), 2e-3).item()
+        first = loss if first is None else first
+    test = rng.uniform(0, 1, size=(2000, D))
+    pred = net.eval(dev(test)).cpu().numpy()
+    rmse = np.sqrt(np.mean((pred - f(test)) ** 2))
+    assert loss < 0.1 * first and rmse < 0.2 * np.std(f(test)), (first, loss, rmse)
+
+
+# ------------------------------------------------------- delayed acceptance
+def test_stage1_compaction_and_stage2(A):
+    import torch
+    rng = np.random.default_rng(9)
+    Q, d = 1000, 3
+    lo, hi = np.zeros(d), np.ones(d)
+    prop = rng.uniform(-0.1, 1.1, size=(Q, d))
+    lh_cur, lh_prop = rng.normal(size=Q), rng.normal(size=Q)
+    lu1, lu2 = np.log(rng.uniform(size=Q)), np.log(rng.uniform(size=Q))
+    inbox = np.all((prop >= lo) & (prop <= hi), axis=1)
+    keep = inbox & (lu1 < lh_prop - lh_cur)
+    idx_ref = np.nonzero(keep)[0]
+    t = {k: dev(v) for k, v in dict(prop=prop, lo=lo, hi=hi, lh_cur=lh_cur, lh_prop=lh_prop,
+                                    lu1=lu1, lu2=lu2).items()}
+    idx = torch.full((Q,), -1, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    work = torch.empty(A.da_work_size(Q), dtype=torch.int32, device="cuda")
+    A.da_stage1(t["prop"], t["lo"], t["hi"], t["lh_cur"], t["lh_prop"], t["lu1"], idx, count, work)
+    n = count.item()
+    assert n == idx_ref.size and np.array_equal(idx.cpu().numpy()[:n], idx_ref)
+    assert np.array_equal(work.cpu().numpy()[:Q], keep.astype(np.int32))
+    cap = 512
+    sub = torch.empty((cap, d), dtype=torch.float64, device="cuda")
+    A.gather_rows(t["prop"], idx, count, cap, sub)
+    s = sub.cpu().numpy()
+    assert np.array_equal(s[:n], prop[idx_ref]) and (s[n:] == prop[idx_ref[-1]]).all()
+    ll_prop = rng.normal(size=cap)
+    cur = rng.uniform(0, 1, size=(Q, d))
+    ll_cur = rng.normal(size=Q)
+    th_cur, llc, lhc = dev(cur), dev(ll_cur), t["lh_cur"].clone()
+    acc = torch.zeros(Q, dtype=torch.int32, device="cuda")
+    A.da_stage2(idx, count, cap, dev(ll_prop), t["lh_prop"], t["lu2"], t["prop"], th_cur, llc, lhc,
+                acc)
+    exp_cur, exp_ll, exp_lh = cur.copy(), ll_cur.copy(), lh_cur.copy()
+    for j, i in enumerate(idx_ref):
+        if lu2[i] < (ll_prop[j] - ll_cur[i]) - (lh_prop[i] - lh_cur[i]):
+            exp_cur[i], exp_ll[i], exp_lh[i] = prop[i], ll_prop[j], lh_prop[i]
+    assert np.array_equal(th_cur.cpu().numpy(), exp_cur)
+    assert np.array_equal(llc.cpu().numpy(), exp_ll) and np.array_equal(lhc.cpu().numpy(), exp_lh)
+
+
+def test_da_chain_replays_exactly(A):
+    """Three DA iterations of 256 chains on a 2-pulsar dataset: every chain
+    state equals the per-chain reference decisions (oracle logL at the
+    survivors, the recorded surrogate values and random numbers)."""
+    import torch
+    import oracle
+    d = pi.subset(pi.make_pta("t", n_psr=2, counts=[60, 40], seed=50), [0, 1])
+    d.free = np.zeros(d.n_canon, bool)
+    d.free[[0, 1, 2]] = True
+    ds = A.Dataset(d)
+    from oracle import mlp
+    lo, hi = d.lo[d.free], d.hi[d.free]
+    net = A.MLP(3, 64, 64)
+    ll_truth, _ = oracle.loglike(d, d.truth[None])
+    net.load(mlp.init(3, 64, 1), lo, hi, float(ll_truth[0]), 10.0)
+    Q = 256
+    th0 = dev(np.clip(d.truth[d.free] + np.random.default_rng(1).normal(size=(Q, 3)) * 0.05, lo, hi))
+    sampler = A.DelayedAcceptance(ds, net, th0, lo, hi, (hi - lo) * 0.02, seed=3)
+    rec = []
+    for _ in range(3):
+        sampler.step(record=rec)
+    torch.cuda.synchronize()
+    cur = rec[0]["theta"].cpu().numpy()
+    llc = rec[0]["ll_cur"].cpu().numpy()
+    lhc = rec[0]["lh_cur"].cpu().numpy()
+    for r in rec:
+        prop = r["prop"].cpu().numpy()
+        lhp = r["lh_prop"].cpu().numpy()
+        lu1, lu2 = r["logu1"].cpu().numpy(), r["logu2"].cpu().numpy()
+        assert np.array_equal(r["theta"].cpu().numpy(), cur)
+        surv = [i for i in range(Q) if np.all((prop[i] >= lo) & (prop[i] <= hi))
+                and lu1[i] < lhp[i] - lhc[i]]
+        assert r["n"] == len(surv)
+        if surv:
+            llp, _ = oracle.loglike(d, d.to_canon(prop[surv]))
+            for j, i in enumerate(surv):
+                if lu2[i] < (llp[j] - llc[i]) - (lhp[i] - lhc[i]):
+                    cur[i], llc[i], lhc[i] = prop[i], llp[j], lhp[i]
+    assert np.array_equal(sampler.theta.cpu().numpy(), cur)
+    assert np.allclose(sampler.ll.cpu().numpy(), llc, rtol=1e-12, atol=0)
+
+
+def test_trained_surrogate_saves_exact_evaluations(A):
+    """What the learned part gains: on the 10-parameter 10-pulsar workload,
+    a surrogate trained on exact-filter targets near the truth lets delayed
+    acceptance skip most rejected proposals' exact evaluations, while its
+    chains agree with plain exact-likelihood MH run on the same random
+    numbers (same posterior means within Monte Carlo error)."""
+    import torch
+    d = pi.make_config("cfg5")
+    ds = A.Dataset(d)
+    lo, hi = d.lo[d.free], d.hi[d.free]
+    # training set: exact targets from the GPU filter, near the truth
+    th_tr = pi.theta_near_truth(d, 65536, 301, scale=0.02)
+    t_tr = dev(th_tr)
+    y_tr, _ = ds.loglike(t_tr)
+    y = y_tr.cpu().numpy()
+    from oracle import mlp
+    net = A.MLP(10, 256, 1024)
+    net.load(mlp.init(10, 256, 2), lo, hi, float(y.mean()), float(y.std()))
+    rng = np.random.default_rng(0)
+    for ep in range(4):
+        perm = rng.permutation(th_tr.shape[0])
+        for b in range(0, th_tr.shape[0], 1024):
+            sel = torch.as_tensor(perm[b:b + 1024], device="cuda")
+            net.train_step(t_tr[sel].contiguous(), y_tr[sel].contiguous(), 1e-3)
+    Q, T = 512, 40
+    th0 = dev(pi.theta_near_truth(d, Q, 401, scale=0.002))
+    step = (hi - lo) * 0.002
+    da = A.DelayedAcceptance(ds, net, th0, lo, hi, step, seed=5)
+    # plain MH on the same proposals and stage-2 uniforms
+    cur = th0.clone()
+    llc, _ = ds.loglike(cur)
+    llc = llc.clone()
+    lo_t, hi_t = dev(lo), dev(hi)
+    n_mh_exact = 0
+    for _ in range(T):
+        eps, lu1, lu2 = da.draws()
+        da.step(eps, lu1, lu2)
+        prop = cur + eps
+        inb = ((prop >= lo_t) & (prop <= hi_t)).all(1)
+        llp, _ = ds.loglike(prop.contiguous())
+        n_mh_exact += Q
+        acc = inb & (lu2 < llp - llc)
+        cur = torch.where(acc[:, None], prop, cur)
+        llc = torch.where(acc, llp, llc)
+    print("DA exact evaluations %d vs MH %d" % (da.n_exact, n_mh_exact))
+    assert da.n_exact < n_mh_exact, (da.n_exact, n_mh_exact)
+    m_da = da.theta.mean(0).cpu().numpy()
+    m_mh = cur.mean(0).cpu().numpy()
+    sd = cur.std(0).cpu().numpy() + 1e-12
+    assert (np.abs(m_da - m_mh) < 6 * sd / np.sqrt(Q) + 1e-3 * (hi - lo)).all()
