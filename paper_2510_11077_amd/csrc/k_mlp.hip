@@ -203,7 +203,8 @@ struct AdamArgs {
   __bf16 *w2T, *w3T;      // transposed copies
   int64_t n;
   int d_in, width;
-  float lr, b1, b2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+  // 1 - beta is formed in double on the host: 1.0f - 0.999f is 1.3e-5 off
+  float lr, b1, b2, omb1, omb2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
   int do_update;                  // 0: only refresh the copies from master
 };
 
@@ -232,8 +233,8 @@ __global__ void k_adam(AdamArgs a) {
   float w = a.master[i];
   if (a.do_update) {
     const float g = a.g[i];
-    const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
-    const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+    const float m = a.b1 * a.m[i] + a.omb1 * g;
+    const float v = a.b2 * a.v[i] + a.omb2 * g * g;
     a.m[i] = m;
     a.v[i] = v;
     w -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
@@ -504,6 +505,8 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
   a.lr = lr;
   a.b1 = 0.9f;
   a.b2 = 0.999f;
+  a.omb1 = (float)(1.0 - 0.9);
+  a.omb2 = (float)(1.0 - 0.999);
   a.eps = 1e-8f;
   a.c1 = update ? (float)(1.0 / (1.0 - std::pow(0.9, (double)step))) : 1.0f;
   a.c2 = update ? (float)(1.0 / (1.0 - std::pow(0.999, (double)step))) : 1.0f;
