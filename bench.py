@@ -30,6 +30,116 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 # Joseph rank-2 update of 10 entries 60, quadratic form 3, log-det 1.
 FLOP_PER_STEP_M2 = 135
 FLOP_PER_STEP_M1 = 47
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
+
+
+def surrogate_leg(A, pi, dev, stream, log):
+    """10-parameter, 10-pulsar workload: exact targets from the batched
+    filter, training on the GPU, inference throughput, accuracy, and
+    delayed-acceptance screening against plain MH on the same proposals."""
+    import numpy as np
+    import torch
+
+    d5 = pi.make_config("cfg5")
+    ds5 = A.Dataset(d5)
+    lo, hi = d5.lo[d5.free], d5.hi[d5.free]
+    out = {}
+    # 1M exact-filter targets in the high-likelihood region (two box sizes)
+    n_train = 1 << 20
+    th = np.concatenate([pi.theta_near_truth(d5, n_train // 2, 301, scale=0.02),
+                         pi.theta_near_truth(d5, n_train // 2, 302, scale=0.005)])
+    t_th = torch.as_tensor(th, dtype=torch.float64, device=dev)
+    y = torch.empty(n_train, dtype=torch.float64, device=dev)
+    chunk = 65536
+    ds5.loglike(t_th[:chunk], out=y[:chunk], want_status=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(0, n_train, chunk):
+        ds5.loglike(t_th[c:c + chunk], out=y[c:c + chunk], want_status=False)
+    torch.cuda.synchronize()
+    out["target_generation_evals_per_s"] = n_train / (time.perf_counter() - t0)
+    yn = y.cpu().numpy()
+    mu, sd = float(yn.mean()), float(yn.std())
+    net = A.MLP(10, 256, 4096)
+    net.load(pi.mlp_weights(10, 256, 1), lo, hi, mu, sd)
+    B, epochs = 4096, 12
+    rng = np.random.default_rng(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(n_train), device=dev)
+        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * ep / epochs))
+        for b in range(0, n_train, B):
+            sel = perm[b:b + B]
+            net.train_step(t_th[sel], y[sel], lr)
+            steps += 1
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out["train"] = {"samples": n_train, "epochs": epochs, "batch": B, "steps": steps,
+                    "seconds": train_s, "samples_per_s": steps * B / train_s,
+                    "final_loss": float(net.loss.item())}
+    log("surrogate: trained %d steps in %.2f s, loss %.3g" % (steps, train_s, net.loss.item()))
+    # inference throughput on 65,536 queries
+    Qn = 65536
+    tq = torch.as_tensor(pi.theta_near_truth(d5, Qn, 303, scale=0.005), dtype=torch.float64,
+                         device=dev)
+    yq = torch.empty(Qn, dtype=torch.float64, device=dev)
+    ms, _ = timed(lambda: net.eval(tq, out=yq), 50, 5, stream)
+    flop = 2.0 * (10 * 256 + 2 * 256 * 256 + 256) * Qn
+    out["eval_65536"] = {"ms_per_batch": ms, "evals_per_s": Qn / (ms * 1e-3),
+                         "roofline": {"bound": "mfma", "achieved": flop / (ms * 1e-3) / 1e12,
+                                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": flop / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}}
+    # accuracy on held-out posterior-bulk points
+    ye, _ = ds5.loglike(tq, want_status=False)
+    err = (yq - ye).abs().cpu().numpy()
+    out["accuracy_heldout_bulk"] = {"frac_abs_err_le_0.1": float((err <= 0.1).mean()),
+                                    "median_abs_err": float(np.median(err)),
+                                    "p90_abs_err": float(np.quantile(err, 0.9))}
+    # delayed acceptance vs plain MH on the same proposals, 65,536 chains
+    Qc, T = 65536, 10
+    th0 = torch.as_tensor(pi.theta_near_truth(d5, Qc, 401, scale=0.002), dtype=torch.float64,
+                          device=dev)
+    step = (hi - lo) * 0.005
+    da = A.DelayedAcceptance(ds5, net, th0, lo, hi, step, seed=7)
+    draws = [da.draws() for _ in range(T)]
+    for i in range(2):  # warm the fixed-size exact workspaces
+        da.step(*draws[i])
+    da.n_exact = da.n_prop = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(2, T):
+        da.step(*draws[i])
+    torch.cuda.synchronize()
+    da_s = time.perf_counter() - t0
+    n_prop = da.n_prop
+    # plain MH: every proposal evaluated exactly
+    cur = th0.clone()
+    llc, _ = ds5.loglike(cur, want_status=False)
+    llc = llc.clone()
+    lo_t = torch.as_tensor(lo, device=dev)
+    hi_t = torch.as_tensor(hi, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(2, T):
+        eps, _, lu2 = draws[i]
+        prop = (cur + eps).contiguous()
+        llp, _ = ds5.loglike(prop, want_status=False)
+        acc = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu2 < llp - llc)
+        cur = torch.where(acc[:, None], prop, cur)
+        llc = torch.where(acc, llp, llc)
+    torch.cuda.synchronize()
+    mh_s = time.perf_counter() - t0
+    out["delayed_acceptance_65536_chains"] = {
+        "screened_proposals_per_s": n_prop / da_s,
+        "plain_mh_proposals_per_s": n_prop / mh_s,
+        "exact_evals_fraction": da.n_exact / n_prop,
+        "iterations_timed": T - 2,
+    }
+    log("DA: %.4g proposals/s screened vs %.4g plain MH, exact fraction %.3f"
+        % (n_prop / da_s, n_prop / mh_s, da.n_exact / n_prop))
+    return out
 
 
 def log(msg):
@@ -183,6 +293,7 @@ def main():
             log("grad: %.3f ms/call, %.4g evals/s" % (ms4, S4 / (ms4 * 1e-3)))
         except A.ArgusError as e:
             extra["grad_47psr_1024samples"] = "unavailable: %s" % e
+        extra["surrogate_10psr_10param"] = surrogate_leg(A, pi, dev, stream, log)
     res["extra"] = extra
 
     # ------------------------------------------------------- CPU oracle

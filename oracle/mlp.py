@@ -57,20 +57,6 @@ def pack(p, d_in, width):
     return np.concatenate([np.asarray(p[name], np.float64).ravel() for name, _ in layout(d_in, width)])
 
 
-def init(d_in, width, seed):
-    """He-uniform weights, zero biases, as FP32 values."""
-    rng = np.random.default_rng(seed)
-    p = {}
-    for name, shape in layout(d_in, width):
-        if name.startswith("W"):
-            fan_in = shape[1] if len(shape) == 2 else shape[0]
-            lim = np.sqrt(6.0 / fan_in)
-            p[name] = rng.uniform(-lim, lim, size=shape).astype(np.float32).astype(np.float64)
-        else:
-            p[name] = np.zeros(shape)
-    return pack(p, d_in, width)
-
-
 def standardise_inputs(theta, lo, hi):
     """Map the prior box to [-1, 1]."""
     return 2.0 * (np.asarray(theta, np.float64) - lo) / (hi - lo) - 1.0

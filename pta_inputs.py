@@ -290,3 +290,17 @@ def theta_near_truth(d: PTAData, S: int, seed: int, scale=0.05) -> np.ndarray:
     lo, hi, tr = d.lo[d.free], d.hi[d.free], d.truth[d.free]
     w = (hi - lo) * scale
     return np.clip(tr + rng.uniform(-w, w, size=(S, tr.size)), lo, hi)
+
+
+def mlp_weights(d_in: int, width: int, seed: int) -> np.ndarray:
+    """Initial surrogate weights, packed as W1 [w, d], b1, W2 [w, w], b2,
+    W3 [w, w], b3, W4 [w], b4: He-uniform weights U(-sqrt(6/fan_in), ...),
+    zero biases, values representable in FP32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, shape in ((d_in, (width, d_in)), (width, (width, width)), (width, (width, width))):
+        lim = np.sqrt(6.0 / fan_in)
+        parts += [rng.uniform(-lim, lim, size=shape).ravel(), np.zeros(width)]
+    lim = np.sqrt(6.0 / width)
+    parts += [rng.uniform(-lim, lim, size=width), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)

@@ -32,7 +32,7 @@ def dev(x, dtype=None):
 
 def rand_net(seed):
     from oracle import mlp
-    flat = mlp.init(D, W, seed)
+    flat = pi.mlp_weights(D, W, seed)
     rng = np.random.default_rng(seed + 1)
     p = mlp.unpack(flat, D, W)
     for b in ("b1", "b2", "b3"):
@@ -122,7 +122,7 @@ def test_training_lowers_the_loss(A):
     lo, hi = np.zeros(D), np.ones(D)
     f = lambda t: 50.0 * np.sin(3 * t[:, 0]) + 30.0 * t[:, 1] * t[:, 2] - 20 * t[:, 3] ** 2
     from oracle import mlp
-    net = make(A, mlp.init(D, W, 8), lo, hi, 0.0, 40.0)
+    net = make(A, pi.mlp_weights(D, W, 8), lo, hi, 0.0, 40.0)
     th_all = rng.uniform(0, 1, size=(512 * 150, D))
     y_all = f(th_all)
     first = None
@@ -191,7 +191,7 @@ def test_da_chain_replays_exactly(A):
     lo, hi = d.lo[d.free], d.hi[d.free]
     net = A.MLP(3, 64, 64)
     ll_truth, _ = oracle.loglike(d, d.truth[None])
-    net.load(mlp.init(3, 64, 1), lo, hi, float(ll_truth[0]), 10.0)
+    net.load(pi.mlp_weights(3, 64, 1), lo, hi, float(ll_truth[0]), 10.0)
     Q = 256
     th0 = dev(np.clip(d.truth[d.free] + np.random.default_rng(1).normal(size=(Q, 3)) * 0.05, lo, hi))
     sampler = A.DelayedAcceptance(ds, net, th0, lo, hi, (hi - lo) * 0.02, seed=3)
@@ -236,7 +236,7 @@ def test_trained_surrogate_saves_exact_evaluations(A):
     y = y_tr.cpu().numpy()
     from oracle import mlp
     net = A.MLP(10, 256, 1024)
-    net.load(mlp.init(10, 256, 2), lo, hi, float(y.mean()), float(y.std()))
+    net.load(pi.mlp_weights(10, 256, 2), lo, hi, float(y.mean()), float(y.std()))
     rng = np.random.default_rng(0)
     for ep in range(4):
         perm = rng.permutation(th_tr.shape[0])

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import scipy.stats as ss
 
+import pta_inputs as pi
 from oracle import da, mlp
 
 D_IN, W = 10, 32  # a narrow network keeps the checks fast; layout is generic
@@ -42,7 +43,7 @@ def test_bf16_matches_torch():
 
 def test_forward_matches_torch():
     import torch
-    flat = mlp.init(D_IN, W, 1)
+    flat = pi.mlp_weights(D_IN, W, 1)
     flat[np.arange(flat.size) % 7 == 0] += 0.01  # nonzero biases
     x = np.random.default_rng(2).uniform(-1, 1, size=(40, D_IN))
     out, _ = mlp.forward(flat, x, D_IN, W, emulate=False)
@@ -52,7 +53,7 @@ def test_forward_matches_torch():
 
 def test_gradient_matches_autograd_and_fd():
     import torch
-    flat = mlp.init(D_IN, W, 3)
+    flat = pi.mlp_weights(D_IN, W, 3)
     rng = np.random.default_rng(4)
     x = rng.uniform(-1, 1, size=(24, D_IN))
     t = rng.normal(size=24)
@@ -95,7 +96,7 @@ def test_adam_matches_torch():
 
 
 def test_emulated_forward_is_close_to_exact():
-    flat = mlp.init(D_IN, W, 7)
+    flat = pi.mlp_weights(D_IN, W, 7)
     x = np.random.default_rng(8).uniform(-1, 1, size=(64, D_IN))
     a, _ = mlp.forward(flat, x, D_IN, W, emulate=True)
     b, _ = mlp.forward(flat, x, D_IN, W, emulate=False)
