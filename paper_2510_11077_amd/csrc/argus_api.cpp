@@ -400,7 +400,11 @@ int argus_loglike(argus_dataset_t ds, const double* theta, int64_t S, double* lo
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPCHK(hipStreamIsCapturing(st, &cs));
   const char* ng = std::getenv("ARGUS_NO_GRAPH");
-  if (cs != hipStreamCaptureStatusNone || (ng && std::strcmp(ng, "1") == 0))
+  const bool stable = w->last_theta == theta && w->last_out == logl && w->last_status == status;
+  w->last_theta = theta;
+  w->last_out = logl;
+  w->last_status = status;
+  if (cs != hipStreamCaptureStatusNone || (ng && std::strcmp(ng, "1") == 0) || !stable)
     return launch_loglike_seq(ds, w, theta, logl, status, w->cfg, st);
   if (!w->has_graph || w->g_theta != theta || w->g_out != logl || w->g_status != status) {
     if (w->has_graph) {

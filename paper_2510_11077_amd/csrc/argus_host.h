@@ -64,6 +64,11 @@ struct Workspace {
   const void* g_theta = nullptr;
   const void* g_out = nullptr;
   const void* g_status = nullptr;
+  // pointers of the previous call: a graph is captured and replayed only
+  // for pointers seen on two consecutive calls
+  const void* last_theta = nullptr;
+  const void* last_out = nullptr;
+  const void* last_status = nullptr;
   // gradient workspace: level-1 checkpoints, per-wave level-2 scratch,
   // per-pulsar gradient parts
   DevBuf ckpt, scratch, gpart, c1, seg_base, stat_tmp;

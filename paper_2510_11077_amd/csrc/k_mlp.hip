@@ -161,35 +161,60 @@ __global__ void k_dz_last(const float* dout, const float* W4, const float* z3, i
   dzT[(int64_t)n * ldT + m] = b;
 }
 
-// Row sums of a [rows x ld] bf16 matrix over its first B columns (the bias
-// gradients, from the transposed dZ), in index order.
-__global__ void k_rowsum_bf16(const __bf16* a, int rows, int64_t B, int64_t ld, float* out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  float acc = 0.0f;
-  const __bf16* p = a + r * ld;
-  for (int64_t m = 0; m < B; ++m) acc += (float)p[m];
-  out[r] = acc;
+// Fixed-order block reduction of 256 per-thread partial sums (deterministic).
+__device__ __forceinline__ float block_sum(float v, float* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const float r = sh[0];
+  __syncthreads();
+  return r;
 }
 
-// Output-layer gradients and the loss: gW4[n] = sum_m dout[m] a3T[n][m],
-// gb4 = sum_m dout[m], loss = sum_m sq[m] / B; one block, index order.
-__global__ void k_head_grad(const float* dout, const float* sq, const __bf16* a3T, int64_t ldT,
-                            int64_t B, int width, float* gW4, float* gb4, float* loss) {
-  for (int n = threadIdx.x; n < width; n += blockDim.x) {
-    float acc = 0.0f;
+// Row sums of a [rows x ld] bf16 matrix over its first B columns (the bias
+// gradients, from the transposed dZ): one block per row, each thread sums a
+// strided slice, then a fixed-order tree.
+__global__ void __launch_bounds__(256) k_rowsum_bf16(const __bf16* a, int rows, int64_t B,
+                                                     int64_t ld, float* out) {
+  __shared__ float sh[256];
+  const int r = blockIdx.x;
+  const __bf16* p = a + r * ld;
+  float acc = 0.0f;
+  for (int64_t m = threadIdx.x; m < B; m += 256) acc += (float)p[m];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[r] = acc;
+}
+
+// Output-layer gradients and the loss: block n < width computes
+// gW4[n] = sum_m dout[m] a3T[n][m]; block `width` computes gb4 = sum_m dout[m]
+// and loss = sum_m sq[m] / B. Fixed-order reductions.
+__global__ void __launch_bounds__(256) k_head_grad(const float* dout, const float* sq,
+                                                   const __bf16* a3T, int64_t ldT, int64_t B,
+                                                   int width, float* gW4, float* gb4,
+                                                   float* loss) {
+  __shared__ float sh[256];
+  const int n = blockIdx.x;
+  if (n < width) {
     const __bf16* p = a3T + n * ldT;
-    for (int64_t m = 0; m < B; ++m) acc = fmaf(dout[m], (float)p[m], acc);
-    gW4[n] = acc;
+    float acc = 0.0f;
+    for (int64_t m = threadIdx.x; m < B; m += 256) acc = fmaf(dout[m], (float)p[m], acc);
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) gW4[n] = acc;
+    return;
   }
+  float a = 0.0f, q = 0.0f;
+  for (int64_t m = threadIdx.x; m < B; m += 256) {
+    a += dout[m];
+    q += sq[m];
+  }
+  a = block_sum(a, sh);
+  q = block_sum(q, sh);
   if (threadIdx.x == 0) {
-    float a = 0.0f, s = 0.0f;
-    for (int64_t m = 0; m < B; ++m) {
-      a += dout[m];
-      s += sq[m];
-    }
     *gb4 = a;
-    *loss = s / (float)B;
+    *loss = q / (float)B;
   }
 }
 
@@ -359,6 +384,17 @@ struct argus_mlp {
   // inference buffers (grown on demand)
   argus::DevBuf e_x0, e_a, e_b;
   int64_t e_cap = 0;
+  // captured inference sequence, replayed for pointers seen on two
+  // consecutive calls
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t e_exec{};
+  bool e_has_graph = false;
+  const void *e_theta = nullptr, *e_out = nullptr, *l_theta = nullptr, *l_out = nullptr;
+  int64_t e_Q = -1, l_Q = -1;
+  ~argus_mlp() {
+    if (e_has_graph) (void)hipGraphExecDestroy(e_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
   // training buffers
   argus::DevBuf x0, x0T, z[3], a[3], aT[3], dz[3], dzT[3], t, dout, sq, g;
 };
@@ -449,7 +485,7 @@ int mlp_backprop(argus_mlp* h, const double* theta, const double* target, int64_
   hipLaunchKernelGGL(k_out_train, dim3(blocks(B, 256)), dim3(256), 0, st, A[2], B, w, p + oW4,
                      p + oW4 + w, h->t.as<float>(), h->dout.as<float>(), h->sq.as<float>());
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_head_grad, dim3(1), dim3(256), 0, st, h->dout.as<float>(),
+  hipLaunchKernelGGL(k_head_grad, dim3(w + 1), dim3(256), 0, st, h->dout.as<float>(),
                      h->sq.as<float>(), h->aT[2].as<__bf16>(), ldT, B, w, g + oW4, g + oW4 + w,
                      loss_out);
   HIPCHK(hipGetLastError());
@@ -469,7 +505,7 @@ int mlp_backprop(argus_mlp* h, const double* theta, const double* target, int64_
     gw.ldc = l == 0 ? d : w;
     (void)K_in;
     if ((rc = launch_gemm(EPI_WGRAD, gw, st))) return rc;
-    hipLaunchKernelGGL(k_rowsum_bf16, dim3(blocks(w, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_rowsum_bf16, dim3(w), dim3(256), 0, st,
                        h->dzT[l].as<__bf16>(), w, B, ldT, g + oW[l] + (int64_t)w * (l == 0 ? d : w));
     HIPCHK(hipGetLastError());
     if (l > 0) {
@@ -512,6 +548,25 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
   a.c2 = update ? (float)(1.0 / (1.0 - std::pow(0.999, (double)step))) : 1.0f;
   a.do_update = update ? 1 : 0;
   hipLaunchKernelGGL(k_adam, dim3(blocks(h->n, 256)), dim3(256), 0, st, a);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+int eval_seq(argus_mlp* h, const double* theta, int64_t Q, double* logl_hat, hipStream_t st) {
+  hipLaunchKernelGGL(k_prep, dim3(blocks(Q * kKin, 256)), dim3(256), 0, st, theta, Q, h->d_in,
+                     h->lo.as<double>(), h->hi.as<double>(), h->e_x0.as<__bf16>(), nullptr, 0,
+                     nullptr, 0.0, 1.0, nullptr);
+  HIPCHK(hipGetLastError());
+  __bf16* A = h->e_a.as<__bf16>();
+  __bf16* Bb = h->e_b.as<__bf16>();
+  // a1 -> A, a2 -> B, a3 -> A
+  int rc = hidden_forward(h, h->e_x0.as<__bf16>(), Q, A, Bb, A, false, st);
+  if (rc) return rc;
+  const int w = h->width;
+  const float* p = h->p32.as<float>();
+  const int64_t oW4 = (int64_t)w * h->d_in + w + 2 * ((int64_t)w * w + w);
+  hipLaunchKernelGGL(k_out_eval, dim3(blocks(Q, 256)), dim3(256), 0, st, A, Q, w, p + oW4,
+                     p + oW4 + w, h->mu, h->sd, logl_hat);
   HIPCHK(hipGetLastError());
   return ARGUS_OK;
 }
@@ -587,6 +642,10 @@ int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo, cons
   HIPCHK(hipStreamSynchronize(st));
   h->mu = out_mu;
   h->sd = out_sd;
+  if (h->e_has_graph) {  // the captured output kernel holds mu and sd by value
+    HIPCHK(hipGraphExecDestroy(h->e_exec));
+    h->e_has_graph = false;
+  }
   if ((rc = refresh(h, const_cast<float*>(master), nullptr, nullptr, false, 0.f, 0, st)))
     return rc;
   h->loaded = true;
@@ -607,22 +666,40 @@ int argus_surrogate_eval(argus_mlp_t h, const double* theta, int64_t Q, double* 
         (rc = h->e_b.alloc(cap * h->width * 2)))
       return rc;
     h->e_cap = cap;
+    if (h->e_has_graph) {
+      HIPCHK(hipGraphExecDestroy(h->e_exec));
+      h->e_has_graph = false;
+    }
   }
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_prep, dim3(blocks(Q * kKin, 256)), dim3(256), 0, st, theta, Q, h->d_in,
-                     h->lo.as<double>(), h->hi.as<double>(), h->e_x0.as<__bf16>(), nullptr, 0,
-                     nullptr, 0.0, 1.0, nullptr);
-  HIPCHK(hipGetLastError());
-  __bf16* A = h->e_a.as<__bf16>();
-  __bf16* Bb = h->e_b.as<__bf16>();
-  // a1 -> A, a2 -> B, a3 -> A
-  if ((rc = hidden_forward(h, h->e_x0.as<__bf16>(), Q, A, Bb, A, false, st))) return rc;
-  const int w = h->width;
-  const float* p = h->p32.as<float>();
-  const int64_t oW4 = (int64_t)w * h->d_in + w + 2 * ((int64_t)w * w + w);
-  hipLaunchKernelGGL(k_out_eval, dim3(blocks(Q, 256)), dim3(256), 0, st, A, Q, w, p + oW4,
-                     p + oW4 + w, h->mu, h->sd, logl_hat);
-  HIPCHK(hipGetLastError());
+  const bool stable = h->l_theta == theta && h->l_out == logl_hat && h->l_Q == Q;
+  h->l_theta = theta;
+  h->l_out = logl_hat;
+  h->l_Q = Q;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(st, &cs));
+  if (!stable || cs != hipStreamCaptureStatusNone) return eval_seq(h, theta, Q, logl_hat, st);
+  if (!h->e_has_graph || h->e_theta != theta || h->e_out != logl_hat || h->e_Q != Q) {
+    if (h->e_has_graph) {
+      HIPCHK(hipGraphExecDestroy(h->e_exec));
+      h->e_has_graph = false;
+    }
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = eval_seq(h, theta, Q, logl_hat, h->cap_stream);
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(ARGUS_E_HIP, "hipStreamEndCapture failed");
+    e = hipGraphInstantiate(&h->e_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(ARGUS_E_HIP, "hipGraphInstantiate failed");
+    h->e_has_graph = true;
+    h->e_theta = theta;
+    h->e_out = logl_hat;
+    h->e_Q = Q;
+  }
+  HIPCHK(hipGraphLaunch(h->e_exec, st));
   return ARGUS_OK;
 }
 
