@@ -6,19 +6,33 @@
 // propagate over the interval since the previous TOA and the measurement of
 // pulsar p updates the joint state.
 //
-// Mapping on CDNA4: one workgroup (256 threads) per parameter sample. The
-// symmetric covariance is cut into 4x4 blocks (a, b), a >= b; each thread
-// holds one block in VGPRs (P(P+1)/2 <= 256). Per TOA:
-//   phase A  every thread predicts its block, F_a P_ab F_b^T + Q_ab (F is
-//            block-diagonal and sparse, Q is block-diagonal plus the HD
-//            term G_ab v_c (1 - phi_c^2) on the (g, g) entry); the threads of
-//            block row/column p write u = P H^T for their pulsar to LDS; the
-//            diagonal owner of p forms the innovation; P threads precompute
-//            the red-OU decay of every pulsar for the next TOA.
-//   barrier
-//   phase B  every thread applies the Joseph rank-2 update
-//            P_ab - K_a u_b^T - u_a K_b^T + S K_a K_b^T to its block.
-// LDS buffers alternate between TOAs, so one barrier per TOA suffices.
+// Blocked evaluation (same recursion, TOAs taken kB at a time). Given the
+// posterior (x0, P0) at the start of a block, the block's measurements are
+// jointly Gaussian: y_k = h_k^T (A_k x0 + xi_k) + eps_k with A_k the
+// block-diagonal transition from the block start to TOA k and xi_k the
+// process noise accumulated since then, whose covariances are closed forms
+// of the elapsed time tau (spin: sigma_s^2 [[t^3/3, t^2/2], [t^2/2, t]];
+// OU: v (1 - e^{-2 rate t}); common: Gamma v_c (1 - e^{-2 lambda t})) and
+// Cov(xi_k, xi_j) = A_{k<-j} Qacc(tau_j) for k >= j. With
+//   Sigma_B[k][j] = h_k^T A_k P0 A_j^T h_j + h_k^T A_{k<-j} Qacc_j h_j + R_k d_kj,
+//   r_k = y_k - h_k^T A_k x0,  L L^T = Sigma_B,  a = L^{-1} r,
+// the Cholesky pivots are exactly the sequential filter's innovation
+// variances S_k = L_kk^2 and a_k = e_k / sqrt(S_k), so the block adds
+// -1/2 sum_k (ln 2 pi + ln S_k + a_k^2) to log L (prediction-error
+// decomposition). The posterior at the block's last TOA is
+//   G = Cov(x_end, y) = A_end P0 A^T H^T + (A_{end<-j} Qacc_j h_j)_j,
+//   V = G L^{-T},  x_end = A_end x0 + V a,
+//   P_end = A_end P0 A_end^T + Qacc_end - V V^T,
+// and the rank-kB downdate V V^T (an n x kB by kB x n product) runs on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Mapping on CDNA4: one workgroup (256 threads) per parameter sample; P0
+// (full n x n, FP64) and the block's work arrays live in LDS (~110 KB).
+// Per block: per-TOA constants (threads j < kB) | T = P0 A^T H^T | Sigma_B and
+// G | Cholesky with the residual as an extra column (wave 0) | V and the
+// mean (row threads) | structured transition + accumulated noise of P0 (one
+// 4x4 block per thread) | P -= V V^T on MFMA tiles. Seven barriers per kB
+// TOAs instead of one per TOA.
 #include <hip/hip_runtime.h>
 
 #include "argus_host.h"
@@ -30,7 +44,10 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxP = kJointMaxPsr;
-constexpr int kChunk = 64;  // TOAs per decay table / ledger fold
+constexpr int kB = 16;                                   // TOAs per block
+constexpr int kNPad = ((4 * kMaxP + 15) / 16) * 16;     // padded state dim
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool finite_d(double v) {
   return __builtin_amdgcn_class(v, 0x1F8);
@@ -55,36 +72,33 @@ __device__ __forceinline__ double prm(const JointArgs& a, int c, int64_t s) {
 }
 
 __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
-  // red-OU decay and noise of every pulsar for the next kChunk TOAs
-  __shared__ double s_ph[kChunk][kMaxP], s_q[kChunk][kMaxP];
-  // (S, e) of each TOA of the chunk, folded into the likelihood by wave 0
-  __shared__ double s_led[kChunk][2];
-  __shared__ double s_rec[kChunk][8];
-  __shared__ double s_u[2][4 * kMaxP];
-  __shared__ double s_e[2];
+  __shared__ double sP[kNPad * kNPad];    // covariance at the block start
+  __shared__ double sT[kNPad][kB];        // P0 A^T H^T
+  __shared__ double sG[kNPad][kB];        // G, then V
+  __shared__ double sS[kB][kB + 1];       // Sigma_B | r  ->  L | a
+  __shared__ double sx[2][kNPad];         // mean, double-buffered by block
+  __shared__ double s_hd[kMaxP * kMaxP];
   __shared__ double s_vr[kMaxP], s_gr[kMaxP], s_ef2[kMaxP], s_eq2[kMaxP];
+  __shared__ double s_eqe[kMaxP], s_qae[kMaxP];  // red decay / noise to the block end
+  __shared__ double s_tau[kB], s_eg[kB], s_ec[kB], s_qrr[kB], s_qrf[kB], s_qa[kB];
+  __shared__ double s_sc[kB], s_R[kB], s_ege[kB], s_ece[kB];
+  __shared__ int s_p[kB];
+  __shared__ double s_end[6];  // tau_end, ec_end, sc_end, qrr_end, qrf_end, qff_end
   __shared__ double s_vc;
   __shared__ int s_pnf;
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
   const int64_t s = blockIdx.x;
   const int P = a.P;
-  const int nb = P * (P + 1) / 2;
-  // block owned by this thread: (ba, bb), ba >= bb
-  int ba = 0, bb = 0;
-  {
-    int t = tid, r = 0;
-    while (t >= r + 1) {
-      t -= r + 1;
-      ++r;
-    }
-    ba = r;
-    bb = t;
-  }
-  const bool owner = tid < nb;
-  const bool diag = owner && ba == bb;
+  const int n = 4 * P;
+  const int np = ((n + 15) / 16) * 16;
+  const double lam = a.mc.lam, ss2 = a.mc.ss2;
 
+  for (int i = tid; i < np * np; i += kThreads) sP[i] = 0.0;
+  for (int i = tid; i < 2 * kNPad; i += kThreads) (&sx[0][0])[i] = 0.0;
+  for (int i = tid; i < P * P; i += kThreads) s_hd[i] = a.hd[i];
   if (tid == 0) {
     const double la = prm(a, 4 * P, s), gc = prm(a, 4 * P + 1, s);
     const double gm1 = gc - 1.0;
@@ -108,176 +122,269 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   }
   __syncthreads();
   const double vc = s_vc;
-  const double gvc = owner ? a.hd[ba * P + bb] * vc : 0.0;  // G_ab v_c
-  // covariance block B[i][j] = Cov(state i of pulsar ba, state j of pulsar bb)
-  double B[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) B[i][j] = 0.0;
-  if (diag) {
-    B[0][0] = a.mc.s_r2;
-    B[1][1] = a.mc.s_f2;
-    B[2][2] = s_vr[ba];
+  // prior at the epoch: diag(s_r^2, s_f^2, v_r) per pulsar, G v_c on g-g
+  if (tid < P) {
+    const int q = tid;
+    sP[(4 * q) * np + 4 * q] = a.mc.s_r2;
+    sP[(4 * q + 1) * np + 4 * q + 1] = a.mc.s_f2;
+    sP[(4 * q + 2) * np + 4 * q + 2] = s_vr[q];
   }
-  B[3][3] = gvc;
-  double x[4] = {0.0, 0.0, 0.0, 0.0};  // mean of pulsar ba (diagonal owners)
-  const double ss2 = a.mc.ss2;
-  // per-lane ledger of wave 0: lane l folds TOAs k = l mod kChunk
+  for (int i = tid; i < P * P; i += kThreads) {
+    const int qa = i / P, qb = i - qa * P;
+    sP[(4 * qa + 3) * np + 4 * qb + 3] = s_hd[i] * vc;
+  }
+  // block ownership for the structured transition: 4x4 block (ba, bb), ba >= bb
+  int ba = 0, bb = 0;
+  {
+    int t = tid, r = 0;
+    while (t >= r + 1) {
+      t -= r + 1;
+      ++r;
+    }
+    ba = r;
+    bb = t;
+  }
+  const bool owner = tid < P * (P + 1) / 2;
+  // ledger (thread 0): sum a_k^2, product of S_k as mantissa and exponent,
+  // first failure
   double quad = 0.0, lm = 1.0;
-  int le = 0, fail_code = 0;
-  int64_t fail_k = INT64_MAX;
+  int le = 0, st = 0;
+  int xb = 0;
+  __syncthreads();
 
-  for (int64_t k0 = 0; k0 < a.N; k0 += kChunk) {
-    const int n = (int)(a.N - k0 < kChunk ? a.N - k0 : kChunk);
-    // stage the chunk's TOA records in LDS (8 doubles each; the last slot
-    // carries the pulsar index) and build its decay table, (TOA j, pulsar q)
-    // spread over all threads
-    for (int idx = tid; idx < n * 8; idx += kThreads)
-      s_rec[idx >> 3][idx & 7] = reinterpret_cast<const double*>(a.rec + k0)[idx];
-    for (int idx = tid; idx < n * P; idx += kThreads) {
-      const int q = idx / n, j = idx - q * n;
-      const double em = expm1_k(-s_gr[q] * a.rec[k0 + j].dt);
-      s_ph[j][q] = 1.0 + em;
-      s_q[j][q] = s_vr[q] * (-em * (2.0 + em));
+  for (int64_t k0 = 0; k0 < a.N; k0 += kB) {
+    const int nb = (int)(a.N - k0 < kB ? a.N - k0 : kB);
+    // ---- 1. per-TOA constants of the block: elapsed tau, decays, noise
+    if (tid < nb) {
+      const int j = tid;
+      double tau = 0.0;
+      for (int l = 0; l <= j; ++l) tau += a.rec[k0 + l].dt;
+      const TOARec r = a.rec[k0 + j];
+      const int p = r.psr;
+      const double em = expm1_k(-s_gr[p] * tau);
+      const double emc = expm1_k(-lam * tau);
+      s_tau[j] = tau;
+      s_eg[j] = 1.0 + em;
+      s_ec[j] = 1.0 + emc;
+      s_qrr[j] = ss2 * (tau * tau * tau / 3.0);
+      s_qrf[j] = ss2 * (tau * tau * 0.5);
+      s_qa[j] = s_vr[p] * (-em * (2.0 + em));
+      s_sc[j] = -emc * (2.0 + emc);
+      s_R[j] = fma(s_ef2[p], r.s2, s_eq2[p]);
+      s_p[j] = p;
+      sS[j][kB] = r.y;  // residual formed in phase 2
+      if (j == nb - 1) s_end[0] = tau;
     }
     __syncthreads();
-    // values of TOA j used before the barrier; those of j + 1 are read from
-    // LDS during the update phase of j, off the critical path
-    double r_dt = s_rec[0][0], r_h2 = s_rec[0][1], r_h3 = s_rec[0][2];
-    double r_phc = s_rec[0][3], r_qcu = s_rec[0][4], r_y = s_rec[0][5];
-    double r_s2 = s_rec[0][6];
-    int r_p = __double_as_longlong(s_rec[0][7]) & 0xffffffff;
-    double pa = s_ph[0][ba], pb = s_ph[0][bb], qa = s_q[0][ba];
-    for (int j = 0; j < n; ++j) {
-      const int64_t k = k0 + j;
-      const int buf = (int)(k & 1);
-      const int p = __builtin_amdgcn_readfirstlane(r_p);
-      const double dt = r_dt, phc = r_phc;
-      if (owner) {
-        // rows: F_a B
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          B[0][c] = fma(dt, B[1][c], B[0][c]);
-          B[2][c] *= pa;
-          B[3][c] *= phc;
-        }
-        // columns: (F_a B) F_b^T
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          B[i][0] = fma(dt, B[i][1], B[i][0]);
-          B[i][2] *= pb;
-          B[i][3] *= phc;
-        }
-        B[3][3] = fma(gvc, r_qcu, B[3][3]);
-        if (diag) {
-          B[0][0] += ss2 * r_h3;
-          B[0][1] += ss2 * r_h2;
-          B[1][0] += ss2 * r_h2;
-          B[1][1] += ss2 * dt;
-          B[2][2] += qa;
-          x[0] = fma(dt, x[1], x[0]);
-          x[2] *= pa;
-          x[3] *= phc;
-          if (ba == p) s_e[buf] = r_y - (x[0] + x[2] + x[3]);
-        }
-        // u = P H^T for the pulsar paired with p in this block
-        if (bb == p) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) s_u[buf][4 * ba + i] = B[i][0] + B[i][2] + B[i][3];
-        } else if (ba == p) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) s_u[buf][4 * bb + c] = B[0][c] + B[2][c] + B[3][c];
-        }
+    // ---- 2. residuals, decays to the block end, T = P0 A^T H^T
+    const double tau_e = s_end[0];
+    const double* x0 = sx[xb];
+    if (tid < nb) {
+      const int j = tid, p = s_p[j];
+      const double dte = tau_e - s_tau[j];
+      s_ege[j] = 1.0 + expm1_k(-s_gr[p] * dte);
+      s_ece[j] = 1.0 + expm1_k(-lam * dte);
+      sS[j][kB] -= x0[4 * p] + s_tau[j] * x0[4 * p + 1] + s_eg[j] * x0[4 * p + 2] +
+                   s_ec[j] * x0[4 * p + 3];
+    } else if (tid >= kWave && tid < kWave + P) {
+      const int q = tid - kWave;
+      const double em = expm1_k(-s_gr[q] * tau_e);
+      s_eqe[q] = 1.0 + em;
+      s_qae[q] = s_vr[q] * (-em * (2.0 + em));
+    } else if (tid == 2 * kWave) {
+      const double emc = expm1_k(-lam * tau_e);
+      s_end[1] = 1.0 + emc;
+      s_end[2] = -emc * (2.0 + emc);
+      s_end[3] = ss2 * (tau_e * tau_e * tau_e / 3.0);
+      s_end[4] = ss2 * (tau_e * tau_e * 0.5);
+      s_end[5] = ss2 * tau_e;
+    }
+    for (int idx = tid; idx < n * nb; idx += kThreads) {
+      const int i = idx / nb, j = idx - i * nb;
+      const double* row = sP + i * np + 4 * s_p[j];
+      sT[i][j] = row[0] + s_tau[j] * row[1] + s_eg[j] * row[2] + s_ec[j] * row[3];
+    }
+    __syncthreads();
+    // ---- 3. Sigma_B (lower triangle) and G
+    const double ec_e = s_end[1];
+    for (int idx = tid; idx < nb * nb; idx += kThreads) {
+      const int k = idx / nb, j = idx - k * nb;
+      if (j > k) continue;
+      const int p = s_p[j], pk = s_p[k];
+      const double base = sT[4 * pk][j] + s_tau[k] * sT[4 * pk + 1][j] +
+                          s_eg[k] * sT[4 * pk + 2][j] + s_ec[k] * sT[4 * pk + 3][j];
+      const double dtk = s_tau[k] - s_tau[j];
+      double noise = (1.0 + expm1_k(-lam * dtk)) * (s_hd[pk * P + p] * vc) * s_sc[j];
+      if (pk == p)
+        noise += fma(dtk, s_qrf[j], s_qrr[j]) + (1.0 + expm1_k(-s_gr[p] * dtk)) * s_qa[j];
+      sS[k][j] = base + noise + (k == j ? s_R[k] : 0.0);
+    }
+    for (int idx = tid; idx < n * nb; idx += kThreads) {
+      const int i = idx / nb, j = idx - i * nb;
+      const int q = i >> 2, c = i & 3, p = s_p[j];
+      double g;
+      if (c == 0)
+        g = fma(tau_e, sT[i + 1][j], sT[i][j]);
+      else if (c == 1)
+        g = sT[i][j];
+      else if (c == 2)
+        g = s_eqe[q] * sT[i][j];
+      else
+        g = ec_e * sT[i][j] + s_ece[j] * (s_hd[q * P + p] * vc) * s_sc[j];
+      if (q == p) {
+        if (c == 0) g += fma(tau_e - s_tau[j], s_qrf[j], s_qrr[j]);
+        else if (c == 1) g += s_qrf[j];
+        else if (c == 2) g += s_ege[j] * s_qa[j];
       }
-      __syncthreads();
-      const double s2 = r_s2;
-      if (j + 1 < n) {
-        r_dt = s_rec[j + 1][0];
-        r_h2 = s_rec[j + 1][1];
-        r_h3 = s_rec[j + 1][2];
-        r_phc = s_rec[j + 1][3];
-        r_qcu = s_rec[j + 1][4];
-        r_y = s_rec[j + 1][5];
-        r_s2 = s_rec[j + 1][6];
-        r_p = __double_as_longlong(s_rec[j + 1][7]) & 0xffffffff;
-        pa = s_ph[j + 1][ba];
-        pb = s_ph[j + 1][bb];
-        qa = s_q[j + 1][ba];
-      }
-      const double* u = s_u[buf];
-      const double S =
-          (u[4 * p] + u[4 * p + 2] + u[4 * p + 3]) + fma(s_ef2[p], s2, s_eq2[p]);
-      const double inv = rcp_nr(S);
-      if (owner) {
-        double ua[4], ub[4], ka[4], kb[4], da[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          ua[i] = u[4 * ba + i];
-          ub[i] = u[4 * bb + i];
-          ka[i] = ua[i] * inv;
-          kb[i] = ub[i] * inv;
-          da[i] = fma(S, ka[i], -ua[i]);
+      sG[i][j] = g;
+    }
+    __syncthreads();
+    // ---- 4. Cholesky of Sigma_B with the residual column (wave 0)
+    if (wave == 0) {
+      for (int k = 0; k < nb; ++k) {
+        const double d = sS[k][k];
+        const double lk = sqrt(d);
+        const double il = 1.0 / lk;
+        const double ak = sS[k][kB] * il;
+        if (lane == 0) {
+          if (st == 0) {
+            if (!finite_d(d)) st = kNonFinite;
+            else if (!(d > 0.0)) st = kNonPD;
+            else if (!finite_d(ak)) st = kNonFinite;
+          }
+          quad = fma(ak, ak, quad);
+          const double pm = lm * d;
+          lm = __builtin_amdgcn_frexp_mant(pm);
+          le += __builtin_amdgcn_frexp_exp(pm);
         }
-        // Joseph form P - K u^T - u K^T + S K K^T = P - K u^T + (S K - u) K^T
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) B[i][c] = fma(da[i], kb[c], fma(-ka[i], ub[c], B[i][c]));
-        if (diag) {
-          const double e = s_e[buf];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x[i] = fma(ka[i], e, x[i]);
+        const int i1 = k + 1 + lane;
+        if (i1 < nb) sS[i1][k] *= il;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int m = nb - k - 1;
+        for (int f = lane; f < m * m; f += kWave) {
+          const int i = k + 1 + f / m, j = k + 1 + f % m;
+          if (j <= i) sS[i][j] = fma(-sS[i][k], sS[j][k], sS[i][j]);
         }
-      }
-      if (tid == 0) {
-        s_led[j][0] = S;
-        s_led[j][1] = s_e[buf];
+        if (lane < m) sS[k + 1 + lane][kB] = fma(-sS[k + 1 + lane][k], ak, sS[k + 1 + lane][kB]);
+        if (lane == 0) {
+          sS[k][k] = lk;
+          sS[k][kB] = ak;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    // wave 0 folds the chunk's innovations into its per-lane ledger
-    if (tid < kWave && lane < n) {
-      const double S = s_led[lane][0], e = s_led[lane][1];
-      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
-      if (!good && fail_code == 0) {
-        fail_code = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
-        fail_k = k0 + lane;
+    __syncthreads();
+    // ---- 5. V = G L^{-T} and the mean at the block end (row threads)
+    if (tid < n) {
+      const int i = tid, q = i >> 2, c = i & 3;
+      double g[kB];
+#pragma unroll
+      for (int k = 0; k < kB; ++k) g[k] = k < nb ? sG[i][k] : 0.0;
+      double xv = 0.0;
+#pragma unroll
+      for (int k = 0; k < kB; ++k) {
+        if (k < nb) {
+          const double v = g[k] * rcp_nr(sS[k][k]);
+          g[k] = v;
+          xv = fma(v, sS[k][kB], xv);
+#pragma unroll
+          for (int k2 = k + 1; k2 < kB; ++k2)
+            if (k2 < nb) g[k2] = fma(-v, sS[k2][k], g[k2]);
+        }
       }
-      quad = fma(e * e, rcp_nr(S), quad);
-      const double pm = lm * S;
-      lm = __builtin_amdgcn_frexp_mant(pm);
-      le += __builtin_amdgcn_frexp_exp(pm);
+#pragma unroll
+      for (int k = 0; k < kB; ++k)
+        if (k < nb) sG[i][k] = g[k];
+      double xa;
+      if (c == 0) xa = fma(tau_e, x0[i + 1], x0[i]);
+      else if (c == 1) xa = x0[i];
+      else if (c == 2) xa = s_eqe[q] * x0[i];
+      else xa = ec_e * x0[i];
+      sx[xb ^ 1][i] = xa + xv;
     }
+    // ---- 6a. P0 <- A_end P0 A_end^T + Qacc_end (one 4x4 block per thread)
+    if (owner) {
+      double B[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) B[i][j] = sP[(4 * ba + i) * np + 4 * bb + j];
+      const double pa = s_eqe[ba], pb = s_eqe[bb];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        B[0][j] = fma(tau_e, B[1][j], B[0][j]);
+        B[2][j] *= pa;
+        B[3][j] *= ec_e;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        B[i][0] = fma(tau_e, B[i][1], B[i][0]);
+        B[i][2] *= pb;
+        B[i][3] *= ec_e;
+      }
+      B[3][3] = fma(s_hd[ba * P + bb] * vc, s_end[2], B[3][3]);
+      if (ba == bb) {
+        B[0][0] += s_end[3];
+        B[0][1] += s_end[4];
+        B[1][0] += s_end[4];
+        B[1][1] += s_end[5];
+        B[2][2] += s_qae[ba];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          sP[(4 * ba + i) * np + 4 * bb + j] = B[i][j];
+          sP[(4 * bb + j) * np + 4 * ba + i] = B[i][j];
+        }
+    }
+    __syncthreads();
+    // ---- 6b. P0 -= V V^T on the FP64 matrix cores, lower tiles, mirrored
+    {
+      const int nt = np / 16;
+      const int ntiles = nt * (nt + 1) / 2;
+      for (int t = wave; t < ntiles; t += kThreads / kWave) {
+        int I = 0, tt = t;
+        while (tt >= I + 1) {
+          tt -= I + 1;
+          ++I;
+        }
+        const int J = tt;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[r] = sP[(16 * I + (lane >> 4) + 4 * r) * np + 16 * J + (lane & 15)];
+        const int ra = 16 * I + (lane & 15), rb = 16 * J + (lane & 15);
+#pragma unroll
+        for (int kc = 0; kc < kB / 4; ++kc) {
+          const int k = 4 * kc + (lane >> 4);
+          const double va = (ra < n && k < nb) ? -sG[ra][k] : 0.0;
+          const double vb = (rb < n && k < nb) ? sG[rb][k] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * I + (lane >> 4) + 4 * r, col = 16 * J + (lane & 15);
+          if (I > J || row >= col) {
+            sP[row * np + col] = acc[r];
+            sP[col * np + row] = acc[r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    xb ^= 1;
   }
-  // wave 0: combine the lanes in lane order; first failure = smallest TOA
-  if (tid < kWave) {
-    __shared__ double s_fold[kWave][2];
-    __shared__ int64_t s_fk[kWave];
-    __shared__ int s_fc[kWave];
-    s_fold[lane][0] = quad;
-    s_fold[lane][1] = log(lm) + (double)le * kLn2;
-    s_fk[lane] = fail_k;
-    s_fc[lane] = fail_code;
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) {
-      double qs = 0.0, ls = 0.0;
-      int64_t fk = INT64_MAX;
-      int st = 0;
-      for (int l = 0; l < kWave; ++l) {
-        qs += s_fold[l][0];
-        ls += s_fold[l][1];
-        if (s_fk[l] < fk) {
-          fk = s_fk[l];
-          st = s_fc[l];
-        }
-      }
-      if (s_pnf) st = kNonFinite;
-      double ll = -0.5 * ((double)a.N * kLn2Pi + ls + qs);
-      if (st == 0 && !finite_d(ll)) st = kNonFinite;
-      a.logl[s] = st ? -INFINITY : ll;
-      if (a.status) a.status[s] = st;
-    }
+  if (tid == 0) {
+    if (s_pnf) st = kNonFinite;
+    double ll = -0.5 * ((double)a.N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    if (st == 0 && !finite_d(ll)) st = kNonFinite;
+    a.logl[s] = st ? -INFINITY : ll;
+    if (a.status) a.status[s] = st;
   }
 }
 

@@ -204,3 +204,33 @@ def test_joint_cfg3_sampled(argus, orc):
     check(ll.cpu().numpy()[idx], st.cpu().numpy()[idx], ref, rst)
     assert (st.cpu().numpy() == 0).all()
     assert np.isfinite(ll.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("counts", [[1], [9, 8], [5, 0, 12], [3] * 22])
+def test_joint_block_edges(argus, orc, counts):
+    """Stream lengths around the 16-TOA block size, an empty pulsar, and the
+    largest supported joint model (22 pulsars, padded MFMA tiles)."""
+    d = pi.make_pta("t", n_psr=len(counts), counts=counts, seed=40 + len(counts),
+                    model=pi.M_JOINT)
+    run(argus, orc, d, pi.sample_theta(d, 5, 12))
+
+
+def test_joint_prior_corners_and_flags(argus, orc):
+    d = pi.make_pta("t", n_psr=4, counts=[20, 35, 3, 50], seed=47, model=pi.M_JOINT)
+    lo, hi = d.lo, d.hi
+    th = np.array([lo, hi, np.where(np.arange(lo.size) % 2, lo, hi), d.truth, d.truth])
+    th[3, 5] = np.nan
+    th[4, -1] = np.inf
+    run(argus, orc, d, th)
+    dz = pi.make_pta("t", n_psr=2, counts=[6, 7], seed=48, model=pi.M_JOINT)
+    dz.s_r = dz.s_f = dz.sigma_s = 0.0
+    z = np.tile(dz.truth, (2, 1))
+    z[0, [0, 4]] = -400.0
+    z[0, [2, 6]] = 0.0
+    z[0, [3, 7]] = -400.0
+    z[0, -2] = -400.0
+    ds = argus.Dataset(dz)
+    ll, st = ds.loglike(dev(z))
+    ref, rst = orc.loglike(dz, z)
+    assert rst[0] == 1
+    check(ll, st, ref, rst)
