@@ -15,24 +15,39 @@
 // OU: v (1 - e^{-2 rate t}); common: Gamma v_c (1 - e^{-2 lambda t})) and
 // Cov(xi_k, xi_j) = A_{k<-j} Qacc(tau_j) for k >= j. With
 //   Sigma_B[k][j] = h_k^T A_k P0 A_j^T h_j + h_k^T A_{k<-j} Qacc_j h_j + R_k d_kj,
-//   r_k = y_k - h_k^T A_k x0,  L L^T = Sigma_B,  a = L^{-1} r,
-// the Cholesky pivots are exactly the sequential filter's innovation
-// variances S_k = L_kk^2 and a_k = e_k / sqrt(S_k), so the block adds
-// -1/2 sum_k (ln 2 pi + ln S_k + a_k^2) to log L (prediction-error
-// decomposition). The posterior at the block's last TOA is
+//   r_k = y_k - h_k^T A_k x0,
 //   G = Cov(x_end, y) = A_end P0 A^T H^T + (A_{end<-j} Qacc_j h_j)_j,
-//   V = G L^{-T},  x_end = A_end x0 + V a,
-//   P_end = A_end P0 A_end^T + Qacc_end - V V^T,
-// and the rank-kB downdate V V^T (an n x kB by kB x n product) runs on the
+// Gaussian elimination of Sigma_B in TOA order (an L D L^T factorisation)
+// reproduces the sequential filter exactly: pivot k is the innovation
+// variance S_k and the eliminated residual is the innovation e_k, so the
+// block adds -1/2 sum_k (ln 2 pi + ln S_k + e_k^2 / S_k) to log L
+// (prediction-error decomposition). Eliminating the rows of G alongside
+// gives, column by column, u_k (the cross-covariance of the end state with
+// innovation k), and the posterior at the block's last TOA is
+//   x_end = A_end x0 + sum_k u_k e_k / S_k,
+//   P_end = A_end P0 A_end^T + Qacc_end - sum_k u_k u_k^T / S_k,
+// a rank-kB downdate U M^T (M = U S^{-1}, n x kB by kB x n) that runs on the
 // FP64 matrix cores (v_mfma_f64_16x16x4f64).
 //
-// Mapping on CDNA4: one workgroup (256 threads) per parameter sample; P0
-// (full n x n, FP64) and the block's work arrays live in LDS (~110 KB).
-// Per block: per-TOA constants (threads j < kB) | T = P0 A^T H^T | Sigma_B and
-// G | Cholesky with the residual as an extra column (wave 0) | V and the
-// mean (row threads) | structured transition + accumulated noise of P0 (one
-// 4x4 block per thread) | P -= V V^T on MFMA tiles. Seven barriers per kB
-// TOAs instead of one per TOA.
+// Mapping on CDNA4: one workgroup (4 waves) per parameter sample; P0 (full
+// n x n, FP64) and the block's work arrays live in LDS (~130 KB). Per block
+// of kB TOAs, three barriers:
+//   A  all waves: T = P0 A^T H^T (n x kB) and the lower triangle of Sigma_B
+//      from the 4x4 pulsar blocks of P0.
+//   C  waves 0-1: the elimination in registers. Lanes 0-15 of each wave hold
+//      the rows of Sigma_B with the residual, lanes 16-63 hold 48 rows of G
+//      (formed from T) with the predicted mean; pivot, innovation and the
+//      pivot column reach every lane by v_readlane, so the whole
+//      factorisation runs without LDS round trips or barriers.
+//      wave 2: P0 <- A_end P0 A_end^T + Qacc_end (one 4x4 pulsar block per
+//      lane). wave 3: the next block's per-TOA constants (elapsed times,
+//      decays, the noise part of its Sigma_B) from records staged in LDS, and
+//      the global loads of the records of the block after it.
+//   D  all waves: P -= U M^T on MFMA tiles (lower tiles, mirrored).
+// The final block is padded to kB with identity rows of Sigma_B, zero
+// residuals and zero columns of G: their pivots are exactly 1 and their
+// innovations exactly 0, so they leave log L, x and P unchanged while every
+// loop keeps a fixed trip count.
 #include <hip/hip_runtime.h>
 
 #include "argus_host.h"
@@ -46,11 +61,37 @@ constexpr int kThreads = 256;
 constexpr int kMaxP = kJointMaxPsr;
 constexpr int kB = 16;                                   // TOAs per block
 constexpr int kNPad = ((4 * kMaxP + 15) / 16) * 16;     // padded state dim
+constexpr int kLdP = kNPad + 2;                          // P row: 16-B aligned
+constexpr int kLdB = kB + 1;                             // rows of n x kB arrays
+constexpr int kPairs = kB * (kB + 1) / 2;               // lower triangle
+constexpr int kGRows = kWave - kB;                       // G rows per wave
+static_assert(2 * kGRows >= kNPad, "two elimination waves cover every row");
+static_assert(kGRows % 4 == 0, "a pulsar's four rows stay in one wave");
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bool finite_d(double v) {
   return __builtin_amdgcn_class(v, 0x1F8);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// row k, column j of the pair with lower-triangle index e (row-major)
+__device__ __forceinline__ void pair_of(int e, int& k, int& j) {
+  k = 0;
+  while ((k + 1) * (k + 2) / 2 <= e) ++k;
+  j = e - k * (k + 1) / 2;
 }
 
 struct JointArgs {
@@ -66,24 +107,45 @@ struct JointArgs {
   ModelConst mc;
 };
 
+// Per-block constants that depend on the TOA records and the parameters but
+// not on the state; prepared one block ahead.
+struct BlockConst {
+  double tau[kB];   // time from the block start (previous TOA) to TOA k
+  double eg[kB];    // e^{-rate_p tau}
+  double ec[kB];    // e^{-lambda tau}
+  double qrr[kB], qrf[kB];  // spin noise accumulated over tau
+  double qa[kB];    // red noise accumulated over tau
+  double sc[kB];    // 1 - e^{-2 lambda tau}
+  double y[kB];
+  double ege[kB], ece[kB];  // decays from TOA k to the block end
+  double nz[4][kB];         // own-pulsar noise of G by state component
+  double ecs[kB];           // ece * sc: common noise of G per unit Gamma v_c
+  double sn[kB][kB];        // noise + white part of Sigma_B (lower), padded identity
+  double eqe[kMaxP], qae[kMaxP];  // per pulsar: red decay / noise over the block
+  double end[6];    // tau_e, ec_e, sc_e, qrr_e, qrf_e, qff_e
+  int p[kB];
+  int nb;
+  int pad_;
+};
+static_assert(sizeof(BlockConst) % sizeof(double) == 0, "zeroed as doubles");
+
 __device__ __forceinline__ double prm(const JointArgs& a, int c, int64_t s) {
   const int j = a.col[c];
   return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
 }
 
 __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
-  __shared__ double sP[kNPad * kNPad];    // covariance at the block start
-  __shared__ double sT[kNPad][kB];        // P0 A^T H^T
-  __shared__ double sG[kNPad][kB];        // G, then V
-  __shared__ double sS[kB][kB + 1];       // Sigma_B | r  ->  L | a
-  __shared__ double sx[2][kNPad];         // mean, double-buffered by block
+  __shared__ double sP[kNPad * kLdP];      // covariance at the block start
+  __shared__ double sT[kNPad * kLdB];      // P0 A^T H^T
+  __shared__ double sU[(kNPad + kB) * kLdB];  // eliminated columns u_k
+  __shared__ double sM[(kNPad + kB) * kLdB];  // u_k / S_k
+  // (rows kNPad.. take the stores of the Sigma_B lanes, which are not read)
+  __shared__ double sS[kB * kLdB];         // Sigma_B, lower triangle
+  __shared__ double sx[2][kNPad + kB];     // mean, double-buffered by block
+  __shared__ double s_rec[2][kB][8];       // staged TOA records
+  __shared__ BlockConst s_bc[2];
   __shared__ double s_hd[kMaxP * kMaxP];
   __shared__ double s_vr[kMaxP], s_gr[kMaxP], s_ef2[kMaxP], s_eq2[kMaxP];
-  __shared__ double s_eqe[kMaxP], s_qae[kMaxP];  // red decay / noise to the block end
-  __shared__ double s_tau[kB], s_eg[kB], s_ec[kB], s_qrr[kB], s_qrf[kB], s_qa[kB];
-  __shared__ double s_sc[kB], s_R[kB], s_ege[kB], s_ece[kB];
-  __shared__ int s_p[kB];
-  __shared__ double s_end[6];  // tau_end, ec_end, sc_end, qrr_end, qrf_end, qff_end
   __shared__ double s_vc;
   __shared__ int s_pnf;
 
@@ -93,12 +155,25 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   const int64_t s = blockIdx.x;
   const int P = a.P;
   const int n = 4 * P;
-  const int np = ((n + 15) / 16) * 16;
+  const int nt = (n + 15) / 16;
+  const int nblk = P * (P + 1) / 2;
+  const int64_t N = a.N;
   const double lam = a.mc.lam, ss2 = a.mc.ss2;
+  const double* recd = reinterpret_cast<const double*>(a.rec);
 
-  for (int i = tid; i < np * np; i += kThreads) sP[i] = 0.0;
-  for (int i = tid; i < 2 * kNPad; i += kThreads) (&sx[0][0])[i] = 0.0;
+  for (int i = tid; i < kNPad * kLdP; i += kThreads) sP[i] = 0.0;
+  for (int i = tid; i < kNPad * kLdB; i += kThreads) sT[i] = 0.0;
+  for (int i = tid; i < (kNPad + kB) * kLdB; i += kThreads) sU[i] = sM[i] = 0.0;
+  for (int i = tid; i < 2 * (kNPad + kB); i += kThreads) (&sx[0][0])[i] = 0.0;
   for (int i = tid; i < P * P; i += kThreads) s_hd[i] = a.hd[i];
+  // padded columns of a short block read finite leftovers, never garbage
+  for (int i = tid; i < (int)(sizeof(s_bc) / sizeof(double)); i += kThreads)
+    reinterpret_cast<double*>(s_bc)[i] = 0.0;
+  for (int i = tid; i < 2 * kB * 8; i += kThreads) (&s_rec[0][0][0])[i] = 0.0;
+  __syncthreads();
+  // records of the first two blocks
+  for (int i = tid; i < 2 * kB * 8; i += kThreads)
+    if ((i >> 3) < N) (&s_rec[0][0][0])[i] = recd[i];
   if (tid == 0) {
     const double la = prm(a, 4 * P, s), gc = prm(a, 4 * P + 1, s);
     const double gm1 = gc - 1.0;
@@ -125,254 +200,306 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   // prior at the epoch: diag(s_r^2, s_f^2, v_r) per pulsar, G v_c on g-g
   if (tid < P) {
     const int q = tid;
-    sP[(4 * q) * np + 4 * q] = a.mc.s_r2;
-    sP[(4 * q + 1) * np + 4 * q + 1] = a.mc.s_f2;
-    sP[(4 * q + 2) * np + 4 * q + 2] = s_vr[q];
+    sP[(4 * q) * kLdP + 4 * q] = a.mc.s_r2;
+    sP[(4 * q + 1) * kLdP + 4 * q + 1] = a.mc.s_f2;
+    sP[(4 * q + 2) * kLdP + 4 * q + 2] = s_vr[q];
   }
   for (int i = tid; i < P * P; i += kThreads) {
     const int qa = i / P, qb = i - qa * P;
-    sP[(4 * qa + 3) * np + 4 * qb + 3] = s_hd[i] * vc;
+    sP[(4 * qa + 3) * kLdP + 4 * qb + 3] = s_hd[i] * vc;
   }
-  // block ownership for the structured transition: 4x4 block (ba, bb), ba >= bb
-  int ba = 0, bb = 0;
-  {
-    int t = tid, r = 0;
-    while (t >= r + 1) {
-      t -= r + 1;
-      ++r;
+
+  // fixed per-thread work assignments
+  int sk = 0, sj = 0;  // phase A: Sigma_B entry of threads < kPairs
+  if (tid < kPairs) pair_of(tid, sk, sj);
+  int pk3[3], pj3[3];  // wave 3: noise pairs of its lanes
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    pk3[u] = pj3[u] = 0;
+    if (lane + kWave * u < kPairs) pair_of(lane + kWave * u, pk3[u], pj3[u]);
+  }
+  int tba[4], tbb[4];  // wave 2: 4x4 pulsar blocks of its lanes
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int bb = lane + kWave * u, ba = 0;
+    while (bb >= ba + 1) {
+      bb -= ba + 1;
+      ++ba;
     }
-    ba = r;
-    bb = t;
+    tba[u] = ba;
+    tbb[u] = bb;
   }
-  const bool owner = tid < P * (P + 1) / 2;
-  // ledger (thread 0): sum a_k^2, product of S_k as mantissa and exponent,
-  // first failure
+
+  // Per-block constants of block b (first TOA k0) into s_bc[b & 1] from the
+  // records staged in s_rec[b & 1]; run by one whole wave.
+  auto prep = [&](int buf, int64_t k0) {
+    BlockConst& bc = s_bc[buf];
+    const double(*rec)[8] = s_rec[buf];
+    const int64_t rem = N - k0;
+    const int nb = rem < kB ? (int)rem : kB;
+    if (lane < kB) {
+      double tau = 0.0;
+#pragma unroll
+      for (int l = 0; l < kB; ++l) {
+        const double dt = rec[l][0];
+        if (l <= lane && l < nb) tau += dt;
+      }
+      if (lane < nb) {
+        const int p = (int)(__double_as_longlong(rec[lane][7]) & 0xffffffffll);
+        const double em = expm1_k(-s_gr[p] * tau);
+        const double emc = expm1_k(-lam * tau);
+        bc.tau[lane] = tau;
+        bc.eg[lane] = 1.0 + em;
+        bc.ec[lane] = 1.0 + emc;
+        bc.qrr[lane] = ss2 * (tau * tau * tau / 3.0);
+        bc.qrf[lane] = ss2 * (tau * tau * 0.5);
+        bc.qa[lane] = s_vr[p] * (-em * (2.0 + em));
+        bc.sc[lane] = -emc * (2.0 + emc);
+        bc.y[lane] = rec[lane][5];
+        bc.sn[lane][lane] = fma(s_ef2[p], rec[lane][6], s_eq2[p]);  // R_k for now
+        bc.p[lane] = p;
+        if (lane == nb - 1) bc.end[0] = tau;
+      }
+    }
+    if (lane == 0) bc.nb = nb;
+    wave_sync();
+    const double tau_e = bc.end[0];
+    if (lane < nb) {
+      const double dte = tau_e - bc.tau[lane];
+      const double ege = 1.0 + expm1_k(-s_gr[bc.p[lane]] * dte);
+      const double ece = 1.0 + expm1_k(-lam * dte);
+      bc.ege[lane] = ege;
+      bc.ece[lane] = ece;
+      bc.nz[0][lane] = fma(dte, bc.qrf[lane], bc.qrr[lane]);
+      bc.nz[1][lane] = bc.qrf[lane];
+      bc.nz[2][lane] = ege * bc.qa[lane];
+      bc.nz[3][lane] = 0.0;
+      bc.ecs[lane] = ece * bc.sc[lane];
+    } else if (lane >= kB && lane < kB + P) {
+      const int q = lane - kB;
+      const double em = expm1_k(-s_gr[q] * tau_e);
+      bc.eqe[q] = 1.0 + em;
+      bc.qae[q] = s_vr[q] * (-em * (2.0 + em));
+    } else if (lane == kWave - 1) {
+      const double emc = expm1_k(-lam * tau_e);
+      bc.end[1] = 1.0 + emc;
+      bc.end[2] = -emc * (2.0 + emc);
+      bc.end[3] = ss2 * (tau_e * tau_e * tau_e / 3.0);
+      bc.end[4] = ss2 * (tau_e * tau_e * 0.5);
+      bc.end[5] = ss2 * tau_e;
+    }
+    // noise part of Sigma_B: common OU (HD-coupled) for every pair, spin and
+    // red noise for pairs of one pulsar, R on the diagonal
+    double sv[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int k = pk3[u], j = pj3[u];
+      sv[u] = k == j ? 1.0 : 0.0;
+      if (lane + kWave * u < kPairs && k < nb) {
+        const int p = bc.p[j], pk = bc.p[k];
+        const double dtk = bc.tau[k] - bc.tau[j];
+        double v = (1.0 + expm1_k(-lam * dtk)) * (s_hd[pk * P + p] * vc) * bc.sc[j];
+        if (pk == p)
+          v += fma(dtk, bc.qrf[j], bc.qrr[j]) + (1.0 + expm1_k(-s_gr[p] * dtk)) * bc.qa[j];
+        if (k == j) v += bc.sn[k][k];
+        sv[u] = v;
+      }
+    }
+    wave_sync();  // R_k read above before the diagonal is overwritten
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (lane + kWave * u < kPairs) bc.sn[pk3[u]][pj3[u]] = sv[u];
+  };
+
+  // ledger (thread 0 keeps it): sum e_k^2 / S_k, product of S_k as mantissa
+  // and exponent, first failure
   double quad = 0.0, lm = 1.0;
   int le = 0, st = 0;
-  int xb = 0;
+  __syncthreads();
+  if (wave == 3 && N > 0) prep(0, 0);
   __syncthreads();
 
-  for (int64_t k0 = 0; k0 < a.N; k0 += kB) {
-    const int nb = (int)(a.N - k0 < kB ? a.N - k0 : kB);
-    // ---- 1. per-TOA constants of the block: elapsed tau, decays, noise
-    if (tid < nb) {
-      const int j = tid;
-      double tau = 0.0;
-      for (int l = 0; l <= j; ++l) tau += a.rec[k0 + l].dt;
-      const TOARec r = a.rec[k0 + j];
-      const int p = r.psr;
-      const double em = expm1_k(-s_gr[p] * tau);
-      const double emc = expm1_k(-lam * tau);
-      s_tau[j] = tau;
-      s_eg[j] = 1.0 + em;
-      s_ec[j] = 1.0 + emc;
-      s_qrr[j] = ss2 * (tau * tau * tau / 3.0);
-      s_qrf[j] = ss2 * (tau * tau * 0.5);
-      s_qa[j] = s_vr[p] * (-em * (2.0 + em));
-      s_sc[j] = -emc * (2.0 + emc);
-      s_R[j] = fma(s_ef2[p], r.s2, s_eq2[p]);
-      s_p[j] = p;
-      sS[j][kB] = r.y;  // residual formed in phase 2
-      if (j == nb - 1) s_end[0] = tau;
-    }
-    __syncthreads();
-    // ---- 2. residuals, decays to the block end, T = P0 A^T H^T
-    const double tau_e = s_end[0];
-    const double* x0 = sx[xb];
-    if (tid < nb) {
-      const int j = tid, p = s_p[j];
-      const double dte = tau_e - s_tau[j];
-      s_ege[j] = 1.0 + expm1_k(-s_gr[p] * dte);
-      s_ece[j] = 1.0 + expm1_k(-lam * dte);
-      sS[j][kB] -= x0[4 * p] + s_tau[j] * x0[4 * p + 1] + s_eg[j] * x0[4 * p + 2] +
-                   s_ec[j] * x0[4 * p + 3];
-    } else if (tid >= kWave && tid < kWave + P) {
-      const int q = tid - kWave;
-      const double em = expm1_k(-s_gr[q] * tau_e);
-      s_eqe[q] = 1.0 + em;
-      s_qae[q] = s_vr[q] * (-em * (2.0 + em));
-    } else if (tid == 2 * kWave) {
-      const double emc = expm1_k(-lam * tau_e);
-      s_end[1] = 1.0 + emc;
-      s_end[2] = -emc * (2.0 + emc);
-      s_end[3] = ss2 * (tau_e * tau_e * tau_e / 3.0);
-      s_end[4] = ss2 * (tau_e * tau_e * 0.5);
-      s_end[5] = ss2 * tau_e;
-    }
-    for (int idx = tid; idx < n * nb; idx += kThreads) {
-      const int i = idx / nb, j = idx - i * nb;
-      const double* row = sP + i * np + 4 * s_p[j];
-      sT[i][j] = row[0] + s_tau[j] * row[1] + s_eg[j] * row[2] + s_ec[j] * row[3];
-    }
-    __syncthreads();
-    // ---- 3. Sigma_B (lower triangle) and G
-    const double ec_e = s_end[1];
-    for (int idx = tid; idx < nb * nb; idx += kThreads) {
-      const int k = idx / nb, j = idx - k * nb;
-      if (j > k) continue;
-      const int p = s_p[j], pk = s_p[k];
-      const double base = sT[4 * pk][j] + s_tau[k] * sT[4 * pk + 1][j] +
-                          s_eg[k] * sT[4 * pk + 2][j] + s_ec[k] * sT[4 * pk + 3][j];
-      const double dtk = s_tau[k] - s_tau[j];
-      double noise = (1.0 + expm1_k(-lam * dtk)) * (s_hd[pk * P + p] * vc) * s_sc[j];
-      if (pk == p)
-        noise += fma(dtk, s_qrf[j], s_qrr[j]) + (1.0 + expm1_k(-s_gr[p] * dtk)) * s_qa[j];
-      sS[k][j] = base + noise + (k == j ? s_R[k] : 0.0);
-    }
-    for (int idx = tid; idx < n * nb; idx += kThreads) {
-      const int i = idx / nb, j = idx - i * nb;
-      const int q = i >> 2, c = i & 3, p = s_p[j];
-      double g;
-      if (c == 0)
-        g = fma(tau_e, sT[i + 1][j], sT[i][j]);
-      else if (c == 1)
-        g = sT[i][j];
-      else if (c == 2)
-        g = s_eqe[q] * sT[i][j];
-      else
-        g = ec_e * sT[i][j] + s_ece[j] * (s_hd[q * P + p] * vc) * s_sc[j];
-      if (q == p) {
-        if (c == 0) g += fma(tau_e - s_tau[j], s_qrf[j], s_qrr[j]);
-        else if (c == 1) g += s_qrf[j];
-        else if (c == 2) g += s_ege[j] * s_qa[j];
-      }
-      sG[i][j] = g;
-    }
-    __syncthreads();
-    // ---- 4. Cholesky of Sigma_B with the residual column (wave 0)
-    if (wave == 0) {
-      for (int k = 0; k < nb; ++k) {
-        const double d = sS[k][k];
-        const double lk = sqrt(d);
-        const double il = 1.0 / lk;
-        const double ak = sS[k][kB] * il;
-        if (lane == 0) {
-          if (st == 0) {
-            if (!finite_d(d)) st = kNonFinite;
-            else if (!(d > 0.0)) st = kNonPD;
-            else if (!finite_d(ak)) st = kNonFinite;
-          }
-          quad = fma(ak, ak, quad);
-          const double pm = lm * d;
-          lm = __builtin_amdgcn_frexp_mant(pm);
-          le += __builtin_amdgcn_frexp_exp(pm);
-        }
-        const int i1 = k + 1 + lane;
-        if (i1 < nb) sS[i1][k] *= il;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int m = nb - k - 1;
-        for (int f = lane; f < m * m; f += kWave) {
-          const int i = k + 1 + f / m, j = k + 1 + f % m;
-          if (j <= i) sS[i][j] = fma(-sS[i][k], sS[j][k], sS[i][j]);
-        }
-        if (lane < m) sS[k + 1 + lane][kB] = fma(-sS[k + 1 + lane][k], ak, sS[k + 1 + lane][kB]);
-        if (lane == 0) {
-          sS[k][k] = lk;
-          sS[k][kB] = ak;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-    __syncthreads();
-    // ---- 5. V = G L^{-T} and the mean at the block end (row threads)
-    if (tid < n) {
-      const int i = tid, q = i >> 2, c = i & 3;
-      double g[kB];
+  int xb = 0;
+  for (int64_t k0 = 0, b = 0; k0 < N; k0 += kB, ++b) {
+    const int cb = (int)(b & 1);
+    const BlockConst& bc = s_bc[cb];
+    const int nb = bc.nb;
+    // ---- A. T = P0 A^T H^T and Sigma_B (lower) from P0
 #pragma unroll
-      for (int k = 0; k < kB; ++k) g[k] = k < nb ? sG[i][k] : 0.0;
-      double xv = 0.0;
+    for (int t = 0; t < (kNPad * kB + kThreads - 1) / kThreads; ++t) {
+      const int e = tid + kThreads * t;
+      const int i = e >> 4, j = e & (kB - 1);
+      if (i < n) {
+        double v = 0.0;
+        if (j < nb) {
+          const double* r = sP + i * kLdP + 4 * bc.p[j];
+          v = r[0] + bc.tau[j] * r[1] + bc.eg[j] * r[2] + bc.ec[j] * r[3];
+        }
+        sT[i * kLdB + j] = v;
+      }
+    }
+    if (tid < kPairs) {
+      double v = bc.sn[sk][sj];
+      if (sk < nb) {
+        const double* B = sP + 4 * bc.p[sk] * kLdP + 4 * bc.p[sj];
+        const double t1 = bc.tau[sj], g1 = bc.eg[sj], c1 = bc.ec[sj];
+        double w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double* r = B + c * kLdP;
+          w[c] = r[0] + t1 * r[1] + g1 * r[2] + c1 * r[3];
+        }
+        v += w[0] + bc.tau[sk] * w[1] + bc.eg[sk] * w[2] + bc.ec[sk] * w[3];
+      }
+      sS[sk * kLdB + sj] = v;
+    }
+    __syncthreads();
+    // ---- C.
+    const double* x0 = sx[xb];
+    const double tau_e = bc.end[0], ec_e = bc.end[1];
+    if (wave < 2) {
+      // load: Sigma_B row + residual (lanes < kB) or a row of G + predicted
+      // mean, stored negated so that both kinds of row eliminate alike
+      double v[kB], slot;
+      const bool sig = lane < kB;
+      const int row = sig ? kNPad + lane : kGRows * wave + lane - kB;
+      if (sig) {
+        const int k = lane;
+#pragma unroll
+        for (int j = 0; j < kB; ++j) v[j] = sS[(j <= k ? k * kLdB + j : j * kLdB + k)];
+        const int pk = bc.p[k < nb ? k : 0];
+        const double* xp = x0 + 4 * pk;
+        const double r = bc.y[k] - (xp[0] + bc.tau[k] * xp[1] + bc.eg[k] * xp[2] + bc.ec[k] * xp[3]);
+        slot = k < nb ? r : 0.0;
+      } else {
+        // G row = (A_end row) T + own-pulsar noise + HD-coupled common noise
+        const bool live = row < n;
+        const int q = live ? row >> 2 : 0, c = row & 3;
+        const int r1 = c == 0 ? row + 1 : row;
+        const double mA = !live ? 0.0 : c == 2 ? bc.eqe[q] : (c == 3 ? ec_e : 1.0);
+        const double mB = live && c == 0 ? tau_e : 0.0;
+        const double f3 = live && c == 3 ? vc : 0.0;
+        const int own = live ? q : -1;
+        const double* hq = s_hd + q * P;
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+          const int p = bc.p[j];
+          double g = fma(mB, sT[r1 * kLdB + j], mA * sT[row * kLdB + j]);
+          g = fma(f3 * bc.ecs[j], hq[p], g);
+          const double o = bc.nz[c][j];
+          g += own == p ? o : 0.0;
+          v[j] = j < nb ? g : 0.0;
+        }
+        slot = -fma(mB, x0[r1], mA * x0[row]);
+      }
+      // elimination in TOA order
 #pragma unroll
       for (int k = 0; k < kB; ++k) {
-        if (k < nb) {
-          const double v = g[k] * rcp_nr(sS[k][k]);
-          g[k] = v;
-          xv = fma(v, sS[k][kB], xv);
+        const double d = readlane_d(v[k], k);
+        const double e = readlane_d(slot, k);
+        double colk[kB];
 #pragma unroll
-          for (int k2 = k + 1; k2 < kB; ++k2)
-            if (k2 < nb) g[k2] = fma(-v, sS[k2][k], g[k2]);
-        }
+        for (int j = k + 1; j < kB; ++j) colk[j] = readlane_d(v[k], j);
+        const double inv = rcp_nr(d);
+        const double m = v[k] * inv;
+#pragma unroll
+        for (int j = k + 1; j < kB; ++j) v[j] = fma(-m, colk[j], v[j]);
+        slot = fma(-m, e, slot);
+        sM[row * kLdB + k] = m;
+        // first failure: non-finite S, then S <= 0, then non-finite e
+        const int nf_d = !finite_d(d), np_d = !(d > 0.0), nf_e = !finite_d(e);
+        const int code = (nf_d * kNonFinite) | ((nf_d ^ 1) & np_d) * kNonPD |
+                         ((nf_d | np_d) ^ 1) * nf_e * kNonFinite;
+        st = st | ((st == 0) * code);
+        quad = fma(e * inv, e, quad);
+        const double pm = lm * d;
+        lm = __builtin_amdgcn_frexp_mant(pm);
+        le += __builtin_amdgcn_frexp_exp(pm);
       }
 #pragma unroll
-      for (int k = 0; k < kB; ++k)
-        if (k < nb) sG[i][k] = g[k];
-      double xa;
-      if (c == 0) xa = fma(tau_e, x0[i + 1], x0[i]);
-      else if (c == 1) xa = x0[i];
-      else if (c == 2) xa = s_eqe[q] * x0[i];
-      else xa = ec_e * x0[i];
-      sx[xb ^ 1][i] = xa + xv;
-    }
-    // ---- 6a. P0 <- A_end P0 A_end^T + Qacc_end (one 4x4 block per thread)
-    if (owner) {
-      double B[4][4];
+      for (int k = 0; k < kB; ++k) sU[row * kLdB + k] = v[k];
+      sx[xb ^ 1][row] = -slot;
+    } else if (wave == 2) {
+      // P0 <- A_end P0 A_end^T + Qacc_end, one 4x4 pulsar block per lane
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int u = 0; u < 4; ++u) {
+        if (lane + kWave * u >= nblk) break;
+        const int ba = tba[u], bb = tbb[u];
+        double B[4][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) B[i][j] = sP[(4 * ba + i) * np + 4 * bb + j];
-      const double pa = s_eqe[ba], pb = s_eqe[bb];
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        B[0][j] = fma(tau_e, B[1][j], B[0][j]);
-        B[2][j] *= pa;
-        B[3][j] *= ec_e;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        B[i][0] = fma(tau_e, B[i][1], B[i][0]);
-        B[i][2] *= pb;
-        B[i][3] *= ec_e;
-      }
-      B[3][3] = fma(s_hd[ba * P + bb] * vc, s_end[2], B[3][3]);
-      if (ba == bb) {
-        B[0][0] += s_end[3];
-        B[0][1] += s_end[4];
-        B[1][0] += s_end[4];
-        B[1][1] += s_end[5];
-        B[2][2] += s_qae[ba];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) B[i][j] = sP[(4 * ba + i) * kLdP + 4 * bb + j];
+        const double pa = bc.eqe[ba], pb = bc.eqe[bb];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          sP[(4 * ba + i) * np + 4 * bb + j] = B[i][j];
-          sP[(4 * bb + j) * np + 4 * ba + i] = B[i][j];
+          B[0][j] = fma(tau_e, B[1][j], B[0][j]);
+          B[2][j] *= pa;
+          B[3][j] *= ec_e;
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          B[i][0] = fma(tau_e, B[i][1], B[i][0]);
+          B[i][2] *= pb;
+          B[i][3] *= ec_e;
+        }
+        B[3][3] = fma(s_hd[ba * P + bb] * vc, bc.end[2], B[3][3]);
+        if (ba == bb) {
+          B[0][0] += bc.end[3];
+          B[0][1] += bc.end[4];
+          B[1][0] += bc.end[4];
+          B[1][1] += bc.end[5];
+          B[2][2] += bc.qae[ba];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            sP[(4 * ba + i) * kLdP + 4 * bb + j] = B[i][j];
+            sP[(4 * bb + j) * kLdP + 4 * ba + i] = B[i][j];
+          }
+      }
+    } else {
+      // records of block b + 2 (issued first, stored last), constants of b + 1
+      const int64_t k2 = k0 + 2 * kB;
+      const bool ok = k2 + (lane >> 2) < N;
+      double r0 = 0.0, r1 = 0.0;
+      if (ok) {
+        r0 = recd[k2 * 8 + 2 * lane];
+        r1 = recd[k2 * 8 + 2 * lane + 1];
+      }
+      if (k0 + kB < N) prep(cb ^ 1, k0 + kB);
+      if (ok) {
+        s_rec[cb][lane >> 2][2 * (lane & 3)] = r0;
+        s_rec[cb][lane >> 2][2 * (lane & 3) + 1] = r1;
+      }
     }
     __syncthreads();
-    // ---- 6b. P0 -= V V^T on the FP64 matrix cores, lower tiles, mirrored
-    {
-      const int nt = np / 16;
-      const int ntiles = nt * (nt + 1) / 2;
-      for (int t = wave; t < ntiles; t += kThreads / kWave) {
-        int I = 0, tt = t;
-        while (tt >= I + 1) {
-          tt -= I + 1;
-          ++I;
-        }
-        const int J = tt;
-        f64x4 acc;
+    // ---- D. P -= U M^T on the FP64 matrix cores, lower tiles, mirrored
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc[r] = sP[(16 * I + (lane >> 4) + 4 * r) * np + 16 * J + (lane & 15)];
-        const int ra = 16 * I + (lane & 15), rb = 16 * J + (lane & 15);
+    for (int u = 0; u < 6; ++u) {
+      const int t = wave + 4 * u;
+      if (t >= nt * (nt + 1) / 2) break;
+      int I = 0, J = t;
+      while (J >= I + 1) {
+        J -= I + 1;
+        ++I;
+      }
+      f64x4 acc;
 #pragma unroll
-        for (int kc = 0; kc < kB / 4; ++kc) {
-          const int k = 4 * kc + (lane >> 4);
-          const double va = (ra < n && k < nb) ? -sG[ra][k] : 0.0;
-          const double vb = (rb < n && k < nb) ? sG[rb][k] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc, 0, 0, 0);
-        }
+      for (int r = 0; r < 4; ++r)
+        acc[r] = sP[(16 * I + (lane >> 4) + 4 * r) * kLdP + 16 * J + (lane & 15)];
+      const double* ua = sU + (16 * I + (lane & 15)) * kLdB + (lane >> 4);
+      const double* mb = sM + (16 * J + (lane & 15)) * kLdB + (lane >> 4);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * I + (lane >> 4) + 4 * r, col = 16 * J + (lane & 15);
-          if (I > J || row >= col) {
-            sP[row * np + col] = acc[r];
-            sP[col * np + row] = acc[r];
-          }
+      for (int kc = 0; kc < kB / 4; ++kc)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-ua[4 * kc], mb[4 * kc], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + (lane >> 4) + 4 * r, col = 16 * J + (lane & 15);
+        if (I > J || row >= col) {
+          sP[row * kLdP + col] = acc[r];
+          sP[col * kLdP + row] = acc[r];
         }
       }
     }
@@ -381,7 +508,7 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   }
   if (tid == 0) {
     if (s_pnf) st = kNonFinite;
-    double ll = -0.5 * ((double)a.N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
     if (st == 0 && !finite_d(ll)) st = kNonFinite;
     a.logl[s] = st ? -INFINITY : ll;
     if (a.status) a.status[s] = st;
