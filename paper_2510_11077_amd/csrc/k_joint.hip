@@ -29,20 +29,24 @@
 // a rank-kB downdate U M^T (M = U S^{-1}, n x kB by kB x n) that runs on the
 // FP64 matrix cores (v_mfma_f64_16x16x4f64).
 //
-// Mapping on CDNA4: one workgroup (4 waves) per parameter sample; P0 (full
-// n x n, FP64) and the block's work arrays live in LDS (~130 KB). Per block
-// of kB TOAs, three barriers:
-//   A  all waves: T = P0 A^T H^T (n x kB) and the lower triangle of Sigma_B
-//      from the 4x4 pulsar blocks of P0.
+// Mapping on CDNA4: one workgroup (16 waves, 4 per SIMD, so that LDS latency
+// overlaps across waves) per parameter sample; P0 (full n x n, FP64) and the
+// block's work arrays live in LDS (~145 KB). Per block of kB TOAs, three
+// barriers:
+//   A  all waves: G (n x kB) and the lower triangle of Sigma_B from the 4x4
+//      pulsar blocks of P0.
 //   C  waves 0-1: the elimination in registers. Lanes 0-15 of each wave hold
 //      the rows of Sigma_B with the residual, lanes 16-63 hold 48 rows of G
-//      (formed from T) with the predicted mean; pivot, innovation and the
+//      with the predicted mean; pivot, innovation and the
 //      pivot column reach every lane by v_readlane, so the whole
 //      factorisation runs without LDS round trips or barriers.
-//      wave 2: P0 <- A_end P0 A_end^T + Qacc_end (one 4x4 pulsar block per
-//      lane). wave 3: the next block's per-TOA constants (elapsed times,
-//      decays, the noise part of its Sigma_B) from records staged in LDS, and
-//      the global loads of the records of the block after it.
+//      Waves on the other two SIMDs: P0 <- A_end P0 A_end^T + Qacc_end on
+//      the lower triangle (4-row column segments, consecutive lanes on
+//      consecutive columns), the log-likelihood ledger of the previous block
+//      (pivots and innovations left in LDS by the elimination), the per-TOA
+//      constants of the block after next (elapsed times, decays) from records
+//      staged in LDS with the global loads of the records of the block after
+//      that, and the noise part of the next block's Sigma_B.
 //   D  all waves: P -= U M^T on MFMA tiles (lower tiles, mirrored).
 // The final block is padded to kB with identity rows of Sigma_B, zero
 // residuals and zero columns of G: their pivots are exactly 1 and their
@@ -57,7 +61,8 @@ namespace argus {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kWaves = 16;                               // 4 per SIMD
+constexpr int kThreads = kWaves * kWave;
 constexpr int kMaxP = kJointMaxPsr;
 constexpr int kB = 16;                                   // TOAs per block
 constexpr int kNPad = ((4 * kMaxP + 15) / 16) * 16;     // padded state dim
@@ -65,8 +70,25 @@ constexpr int kLdP = kNPad + 2;                          // P row: 16-B aligned
 constexpr int kLdB = kB + 1;                             // rows of n x kB arrays
 constexpr int kPairs = kB * (kB + 1) / 2;               // lower triangle
 constexpr int kGRows = kWave - kB;                       // G rows per wave
+constexpr int kNBuf = 3;                                 // block-constant buffers
 static_assert(2 * kGRows >= kNPad, "two elimination waves cover every row");
 static_assert(kGRows % 4 == 0, "a pulsar's four rows stay in one wave");
+static_assert(kThreads / 16 * 2 >= kNPad * kB / 16, "phase A covers G in two passes");
+
+// Work of phase C by wave (SIMD = wave % 4): the elimination owns SIMDs 0
+// and 1 (its waves 0, 1; the other waves there stay idle in C so as not to
+// take its issue slots); SIMDs 2 and 3 take the rest.
+constexpr int kWLedger = 2;      // ledger of the previous block
+constexpr int kWToa = 3;         // per-TOA constants two blocks ahead, records
+__device__ __forceinline__ int pairs_slot(int w) {      // -1: not a pairs wave
+  return w == 7 ? 0 : w == 11 ? 1 : w == 15 ? 2 : -1;
+}
+constexpr int kTfWaves = 6;      // transform: waves 6, 10, 14 and 7, 11, 15
+constexpr int kTfRounds = 3;     // units per lane (2 P (P + 1) <= kTfRounds * 384)
+static_assert(2 * kMaxP * (kMaxP + 1) <= kTfRounds * kTfWaves * kWave, "transform units");
+__device__ __forceinline__ int transform_slot(int w) {  // -1: not a transform wave
+  return w == 6 ? 0 : w == 10 ? 1 : w == 14 ? 2 : w == 7 ? 3 : w == 11 ? 4 : w == 15 ? 5 : -1;
+}
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -79,6 +101,14 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// value of lane + 1 within each row of 16 lanes (0 for the last lane)
+__device__ __forceinline__ double next_lane_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x101, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -108,18 +138,20 @@ struct JointArgs {
 };
 
 // Per-block constants that depend on the TOA records and the parameters but
-// not on the state; prepared one block ahead.
+// not on the state. The per-TOA part is prepared two blocks ahead, the noise
+// of Sigma_B one block ahead.
 struct BlockConst {
   double tau[kB];   // time from the block start (previous TOA) to TOA k
   double eg[kB];    // e^{-rate_p tau}
   double ec[kB];    // e^{-lambda tau}
+  double ieg[kB], iec[kB];  // their reciprocals
   double qrr[kB], qrf[kB];  // spin noise accumulated over tau
   double qa[kB];    // red noise accumulated over tau
   double sc[kB];    // 1 - e^{-2 lambda tau}
+  double R[kB];     // white noise
   double y[kB];
-  double ege[kB], ece[kB];  // decays from TOA k to the block end
-  double nz[4][kB];         // own-pulsar noise of G by state component
-  double ecs[kB];           // ece * sc: common noise of G per unit Gamma v_c
+  double nz[4][kB]; // own-pulsar noise of G by state component
+  double ecs[kB];   // e^{-lambda (tau_e - tau)} sc: common noise of G per Gamma v_c
   double sn[kB][kB];        // noise + white part of Sigma_B (lower), padded identity
   double eqe[kMaxP], qae[kMaxP];  // per pulsar: red decay / noise over the block
   double end[6];    // tau_e, ec_e, sc_e, qrr_e, qrf_e, qff_e
@@ -134,16 +166,23 @@ __device__ __forceinline__ double prm(const JointArgs& a, int c, int64_t s) {
   return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
 }
 
+// e^{-rate (tk - tj)} from the decays of tk and tj; recomputed directly when
+// the decay of tj is too small to divide by
+__device__ __forceinline__ double decay_ratio(double ek, double iej, double ej, double x) {
+  return ej > 1e-280 ? ek * iej : 1.0 + expm1_k(x);
+}
+
 __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   __shared__ double sP[kNPad * kLdP];      // covariance at the block start
-  __shared__ double sT[kNPad * kLdB];      // P0 A^T H^T
+  __shared__ double sG[kNPad * kLdB];      // G = Cov(x_end, y_block)
   __shared__ double sU[(kNPad + kB) * kLdB];  // eliminated columns u_k
   __shared__ double sM[(kNPad + kB) * kLdB];  // u_k / S_k
   // (rows kNPad.. take the stores of the Sigma_B lanes, which are not read)
   __shared__ double sS[kB * kLdB];         // Sigma_B, lower triangle
   __shared__ double sx[2][kNPad + kB];     // mean, double-buffered by block
-  __shared__ double s_rec[2][kB][8];       // staged TOA records
-  __shared__ BlockConst s_bc[2];
+  __shared__ double s_rec[kNBuf][kB][8];   // staged TOA records
+  __shared__ double s_led[2][kB][2];       // pivots S_k and innovations e_k
+  __shared__ BlockConst s_bc[kNBuf];
   __shared__ double s_hd[kMaxP * kMaxP];
   __shared__ double s_vr[kMaxP], s_gr[kMaxP], s_ef2[kMaxP], s_eq2[kMaxP];
   __shared__ double s_vc;
@@ -156,23 +195,23 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   const int P = a.P;
   const int n = 4 * P;
   const int nt = (n + 15) / 16;
-  const int nblk = P * (P + 1) / 2;
+  const int ntl = nt * (nt + 1) / 2;
   const int64_t N = a.N;
   const double lam = a.mc.lam, ss2 = a.mc.ss2;
   const double* recd = reinterpret_cast<const double*>(a.rec);
 
   for (int i = tid; i < kNPad * kLdP; i += kThreads) sP[i] = 0.0;
-  for (int i = tid; i < kNPad * kLdB; i += kThreads) sT[i] = 0.0;
+  for (int i = tid; i < kNPad * kLdB; i += kThreads) sG[i] = 0.0;
   for (int i = tid; i < (kNPad + kB) * kLdB; i += kThreads) sU[i] = sM[i] = 0.0;
   for (int i = tid; i < 2 * (kNPad + kB); i += kThreads) (&sx[0][0])[i] = 0.0;
   for (int i = tid; i < P * P; i += kThreads) s_hd[i] = a.hd[i];
   // padded columns of a short block read finite leftovers, never garbage
-  for (int i = tid; i < (int)(sizeof(s_bc) / sizeof(double)); i += kThreads)
+  for (int i = tid; i < (int)(sizeof(s_bc) / (sizeof(double))); i += kThreads)
     reinterpret_cast<double*>(s_bc)[i] = 0.0;
-  for (int i = tid; i < 2 * kB * 8; i += kThreads) (&s_rec[0][0][0])[i] = 0.0;
+  for (int i = tid; i < kNBuf * kB * 8; i += kThreads) (&s_rec[0][0][0])[i] = 0.0;
   __syncthreads();
-  // records of the first two blocks
-  for (int i = tid; i < 2 * kB * 8; i += kThreads)
+  // records of the first kNBuf blocks
+  for (int i = tid; i < kNBuf * kB * 8; i += kThreads)
     if ((i >> 3) < N) (&s_rec[0][0][0])[i] = recd[i];
   if (tid == 0) {
     const double la = prm(a, 4 * P, s), gc = prm(a, 4 * P + 1, s);
@@ -210,153 +249,233 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   }
 
   // fixed per-thread work assignments
-  int sk = 0, sj = 0;  // phase A: Sigma_B entry of threads < kPairs
-  if (tid < kPairs) pair_of(tid, sk, sj);
-  int pk3[3], pj3[3];  // wave 3: noise pairs of its lanes
+  const int psl = pairs_slot(wave), tsl = transform_slot(wave);
+  // transform units of this lane: unit u = the 4 rows of pulsar q in column
+  // c <= 4q + 3, packed as q * 256 + c (-1: none)
+  int tfu[kTfRounds];
 #pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    pk3[u] = pj3[u] = 0;
-    if (lane + kWave * u < kPairs) pair_of(lane + kWave * u, pk3[u], pj3[u]);
+  for (int rr = 0; rr < kTfRounds; ++rr) {
+    const int u = kWave * (tsl + kTfWaves * rr) + lane;
+    int q = (int)((sqrtf(1.0f + 2.0f * (float)u) - 1.0f) * 0.5f);
+    q += 2 * (q + 1) * (q + 2) <= u ? 1 : 0;
+    q -= 2 * q * (q + 1) > u ? 1 : 0;
+    tfu[rr] = (tsl >= 0 && u < 2 * P * (P + 1)) ? q * 256 + (u - 2 * q * (q + 1)) : -1;
   }
-  int tba[4], tbb[4];  // wave 2: 4x4 pulsar blocks of its lanes
+  int sk = 0, sj = 0;  // phase A: Sigma_B entry of threads kSig0 .. kSig0 + kPairs
+  constexpr int kSig0 = kThreads / 2;
+  if (tid >= kSig0 && tid < kSig0 + kPairs) pair_of(tid - kSig0, sk, sj);
+  int pk = 0, pj = 0;  // pairs waves: one noise pair per lane
+  const int pe = psl >= 0 ? lane + kWave * psl : kPairs;
+  if (pe < kPairs) pair_of(pe, pk, pj);
+  int tI[2], tJ[2];    // phase D: 16x16 tiles of this wave (clamped past the end)
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    int bb = lane + kWave * u, ba = 0;
-    while (bb >= ba + 1) {
-      bb -= ba + 1;
-      ++ba;
+  for (int u = 0; u < 2; ++u) {
+    int J = wave + kWaves * u, I = 0;
+    if (J >= ntl) J = 0;
+    while (J >= I + 1) {
+      J -= I + 1;
+      ++I;
     }
-    tba[u] = ba;
-    tbb[u] = bb;
+    tI[u] = I;
+    tJ[u] = J;
   }
 
-  // Per-block constants of block b (first TOA k0) into s_bc[b & 1] from the
-  // records staged in s_rec[b & 1]; run by one whole wave.
-  auto prep = [&](int buf, int64_t k0) {
+  // Per-TOA constants of the block starting at k0 into s_bc[buf] from the
+  // records staged in s_rec[buf]; run by one whole wave.
+  auto toa_part = [&](int buf, int64_t k0, int lane) {
     BlockConst& bc = s_bc[buf];
     const double(*rec)[8] = s_rec[buf];
     const int64_t rem = N - k0;
     const int nb = rem < kB ? (int)rem : kB;
-    if (lane < kB) {
-      double tau = 0.0;
+    const int lr = lane < kB ? lane : 0;
+    double dts[kB];
 #pragma unroll
-      for (int l = 0; l < kB; ++l) {
-        const double dt = rec[l][0];
-        if (l <= lane && l < nb) tau += dt;
-      }
-      if (lane < nb) {
-        const int p = (int)(__double_as_longlong(rec[lane][7]) & 0xffffffffll);
-        const double em = expm1_k(-s_gr[p] * tau);
-        const double emc = expm1_k(-lam * tau);
-        bc.tau[lane] = tau;
-        bc.eg[lane] = 1.0 + em;
-        bc.ec[lane] = 1.0 + emc;
-        bc.qrr[lane] = ss2 * (tau * tau * tau / 3.0);
-        bc.qrf[lane] = ss2 * (tau * tau * 0.5);
-        bc.qa[lane] = s_vr[p] * (-em * (2.0 + em));
-        bc.sc[lane] = -emc * (2.0 + emc);
-        bc.y[lane] = rec[lane][5];
-        bc.sn[lane][lane] = fma(s_ef2[p], rec[lane][6], s_eq2[p]);  // R_k for now
-        bc.p[lane] = p;
-        if (lane == nb - 1) bc.end[0] = tau;
-      }
-    }
-    if (lane == 0) bc.nb = nb;
-    wave_sync();
-    const double tau_e = bc.end[0];
-    if (lane < nb) {
-      const double dte = tau_e - bc.tau[lane];
-      const double ege = 1.0 + expm1_k(-s_gr[bc.p[lane]] * dte);
-      const double ece = 1.0 + expm1_k(-lam * dte);
-      bc.ege[lane] = ege;
-      bc.ece[lane] = ece;
-      bc.nz[0][lane] = fma(dte, bc.qrf[lane], bc.qrr[lane]);
-      bc.nz[1][lane] = bc.qrf[lane];
-      bc.nz[2][lane] = ege * bc.qa[lane];
-      bc.nz[3][lane] = 0.0;
-      bc.ecs[lane] = ece * bc.sc[lane];
-    } else if (lane >= kB && lane < kB + P) {
-      const int q = lane - kB;
-      const double em = expm1_k(-s_gr[q] * tau_e);
-      bc.eqe[q] = 1.0 + em;
-      bc.qae[q] = s_vr[q] * (-em * (2.0 + em));
+    for (int l = 0; l < kB; ++l) dts[l] = rec[l][0];
+    const long long pbits = __double_as_longlong(rec[lr][7]);
+    const double s2 = rec[lr][6], yv = rec[lr][5];
+    // elapsed times (in stream order) and the end of the block
+    double tau = 0.0;
+#pragma unroll
+    for (int l = 0; l < kB; ++l)
+      if (l <= lane && l < nb) tau += dts[l];
+    const double tau_e = readlane_d(tau, nb - 1);
+    // one pass of two exponentials: TOA lanes (red, common decay over tau),
+    // pulsar lanes (red decay over the block), the last lane (common decay
+    // over the block)
+    const bool toa = lane < nb;
+    const bool psr = lane >= kB && lane < kB + P;
+    const int pq = toa ? (int)(pbits & 0xffffffffll) : (psr ? lane - kB : 0);
+    const double gq = s_gr[pq], vq = s_vr[pq], ef2 = s_ef2[pq], eq2 = s_eq2[pq];
+    const double x1 = toa ? -gq * tau : (psr ? -gq * tau_e : -lam * tau_e);
+    const double x2 = toa ? -lam * tau : 0.0;
+    const double em1 = expm1_k(x1), em2 = expm1_k(x2);
+    const double eg = 1.0 + em1, ec = 1.0 + em2;
+    const double ieg = rcp_nr(eg), iec = rcp_nr(ec);
+    const double qrf = ss2 * (tau * tau * 0.5), qrr = ss2 * (tau * tau * tau / 3.0);
+    const double qa = vq * (-em1 * (2.0 + em1)), sc = -em2 * (2.0 + em2);
+    if (toa) {
+      bc.tau[lane] = tau;
+      bc.eg[lane] = eg;
+      bc.ec[lane] = ec;
+      bc.ieg[lane] = ieg;
+      bc.iec[lane] = iec;
+      bc.qrr[lane] = qrr;
+      bc.qrf[lane] = qrf;
+      bc.qa[lane] = qa;
+      bc.sc[lane] = sc;
+      bc.R[lane] = fma(ef2, s2, eq2);
+      bc.y[lane] = yv;
+      bc.p[lane] = pq;
+    } else if (psr) {
+      bc.eqe[pq] = eg;
+      bc.qae[pq] = qa;
     } else if (lane == kWave - 1) {
-      const double emc = expm1_k(-lam * tau_e);
-      bc.end[1] = 1.0 + emc;
-      bc.end[2] = -emc * (2.0 + emc);
+      bc.end[0] = tau_e;
+      bc.end[1] = eg;
+      bc.end[2] = -em1 * (2.0 + em1);
       bc.end[3] = ss2 * (tau_e * tau_e * tau_e / 3.0);
       bc.end[4] = ss2 * (tau_e * tau_e * 0.5);
       bc.end[5] = ss2 * tau_e;
     }
-    // noise part of Sigma_B: common OU (HD-coupled) for every pair, spin and
-    // red noise for pairs of one pulsar, R on the diagonal
-    double sv[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int k = pk3[u], j = pj3[u];
-      sv[u] = k == j ? 1.0 : 0.0;
-      if (lane + kWave * u < kPairs && k < nb) {
-        const int p = bc.p[j], pk = bc.p[k];
-        const double dtk = bc.tau[k] - bc.tau[j];
-        double v = (1.0 + expm1_k(-lam * dtk)) * (s_hd[pk * P + p] * vc) * bc.sc[j];
-        if (pk == p)
-          v += fma(dtk, bc.qrf[j], bc.qrr[j]) + (1.0 + expm1_k(-s_gr[p] * dtk)) * bc.qa[j];
-        if (k == j) v += bc.sn[k][k];
-        sv[u] = v;
-      }
+    if (lane == 0) bc.nb = nb;
+    wave_sync();
+    // noise of G per TOA: decays to the block end from the ratios
+    const double eqp = bc.eqe[pq], ec_e = bc.end[1];
+    if (toa) {
+      const double dte = tau_e - tau;
+      const double ege = decay_ratio(eqp, ieg, eg, -gq * dte);
+      bc.nz[0][lane] = fma(dte, qrf, qrr);
+      bc.nz[1][lane] = qrf;
+      bc.nz[2][lane] = ege * qa;
+      bc.nz[3][lane] = 0.0;
+      bc.ecs[lane] = (ec_e * iec) * sc;
     }
-    wave_sync();  // R_k read above before the diagonal is overwritten
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (lane + kWave * u < kPairs) bc.sn[pk3[u]][pj3[u]] = sv[u];
   };
 
-  // ledger (thread 0 keeps it): sum e_k^2 / S_k, product of S_k as mantissa
-  // and exponent, first failure
+  // Noise part of Sigma_B of the block in s_bc[buf] (per-TOA part ready):
+  // common OU (HD-coupled) for every pair, spin and red noise for pairs of
+  // one pulsar, R on the diagonal; one pair per lane of the pairs waves.
+  auto pairs_part = [&](int buf) {
+    BlockConst& bc = s_bc[buf];
+    const int nb = bc.nb;
+    const int k = pk, j = pj;
+    const int p = bc.p[j], pkk = bc.p[k];
+    const double tk = bc.tau[k], tj = bc.tau[j];
+    const double eck = bc.ec[k], iecj = bc.iec[j], scj = bc.sc[j];
+    const double egk = bc.eg[k], iegj = bc.ieg[j], egj = bc.eg[j];
+    const double qrfj = bc.qrf[j], qrrj = bc.qrr[j], qaj = bc.qa[j], Rk = bc.R[k];
+    const double hv = s_hd[pkk * P + p], gp = s_gr[p];
+    if (pe < kPairs) {
+      double v = k == j ? 1.0 : 0.0;
+      if (k < nb) {
+        const double dtk = tk - tj;
+        v = (eck * iecj) * (hv * vc) * scj;
+        if (pkk == p) v += fma(dtk, qrfj, qrrj) + decay_ratio(egk, iegj, egj, -gp * dtk) * qaj;
+        if (k == j) v += Rk;
+      }
+      bc.sn[k][j] = v;
+    }
+  };
+
+  // ledger (thread kLedger keeps it): sum e_k^2 / S_k, product of S_k as
+  // mantissa and exponent, first failure
+  constexpr int kLedger = kWLedger * kWave;
   double quad = 0.0, lm = 1.0;
   int le = 0, st = 0;
+  // one block's pivots and innovations folded in by 16 lanes
+  auto ledger = [&](int buf, int lane) {
+    const int k = lane & 15;
+    const double d = s_led[buf][k][0], e = s_led[buf][k][1];
+    const int code = !finite_d(d) ? kNonFinite
+                     : !(d > 0.0) ? kNonPD
+                     : !finite_d(e) ? kNonFinite : 0;
+    int first = code ? k : kB;
+    double qs = e * rcp_nr(d) * e;
+    double mm = __builtin_amdgcn_frexp_mant(d);
+    int me = __builtin_amdgcn_frexp_exp(d);
+#pragma unroll
+    for (int o = 1; o < kB; o <<= 1) {
+      const int f2 = __shfl_xor(first, o, kB);
+      first = f2 < first ? f2 : first;
+      qs += __shfl_xor(qs, o, kB);
+      const double pm = mm * __shfl_xor(mm, o, kB);
+      me += __shfl_xor(me, o, kB) + __builtin_amdgcn_frexp_exp(pm);
+      mm = __builtin_amdgcn_frexp_mant(pm);
+    }
+    const int fcode = __shfl(code, first < kB ? first : 0, kB);
+    if (st == 0 && first < kB) st = fcode;
+    quad += qs;
+    const double pm = lm * mm;
+    lm = __builtin_amdgcn_frexp_mant(pm);
+    le += me + __builtin_amdgcn_frexp_exp(pm);
+  };
+
   __syncthreads();
-  if (wave == 3 && N > 0) prep(0, 0);
+  if (N > 0 && wave == kWToa) toa_part(0, 0, lane);
+  if (N > kB && wave == kWToa + 4) toa_part(1, kB, lane);
+  __syncthreads();
+  if (N > 0 && psl >= 0) pairs_part(0);
   __syncthreads();
 
   int xb = 0;
-  for (int64_t k0 = 0, b = 0; k0 < N; k0 += kB, ++b) {
-    const int cb = (int)(b & 1);
+  int64_t k0 = 0;
+  for (int64_t b = 0; k0 < N; k0 += kB, ++b) {
+    // the thread index is re-read opaquely each block so that the per-lane
+    // addresses of every phase are recomputed here instead of being hoisted
+    // out of the loop and held in registers for its whole length
+    int tidv = tid;
+    __asm__ volatile("" : "+v"(tidv));
+    const int tid = tidv;
+    const int lane = tid & (kWave - 1);
+    const int cb = (int)(b % kNBuf);
     const BlockConst& bc = s_bc[cb];
     const int nb = bc.nb;
-    // ---- A. T = P0 A^T H^T and Sigma_B (lower) from P0
+    const double tau_e = bc.end[0], ec_e = bc.end[1];
+    // ---- A. G = A_end P0 A^T H^T + noise, and Sigma_B (lower) from P0.
+    //         Each row of 16 lanes takes one TOA column j and 16 consecutive
+    //         rows; the r row of a pulsar takes its f row from the next lane.
+    {
+      const int j = (tid >> 4) & 15;
+      const bool jv = j < nb;
+      const int p = bc.p[j];
+      const double t1 = bc.tau[j], g1 = bc.eg[j], c1 = bc.ec[j];
+      const double hs = vc * bc.ecs[j];
 #pragma unroll
-    for (int t = 0; t < (kNPad * kB + kThreads - 1) / kThreads; ++t) {
-      const int e = tid + kThreads * t;
-      const int i = e >> 4, j = e & (kB - 1);
-      if (i < n) {
-        double v = 0.0;
-        if (j < nb) {
-          const double* r = sP + i * kLdP + 4 * bc.p[j];
-          v = r[0] + bc.tau[j] * r[1] + bc.eg[j] * r[2] + bc.ec[j] * r[3];
+      for (int t = 0; t < 2; ++t) {
+        const int i = (tid & 15) + 16 * (tid >> 8) + 64 * t;
+        if (i < kNPad) {  // uniform per row of 16 lanes
+          const double* r0 = sP + i * kLdP + 4 * p;
+          const int q = i >> 2, c = i & 3, qq = q < P ? q : 0;
+          const double mA = c == 2 ? bc.eqe[qq] : (c == 3 ? ec_e : 1.0);
+          const double hv = s_hd[qq * P + p];
+          const double o = bc.nz[c][j];
+          const double d0 = r0[0] + t1 * r0[1] + g1 * r0[2] + c1 * r0[3];
+          const double d1 = next_lane_d(d0);
+          double g = c == 0 ? fma(tau_e, d1, d0) : mA * d0;
+          g = fma(c == 3 ? hs : 0.0, hv, g);
+          g += q == p ? o : 0.0;
+          if (i < n) sG[i * kLdB + j] = jv ? g : 0.0;
         }
-        sT[i * kLdB + j] = v;
       }
     }
-    if (tid < kPairs) {
-      double v = bc.sn[sk][sj];
-      if (sk < nb) {
-        const double* B = sP + 4 * bc.p[sk] * kLdP + 4 * bc.p[sj];
-        const double t1 = bc.tau[sj], g1 = bc.eg[sj], c1 = bc.ec[sj];
-        double w[4];
+    if (tid >= kSig0 && tid < kSig0 + kPairs) {
+      const double sn = bc.sn[sk][sj];
+      const int pa = bc.p[sk], pb = bc.p[sj];
+      const double t1 = bc.tau[sj], g1 = bc.eg[sj], c1 = bc.ec[sj];
+      const double t2 = bc.tau[sk], g2 = bc.eg[sk], c2 = bc.ec[sk];
+      const double* B = sP + 4 * pa * kLdP + 4 * pb;
+      double w[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double* r = B + c * kLdP;
-          w[c] = r[0] + t1 * r[1] + g1 * r[2] + c1 * r[3];
-        }
-        v += w[0] + bc.tau[sk] * w[1] + bc.eg[sk] * w[2] + bc.ec[sk] * w[3];
+      for (int c = 0; c < 4; ++c) {
+        const double* r = B + c * kLdP;
+        w[c] = r[0] + t1 * r[1] + g1 * r[2] + c1 * r[3];
       }
-      sS[sk * kLdB + sj] = v;
+      const double v = w[0] + t2 * w[1] + g2 * w[2] + c2 * w[3];
+      sS[sk * kLdB + sj] = sk < nb ? sn + v : sn;
     }
     __syncthreads();
     // ---- C.
     const double* x0 = sx[xb];
-    const double tau_e = bc.end[0], ec_e = bc.end[1];
     if (wave < 2) {
       // load: Sigma_B row + residual (lanes < kB) or a row of G + predicted
       // mean, stored negated so that both kinds of row eliminate alike
@@ -367,32 +486,22 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
         const int k = lane;
 #pragma unroll
         for (int j = 0; j < kB; ++j) v[j] = sS[(j <= k ? k * kLdB + j : j * kLdB + k)];
-        const int pk = bc.p[k < nb ? k : 0];
-        const double* xp = x0 + 4 * pk;
+        const int pk2 = bc.p[k < nb ? k : 0];
+        const double* xp = x0 + 4 * pk2;
         const double r = bc.y[k] - (xp[0] + bc.tau[k] * xp[1] + bc.eg[k] * xp[2] + bc.ec[k] * xp[3]);
         slot = k < nb ? r : 0.0;
       } else {
-        // G row = (A_end row) T + own-pulsar noise + HD-coupled common noise
         const bool live = row < n;
         const int q = live ? row >> 2 : 0, c = row & 3;
         const int r1 = c == 0 ? row + 1 : row;
         const double mA = !live ? 0.0 : c == 2 ? bc.eqe[q] : (c == 3 ? ec_e : 1.0);
         const double mB = live && c == 0 ? tau_e : 0.0;
-        const double f3 = live && c == 3 ? vc : 0.0;
-        const int own = live ? q : -1;
-        const double* hq = s_hd + q * P;
 #pragma unroll
-        for (int j = 0; j < kB; ++j) {
-          const int p = bc.p[j];
-          double g = fma(mB, sT[r1 * kLdB + j], mA * sT[row * kLdB + j]);
-          g = fma(f3 * bc.ecs[j], hq[p], g);
-          const double o = bc.nz[c][j];
-          g += own == p ? o : 0.0;
-          v[j] = j < nb ? g : 0.0;
-        }
+        for (int j = 0; j < kB; ++j) v[j] = sG[(live ? row : 0) * kLdB + j] * (live ? 1.0 : 0.0);
         slot = -fma(mB, x0[r1], mA * x0[row]);
       }
       // elimination in TOA order
+      double dk = 1.0, ek = 0.0;
 #pragma unroll
       for (int k = 0; k < kB; ++k) {
         const double d = readlane_d(v[k], k);
@@ -406,94 +515,87 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
         for (int j = k + 1; j < kB; ++j) v[j] = fma(-m, colk[j], v[j]);
         slot = fma(-m, e, slot);
         sM[row * kLdB + k] = m;
-        // first failure: non-finite S, then S <= 0, then non-finite e
-        const int nf_d = !finite_d(d), np_d = !(d > 0.0), nf_e = !finite_d(e);
-        const int code = (nf_d * kNonFinite) | ((nf_d ^ 1) & np_d) * kNonPD |
-                         ((nf_d | np_d) ^ 1) * nf_e * kNonFinite;
-        st = st | ((st == 0) * code);
-        quad = fma(e * inv, e, quad);
-        const double pm = lm * d;
-        lm = __builtin_amdgcn_frexp_mant(pm);
-        le += __builtin_amdgcn_frexp_exp(pm);
+        dk = lane == k ? d : dk;
+        ek = lane == k ? e : ek;
       }
 #pragma unroll
       for (int k = 0; k < kB; ++k) sU[row * kLdB + k] = v[k];
       sx[xb ^ 1][row] = -slot;
-    } else if (wave == 2) {
-      // P0 <- A_end P0 A_end^T + Qacc_end, one 4x4 pulsar block per lane
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (lane + kWave * u >= nblk) break;
-        const int ba = tba[u], bb = tbb[u];
-        double B[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) B[i][j] = sP[(4 * ba + i) * kLdP + 4 * bb + j];
-        const double pa = bc.eqe[ba], pb = bc.eqe[bb];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          B[0][j] = fma(tau_e, B[1][j], B[0][j]);
-          B[2][j] *= pa;
-          B[3][j] *= ec_e;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          B[i][0] = fma(tau_e, B[i][1], B[i][0]);
-          B[i][2] *= pb;
-          B[i][3] *= ec_e;
-        }
-        B[3][3] = fma(s_hd[ba * P + bb] * vc, bc.end[2], B[3][3]);
-        if (ba == bb) {
-          B[0][0] += bc.end[3];
-          B[0][1] += bc.end[4];
-          B[1][0] += bc.end[4];
-          B[1][1] += bc.end[5];
-          B[2][2] += bc.qae[ba];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            sP[(4 * ba + i) * kLdP + 4 * bb + j] = B[i][j];
-            sP[(4 * bb + j) * kLdP + 4 * ba + i] = B[i][j];
-          }
+      if (wave == 0 && sig) {
+        s_led[b & 1][lane][0] = dk;
+        s_led[b & 1][lane][1] = ek;
       }
-    } else {
-      // records of block b + 2 (issued first, stored last), constants of b + 1
-      const int64_t k2 = k0 + 2 * kB;
-      const bool ok = k2 + (lane >> 2) < N;
+    } else if (wave == kWLedger) {
+      if (lane < kB && b > 0) ledger((b - 1) & 1, lane);
+    } else if (wave == kWToa) {
+      // records of block b + 3 (issued first, stored last), per-TOA
+      // constants of block b + 2
+      const int64_t k3 = k0 + 3 * kB;
+      const bool ok = k3 + (lane >> 2) < N;
       double r0 = 0.0, r1 = 0.0;
       if (ok) {
-        r0 = recd[k2 * 8 + 2 * lane];
-        r1 = recd[k2 * 8 + 2 * lane + 1];
+        r0 = recd[k3 * 8 + 2 * lane];
+        r1 = recd[k3 * 8 + 2 * lane + 1];
       }
-      if (k0 + kB < N) prep(cb ^ 1, k0 + kB);
+      if (k0 + 2 * kB < N) toa_part((int)((b + 2) % kNBuf), k0 + 2 * kB, lane);
       if (ok) {
         s_rec[cb][lane >> 2][2 * (lane & 3)] = r0;
         s_rec[cb][lane >> 2][2 * (lane & 3) + 1] = r1;
+      }
+    } else if (tsl >= 0) {
+      if (psl >= 0 && k0 + kB < N) pairs_part((int)((b + 1) % kNBuf));
+      // P0 <- A_end P0 A_end^T + Qacc_end on the lower triangle of 4x4
+      // pulsar blocks (the downdate below rewrites the upper triangle from
+      // the lower); consecutive lanes take consecutive columns, the column
+      // mix of the r column takes the f column from the next lane
+      const double sce = bc.end[2] * vc, e3 = bc.end[3], e4 = bc.end[4], e5 = bc.end[5];
+#pragma unroll
+      for (int rr = 0; rr < kTfRounds; ++rr) {
+        const int tu = tfu[rr];
+        // units are a prefix of the lanes: none in lane 0, none in the wave
+        if (__builtin_amdgcn_readfirstlane(tu) < 0) continue;
+        const bool live = tu >= 0;
+        const int q = live ? tu >> 8 : 0, c = live ? tu & 255 : 0, cc = c & 3, qc = c >> 2;
+        double x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[i] = sP[(4 * q + i) * kLdP + c];
+        const double eq_r = bc.eqe[q], eq_c = bc.eqe[qc], qa_r = bc.qae[q];
+        const double hv = s_hd[q * P + qc];
+        x[0] = fma(tau_e, x[1], x[0]);
+        x[2] *= eq_r;
+        x[3] *= ec_e;
+        const double mc = cc == 2 ? eq_c : (cc == 3 ? ec_e : 1.0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double nx = next_lane_d(x[i]);
+          x[i] = cc == 0 ? fma(tau_e, nx, x[i]) : mc * x[i];
+        }
+        const bool own = qc == q;
+        x[0] += own ? (cc == 0 ? e3 : (cc == 1 ? e4 : 0.0)) : 0.0;
+        x[1] += own ? (cc == 0 ? e4 : (cc == 1 ? e5 : 0.0)) : 0.0;
+        x[2] += own && cc == 2 ? qa_r : 0.0;
+        x[3] = fma(hv * sce, cc == 3 ? 1.0 : 0.0, x[3]);
+        if (live) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sP[(4 * q + i) * kLdP + c] = x[i];
+        }
       }
     }
     __syncthreads();
     // ---- D. P -= U M^T on the FP64 matrix cores, lower tiles, mirrored
 #pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      const int t = wave + 4 * u;
-      if (t >= nt * (nt + 1) / 2) break;
-      int I = 0, J = t;
-      while (J >= I + 1) {
-        J -= I + 1;
-        ++I;
-      }
+    for (int u = 0; u < 2; ++u) {
+      if (wave + kWaves * u >= ntl) break;
+      const int I = tI[u], J = tJ[u];
       f64x4 acc;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         acc[r] = sP[(16 * I + (lane >> 4) + 4 * r) * kLdP + 16 * J + (lane & 15)];
-      const double* ua = sU + (16 * I + (lane & 15)) * kLdB + (lane >> 4);
-      const double* mb = sM + (16 * J + (lane & 15)) * kLdB + (lane >> 4);
+      const double* pu = sU + (16 * I + (lane & 15)) * kLdB + (lane >> 4);
+      const double* pm = sM + (16 * J + (lane & 15)) * kLdB + (lane >> 4);
 #pragma unroll
       for (int kc = 0; kc < kB / 4; ++kc)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-ua[4 * kc], mb[4 * kc], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pu[4 * kc], pm[4 * kc], acc, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * I + (lane >> 4) + 4 * r, col = 16 * J + (lane & 15);
@@ -506,7 +608,8 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
     __syncthreads();
     xb ^= 1;
   }
-  if (tid == 0) {
+  if (wave == kWLedger && lane < kB && k0 > 0) ledger((int)(((k0 / kB) - 1) & 1), lane);
+  if (tid == kLedger) {
     if (s_pnf) st = kNonFinite;
     double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
     if (st == 0 && !finite_d(ll)) st = kNonFinite;
