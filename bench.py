@@ -8,6 +8,7 @@ g], 4096 parameter samples), one step = one batched call over all samples
 inputs resident in HBM. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+                  [--copy-calib]
 """
 from __future__ import annotations
 
@@ -142,6 +143,40 @@ def surrogate_leg(A, pi, dev, stream, log):
     return out
 
 
+COPY_CALIB_BYTES = 256 << 20
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_filter_m2_47psr_4096samples_pmc.txt")
+FILTER_SOURCES = [os.path.join(ROOT, "paper_2510_11077_amd", "csrc", f)
+                  for f in ("k_filter.hip", "argus_internal.h")]
+
+
+def filter_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FILTER_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline filter kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (each scaled by the same counter
+    on a plain copy of known size); None when there is none or when the
+    kernel source has changed since the counters were taken."""
+    try:
+        with open(PMC_SUMMARY) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != filter_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -170,6 +205,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -186,6 +223,16 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     dev = "cuda:0"
+
+    if args.copy_calib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # give the scale that turns the filter's counters into HBM bytes
+        src = torch.ones(COPY_CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------------------------------------------------- headline
     d = pi.make_config("cfg2")
@@ -233,7 +280,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "k_filter<2> (+ k_reduce in the same timed step)",
             "flop_per_launch": flop,
         },

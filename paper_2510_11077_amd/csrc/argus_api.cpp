@@ -305,6 +305,9 @@ int argus_dataset_create(const argus_dataset_desc* d, argus_dataset_t* out) {
     if (d->fixed) fixed[c] = d->fixed[c];
   }
   ds->D = D;
+  std::vector<int32_t> icol(D > 0 ? D : 1, 0);
+  for (int c = 0; c < ds->C; ++c)
+    if (col[c] >= 0) icol[col[c]] = c;
   ds->off_h.assign(d->toa_off, d->toa_off + ds->P + 1);
   ds->counts.resize(ds->P);
   for (int p = 0; p < ds->P; ++p) ds->counts[p] = d->toa_off[p + 1] - d->toa_off[p];
@@ -345,6 +348,7 @@ int argus_dataset_create(const argus_dataset_desc* d, argus_dataset_t* out) {
       (rc = ds->rec.alloc(N * sizeof(TOARec))) ||
       (rc = ds->off.upload(d->toa_off, (ds->P + 1) * sizeof(int64_t))) ||
       (rc = ds->col.upload(col.data(), ds->C * sizeof(int32_t))) ||
+      (rc = ds->icol.upload(icol.data(), icol.size() * sizeof(int32_t))) ||
       (rc = ds->fixed.upload(fixed.data(), ds->C * sizeof(double))))
     return rc;
   StageArgs sa{ds->t.as<double>(), ds->y.as<double>(), ds->sig.as<double>(),

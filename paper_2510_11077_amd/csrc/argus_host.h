@@ -85,7 +85,7 @@ struct argus_dataset {
   int64_t N = 0;
   int device = 0, n_cu = 256;
   argus::ModelConst mc{};
-  argus::DevBuf rec, off, col, fixed, hd, t, y, sig;
+  argus::DevBuf rec, off, col, icol, fixed, hd, t, y, sig;  // icol: theta column -> canonical
   std::vector<int64_t> off_h, counts;
   std::map<int64_t, std::unique_ptr<argus::Workspace>> ws;
   hipStream_t cap_stream = nullptr;

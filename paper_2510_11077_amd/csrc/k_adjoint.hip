@@ -361,32 +361,29 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
   }
 }
 
-// grad[s, col(c)] from the per-pulsar parts: a pulsar's own parameters from
-// its filter, the common ones summed over pulsars in index order; rows of
-// failed samples are zero.
-__global__ void k_grad_reduce(const double* gpart, const int32_t* status, const int32_t* col,
-                              double* grad, int64_t S, int D, int P, int model) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const bool bad = status[s] != 0;
-  double* g = grad + s * D;
+// grad[s, c] from the per-pulsar parts, one thread per element (consecutive
+// threads on consecutive columns of a row, so the rows are written whole): a
+// pulsar's own parameters from its filter, the common ones summed over
+// pulsars in index order; rows of failed samples are zero.
+__global__ void __launch_bounds__(256) k_grad_reduce(const double* gpart, const int32_t* status,
+                                                     const int32_t* icol, double* grad, int64_t S,
+                                                     int D, int P, int model) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S * D) return;
+  const int64_t s = i / D;
+  const int c = (int)(i - s * D);
+  const int k = icol[c];  // canonical parameter of column c
+  double v;
   if (model == 1) {
-    for (int c = 0; c < 2; ++c)
-      if (col[c] >= 0) g[col[c]] = bad ? 0.0 : gpart[(int64_t)c * S + s];
-    return;
+    v = gpart[(int64_t)k * S + s];
+  } else if (k < 4 * P) {
+    v = gpart[((int64_t)(k >> 2) * 6 + (k & 3)) * S + s];
+  } else {
+    const int j = k - 4 * P;
+    v = 0.0;
+    for (int p = 0; p < P; ++p) v += gpart[((int64_t)p * 6 + 4 + j) * S + s];
   }
-  for (int p = 0; p < P; ++p)
-    for (int j = 0; j < 4; ++j) {
-      const int cj = col[4 * p + j];
-      if (cj >= 0) g[cj] = bad ? 0.0 : gpart[((int64_t)p * 6 + j) * S + s];
-    }
-  for (int j = 0; j < 2; ++j) {
-    const int cj = col[4 * P + j];
-    if (cj < 0) continue;
-    double acc = 0.0;
-    for (int p = 0; p < P; ++p) acc += gpart[((int64_t)p * 6 + 4 + j) * S + s];
-    g[cj] = bad ? 0.0 : acc;
-  }
+  grad[i] = status[s] != 0 ? 0.0 : v;
 }
 
 }  // namespace
@@ -456,9 +453,10 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
                w->counter.as<int32_t>(), S, ds->P};
   HIPCHK(launch_reduce(r, st));
   const int blk = 256;
-  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((S + blk - 1) / blk)), dim3(blk), 0, st,
-                     w->gpart.as<double>(), stat, ds->col.as<int32_t>(), grad, S, ds->D,
-                     ds->P, ds->model);
+  if (ds->D > 0)
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((S * ds->D + blk - 1) / blk)), dim3(blk), 0,
+                       st, w->gpart.as<double>(), stat, ds->icol.as<int32_t>(), grad, S, ds->D,
+                       ds->P, ds->model);
   HIPCHK(hipGetLastError());
   return ARGUS_OK;
 }

@@ -46,6 +46,8 @@ struct GemmArgs {
   const float* zin;   // BWD [M x N] pre-activation of the layer being entered
   float* C;           // WGRAD [M x ldc]
   int ldc;
+  float* part;        // WGRAD split over K: partial products [gridDim.z][M x N]
+  int kchunk;         // K per workgroup along z (a multiple of 16)
 };
 
 __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
@@ -62,7 +64,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   const __bf16* xp = g.X + (size_t)mr * g.ldx + kk;
   const __bf16* yp = g.Y + (size_t)nr * g.ldy + kk;
   f32x16 acc = {};
-  for (int k = 0; k < g.K; k += 16) {
+  const int kb = blockIdx.z * g.kchunk, ke = min(g.K, kb + g.kchunk);
+  for (int k = kb; k < ke; k += 16) {
     const bf16x8 a = *reinterpret_cast<const bf16x8*>(xp + k);
     const bf16x8 b = *reinterpret_cast<const bf16x8*>(yp + k);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
@@ -75,7 +78,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     if (row >= g.M) continue;
     const float v = acc[r];
     if (EPI == EPI_WGRAD) {
-      g.C[(size_t)row * g.ldc + col] = v;
+      if (g.part)
+        g.part[((size_t)blockIdx.z * g.M + row) * g.N + col] = v;
+      else
+        g.C[(size_t)row * g.ldc + col] = v;
     } else {
       float o;
       if (EPI == EPI_FWD) {
@@ -92,6 +98,18 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       if (g.outT) g.outT[(size_t)col * g.ldoT + row] = ob;
     }
   }
+}
+
+// Sum of the split-K partial products in split order (deterministic).
+__global__ void __launch_bounds__(256) k_sum_parts(const float* part, int nsplit, int M, int N,
+                                                   float* C, int ldc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int64_t mn = (int64_t)M * N;
+  float acc = part[i];
+  for (int s2 = 1; s2 < nsplit; ++s2) acc += part[s2 * mn + i];
+  const int64_t row = i / N, col = i - row * N;
+  C[row * ldc + col] = acc;
 }
 
 // Inputs mapped from the prior box to [-1, 1], rounded to BF16, padded with
@@ -397,6 +415,7 @@ struct argus_mlp {
   }
   // training buffers
   argus::DevBuf x0, x0T, z[3], a[3], aT[3], dz[3], dzT[3], t, dout, sq, g;
+  argus::DevBuf wpart;  // split-K partial weight gradients
 };
 
 namespace argus {
@@ -404,8 +423,11 @@ namespace {
 
 int64_t mlp_params(int d, int w) { return (int64_t)w * d + 2LL * w * w + 4LL * w + 1; }
 
-int launch_gemm(int epi, const GemmArgs& g, hipStream_t st) {
-  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
+constexpr int kWgradSplits = 16;
+
+int launch_gemm(int epi, GemmArgs g, hipStream_t st, int nsplit = 1) {
+  if (g.kchunk <= 0) g.kchunk = g.K;
+  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, nsplit);
   if (epi == EPI_FWD)
     hipLaunchKernelGGL(k_gemm<EPI_FWD>, grid, dim3(256), 0, st, g);
   else if (epi == EPI_BWD)
@@ -499,12 +521,19 @@ int mlp_backprop(argus_mlp* h, const double* theta, const double* target, int64_
     // weight gradient dW_l = dZ_l^T A_{l-1}
     const int K_in = l == 0 ? kKin : w;
     const __bf16* AinT = l == 0 ? h->x0T.as<__bf16>() : h->aT[l - 1].as<__bf16>();
-    GemmArgs gw = gemm(h->dzT[l].as<__bf16>(), (int)ldT, AinT, (int)ldT, w,
-                       l == 0 ? d : w, (int)B);
-    gw.C = g + oW[l];
-    gw.ldc = l == 0 ? d : w;
+    const int Nw = l == 0 ? d : w;
+    GemmArgs gw = gemm(h->dzT[l].as<__bf16>(), (int)ldT, AinT, (int)ldT, w, Nw, (int)B);
     (void)K_in;
-    if ((rc = launch_gemm(EPI_WGRAD, gw, st))) return rc;
+    // K = batch is long and M x N small: split K so that the launch fills the
+    // chip, then sum the partials in split order
+    const int nsplit = (int)std::min<int64_t>(kWgradSplits, B / 64);
+    gw.kchunk = (int)(((B + nsplit - 1) / nsplit + 63) / 64 * 64);
+    const int nsp = (int)((B + gw.kchunk - 1) / gw.kchunk);
+    gw.part = h->wpart.as<float>();
+    if ((rc = launch_gemm(EPI_WGRAD, gw, st, nsp))) return rc;
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks((int64_t)w * Nw, 256)), dim3(256), 0, st,
+                       h->wpart.as<float>(), nsp, w, Nw, g + oW[l], Nw);
+    HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_rowsum_bf16, dim3(w), dim3(256), 0, st,
                        h->dzT[l].as<__bf16>(), w, B, ldT, g + oW[l] + (int64_t)w * (l == 0 ? d : w));
     HIPCHK(hipGetLastError());
@@ -600,7 +629,7 @@ int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t
       (rc = h->lo.alloc(kKin * 8)) || (rc = h->hi.alloc(kKin * 8)) ||
       (rc = h->x0.alloc(B * kKin * 2)) || (rc = h->x0T.alloc(B * kKin * 2)) ||
       (rc = h->t.alloc(B * 4)) || (rc = h->dout.alloc(B * 4)) || (rc = h->sq.alloc(B * 4)) ||
-      (rc = h->g.alloc(h->n * 4)))
+      (rc = h->g.alloc(h->n * 4)) || (rc = h->wpart.alloc(kWgradSplits * w * w * 4)))
     return rc;
   for (int l = 0; l < 3; ++l)
     if ((rc = h->z[l].alloc(B * w * 4)) || (rc = h->a[l].alloc(B * w * 2)) ||
