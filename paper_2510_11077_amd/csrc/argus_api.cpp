@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <numeric>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -138,6 +139,38 @@ std::vector<int32_t> make_items(const std::vector<int64_t>& counts, int64_t S) {
   return it;
 }
 
+// Items (tile, pulsar) split into n_bins lists of about equal total TOA
+// steps (longest item first to the least-loaded list), each list longest
+// first, concatenated; off[b]..off[b+1] is list b. Lists 4c..4c+3 are the
+// four SIMDs of block c, one block per CU.
+std::vector<int32_t> make_items_binned(const std::vector<int64_t>& counts, int64_t S,
+                                       int n_bins, std::vector<int32_t>* off) {
+  const int64_t tiles = (S + kWave - 1) / kWave;
+  std::vector<int> order(counts.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return counts[a] > counts[b]; });
+  std::vector<std::vector<int32_t>> bins(n_bins);
+  using E = std::pair<int64_t, int>;
+  std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+  for (int b = 0; b < n_bins; ++b) heap.push({0, b});
+  for (int p : order)
+    for (int64_t t = 0; t < tiles; ++t) {
+      const E e = heap.top();
+      heap.pop();
+      bins[e.second].push_back((int32_t)t);
+      bins[e.second].push_back(p);
+      heap.push({e.first + std::max<int64_t>(counts[p], 1), e.second});
+    }
+  std::vector<int32_t> it;
+  off->assign(1, 0);
+  for (auto& b : bins) {
+    it.insert(it.end(), b.begin(), b.end());
+    off->push_back((int32_t)(it.size() / 2));
+  }
+  return it;
+}
+
 int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
                        double* logl, int32_t* status, const TuneCfg& cfg,
                        hipStream_t st) {
@@ -147,15 +180,17 @@ int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
   a.theta = theta;
   a.col = ds->col.as<int32_t>();
   a.fixed = ds->fixed.as<double>();
-  a.items = w->items.as<int32_t>();
+  const bool bal = cfg.order == 1;
+  a.items = (bal ? w->items_bal : w->items).as<int32_t>();
+  a.bin_off = bal ? w->bin_off.as<int32_t>() : nullptr;
   a.counter = w->counter.as<int32_t>();
   a.part = w->part.as<double>();
   a.pstat = w->pstat.as<int32_t>();
   a.S = w->S;
   a.D = ds->D;
   a.P = ds->P;
-  a.n_items = w->n_items;
-  a.dynamic = cfg.dynamic;
+  a.n_items = bal ? w->n_items_bal : w->n_items;
+  a.dynamic = bal ? 2 : cfg.dynamic;
   a.mc = ds->mc;
   HIPCHK(launch_filter(ds->model, a, cfg.grid, cfg.block, st));
   ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, status,
@@ -174,10 +209,12 @@ std::vector<TuneCfg> candidates(const argus_dataset* ds, const Workspace* w) {
     const int64_t grid = (waves + wpb - 1) / wpb;
     for (auto& x : c)
       if (x.block == block && x.grid == grid && x.dynamic == dyn) return;
-    c.push_back({block, (int)grid, dyn, 0.f});
+    c.push_back({block, (int)grid, dyn, 0, 0.f});
   };
   add(64, w->n_items, 0);
   add(256, w->n_items, 0);
+  if (w->n_items_bal > 0)
+    for (int b : {256, 512, 1024}) c.push_back({b, w->n_bins, 0, 1, 0.f});
   for (int k : {1, 2, 3, 4, 6}) add(64, (int64_t)simd * k, 1);
   for (int k : {2, 4}) add(256, (int64_t)simd * k, 1);
   return c;
@@ -187,19 +224,23 @@ int autotune(argus_dataset* ds, Workspace* w, const double* theta, double* logl,
              int32_t* status, hipStream_t st) {
   const char* forced = std::getenv("ARGUS_CFG");
   if (forced) {
-    int b = 0, g = 0, dyn = 0;
-    if (std::sscanf(forced, "%d,%d,%d", &b, &g, &dyn) == 3 && b >= 64 && b <= 256 &&
-        b % 64 == 0 && g >= 1) {
-      w->cfg = {b, g, dyn, 0.f};
+    int b = 0, g = 0, dyn = 0, ord = 0;
+    const int nf = std::sscanf(forced, "%d,%d,%d,%d", &b, &g, &dyn, &ord);
+    const bool ok0 = ord == 0 && b >= 64 && b <= 256 && (dyn == 0 || dyn == 1);
+    const bool ok1 = ord == 1 && b >= 64 && b <= 1024 && w->n_items_bal > 0;
+    if (nf >= 3 && b % 64 == 0 && g >= 1 && (ok0 || ok1)) {
+      w->cfg = {b, ord == 1 ? w->n_bins : g, ord == 1 ? 0 : dyn, ord, 0.f};
       w->tuned = true;
       return ARGUS_OK;
     }
-    return fail(ARGUS_E_INVAL, "ARGUS_CFG must be 'block,grid,dynamic'");
+    return fail(ARGUS_E_INVAL,
+                "ARGUS_CFG must be 'block,grid,dynamic[,order]' (order 0: block <= 256; "
+                "order 1: per-SIMD lists, block <= 1024, grid ignored)");
   }
   const char* en = std::getenv("ARGUS_TUNE");
   if (en && std::strcmp(en, "0") == 0) {
     const int wpb = 1;
-    w->cfg = {64 * wpb, (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu), 1, 0.f};
+    w->cfg = {64 * wpb, (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu), 1, 0, 0.f};
     w->tuned = true;
     return ARGUS_OK;
   }
@@ -231,8 +272,8 @@ int autotune(argus_dataset* ds, Workspace* w, const double* theta, double* logl,
   w->tune_log.clear();
   for (auto& c : cand) {
     char b[128];
-    std::snprintf(b, sizeof b, "block=%d grid=%d dyn=%d: %.4f ms\n", c.block, c.grid,
-                  c.dynamic, c.ms);
+    std::snprintf(b, sizeof b, "block=%d grid=%d dyn=%d order=%d: %.4f ms\n", c.block, c.grid,
+                  c.dynamic, c.order, c.ms);
     w->tune_log += b;
   }
   return ARGUS_OK;
@@ -261,6 +302,14 @@ Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc) {
     std::vector<int32_t> items = make_items(ds->counts, S);
     w->n_items = (int)(items.size() / 2);
     if ((*rc = w->items.upload(items.data(), items.size() * sizeof(int32_t)))) return nullptr;
+    std::vector<int32_t> boff;
+    std::vector<int32_t> bal = make_items_binned(ds->counts, S, 4 * ds->n_cu, &boff);
+    w->n_items_bal = (int)(bal.size() / 2);
+    w->n_bins = ds->n_cu;  // blocks
+    if (bal.empty()) bal.assign(2, -1);  // keep the buffer non-empty
+    if ((*rc = w->items_bal.upload(bal.data(), bal.size() * sizeof(int32_t))) ||
+        (*rc = w->bin_off.upload(boff.data(), boff.size() * sizeof(int32_t))))
+      return nullptr;
   }
   Workspace* raw = w.get();
   ds->ws[S] = std::move(w);
@@ -477,8 +526,9 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
   } else {
     const Workspace* w = it->second.get();
     char b[160];
-    std::snprintf(b, sizeof b, "chosen block=%d grid=%d dyn=%d items=%d\n", w->cfg.block,
-                  w->cfg.grid, w->cfg.dynamic, w->n_items);
+    std::snprintf(b, sizeof b, "chosen block=%d grid=%d dyn=%d order=%d items=%d\n",
+                  w->cfg.block, w->cfg.grid, w->cfg.dynamic, w->cfg.order,
+                  w->cfg.order == 1 ? w->n_items_bal : w->n_items);
     s = b + w->tune_log;
   }
   std::snprintf(buf, len, "%s", s.c_str());

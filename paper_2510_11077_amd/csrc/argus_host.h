@@ -47,6 +47,7 @@ struct TuneCfg {
   int block = 64;
   int grid = 1;
   int dynamic = 1;
+  int order = 0;  // 0: items longest-first; 1: one block per CU, per-SIMD item lists
   float ms = 0.f;
 };
 
@@ -55,6 +56,10 @@ struct Workspace {
   int64_t S = 0;
   DevBuf part, pstat, logl_tmp, items, counter;
   int n_items = 0;
+  // the same items in one list per SIMD (4 per CU) with about equal TOA
+  // steps per list
+  DevBuf items_bal, bin_off;
+  int n_items_bal = 0, n_bins = 0;
   TuneCfg cfg;
   bool tuned = false;
   std::string tune_log;

@@ -114,11 +114,13 @@ struct FilterArgs {
   const int32_t* col;    // [C] theta column of canonical param, or -1
   const double* fixed;   // [C]
   const int32_t* items;  // [n_items*2] (sample tile, pulsar), longest first
+  // per-SIMD mode: items of SIMD j of block b are [bin_off[4b+j], bin_off[4b+j+1])
+  const int32_t* bin_off;
   int32_t* counter;      // work-queue head (zero before launch)
   double* part;          // [P*S] per-pulsar log-likelihood terms
   int32_t* pstat;        // [P*S] per-pulsar status words
   int64_t S;
-  int32_t D, P, n_items, dynamic;
+  int32_t D, P, n_items, dynamic;  // dynamic: 0 static, 1 global queue, 2 per-SIMD queues
   ModelConst mc;
 };
 

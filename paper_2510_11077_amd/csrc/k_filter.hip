@@ -82,13 +82,14 @@ struct F4 {
   int st;
 };
 
-__device__ __forceinline__ void step4(F4& f, const TOARec r, double gr,
+// em = expm1(-rate dt) for this record (computed a step ahead by the caller:
+// it does not depend on the state, so it overlaps the previous step's chain)
+__device__ __forceinline__ void step4(F4& f, const TOARec r, double em,
                                       double vr, double vc, double efac2,
                                       double equad2, double ss2) {
   const double dt = r.dt;
   // red OU over dt for this lane's rate: phi = 1 + expm1(-g dt),
   // q = v (1 - phi^2) = -v em (2 + em) without cancellation
-  const double em = expm1_k(-gr * dt);
   const double phr = 1.0 + em;
   const double qr = vr * (-em * (2.0 + em));
   const double phc = r.phc;
@@ -177,25 +178,53 @@ __device__ __forceinline__ double finish(double n, double quad,
   return st ? -INFINITY : ll;
 }
 
-template <int MODEL>
-__global__ void __launch_bounds__(256) k_filter(FilterArgs a) {
+// MAXT: launch bound (256, or 1024 for the one-block-per-CU layout)
+template <int MODEL, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wpb = blockDim.x / kWave;
   const int gwave = __builtin_amdgcn_readfirstlane(
       (int)(blockIdx.x * wpb + (threadIdx.x / kWave)));
   const int nwaves = gridDim.x * wpb;
+  // per-SIMD queues (one block per CU): the host splits the items into one
+  // list per SIMD of about equal TOA steps; a wave reads which SIMD it runs
+  // on and takes items, longest first, from that SIMD's list, then from the
+  // other three, so every item is taken wherever the waves were placed. A
+  // SIMD issues from its older waves first, so what sets its finishing time
+  // is the total it is given, which is what the lists balance.
+  __shared__ int q_head[4];
+  int simd = 0, q_sl = 0, q_lo = 0, q_hi = 0;
+  if (a.dynamic == 2) {
+    if (threadIdx.x < 4) q_head[threadIdx.x] = 0;
+    __syncthreads();
+    simd = (int)((__builtin_amdgcn_s_getreg((31 << 11) | 4) >> 4) & 3);  // HW_ID.SIMD_ID
+    q_lo = a.bin_off[4 * blockIdx.x + simd];
+    q_hi = a.bin_off[4 * blockIdx.x + simd + 1];
+  }
   int next = gwave;
   for (;;) {
     int it;
-    if (a.dynamic) {
+    if (a.dynamic == 1) {
       int v = 0;
       if (lane == 0) v = atomicAdd(a.counter, 1);
       it = __builtin_amdgcn_readfirstlane(v);
+    } else if (a.dynamic == 2) {
+      // next item of list (simd + q_sl) % 4; an exhausted list moves on
+      for (;;) {
+        int v = 0;
+        if (lane == 0) v = atomicAdd(&q_head[(simd + q_sl) & 3], 1);
+        it = q_lo + __builtin_amdgcn_readfirstlane(v);
+        if (it < q_hi || ++q_sl == 4) break;
+        const int sl = (simd + q_sl) & 3;
+        q_lo = a.bin_off[4 * blockIdx.x + sl];
+        q_hi = a.bin_off[4 * blockIdx.x + sl + 1];
+      }
+      if (it >= q_hi) break;
     } else {
       it = next;
       next += nwaves;
     }
-    if (it >= a.n_items) break;
+    if (a.dynamic != 2 && it >= a.n_items) break;
     const int tile = a.items[2 * it];
     const int p = a.items[2 * it + 1];
     const int64_t s_raw = (int64_t)tile * kWave + lane;
@@ -235,8 +264,21 @@ __global__ void __launch_bounds__(256) k_filter(FilterArgs a) {
       f.st = pnf ? kPNF : 0;
       const double ss2 = a.mc.ss2;
       const RecPtr rec = (RecPtr)a.rec;
-      for (int64_t k = kb; k < ke; ++k)
-        step4(f, load_rec(rec, k), gr, vr, vc, efac2, equad2, ss2);
+      // the next record and its red decay are fetched one step ahead (the
+      // index is clamped, so the last iteration repeats harmless work)
+      TOARec rn{};
+      double emn = 0.0;
+      if (kb < ke) {
+        rn = load_rec(rec, kb);
+        emn = expm1_k(-gr * rn.dt);
+      }
+      for (int64_t k = kb; k < ke; ++k) {
+        const TOARec r = rn;
+        const double em = emn;
+        rn = load_rec(rec, k + 1 < ke ? k + 1 : k);
+        emn = expm1_k(-gr * rn.dt);
+        step4(f, r, em, vr, vc, efac2, equad2, ss2);
+      }
       st = f.st;
       ll = finish((double)(ke - kb), f.quad, f.L, st);
     }
@@ -466,10 +508,15 @@ hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st) {
 
 hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
                          hipStream_t st) {
-  if (model == 1)
-    hipLaunchKernelGGL(k_filter<1>, dim3(grid), dim3(block), 0, st, a);
+  const bool big = block > 256;
+  if (model == 1 && !big)
+    hipLaunchKernelGGL((k_filter<1, 256>), dim3(grid), dim3(block), 0, st, a);
+  else if (model == 1)
+    hipLaunchKernelGGL((k_filter<1, 1024>), dim3(grid), dim3(block), 0, st, a);
+  else if (!big)
+    hipLaunchKernelGGL((k_filter<2, 256>), dim3(grid), dim3(block), 0, st, a);
   else
-    hipLaunchKernelGGL(k_filter<2>, dim3(grid), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_filter<2, 1024>), dim3(grid), dim3(block), 0, st, a);
   return hipGetLastError();
 }
 

@@ -234,3 +234,17 @@ def test_joint_prior_corners_and_flags(argus, orc):
     ref, rst = orc.loglike(dz, z)
     assert rst[0] == 1
     check(ll, st, ref, rst)
+
+
+@pytest.mark.parametrize("cfg", ["64,7,0", "256,3,0", "1024,1,0,1", "256,1,0,1", "64,1,0,1",
+                                 "64,5,1"])
+def test_forced_launch_layouts(argus, orc, cfg, monkeypatch):
+    """Every launch layout the tuner can pick gives the same parity: static
+    longest-first with a grid smaller than the item count, one block per CU
+    with per-SIMD lists (most lists here are empty; with one wave per block
+    every list is drained by taking from the others), and the global dynamic
+    queue."""
+    monkeypatch.setenv("ARGUS_CFG", cfg)
+    d = pi.make_pta("t", n_psr=7, counts=[400, 3, 0, 1200, 64, 777, 90], seed=49)
+    th = pi.sample_theta(d, 200, 14)
+    run(argus, orc, d, th)
