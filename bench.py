@@ -115,21 +115,32 @@ def surrogate_leg(A, pi, dev, stream, log):
     torch.cuda.synchronize()
     da_s = time.perf_counter() - t0
     n_prop = da.n_prop
-    # plain MH: every proposal evaluated exactly
+    # plain MH: every proposal evaluated exactly, in fixed buffers (so the
+    # batched call replays its graph, as a well-written sampler would)
     cur = th0.clone()
     llc, _ = ds5.loglike(cur, want_status=False)
     llc = llc.clone()
     lo_t = torch.as_tensor(lo, device=dev)
     hi_t = torch.as_tensor(hi, device=dev)
+    prop = torch.empty_like(cur)
+    llp = torch.empty_like(llc)
+
+    def mh_step(i):
+        eps, _, lu2 = draws[i]
+        torch.add(cur, eps, out=prop)
+        ds5.loglike(prop, out=llp, want_status=False)
+        acc = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu2 < llp - llc)
+        torch.where(acc[:, None], prop, cur, out=cur)
+        torch.where(acc, llp, llc, out=llc)
+
+    for i in range(2):  # warm-up: graph capture for the fixed buffers
+        mh_step(i)
+    cur.copy_(th0)
+    llc.copy_(ds5.loglike(cur, want_status=False)[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(2, T):
-        eps, _, lu2 = draws[i]
-        prop = (cur + eps).contiguous()
-        llp, _ = ds5.loglike(prop, want_status=False)
-        acc = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu2 < llp - llc)
-        cur = torch.where(acc[:, None], prop, cur)
-        llc = torch.where(acc, llp, llc)
+        mh_step(i)
     torch.cuda.synchronize()
     mh_s = time.perf_counter() - t0
     out["delayed_acceptance_65536_chains"] = {
