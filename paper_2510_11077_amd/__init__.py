@@ -308,6 +308,15 @@ class DelayedAcceptance:
         self.count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.work = torch.empty(da_work_size(self.Q), dtype=torch.int32, device=dev)
         self.acc = torch.zeros(self.Q, dtype=torch.int32, device=dev)
+        # fixed buffers: the batched calls see the same pointers every step
+        # (their captured graphs replay), sliced to the exact-evaluation size
+        self.prop = torch.empty_like(self.theta)
+        self.lh_prop = torch.empty_like(self.lh)
+        self.sub = torch.empty_like(self.theta)
+        self.ll_sub = torch.empty_like(self.ll)
+        # exact-evaluation sizes are rounded up to a multiple of this, so only
+        # a few sizes (each with its tuned workspace) ever occur
+        self.gran = max(64, -(-self.Q // 32))
         self.n_exact = 0
         self.n_prop = 0
 
@@ -323,8 +332,9 @@ class DelayedAcceptance:
         import torch
         if eps is None:
             eps, logu1, logu2 = self.draws()
-        prop = (self.theta + eps).contiguous()
-        lh_prop = self.net.eval(prop)
+        prop, lh_prop = self.prop, self.lh_prop
+        torch.add(self.theta, eps, out=prop)
+        self.net.eval(prop, out=lh_prop)
         da_stage1(prop, self.lo, self.hi, self.lh, lh_prop, logu1, self.idx, self.count,
                   self.work)
         n = int(self.count.item())
@@ -335,11 +345,10 @@ class DelayedAcceptance:
                                theta=self.theta.clone(), n=n))
         if n == 0:
             return 0
-        cap = max(64, 1 << (n - 1).bit_length())  # fixed sizes keep tuned workspaces
-        cap = min(cap, self.Q)
-        sub = torch.empty((cap, self.d), dtype=torch.float64, device=prop.device)
+        cap = min(-(-n // self.gran) * self.gran, self.Q)
+        sub = self.sub[:cap]
         gather_rows(prop, self.idx, self.count, cap, sub)
-        ll_prop, _ = self.ds.loglike(sub, want_status=False)
+        ll_prop, _ = self.ds.loglike(sub, out=self.ll_sub[:cap], want_status=False)
         self.n_exact += n
         da_stage2(self.idx, self.count, cap, ll_prop, lh_prop, logu2, prop, self.theta, self.ll,
                   self.lh, self.acc)

@@ -20,6 +20,7 @@
 // 8(r/4) + 4(l/32) + r%4, column l%32.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "argus_host.h"
@@ -50,7 +51,11 @@ struct GemmArgs {
   int kchunk;         // K per workgroup along z (a multiple of 16)
 };
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+// logistic function with the fast exponential and the hardware reciprocal
+// (errors of a few FP32 ulp, far below the BF16 rounding of every use)
+__device__ __forceinline__ float sigm(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
@@ -152,6 +157,132 @@ __global__ void k_out_eval(const __bf16* a3, int64_t Q, int width, const float* 
   if (m >= Q) return;
   const float o = out_row(a3 + m * width, width, W4, b4[0]);
   out[m] = (double)o * sd + mu;
+}
+
+// Fused inference for width W <= 256: one persistent block of W / 32 waves
+// per CU. Wave w owns output columns [32 w, 32 w + 32) of every hidden layer
+// and keeps those columns of W1, W2, W3 in registers as MFMA B fragments for
+// the whole launch; 64-row chunks of queries go through standardisation,
+// the three hidden layers (activations in LDS, BF16, ping-pong) and the FP32
+// output layer. Same rounding as the unfused path: inputs, weights and each
+// activation in BF16, FP32 accumulation, bias and SiLU in FP32.
+struct FusedArgs {
+  const double* theta;   // [Q x d_in]
+  const double* lo;      // [d_in]
+  const double* hi;
+  const __bf16* W1;      // [W x kKin]
+  const __bf16* W2;      // [W x W] (out x in)
+  const __bf16* W3;
+  const float* p32;      // packed FP32 parameters (biases, W4, b4)
+  double* out;           // [Q]
+  int64_t Q;
+  int d_in;
+  double mu, sd;
+};
+
+template <int W>
+__global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
+  constexpr int NW = W / 32;     // waves
+  constexpr int KS = W / 16;     // K steps of a hidden layer
+  constexpr int R = 64;          // query rows per chunk
+  constexpr int LDA = W + 8;     // activation row stride (16-B pad: b128 reads spread over banks)
+  constexpr int LDX = kKin + 8;
+  __shared__ __bf16 s_x[R * LDX];
+  __shared__ __bf16 s_a[2][R * LDA];
+  __shared__ float s_o[NW][R];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int ncol = 32 * w + (l & 31);     // B-fragment / accumulator column
+  const int kh = 8 * (l >> 5);            // this lane's K half within a step
+  bf16x8 w1[2], w2[KS], w3[KS];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+    w1[ks] = *reinterpret_cast<const bf16x8*>(f.W1 + (size_t)ncol * kKin + 16 * ks + kh);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    w2[ks] = *reinterpret_cast<const bf16x8*>(f.W2 + (size_t)ncol * W + 16 * ks + kh);
+    w3[ks] = *reinterpret_cast<const bf16x8*>(f.W3 + (size_t)ncol * W + 16 * ks + kh);
+  }
+  const int d = f.d_in;
+  const float* b1 = f.p32 + (int64_t)W * d;
+  const float* b2 = b1 + W + (int64_t)W * W;
+  const float* b3 = b2 + W + (int64_t)W * W;
+  const float* W4 = b3 + W;
+  const float bias1 = b1[ncol], bias2 = b2[ncol], bias3 = b3[ncol], b4 = W4[W];
+
+  // one hidden layer: src rows (stride lds) x this wave's 32 columns -> dst;
+  // ksn carries the number of K steps as a type (2 for the input layer)
+  auto layer = [&](auto ksn, const __bf16* src, int lds, const bf16x8* wf, float bias,
+                   __bf16* dst) {
+    constexpr int KSN = decltype(ksn)::value;
+#pragma unroll
+    for (int rb = 0; rb < R / 32; ++rb) {
+      f32x16 acc = {};
+      const __bf16* ap = src + (rb * 32 + (l & 31)) * lds + kh;
+#pragma unroll
+      for (int ks = 0; ks < KSN; ++ks) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap + 16 * ks);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wf[ks], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = rb * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+        const float z = acc[r] + bias;
+        dst[row * LDA + ncol] = (__bf16)(z * sigm(z));
+      }
+    }
+  };
+
+  // standardised inputs of a chunk (rows past Q are zero), loaded into
+  // registers one chunk ahead
+  constexpr int NT = NW * 64, PF = (R * kKin + NT - 1) / NT;
+  float pf[PF];
+  auto fetch = [&](int64_t row0) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int i = t + j * NT;
+      const int m = i / kKin, k = i - m * kKin;
+      float v = 0.0f;
+      if (i < R * kKin && k < d && row0 + m < f.Q)
+        v = (float)(2.0 * (f.theta[(row0 + m) * d + k] - f.lo[k]) / (f.hi[k] - f.lo[k]) - 1.0);
+      pf[j] = v;
+    }
+  };
+  fetch((int64_t)blockIdx.x * R);
+  for (int64_t c = blockIdx.x; c * R < f.Q; c += gridDim.x) {
+    const int64_t row0 = c * R;
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int i = t + j * NT;
+      if (i < R * kKin) s_x[(i / kKin) * LDX + i % kKin] = (__bf16)pf[j];
+    }
+    fetch(row0 + (int64_t)gridDim.x * R);
+    __syncthreads();
+    layer(std::integral_constant<int, 2>{}, s_x, LDX, w1, bias1, s_a[0]);
+    __syncthreads();
+    layer(std::integral_constant<int, KS>{}, s_a[0], LDA, w2, bias2, s_a[1]);
+    __syncthreads();
+    layer(std::integral_constant<int, KS>{}, s_a[1], LDA, w3, bias3, s_a[0]);
+    __syncthreads();
+    // output layer in FP32: wave w sums its 32 columns for row l
+    {
+      const __bf16* ar = s_a[0] + l * LDA + 32 * w;
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 32; j += 8) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(ar + j);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc = fmaf((float)v[i], W4[32 * w + j + i], acc);
+      }
+      s_o[w][l] = acc;
+    }
+    __syncthreads();
+    if (t < R && row0 + t < f.Q) {
+      float o = 0.0f;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) o += s_o[ww][t];
+      f.out[row0 + t] = (double)(o + b4) * f.sd + f.mu;
+    }
+  }
 }
 
 // Training head: o, residual, dout = 2 (o - t) / B, squared residual.
@@ -395,7 +526,7 @@ __global__ void k_da2(DA2Args a) {
 struct argus_mlp {
   int d_in = 0, width = 0;
   int64_t n = 0, max_batch = 0;
-  int device = 0;
+  int device = 0, n_cu = 256;
   argus::DevBuf p32, w1, w2, w3, w2T, w3T, lo, hi;
   double mu = 0.0, sd = 1.0;
   bool loaded = false;
@@ -582,6 +713,21 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
 }
 
 int eval_seq(argus_mlp* h, const double* theta, int64_t Q, double* logl_hat, hipStream_t st) {
+  if (h->width <= 256) {
+    FusedArgs f{theta, h->lo.as<double>(), h->hi.as<double>(), h->w1.as<__bf16>(),
+                h->w2.as<__bf16>(), h->w3.as<__bf16>(), h->p32.as<float>(), logl_hat, Q,
+                h->d_in, h->mu, h->sd};
+    const unsigned grid = (unsigned)std::min<int64_t>(h->n_cu, (Q + 63) / 64);
+    const dim3 block(h->width * 2);
+    switch (h->width) {
+      case 64: hipLaunchKernelGGL(k_mlp_fused<64>, dim3(grid), block, 0, st, f); break;
+      case 128: hipLaunchKernelGGL(k_mlp_fused<128>, dim3(grid), block, 0, st, f); break;
+      case 192: hipLaunchKernelGGL(k_mlp_fused<192>, dim3(grid), block, 0, st, f); break;
+      default: hipLaunchKernelGGL(k_mlp_fused<256>, dim3(grid), block, 0, st, f); break;
+    }
+    HIPCHK(hipGetLastError());
+    return ARGUS_OK;
+  }
   hipLaunchKernelGGL(k_prep, dim3(blocks(Q * kKin, 256)), dim3(256), 0, st, theta, Q, h->d_in,
                      h->lo.as<double>(), h->hi.as<double>(), h->e_x0.as<__bf16>(), nullptr, 0,
                      nullptr, 0.0, 1.0, nullptr);
@@ -621,6 +767,7 @@ int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t
   h->n = mlp_params(d_in, width);
   h->max_batch = max_batch;
   HIPCHK(hipGetDevice(&h->device));
+  HIPCHK(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
   const int64_t w = width, B = max_batch;
   int rc;
   if ((rc = h->p32.alloc(h->n * 4)) || (rc = h->w1.alloc(w * kKin * 2)) ||
