@@ -347,8 +347,10 @@ def main():
             ds.loglike_grad(t4, o4, g4, s4)
             ms4, _ = timed(lambda: ds.loglike_grad(t4, o4, g4, s4), 10, 2, stream)
             extra["grad_47psr_1024samples"] = {"ms_per_call": ms4,
-                                               "evals_per_s": S4 / (ms4 * 1e-3)}
+                                               "evals_per_s": S4 / (ms4 * 1e-3),
+                                               "sweep": "tangent (forward-mode), tuned split"}
             log("grad: %.3f ms/call, %.4g evals/s" % (ms4, S4 / (ms4 * 1e-3)))
+            log("grad tune: " + ds.tune_info(S4).replace("\n", " | "))
         except A.ArgusError as e:
             extra["grad_47psr_1024samples"] = "unavailable: %s" % e
         extra["surrogate_10psr_10param"] = surrogate_leg(A, pi, dev, stream, log)

@@ -530,6 +530,10 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
                   w->cfg.block, w->cfg.grid, w->cfg.dynamic, w->cfg.order,
                   w->cfg.order == 1 ? w->n_items_bal : w->n_items);
     s = b + w->tune_log;
+    if (w->tan_nd) {
+      std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nd);
+      s += b + w->grad_log;
+    }
   }
   std::snprintf(buf, len, "%s", s.c_str());
   return ARGUS_OK;

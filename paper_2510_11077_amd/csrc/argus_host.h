@@ -80,6 +80,9 @@ struct Workspace {
   int64_t tot_seg = 0;
   int max_sub = 0, grad_waves = 0;
   bool grad_ready = false;
+  // tangent-mode gradient: directions per wave (0 = not tuned yet)
+  int tan_nd = 0;
+  std::string grad_log;
   ~Workspace();
 };
 

@@ -27,6 +27,9 @@
 // pulsar), lane = sample, TOA records read with scalar loads.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "argus_host.h"
@@ -361,6 +364,253 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward-mode (tangent) gradient: the same recursion differentiated along a
+// parameter direction d, carried alongside the filter. With the base step's
+// F, u, S, K, e and the tangents (dx, dP) of the posterior:
+//   dx- = F dx + dF x,  dP- = F dP F^T + dF P F^T + F P dF^T + dQ,
+//   de = -h.dx-,  du = dP- h,  dS = h.du + dR,  dK = (du - K dS) / S,
+//   dx+ = dx- + dK e + K de,
+//   dP+ = dP- - du K^T - K du^T + dS K K^T  (the Joseph update's tangent at
+//         the optimal gain; its dK terms cancel because u = S K),
+//   dl += -1/2 (dS / S (1 - e^2 / S) + 2 e de / S).
+// The parameters enter through the red-OU decay phi (its rate), the OU and
+// spin noise, R and the prior. Each wave carries ND of the model's
+// directions (6 for model 2: log10 sigma_red, log10 gamma_red, EFAC,
+// log10 EQUAD, log10 A, gamma; 2 for model 1: log10 sigma_s, EFAC); a
+// (tile, pulsar) item is split over 6 / ND waves, trading repeated base
+// filters for shorter serial chains. One pass, no checkpoints.
+struct TanArgs {
+  const TOARec* rec;
+  const int64_t* off;
+  const double* theta;
+  const int32_t* col;
+  const double* fixed;
+  const int32_t* items;  // (tile, pulsar), longest first
+  int32_t* counter;
+  double* part;          // [P*S]
+  int32_t* pstat;        // [P*S]
+  double* gpart;         // [P * 6 * S]
+  int64_t S;
+  int32_t D, P, n_items, ngroups;
+  ModelConst mc;
+};
+
+__device__ __forceinline__ double tprm(const TanArgs& a, int c, int64_t s) {
+  const int j = a.col[c];
+  return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
+}
+
+struct Tan {
+  double xr, xf, xa, xg;
+  Cov4 P;
+  double dl;
+};
+
+template <int MODEL, int ND>
+__global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const RecPtr rec = (RecPtr)a.rec;
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int it = __builtin_amdgcn_readfirstlane(v);
+    if (it >= a.n_items * a.ngroups) break;
+    const int base = it / a.ngroups, grp = it - base * a.ngroups;
+    const int tile = a.items[2 * base];
+    const int p = a.items[2 * base + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int64_t kb = a.off[p], N = a.off[p + 1] - kb;
+
+    // parameters, base constants and each direction's sources
+    double gr = 1.0, vr = 0.0, vc = 0.0, efac2, equad2 = 0.0, ss2;
+    double sv[ND], sg[ND], sc[ND], sr2[ND], sq2[ND], ss[ND];
+    bool pnf;
+    double t1 = 0.0, t2 = 0.0, t5 = 2.0;
+    if (MODEL == 1) {
+      const double t0 = tprm(a, 0, s);
+      t1 = tprm(a, 1, s);
+      pnf = !(finite_d(t0) && finite_d(t1));
+      const double sgs = exp10(t0);
+      ss2 = sgs * sgs;
+      efac2 = t1 * t1;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        const int dir = grp * ND + j;
+        sv[j] = sg[j] = sc[j] = sq2[j] = 0.0;
+        ss[j] = dir == 0 ? 2.0 * kLn10 * ss2 : 0.0;
+        sr2[j] = dir == 1 ? 2.0 * t1 : 0.0;
+      }
+    } else {
+      const int c0 = 4 * p, cc = 4 * a.P;
+      const double t0 = tprm(a, c0, s);
+      t1 = tprm(a, c0 + 1, s);
+      t2 = tprm(a, c0 + 2, s);
+      const double t3 = tprm(a, c0 + 3, s), t4 = tprm(a, cc, s);
+      t5 = tprm(a, cc + 1, s);
+      pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) && finite_d(t4) &&
+              finite_d(t5));
+      gr = exp10(t1);
+      const double sr = exp10(t0), eq = exp10(t3);
+      vr = sr * sr / (2.0 * gr);
+      const double gm1 = t5 - 1.0;
+      vc = exp(2.0 * kLn10 * t4 + (t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+           (12.0 * kPi * kPi * gm1);
+      efac2 = t2 * t2;
+      equad2 = eq * eq;
+      ss2 = a.mc.ss2;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        const int dir = grp * ND + j;
+        sv[j] = dir == 0 ? 2.0 * kLn10 * vr : (dir == 1 ? -kLn10 * vr : 0.0);
+        sg[j] = dir == 1 ? kLn10 * gr : 0.0;
+        sr2[j] = dir == 2 ? 2.0 * t2 : 0.0;
+        sq2[j] = dir == 3 ? 2.0 * kLn10 * equad2 : 0.0;
+        sc[j] = dir == 4 ? 2.0 * kLn10 * vc
+                         : (dir == 5 ? vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / gm1) : 0.0);
+        ss[j] = 0.0;
+      }
+    }
+
+    // base filter state and the tangents (prior P0 = diag(s_r^2, s_f^2, v_r, v_c))
+    State st{0.0, 0.0, 0.0, 0.0,
+             Cov4{a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, 0.0, vr, 0.0, 0.0, 0.0, vc}};
+    Tan tg[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      tg[j] = Tan{0.0, 0.0, 0.0, 0.0, Cov4{0, 0, 0, 0, 0, sv[j], 0, 0, 0, sc[j]}, 0.0};
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+
+    // the next record and its red decay one step ahead
+    TOARec rn{};
+    double emn = 0.0;
+    if (N > 0) {
+      rn = load_rec(rec, kb);
+      emn = expm1_k(-gr * rn.dt);
+    }
+    for (int64_t k = 0; k < N; ++k) {
+      const TOARec r = rn;
+      const double em = emn;
+      rn = load_rec(rec, kb + (k + 1 < N ? k + 1 : k));
+      emn = expm1_k(-gr * rn.dt);
+      const double dt = r.dt, phc = r.phc;
+      const double ph = 1.0 + em, qfac = -em * (2.0 + em);
+      // base predict
+      const Cov4& Q0 = st.P;
+      const double fpra = fma(dt, Q0.fa, Q0.ra), fpfa = Q0.fa, fpaa = ph * Q0.aa,
+                   fpga = phc * Q0.ag;  // (F P)_{., a} of the posterior
+      const double xa0 = st.xa;
+      Cov4 Pm;
+      const double prf1 = fma(dt, Q0.ff, Q0.rf);
+      Pm.rr = fma(dt, Q0.rf + prf1, Q0.rr) + ss2 * r.h3;
+      Pm.rf = prf1 + ss2 * r.h2;
+      Pm.ff = Q0.ff + ss2 * dt;
+      Pm.ra = ph * fpra;
+      Pm.fa = ph * fpfa;
+      Pm.aa = fma(ph * ph, Q0.aa, vr * qfac);
+      Pm.rg = phc * fma(dt, Q0.fg, Q0.rg);
+      Pm.fg = phc * Q0.fg;
+      Pm.ag = (ph * phc) * Q0.ag;
+      Pm.gg = fma(phc * phc, Q0.gg, vc * r.qcu);
+      const double xr = fma(dt, st.xf, st.xr), xf = st.xf, xa = ph * st.xa, xg = phc * st.xg;
+      const double e = r.y - (xr + xa + xg);
+      const double ur = Pm.rr + Pm.ra + Pm.rg, uf = Pm.rf + Pm.fa + Pm.fg;
+      const double ua = Pm.ra + Pm.aa + Pm.ag, ug = Pm.rg + Pm.ag + Pm.gg;
+      const double S = (ur + ua + ug) + fma(efac2, r.s2, equad2);
+      const double inv = rcp_nr(S);
+      const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
+      const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);  // (1 - e^2/S)/S
+      // tangents
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        Tan& d = tg[j];
+        const double dph = -dt * ph * sg[j];
+        const double dqa = fma(sv[j], qfac, -2.0 * vr * ph * dph);
+        // dx-
+        const double dxr = fma(dt, d.xf, d.xr), dxf = d.xf;
+        const double dxa = fma(ph, d.xa, dph * xa0), dxg = phc * d.xg;
+        // dP- = F dP F^T + (dF P F^T + F P dF^T) + dQ
+        const Cov4& D0 = d.P;
+        Cov4 Dm;
+        const double drf1 = fma(dt, D0.ff, D0.rf);
+        Dm.rr = fma(dt, D0.rf + drf1, D0.rr) + ss[j] * r.h3;
+        Dm.rf = drf1 + ss[j] * r.h2;
+        Dm.ff = fma(ss[j], dt, D0.ff);
+        Dm.ra = fma(ph, fma(dt, D0.fa, D0.ra), dph * fpra);
+        Dm.fa = fma(ph, D0.fa, dph * fpfa);
+        Dm.aa = fma(ph * ph, D0.aa, fma(2.0 * dph, fpaa, dqa));
+        Dm.rg = phc * fma(dt, D0.fg, D0.rg);
+        Dm.fg = phc * D0.fg;
+        Dm.ag = fma(ph * phc, D0.ag, dph * fpga);
+        Dm.gg = fma(phc * phc, D0.gg, sc[j] * r.qcu);
+        // update
+        const double de = -(dxr + dxa + dxg);
+        const double dur = Dm.rr + Dm.ra + Dm.rg, duf = Dm.rf + Dm.fa + Dm.fg;
+        const double dua = Dm.ra + Dm.aa + Dm.ag, dug = Dm.rg + Dm.ag + Dm.gg;
+        const double dS = (dur + dua + dug) + fma(sr2[j], r.s2, sq2[j]);
+        const double dkr = (dur - kr * dS) * inv, dkf = (duf - kf * dS) * inv;
+        const double dka = (dua - ka * dS) * inv, dkg = (dug - kg * dS) * inv;
+        d.xr = fma(dkr, e, fma(kr, de, dxr));
+        d.xf = fma(dkf, e, fma(kf, de, dxf));
+        d.xa = fma(dka, e, fma(ka, de, dxa));
+        d.xg = fma(dkg, e, fma(kg, de, dxg));
+#define TAN_UPD(dp, ki, dui, kj, duj) dp = fma(dS * (ki), kj, fma(-(dui), kj, fma(-(ki), duj, dp)))
+        TAN_UPD(Dm.rr, kr, dur, kr, dur);
+        TAN_UPD(Dm.rf, kr, dur, kf, duf);
+        TAN_UPD(Dm.ff, kf, duf, kf, duf);
+        TAN_UPD(Dm.ra, kr, dur, ka, dua);
+        TAN_UPD(Dm.fa, kf, duf, ka, dua);
+        TAN_UPD(Dm.aa, ka, dua, ka, dua);
+        TAN_UPD(Dm.rg, kr, dur, kg, dug);
+        TAN_UPD(Dm.fg, kf, duf, kg, dug);
+        TAN_UPD(Dm.ag, ka, dua, kg, dug);
+        TAN_UPD(Dm.gg, kg, dug, kg, dug);
+#undef TAN_UPD
+        d.P = Dm;
+        d.dl = fma(-0.5, fma(dS, hS, 2.0 * ei * de), d.dl);
+      }
+      // base update (Joseph form, as the likelihood kernel)
+      st.xr = fma(kr, e, xr);
+      st.xf = fma(kf, e, xf);
+      st.xa = fma(ka, e, xa);
+      st.xg = fma(kg, e, xg);
+      const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+      const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug);
+      JOSEPH(Pm.rr, kr, ur, dr, kr);
+      JOSEPH(Pm.rf, kr, uf, dr, kf);
+      JOSEPH(Pm.ff, kf, uf, df, kf);
+      JOSEPH(Pm.ra, kr, ua, dr, ka);
+      JOSEPH(Pm.fa, kf, ua, df, ka);
+      JOSEPH(Pm.aa, ka, ua, da, ka);
+      JOSEPH(Pm.rg, kr, ug, dr, kg);
+      JOSEPH(Pm.fg, kf, ug, df, kg);
+      JOSEPH(Pm.ag, ka, ug, da, kg);
+      JOSEPH(Pm.gg, kg, ug, dg, kg);
+      st.P = Pm;
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e, ei, quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    }
+    if (valid) {
+      if (grp == 0) {
+        double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+        if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+        a.part[(int64_t)p * a.S + s] = stat ? -INFINITY : ll;
+        a.pstat[(int64_t)p * a.S + s] = stat;
+      }
+      double* g = a.gpart + (int64_t)p * 6 * a.S + s;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) g[(int64_t)(grp * ND + j) * a.S] = tg[j].dl;
+    }
+  }
+}
+
 // grad[s, c] from the per-pulsar parts, one thread per element (consecutive
 // threads on consecutive columns of a row, so the rows are written whole): a
 // pulsar's own parameters from its filter, the common ones summed over
@@ -388,8 +638,122 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const double* gpart, const 
 
 }  // namespace
 
+namespace {
+
+// Per-sample log-likelihood, status and gradient rows from the per-pulsar
+// parts (shared by both gradient sweeps).
+int grad_finish(argus_dataset* ds, Workspace* w, int64_t S, double* logl, double* grad,
+                int32_t* status, hipStream_t st) {
+  int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();
+  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, stat,
+               w->counter.as<int32_t>(), S, ds->P};
+  HIPCHK(launch_reduce(r, st));
+  const int blk = 256;
+  if (ds->D > 0)
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((S * ds->D + blk - 1) / blk)), dim3(blk), 0,
+                       st, w->gpart.as<double>(), stat, ds->icol.as<int32_t>(), grad, S, ds->D,
+                       ds->P, ds->model);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nd, hipStream_t st) {
+  TanArgs a{};
+  a.rec = ds->rec.as<TOARec>();
+  a.off = ds->off.as<int64_t>();
+  a.theta = theta;
+  a.col = ds->col.as<int32_t>();
+  a.fixed = ds->fixed.as<double>();
+  a.items = w->items.as<int32_t>();
+  a.counter = w->counter.as<int32_t>();
+  a.part = w->part.as<double>();
+  a.pstat = w->pstat.as<int32_t>();
+  a.gpart = w->gpart.as<double>();
+  a.S = w->S;
+  a.D = ds->D;
+  a.P = ds->P;
+  a.n_items = w->n_items;
+  a.mc = ds->mc;
+  const int ndir = ds->model == 1 ? 2 : 6;
+  a.ngroups = ndir / nd;
+  const int64_t waves = std::max<int64_t>(
+      4, std::min<int64_t>((int64_t)w->n_items * a.ngroups, 8LL * ds->n_cu));
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  if (ds->model == 1)
+    hipLaunchKernelGGL((k_tangent<1, 2>), grid, block, 0, st, a);
+  else if (nd == 6)
+    hipLaunchKernelGGL((k_tangent<2, 6>), grid, block, 0, st, a);
+  else if (nd == 3)
+    hipLaunchKernelGGL((k_tangent<2, 3>), grid, block, 0, st, a);
+  else if (nd == 2)
+    hipLaunchKernelGGL((k_tangent<2, 2>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_tangent<2, 1>), grid, block, 0, st, a);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+}  // namespace
+
+// Tangent-mode gradient (the default): one streaming pass per direction
+// group; on the first call for a sample count the directions per wave are
+// chosen by timing (model 2: 6, 3, 2 or 1).
+int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl,
+                    double* grad, int32_t* status, hipStream_t st) {
+  int rc = ARGUS_OK;
+  Workspace* w = get_workspace(ds, S, &rc);
+  if (!w) return rc;
+  if (w->gpart.p == nullptr && (rc = w->gpart.alloc((size_t)ds->P * 6 * S * sizeof(double))))
+    return rc;
+  if (w->tan_nd == 0) {
+    const char* forced = std::getenv("ARGUS_TAN_ND");
+    int nd = forced ? std::atoi(forced) : 0;
+    if (ds->model == 1) nd = 2;
+    if (nd == 1 || nd == 2 || nd == 3 || nd == 6) {
+      w->tan_nd = nd;
+    } else {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      float best = 1e30f;
+      int pick = 6;
+      w->grad_log.clear();
+      for (int c : {6, 3, 2, 1}) {
+        float m = 1e30f;
+        for (int rep = 0; rep < 3 && rc == ARGUS_OK; ++rep) {
+          if (hipEventRecord(e0, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
+          if (!rc) rc = launch_tangent(ds, w, theta, c, st);
+          if (!rc) rc = grad_finish(ds, w, S, logl, grad, status, st);
+          if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
+          if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "sync");
+          float ms = 0;
+          if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "t");
+          if (rep > 0) m = std::min(m, ms);
+        }
+        if (rc) break;
+        char b[80];
+        std::snprintf(b, sizeof b, "tangent directions per wave %d: %.4f ms\n", c, m);
+        w->grad_log += b;
+        if (m < best) {
+          best = m;
+          pick = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (rc) return rc;
+      w->tan_nd = pick;
+    }
+  }
+  if ((rc = launch_tangent(ds, w, theta, w->tan_nd, st))) return rc;
+  return grad_finish(ds, w, S, logl, grad, status, st);
+}
+
 int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
                  int32_t* status, hipStream_t st) {
+  const char* mode = std::getenv("ARGUS_GRAD");
+  if (!(mode && std::strcmp(mode, "adjoint") == 0))
+    return tangent_loglike(ds, theta, S, logl, grad, status, st);
   int rc = ARGUS_OK;
   Workspace* w = get_workspace(ds, S, &rc);
   if (!w) return rc;
@@ -448,17 +812,7 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
   a.mc = ds->mc;
   hipLaunchKernelGGL(k_adjoint, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
   HIPCHK(hipGetLastError());
-  int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();
-  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, stat,
-               w->counter.as<int32_t>(), S, ds->P};
-  HIPCHK(launch_reduce(r, st));
-  const int blk = 256;
-  if (ds->D > 0)
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((S * ds->D + blk - 1) / blk)), dim3(blk), 0,
-                       st, w->gpart.as<double>(), stat, ds->icol.as<int32_t>(), grad, S, ds->D,
-                       ds->P, ds->model);
-  HIPCHK(hipGetLastError());
-  return ARGUS_OK;
+  return grad_finish(ds, w, S, logl, grad, status, st);
 }
 
 }  // namespace argus

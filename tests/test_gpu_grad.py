@@ -1,6 +1,7 @@
-"""Gradient of the batched likelihood (adjoint kernel) against the oracle's
-complex-step derivative and against central differences of the GPU
-likelihood. Tolerances: ||g - g_ref||_inf <= 1e-9 max(||g_ref||_inf, 1) per
+"""Gradient of the batched likelihood against the oracle's complex-step
+derivative and against central differences of the GPU likelihood, for both
+gradient sweeps (every test runs with the tangent sweep, the default, and
+with the reverse-mode adjoint). Tolerances: ||g - g_ref||_inf <= 1e-9 max(||g_ref||_inf, 1) per
 sample row and, per component, |g_j - g_ref,j| <= 1e-9 (|g_ref,j| +
 1e-3 ||g_ref||_inf); central differences (h = 1e-6): 1e-5 max(|g_j|, 1)."""
 import numpy as np
@@ -18,6 +19,15 @@ def argus():
         pytest.skip("no HIP device")
     import paper_2510_11077_amd as A
     return A
+
+
+@pytest.fixture(autouse=True, params=["tangent", "adjoint"])
+def sweep(request, monkeypatch):
+    if request.param == "adjoint":
+        monkeypatch.setenv("ARGUS_GRAD", "adjoint")
+    else:
+        monkeypatch.delenv("ARGUS_GRAD", raising=False)
+    return request.param
 
 
 @pytest.fixture(scope="module")
@@ -146,3 +156,16 @@ def test_grad_repeatable(argus):
     g1 = g1.clone()
     _, g2, _ = ds.loglike_grad(th)
     assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+
+
+@pytest.mark.parametrize("nd", ["1", "2", "3", "6"])
+def test_tangent_direction_splits(argus, orc, nd, sweep, monkeypatch):
+    """The tangent sweep with each split of the six directions over waves."""
+    if sweep != "tangent":
+        pytest.skip("tangent sweep only")
+    monkeypatch.setenv("ARGUS_TAN_ND", nd)
+    d = pi.make_pta("t", n_psr=4, counts=[90, 3, 0, 260], seed=51)
+    th = pi.sample_theta(d, 66, 17)
+    ll, g, st = argus.Dataset(d).loglike_grad(dev(th))
+    assert (st.cpu().numpy() == 0).all()
+    check_grad(g.cpu().numpy(), oracle_grad(orc, d, th))
