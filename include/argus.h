@@ -102,8 +102,16 @@ int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S,
 int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S,
                         double* logl, int32_t* status, void* stream);
 
-/* logL and its gradient w.r.t. the D free parameters (models 1, 2): reverse
- * (adjoint) Kalman sweep with checkpointed filter states. grad: dev [S*D]. */
+/* logL and its gradient w.r.t. the D free parameters (models 1, 2) (paper:
+ * Functionality, "Sampler Integration": samplers consume the likelihood and
+ * its gradient). grad: dev [S*D] row-major FP64, caller-owned; rows of
+ * failed samples (status != 0) are 0. By default a tangent (forward-mode)
+ * sweep carries the derivatives of the filter state along each parameter
+ * direction in one pass; the first call for a new S chooses, by timing, how
+ * many directions each wave carries (synchronises). With the environment
+ * variable ARGUS_GRAD=adjoint the reverse-mode sweep with checkpointed
+ * filter states is used instead; both give the derivative of the same
+ * recursion. Model 3 returns ARGUS_E_UNSUPPORTED. */
 int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
                        double* logl, double* grad, int32_t* status,
                        void* stream);
