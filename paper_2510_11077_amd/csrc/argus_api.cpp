@@ -521,19 +521,19 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
   if (!ds || !buf || len <= 0) return fail(ARGUS_E_INVAL, "bad argument");
   auto it = ds->ws.find(S);
   std::string s;
-  if (it == ds->ws.end() || !it->second->tuned) {
-    s = "not tuned";
+  const Workspace* w = it == ds->ws.end() ? nullptr : it->second.get();
+  char b[160];
+  if (!w || !w->tuned) {
+    s = "likelihood launch not tuned\n";
   } else {
-    const Workspace* w = it->second.get();
-    char b[160];
     std::snprintf(b, sizeof b, "chosen block=%d grid=%d dyn=%d order=%d items=%d\n",
                   w->cfg.block, w->cfg.grid, w->cfg.dynamic, w->cfg.order,
                   w->cfg.order == 1 ? w->n_items_bal : w->n_items);
     s = b + w->tune_log;
-    if (w->tan_nd) {
-      std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nd);
-      s += b + w->grad_log;
-    }
+  }
+  if (w && w->tan_nd) {
+    std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nd);
+    s += b + w->grad_log;
   }
   std::snprintf(buf, len, "%s", s.c_str());
   return ARGUS_OK;
