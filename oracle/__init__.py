@@ -5,7 +5,8 @@ CPU-baseline leg of the benchmark, never by the product path. It shares no
 code with the GPU library.
 
 * ``liboracle.so`` (argus_oracle.cpp): the Kalman recursion written out
-  densely in Joseph form, templated for complex-step gradients.
+  densely in Joseph form, templated for complex-step gradients, and the
+  Rauch-Tung-Striebel smoother on its filtered and predicted moments.
 * ``dense``: the same likelihood by its plain definition, log N(y; 0, C) with
   C built from closed-form covariance functions, used to pin the recursion.
 * ``mlp``: FP64 NumPy surrogate network with BF16 rounding emulation + Adam.
@@ -59,6 +60,8 @@ def lib():
         _lib.oracle_hd.argtypes = [P, C.c_int, P]
         _lib.oracle_common_variance.argtypes = [C.c_double, C.c_double, C.c_double]
         _lib.oracle_common_variance.restype = C.c_double
+        _lib.oracle_smooth_stream.argtypes = [P, P, C.c_int, P, P, P, P]
+        _lib.oracle_smooth.argtypes = [P, P, C.c_int64, P, P, P, C.c_int]
         _lib.oracle_n_canon.argtypes = [P]
         _lib.oracle_n_canon.restype = C.c_int
     return _lib
@@ -139,6 +142,38 @@ def trace(d, canon, q=0):
                        _ptr(r["Pf"]), _ptr(r["Pp"]), _ptr(ll), _ptr(st))
     r["ll"], r["status"] = float(ll[0]), int(st[0])
     return r
+
+
+def smooth(d, canon, nthreads=None):
+    """Rauch-Tung-Striebel smoothed moments of each TOA's own pulsar state
+    -> (mean [S, N, nc], var [S, N, nc], status [S]); nc = 2 (model 1) or 4
+    ([r, f, a, g]); NaN where that pulsar's filter failed."""
+    ds = _as_ds(d)
+    c = np.ascontiguousarray(np.atleast_2d(canon), np.float64)
+    assert c.shape[1] == ds.C
+    S, N = c.shape[0], int(ds.off[-1])
+    nc = 2 if ds.model == 1 else 4
+    mean = np.empty((S, N, nc))
+    var = np.empty((S, N, nc))
+    st = np.empty(S, np.int32)
+    lib().oracle_smooth(C.byref(ds.desc), _ptr(c), S, _ptr(mean), _ptr(var), _ptr(st),
+                        nthreads or default_threads())
+    return mean, var, st
+
+
+def smooth_stream(d, canon, q=0):
+    """Smoothed mean xs [N, n] and covariance Ps [N, n, n] of one filter's
+    full state, in stream order (pulsar q, or the joint merged stream)."""
+    ds = _as_ds(d)
+    c = np.ascontiguousarray(canon, np.float64).ravel()
+    N = int(ds.off[-1]) if ds.model == 3 else int(ds.off[q + 1] - ds.off[q])
+    n = ds.n
+    xs, Ps = np.empty((N, n)), np.empty((N, n, n))
+    ll = np.empty(1)
+    st = np.empty(1, np.int32)
+    lib().oracle_smooth_stream(C.byref(ds.desc), _ptr(c), q, _ptr(xs), _ptr(Ps), _ptr(ll),
+                               _ptr(st))
+    return dict(xs=xs, Ps=Ps, ll=float(ll[0]), status=int(st[0]))
 
 
 def merged_order(d):

@@ -118,3 +118,156 @@ def grad(d, c):
     for j, dC in parts.items():
         g[j] = 0.5 * (alpha @ dC @ alpha - np.sum(Ci * dC))
     return g
+
+
+def state_cross_cov(d, c):
+    """Prior covariances of the latent state at every TOA with every TOA's
+    residual: K [nc, N, N], K[m, k, j] = Cov(x_m(t_k) of TOA k's pulsar, y_j),
+    and the prior variances V [nc, N] of those state components. Components
+    [r, f, a, g] (model 1: [r, f]); from the same covariance functions as
+    covariance(), with the spin ones differentiated in the first time:
+      Cov(f(s), r(s')) = s_f^2 s' + sigma_s^2 (s <= s' ? s s' - s^2/2 : s'^2/2),
+      Var r(s) = s_r^2 + s_f^2 s^2 + sigma_s^2 s^3/3,  Var f(s) = s_f^2 + sigma_s^2 s."""
+    c = np.asarray(c, np.float64)
+    t = np.asarray(d.t, np.float64)
+    N = t.size
+    psr = np.repeat(np.arange(d.n_psr), np.diff(d.off))
+    same = (psr[:, None] == psr[None, :]).astype(np.float64)
+    ss2 = 10.0 ** (2 * c[0]) if d.model == 1 else d.sigma_s ** 2
+    tk, tj = t[:, None], t[None, :]
+    m = np.minimum(tk, tj)
+    M = np.maximum(tk, tj)
+    Kr = d.s_r ** 2 + d.s_f ** 2 * tk * tj + ss2 * m * m * (3 * M - m) / 6.0
+    Kf = d.s_f ** 2 * tj + ss2 * np.where(tk <= tj, tk * tj - 0.5 * tk * tk, 0.5 * tj * tj)
+    Vr = d.s_r ** 2 + d.s_f ** 2 * t * t + ss2 * t ** 3 / 3.0
+    Vf = d.s_f ** 2 + ss2 * t
+    if d.model == 1:
+        return np.stack([Kr * same, Kf * same]), np.stack([Vr, Vf])
+    P = d.n_psr
+    tau = np.abs(tk - tj)
+    gr = 10.0 ** c[1:4 * P:4]
+    vr = 10.0 ** (2 * c[0:4 * P:4]) / (2 * gr)
+    Ka = vr[psr][:, None] * np.exp(-gr[psr][:, None] * tau) * same
+    G = hd_closed_form(d.pos) if d.model == 3 else np.eye(P)
+    vc = common_var(c[4 * P], c[4 * P + 1], d.t_span)
+    Kg = vc * G[psr[:, None], psr[None, :]] * np.exp(-(2 * np.pi / d.t_span) * tau)
+    V = np.stack([Vr, Vf, vr[psr], vc * np.diag(G)[psr]])
+    return np.stack([Kr * same, Kf * same, Ka, Kg]), V
+
+
+def smooth(d, c):
+    """Posterior mean and variance of each TOA's own pulsar state given all
+    residuals, by Gaussian conditioning:
+        E[x | y] = K C^-1 y,  Var[x | y] = V - diag(K C^-1 K^T)
+    -> mean [N, nc], var [N, nc]."""
+    Cm = covariance(d, c)
+    y = np.asarray(d.y, np.float64)
+    cf = sla.cho_factor(Cm, lower=True)
+    alpha = sla.cho_solve(cf, y)
+    K, V = state_cross_cov(d, c)
+    mean = np.einsum("mkj,j->km", K, alpha)
+    var = np.empty_like(mean)
+    for m in range(K.shape[0]):
+        var[:, m] = V[m] - np.einsum("kj,jk->k", K[m], sla.cho_solve(cf, K[m].T))
+    return mean, var
+
+
+def noise_posterior(d, c):
+    """Posterior mean and variance of the white noise n = y - h.x at every
+    TOA: E[n | y] = R C^-1 y and Var[n | y] = R - R^2 diag(C^-1), R the
+    white variances (the same conditioning with Cov(n, y) = R)."""
+    Cm = covariance(d, c)
+    y = np.asarray(d.y, np.float64)
+    c = np.asarray(c, np.float64)
+    sig = np.asarray(d.sigma, np.float64)
+    if d.model == 1:
+        R = c[1] ** 2 * sig ** 2
+    else:
+        psr = np.repeat(np.arange(d.n_psr), np.diff(d.off))
+        R = c[4 * psr + 2] ** 2 * sig ** 2 + 10.0 ** (2 * c[4 * psr + 3])
+    cf = sla.cho_factor(Cm, lower=True)
+    Ci = sla.cho_solve(cf, np.eye(y.size))
+    return R * (Ci @ y), R - R * R * np.diag(Ci)
+
+
+def smooth_mp(d, c, dps=40):
+    """smooth() in mpmath arithmetic at dps decimal digits, for tiny inputs
+    whose posterior variances are many decades below the prior ones (in
+    fp64, V - diag(K C^-1 K^T) then cancels to a few digits). Covariance
+    functions as in covariance() and state_cross_cov(), evaluated at high
+    precision from the same fp64 inputs."""
+    import mpmath as mp
+    with mp.workdps(dps):
+        c = [mp.mpf(float(v)) for v in np.asarray(c, np.float64)]
+        t = [mp.mpf(float(v)) for v in d.t]
+        y = mp.matrix([mp.mpf(float(v)) for v in d.y])
+        sig = [mp.mpf(float(v)) for v in d.sigma]
+        N = len(t)
+        psr = np.repeat(np.arange(d.n_psr), np.diff(d.off))
+        sr, sf = mp.mpf(float(d.s_r)), mp.mpf(float(d.s_f))
+        if d.model == 1:
+            ss2 = mp.mpf(10) ** (2 * c[0])
+        else:
+            ss2 = mp.mpf(float(d.sigma_s)) ** 2
+            P = d.n_psr
+            gr = [mp.mpf(10) ** c[4 * q + 1] for q in range(P)]
+            vr = [mp.mpf(10) ** (2 * c[4 * q]) / (2 * gr[q]) for q in range(P)]
+            G = hd_closed_form(d.pos) if d.model == 3 else np.eye(P)
+            A, gam = c[4 * P], c[4 * P + 1]
+            fyr, T = 1 / mp.mpf(YEAR), mp.mpf(float(d.t_span))
+            vc = mp.mpf(10) ** (2 * A) * fyr ** (gam - 3) * T ** (gam - 1) / (
+                12 * mp.pi ** 2 * (gam - 1))
+            lam = 2 * mp.pi / T
+
+        def k_spin(a, b):  # Cov(r(a), r(b)), Cov(f(a), r(b))
+            mn, mx = min(a, b), max(a, b)
+            kr = sr ** 2 + sf ** 2 * a * b + ss2 * mn * mn * (3 * mx - mn) / 6
+            kf = sf ** 2 * b + ss2 * (a * b - a * a / 2 if a <= b else b * b / 2)
+            return kr, kf
+
+        nc = 2 if d.model == 1 else 4
+        K = [mp.matrix(N, N) for _ in range(nc)]
+        Cm = mp.matrix(N, N)
+        for i in range(N):
+            for j in range(N):
+                pi_, pj = int(psr[i]), int(psr[j])
+                comp = [mp.mpf(0)] * nc
+                if pi_ == pj:
+                    comp[0], comp[1] = k_spin(t[i], t[j])
+                if d.model != 1:
+                    tau = abs(t[i] - t[j])
+                    if pi_ == pj:
+                        comp[2] = vr[pi_] * mp.exp(-gr[pi_] * tau)
+                    comp[3] = vc * mp.mpf(float(G[pi_, pj])) * mp.exp(-lam * tau)
+                for m in range(nc):
+                    K[m][i, j] = comp[m]
+                # y = r + a + g + white: Cov(y_i, y_j) = Cov(r_i + a_i + g_i, y_j)
+                Cm[i, j] = comp[0] + (comp[2] + comp[3] if d.model != 1 else 0)
+            pq = int(psr[i])
+            if d.model == 1:
+                Cm[i, i] += c[1] ** 2 * sig[i] ** 2
+            else:
+                Cm[i, i] += c[4 * pq + 2] ** 2 * sig[i] ** 2 + mp.mpf(10) ** (2 * c[4 * pq + 3])
+        Ci = mp.inverse(Cm)
+        alpha = Ci * y
+        mean = np.empty((N, nc))
+        var = np.empty((N, nc))
+        for m in range(nc):
+            km = K[m] * alpha
+            W = K[m] * Ci
+            for k in range(N):
+                pq = int(psr[k])
+                if m == 0:
+                    v0 = sr ** 2 + sf ** 2 * t[k] ** 2 + ss2 * t[k] ** 3 / 3
+                elif m == 1:
+                    v0 = sf ** 2 + ss2 * t[k]
+                elif m == 2:
+                    v0 = vr[pq]
+                else:
+                    v0 = vc * mp.mpf(float(G[pq, pq]))
+                s = mp.mpf(0)
+                for j in range(N):
+                    s += W[k, j] * K[m][k, j]
+                mean[k, m] = float(km[k])
+                var[k, m] = float(v0 - s)
+        return mean, var
