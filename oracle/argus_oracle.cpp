@@ -694,9 +694,12 @@ int oracle_smooth_stream(const oracle_ds* o, const double* c, int q, double* xs,
 
 // Smoothed mean and variance of the emitting pulsar's own state components
 // at every TOA, for S canonical vectors c [S x C]: mean, var [S x N x nc]
-// in dataset TOA order, nc = 2 (model 1) or 4. Entries of a pulsar whose
-// filter fails for a sample (and of every pulsar when a parameter is
-// non-finite) are NaN; status [S] takes the first failure in pulsar order.
+// in dataset TOA order, nc = 2 (model 1) or 4. The entries of a filter that
+// fails are NaN: per pulsar in the per-pulsar models (its innovation
+// variance not positive, or a non-finite parameter among its own four and
+// the two common ones), all of them in the joint model. status [S] as for
+// the likelihood: NONFINITE for a non-finite parameter anywhere in the row,
+// else the first failure in pulsar order.
 int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, double* var,
                   int32_t* status, int nthreads) {
   DS d = make_ds(o);
@@ -706,15 +709,21 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
   parallel_for(S, nthreads, [&](int64_t s) {
     double* ms = mean + s * Nt * nc;
     double* vs = var + s * Nt * nc;
+    const double* cs = c + s * C;
     int32_t sst = 0;
     const double nan = std::numeric_limits<double>::quiet_NaN();
-    if (!finite_params(c + s * C, C)) {
+    const bool row_finite = finite_params(cs, C);
+    if (!row_finite && d.model != M_PSR4) {
       std::fill(ms, ms + Nt * nc, nan);
       std::fill(vs, vs + Nt * nc, nan);
       status[s] = S_NONFINITE;
       return;
     }
-    Par<double> p = make_par<double>(d, c + s * C);
+    // non-finite entries only reach the pulsars that read them
+    std::vector<double> cf(cs, cs + C);
+    for (double& v : cf)
+      if (!std::isfinite(v)) v = 0.0;
+    Par<double> p = make_par<double>(d, cf.data());
     if (d.model == M_JOINT) {
       const int n = 4 * d.P;
       const int64_t N = (int64_t)d.m_idx.size();
@@ -731,9 +740,12 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
     } else {
       for (int q = 0; q < d.P; ++q) {
         const int64_t b = d.off[q], N = d.off[q + 1] - b;
-        std::vector<double> xs(N * nc), Ps(N * nc * nc);
+        std::vector<double> xs(N * nc, nan), Ps(N * nc * nc, nan);
         int32_t qs = 0;
-        smooth_stream(d, p, q, xs.data(), Ps.data(), &qs);
+        if (d.model == M_PSR4 && !(finite_params(cs + 4 * q, 4) && finite_params(cs + 4 * d.P, 2)))
+          qs = S_NONFINITE;
+        else
+          smooth_stream(d, p, q, xs.data(), Ps.data(), &qs);
         if (qs && !sst) sst = qs;
         for (int64_t k = 0; k < N; ++k)
           for (int a = 0; a < nc; ++a) {
@@ -742,7 +754,7 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
           }
       }
     }
-    status[s] = sst;
+    status[s] = row_finite ? sst : S_NONFINITE;
   });
   return 0;
 }

@@ -117,13 +117,15 @@ def test_last_toa_is_filtered_and_smoothing_shrinks_variance(oracle_mod):
 def test_failed_filters_give_nan(oracle_mod):
     d = pta([10, 12, 8], seed=34)
     th = np.tile(d.truth, (3, 1))
-    th[1, 5] = np.nan  # a parameter of pulsar 1: the whole sample fails
+    th[1, 5] = np.nan   # a parameter of pulsar 1: only its entries fail
+    th[2, -1] = np.inf  # the common gamma: every pulsar fails
     dz = pta([6, 7], seed=48)
     dz.s_r = dz.s_f = dz.sigma_s = 0.0
     m, v, st = oracle_mod.smooth(d, d.to_canon(th))
-    assert list(st) == [0, 2, 0]
-    assert np.isnan(m[1]).all() and np.isnan(v[1]).all()
-    assert np.isfinite(m[[0, 2]]).all() and np.isfinite(v[[0, 2]]).all()
+    assert list(st) == [0, 2, 2]
+    assert np.isnan(m[1, 10:22]).all() and np.isnan(v[1, 10:22]).all()
+    assert np.isfinite(m[1, :10]).all() and np.isfinite(v[1, 22:]).all()
+    assert np.isnan(m[2]).all() and np.isfinite(m[0]).all() and np.isfinite(v[0]).all()
     # every variance zero in pulsar 0 only: that pulsar's entries are NaN
     z = np.tile(dz.truth, (2, 1))
     z[0, [0, 2, 3]] = [-400.0, 0.0, -400.0]
