@@ -116,6 +116,26 @@ int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
                        double* logl, double* grad, int32_t* status,
                        void* stream);
 
+/* Smoothed latent states (models 1, 2): for every TOA k of every pulsar and
+ * every sample s, the posterior mean and variance of that pulsar's state
+ * components at t_k given all of its TOAs (paper: Summary and Statement of
+ * Need: the filter tracks the realised, time-ordered noise; the fixed-interval
+ * smoother completes it with the later data). Components c: r, f, a, g
+ * (nc = 4) for model 2; r, f (nc = 2) for model 1.
+ *   mean: dev [N*nc*S] FP64, element ((k*nc + c)*S + s), k the dataset's
+ *         global TOA index (pulsar-major CSR order)
+ *   var:  dev, same layout, or NULL for means only
+ *   logl, status: dev [S] or NULL, as argus_loglike
+ * The entries of a pulsar whose filter fails for a sample (innovation
+ * variance not positive, or a non-finite parameter among its own and the
+ * common ones) are NaN. Computed from the reverse sweep of the checkpointed
+ * adjoint gradient, no matrix inverse: E[x|y] = x + P xb and Cov[x|y] = P +
+ * P (2M - xb xb^T) P with (x, P) filtered and (xb, M) the adjoints of logL
+ * with respect to them. Model 3 returns ARGUS_E_UNSUPPORTED; N*4*S above
+ * 2^40 elements returns ARGUS_E_UNSUPPORTED. */
+int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
+                 double* var, double* logl, int32_t* status, void* stream);
+
 /* ---------------------------------------------------------------------
  * Learned surrogate of logL (an MLP d -> w -> w -> w -> 1, SiLU hidden
  * layers) and delayed-acceptance screening with the exact filter as judge

@@ -44,6 +44,7 @@ _lib.argus_dataset_n_params.argtypes = [_V, C.POINTER(C.c_int32)]
 for _n in ("argus_loglike", "argus_loglike_terms", "argus_loglike_plain"):
     getattr(_lib, _n).argtypes = [_V, _V, C.c_int64, _V, _V, _V]
 _lib.argus_loglike_grad.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V]
+_lib.argus_smooth.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V, _V]
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
 _lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)]
 _lib.argus_mlp_destroy.argtypes = [_V]
@@ -92,6 +93,7 @@ class Dataset:
     def __init__(self, d):
         self.model = int(d.model)
         self.n_psr = int(d.n_psr)
+        self.n_toa = int(np.asarray(d.off)[-1])
         self._keep = dict(
             off=np.ascontiguousarray(d.off, np.int64),
             t=np.ascontiguousarray(d.t, np.float64),
@@ -180,6 +182,29 @@ class Dataset:
                                        _dev_ptr(grad, torch.float64, "grad"), status.data_ptr(),
                                        _stream(stream)))
         return out, grad, status
+
+    def smooth(self, theta, mean=None, var=None, want_var=True, stream=None):
+        """Smoothed latent states (models 1, 2): posterior mean and variance
+        of each TOA's own pulsar state given all its TOAs, mean/var
+        [N, nc, S] float64 (nc = 2 for model 1, 4 for model 2: r, f, a, g),
+        plus logl [S] and status [S]."""
+        import torch
+        tp = self._theta(theta)
+        S = theta.shape[0]
+        nc = 2 if self.model == M1_SPIN else 4
+        shape = (self.n_toa, nc, S)
+        if mean is None:
+            mean = torch.empty(shape, dtype=torch.float64, device=theta.device)
+        if var is None and want_var:
+            var = torch.empty(shape, dtype=torch.float64, device=theta.device)
+        for name, t in (("mean", mean), ("var", var)):
+            if t is not None and tuple(t.shape) != shape:
+                raise ArgusError("%s must be %s" % (name, shape))
+        out, status = self._outs(theta, None, None, True)
+        _check(_lib.argus_smooth(self._h, tp, S, _dev_ptr(mean, torch.float64, "mean"),
+                                 _dev_ptr(var, torch.float64, "var"), out.data_ptr(),
+                                 status.data_ptr(), _stream(stream)))
+        return mean, var, out, status
 
     def tune_info(self, S: int) -> str:
         buf = C.create_string_buffer(4096)

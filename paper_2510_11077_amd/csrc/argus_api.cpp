@@ -549,3 +549,14 @@ extern "C" int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64
     return fail(ARGUS_E_UNSUPPORTED, "the gradient covers models 1 and 2");
   return grad_loglike(ds, theta, S, logl, grad, status, (hipStream_t)stream);
 }
+
+extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
+                            double* var, double* logl, int32_t* status, void* stream) {
+  int rc = check_call(ds, theta, S, mean);
+  if (rc || S == 0) return rc;
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "the smoother covers models 1 and 2");
+  if (ds->N > 0 && (uint64_t)ds->N * 4 * (uint64_t)S > ((uint64_t)1 << 40))
+    return fail(ARGUS_E_UNSUPPORTED, "N * S too large for one call");
+  return smooth_states(ds, theta, S, mean, var, logl, status, (hipStream_t)stream);
+}

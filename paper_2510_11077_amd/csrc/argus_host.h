@@ -106,4 +106,6 @@ int joint_loglike(argus_dataset* ds, const double* theta, int64_t S, double* log
                   int32_t* status, hipStream_t st);
 int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
                  int32_t* status, hipStream_t st);
+int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mean, double* var,
+                  double* logl, int32_t* status, hipStream_t st);
 }  // namespace argus

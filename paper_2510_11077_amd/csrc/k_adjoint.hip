@@ -1,7 +1,11 @@
 // Gradient of the batched per-pulsar log-likelihood by a hand-written
 // adjoint (reverse-mode) Kalman sweep. The paper's samplers consume the
 // likelihood and its gradient (Functionality, "Sampler Integration"); here
-// the gradient is the exact derivative of the same recursion.
+// the gradient is the exact derivative of the same recursion. The same
+// sweep, with the adjoints of each filtered state turned into that state's
+// posterior given all TOAs, is the fixed-interval smoother of the latent
+// noise (the filter tracking the realised noise: Summary, Statement of
+// Need).
 //
 // Per TOA the forward map is (x, P) -> (x+, P+) with
 //   x- = F x, P- = F P F^T + Q, e = y - h.x-, u = P- h, S = h.u + R,
@@ -74,8 +78,10 @@ struct AdjArgs {
   double* part;             // [P*S] log-likelihood terms
   int32_t* pstat;           // [P*S]
   double* gpart;            // [P * 6 * S] per-pulsar parameter gradients
+  double* smean;            // smoothing: [N * nc * S] posterior means
+  double* svar;             // smoothing: [N * nc * S] posterior variances, or null
   int64_t S, tot_seg;
-  int32_t D, P, n_items, max_sub, model;
+  int32_t D, P, n_items, max_sub, model, nc;
   ModelConst mc;
 };
 
@@ -135,27 +141,40 @@ __device__ __forceinline__ void fwd_step(State& s, const TOARec& r, const LaneP&
   const double uf = p.P.rf + p.P.fa + p.P.fg;
   const double ua = p.P.ra + p.P.aa + p.P.ag;
   const double ug = p.P.rg + p.P.ag + p.P.gg;
-  S = (ur + ua + ug) + fma(L.efac2, r.s2, L.equad2);
+  const double R = fma(L.efac2, r.s2, L.equad2);
+  S = (ur + ua + ug) + R;
   inv = rcp_nr(S);
   const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
   s.xr = fma(kr, e, p.xr);
   s.xf = fma(kf, e, p.xf);
   s.xa = fma(ka, e, p.xa);
   s.xg = fma(kg, e, p.xg);
-  const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
-  const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug);
-  Cov4 P = p.P;
-  JOSEPH(P.rr, kr, ur, dr, kr);
-  JOSEPH(P.rf, kr, uf, dr, kf);
-  JOSEPH(P.ff, kf, uf, df, kf);
-  JOSEPH(P.ra, kr, ua, dr, ka);
-  JOSEPH(P.fa, kf, ua, df, ka);
-  JOSEPH(P.aa, ka, ua, da, ka);
-  JOSEPH(P.rg, kr, ug, dr, kg);
-  JOSEPH(P.fg, kf, ug, df, kg);
-  JOSEPH(P.ag, ka, ug, da, kg);
-  JOSEPH(P.gg, kg, ug, dg, kg);
-  s.P = P;
+  // Joseph form (I - k h^T) P- (I - k h^T)^T + R k k^T, evaluated as
+  // W = P- - k u^T, z = R k - W h, P+ = W + z k^T. Regrouping it to
+  // P- - k u^T + (S k - u) k^T (exact at the computed k) would lose the
+  // low digits of R inside the rounded S = h.u + R: after a long gap, when
+  // h.u >> R, the observed variance then carries a relative error of
+  // eps h.u / R. Here the rounding of W enters W h as well and is damped by
+  // the factor R / S.
+  const double wrr = fma(-kr, ur, p.P.rr), wra = fma(-kr, ua, p.P.ra), wrg = fma(-kr, ug, p.P.rg);
+  const double wfr = fma(-kf, ur, p.P.rf), wfa = fma(-kf, ua, p.P.fa), wfg = fma(-kf, ug, p.P.fg);
+  const double war = fma(-ka, ur, p.P.ra), waa = fma(-ka, ua, p.P.aa), wag = fma(-ka, ug, p.P.ag);
+  const double wgr = fma(-kg, ur, p.P.rg), wga = fma(-kg, ua, p.P.ag), wgg = fma(-kg, ug, p.P.gg);
+  const double wrf = fma(-kr, uf, p.P.rf), wff = fma(-kf, uf, p.P.ff);
+  const double zr = fma(R, kr, -((wrr + wra) + wrg));
+  const double zf = fma(R, kf, -((wfr + wfa) + wfg));
+  const double za = fma(R, ka, -((war + waa) + wag));
+  const double zg = fma(R, kg, -((wgr + wga) + wgg));
+  s.P.rr = fma(zr, kr, wrr);
+  s.P.rf = fma(zr, kf, wrf);
+  s.P.ff = fma(zf, kf, wff);
+  s.P.ra = fma(zr, ka, wra);
+  s.P.fa = fma(zf, ka, wfa);
+  s.P.aa = fma(za, ka, waa);
+  s.P.rg = fma(zr, kg, wrg);
+  s.P.fg = fma(zf, kg, wfg);
+  s.P.ag = fma(za, kg, wag);
+  s.P.gg = fma(zg, kg, wgg);
 }
 
 __device__ __forceinline__ void fwd_only(State& s, const TOARec& r, const LaneP& L) {
@@ -228,11 +247,58 @@ __device__ __forceinline__ void rev_step(const State& sp, const TOARec& r, const
   M.gg = (phc * phc) * Mm.gg;
 }
 
+// Smoothed moments at one TOA from the filtered state f after it and the
+// adjoints (xb, M) of that state, i.e. the derivatives of the total
+// log-likelihood with respect to the filtered mean and covariance. For a
+// Gaussian N(x; m, P) that the later data reweight, d log Z / dm = P^-1 (mu - m)
+// and d log Z / dP = 1/2 P^-1 (Sigma + (mu - m)(mu - m)^T - P) P^-1, so
+//   E[x | y] = x + P xb,   Cov[x | y] = P + P (2 M - xb xb^T) P
+// (the Bryson-Frazier form of the fixed-interval smoother; no inverse).
+// Writes the first nc components of the mean and the variance diagonal
+// at entry ((k * nc + c) * S + s); NaN when the filter failed.
+__device__ __forceinline__ void put_smooth(const AdjArgs& a, int64_t k, int64_t s,
+                                           const State& f, const double xb[4], const Cov4& M,
+                                           bool bad) {
+  const double P[4][4] = {{f.P.rr, f.P.rf, f.P.ra, f.P.rg},
+                          {f.P.rf, f.P.ff, f.P.fa, f.P.fg},
+                          {f.P.ra, f.P.fa, f.P.aa, f.P.ag},
+                          {f.P.rg, f.P.fg, f.P.ag, f.P.gg}};
+  const double B[4][4] = {{2.0 * M.rr - xb[0] * xb[0], 2.0 * M.rf - xb[0] * xb[1],
+                           2.0 * M.ra - xb[0] * xb[2], 2.0 * M.rg - xb[0] * xb[3]},
+                          {2.0 * M.rf - xb[1] * xb[0], 2.0 * M.ff - xb[1] * xb[1],
+                           2.0 * M.fa - xb[1] * xb[2], 2.0 * M.fg - xb[1] * xb[3]},
+                          {2.0 * M.ra - xb[2] * xb[0], 2.0 * M.fa - xb[2] * xb[1],
+                           2.0 * M.aa - xb[2] * xb[2], 2.0 * M.ag - xb[2] * xb[3]},
+                          {2.0 * M.rg - xb[3] * xb[0], 2.0 * M.fg - xb[3] * xb[1],
+                           2.0 * M.ag - xb[3] * xb[2], 2.0 * M.gg - xb[3] * xb[3]}};
+  const double x[4] = {f.xr, f.xf, f.xa, f.xg};
+  double* mo = a.smean + k * a.nc * a.S + s;
+  double* vo = a.svar ? a.svar + k * a.nc * a.S + s : nullptr;
+  const double nan = __builtin_nan("");
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (c >= a.nc) break;
+    double m = x[c], v = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      m = fma(P[c][i], xb[i], m);
+      double bp = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bp = fma(B[i][j], P[j][c], bp);
+      v = fma(P[c][i], bp, v);
+    }
+    mo[c * a.S] = bad ? nan : m;
+    if (vo) vo[c * a.S] = bad ? nan : P[c][c] + v;
+  }
+}
+
 __device__ __forceinline__ double prm(const AdjArgs& a, int c, int64_t s) {
   const int j = a.col[c];
   return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
 }
 
+// SMOOTH: write the smoothed moments of every TOA instead of the gradient.
+template <bool SMOOTH>
 __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int gwave = __builtin_amdgcn_readfirstlane(
@@ -311,6 +377,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     double xb[4] = {0.0, 0.0, 0.0, 0.0};
     Cov4 M{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     Grad G{0, 0, 0, 0, 0, 0};
+    // the last TOA's smoothed moments are its filtered ones
+    if (SMOOTH && valid && N > 0) put_smooth(a, kb + N - 1, s, st, xb, M, stat != 0);
     const int64_t nseg = (N + c1 - 1) / c1;
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
       const int64_t k0 = sg * c1;
@@ -338,6 +406,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
           State cur = s0;
           for (int j = 0; j < i; ++j) fwd_only(cur, load_rec(rec, kk + j), L);
           rev_step(cur, load_rec(rec, kk + i), L, xb, M, G);
+          // (xb, M) are now the adjoints of the filtered state after TOA ks + i - 1
+          if (SMOOTH && valid && ks + i > 0) put_smooth(a, kk + i - 1, s, cur, xb, M, stat != 0);
         }
       }
     }
@@ -348,6 +418,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     if (valid) {
       a.part[(int64_t)p * a.S + s] = ll;
       a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+    if (valid && !SMOOTH) {
       double* g = a.gpart + (int64_t)p * 6 * a.S + s;
       if (a.model == 1) {
         g[0] = G.ss2 * 2.0 * kLn10 * L.ss2;  // log10 sigma_s
@@ -749,44 +821,44 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
   return grad_finish(ds, w, S, logl, grad, status, st);
 }
 
-int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
-                 int32_t* status, hipStream_t st) {
-  const char* mode = std::getenv("ARGUS_GRAD");
-  if (!(mode && std::strcmp(mode, "adjoint") == 0))
-    return tangent_loglike(ds, theta, S, logl, grad, status, st);
-  int rc = ARGUS_OK;
-  Workspace* w = get_workspace(ds, S, &rc);
-  if (!w) return rc;
+namespace {
+
+// Checkpoint layout of the reverse sweep for one sample count: level-1
+// strides ceil(sqrt(N_p)) rounded up to a multiple of 4, segment offsets,
+// the level-1 store and the per-wave level-2 scratch.
+int adjoint_setup(argus_dataset* ds, Workspace* w, int64_t S) {
+  if (w->grad_ready) return ARGUS_OK;
   const int64_t tiles = (S + kWave - 1) / kWave;
-  if (!w->grad_ready) {
-    // level-1 strides and segment offsets
-    std::vector<int32_t> c1(ds->P);
-    std::vector<int64_t> base(ds->P);
-    int64_t tot = 0;
-    int cmax = 4;
-    for (int p = 0; p < ds->P; ++p) {
-      const int64_t n = ds->counts[p];
-      int64_t r = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1)));
-      r = ((r + 3) / 4) * 4;
-      c1[p] = (int32_t)r;
-      cmax = std::max<int>(cmax, (int)r);
-      base[p] = tot;
-      tot += (n + r - 1) / r;
-    }
-    w->tot_seg = tot;
-    w->max_sub = cmax / 4;
-    w->grad_waves = (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu);
-    w->grad_waves = ((w->grad_waves + 3) / 4) * 4;
-    if ((rc = w->c1.upload(c1.data(), c1.size() * sizeof(int32_t))) ||
-        (rc = w->seg_base.upload(base.data(), base.size() * sizeof(int64_t))) ||
-        (rc = w->ckpt.alloc((size_t)std::max<int64_t>(tiles * tot, 1) * kFields * kWave *
-                            sizeof(double))) ||
-        (rc = w->scratch.alloc((size_t)w->grad_waves * w->max_sub * kFields * kWave *
-                               sizeof(double))) ||
-        (rc = w->gpart.alloc((size_t)ds->P * 6 * S * sizeof(double))))
-      return rc;
-    w->grad_ready = true;
+  std::vector<int32_t> c1(ds->P);
+  std::vector<int64_t> base(ds->P);
+  int64_t tot = 0;
+  int cmax = 4;
+  for (int p = 0; p < ds->P; ++p) {
+    const int64_t n = ds->counts[p];
+    int64_t r = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(n, 1)));
+    r = ((r + 3) / 4) * 4;
+    c1[p] = (int32_t)r;
+    cmax = std::max<int>(cmax, (int)r);
+    base[p] = tot;
+    tot += (n + r - 1) / r;
   }
+  w->tot_seg = tot;
+  w->max_sub = cmax / 4;
+  w->grad_waves = (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu);
+  w->grad_waves = ((w->grad_waves + 3) / 4) * 4;
+  int rc;
+  if ((rc = w->c1.upload(c1.data(), c1.size() * sizeof(int32_t))) ||
+      (rc = w->seg_base.upload(base.data(), base.size() * sizeof(int64_t))) ||
+      (rc = w->ckpt.alloc((size_t)std::max<int64_t>(tiles * tot, 1) * kFields * kWave *
+                          sizeof(double))) ||
+      (rc = w->scratch.alloc((size_t)w->grad_waves * w->max_sub * kFields * kWave *
+                             sizeof(double))))
+    return rc;
+  w->grad_ready = true;
+  return ARGUS_OK;
+}
+
+AdjArgs adjoint_args(argus_dataset* ds, Workspace* w, const double* theta, int64_t S) {
   AdjArgs a{};
   a.rec = ds->rec.as<TOARec>();
   a.off = ds->off.as<int64_t>();
@@ -801,7 +873,6 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
   a.scratch = w->scratch.as<double>();
   a.part = w->part.as<double>();
   a.pstat = w->pstat.as<int32_t>();
-  a.gpart = w->gpart.as<double>();
   a.S = S;
   a.tot_seg = w->tot_seg;
   a.D = ds->D;
@@ -809,10 +880,50 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
   a.n_items = w->n_items;
   a.max_sub = w->max_sub;
   a.model = ds->model;
+  a.nc = ds->model == 1 ? 2 : 4;
   a.mc = ds->mc;
-  hipLaunchKernelGGL(k_adjoint, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+  return a;
+}
+
+}  // namespace
+
+int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
+                 int32_t* status, hipStream_t st) {
+  const char* mode = std::getenv("ARGUS_GRAD");
+  if (!(mode && std::strcmp(mode, "adjoint") == 0))
+    return tangent_loglike(ds, theta, S, logl, grad, status, st);
+  int rc = ARGUS_OK;
+  Workspace* w = get_workspace(ds, S, &rc);
+  if (!w) return rc;
+  if ((rc = adjoint_setup(ds, w, S))) return rc;
+  if (w->gpart.p == nullptr && (rc = w->gpart.alloc((size_t)ds->P * 6 * S * sizeof(double))))
+    return rc;
+  AdjArgs a = adjoint_args(ds, w, theta, S);
+  a.gpart = w->gpart.as<double>();
+  hipLaunchKernelGGL(k_adjoint<false>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
   HIPCHK(hipGetLastError());
   return grad_finish(ds, w, S, logl, grad, status, st);
+}
+
+// Smoothed latent states: the adjoint sweep with the per-TOA moments written
+// in place of the gradient.
+int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mean, double* var,
+                  double* logl, int32_t* status, hipStream_t st) {
+  int rc = ARGUS_OK;
+  Workspace* w = get_workspace(ds, S, &rc);
+  if (!w) return rc;
+  if ((rc = adjoint_setup(ds, w, S))) return rc;
+  AdjArgs a = adjoint_args(ds, w, theta, S);
+  a.smean = mean;
+  a.svar = var;
+  hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+  HIPCHK(hipGetLastError());
+  double* ll = logl ? logl : w->logl_tmp.as<double>();
+  int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();
+  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), ll, stat, w->counter.as<int32_t>(),
+               S, ds->P};
+  HIPCHK(launch_reduce(r, st));
+  return ARGUS_OK;
 }
 
 }  // namespace argus

@@ -135,3 +135,25 @@ def test_failed_filters_give_nan(oracle_mod):
     assert np.isnan(m[0, :6]).all() and np.isfinite(m[0, 6:]).all()
     # deterministic spin states (zero prior, no spin noise) smooth to exactly 0
     assert (m[1, :, :2] == 0).all() and (v[1, :, :2] == 0).all()
+
+
+def test_spin_noise_after_a_long_gap(oracle_mod):
+    """The regime where a plain covariance update loses digits: the
+    strongest spin noise of the prior and a gap of about 800 days, after
+    which the predicted residual variance exceeds the white variance by
+    about 13 decades. The smoother must still match 40-digit conditioning."""
+    import dataclasses
+    from oracle import dense
+    d = spin(n=200, seed=9)
+    keep = np.r_[0:25, 75:100]
+    d = dataclasses.replace(d, t=d.t[keep], y=d.y[keep], sigma=d.sigma[keep],
+                            off=np.array([0, keep.size], np.int64))
+    c = np.array([[d.hi[0], 1.0], [d.hi[0] - 0.5, 0.9]])
+    m, v, st = oracle_mod.smooth(d, c)
+    assert (st == 0).all()
+    tr = oracle_mod.trace(d, c[0])
+    assert tr["S"].max() / (c[0, 1] * d.sigma.min()) ** 2 > 1e12
+    for s in range(len(c)):
+        em, ev = dense.smooth_mp(d, c[s])
+        assert err_mean(m[s], em, ev) < 1e-11
+        assert err_var(v[s], ev) < 1e-11
