@@ -353,6 +353,36 @@ def main():
             log("grad tune: " + ds.tune_info(S4).replace("\n", " | "))
         except A.ArgusError as e:
             extra["grad_47psr_1024samples"] = "unavailable: %s" % e
+
+        # smoothed latent states of every TOA, same data and samples
+        try:
+            nc = 4
+            sm = torch.empty((d.n_toa, nc, S4), dtype=torch.float64, device=dev)
+            sv = torch.empty_like(sm)
+            ds.smooth(t4, sm, sv)
+            ms5, _ = timed(lambda: ds.smooth(t4, sm, sv), 5, 1, stream)
+            out_bytes = 2 * sm.numel() * 8
+            leg = {"ms_per_call": ms5, "samples_per_s": S4 / (ms5 * 1e-3),
+                   "toa_states_per_s": d.n_toa * S4 / (ms5 * 1e-3),
+                   "output_GB": out_bytes / 1e9,
+                   "output_write_GB_per_s": out_bytes / (ms5 * 1e-3) / 1e9}
+            log("smooth: %.3f ms/call, %.4g TOA-states/s, %.1f GB/s of output"
+                % (ms5, leg["toa_states_per_s"], leg["output_write_GB_per_s"]))
+            if not args.no_cpu:
+                import oracle
+                oracle.build()
+                n5 = 32
+                c5 = d.to_canon(t4[:n5].cpu().numpy())
+                t0 = time.perf_counter()
+                oracle.smooth(d, c5, nthreads=oracle.default_threads())
+                w5 = time.perf_counter() - t0
+                leg["cpu_oracle_samples_per_s"] = n5 / w5
+                leg["cpu_oracle_sample"] = ("first %d samples, RTS on the dense Joseph-form "
+                                            "filter, %d threads" % (n5, oracle.default_threads()))
+            extra["smooth_47psr_1024samples"] = leg
+            del sm, sv
+        except A.ArgusError as e:
+            extra["smooth_47psr_1024samples"] = "unavailable: %s" % e
         extra["surrogate_10psr_10param"] = surrogate_leg(A, pi, dev, stream, log)
     res["extra"] = extra
 
