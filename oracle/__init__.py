@@ -62,6 +62,7 @@ def lib():
         _lib.oracle_common_variance.restype = C.c_double
         _lib.oracle_smooth_stream.argtypes = [P, P, C.c_int, P, P, P, P]
         _lib.oracle_smooth.argtypes = [P, P, C.c_int64, P, P, P, C.c_int]
+        _lib.oracle_scan_filter.argtypes = [P, P, C.c_int, C.c_int, C.c_int, P, P, P]
         _lib.oracle_n_canon.argtypes = [P]
         _lib.oracle_n_canon.restype = C.c_int
     return _lib
@@ -174,6 +175,22 @@ def smooth_stream(d, canon, q=0):
     lib().oracle_smooth_stream(C.byref(ds.desc), _ptr(c), q, _ptr(xs), _ptr(Ps), _ptr(ll),
                                _ptr(st))
     return dict(xs=xs, Ps=Ps, ll=float(ll[0]), status=int(st[0]))
+
+
+def scan_filter(d, canon, q=0, order=0, nchunk=1):
+    """Filtered moments of pulsar q by the associative scan (per-pulsar
+    models) in evaluation order 0 (left fold), 1 (recursive doubling) or 2
+    (nchunk chunks) -> dict xs [N, n], Ps [N, n, n], ll."""
+    ds = _as_ds(d)
+    assert ds.model != 3
+    c = np.ascontiguousarray(canon, np.float64).ravel()
+    N = int(ds.off[q + 1] - ds.off[q])
+    n = ds.n
+    xs, Ps = np.empty((N, n)), np.empty((N, n, n))
+    ll = np.empty(1)
+    lib().oracle_scan_filter(C.byref(ds.desc), _ptr(c), q, order, nchunk, _ptr(xs), _ptr(Ps),
+                             _ptr(ll))
+    return dict(xs=xs, Ps=Ps, ll=float(ll[0]))
 
 
 def merged_order(d):

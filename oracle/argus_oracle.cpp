@@ -566,6 +566,205 @@ void parallel_for(int64_t S, int nthreads, F f) {
   for (auto& x : th) x.join();
 }
 
+// ------------------------------------------------------ parallel-in-time
+// The filter as an associative scan (Sarkka & Garcia-Fernandez 2021). Step k
+// is summarised by an element (A, b, C, eta, J): given the filtered state
+// x_{k-1}, x_k ~ N(A x_{k-1} + b, C) after y_k, and y_k's likelihood as a
+// function of x_{k-1} is proportional to exp(eta^T x - x^T J x / 2). With
+// S = h Q h^T + R, K = Q h^T / S:
+//   A = (I - K h) F,  b = K y,  C = (I - K h) Q,
+//   eta = F^T h^T y / S,  J = F^T h^T h F / S;
+// the first step folds in the prior: A = 0, b and C its filtered mean and
+// covariance, eta = 0, J = 0. Two elements compose as (i then j)
+//   A  = A_j T A_i,              T = (I + C_i J_j)^-1,
+//   b  = A_j T (b_i + C_i eta_j) + b_j,
+//   C  = A_j T C_i A_j^T + C_j,
+//   eta = A_i^T U (eta_j - J_j b_i) + eta_i,   U = (I + J_j C_i)^-1,
+//   J  = A_i^T U J_j A_i + J_i,
+// and the inclusive prefix up to k has A = 0, b = x_k, C = P_k.
+struct Elem {
+  std::vector<double> A, b, C, eta, J;
+};
+
+Elem elem_zero(int n) {
+  Elem e;
+  e.A.assign(n * n, 0.0);
+  e.b.assign(n, 0.0);
+  e.C.assign(n * n, 0.0);
+  e.eta.assign(n, 0.0);
+  e.J.assign(n * n, 0.0);
+  return e;
+}
+
+// X = (I + P Q)^-1 Y for n x n P, Q and n x r Y
+void solve_ipq(int n, int r, const double* P, const double* Q, const double* Y, double* X) {
+  std::vector<double> M(n * n), B(Y, Y + n * r);
+  mm(n, P, Q, M.data());
+  for (int i = 0; i < n; ++i) M[i * n + i] += 1.0;
+  gauss_solve(n, r, M.data(), B.data());
+  std::copy(B.begin(), B.end(), X);
+}
+
+Elem combine(const Elem& ei, const Elem& ej, int n) {
+  Elem o = elem_zero(n);
+  std::vector<double> T1(n * n), T2(n * n), TA(n * n), v(n), w(n);
+  // T A_i, T C_i and T (b_i + C_i eta_j): one solve with 2n + 1 columns
+  std::vector<double> Y(n * (2 * n + 1)), X(n * (2 * n + 1));
+  for (int r = 0; r < n; ++r) {
+    double s = ei.b[r];
+    for (int m = 0; m < n; ++m) s += ei.C[r * n + m] * ej.eta[m];
+    for (int c = 0; c < n; ++c) {
+      Y[r * (2 * n + 1) + c] = ei.A[r * n + c];
+      Y[r * (2 * n + 1) + n + c] = ei.C[r * n + c];
+    }
+    Y[r * (2 * n + 1) + 2 * n] = s;
+  }
+  solve_ipq(n, 2 * n + 1, ei.C.data(), ej.J.data(), Y.data(), X.data());
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) {
+      double sa = 0.0, sc = 0.0;
+      for (int m = 0; m < n; ++m) {
+        sa += ej.A[r * n + m] * X[m * (2 * n + 1) + c];
+        sc += ej.A[r * n + m] * X[m * (2 * n + 1) + n + c];
+      }
+      o.A[r * n + c] = sa;
+      T1[r * n + c] = sc;  // A_j T C_i
+    }
+  for (int r = 0; r < n; ++r) {
+    double sb = ej.b[r];
+    for (int m = 0; m < n; ++m) sb += ej.A[r * n + m] * X[m * (2 * n + 1) + 2 * n];
+    o.b[r] = sb;
+    for (int c = 0; c < n; ++c) {
+      double sc = ej.C[r * n + c];
+      for (int m = 0; m < n; ++m) sc += T1[r * n + m] * ej.A[c * n + m];
+      o.C[r * n + c] = sc;
+    }
+  }
+  // U J_j A_i and U (eta_j - J_j b_i): one solve with n + 1 columns
+  std::vector<double> Y2(n * (n + 1)), X2(n * (n + 1));
+  for (int r = 0; r < n; ++r) {
+    double s = ej.eta[r];
+    for (int m = 0; m < n; ++m) s -= ej.J[r * n + m] * ei.b[m];
+    for (int c = 0; c < n; ++c) {
+      double t = 0.0;
+      for (int m = 0; m < n; ++m) t += ej.J[r * n + m] * ei.A[m * n + c];
+      Y2[r * (n + 1) + c] = t;
+    }
+    Y2[r * (n + 1) + n] = s;
+  }
+  solve_ipq(n, n + 1, ej.J.data(), ei.C.data(), Y2.data(), X2.data());
+  for (int r = 0; r < n; ++r) {
+    double se = ei.eta[r];
+    for (int m = 0; m < n; ++m) se += ei.A[m * n + r] * X2[m * (n + 1) + n];
+    o.eta[r] = se;
+    for (int c = 0; c < n; ++c) {
+      double sj = ei.J[r * n + c];
+      for (int m = 0; m < n; ++m) sj += ei.A[m * n + r] * X2[m * (n + 1) + c];
+      o.J[r * n + c] = sj;
+    }
+  }
+  return o;
+}
+
+// Elements of every step of pulsar q's stream (per-pulsar models).
+std::vector<Elem> scan_elements(const DS& d, const Par<double>& p, int q) {
+  const int n = d.model == M_SPIN ? 2 : 4;
+  const int64_t b0 = d.off[q], N = d.off[q + 1] - b0;
+  std::vector<Elem> el(N, elem_zero(n));
+  std::vector<double> F(n * n), Q(n * n), P0(n * n), H(n, 0.0), u(n), K(n), hF(n), IKH(n * n),
+      tmp(n * n);
+  H[0] = 1.0;
+  if (n == 4) H[2] = H[3] = 1.0;
+  model_p0(d, p, q, n, P0.data());
+  double t_prev = 0.0;
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t j = b0 + k;
+    model_fq(d, p, q, d.t[j] - t_prev, n, F.data(), Q.data());
+    t_prev = d.t[j];
+    const double sk = d.sig[j];
+    const double R = p.psr[q].efac2 * sk * sk + p.psr[q].equad2;
+    Elem& e = el[k];
+    // the covariance entering the update: F P0 F^T + Q at the first step, Q after
+    std::vector<double> Pp(Q);
+    if (k == 0) {
+      mm(n, F.data(), P0.data(), tmp.data());
+      mmt(n, tmp.data(), F.data(), Pp.data());
+      for (int i = 0; i < n * n; ++i) Pp[i] += Q[i];
+    }
+    double S = R;
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int m = 0; m < n; ++m) s += Pp[i * n + m] * H[m];
+      u[i] = s;
+      S += H[i] * s;
+    }
+    for (int i = 0; i < n; ++i) K[i] = u[i] / S;
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m) IKH[i * n + m] = (i == m ? 1.0 : 0.0) - K[i] * H[m];
+    // C = (I - K h) Pp (I - K h)^T + K R K^T (Joseph form of (I - K h) Pp)
+    mm(n, IKH.data(), Pp.data(), tmp.data());
+    mmt(n, tmp.data(), IKH.data(), e.C.data());
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m) e.C[i * n + m] += K[i] * R * K[m];
+    if (k == 0) {  // prior folded in: A = 0, b = filtered mean (prior mean 0)
+      for (int i = 0; i < n; ++i) e.b[i] = K[i] * d.y[j];
+      continue;
+    }
+    mm(n, IKH.data(), F.data(), e.A.data());
+    for (int i = 0; i < n; ++i) e.b[i] = K[i] * d.y[j];
+    for (int c = 0; c < n; ++c) {
+      double s = 0.0;
+      for (int m = 0; m < n; ++m) s += H[m] * F[m * n + c];
+      hF[c] = s;
+    }
+    for (int r = 0; r < n; ++r) {
+      e.eta[r] = hF[r] * d.y[j] / S;
+      for (int c = 0; c < n; ++c) e.J[r * n + c] = hF[r] * hF[c] / S;
+    }
+  }
+  return el;
+}
+
+// Inclusive prefix of the elements in one of three evaluation orders:
+// 0 left fold; 1 recursive doubling (prefix k combines the prefixes ending
+// at k - 2^l and k at level l); 2 chunked (nchunk chunks folded internally,
+// the chunk totals folded, then each chunk's prefixes from the total of the
+// chunks before it).
+std::vector<Elem> scan_prefix(const std::vector<Elem>& el, int n, int order, int nchunk) {
+  const int64_t N = (int64_t)el.size();
+  std::vector<Elem> pre(el);
+  if (N == 0) return pre;
+  if (order == 0) {
+    for (int64_t k = 1; k < N; ++k) pre[k] = combine(pre[k - 1], el[k], n);
+  } else if (order == 1) {
+    for (int64_t dd = 1; dd < N; dd *= 2) {
+      std::vector<Elem> nxt(pre);
+      for (int64_t k = dd; k < N; ++k) nxt[k] = combine(pre[k - dd], pre[k], n);
+      pre.swap(nxt);
+    }
+  } else {
+    const int64_t C = std::max<int64_t>(1, std::min<int64_t>(nchunk, N));
+    std::vector<int64_t> edge(C + 1);
+    for (int64_t c = 0; c <= C; ++c) edge[c] = c * N / C;
+    std::vector<Elem> tot(C);
+    for (int64_t c = 0; c < C; ++c) {
+      Elem a = el[edge[c]];
+      for (int64_t k = edge[c] + 1; k < edge[c + 1]; ++k) a = combine(a, el[k], n);
+      tot[c] = a;
+    }
+    for (int64_t c = 1; c < C; ++c) tot[c] = combine(tot[c - 1], tot[c], n);
+    for (int64_t c = 0; c < C; ++c) {
+      Elem a = c == 0 ? el[edge[0]] : combine(tot[c - 1], el[edge[c]], n);
+      pre[edge[c]] = a;
+      for (int64_t k = edge[c] + 1; k < edge[c + 1]; ++k) {
+        a = combine(a, el[k], n);
+        pre[k] = a;
+      }
+    }
+  }
+  return pre;
+}
+
 }  // namespace
 
 // ====================================================================== C API
@@ -756,6 +955,48 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
     }
     status[s] = row_finite ? sst : S_NONFINITE;
   });
+  return 0;
+}
+
+// Filtered moments of pulsar q (per-pulsar models) by the associative scan
+// in evaluation order `order` (see scan_prefix), and the log-likelihood from
+// them: the predicted moments of step k come from the prefix ending at k - 1
+// (the prior before the first step). xs [N*n], Ps [N*n*n].
+int oracle_scan_filter(const oracle_ds* o, const double* c, int q, int order, int nchunk,
+                       double* xs, double* Ps, double* ll) {
+  DS d = make_ds(o);
+  if (d.model == M_JOINT) return -1;
+  Par<double> p = make_par<double>(d, c);
+  const int n = d.model == M_SPIN ? 2 : 4;
+  std::vector<Elem> el = scan_elements(d, p, q);
+  std::vector<Elem> pre = scan_prefix(el, n, order, nchunk);
+  const int64_t b0 = d.off[q], N = d.off[q + 1] - b0;
+  std::vector<double> F(n * n), Q(n * n), P(n * n), x(n, 0.0), Pp(n * n), tmp(n * n);
+  model_p0(d, p, q, n, P.data());
+  double acc = 0.0, t_prev = 0.0;
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t j = b0 + k;
+    model_fq(d, p, q, d.t[j] - t_prev, n, F.data(), Q.data());
+    t_prev = d.t[j];
+    mm(n, F.data(), P.data(), tmp.data());
+    mmt(n, tmp.data(), F.data(), Pp.data());
+    double hx = 0.0, S = p.psr[q].efac2 * d.sig[j] * d.sig[j] + p.psr[q].equad2;
+    const int hidx[3] = {0, 2, 3};
+    for (int a = 0; a < (n == 2 ? 1 : 3); ++a) {
+      const int i = hidx[a];
+      double fx = 0.0;
+      for (int m = 0; m < n; ++m) fx += F[i * n + m] * x[m];
+      hx += fx;
+      for (int b = 0; b < (n == 2 ? 1 : 3); ++b) S += Pp[i * n + hidx[b]] + Q[i * n + hidx[b]];
+    }
+    const double e = d.y[j] - hx;
+    acc += -0.5 * (std::log(2.0 * kPi) + std::log(S) + e * e / S);
+    x = pre[k].b;
+    P = pre[k].C;
+    std::copy(x.begin(), x.end(), xs + k * n);
+    std::copy(P.begin(), P.end(), Ps + k * n * n);
+  }
+  *ll = acc;
   return 0;
 }
 
