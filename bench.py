@@ -319,8 +319,12 @@ def main():
         s1 = torch.empty(64, dtype=torch.int32, device=dev)
         ds1.loglike(t1, o1, s1)
         ms1, _ = timed(lambda: ds1.loglike(t1, o1, s1), 50, 5, stream)
+        tune1 = ds1.tune_info(64)
+        chosen1 = [l for l in tune1.splitlines() if l.startswith("chosen")]
         extra["spin_1psr_500toa_64samples"] = {"us_per_call": ms1 * 1e3,
-                                                "evals_per_s": 64 / (ms1 * 1e-3)}
+                                                "evals_per_s": 64 / (ms1 * 1e-3),
+                                                "layout": chosen1[0] if chosen1 else tune1}
+        log("spin 1 pulsar: %.2f us/call; tune: %s" % (ms1 * 1e3, tune1.replace("\n", " | ")))
 
         # joint 80-state HD model, 20 pulsars x 1000 TOAs, 256 samples
         d3 = pi.make_config("cfg3")

@@ -192,7 +192,10 @@ int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
   a.n_items = bal ? w->n_items_bal : w->n_items;
   a.dynamic = bal ? 2 : cfg.dynamic;
   a.mc = ds->mc;
-  HIPCHK(launch_filter(ds->model, a, cfg.grid, cfg.block, st));
+  if (cfg.order == 2)
+    HIPCHK(launch_scan(ds->model, a, cfg.grid, cfg.block / kWave, st));
+  else
+    HIPCHK(launch_filter(ds->model, a, cfg.grid, cfg.block, st));
   ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, status,
                w->counter.as<int32_t>(), w->S, ds->P};
   HIPCHK(launch_reduce(r, st));
@@ -217,6 +220,10 @@ std::vector<TuneCfg> candidates(const argus_dataset* ds, const Workspace* w) {
     for (int b : {256, 512, 1024}) c.push_back({b, w->n_bins, 0, 1, 0.f});
   for (int k : {1, 2, 3, 4, 6}) add(64, (int64_t)simd * k, 1);
   for (int k : {2, 4}) add(256, (int64_t)simd * k, 1);
+  // time-parallel filter, one workgroup of nw waves per item: only when the
+  // items leave most SIMDs idle
+  if ((int64_t)w->n_items * 4 <= simd)
+    for (int nw : {4, 8, 16}) c.push_back({nw * kWave, w->n_items, 0, 2, 0.f});
   return c;
 }
 
@@ -228,14 +235,16 @@ int autotune(argus_dataset* ds, Workspace* w, const double* theta, double* logl,
     const int nf = std::sscanf(forced, "%d,%d,%d,%d", &b, &g, &dyn, &ord);
     const bool ok0 = ord == 0 && b >= 64 && b <= 256 && (dyn == 0 || dyn == 1);
     const bool ok1 = ord == 1 && b >= 64 && b <= 1024 && w->n_items_bal > 0;
-    if (nf >= 3 && b % 64 == 0 && g >= 1 && (ok0 || ok1)) {
-      w->cfg = {b, ord == 1 ? w->n_bins : g, ord == 1 ? 0 : dyn, ord, 0.f};
+    const bool ok2 = ord == 2 && (b == 256 || b == 512 || b == 1024);
+    if (nf >= 3 && b % 64 == 0 && g >= 1 && (ok0 || ok1 || ok2)) {
+      w->cfg = {b, ord == 1 ? w->n_bins : g, ord == 0 ? dyn : 0, ord, 0.f};
       w->tuned = true;
       return ARGUS_OK;
     }
     return fail(ARGUS_E_INVAL,
                 "ARGUS_CFG must be 'block,grid,dynamic[,order]' (order 0: block <= 256; "
-                "order 1: per-SIMD lists, block <= 1024, grid ignored)");
+                "order 1: per-SIMD lists, block <= 1024, grid ignored; order 2: "
+                "time-parallel filter, block 256, 512 or 1024 = 4, 8 or 16 chunks)");
   }
   const char* en = std::getenv("ARGUS_TUNE");
   if (en && std::strcmp(en, "0") == 0) {

@@ -47,7 +47,8 @@ struct TuneCfg {
   int block = 64;
   int grid = 1;
   int dynamic = 1;
-  int order = 0;  // 0: items longest-first; 1: one block per CU, per-SIMD item lists
+  int order = 0;  // 0: items longest-first; 1: one block per CU, per-SIMD item lists;
+                  // 2: time-parallel filter, block / 64 chunks per item
   float ms = 0.f;
 };
 

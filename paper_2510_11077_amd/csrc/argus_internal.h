@@ -165,6 +165,9 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t st);
 hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st);
 hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
                          hipStream_t st);
+// Time-parallel filter (models 1, 2): one workgroup of nw waves (4, 8 or 16)
+// per item, grid workgroups striding over the items.
+hipError_t launch_scan(int model, const FilterArgs& a, int grid, int nw, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_plain(const PlainArgs& a, hipStream_t st);
 

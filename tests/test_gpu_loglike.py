@@ -237,14 +237,59 @@ def test_joint_prior_corners_and_flags(argus, orc):
 
 
 @pytest.mark.parametrize("cfg", ["64,7,0", "256,3,0", "1024,1,0,1", "256,1,0,1", "64,1,0,1",
-                                 "64,5,1"])
+                                 "64,5,1", "256,4,0,2", "512,3,0,2", "1024,1,0,2"])
 def test_forced_launch_layouts(argus, orc, cfg, monkeypatch):
     """Every launch layout the tuner can pick gives the same parity: static
     longest-first with a grid smaller than the item count, one block per CU
     with per-SIMD lists (most lists here are empty; with one wave per block
-    every list is drained by taking from the others), and the global dynamic
-    queue."""
+    every list is drained by taking from the others), the global dynamic
+    queue, and the time-parallel filter with 4, 8 and 16 chunks per item
+    (fewer workgroups than items, streams shorter than the chunk count)."""
     monkeypatch.setenv("ARGUS_CFG", cfg)
     d = pi.make_pta("t", n_psr=7, counts=[400, 3, 0, 1200, 64, 777, 90], seed=49)
     th = pi.sample_theta(d, 200, 14)
     run(argus, orc, d, th)
+
+
+# ------------------------------------------------ time-parallel filter
+@pytest.mark.parametrize("nw", [4, 8, 16])
+def test_time_parallel_spin_model(argus, orc, nw, monkeypatch):
+    """The single-pulsar spin workload (500 TOAs, 64 samples) and its prior
+    corners through the chunked scan, and the 800-day-gap stream where the
+    predicted residual variance exceeds the white one by 13 decades."""
+    import dataclasses
+    monkeypatch.setenv("ARGUS_CFG", "%d,1,0,2" % (64 * nw))
+    d = pi.make_config("cfg1")
+    run(argus, orc, d, pi.sample_theta(d, 64, pi.THETA_SEED["cfg1"]))
+    run(argus, orc, d, np.array([d.lo, d.hi, [d.lo[0], d.hi[1]], [d.hi[0], d.lo[1]]]))
+    g = pi.make_spin("t1", n_toa=200, seed=9)
+    keep = np.r_[0:25, 75:100]
+    g = dataclasses.replace(g, t=g.t[keep], y=g.y[keep], sigma=g.sigma[keep],
+                            off=np.array([0, keep.size], np.int64))
+    run(argus, orc, g, np.array([[g.hi[0], 1.0], [g.hi[0] - 0.5, 0.9], [g.lo[0], 1.1]]))
+
+
+@pytest.mark.parametrize("nw", [4, 8, 16])
+def test_time_parallel_per_pulsar_model(argus, orc, nw, monkeypatch):
+    monkeypatch.setenv("ARGUS_CFG", "%d,2,0,2" % (64 * nw))
+    d = pi.make_pta("t", n_psr=5, counts=[2000, 3, 0, 17, 600], seed=50)
+    lo, hi = d.lo, d.hi
+    th = np.vstack([pi.sample_theta(d, 60, 15), [lo, hi, np.where(np.arange(lo.size) % 2, lo, hi)]])
+    run(argus, orc, d, th)
+
+
+def test_time_parallel_status_flags(argus, orc, monkeypatch):
+    monkeypatch.setenv("ARGUS_CFG", "512,1,0,2")
+    test_status_flags(argus, orc)
+
+
+def test_time_parallel_is_chosen_for_one_item(argus):
+    """With one (tile, pulsar) item the tuner times the chunked scan against
+    the sequential layouts; the report names what it chose."""
+    import torch
+    d = pi.make_config("cfg1")
+    ds = argus.Dataset(d)
+    ds.loglike(dev(pi.sample_theta(d, 64, 1)))
+    torch.cuda.synchronize()
+    info = ds.tune_info(64)
+    assert "order=2" in info
