@@ -240,7 +240,14 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       const double ss2 = ss * ss, efac2 = efac * efac;
       F2 f{0.0, 0.0, a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, {1.0, 0}, pnf ? kPNF : 0};
       const RecPtr rec = (RecPtr)a.rec;
-      for (int64_t k = kb; k < ke; ++k) step2(f, load_rec(rec, k), ss2, efac2);
+      // the next record is fetched one step ahead (index clamped)
+      TOARec rn{};
+      if (kb < ke) rn = load_rec(rec, kb);
+      for (int64_t k = kb; k < ke; ++k) {
+        const TOARec r = rn;
+        rn = load_rec(rec, k + 1 < ke ? k + 1 : k);
+        step2(f, r, ss2, efac2);
+      }
       st = f.st;
       ll = finish((double)(ke - kb), f.quad, f.L, st);
     } else {

@@ -431,9 +431,16 @@ __global__ void __launch_bounds__(NW * 64) k_scan(FilterArgs a) {
                         (12.0 * kPi * kPi * gm1);
       L = Lane<NS>{gr, sr * sr / (2.0 * gr), vc, efac * efac, eq * eq, a.mc.ss2};
     }
-    auto step_at = [&](int64_t k) {
-      const TOARec r = load_rec(rec, k);
-      return make_step<NS>(r, L, NS == 4 ? expm1_k(-L.gr * r.dt) : 0.0);
+    // the chunk's steps, each record fetched one step ahead (the index is
+    // clamped, so the last iteration repeats a harmless load)
+    auto run = [&](auto&& body) {
+      if (c1 <= c0) return;
+      TOARec rn = load_rec(rec, c0);
+      for (int64_t k = c0; k < c1; ++k) {
+        const TOARec r = rn;
+        rn = load_rec(rec, k + 1 < c1 ? k + 1 : k);
+        body(make_step<NS>(r, L, NS == 4 ? expm1_k(-L.gr * r.dt) : 0.0));
+      }
     };
 
     // ---- phase 1: chunk 0 filtered from the prior; the others summarised
@@ -453,7 +460,7 @@ __global__ void __launch_bounds__(NW * 64) k_scan(FilterArgs a) {
       f.quad = 0.0;
       f.L = {1.0, 0};
       f.st = pnf ? kPNF : 0;
-      for (int64_t k = c0; k < c1; ++k) filt_step<NS>(f, step_at(k));
+      run([&](const Step& t) { filt_step<NS>(f, t); });
       if (NW > 1) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) s_state[0][i][lane] = f.x[i];
@@ -465,7 +472,7 @@ __global__ void __launch_bounds__(NW * 64) k_scan(FilterArgs a) {
       s_st[0][lane] = f.st;
     } else {
       elem_identity<NS>(E);
-      for (int64_t k = c0; k < c1; ++k) elem_step<NS>(E, step_at(k));
+      run([&](const Step& t) { elem_step<NS>(E, t); });
     }
 
     // ---- phase 2: filtered state at the end of chunk w, in chunk order
@@ -497,7 +504,7 @@ __global__ void __launch_bounds__(NW * 64) k_scan(FilterArgs a) {
       f.quad = 0.0;
       f.L = {1.0, 0};
       f.st = 0;
-      for (int64_t k = c0; k < c1; ++k) filt_step<NS>(f, step_at(k));
+      run([&](const Step& t) { filt_step<NS>(f, t); });
       s_ll[w][lane] = -0.5 * ((double)(c1 - c0) * kLn2Pi +
                               (log(f.L.m) + (double)f.L.e * kLn2) + f.quad);
       s_st[w][lane] = f.st;
