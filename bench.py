@@ -358,6 +358,30 @@ def main():
         except A.ArgusError as e:
             extra["grad_47psr_1024samples"] = "unavailable: %s" % e
 
+        # HMC on the gradient path: 1024 chains on the 47-pulsar data
+        try:
+            lo4 = torch.as_tensor(d.lo[d.free], dtype=torch.float64, device=dev)
+            hi4 = torch.as_tensor(d.hi[d.free], dtype=torch.float64, device=dev)
+            th_h = torch.as_tensor(pi.theta_near_truth(d, S4, 31, scale=0.002),
+                                   dtype=torch.float64, device=dev)
+            n_lf = 8
+            hm = A.HMC(ds, th_h, lo4, hi4, 0.25, (1e-3 * (hi4 - lo4)) ** 2, n_lf, seed=2)
+            hm.step()
+            torch.cuda.synchronize()
+            hm.accepted.zero_()
+            hm.n_steps = 0
+            ms6, _ = timed(hm.step, 3, 0, stream)
+            extra["hmc_47psr_1024chains"] = {
+                "ms_per_transition": ms6, "leapfrog_steps": n_lf,
+                "chain_transitions_per_s": S4 / (ms6 * 1e-3),
+                "gradient_evals_per_s": S4 * n_lf / (ms6 * 1e-3),
+                "acceptance": hm.acceptance()}
+            log("hmc: %.3f ms/transition (%d leapfrog), %.4g chain-transitions/s, acceptance %.2f"
+                % (ms6, n_lf, S4 / (ms6 * 1e-3), hm.acceptance()))
+            del hm
+        except A.ArgusError as e:
+            extra["hmc_47psr_1024chains"] = "unavailable: %s" % e
+
         # smoothed latent states of every TOA, same data and samples
         try:
             nc = 4

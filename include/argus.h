@@ -116,6 +116,30 @@ int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
                        double* logl, double* grad, int32_t* status,
                        void* stream);
 
+/* One Hamiltonian Monte Carlo transition for each of S independent chains
+ * (models 1, 2), the gradient-based sampling the likelihood and its
+ * gradient serve (paper: Functionality, "Sampler Integration"). Chain s
+ * draws its momentum p = z_s / sqrt(inv_mass) (M = diag(1 / inv_mass)),
+ * takes n_leapfrog >= 1 kick-drift-kick steps of size eps[s] on
+ * log pi = logL + log prior, the prior uniform on the box [lo, hi], and
+ * accepts the end point when logu[s] < H0 - H1, H = -log pi + p^T M^-1 p / 2.
+ * A trajectory that leaves the box or meets a failed likelihood (status !=
+ * 0) at any leapfrog position is rejected. Each leapfrog position costs one
+ * batched gradient evaluation (argus_loglike_grad's sweep).
+ *   eps: dev [S]; inv_mass, lo, hi: dev [D]; z: dev [S*D] standard normal
+ *   draws; logu: dev [S] log of uniform draws (caller's random numbers)
+ *   theta, logl, grad: dev [S*D], [S], [S*D], the chains' current positions,
+ *   logL and gradient there (from argus_loglike_grad), updated in place for
+ *   accepted chains
+ *   accepted: dev [S] int32, incremented for accepted chains
+ *   energy_err: dev [S] H1 - H0 (+inf when the trajectory left the box or
+ *   met a failed likelihood), or NULL
+ * Allocates per-sample-count work buffers on the first call for S. */
+int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog, const double* eps,
+                   const double* inv_mass, const double* lo, const double* hi,
+                   const double* z, const double* logu, double* theta, double* logl,
+                   double* grad, int32_t* accepted, double* energy_err, void* stream);
+
 /* Smoothed latent states (models 1, 2): for every TOA k of every pulsar and
  * every sample s, the posterior mean and variance of that pulsar's state
  * components at t_k given all of its TOAs (paper: Summary and Statement of

@@ -11,8 +11,8 @@ chain at theta with log-density l(theta) and gradient g,
     H1 = -l(theta') + 1/2 sum(m_inv p'^2)
     accept when log u < H0 - H1 (a NaN H1 rejects)
 
-with a uniform prior on the box [lo, hi]: a trajectory that leaves the box
-at any leapfrog position has l = -inf and is rejected. z (standard normal
+with a uniform prior on the box [lo, hi]: a trajectory that leaves the box,
+or whose density fails, at any leapfrog position is rejected. z (standard normal
 draws) and log u are inputs, so a transition is a deterministic function of
 them.
 
@@ -26,7 +26,8 @@ import numpy as np
 def leapfrog(x, p, g, eps, m_inv, n_leapfrog, logl_grad, lo=None, hi=None):
     """n_leapfrog kick-drift-kick steps from (x, p) with g = grad l(x):
     returns (x, p, l(x), g, inside) at the end; inside is False for chains
-    whose position left [lo, hi] at any step."""
+    whose position left [lo, hi] or whose density failed (l not finite) at
+    any step."""
     eps = np.asarray(eps, np.float64).reshape(-1, 1)
     m_inv = np.asarray(m_inv, np.float64).reshape(1, -1)
     x = np.asarray(x, np.float64).copy()
@@ -40,6 +41,7 @@ def leapfrog(x, p, g, eps, m_inv, n_leapfrog, logl_grad, lo=None, hi=None):
         if lo is not None:
             inside &= np.all((x >= lo) & (x <= hi), axis=1)
         l1, g = logl_grad(x)
+        inside &= np.isfinite(l1)
         p = p + 0.5 * eps * g
     return x, p, l1, g, inside
 

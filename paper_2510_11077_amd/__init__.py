@@ -45,6 +45,8 @@ for _n in ("argus_loglike", "argus_loglike_terms", "argus_loglike_plain"):
     getattr(_lib, _n).argtypes = [_V, _V, C.c_int64, _V, _V, _V]
 _lib.argus_loglike_grad.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V]
 _lib.argus_smooth.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V, _V]
+_lib.argus_hmc_step.argtypes = [_V, C.c_int64, C.c_int32, _V, _V, _V, _V, _V, _V, _V, _V, _V,
+                                _V, _V, _V]
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
 _lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)]
 _lib.argus_mlp_destroy.argtypes = [_V]
@@ -205,6 +207,21 @@ class Dataset:
                                  _dev_ptr(var, torch.float64, "var"), out.data_ptr(),
                                  status.data_ptr(), _stream(stream)))
         return mean, var, out, status
+
+    def hmc_step(self, theta, logl, grad, eps, inv_mass, lo, hi, z, logu, n_leapfrog,
+                 accepted, energy_err=None, stream=None):
+        """One HMC transition per chain (rows of theta), in place on theta,
+        logl, grad and accepted (see argus_hmc_step)."""
+        import torch
+        tp = self._theta(theta)
+        S = theta.shape[0]
+        f64 = torch.float64
+        _check(_lib.argus_hmc_step(
+            self._h, S, int(n_leapfrog), _dev_ptr(eps, f64, "eps"),
+            _dev_ptr(inv_mass, f64, "inv_mass"), _dev_ptr(lo, f64, "lo"), _dev_ptr(hi, f64, "hi"),
+            _dev_ptr(z, f64, "z"), _dev_ptr(logu, f64, "logu"), tp, _dev_ptr(logl, f64, "logl"),
+            _dev_ptr(grad, f64, "grad"), _dev_ptr(accepted, torch.int32, "accepted"),
+            _dev_ptr(energy_err, f64, "energy_err"), _stream(stream)))
 
     def tune_info(self, S: int) -> str:
         buf = C.create_string_buffer(4096)
@@ -378,6 +395,51 @@ class DelayedAcceptance:
         da_stage2(self.idx, self.count, cap, ll_prop, lh_prop, logu2, prop, self.theta, self.ll,
                   self.lh, self.acc)
         return n
+
+
+class HMC:
+    """Batched Hamiltonian Monte Carlo on the gradient path: S chains (rows
+    of theta0) with a uniform prior on [lo, hi], diagonal inverse mass
+    inv_mass, step sizes eps (scalar or per chain) and n_leapfrog steps per
+    transition. The random numbers (momentum draws, accept uniforms) come
+    from a seeded device generator and are passed to argus_hmc_step."""
+
+    def __init__(self, ds, theta0, lo, hi, eps, inv_mass, n_leapfrog, seed=0):
+        import torch
+        self.ds = ds
+        dev = theta0.device
+        f64 = torch.float64
+        self.theta = theta0.to(f64).contiguous().clone()
+        S, D = self.theta.shape
+        self.lo = torch.as_tensor(lo, dtype=f64, device=dev).contiguous()
+        self.hi = torch.as_tensor(hi, dtype=f64, device=dev).contiguous()
+        self.inv_mass = torch.as_tensor(inv_mass, dtype=f64, device=dev).expand(D).contiguous()
+        self.eps = torch.as_tensor(eps, dtype=f64, device=dev).expand(S).contiguous()
+        self.n_leapfrog = int(n_leapfrog)
+        self.logl, self.grad, st = ds.loglike_grad(self.theta)
+        self.accepted = torch.zeros(S, dtype=torch.int32, device=dev)
+        self.energy_err = torch.empty(S, dtype=f64, device=dev)
+        self.z = torch.empty((S, D), dtype=f64, device=dev)
+        self.u = torch.empty(S, dtype=f64, device=dev)
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+        self.n_steps = 0
+
+    def step(self, z=None, logu=None):
+        """One transition of every chain; z, logu override the draws."""
+        import torch
+        if z is None:
+            self.z.normal_(generator=self.gen)
+            z = self.z
+        if logu is None:
+            self.u.uniform_(generator=self.gen)
+            logu = torch.log(self.u)
+        self.ds.hmc_step(self.theta, self.logl, self.grad, self.eps, self.inv_mass, self.lo,
+                         self.hi, z, logu, self.n_leapfrog, self.accepted, self.energy_err)
+        self.n_steps += 1
+
+    def acceptance(self) -> float:
+        return float(self.accepted.sum().item()) / max(1, self.n_steps * self.theta.shape[0])
 
 
 def _make_loglike_fn():

@@ -559,6 +559,23 @@ extern "C" int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64
   return grad_loglike(ds, theta, S, logl, grad, status, (hipStream_t)stream);
 }
 
+extern "C" int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog,
+                              const double* eps, const double* inv_mass, const double* lo,
+                              const double* hi, const double* z, const double* logu,
+                              double* theta, double* logl, double* grad, int32_t* accepted,
+                              double* energy_err, void* stream) {
+  int rc = check_call(ds, theta, S, logl);
+  if (rc || S == 0) return rc;
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "HMC needs the gradient (models 1 and 2)");
+  if (ds->D < 1) return fail(ARGUS_E_INVAL, "HMC needs at least one free parameter");
+  if (n_leapfrog < 1) return fail(ARGUS_E_INVAL, "n_leapfrog must be >= 1");
+  if (!eps || !inv_mass || !lo || !hi || !z || !logu || !grad || !accepted)
+    return fail(ARGUS_E_INVAL, "a required HMC pointer is NULL");
+  return hmc_step(ds, S, n_leapfrog, eps, inv_mass, lo, hi, z, logu, theta, logl, grad,
+                  accepted, energy_err, (hipStream_t)stream);
+}
+
 extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
                             double* var, double* logl, int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, mean);

@@ -84,6 +84,8 @@ struct Workspace {
   // tangent-mode gradient: directions per wave (0 = not tuned yet)
   int tan_nd = 0;
   std::string grad_log;
+  // HMC: proposal position, momentum, gradient, logL, initial energy, flags
+  DevBuf hmc_x, hmc_p, hmc_g, hmc_l, hmc_h0, hmc_ok;
   ~Workspace();
 };
 
@@ -109,4 +111,8 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
                  int32_t* status, hipStream_t st);
 int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mean, double* var,
                   double* logl, int32_t* status, hipStream_t st);
+int hmc_step(argus_dataset* ds, int64_t S, int32_t n_leapfrog, const double* eps,
+             const double* m_inv, const double* lo, const double* hi, const double* z,
+             const double* logu, double* theta, double* logl, double* grad,
+             int32_t* accepted, double* dh, hipStream_t st);
 }  // namespace argus
