@@ -140,6 +140,43 @@ int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog, const doub
                    const double* z, const double* logu, double* theta, double* logl,
                    double* grad, int32_t* accepted, double* energy_err, void* stream);
 
+/* One No-U-Turn Sampler transition for each of S independent chains (models
+ * 1, 2): the sampler of the paper's posteriors (Functionality, "Sampler
+ * Integration", and its figure: NUTS, Hoffman & Gelman 2014), with
+ * multinomial trajectory sampling and the generalised no-U-turn criterion.
+ * Per chain: momentum p = z_s / sqrt(inv_mass); doubling j (< max_depth)
+ * grows 2^j leapfrog leaves of size eps[s] in direction dirs[s*max_depth+j]
+ * (+1 or -1) from the trajectory end on that side. A leaf diverges when
+ * H - H0 > 1000, H is not a number, it leaves the box [lo, hi] or its
+ * likelihood fails (H = -logL + p^T M^-1 p / 2). Inside a subtree, halves
+ * A, B merge with the proposal taken from B when the merge's uniform
+ * u_sub[(s*max_depth + j)*2^(max_depth-1) + m] < exp(W_B - W) (W the
+ * log-sum-exp of -H over leaves, m the merge's post-order index within the
+ * subtree) and the merged subtree makes a U-turn unless both end momenta,
+ * scaled by inv_mass, have a positive dot product with the summed momentum;
+ * a U-turn or divergence inside a subtree discards it and ends the
+ * transition. A valid subtree's proposal replaces the trajectory's when
+ * u_top[s*max_depth + j] < exp(W_sub - W_traj); the trajectory stops at a
+ * U-turn between its ends or after max_depth doublings.
+ *   eps: dev [S]; inv_mass, lo, hi: dev [D]; z: dev [S*D] standard normal
+ *   draws; dirs: dev int32 [S*max_depth]; u_top: dev [S*max_depth];
+ *   u_sub: dev [S*max_depth*2^(max_depth-1)] uniforms in (0, 1)
+ *   theta, logl, grad: dev [S*D], [S], [S*D], current state in, the
+ *   transition's result out (from argus_loglike_grad at the start)
+ *   depth, n_leapfrog, divergent: dev int32 [S] out (doublings accepted,
+ *   leapfrog steps taken, 1 if the transition ended on a divergence)
+ *   accept_stat: dev [S] mean of min(1, exp(H0 - H)) over the leaves, or NULL
+ * max_depth in [1, 10]. All chains step together: each leaf is one batched
+ * gradient evaluation; the call synchronises the stream once per leaf to
+ * stop when no chain is still building. Allocates per-sample-count work
+ * buffers on the first call for S (and for a larger max_depth). */
+int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const double* eps,
+                    const double* inv_mass, const double* lo, const double* hi,
+                    const double* z, const int32_t* dirs, const double* u_top,
+                    const double* u_sub, double* theta, double* logl, double* grad,
+                    int32_t* depth, int32_t* n_leapfrog, int32_t* divergent,
+                    double* accept_stat, void* stream);
+
 /* Smoothed latent states (models 1, 2): for every TOA k of every pulsar and
  * every sample s, the posterior mean and variance of that pulsar's state
  * components at t_k given all of its TOAs (paper: Summary and Statement of

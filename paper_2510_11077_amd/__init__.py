@@ -47,6 +47,7 @@ _lib.argus_loglike_grad.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V]
 _lib.argus_smooth.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V, _V]
 _lib.argus_hmc_step.argtypes = [_V, C.c_int64, C.c_int32, _V, _V, _V, _V, _V, _V, _V, _V, _V,
                                 _V, _V, _V]
+_lib.argus_nuts_step.argtypes = [_V, C.c_int64, C.c_int32] + [_V] * 16
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
 _lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)]
 _lib.argus_mlp_destroy.argtypes = [_V]
@@ -222,6 +223,23 @@ class Dataset:
             _dev_ptr(z, f64, "z"), _dev_ptr(logu, f64, "logu"), tp, _dev_ptr(logl, f64, "logl"),
             _dev_ptr(grad, f64, "grad"), _dev_ptr(accepted, torch.int32, "accepted"),
             _dev_ptr(energy_err, f64, "energy_err"), _stream(stream)))
+
+    def nuts_step(self, theta, logl, grad, eps, inv_mass, lo, hi, z, dirs, u_top, u_sub,
+                  max_depth, depth, n_leapfrog, divergent, accept_stat=None, stream=None):
+        """One NUTS transition per chain, in place on theta, logl, grad (see
+        argus_nuts_step)."""
+        import torch
+        tp = self._theta(theta)
+        S = theta.shape[0]
+        f64, i32 = torch.float64, torch.int32
+        _check(_lib.argus_nuts_step(
+            self._h, S, int(max_depth), _dev_ptr(eps, f64, "eps"),
+            _dev_ptr(inv_mass, f64, "inv_mass"), _dev_ptr(lo, f64, "lo"), _dev_ptr(hi, f64, "hi"),
+            _dev_ptr(z, f64, "z"), _dev_ptr(dirs, i32, "dirs"), _dev_ptr(u_top, f64, "u_top"),
+            _dev_ptr(u_sub, f64, "u_sub"), tp, _dev_ptr(logl, f64, "logl"),
+            _dev_ptr(grad, f64, "grad"), _dev_ptr(depth, i32, "depth"),
+            _dev_ptr(n_leapfrog, i32, "n_leapfrog"), _dev_ptr(divergent, i32, "divergent"),
+            _dev_ptr(accept_stat, f64, "accept_stat"), _stream(stream)))
 
     def tune_info(self, S: int) -> str:
         buf = C.create_string_buffer(4096)
@@ -440,6 +458,50 @@ class HMC:
 
     def acceptance(self) -> float:
         return float(self.accepted.sum().item()) / max(1, self.n_steps * self.theta.shape[0])
+
+
+class NUTS:
+    """Batched No-U-Turn Sampler on the gradient path: S chains (rows of
+    theta0), uniform prior on [lo, hi], diagonal inverse mass, step sizes
+    eps (scalar or per chain), trees of at most max_depth doublings. The
+    random numbers come from a seeded device generator and are passed to
+    argus_nuts_step."""
+
+    def __init__(self, ds, theta0, lo, hi, eps, inv_mass, max_depth=8, seed=0):
+        import torch
+        self.ds = ds
+        dev = theta0.device
+        f64, i32 = torch.float64, torch.int32
+        self.theta = theta0.to(f64).contiguous().clone()
+        S, D = self.theta.shape
+        self.lo = torch.as_tensor(lo, dtype=f64, device=dev).contiguous()
+        self.hi = torch.as_tensor(hi, dtype=f64, device=dev).contiguous()
+        self.inv_mass = torch.as_tensor(inv_mass, dtype=f64, device=dev).expand(D).contiguous()
+        self.eps = torch.as_tensor(eps, dtype=f64, device=dev).expand(S).contiguous()
+        self.max_depth = int(max_depth)
+        self.logl, self.grad, _ = ds.loglike_grad(self.theta)
+        usz = 2 ** (self.max_depth - 1)
+        self.z = torch.empty((S, D), dtype=f64, device=dev)
+        self.dirs = torch.empty((S, self.max_depth), dtype=i32, device=dev)
+        self.u_top = torch.empty((S, self.max_depth), dtype=f64, device=dev)
+        self.u_sub = torch.empty((S, self.max_depth, usz), dtype=f64, device=dev)
+        self.depth = torch.zeros(S, dtype=i32, device=dev)
+        self.n_leapfrog = torch.zeros(S, dtype=i32, device=dev)
+        self.divergent = torch.zeros(S, dtype=i32, device=dev)
+        self.accept_stat = torch.zeros(S, dtype=f64, device=dev)
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+
+    def step(self):
+        """One transition of every chain."""
+        self.z.normal_(generator=self.gen)
+        self.u_top.uniform_(generator=self.gen)
+        self.u_sub.uniform_(generator=self.gen)
+        self.dirs.random_(0, 2, generator=self.gen)
+        self.dirs.mul_(2).sub_(1)
+        self.ds.nuts_step(self.theta, self.logl, self.grad, self.eps, self.inv_mass, self.lo,
+                          self.hi, self.z, self.dirs, self.u_top, self.u_sub, self.max_depth,
+                          self.depth, self.n_leapfrog, self.divergent, self.accept_stat)
 
 
 def _make_loglike_fn():

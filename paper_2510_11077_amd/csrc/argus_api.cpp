@@ -576,6 +576,25 @@ extern "C" int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog,
                   accepted, energy_err, (hipStream_t)stream);
 }
 
+extern "C" int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth,
+                               const double* eps, const double* inv_mass, const double* lo,
+                               const double* hi, const double* z, const int32_t* dirs,
+                               const double* u_top, const double* u_sub, double* theta,
+                               double* logl, double* grad, int32_t* depth, int32_t* n_leapfrog,
+                               int32_t* divergent, double* accept_stat, void* stream) {
+  int rc = check_call(ds, theta, S, logl);
+  if (rc || S == 0) return rc;
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "NUTS needs the gradient (models 1 and 2)");
+  if (ds->D < 1) return fail(ARGUS_E_INVAL, "NUTS needs at least one free parameter");
+  if (max_depth < 1 || max_depth > 10) return fail(ARGUS_E_INVAL, "max_depth must be in [1, 10]");
+  if (!eps || !inv_mass || !lo || !hi || !z || !dirs || !u_top || !u_sub || !grad || !depth ||
+      !n_leapfrog || !divergent)
+    return fail(ARGUS_E_INVAL, "a required NUTS pointer is NULL");
+  return nuts_step(ds, S, max_depth, eps, inv_mass, lo, hi, z, dirs, u_top, u_sub, theta, logl,
+                   grad, depth, n_leapfrog, divergent, accept_stat, (hipStream_t)stream);
+}
+
 extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
                             double* var, double* logl, int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, mean);

@@ -86,6 +86,9 @@ struct Workspace {
   std::string grad_log;
   // HMC: proposal position, momentum, gradient, logL, initial energy, flags
   DevBuf hmc_x, hmc_p, hmc_g, hmc_l, hmc_h0, hmc_ok;
+  // NUTS: trajectory, cursor and subtree-stack buffers for depth <= nuts_md
+  DevBuf nuts_f, nuts_i;
+  int nuts_md = 0;
   ~Workspace();
 };
 
@@ -111,6 +114,11 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
                  int32_t* status, hipStream_t st);
 int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mean, double* var,
                   double* logl, int32_t* status, hipStream_t st);
+int nuts_step(argus_dataset* ds, int64_t S, int32_t max_depth, const double* eps,
+              const double* m_inv, const double* lo, const double* hi, const double* z,
+              const int32_t* dirs, const double* u_top, const double* u_sub, double* theta,
+              double* logl, double* grad, int32_t* depth, int32_t* n_leapfrog,
+              int32_t* divergent, double* accept_stat, hipStream_t st);
 int hmc_step(argus_dataset* ds, int64_t S, int32_t n_leapfrog, const double* eps,
              const double* m_inv, const double* lo, const double* hi, const double* z,
              const double* logu, double* theta, double* logl, double* grad,
