@@ -359,11 +359,11 @@ def main():
             extra["grad_47psr_1024samples"] = "unavailable: %s" % e
 
         # HMC on the gradient path: 1024 chains on the 47-pulsar data
+        lo4 = torch.as_tensor(d.lo[d.free], dtype=torch.float64, device=dev)
+        hi4 = torch.as_tensor(d.hi[d.free], dtype=torch.float64, device=dev)
+        th_h = torch.as_tensor(pi.theta_near_truth(d, S4, 31, scale=0.002),
+                               dtype=torch.float64, device=dev)
         try:
-            lo4 = torch.as_tensor(d.lo[d.free], dtype=torch.float64, device=dev)
-            hi4 = torch.as_tensor(d.hi[d.free], dtype=torch.float64, device=dev)
-            th_h = torch.as_tensor(pi.theta_near_truth(d, S4, 31, scale=0.002),
-                                   dtype=torch.float64, device=dev)
             n_lf = 8
             hm = A.HMC(ds, th_h, lo4, hi4, 0.25, (1e-3 * (hi4 - lo4)) ** 2, n_lf, seed=2)
             hm.step()
@@ -381,6 +381,33 @@ def main():
             del hm
         except A.ArgusError as e:
             extra["hmc_47psr_1024chains"] = "unavailable: %s" % e
+
+        # NUTS on the gradient path: same chains and data
+        try:
+            nu = A.NUTS(ds, th_h, lo4, hi4, 0.25, (1e-3 * (hi4 - lo4)) ** 2, max_depth=6, seed=3)
+            nu.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n_tr, n_lf_tot = 2, 0
+            for _ in range(n_tr):
+                nu.step()
+                n_lf_tot += int(nu.n_leapfrog.max().item())
+            torch.cuda.synchronize()
+            ms7 = (time.perf_counter() - t0) * 1e3 / n_tr
+            extra["nuts_47psr_1024chains"] = {
+                "ms_per_transition": ms7, "max_depth": 6,
+                "chain_transitions_per_s": S4 / (ms7 * 1e-3),
+                "lockstep_leapfrog_steps_per_transition": n_lf_tot / n_tr,
+                "mean_tree_depth": float(nu.depth.double().mean().item()),
+                "mean_accept_stat": float(nu.accept_stat.mean().item()),
+                "divergent_fraction": float(nu.divergent.double().mean().item()),
+                "clock": "host wall clock (the call synchronises once per leaf)"}
+            log("nuts: %.2f ms/transition, mean depth %.2f, accept stat %.2f"
+                % (ms7, extra["nuts_47psr_1024chains"]["mean_tree_depth"],
+                   extra["nuts_47psr_1024chains"]["mean_accept_stat"]))
+            del nu
+        except A.ArgusError as e:
+            extra["nuts_47psr_1024chains"] = "unavailable: %s" % e
 
         # smoothed latent states of every TOA, same data and samples
         try:
