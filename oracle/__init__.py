@@ -40,7 +40,7 @@ class _DS(C.Structure):
                 ("off", C.c_void_p), ("t", C.c_void_p), ("y", C.c_void_p),
                 ("sigma", C.c_void_p), ("pos", C.c_void_p),
                 ("t_span", C.c_double), ("s_r", C.c_double), ("s_f", C.c_double),
-                ("sigma_s", C.c_double)]
+                ("sigma_s", C.c_double), ("freq", C.c_void_p)]
 
 
 _lib = None
@@ -84,14 +84,16 @@ class Dataset:
         self.y = np.ascontiguousarray(d.y, np.float64)
         self.sigma = np.ascontiguousarray(d.sigma, np.float64)
         self.pos = None if d.pos is None else np.ascontiguousarray(d.pos, np.float64)
+        fr = getattr(d, "freq", None)
+        self.freq = None if fr is None else np.ascontiguousarray(fr, np.float64)
         self.desc = _DS(self.model, self.n_psr, _ptr(self.off), _ptr(self.t), _ptr(self.y),
                         _ptr(self.sigma), _ptr(self.pos), float(d.t_span), float(d.s_r),
-                        float(d.s_f), float(d.sigma_s))
+                        float(d.s_f), float(d.sigma_s), _ptr(self.freq))
         self.C = lib().oracle_n_canon(C.byref(self.desc))
 
     @property
     def n(self) -> int:
-        return 2 if self.model == 1 else (4 if self.model == 2 else 4 * self.n_psr)
+        return {1: 2, 2: 4, 4: 5}.get(self.model, 4 * self.n_psr)
 
 
 def _as_ds(d) -> Dataset:
@@ -153,7 +155,7 @@ def smooth(d, canon, nthreads=None):
     c = np.ascontiguousarray(np.atleast_2d(canon), np.float64)
     assert c.shape[1] == ds.C
     S, N = c.shape[0], int(ds.off[-1])
-    nc = 2 if ds.model == 1 else 4
+    nc = {1: 2, 4: 5}.get(ds.model, 4)
     mean = np.empty((S, N, nc))
     var = np.empty((S, N, nc))
     st = np.empty(S, np.int32)

@@ -48,7 +48,8 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kLn10 = 2.30258509299404568402;
 constexpr double kYear = 31557600.0;  // Julian year, seconds
 
-enum { M_SPIN = 1, M_PSR4 = 2, M_JOINT = 3 };
+enum { M_SPIN = 1, M_PSR4 = 2, M_JOINT = 3, M_DM = 4 };
+constexpr double kNuRef = 1400.0;  // MHz: the DM state is the delay at this frequency
 enum { S_NONPD = 1, S_NONFINITE = 2 };
 
 // ---------------------------------------------------------------- scalars
@@ -85,6 +86,7 @@ struct DS {
   const double* y = nullptr;
   const double* sig = nullptr;
   const double* pos = nullptr;
+  const double* freq = nullptr;  // MHz per TOA (model 4)
   double t_span = 0, s_r = 0, s_f = 0, sigma_s = 0;
   // merged, time-ordered stream (joint model only)
   std::vector<int64_t> m_idx;  // global TOA index
@@ -92,7 +94,17 @@ struct DS {
   std::vector<double> hd;      // P x P Hellings-Downs matrix
 };
 
-int n_canon(const DS& d) { return d.model == M_SPIN ? 2 : 4 * d.P + 2; }
+// canonical parameters per pulsar, and the state dimension of one filter
+int per_psr(const DS& d) { return d.model == M_DM ? 6 : 4; }
+int n_canon(const DS& d) { return d.model == M_SPIN ? 2 : per_psr(d) * d.P + 2; }
+int state_dim(const DS& d) {
+  switch (d.model) {
+    case M_SPIN: return 2;
+    case M_PSR4: return 4;
+    case M_DM: return 5;
+    default: return 4 * d.P;
+  }
+}
 
 // Hellings & Downs (1983) overlap reduction, earth term plus the pulsar term
 // on the diagonal: G_ab = 3/2 x ln x - x/4 + 1/2 + delta_ab/2,
@@ -127,6 +139,7 @@ T common_variance(const T& log10A, const T& gam, double t_span) {
 template <class T>
 struct Psr {
   T vr, gr, efac2, equad2;
+  T vd, gd;  // DM OU variance and rate (model 4)
 };
 template <class T>
 struct Par {
@@ -145,18 +158,25 @@ Par<T> make_par(const DS& d, const T* c) {
     p.ss2 = ss * ss;
     p.vc = T(0.0);
     p.psr.resize(1);
-    p.psr[0] = {T(0.0), T(1.0), c[1] * c[1], T(0.0)};
+    p.psr[0] = {T(0.0), T(1.0), c[1] * c[1], T(0.0), T(0.0), T(1.0)};
     return p;
   }
+  const int k = per_psr(d);
   p.ss2 = T(d.sigma_s * d.sigma_s);
-  p.vc = common_variance(c[4 * d.P], c[4 * d.P + 1], d.t_span);
+  p.vc = common_variance(c[k * d.P], c[k * d.P + 1], d.t_span);
   p.psr.resize(d.P);
   for (int q = 0; q < d.P; ++q) {
-    const T* cq = c + 4 * q;
+    const T* cq = c + k * q;
     T sr = p10(cq[0]);
     T gr = p10(cq[1]);
     T eq = p10(cq[3]);
-    p.psr[q] = {sr * sr / (2.0 * gr), gr, cq[2] * cq[2], eq * eq};
+    p.psr[q] = {sr * sr / (2.0 * gr), gr, cq[2] * cq[2], eq * eq, T(0.0), T(1.0)};
+    if (d.model == M_DM) {
+      T sd = p10(cq[4]);
+      T gd = p10(cq[5]);
+      p.psr[q].vd = sd * sd / (2.0 * gd);
+      p.psr[q].gd = gd;
+    }
   }
   return p;
 }
@@ -202,8 +222,12 @@ void block_fq(const DS& d, const Par<T>& p, int q, double dt, int n, int o,
   F[(o + 2) * n + o + 2] = xexp(-s.gr * dt);
   Q[(o + 2) * n + o + 2] = s.vr * (-xexpm1(-2.0 * s.gr * dt));
   F[(o + 3) * n + o + 3] = T(std::exp(-p.lam * dt));
-  if (d.model == M_PSR4)
+  if (d.model != M_JOINT)
     Q[(o + 3) * n + o + 3] = p.vc * (-std::expm1(-2.0 * p.lam * dt));
+  if (d.model == M_DM) {  // DM delay at the reference frequency: OU
+    F[(o + 4) * n + o + 4] = xexp(-s.gd * dt);
+    Q[(o + 4) * n + o + 4] = s.vd * (-xexpm1(-2.0 * s.gd * dt));
+  }
 }
 
 // Full F, Q of the filter that processes pulsar q (per-pulsar models) or the
@@ -233,7 +257,8 @@ void model_p0(const DS& d, const Par<T>& p, int q, int n, T* P0) {
     P0[(o + 1) * n + o + 1] = T(d.s_f * d.s_f);
     if (d.model == M_SPIN) return;
     P0[(o + 2) * n + o + 2] = p.psr[a].vr;
-    if (d.model == M_PSR4) P0[(o + 3) * n + o + 3] = p.vc;
+    if (d.model != M_JOINT) P0[(o + 3) * n + o + 3] = p.vc;
+    if (d.model == M_DM) P0[(o + 4) * n + o + 4] = p.psr[a].vd;
   };
   if (d.model != M_JOINT) {
     blk(q, 0);
@@ -267,7 +292,7 @@ void put(double* dst, const T* src, int m) {
 template <class T, class IdxF, class PsrF>
 T kalman(const DS& d, const Par<T>& p, int q_fixed, int64_t N, IdxF idx,
          PsrF psr_of, int32_t* status, Trace* tr) {
-  const int n = d.model == M_SPIN ? 2 : (d.model == M_PSR4 ? 4 : 4 * d.P);
+  const int n = state_dim(d);
   std::vector<T> x(n, T(0.0)), xp(n), P(n * n), Pp(n * n), F(n * n), Q(n * n),
       tmp(n * n), A(n * n), H(n), u(n), K(n);
   model_p0(d, p, q_fixed, n, P.data());
@@ -291,13 +316,17 @@ T kalman(const DS& d, const Par<T>& p, int q_fixed, int64_t N, IdxF idx,
     mm(n, F.data(), P.data(), tmp.data());
     mmt(n, tmp.data(), F.data(), Pp.data());
     for (int i = 0; i < n * n; ++i) Pp[i] += Q[i];
-    // measurement row: residual = r + a + g of pulsar q
+    // measurement row: residual = r + a + g (+ (nu_ref / nu)^2 m) of pulsar q
     std::fill(H.begin(), H.end(), T(0.0));
     const int o = d.model == M_JOINT ? 4 * q : 0;
     H[o] = T(1.0);
     if (d.model != M_SPIN) {
       H[o + 2] = T(1.0);
       H[o + 3] = T(1.0);
+    }
+    if (d.model == M_DM) {
+      const double ck = kNuRef / d.freq[j];
+      H[o + 4] = T(ck * ck);
     }
     const Psr<T>& ps = p.psr[d.model == M_JOINT ? q : q_fixed];
     const double sk = d.sig[j];
@@ -510,7 +539,7 @@ bool rts(const DS& d, const Par<double>& p, int q_fixed, int64_t N, IdxF idx, in
 // fails (status set).
 double smooth_stream(const DS& d, const Par<double>& p, int q, double* xs, double* Ps,
                      int32_t* st) {
-  const int n = d.model == M_SPIN ? 2 : (d.model == M_PSR4 ? 4 : 4 * d.P);
+  const int n = state_dim(d);
   const int64_t N = d.model == M_JOINT ? (int64_t)d.m_idx.size() : d.off[q + 1] - d.off[q];
   std::vector<double> e(N), S(N), x(N * n), Pf(N * n * n), Pp(N * n * n), xp(N * n);
   Trace tr{e.data(), S.data(), x.data(), Pf.data(), Pp.data(), xp.data()};
@@ -783,6 +812,7 @@ typedef struct {
   double t_span;      // seconds
   double s_r, s_f;    // prior std of the spin offset r (s) and f
   double sigma_s;     // spin random-walk amplitude (per-pulsar models 2/3)
+  const double* freq; // [N] radio frequency per TOA, MHz (model 4), may be NULL
 } oracle_ds;
 
 static DS make_ds(const oracle_ds* o) {
@@ -798,12 +828,13 @@ static DS make_ds(const oracle_ds* o) {
   d.s_r = o->s_r;
   d.s_f = o->s_f;
   d.sigma_s = o->sigma_s;
+  d.freq = o->freq;
   build_merged(d);
   return d;
 }
 
 int oracle_n_canon(const oracle_ds* o) {
-  return o->model == M_SPIN ? 2 : 4 * o->n_psr + 2;
+  return o->model == M_SPIN ? 2 : (o->model == M_DM ? 6 : 4) * o->n_psr + 2;
 }
 
 // logL for S samples of canonical parameters c [S x C]. per_psr (nullable)
@@ -837,9 +868,10 @@ int oracle_grad_cs(const oracle_ds* o, const double* c, int64_t S,
       cc[w] += cd(0.0, h);
       int32_t st = 0;
       cd l;
-      if (d.model == M_PSR4 && w < 4 * d.P) {
+      const int k = per_psr(d);
+      if ((d.model == M_PSR4 || d.model == M_DM) && w < k * d.P) {
         Par<cd> p = make_par<cd>(d, cc.data());
-        l = psr_loglike<cd>(d, p, w / 4, &st, nullptr);
+        l = psr_loglike<cd>(d, p, w / k, &st, nullptr);
       } else {
         l = sample_loglike<cd>(d, cc.data(), &st, nullptr);
       }
@@ -883,7 +915,7 @@ int oracle_smooth_stream(const oracle_ds* o, const double* c, int q, double* xs,
   }
   *status = st;
   if (st) {
-    const int n = d.model == M_SPIN ? 2 : (d.model == M_PSR4 ? 4 : 4 * d.P);
+    const int n = state_dim(d);
     const int64_t N = d.model == M_JOINT ? (int64_t)d.m_idx.size() : d.off[q + 1] - d.off[q];
     std::fill(xs, xs + N * n, std::numeric_limits<double>::quiet_NaN());
     std::fill(Ps, Ps + N * n * n, std::numeric_limits<double>::quiet_NaN());
@@ -903,7 +935,8 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
                   int32_t* status, int nthreads) {
   DS d = make_ds(o);
   const int C = n_canon(d);
-  const int nc = d.model == M_SPIN ? 2 : 4;
+  const int nc = d.model == M_JOINT ? 4 : state_dim(d);
+  const int kp = per_psr(d);
   const int64_t Nt = d.off[d.P];
   parallel_for(S, nthreads, [&](int64_t s) {
     double* ms = mean + s * Nt * nc;
@@ -912,7 +945,7 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
     int32_t sst = 0;
     const double nan = std::numeric_limits<double>::quiet_NaN();
     const bool row_finite = finite_params(cs, C);
-    if (!row_finite && d.model != M_PSR4) {
+    if (!row_finite && d.model != M_PSR4 && d.model != M_DM) {
       std::fill(ms, ms + Nt * nc, nan);
       std::fill(vs, vs + Nt * nc, nan);
       status[s] = S_NONFINITE;
@@ -941,7 +974,8 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
         const int64_t b = d.off[q], N = d.off[q + 1] - b;
         std::vector<double> xs(N * nc, nan), Ps(N * nc * nc, nan);
         int32_t qs = 0;
-        if (d.model == M_PSR4 && !(finite_params(cs + 4 * q, 4) && finite_params(cs + 4 * d.P, 2)))
+        if ((d.model == M_PSR4 || d.model == M_DM) &&
+            !(finite_params(cs + kp * q, kp) && finite_params(cs + kp * d.P, 2)))
           qs = S_NONFINITE;
         else
           smooth_stream(d, p, q, xs.data(), Ps.data(), &qs);
@@ -965,7 +999,7 @@ int oracle_smooth(const oracle_ds* o, const double* c, int64_t S, double* mean, 
 int oracle_scan_filter(const oracle_ds* o, const double* c, int q, int order, int nchunk,
                        double* xs, double* Ps, double* ll) {
   DS d = make_ds(o);
-  if (d.model == M_JOINT) return -1;
+  if (d.model == M_JOINT || d.model == M_DM) return -1;
   Par<double> p = make_par<double>(d, c);
   const int n = d.model == M_SPIN ? 2 : 4;
   std::vector<Elem> el = scan_elements(d, p, q);
@@ -1015,7 +1049,7 @@ int oracle_model_mats(const oracle_ds* o, const double* c, int q, double dt,
                       double* F, double* Q, double* P0) {
   DS d = make_ds(o);
   Par<double> p = make_par<double>(d, c);
-  const int n = d.model == M_SPIN ? 2 : (d.model == M_PSR4 ? 4 : 4 * d.P);
+  const int n = state_dim(d);
   model_fq(d, p, q, dt, n, F, Q);
   model_p0(d, p, q, n, P0);
   return n;

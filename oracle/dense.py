@@ -11,7 +11,9 @@ Covariance functions (s = t - t0, t0 = 0 where the prior holds):
       s_r^2 + s_f^2 s s' + sigma_s^2 m^2 (3M - m) / 6,  m = min, M = max
   OU red noise (stationary):       v_r exp(-gamma_r |s - s'|)
   OU common process:               v_c exp(-lambda_c |s - s'|) * G_ab
-      (G = identity for the per-pulsar model, Hellings-Downs for the joint)
+      (G = identity for the per-pulsar models, Hellings-Downs for the joint)
+  OU DM delay (model 4):           c c' v_d exp(-gamma_d |s - s'|),
+      c = (1400 MHz / nu)^2 the chromatic factor of each TOA
   white:                           (EFAC^2 sigma_k^2 + EQUAD^2) delta
 Gradient: d logL / d theta = 1/2 (alpha^T dC alpha - tr(C^-1 dC)),
 alpha = C^-1 y (Rasmussen & Williams 2006, eq. 5.9).
@@ -69,17 +71,18 @@ def covariance(d, c, with_parts=False):
         parts[1] = np.diag(2 * c[1] * d.sigma ** 2)
         return (Cm, parts) if with_parts else Cm
     P = d.n_psr
+    k = 6 if d.model == 4 else 4
     G = hd_closed_form(d.pos) if d.model == 3 else np.eye(P)
-    vc = common_var(c[4 * P], c[4 * P + 1], d.t_span)
+    vc = common_var(c[k * P], c[k * P + 1], d.t_span)
     Kc = np.exp(-lam * tau) * G[psr[:, None], psr[None, :]] * vc
     Cm += Kc
-    parts[4 * P] = 2 * LN10 * Kc
-    parts[4 * P + 1] = (np.log(1.0 / YEAR) + np.log(d.t_span) - 1.0 / (c[4 * P + 1] - 1.0)) * Kc
+    parts[k * P] = 2 * LN10 * Kc
+    parts[k * P + 1] = (np.log(1.0 / YEAR) + np.log(d.t_span) - 1.0 / (c[k * P + 1] - 1.0)) * Kc
     ss2 = d.sigma_s ** 2
     for q in range(P):
         sl = slice(int(d.off[q]), int(d.off[q + 1]))
         tq = t[sl]
-        lsr, lgr, efac, leq = c[4 * q:4 * q + 4]
+        lsr, lgr, efac, leq = c[k * q:k * q + 4]
         gr = 10.0 ** lgr
         vr = 10.0 ** (2 * lsr) / (2 * gr)
         base, walk = _spin_k(tq, d.s_r, d.s_f, ss2)
@@ -87,14 +90,22 @@ def covariance(d, c, with_parts=False):
         Kr = vr * np.exp(-gr * tq_tau)
         Rq = efac ** 2 * d.sigma[sl] ** 2 + 10.0 ** (2 * leq)
         Cm[sl, sl] += base + walk + Kr + np.diag(Rq)
+        blocks = [2 * LN10 * Kr, -LN10 * (1.0 + gr * tq_tau) * Kr,
+                  np.diag(2 * efac * d.sigma[sl] ** 2),
+                  np.diag(2 * LN10 * 10.0 ** (2 * leq) * np.ones(tq.size))]
+        if d.model == 4:
+            lsd, lgd = c[k * q + 4:k * q + 6]
+            gd = 10.0 ** lgd
+            vd = 10.0 ** (2 * lsd) / (2 * gd)
+            ch = (1400.0 / np.asarray(d.freq, np.float64)[sl]) ** 2
+            Kd = vd * np.exp(-gd * tq_tau) * np.outer(ch, ch)
+            Cm[sl, sl] += Kd
+            blocks += [2 * LN10 * Kd, -LN10 * (1.0 + gd * tq_tau) * Kd]
         if with_parts:
-            for j, blk in enumerate([2 * LN10 * Kr,
-                                     -LN10 * (1.0 + gr * tq_tau) * Kr,
-                                     np.diag(2 * efac * d.sigma[sl] ** 2),
-                                     np.diag(2 * LN10 * 10.0 ** (2 * leq) * np.ones(tq.size))]):
+            for j, blk in enumerate(blocks):
                 full = np.zeros((N, N))
                 full[sl, sl] = blk
-                parts[4 * q + j] = full
+                parts[k * q + j] = full
     return (Cm, parts) if with_parts else Cm
 
 

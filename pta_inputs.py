@@ -17,6 +17,9 @@ white noise) at the five configurations the benchmarks use:
   cfg3  20 pulsars x 1000 TOAs, joint 80-state model with HD coupling
   cfg4  cfg2's data (gradient workload)
   cfg5  pulsars 0-9 of cfg2 with a 10-parameter free vector
+and, for the per-pulsar model with dispersion-measure variations
+(state [r, f, a, g, m]), cfg2dm: cfg2's pulsars and cadences observed in
+four radio bands, with an OU DM delay per pulsar.
 """
 from __future__ import annotations
 
@@ -25,7 +28,12 @@ from dataclasses import dataclass, field
 import numpy as np
 
 YEAR = 31557600.0  # Julian year, s
-M_SPIN, M_PSR4, M_JOINT = 1, 2, 3
+M_SPIN, M_PSR4, M_JOINT, M_DM = 1, 2, 3, 4
+NU_REF = 1400.0  # MHz: the DM delay state is the delay at this frequency
+BANDS = np.array([430.0, 820.0, 1400.0, 2300.0])  # MHz
+BAND_P = np.array([0.15, 0.35, 0.35, 0.15])
+DM_LO = np.array([-14.0, -9.0])        # log10 sigma_dm, log10 gamma_dm
+DM_HI = np.array([-10.0, -7.0])
 
 # per-pulsar canonical parameters (models 2 and 3), then the two common ones
 PSR_PARAM_NAMES = ("log10_sigma_red", "log10_gamma_red", "efac", "log10_equad")
@@ -37,9 +45,9 @@ COMMON_TRUTH = np.array([-14.5, 13.0 / 3.0])
 SPIN_LO = np.array([-20.0, 0.8])       # model 1: log10 sigma_s, efac
 SPIN_HI = np.array([-12.0, 1.2])
 
-DATA_SEED = {"cfg1": 101, "cfg2": 102, "cfg3": 103, "cfg4": 102, "cfg5": 102}
-THETA_SEED = {"cfg1": 201, "cfg2": 202, "cfg3": 203, "cfg4": 204, "cfg5": 205}
-N_SAMPLES = {"cfg1": 64, "cfg2": 4096, "cfg3": 256, "cfg4": 1024, "cfg5": 65536}
+DATA_SEED = {"cfg1": 101, "cfg2": 102, "cfg3": 103, "cfg4": 102, "cfg5": 102, "cfg2dm": 102}
+THETA_SEED = {"cfg1": 201, "cfg2": 202, "cfg3": 203, "cfg4": 204, "cfg5": 205, "cfg2dm": 206}
+N_SAMPLES = {"cfg1": 64, "cfg2": 4096, "cfg3": 256, "cfg4": 1024, "cfg5": 65536, "cfg2dm": 4096}
 
 
 @dataclass
@@ -60,10 +68,13 @@ class PTAData:
     lo: np.ndarray = field(default=None)        # prior box [C]
     hi: np.ndarray = field(default=None)
     free: np.ndarray = field(default=None)      # bool [C]
+    freq: np.ndarray = field(default=None)      # float64 [N] radio frequency, MHz (model 4)
 
     @property
     def n_canon(self) -> int:
-        return 2 if self.model == M_SPIN else 4 * self.n_psr + 2
+        if self.model == M_SPIN:
+            return 2
+        return (6 if self.model == M_DM else 4) * self.n_psr + 2
 
     @property
     def n_toa(self) -> int:
@@ -238,6 +249,35 @@ def make_pta(name="cfg2", n_psr=47, n_range=(200, 2000), counts=None,
                    np.ones(truth.size, bool))
 
 
+def make_pta_dm(name="cfg2dm", n_psr=47, n_range=(200, 2000), counts=None, T_years=12.0,
+                seed=None, common=COMMON_TRUTH):
+    """Model 4: make_pta's pulsars (same draws, so the same cadences, errors,
+    truths and residuals) observed at a radio frequency drawn per TOA from
+    four bands, plus a DM delay per pulsar: an OU series with the Lorentzian
+    spectrum of its (sigma_dm, gamma_dm), scaled by (NU_REF / nu)^2. Per
+    pulsar parameters [log10 sigma_red, log10 gamma_red, EFAC, log10 EQUAD,
+    log10 sigma_dm, log10 gamma_dm], then [log10 A, gamma]."""
+    base = make_pta(name, n_psr=n_psr, n_range=n_range, counts=counts, T_years=T_years,
+                    seed=seed, model=M_DM, common=common)
+    rng = np.random.default_rng(7919 + (DATA_SEED.get(name, 102) if seed is None else seed))
+    P, T = base.n_psr, base.t_span
+    dtruth = rng.uniform(DM_LO, DM_HI, size=(P, 2))
+    freq = rng.choice(BANDS, size=base.n_toa, p=BAND_P)
+    y = base.y.copy()
+    for p in range(P):
+        a, b = int(base.off[p]), int(base.off[p + 1])
+        lsd, lgd = dtruth[p]
+        gd = 10.0 ** lgd
+        vd = 10.0 ** (2 * lsd) / (2 * gd)
+        y[a:b] += _red_series(rng, base.t[a:b], vd, gd, T) * (NU_REF / freq[a:b]) ** 2
+    pt = base.truth[:4 * P].reshape(P, 4)
+    truth = np.concatenate([np.hstack([pt, dtruth]).ravel(), base.truth[-2:]])
+    lo = np.concatenate([np.tile(np.r_[PSR_LO, DM_LO], P), COMMON_LO])
+    hi = np.concatenate([np.tile(np.r_[PSR_HI, DM_HI], P), COMMON_HI])
+    return PTAData(name, M_DM, P, base.off, base.t, y, base.sigma, base.pos, T, base.s_r,
+                   base.s_f, base.sigma_s, truth, lo, hi, np.ones(truth.size, bool), freq)
+
+
 def subset(d: PTAData, psrs, name=None, free=None) -> PTAData:
     """Pulsars `psrs` of d (same data, same truths); optional free mask."""
     psrs = list(psrs)
@@ -273,6 +313,8 @@ def make_config(name: str) -> PTAData:
         return make_pta("cfg3", n_psr=20, counts=np.full(20, 1000), model=M_JOINT)
     if name == "cfg5":
         return subset(make_pta("cfg2"), range(10), "cfg5", cfg5_free_mask(10))
+    if name == "cfg2dm":
+        return make_pta_dm("cfg2dm")
     raise ValueError(name)
 
 
