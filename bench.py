@@ -31,6 +31,11 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 # Joseph rank-2 update of 10 entries 60, quadratic form 3, log-det 1.
 FLOP_PER_STEP_M2 = 135
 FLOP_PER_STEP_M1 = 47
+# model 4 (state [r, f, a, g, m]), same accounting: both OU discretisations
+# 12, common-OU noise 1, mean predict 5, covariance predict 38, innovation
+# and S with the chromatic row 32, reciprocal 1, gain + mean update + S K 20,
+# Joseph rank-2 update of 15 entries 90, quadratic form 3, log-det 1.
+FLOP_PER_STEP_M4 = 203
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 
@@ -325,6 +330,25 @@ def main():
                                                 "evals_per_s": 64 / (ms1 * 1e-3),
                                                 "layout": chosen1[0] if chosen1 else tune1}
         log("spin 1 pulsar: %.2f us/call; tune: %s" % (ms1 * 1e3, tune1.replace("\n", " | ")))
+
+        # 47 pulsars with DM variations in four radio bands, 4096 samples
+        d6 = pi.make_config("cfg2dm")
+        S6 = pi.N_SAMPLES["cfg2dm"]
+        t6 = torch.as_tensor(pi.sample_theta(d6, S6, pi.THETA_SEED["cfg2dm"]),
+                             dtype=torch.float64, device=dev)
+        ds6 = A.Dataset(d6)
+        o6 = torch.empty(S6, dtype=torch.float64, device=dev)
+        s6 = torch.empty(S6, dtype=torch.int32, device=dev)
+        ds6.loglike(t6, o6, s6)
+        ms6d, _ = timed(lambda: ds6.loglike(t6, o6, s6), 20, 3, stream)
+        fl6 = int(d6.n_toa) * S6 * FLOP_PER_STEP_M4
+        extra["dm_47psr_4096samples"] = {
+            "ms_per_call": ms6d, "evals_per_s": S6 / (ms6d * 1e-3),
+            "tflops_algorithmic": fl6 / (ms6d * 1e-3) / 1e12,
+            "frac_fp64_peak": fl6 / (ms6d * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+        log("DM model: %.3f ms/call, %.4g evals/s, %.2f TFLOP/s (alg.)"
+            % (ms6d, S6 / (ms6d * 1e-3), fl6 / (ms6d * 1e-3) / 1e12))
+        del ds6
 
         # joint 80-state HD model, 20 pulsars x 1000 TOAs, 256 samples
         d3 = pi.make_config("cfg3")

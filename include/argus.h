@@ -23,6 +23,14 @@
  *                      power law (mapped to the OU variance over 1/T_span..inf)
  *   ARGUS_M3_JOINT_HD  the same P pulsars in one joint 4P-dim state whose
  *                      common-process noise is Hellings-Downs correlated
+ *   ARGUS_M4_PSR5_DM   model 2 with DM variations (Statement of Need: DM
+ *                      variations are another latent stochastic process):
+ *                      [r, f, a, g, m] per pulsar, m the DM delay at 1400 MHz
+ *                      (an OU process, stationary at t0), seen at a TOA of
+ *                      radio frequency nu through (1400 MHz / nu)^2;
+ *                      canonical params per pulsar [log10 sigma_red,
+ *                      log10 gamma_red, EFAC, log10 EQUAD, log10 sigma_dm,
+ *                      log10 gamma_dm], then [log10 A, gamma]
  * Measurement: y_k = r + a + g + white, white variance EFAC^2 sigma_k^2 +
  * EQUAD^2 (model 1: EFAC^2 sigma_k^2). Every filter starts from the prior at
  * the epoch t0 = 0 and predicts to its first TOA.
@@ -55,7 +63,7 @@ extern "C" {
 enum { ARGUS_OK = 0, ARGUS_E_INVAL = 1, ARGUS_E_HIP = 2, ARGUS_E_NOMEM = 3,
        ARGUS_E_UNSUPPORTED = 4 };
 enum { ARGUS_S_NONPD = 1, ARGUS_S_NONFINITE = 2 };
-enum { ARGUS_M1_SPIN = 1, ARGUS_M2_PSR4 = 2, ARGUS_M3_JOINT_HD = 3 };
+enum { ARGUS_M1_SPIN = 1, ARGUS_M2_PSR4 = 2, ARGUS_M3_JOINT_HD = 3, ARGUS_M4_PSR5_DM = 4 };
 
 typedef struct argus_dataset* argus_dataset_t;
 
@@ -74,12 +82,16 @@ typedef struct {
   double t_span;            /* s; sets the common OU rate 2 pi / t_span and the
                                power-law low-frequency cutoff 1 / t_span */
   double s_r, s_f;          /* prior std of r (s) and f at t0 */
-  double sigma_s;           /* spin random-walk amplitude (models 2, 3) */
+  double sigma_s;           /* spin random-walk amplitude (models 2, 3, 4) */
+  const double* freq;       /* host [N] radio frequency of each TOA, MHz, > 0;
+                               model 4 only, else NULL */
 } argus_dataset_desc;
 
 /* Copies the data to the device, orders the joint stream by (t, pulsar),
- * and precomputes per-TOA intervals and the common-process decay.
- * C = 2 (model 1) or 4P + 2. Synchronises. */
+ * and precomputes per-TOA intervals, the common-process decay and (model 4)
+ * the chromatic factors. C = 2 (model 1), 4P + 2 (models 2, 3) or 6P + 2
+ * (model 4). Synchronises. Model 4 has the likelihood and its per-pulsar
+ * terms; the other calls return ARGUS_E_UNSUPPORTED for it. */
 int argus_dataset_create(const argus_dataset_desc* desc, argus_dataset_t* out);
 int argus_dataset_destroy(argus_dataset_t ds);
 /* D = number of free parameters (columns of theta). */

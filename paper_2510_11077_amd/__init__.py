@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libargus.so")
 
-M1_SPIN, M2_PSR4, M3_JOINT_HD = 1, 2, 3
+M1_SPIN, M2_PSR4, M3_JOINT_HD, M4_PSR5_DM = 1, 2, 3, 4
 S_NONPD, S_NONFINITE = 1, 2
 
 if not os.path.exists(LIB_PATH):
@@ -33,7 +33,7 @@ class _Desc(C.Structure):
                 ("t", C.c_void_p), ("y", C.c_void_p), ("sigma", C.c_void_p),
                 ("pos", C.c_void_p), ("fixed", C.c_void_p), ("free_mask", C.c_void_p),
                 ("t_span", C.c_double), ("s_r", C.c_double), ("s_f", C.c_double),
-                ("sigma_s", C.c_double)]
+                ("sigma_s", C.c_double), ("freq", C.c_void_p)]
 
 
 _V = C.c_void_p
@@ -105,12 +105,14 @@ class Dataset:
             pos=None if getattr(d, "pos", None) is None else np.ascontiguousarray(d.pos, np.float64),
             fixed=np.ascontiguousarray(d.truth, np.float64),
             free=None if getattr(d, "free", None) is None else np.ascontiguousarray(d.free, np.uint8),
+            freq=None if getattr(d, "freq", None) is None else np.ascontiguousarray(d.freq, np.float64),
         )
         k = self._keep
         p = lambda a: None if a is None else a.ctypes.data
         desc = _Desc(self.model, self.n_psr, p(k["off"]), p(k["t"]), p(k["y"]), p(k["sigma"]),
                      p(k["pos"]) if self.model == M3_JOINT_HD else None, p(k["fixed"]), p(k["free"]),
-                     float(d.t_span), float(d.s_r), float(d.s_f), float(d.sigma_s))
+                     float(d.t_span), float(d.s_r), float(d.s_f), float(d.sigma_s),
+                     p(k["freq"]) if self.model == M4_PSR5_DM else None)
         h = _V()
         _check(_lib.argus_dataset_create(C.byref(desc), C.byref(h)))
         self._h = h

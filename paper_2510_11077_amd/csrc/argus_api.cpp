@@ -77,7 +77,7 @@ bool finite(double v) { return std::isfinite(v); }
 
 int validate(const argus_dataset_desc* d) {
   if (!d) return fail(ARGUS_E_INVAL, "desc is NULL");
-  if (d->model < 1 || d->model > 3) return fail(ARGUS_E_INVAL, "unknown model");
+  if (d->model < 1 || d->model > 4) return fail(ARGUS_E_INVAL, "unknown model");
   if (d->n_psr < 1) return fail(ARGUS_E_INVAL, "n_psr must be >= 1");
   if (d->model == ARGUS_M1_SPIN && d->n_psr != 1)
     return fail(ARGUS_E_INVAL, "model 1 takes exactly one pulsar");
@@ -103,6 +103,12 @@ int validate(const argus_dataset_desc* d) {
       if (!finite(d->sigma[k]) || !(d->sigma[k] > 0.0))
         return fail(ARGUS_E_INVAL, "sigma must be finite and > 0");
     }
+  if (d->model == ARGUS_M4_PSR5_DM) {
+    if (N > 0 && !d->freq) return fail(ARGUS_E_INVAL, "freq is required for model 4");
+    for (int64_t k = 0; k < N; ++k)
+      if (!finite(d->freq[k]) || !(d->freq[k] > 0.0))
+        return fail(ARGUS_E_INVAL, "freq must be finite and > 0");
+  }
   if (d->model == ARGUS_M3_JOINT_HD) {
     if (!d->pos) return fail(ARGUS_E_INVAL, "pos is required for the joint model");
     for (int i = 0; i < 3 * d->n_psr; ++i)
@@ -113,7 +119,7 @@ int validate(const argus_dataset_desc* d) {
   if (!finite(d->s_r) || !finite(d->s_f) || !finite(d->sigma_s) || d->s_r < 0 ||
       d->s_f < 0 || d->sigma_s < 0)
     return fail(ARGUS_E_INVAL, "s_r, s_f, sigma_s must be finite and >= 0");
-  const int C = d->model == ARGUS_M1_SPIN ? 2 : 4 * d->n_psr + 2;
+  const int C = d->model == ARGUS_M1_SPIN ? 2 : (d->model == ARGUS_M4_PSR5_DM ? 6 : 4) * d->n_psr + 2;
   for (int c = 0; c < C; ++c) {
     const bool fr = d->free_mask ? d->free_mask[c] != 0 : true;
     if (!fr && (!d->fixed || !finite(d->fixed[c])))
@@ -176,6 +182,7 @@ int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
                        hipStream_t st) {
   FilterArgs a{};
   a.rec = ds->rec.as<TOARec>();
+  a.chrom = ds->chrom.as<double>();
   a.off = ds->off.as<int64_t>();
   a.theta = theta;
   a.col = ds->col.as<int32_t>();
@@ -222,7 +229,7 @@ std::vector<TuneCfg> candidates(const argus_dataset* ds, const Workspace* w) {
   for (int k : {2, 4}) add(256, (int64_t)simd * k, 1);
   // time-parallel filter, one workgroup of nw waves per item: only when the
   // items leave most SIMDs idle
-  if ((int64_t)w->n_items * 4 <= simd)
+  if (ds->model != ARGUS_M4_PSR5_DM && (int64_t)w->n_items * 4 <= simd)
     for (int nw : {4, 8, 16}) c.push_back({nw * kWave, w->n_items, 0, 2, 0.f});
   return c;
 }
@@ -235,7 +242,8 @@ int autotune(argus_dataset* ds, Workspace* w, const double* theta, double* logl,
     const int nf = std::sscanf(forced, "%d,%d,%d,%d", &b, &g, &dyn, &ord);
     const bool ok0 = ord == 0 && b >= 64 && b <= 256 && (dyn == 0 || dyn == 1);
     const bool ok1 = ord == 1 && b >= 64 && b <= 1024 && w->n_items_bal > 0;
-    const bool ok2 = ord == 2 && (b == 256 || b == 512 || b == 1024);
+    const bool ok2 = ord == 2 && (b == 256 || b == 512 || b == 1024) &&
+                     ds->model != ARGUS_M4_PSR5_DM;
     if (nf >= 3 && b % 64 == 0 && g >= 1 && (ok0 || ok1 || ok2)) {
       w->cfg = {b, ord == 1 ? w->n_bins : g, ord == 0 ? dyn : 0, ord, 0.f};
       w->tuned = true;
@@ -341,7 +349,7 @@ int argus_dataset_create(const argus_dataset_desc* d, argus_dataset_t* out) {
   auto ds = std::make_unique<argus_dataset>();
   ds->model = d->model;
   ds->P = d->n_psr;
-  ds->C = d->model == ARGUS_M1_SPIN ? 2 : 4 * d->n_psr + 2;
+  ds->C = d->model == ARGUS_M1_SPIN ? 2 : (d->model == ARGUS_M4_PSR5_DM ? 6 : 4) * d->n_psr + 2;
   ds->N = d->toa_off[d->n_psr];
   HIPCHK(hipGetDevice(&ds->device));
   hipDeviceProp_t prop;
@@ -409,6 +417,14 @@ int argus_dataset_create(const argus_dataset_desc* d, argus_dataset_t* out) {
       (rc = ds->icol.upload(icol.data(), icol.size() * sizeof(int32_t))) ||
       (rc = ds->fixed.upload(fixed.data(), ds->C * sizeof(double))))
     return rc;
+  if (d->model == ARGUS_M4_PSR5_DM) {
+    std::vector<double> ch(N > 0 ? N : 1, 0.0);
+    for (int64_t k = 0; k < N; ++k) {
+      const double r = kNuRef / d->freq[k];
+      ch[k] = r * r;
+    }
+    if ((rc = ds->chrom.upload(ch.data(), ch.size() * sizeof(double)))) return rc;
+  }
   StageArgs sa{ds->t.as<double>(), ds->y.as<double>(), ds->sig.as<double>(),
                dsrc.as<int64_t>(), dprev.as<int64_t>(), dpsr.as<int32_t>(),
                ds->rec.as<TOARec>(), N, ds->mc.lam};
@@ -496,7 +512,7 @@ int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S, doub
   int rc = check_call(ds, theta, S, terms);
   if (rc || S == 0) return rc;
   if (ds->model == ARGUS_M3_JOINT_HD)
-    return fail(ARGUS_E_UNSUPPORTED, "per-pulsar terms exist for models 1 and 2 only");
+    return fail(ARGUS_E_UNSUPPORTED, "per-pulsar terms exist for models 1, 2 and 4 only");
   hipStream_t st = (hipStream_t)stream;
   Workspace* w = get_workspace(ds, S, &rc);
   if (!w) return rc;
@@ -513,7 +529,7 @@ int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S, doub
                         int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD)
+  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
     return fail(ARGUS_E_UNSUPPORTED, "the plain baseline covers models 1 and 2");
   hipStream_t st = (hipStream_t)stream;
   for (int64_t s = 0; s < S; ++s) {
@@ -554,7 +570,7 @@ extern "C" int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
   if (ds->D > 0 && !grad) return fail(ARGUS_E_INVAL, "grad is NULL");
-  if (ds->model == ARGUS_M3_JOINT_HD)
+  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
     return fail(ARGUS_E_UNSUPPORTED, "the gradient covers models 1 and 2");
   return grad_loglike(ds, theta, S, logl, grad, status, (hipStream_t)stream);
 }
@@ -566,7 +582,7 @@ extern "C" int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog,
                               double* energy_err, void* stream) {
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD)
+  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
     return fail(ARGUS_E_UNSUPPORTED, "HMC needs the gradient (models 1 and 2)");
   if (ds->D < 1) return fail(ARGUS_E_INVAL, "HMC needs at least one free parameter");
   if (n_leapfrog < 1) return fail(ARGUS_E_INVAL, "n_leapfrog must be >= 1");
@@ -584,7 +600,7 @@ extern "C" int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth,
                                int32_t* divergent, double* accept_stat, void* stream) {
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD)
+  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
     return fail(ARGUS_E_UNSUPPORTED, "NUTS needs the gradient (models 1 and 2)");
   if (ds->D < 1) return fail(ARGUS_E_INVAL, "NUTS needs at least one free parameter");
   if (max_depth < 1 || max_depth > 10) return fail(ARGUS_E_INVAL, "max_depth must be in [1, 10]");
@@ -599,7 +615,7 @@ extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, 
                             double* var, double* logl, int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, mean);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD)
+  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
     return fail(ARGUS_E_UNSUPPORTED, "the smoother covers models 1 and 2");
   if (ds->N > 0 && (uint64_t)ds->N * 4 * (uint64_t)S > ((uint64_t)1 << 40))
     return fail(ARGUS_E_UNSUPPORTED, "N * S too large for one call");

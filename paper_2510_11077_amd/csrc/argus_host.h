@@ -100,6 +100,7 @@ struct argus_dataset {
   int device = 0, n_cu = 256;
   argus::ModelConst mc{};
   argus::DevBuf rec, off, col, icol, fixed, hd, t, y, sig;  // icol: theta column -> canonical
+  argus::DevBuf chrom;  // model 4: (nu_ref / nu)^2 per TOA
   std::vector<int64_t> off_h, counts;
   std::map<int64_t, std::unique_ptr<argus::Workspace>> ws;
   hipStream_t cap_stream = nullptr;

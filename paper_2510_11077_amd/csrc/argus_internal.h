@@ -13,6 +13,7 @@ constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kLn10 = 2.30258509299404568402;
 constexpr double kLn2Pi = 1.83787706640934548356;
 constexpr double kYear = 31557600.0;
+constexpr double kNuRef = 1400.0;  // MHz: reference frequency of the DM delay state
 
 // status words; kPNF marks "a parameter of this filter is not finite" and has
 // priority over the innovation flags when a sample's pulsars are combined
@@ -40,6 +41,7 @@ static_assert(sizeof(TOARec) == 64, "TOA record is one 64-B line");
 // constant address space: the compiler then issues one scalar 64-B load
 // (s_load_dwordx16) per record instead of 64 vector loads.
 typedef __attribute__((address_space(4))) const TOARec* RecPtr;
+typedef __attribute__((address_space(4))) const double* ConstDPtr;
 
 __device__ __forceinline__ TOARec load_rec(RecPtr r, int64_t k) {
   TOARec x;
@@ -106,9 +108,10 @@ struct ModelConst {
   double lam;          // 2 pi / t_span
 };
 
-// Arguments of the batched per-pulsar filter (models 1, 2).
+// Arguments of the batched per-pulsar filter (models 1, 2, 4).
 struct FilterArgs {
   const TOARec* rec;     // [N]
+  const double* chrom;   // [N] chromatic factor (nu_ref / nu)^2 per TOA (model 4), else null
   const int64_t* off;    // [P+1]
   const double* theta;   // [S*D]
   const int32_t* col;    // [C] theta column of canonical param, or -1

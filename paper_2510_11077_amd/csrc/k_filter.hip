@@ -140,6 +140,84 @@ __device__ __forceinline__ void step4(F4& f, const TOARec r, double em,
   acc_mul(f.L, S);
 }
 
+// ------------------------------------------------------------ model 4 step
+// The model 2 state plus m, the DM delay at the reference frequency (an OU
+// process), observed with the chromatic factor c = (nu_ref / nu)^2 of the
+// TOA: h = [1, 0, 1, 1, c].
+struct F5 {
+  double xr, xf, xa, xg, xm;
+  double prr, prf, pff, pra, pfa, paa, prg, pfg, pag, pgg, prm, pfm, pam, pgm, pmm;
+  double quad;
+  LogAcc L;
+  int st;
+};
+
+// em, emd = expm1(-rate dt) of the red and DM processes for this record
+__device__ __forceinline__ void step5(F5& f, const TOARec r, double c, double em, double emd,
+                                      double vr, double vc, double vd, double efac2,
+                                      double equad2, double ss2) {
+  const double dt = r.dt;
+  const double phr = 1.0 + em, phd = 1.0 + emd;
+  const double qr = vr * (-em * (2.0 + em));
+  const double qd = vd * (-emd * (2.0 + emd));
+  const double phc = r.phc;
+  const double qc = vc * r.qcu;
+  f.xr = fma(dt, f.xf, f.xr);
+  f.xa *= phr;
+  f.xg *= phc;
+  f.xm *= phd;
+  const double prf1 = fma(dt, f.pff, f.prf);
+  f.prr = fma(dt, f.prf + prf1, f.prr) + ss2 * r.h3;
+  f.prf = prf1 + ss2 * r.h2;
+  f.pff = f.pff + ss2 * dt;
+  f.pra = phr * fma(dt, f.pfa, f.pra);
+  f.pfa = phr * f.pfa;
+  f.paa = fma(phr * phr, f.paa, qr);
+  f.prg = phc * fma(dt, f.pfg, f.prg);
+  f.pfg = phc * f.pfg;
+  f.pag = (phr * phc) * f.pag;
+  f.pgg = fma(phc * phc, f.pgg, qc);
+  f.prm = phd * fma(dt, f.pfm, f.prm);
+  f.pfm = phd * f.pfm;
+  f.pam = (phr * phd) * f.pam;
+  f.pgm = (phc * phd) * f.pgm;
+  f.pmm = fma(phd * phd, f.pmm, qd);
+  const double e = r.y - fma(c, f.xm, f.xr + f.xa + f.xg);
+  const double ur = fma(c, f.prm, f.prr + f.pra + f.prg);
+  const double uf = fma(c, f.pfm, f.prf + f.pfa + f.pfg);
+  const double ua = fma(c, f.pam, f.pra + f.paa + f.pag);
+  const double ug = fma(c, f.pgm, f.prg + f.pag + f.pgg);
+  const double um = fma(c, f.pmm, f.prm + f.pam + f.pgm);
+  const double S = fma(c, um, ur + ua + ug) + fma(efac2, r.s2, equad2);
+  step_status(f.st, S, e);
+  const double inv = rcp_nr(S);
+  const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv, km = um * inv;
+  f.xr = fma(kr, e, f.xr);
+  f.xf = fma(kf, e, f.xf);
+  f.xa = fma(ka, e, f.xa);
+  f.xg = fma(kg, e, f.xg);
+  f.xm = fma(km, e, f.xm);
+  const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+  const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug), dm = fma(S, km, -um);
+  JOSEPH(f.prr, kr, ur, dr, kr);
+  JOSEPH(f.prf, kr, uf, dr, kf);
+  JOSEPH(f.pff, kf, uf, df, kf);
+  JOSEPH(f.pra, kr, ua, dr, ka);
+  JOSEPH(f.pfa, kf, ua, df, ka);
+  JOSEPH(f.paa, ka, ua, da, ka);
+  JOSEPH(f.prg, kr, ug, dr, kg);
+  JOSEPH(f.pfg, kf, ug, df, kg);
+  JOSEPH(f.pag, ka, ug, da, kg);
+  JOSEPH(f.pgg, kg, ug, dg, kg);
+  JOSEPH(f.prm, kr, um, dr, km);
+  JOSEPH(f.pfm, kf, um, df, km);
+  JOSEPH(f.pam, ka, um, da, km);
+  JOSEPH(f.pgm, kg, um, dg, km);
+  JOSEPH(f.pmm, km, um, dm, km);
+  f.quad = fma(e * e, inv, f.quad);
+  acc_mul(f.L, S);
+}
+
 // ------------------------------------------------------------ model 1 step
 struct F2 {
   double xr, xf, prr, prf, pff, quad;
@@ -247,6 +325,52 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
         const TOARec r = rn;
         rn = load_rec(rec, k + 1 < ke ? k + 1 : k);
         step2(f, r, ss2, efac2);
+      }
+      st = f.st;
+      ll = finish((double)(ke - kb), f.quad, f.L, st);
+    } else if (MODEL == 4) {
+      const int c0 = 6 * p, cc = 6 * a.P;
+      const double lsr = load_param(a, c0, s), lgr = load_param(a, c0 + 1, s);
+      const double efac = load_param(a, c0 + 2, s), leq = load_param(a, c0 + 3, s);
+      const double lsd = load_param(a, c0 + 4, s), lgd = load_param(a, c0 + 5, s);
+      const double la = load_param(a, cc, s), gc = load_param(a, cc + 1, s);
+      const bool pnf = !(finite_d(lsr) && finite_d(lgr) && finite_d(efac) && finite_d(leq) &&
+                         finite_d(lsd) && finite_d(lgd) && finite_d(la) && finite_d(gc));
+      const double gr = exp10(lgr), sr = exp10(lsr), eq = exp10(leq);
+      const double gd = exp10(lgd), sd = exp10(lsd);
+      const double vr = sr * sr / (2.0 * gr), vd = sd * sd / (2.0 * gd);
+      const double vc = common_var(la, gc, a.mc);
+      const double efac2 = efac * efac, equad2 = eq * eq;
+      F5 f{};
+      f.prr = a.mc.s_r2;
+      f.pff = a.mc.s_f2;
+      f.paa = vr;
+      f.pgg = vc;
+      f.pmm = vd;
+      f.L = {1.0, 0};
+      f.st = pnf ? kPNF : 0;
+      const double ss2 = a.mc.ss2;
+      const RecPtr rec = (RecPtr)a.rec;
+      const ConstDPtr chrom = (ConstDPtr)a.chrom;
+      // the next record, its chromatic factor and both decays are fetched
+      // one step ahead (index clamped)
+      TOARec rn{};
+      double cn = 0.0, emn = 0.0, emdn = 0.0;
+      if (kb < ke) {
+        rn = load_rec(rec, kb);
+        cn = chrom[kb];
+        emn = expm1_k(-gr * rn.dt);
+        emdn = expm1_k(-gd * rn.dt);
+      }
+      for (int64_t k = kb; k < ke; ++k) {
+        const TOARec r = rn;
+        const double c = cn, em = emn, emd = emdn;
+        const int64_t kn = k + 1 < ke ? k + 1 : k;
+        rn = load_rec(rec, kn);
+        cn = chrom[kn];
+        emn = expm1_k(-gr * rn.dt);
+        emdn = expm1_k(-gd * rn.dt);
+        step5(f, r, c, em, emd, vr, vc, vd, efac2, equad2, ss2);
       }
       st = f.st;
       ll = finish((double)(ke - kb), f.quad, f.L, st);
@@ -516,7 +640,11 @@ hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st) {
 hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
                          hipStream_t st) {
   const bool big = block > 256;
-  if (model == 1 && !big)
+  if (model == 4 && !big)
+    hipLaunchKernelGGL((k_filter<4, 256>), dim3(grid), dim3(block), 0, st, a);
+  else if (model == 4)
+    hipLaunchKernelGGL((k_filter<4, 1024>), dim3(grid), dim3(block), 0, st, a);
+  else if (model == 1 && !big)
     hipLaunchKernelGGL((k_filter<1, 256>), dim3(grid), dim3(block), 0, st, a);
   else if (model == 1)
     hipLaunchKernelGGL((k_filter<1, 1024>), dim3(grid), dim3(block), 0, st, a);
