@@ -21,6 +21,11 @@ S_NONPD, S_NONFINITE = 1, 2
 if not os.path.exists(LIB_PATH):
     raise ImportError("libargus.so is not built: run `python paper_2510_11077_amd/build.py`")
 
+# PyTorch ships its own HIP runtime; it is loaded first so that libargus
+# binds to that same runtime (two runtimes in one process do not share
+# devices, streams or allocations).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 
