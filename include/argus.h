@@ -90,8 +90,9 @@ typedef struct {
 /* Copies the data to the device, orders the joint stream by (t, pulsar),
  * and precomputes per-TOA intervals, the common-process decay and (model 4)
  * the chromatic factors. C = 2 (model 1), 4P + 2 (models 2, 3) or 6P + 2
- * (model 4). Synchronises. Model 4 has the likelihood and its per-pulsar
- * terms; the other calls return ARGUS_E_UNSUPPORTED for it. */
+ * (model 4). Synchronises. Model 4 has the likelihood, its per-pulsar
+ * terms, the gradient (tangent sweep) and the samplers; the plain baseline
+ * and the smoother return ARGUS_E_UNSUPPORTED for it. */
 int argus_dataset_create(const argus_dataset_desc* desc, argus_dataset_t* out);
 int argus_dataset_destroy(argus_dataset_t ds);
 /* D = number of free parameters (columns of theta). */
@@ -114,7 +115,7 @@ int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S,
 int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S,
                         double* logl, int32_t* status, void* stream);
 
-/* logL and its gradient w.r.t. the D free parameters (models 1, 2) (paper:
+/* logL and its gradient w.r.t. the D free parameters (models 1, 2, 4) (paper:
  * Functionality, "Sampler Integration": samplers consume the likelihood and
  * its gradient). grad: dev [S*D] row-major FP64, caller-owned; rows of
  * failed samples (status != 0) are 0. By default a tangent (forward-mode)
@@ -122,14 +123,15 @@ int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S,
  * direction in one pass; the first call for a new S chooses, by timing, how
  * many directions each wave carries (synchronises). With the environment
  * variable ARGUS_GRAD=adjoint the reverse-mode sweep with checkpointed
- * filter states is used instead; both give the derivative of the same
- * recursion. Model 3 returns ARGUS_E_UNSUPPORTED. */
+ * filter states is used instead (models 1, 2; model 4 always uses the
+ * tangent sweep); both give the derivative of the same recursion. Model 3
+ * returns ARGUS_E_UNSUPPORTED. */
 int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64_t S,
                        double* logl, double* grad, int32_t* status,
                        void* stream);
 
 /* One Hamiltonian Monte Carlo transition for each of S independent chains
- * (models 1, 2), the gradient-based sampling the likelihood and its
+ * (models 1, 2, 4), the gradient-based sampling the likelihood and its
  * gradient serve (paper: Functionality, "Sampler Integration"). Chain s
  * draws its momentum p = z_s / sqrt(inv_mass) (M = diag(1 / inv_mass)),
  * takes n_leapfrog >= 1 kick-drift-kick steps of size eps[s] on
@@ -153,7 +155,7 @@ int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog, const doub
                    double* grad, int32_t* accepted, double* energy_err, void* stream);
 
 /* One No-U-Turn Sampler transition for each of S independent chains (models
- * 1, 2): the sampler of the paper's posteriors (Functionality, "Sampler
+ * 1, 2, 4): the sampler of the paper's posteriors (Functionality, "Sampler
  * Integration", and its figure: NUTS, Hoffman & Gelman 2014), with
  * multinomial trajectory sampling and the generalised no-U-turn criterion.
  * Per chain: momentum p = z_s / sqrt(inv_mass); doubling j (< max_depth)

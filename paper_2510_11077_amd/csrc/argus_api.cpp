@@ -570,8 +570,8 @@ extern "C" int argus_loglike_grad(argus_dataset_t ds, const double* theta, int64
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
   if (ds->D > 0 && !grad) return fail(ARGUS_E_INVAL, "grad is NULL");
-  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
-    return fail(ARGUS_E_UNSUPPORTED, "the gradient covers models 1 and 2");
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "the gradient covers models 1, 2 and 4");
   return grad_loglike(ds, theta, S, logl, grad, status, (hipStream_t)stream);
 }
 
@@ -582,8 +582,8 @@ extern "C" int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog,
                               double* energy_err, void* stream) {
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
-    return fail(ARGUS_E_UNSUPPORTED, "HMC needs the gradient (models 1 and 2)");
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "HMC needs the gradient (models 1, 2 and 4)");
   if (ds->D < 1) return fail(ARGUS_E_INVAL, "HMC needs at least one free parameter");
   if (n_leapfrog < 1) return fail(ARGUS_E_INVAL, "n_leapfrog must be >= 1");
   if (!eps || !inv_mass || !lo || !hi || !z || !logu || !grad || !accepted)
@@ -600,8 +600,8 @@ extern "C" int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth,
                                int32_t* divergent, double* accept_stat, void* stream) {
   int rc = check_call(ds, theta, S, logl);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
-    return fail(ARGUS_E_UNSUPPORTED, "NUTS needs the gradient (models 1 and 2)");
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "NUTS needs the gradient (models 1, 2 and 4)");
   if (ds->D < 1) return fail(ARGUS_E_INVAL, "NUTS needs at least one free parameter");
   if (max_depth < 1 || max_depth > 10) return fail(ARGUS_E_INVAL, "max_depth must be in [1, 10]");
   if (!eps || !inv_mass || !lo || !hi || !z || !dirs || !u_top || !u_sub || !grad || !depth ||

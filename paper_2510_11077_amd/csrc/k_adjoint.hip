@@ -454,6 +454,7 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
 // filters for shorter serial chains. One pass, no checkpoints.
 struct TanArgs {
   const TOARec* rec;
+  const double* chrom;   // [N] chromatic factor per TOA (model 4)
   const int64_t* off;
   const double* theta;
   const int32_t* col;
@@ -462,7 +463,7 @@ struct TanArgs {
   int32_t* counter;
   double* part;          // [P*S]
   int32_t* pstat;        // [P*S]
-  double* gpart;         // [P * 6 * S]
+  double* gpart;         // [P * 6 * S] (model 4: [P * 8 * S])
   int64_t S;
   int32_t D, P, n_items, ngroups;
   ModelConst mc;
@@ -683,6 +684,237 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
   }
 }
 
+// Tangent sweep of model 4 (state [r, f, a, g, m], h = [1, 0, 1, 1, c] with
+// the chromatic factor c of each TOA): the same differentiated recursion
+// over five states. dF is diagonal, nonzero at a (red decay, its rate) and
+// m (DM decay, its rate), so (dF P F^T + F P dF^T)_ij = dF_ii (F P)_ji +
+// dF_jj (F P)_ij. Eight directions per pulsar: log10 sigma_red,
+// log10 gamma_red, EFAC, log10 EQUAD, log10 sigma_dm, log10 gamma_dm,
+// log10 A, gamma. Matrices are kept as lower triangles (index si(i, j)).
+__host__ __device__ constexpr int si5(int i, int j) {
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+__device__ __forceinline__ constexpr bool h5(int i) { return i != 1; }
+
+template <int ND>
+__global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
+  constexpr int NS = 5, NP = 15;
+  const int lane = threadIdx.x & (kWave - 1);
+  const RecPtr rec = (RecPtr)a.rec;
+  const ConstDPtr chrom = (ConstDPtr)a.chrom;
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int it = __builtin_amdgcn_readfirstlane(v);
+    if (it >= a.n_items * a.ngroups) break;
+    const int base = it / a.ngroups, grp = it - base * a.ngroups;
+    const int tile = a.items[2 * base];
+    const int p = a.items[2 * base + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int64_t kb = a.off[p], N = a.off[p + 1] - kb;
+
+    const int c0 = 6 * p, cc = 6 * a.P;
+    const double t0 = tprm(a, c0, s), t1 = tprm(a, c0 + 1, s), t2 = tprm(a, c0 + 2, s);
+    const double t3 = tprm(a, c0 + 3, s), t4 = tprm(a, c0 + 4, s), t5 = tprm(a, c0 + 5, s);
+    const double t6 = tprm(a, cc, s), t7 = tprm(a, cc + 1, s);
+    const bool pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) &&
+                       finite_d(t4) && finite_d(t5) && finite_d(t6) && finite_d(t7));
+    const double gr = exp10(t1), sr = exp10(t0), eq = exp10(t3);
+    const double gd = exp10(t5), sdm = exp10(t4);
+    const double vr = sr * sr / (2.0 * gr), vd = sdm * sdm / (2.0 * gd);
+    const double gm1 = t7 - 1.0;
+    const double vc = exp(2.0 * kLn10 * t6 + (t7 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+                      (12.0 * kPi * kPi * gm1);
+    const double efac2 = t2 * t2, equad2 = eq * eq, ss2 = a.mc.ss2;
+    // each direction's sources: variances (red, common, DM), rates (red,
+    // DM), white-noise terms
+    double sv[ND], sg[ND], sc[ND], sd[ND], sgd[ND], sr2[ND], sq2[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const int dir = grp * ND + j;
+      sv[j] = dir == 0 ? 2.0 * kLn10 * vr : (dir == 1 ? -kLn10 * vr : 0.0);
+      sg[j] = dir == 1 ? kLn10 * gr : 0.0;
+      sr2[j] = dir == 2 ? 2.0 * t2 : 0.0;
+      sq2[j] = dir == 3 ? 2.0 * kLn10 * equad2 : 0.0;
+      sd[j] = dir == 4 ? 2.0 * kLn10 * vd : (dir == 5 ? -kLn10 * vd : 0.0);
+      sgd[j] = dir == 5 ? kLn10 * gd : 0.0;
+      sc[j] = dir == 6 ? 2.0 * kLn10 * vc
+                       : (dir == 7 ? vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / gm1) : 0.0);
+    }
+    // base state and tangents (prior P0 = diag(s_r^2, s_f^2, v_r, v_c, v_d))
+    double x[NS] = {0.0, 0.0, 0.0, 0.0, 0.0}, P[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = 0.0;
+    P[si5(0, 0)] = a.mc.s_r2;
+    P[si5(1, 1)] = a.mc.s_f2;
+    P[si5(2, 2)] = vr;
+    P[si5(3, 3)] = vc;
+    P[si5(4, 4)] = vd;
+    double dx[ND][NS], dP[ND][NP], dl[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) dx[j][i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) dP[j][i] = 0.0;
+      dP[j][si5(2, 2)] = sv[j];
+      dP[j][si5(3, 3)] = sc[j];
+      dP[j][si5(4, 4)] = sd[j];
+      dl[j] = 0.0;
+    }
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+
+    for (int64_t k = 0; k < N; ++k) {
+      const TOARec r = load_rec(rec, kb + k);
+      const double c = chrom[kb + k];
+      const double dt = r.dt;
+      const double em = expm1_k(-gr * dt), emd = expm1_k(-gd * dt);
+      const double ph = 1.0 + em, phd = 1.0 + emd, phc = r.phc;
+      const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
+      const double dg[NS] = {1.0, 1.0, ph, phc, phd};  // diagonal part of F
+      // F P (posterior), needed by the tangents: row i of F times P
+      double FP[NS][NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        FP[0][j] = fma(dt, P[si5(1, j)], P[si5(0, j)]);
+#pragma unroll
+        for (int i = 1; i < NS; ++i) FP[i][j] = dg[i] * P[si5(i, j)];
+      }
+      // base predict
+      double xm[NS], Pm[NP];
+      xm[0] = fma(dt, x[1], x[0]);
+#pragma unroll
+      for (int i = 1; i < NS; ++i) xm[i] = dg[i] * x[i];
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+          Pm[si5(i, j)] = j == 0 ? fma(dt, FP[i][1], FP[i][0]) : dg[j] * FP[i][j];
+      Pm[si5(0, 0)] += ss2 * r.h3;
+      Pm[si5(1, 0)] += ss2 * r.h2;
+      Pm[si5(1, 1)] += ss2 * dt;
+      Pm[si5(2, 2)] = fma(vr, qf, Pm[si5(2, 2)]);
+      Pm[si5(3, 3)] = fma(vc, r.qcu, Pm[si5(3, 3)]);
+      Pm[si5(4, 4)] = fma(vd, qfd, Pm[si5(4, 4)]);
+      const double hw[NS] = {1.0, 0.0, 1.0, 1.0, c};
+      double u[NS], hx = 0.0;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < NS; ++l)
+          if (h5(l)) t = fma(hw[l], Pm[si5(i, l)], t);
+        u[i] = t;
+        if (h5(i)) hx = fma(hw[i], xm[i], hx);
+      }
+      double hu = 0.0;
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if (h5(i)) hu = fma(hw[i], u[i], hu);
+      const double S = hu + fma(efac2, r.s2, equad2);
+      const double e = r.y - hx;
+      const double inv = rcp_nr(S);
+      double K[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) K[i] = u[i] * inv;
+      const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);
+      // tangents
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        const double dph = -dt * ph * sg[j], dphd = -dt * phd * sgd[j];
+        const double ddg[NS] = {0.0, 0.0, dph, 0.0, dphd};  // dF (diagonal)
+        // dx- = F dx + dF x
+        double ddx[NS];
+        ddx[0] = fma(dt, dx[j][1], dx[j][0]);
+        ddx[1] = dx[j][1];
+        ddx[2] = fma(ph, dx[j][2], dph * x[2]);
+        ddx[3] = phc * dx[j][3];
+        ddx[4] = fma(phd, dx[j][4], dphd * x[4]);
+        // dP- = F dP F^T + dF_ii (F P)_qi + dF_qq (F P)_iq + dQ
+        double FD[NS][NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          FD[0][q] = fma(dt, dP[j][si5(1, q)], dP[j][si5(0, q)]);
+#pragma unroll
+          for (int i = 1; i < NS; ++i) FD[i][q] = dg[i] * dP[j][si5(i, q)];
+        }
+        double D[NP];
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+          for (int q = 0; q <= i; ++q) {
+            double t = q == 0 ? fma(dt, FD[i][1], FD[i][0]) : dg[q] * FD[i][q];
+            if (i == 2 || i == 4) t = fma(ddg[i], FP[q][i], t);
+            if (q == 2 || q == 4) t = fma(ddg[q], FP[i][q], t);
+            D[si5(i, q)] = t;
+          }
+        D[si5(2, 2)] += fma(sv[j], qf, -2.0 * vr * ph * dph);
+        D[si5(3, 3)] = fma(sc[j], r.qcu, D[si5(3, 3)]);
+        D[si5(4, 4)] += fma(sd[j], qfd, -2.0 * vd * phd * dphd);
+        // update
+        double du[NS], de = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          double t = 0.0;
+#pragma unroll
+          for (int l = 0; l < NS; ++l)
+            if (h5(l)) t = fma(hw[l], D[si5(i, l)], t);
+          du[i] = t;
+          if (h5(i)) de = fma(-hw[i], ddx[i], de);
+        }
+        double hdu = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+          if (h5(i)) hdu = fma(hw[i], du[i], hdu);
+        const double dS = hdu + fma(sr2[j], r.s2, sq2[j]);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const double dk = fma(-K[i], dS, du[i]) * inv;
+          dx[j][i] = fma(dk, e, fma(K[i], de, ddx[i]));
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+          for (int q = 0; q <= i; ++q)
+            dP[j][si5(i, q)] =
+                fma(dS * K[i], K[q], fma(-du[i], K[q], fma(-K[i], du[q], D[si5(i, q)])));
+        dl[j] = fma(-0.5, fma(dS, hS, 2.0 * ei * de), dl[j]);
+      }
+      // base update (the likelihood kernel's Joseph form)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) x[i] = fma(K[i], e, xm[i]);
+      double dd[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) dd[i] = fma(S, K[i], -u[i]);
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+#pragma unroll
+        for (int q = 0; q <= i; ++q)
+          P[si5(i, q)] = fma(dd[i], K[q], fma(-K[i], u[q], Pm[si5(i, q)]));
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e, ei, quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    }
+    if (valid) {
+      if (grp == 0) {
+        double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+        if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+        a.part[(int64_t)p * a.S + s] = stat ? -INFINITY : ll;
+        a.pstat[(int64_t)p * a.S + s] = stat;
+      }
+      double* g = a.gpart + (int64_t)p * 8 * a.S + s;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) g[(int64_t)(grp * ND + j) * a.S] = dl[j];
+    }
+  }
+}
+
 // grad[s, c] from the per-pulsar parts, one thread per element (consecutive
 // threads on consecutive columns of a row, so the rows are written whole): a
 // pulsar's own parameters from its filter, the common ones summed over
@@ -696,14 +928,16 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const double* gpart, const 
   const int c = (int)(i - s * D);
   const int k = icol[c];  // canonical parameter of column c
   double v;
+  // per pulsar: kp own parameters, np gradient parts (own + the two common)
+  const int kp = model == 4 ? 6 : 4, np = kp + 2;
   if (model == 1) {
     v = gpart[(int64_t)k * S + s];
-  } else if (k < 4 * P) {
-    v = gpart[((int64_t)(k >> 2) * 6 + (k & 3)) * S + s];
+  } else if (k < kp * P) {
+    v = gpart[((int64_t)(k / kp) * np + (k % kp)) * S + s];
   } else {
-    const int j = k - 4 * P;
+    const int j = k - kp * P;
     v = 0.0;
-    for (int p = 0; p < P; ++p) v += gpart[((int64_t)p * 6 + 4 + j) * S + s];
+    for (int p = 0; p < P; ++p) v += gpart[((int64_t)p * np + kp + j) * S + s];
   }
   grad[i] = status[s] != 0 ? 0.0 : v;
 }
@@ -732,6 +966,7 @@ int grad_finish(argus_dataset* ds, Workspace* w, int64_t S, double* logl, double
 int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nd, hipStream_t st) {
   TanArgs a{};
   a.rec = ds->rec.as<TOARec>();
+  a.chrom = ds->chrom.as<double>();
   a.off = ds->off.as<int64_t>();
   a.theta = theta;
   a.col = ds->col.as<int32_t>();
@@ -746,12 +981,19 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nd,
   a.P = ds->P;
   a.n_items = w->n_items;
   a.mc = ds->mc;
-  const int ndir = ds->model == 1 ? 2 : 6;
+  const int ndir = ds->model == 1 ? 2 : (ds->model == 4 ? 8 : 6);
   a.ngroups = ndir / nd;
   const int64_t waves = std::max<int64_t>(
       4, std::min<int64_t>((int64_t)w->n_items * a.ngroups, 8LL * ds->n_cu));
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-  if (ds->model == 1)
+  if (ds->model == 4) {
+    if (nd == 4)
+      hipLaunchKernelGGL((k_tangent5<4>), grid, block, 0, st, a);
+    else if (nd == 2)
+      hipLaunchKernelGGL((k_tangent5<2>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_tangent5<1>), grid, block, 0, st, a);
+  } else if (ds->model == 1)
     hipLaunchKernelGGL((k_tangent<1, 2>), grid, block, 0, st, a);
   else if (nd == 6)
     hipLaunchKernelGGL((k_tangent<2, 6>), grid, block, 0, st, a);
@@ -775,13 +1017,17 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
   int rc = ARGUS_OK;
   Workspace* w = get_workspace(ds, S, &rc);
   if (!w) return rc;
-  if (w->gpart.p == nullptr && (rc = w->gpart.alloc((size_t)ds->P * 6 * S * sizeof(double))))
+  const int gstride = ds->model == 4 ? 8 : 6;  // gradient parts per pulsar
+  if (w->gpart.p == nullptr &&
+      (rc = w->gpart.alloc((size_t)ds->P * gstride * S * sizeof(double))))
     return rc;
   if (w->tan_nd == 0) {
     const char* forced = std::getenv("ARGUS_TAN_ND");
     int nd = forced ? std::atoi(forced) : 0;
     if (ds->model == 1) nd = 2;
-    if (nd == 1 || nd == 2 || nd == 3 || nd == 6) {
+    const bool ok = ds->model == 4 ? (nd == 1 || nd == 2 || nd == 4)
+                                   : (nd == 1 || nd == 2 || nd == 3 || nd == 6);
+    if (ok) {
       w->tan_nd = nd;
     } else {
       hipEvent_t e0, e1;
@@ -790,7 +1036,9 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
       float best = 1e30f;
       int pick = 6;
       w->grad_log.clear();
-      for (int c : {6, 3, 2, 1}) {
+      const std::vector<int> splits =
+          ds->model == 4 ? std::vector<int>{4, 2, 1} : std::vector<int>{6, 3, 2, 1};
+      for (int c : splits) {
         float m = 1e30f;
         for (int rep = 0; rep < 3 && rc == ARGUS_OK; ++rep) {
           if (hipEventRecord(e0, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
@@ -890,7 +1138,7 @@ AdjArgs adjoint_args(argus_dataset* ds, Workspace* w, const double* theta, int64
 int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl, double* grad,
                  int32_t* status, hipStream_t st) {
   const char* mode = std::getenv("ARGUS_GRAD");
-  if (!(mode && std::strcmp(mode, "adjoint") == 0))
+  if (!(mode && std::strcmp(mode, "adjoint") == 0) || ds->model == 4)
     return tangent_loglike(ds, theta, S, logl, grad, status, st);
   int rc = ARGUS_OK;
   Workspace* w = get_workspace(ds, S, &rc);

@@ -93,11 +93,82 @@ def test_dm_forced_layouts(argus, orc, cfg, monkeypatch):
     run(argus, orc, d, pi.sample_theta(d, 200, 15))
 
 
-def test_dm_unsupported_calls(argus):
+def test_dm_smoother_unsupported(argus):
     d = pi.make_pta_dm("t", n_psr=2, counts=[5, 6], seed=55)
     ds = argus.Dataset(d)
-    th = dev(pi.sample_theta(d, 2, 1))
-    with pytest.raises(argus.ArgusError, match="gradient"):
-        ds.loglike_grad(th)
     with pytest.raises(argus.ArgusError, match="smoother"):
-        ds.smooth(th)
+        ds.smooth(dev(pi.sample_theta(d, 2, 1)))
+
+
+# ------------------------------------------------------------------ gradient
+def check_grad(g, gref, tol=1e-9):
+    """As for the other models: ||g - g_ref||_inf <= tol max(||g_ref||_inf, 1)
+    per row and, per component, tol (|g_ref,j| + 1e-3 ||g_ref||_inf)."""
+    for s in range(gref.shape[0]):
+        inf = np.abs(gref[s]).max()
+        d = np.abs(g[s] - gref[s])
+        assert d.max() <= tol * max(inf, 1.0), (s, d.max(), inf)
+        assert (d <= tol * (np.abs(gref[s]) + 1e-3 * inf)).all(), s
+
+
+@pytest.mark.parametrize("nd", ["", "1", "2", "4"])
+def test_dm_gradient(argus, orc, nd, monkeypatch):
+    """The model-4 tangent sweep (eight directions per pulsar, split over
+    8 / nd waves; "" lets the first call choose) against the oracle's
+    complex-step derivative, ragged pulsars and tiles."""
+    if nd:
+        monkeypatch.setenv("ARGUS_TAN_ND", nd)
+    else:
+        monkeypatch.delenv("ARGUS_TAN_ND", raising=False)
+    d = pi.make_pta_dm("t", n_psr=5, counts=[1, 0, 7, 37, 130], seed=56)
+    th = pi.sample_theta(d, 70, 16)
+    ds = argus.Dataset(d)
+    ll, g, st = ds.loglike_grad(dev(th))
+    assert (st.cpu().numpy() == 0).all()
+    gref = orc.grad_cs(d, d.to_canon(th), which=d.free_idx)
+    check_grad(g.cpu().numpy(), gref)
+    ref, _ = orc.loglike(d, d.to_canon(th))
+    assert (np.abs(ll.cpu().numpy() - ref) <= TOL * np.maximum(np.abs(ref), 1)).all()
+
+
+def test_dm_gradient_long_pulsar_and_free_mask(argus, orc):
+    d = pi.make_pta_dm("t", n_psr=2, counts=[2000, 333], seed=57)
+    d.free = np.zeros(d.truth.size, bool)
+    d.free[[0, 1, 4, 5, 8, 10, 11, 12, 13]] = True
+    th = pi.sample_theta(d, 64, 17)
+    ds = argus.Dataset(d)
+    _, g, _ = ds.loglike_grad(dev(th))
+    check_grad(g.cpu().numpy(), orc.grad_cs(d, d.to_canon(th), which=d.free_idx))
+
+
+def test_dm_hmc_transition(argus, orc):
+    """One HMC transition of the DM model against the oracle transition on
+    the same draws (the sampler sees model 4 through the gradient)."""
+    import torch
+    from oracle import hmc
+    d = pi.make_pta_dm("t", n_psr=2, counts=[40, 25], seed=58)
+    S, L = 16, 3
+    th0 = pi.theta_near_truth(d, S, 18, scale=0.02)
+    width = d.hi - d.lo
+    inv_mass = (0.01 * width) ** 2
+    rng = np.random.default_rng(19)
+    z = rng.normal(size=th0.shape)
+    logu = np.log(rng.random(S))
+    ds = argus.Dataset(d)
+    t = dev(th0)
+    ll, g, _ = ds.loglike_grad(t)
+    acc = torch.zeros(S, dtype=torch.int32, device="cuda")
+    dh = torch.empty(S, dtype=torch.float64, device="cuda")
+    ds.hmc_step(t, ll, g, dev(np.full(S, 0.2)), dev(inv_mass), dev(d.lo), dev(d.hi), dev(z),
+                dev(logu), L, acc, dh)
+    f = hmc.oracle_target(d, orc)
+    l0, g0 = f(th0)
+    rt, rl, _, racc, rdh = hmc.transition(th0, l0, g0, np.full(S, 0.2), inv_mass, d.lo, d.hi,
+                                          z, logu, L, f)
+    clear = np.abs(logu + rdh) > 1e-5
+    assert np.array_equal(acc.cpu().numpy().astype(bool)[clear], racc[clear])
+    fin = np.isfinite(rdh)
+    assert (np.abs(dh.cpu().numpy()[fin] - rdh[fin]) <= 1e-6 + 1e-9 * np.abs(l0[fin])).all()
+    a = racc & clear
+    disp = np.max(np.abs(rt[a] - th0[a]), axis=1, keepdims=True)
+    assert (np.abs(t.cpu().numpy()[a] - rt[a]) <= 1e-7 * disp).all()
