@@ -90,7 +90,7 @@ int validate(const argus_dataset_desc* d) {
     if (d->toa_off[p + 1] < d->toa_off[p])
       return fail(ARGUS_E_INVAL, "toa_off must be non-decreasing");
   const int64_t N = d->toa_off[d->n_psr];
-  if (N > (int64_t)1 << 31) return fail(ARGUS_E_UNSUPPORTED, "too many TOAs");
+  if (N > INT32_MAX) return fail(ARGUS_E_UNSUPPORTED, "too many TOAs (at most 2^31 - 1)");
   if (N > 0 && (!d->t || !d->y || !d->sigma))
     return fail(ARGUS_E_INVAL, "t, y and sigma are required");
   for (int p = 0; p < d->n_psr; ++p)

@@ -72,7 +72,12 @@ __constant__ double kExpm1Coef[12] = {
     1.0 / 720.0,      1.0 / 5040.0,      1.0 / 40320.0,     1.0 / 362880.0,
     1.0 / 3628800.0,  1.0 / 39916800.0,  1.0 / 479001600.0, 1.0 / 6227020800.0};
 
-__device__ __forceinline__ double expm1_k(double x) {
+// c13 is the top coefficient 1/13!, passed in so that a loop can hold it in
+// a VGPR: the first Horner step then reads one SGPR (the next coefficient)
+// instead of needing a copy. The clamp keeps the conversion of k to int
+// defined; 2^k is 0 below k = -1075 either way. For k = 0 the last fma
+// returns p exactly.
+__device__ __forceinline__ double expm1_v(double x, double c13) {
   const double kInvLn2 = 1.44269504088896338700;
   const double kLn2Hi = 6.93147180369123816490e-01;
   const double kLn2Lo = 1.90821492927058770002e-10;
@@ -80,13 +85,29 @@ __device__ __forceinline__ double expm1_k(double x) {
   double r = __builtin_fma(-kf, kLn2Hi, x);
   r = __builtin_fma(-kf, kLn2Lo, r);
   // Q(r) = sum_{n=2}^{13} r^(n-2) / n!
-  double q = kExpm1Coef[11];
+  double q = __builtin_fma(c13, r, kExpm1Coef[10]);
 #pragma unroll
-  for (int i = 10; i >= 0; --i) q = __builtin_fma(q, r, kExpm1Coef[i]);
+  for (int i = 9; i >= 0; --i) q = __builtin_fma(q, r, kExpm1Coef[i]);
   const double p = __builtin_fma(r * r, q, r);      // expm1(r)
-  const int k = (int)kf;
-  const double t = __builtin_ldexp(1.0, k < -1100 ? -1100 : k);
-  return k == 0 ? p : __builtin_fma(t, p, t - 1.0);
+  const double t = __builtin_ldexp(1.0, (int)__builtin_fmax(kf, -1100.0));
+  return __builtin_fma(t, p, t - 1.0);
+}
+__device__ __forceinline__ double expm1_k(double x) { return expm1_v(x, kExpm1Coef[11]); }
+
+// A copy of a wave-uniform value held in a VGPR, so that FP64 operations
+// pairing it with a per-TOA SGPR operand need no register copy (a VOP3
+// instruction reads at most one SGPR).
+__device__ __forceinline__ double in_vgpr(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Orders the fetch pipeline of the filter loops: the record whose first
+// field is d (fetched one step earlier) is waited for here, and no later
+// memory access is moved above this point, so the fetch issued next has a
+// whole step to arrive (a scalar-load wait covers every load in flight).
+__device__ __forceinline__ void sgpr_ready(double d) {
+  asm volatile("" ::"s"(d) : "memory");
 }
 
 // 1/S from the hardware reciprocal refined by two Newton steps (error within

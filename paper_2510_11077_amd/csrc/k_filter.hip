@@ -308,7 +308,10 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
-    const int64_t kb = a.off[p], ke = a.off[p + 1];
+    // TOA range of the pulsar (wave-uniform; the host bounds N below 2^31),
+    // so the record index and loop control live in SGPRs
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int ke = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]);
     double ll;
     int st;
     if (MODEL == 1) {
@@ -321,7 +324,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       // the next record is fetched one step ahead (index clamped)
       TOARec rn{};
       if (kb < ke) rn = load_rec(rec, kb);
-      for (int64_t k = kb; k < ke; ++k) {
+      for (int k = kb; k < ke; ++k) {
         const TOARec r = rn;
         rn = load_rec(rec, k + 1 < ke ? k + 1 : k);
         step2(f, r, ss2, efac2);
@@ -352,25 +355,27 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       const double ss2 = a.mc.ss2;
       const RecPtr rec = (RecPtr)a.rec;
       const ConstDPtr chrom = (ConstDPtr)a.chrom;
+      const double ss2v = in_vgpr(ss2), c13 = in_vgpr(kExpm1Coef[11]);
       // the next record, its chromatic factor and both decays are fetched
-      // one step ahead (index clamped)
+      // one step ahead (index clamped; with twice the per-pulsar state of
+      // model 2 there are not enough SGPRs for a second record in flight)
       TOARec rn{};
       double cn = 0.0, emn = 0.0, emdn = 0.0;
       if (kb < ke) {
         rn = load_rec(rec, kb);
         cn = chrom[kb];
-        emn = expm1_k(-gr * rn.dt);
-        emdn = expm1_k(-gd * rn.dt);
+        emn = expm1_v(-gr * rn.dt, c13);
+        emdn = expm1_v(-gd * rn.dt, c13);
       }
-      for (int64_t k = kb; k < ke; ++k) {
+      for (int k = kb; k < ke; ++k) {
         const TOARec r = rn;
         const double c = cn, em = emn, emd = emdn;
-        const int64_t kn = k + 1 < ke ? k + 1 : k;
+        const int kn = k + 1 < ke ? k + 1 : k;
         rn = load_rec(rec, kn);
         cn = chrom[kn];
-        emn = expm1_k(-gr * rn.dt);
-        emdn = expm1_k(-gd * rn.dt);
-        step5(f, r, c, em, emd, vr, vc, vd, efac2, equad2, ss2);
+        emn = expm1_v(-gr * rn.dt, c13);
+        emdn = expm1_v(-gd * rn.dt, c13);
+        step5(f, r, c, em, emd, vr, vc, vd, efac2, equad2, ss2v);
       }
       st = f.st;
       ll = finish((double)(ke - kb), f.quad, f.L, st);
@@ -395,20 +400,26 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       f.st = pnf ? kPNF : 0;
       const double ss2 = a.mc.ss2;
       const RecPtr rec = (RecPtr)a.rec;
-      // the next record and its red decay are fetched one step ahead (the
-      // index is clamped, so the last iteration repeats harmless work)
-      TOARec rn{};
-      double emn = 0.0;
+      const double ss2v = in_vgpr(ss2), c13 = in_vgpr(kExpm1Coef[11]);
+      // Two records in flight: step k waits for the record of step k + 1
+      // (fetched during step k - 1), evaluates its red decay, and fetches
+      // the record of step k + 2, so every scalar load has a whole step to
+      // arrive; the last steps refetch the final record (index clamped).
+      TOARec r1{}, r2{};
+      double em1 = 0.0;
       if (kb < ke) {
-        rn = load_rec(rec, kb);
-        emn = expm1_k(-gr * rn.dt);
+        r1 = load_rec(rec, kb);
+        r2 = load_rec(rec, kb + 1 < ke ? kb + 1 : kb);
+        em1 = expm1_v(-gr * r1.dt, c13);
       }
-      for (int64_t k = kb; k < ke; ++k) {
-        const TOARec r = rn;
-        const double em = emn;
-        rn = load_rec(rec, k + 1 < ke ? k + 1 : k);
-        emn = expm1_k(-gr * rn.dt);
-        step4(f, r, em, vr, vc, efac2, equad2, ss2);
+      for (int k = kb; k < ke; ++k) {
+        const TOARec r = r1;
+        const double em = em1;
+        r1 = r2;
+        sgpr_ready(r1.dt);
+        r2 = load_rec(rec, k < ke - 2 ? k + 2 : ke - 1);
+        em1 = expm1_v(-gr * r1.dt, c13);
+        step4(f, r, em, vr, vc, efac2, equad2, ss2v);
       }
       st = f.st;
       ll = finish((double)(ke - kb), f.quad, f.L, st);
