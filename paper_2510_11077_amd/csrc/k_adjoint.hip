@@ -495,7 +495,8 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
-    const int64_t kb = a.off[p], N = a.off[p + 1] - kb;
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
 
     // parameters, base constants and each direction's sources
     double gr = 1.0, vr = 0.0, vc = 0.0, efac2, equad2 = 0.0, ss2;
@@ -557,18 +558,26 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
     double quad = 0.0, lm = 1.0;
     int le = 0, stat = pnf ? kPNF : 0;
 
-    // the next record and its red decay one step ahead
-    TOARec rn{};
-    double emn = 0.0;
+    // Two records in flight: step k waits for the record of step k + 1,
+    // computes its red decay and fetches the record of step k + 2 (index
+    // clamped to the pulsar's last TOA). ss2 and the top expm1 coefficient
+    // are held in VGPRs (FP64 ops with a per-TOA SGPR operand need no copy).
+    ss2 = in_vgpr(ss2);
+    const double c13 = in_vgpr(kExpm1Coef[11]);
+    TOARec r1{}, r2{};
+    double em1 = 0.0;
     if (N > 0) {
-      rn = load_rec(rec, kb);
-      emn = expm1_k(-gr * rn.dt);
+      r1 = load_rec(rec, kb);
+      r2 = load_rec(rec, kb + (N > 1 ? 1 : 0));
+      em1 = expm1_v(-gr * r1.dt, c13);
     }
-    for (int64_t k = 0; k < N; ++k) {
-      const TOARec r = rn;
-      const double em = emn;
-      rn = load_rec(rec, kb + (k + 1 < N ? k + 1 : k));
-      emn = expm1_k(-gr * rn.dt);
+    for (int k = 0; k < N; ++k) {
+      const TOARec r = r1;
+      const double em = em1;
+      r1 = r2;
+      sgpr_ready(r1.dt);
+      r2 = load_rec(rec, kb + (k < N - 2 ? k + 2 : N - 1));
+      em1 = expm1_v(-gr * r1.dt, c13);
       const double dt = r.dt, phc = r.phc;
       const double ph = 1.0 + em, qfac = -em * (2.0 + em);
       // base predict
@@ -713,7 +722,8 @@ __global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
-    const int64_t kb = a.off[p], N = a.off[p + 1] - kb;
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
 
     const int c0 = 6 * p, cc = 6 * a.P;
     const double t0 = tprm(a, c0, s), t1 = tprm(a, c0 + 1, s), t2 = tprm(a, c0 + 2, s);
@@ -767,11 +777,26 @@ __global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
     double quad = 0.0, lm = 1.0;
     int le = 0, stat = pnf ? kPNF : 0;
 
-    for (int64_t k = 0; k < N; ++k) {
-      const TOARec r = load_rec(rec, kb + k);
-      const double c = chrom[kb + k];
+    // the next record, its chromatic factor and both decays one step ahead
+    // (index clamped); the top expm1 coefficient is held in a VGPR
+    const double c13 = in_vgpr(kExpm1Coef[11]);
+    TOARec rn{};
+    double cn = 0.0, emn = 0.0, emdn = 0.0;
+    if (N > 0) {
+      rn = load_rec(rec, kb);
+      cn = chrom[kb];
+      emn = expm1_v(-gr * rn.dt, c13);
+      emdn = expm1_v(-gd * rn.dt, c13);
+    }
+    for (int k = 0; k < N; ++k) {
+      const TOARec r = rn;
+      const double c = cn, em = emn, emd = emdn;
+      const int kn = kb + (k + 1 < N ? k + 1 : k);
+      rn = load_rec(rec, kn);
+      cn = chrom[kn];
+      emn = expm1_v(-gr * rn.dt, c13);
+      emdn = expm1_v(-gd * rn.dt, c13);
       const double dt = r.dt;
-      const double em = expm1_k(-gr * dt), emd = expm1_k(-gd * dt);
       const double ph = 1.0 + em, phd = 1.0 + emd, phc = r.phc;
       const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
       const double dg[NS] = {1.0, 1.0, ph, phc, phd};  // diagonal part of F
