@@ -67,7 +67,10 @@ def surrogate_leg(A, pi, dev, stream, log):
     yn = y.cpu().numpy()
     mu, sd = float(yn.mean()), float(yn.std())
     net = A.MLP(10, 256, 4096)
-    net.load(pi.mlp_weights(10, 256, 1), lo, hi, mu, sd)
+    # input box = the range of the training inputs: the network sees them
+    # mapped to [-1, 1] and rounded to BF16, so the prior box (25x wider
+    # than this data) would quantise the bulk to a few steps per axis
+    net.load(pi.mlp_weights(10, 256, 1), th.min(0), th.max(0), mu, sd)
     B, epochs = 4096, 12
     rng = np.random.default_rng(0)
     torch.cuda.synchronize()
@@ -113,6 +116,7 @@ def surrogate_leg(A, pi, dev, stream, log):
     for i in range(2):  # warm the fixed-size exact workspaces
         da.step(*draws[i])
     da.n_exact = da.n_prop = 0
+    da.acc.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(2, T):
@@ -120,6 +124,7 @@ def surrogate_leg(A, pi, dev, stream, log):
     torch.cuda.synchronize()
     da_s = time.perf_counter() - t0
     n_prop = da.n_prop
+    da_moves = int(da.acc.sum().item())
     # plain MH: every proposal evaluated exactly, in fixed buffers (so the
     # batched call replays its graph, as a well-written sampler would)
     cur = th0.clone()
@@ -130,6 +135,8 @@ def surrogate_leg(A, pi, dev, stream, log):
     prop = torch.empty_like(cur)
     llp = torch.empty_like(llc)
 
+    mh_moves = torch.zeros((), dtype=torch.int64, device=dev)
+
     def mh_step(i):
         eps, _, lu2 = draws[i]
         torch.add(cur, eps, out=prop)
@@ -137,11 +144,13 @@ def surrogate_leg(A, pi, dev, stream, log):
         acc = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu2 < llp - llc)
         torch.where(acc[:, None], prop, cur, out=cur)
         torch.where(acc, llp, llc, out=llc)
+        mh_moves.add_(acc.sum())
 
     for i in range(2):  # warm-up: graph capture for the fixed buffers
         mh_step(i)
     cur.copy_(th0)
     llc.copy_(ds5.loglike(cur, want_status=False)[0])
+    mh_moves.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(2, T):
@@ -152,10 +161,17 @@ def surrogate_leg(A, pi, dev, stream, log):
         "screened_proposals_per_s": n_prop / da_s,
         "plain_mh_proposals_per_s": n_prop / mh_s,
         "exact_evals_fraction": da.n_exact / n_prop,
+        # second-stage acceptance: accepted moves per exact evaluation (1 for
+        # a surrogate equal to the exact logL); accepted moves of both chains
+        "stage2_acceptance": da_moves / max(da.n_exact, 1),
+        "accepted_moves_da": da_moves,
+        "accepted_moves_plain_mh": int(mh_moves.item()),
         "iterations_timed": T - 2,
     }
-    log("DA: %.4g proposals/s screened vs %.4g plain MH, exact fraction %.3f"
-        % (n_prop / da_s, n_prop / mh_s, da.n_exact / n_prop))
+    log("DA: %.4g proposals/s screened vs %.4g plain MH, exact fraction %.3f, stage-2 "
+        "acceptance %.3f, accepted moves %d vs %d"
+        % (n_prop / da_s, n_prop / mh_s, da.n_exact / n_prop, da_moves / max(da.n_exact, 1),
+           da_moves, int(mh_moves.item())))
     return out
 
 

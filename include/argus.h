@@ -223,8 +223,10 @@ int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mea
  *   W4 [w] | b4 [1]          (n = w d + 2 w^2 + 4 w + 1)
  * The caller owns the master block and the Adam moments (device FP32); the
  * handle owns the BF16 copies and activation workspaces. Inputs are mapped
- * from the box [in_lo, in_hi] to [-1, 1]; the network predicts the
- * standardised target (logL - out_mu) / out_sd.
+ * from the box [in_lo, in_hi] to [-1, 1] and rounded to BF16 (8 significant
+ * bits), so the box should be the range of the training inputs rather than a
+ * much wider prior box; the network predicts the standardised target
+ * (logL - out_mu) / out_sd.
  * ------------------------------------------------------------------- */
 typedef struct argus_mlp* argus_mlp_t;
 

@@ -235,7 +235,8 @@ def test_trained_surrogate_saves_exact_evaluations(A):
     y_tr, _ = ds.loglike(t_tr)
     y = y_tr.cpu().numpy()
     net = A.MLP(10, 256, 2048)
-    net.load(pi.mlp_weights(10, 256, 2), lo, hi, float(y.mean()), float(y.std()))
+    net.load(pi.mlp_weights(10, 256, 2), th_tr.min(0), th_tr.max(0), float(y.mean()),
+             float(y.std()))
     rng = np.random.default_rng(0)
     epochs = 8
     for ep in range(epochs):
@@ -244,6 +245,12 @@ def test_trained_surrogate_saves_exact_evaluations(A):
         for b in range(0, th_tr.shape[0], 2048):
             sel = perm[b:b + 2048]
             net.train_step(t_tr[sel], y_tr[sel], lr)
+    # accuracy on held-out bulk points (the input box is the training
+    # inputs' range, so their BF16 inputs resolve the bulk)
+    t_ho = dev(pi.theta_near_truth(d, 4096, 402, scale=0.005))
+    err = (net.eval(t_ho) - ds.loglike(t_ho)[0]).abs().cpu().numpy()
+    print("held-out |dlogL|: median %.4f, within 0.1: %.4f" % (np.median(err), (err <= 0.1).mean()))
+    assert (err <= 0.1).mean() > 0.8  # 0.91 measured
     Q, T = 512, 40
     th0 = dev(pi.theta_near_truth(d, Q, 401, scale=0.002))
     step = (hi - lo) * 0.002
@@ -272,4 +279,6 @@ def test_trained_surrogate_saves_exact_evaluations(A):
     assert da.n_exact < 0.8 * n_mh_exact
     assert a_da / da.n_exact > a_mh / n_mh_exact
     assert a_da > 0.5 * a_mh
+    # an accurate surrogate: the exact filter confirms almost every move it passes
+    assert a_da / da.n_exact > 0.7  # 0.81 measured
     assert torch.isfinite(da.ll).all()
