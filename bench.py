@@ -317,6 +317,20 @@ def main():
             "flop_per_launch": flop,
         },
     }
+    # the published FP64 peak assumes the maximum engine clock; the FP64 FMA
+    # rate this device sustains with every SIMD busy, and its clock then
+    try:
+        tf, mhz = A.fp64_rate(1)
+        res["roofline"]["attainable"] = tf
+        res["roofline"]["frac_attainable"] = achieved / tf
+        res["roofline"]["attainable_note"] = (
+            "sustained FP64 FMA rate on this device, all 256 CUs busy (argus_fp64_rate, one "
+            "wave per SIMD); mean shader clock %.0f MHz against 2400 MHz for the published "
+            "peak" % mhz)
+        log("FP64 FMA rate under full load: %.1f TFLOP/s at %.0f MHz" % (tf, mhz))
+    except A.ArgusError as e:
+        res["roofline"]["attainable"] = None
+        res["roofline"]["attainable_note"] = "unavailable: %s" % e
 
     extra = {}
     if not args.no_extra:

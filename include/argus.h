@@ -285,6 +285,18 @@ int argus_da_stage2(const int32_t* idx, const int32_t* count, int64_t cap,
                     const double* theta_prop, double* theta_cur, double* ll_cur,
                     double* lh_cur, int32_t* acc, int32_t d, void* stream);
 
+/* Device diagnostic for roofline reports (not part of the method): the
+ * sustained FP64 FMA rate of the current device with every CU busy
+ * (one block per CU, waves_per_simd in 1..4 waves on each SIMD, four
+ * independent FMA chains per lane, about 1 ms), in TFLOP/s over the span
+ * from the first wave's start to the last wave's end on the device's wall
+ * clock, and the mean shader clock over the waves in MHz. The published
+ * FP64 peak assumes the maximum engine clock; under full FP64 load the clock
+ * settles lower, and this is the rate the FP64-VALU kernels can reach.
+ * Allocates and synchronises the stream; -> ARGUS_E_INVAL for bad
+ * arguments, ARGUS_E_HIP if the launch or a clock query fails. */
+int argus_fp64_rate(int32_t waves_per_simd, double* tflops, double* clock_mhz, void* stream);
+
 /* Human-readable launch configuration chosen for (ds, S), for reports. */
 int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len);
 

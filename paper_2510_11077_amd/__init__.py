@@ -54,6 +54,7 @@ _lib.argus_hmc_step.argtypes = [_V, C.c_int64, C.c_int32, _V, _V, _V, _V, _V, _V
                                 _V, _V, _V]
 _lib.argus_nuts_step.argtypes = [_V, C.c_int64, C.c_int32] + [_V] * 16
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
+_lib.argus_fp64_rate.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), _V]
 _lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)]
 _lib.argus_mlp_destroy.argtypes = [_V]
 _lib.argus_mlp_n_params.argtypes = [_V, C.POINTER(C.c_int64)]
@@ -331,6 +332,15 @@ def da_stage1(theta_prop, lo, hi, lh_cur, lh_prop, logu1, idx, count, work, stre
                                 lh_cur.data_ptr(), lh_prop.data_ptr(), logu1.data_ptr(), Q, d,
                                 idx.data_ptr(), count.data_ptr(), work.data_ptr(),
                                 _stream(stream)))
+
+
+def fp64_rate(waves_per_simd: int = 1, stream=None):
+    """Sustained FP64 FMA rate (TFLOP/s) and mean shader clock (MHz) of the
+    current device with every CU busy (argus_fp64_rate): the attainable
+    ceiling for FP64-VALU kernels, next to the published peak."""
+    tf, mhz = C.c_double(), C.c_double()
+    _check(_lib.argus_fp64_rate(int(waves_per_simd), C.byref(tf), C.byref(mhz), _stream(stream)))
+    return tf.value, mhz.value
 
 
 def da_work_size(Q: int) -> int:

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libargus.so")
 SOURCES = ["argus_api.cpp", "k_filter.hip", "k_scan.hip", "k_joint.hip", "k_adjoint.hip",
-           "k_hmc.hip", "k_nuts.hip", "k_mlp.hip"]
+           "k_hmc.hip", "k_nuts.hip", "k_mlp.hip", "k_probe.hip"]
 ARCH = os.environ.get("ARGUS_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",

@@ -611,6 +611,16 @@ extern "C" int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth,
                    grad, depth, n_leapfrog, divergent, accept_stat, (hipStream_t)stream);
 }
 
+extern "C" int argus_fp64_rate(int32_t waves_per_simd, double* tflops, double* clock_mhz,
+                               void* stream) {
+  if (!tflops || !clock_mhz) return fail(ARGUS_E_INVAL, "tflops and clock_mhz are required");
+  if (waves_per_simd < 1 || waves_per_simd > 4)
+    return fail(ARGUS_E_INVAL, "waves_per_simd must be 1..4");
+  // about 1 ms of FMAs at one wave per SIMD
+  return fp64_rate(waves_per_simd, 2000 / waves_per_simd, tflops, clock_mhz,
+                   (hipStream_t)stream);
+}
+
 extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
                             double* var, double* logl, int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, mean);

@@ -1,0 +1,35 @@
+"""argus_fp64_rate, the device diagnostic behind the bench's attainable FP64
+rate: it runs on every CU and returns a plausible rate and clock, and more
+waves per SIMD do not report more than the SIMDs can issue."""
+import math
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2510_11077_amd as A
+    return A
+
+
+def test_fp64_rate_is_plausible(A):
+    tf1, mhz1 = A.fp64_rate(1)
+    tf4, mhz4 = A.fp64_rate(4)
+    print("1 wave/SIMD: %.1f TFLOP/s at %.0f MHz; 4 waves/SIMD: %.1f at %.0f" % (tf1, mhz1, tf4, mhz4))
+    for tf, mhz in ((tf1, mhz1), (tf4, mhz4)):
+        assert math.isfinite(tf) and math.isfinite(mhz)
+        assert 300.0 < mhz < 3000.0
+        # 16 FP64 FMA lanes per SIMD per cycle at the measured clock bound the rate
+        assert 1.0 < tf <= 1.05 * 2 * 16 * 4 * 256 * mhz * 1e6 / 1e12
+
+
+def test_fp64_rate_rejects_bad_arguments(A):
+    with pytest.raises(A.ArgusError):
+        A.fp64_rate(0)
+    with pytest.raises(A.ArgusError):
+        A.fp64_rate(5)
