@@ -319,6 +319,7 @@ Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc) {
     std::vector<int32_t> items = make_items(ds->counts, S);
     w->n_items = (int)(items.size() / 2);
     if ((*rc = w->items.upload(items.data(), items.size() * sizeof(int32_t)))) return nullptr;
+    w->items_host = items;
     std::vector<int32_t> boff;
     std::vector<int32_t> bal = make_items_binned(ds->counts, S, 4 * ds->n_cu, &boff);
     w->n_items_bal = (int)(bal.size() / 2);
@@ -556,8 +557,14 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
                   w->cfg.order == 1 ? w->n_items_bal : w->n_items);
     s = b + w->tune_log;
   }
-  if (w && w->tan_nd) {
-    std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nd);
+  if (w && w->tan_nda) {
+    if (w->tan_nda == w->tan_ndb)
+      std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nda);
+    else
+      std::snprintf(b, sizeof b,
+                    "gradient: tangent sweep, %d directions per wave for pulsars of >= %lld "
+                    "TOAs, %d for the others\n",
+                    w->tan_nda, (long long)w->tan_thresh, w->tan_ndb);
     s += b + w->grad_log;
   }
   std::snprintf(buf, len, "%s", s.c_str());

@@ -81,8 +81,15 @@ struct Workspace {
   int64_t tot_seg = 0;
   int max_sub = 0, grad_waves = 0;
   bool grad_ready = false;
-  // tangent-mode gradient: directions per wave (0 = not tuned yet)
-  int tan_nd = 0;
+  // tangent-mode gradient: directions per wave, tan_nda for pulsars of at
+  // least tan_thresh TOAs and tan_ndb for the others (0 = not tuned yet),
+  // and the work units of the split they were built for
+  int tan_nda = 0, tan_ndb = 0;
+  int64_t tan_thresh = 0;
+  DevBuf tan_units;
+  int n_tan_units = 0, units_nda = 0, units_ndb = 0;
+  int64_t units_thresh = -1;
+  std::vector<int32_t> items_host;  // the items, as uploaded
   std::string grad_log;
   // HMC: proposal position, momentum, gradient, logL, initial energy, flags
   DevBuf hmc_x, hmc_p, hmc_g, hmc_l, hmc_h0, hmc_ok;

@@ -460,12 +460,15 @@ struct TanArgs {
   const int32_t* col;
   const double* fixed;
   const int32_t* items;  // (tile, pulsar), longest first
+  // k_tangent work units, longest first: (item index, group | ND << 8)
+  const int32_t* units;
+  int32_t n_units;
   int32_t* counter;
   double* part;          // [P*S]
   int32_t* pstat;        // [P*S]
   double* gpart;         // [P * 6 * S] (model 4: [P * 8 * S])
   int64_t S;
-  int32_t D, P, n_items, ngroups;
+  int32_t D, P, n_items;
   ModelConst mc;
 };
 
@@ -480,18 +483,13 @@ struct Tan {
   double dl;
 };
 
+// One work unit: the base filter of (tile, pulsar) and its directions
+// grp * ND .. grp * ND + ND - 1 (group 0 also writes the log-likelihood).
 template <int MODEL, int ND>
-__global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ void tangent_unit(const TanArgs& a, const int lane, const int tile,
+                                             const int p, const int grp) {
   const RecPtr rec = (RecPtr)a.rec;
-  for (;;) {
-    int v = 0;
-    if (lane == 0) v = atomicAdd(a.counter, 1);
-    const int it = __builtin_amdgcn_readfirstlane(v);
-    if (it >= a.n_items * a.ngroups) break;
-    const int base = it / a.ngroups, grp = it - base * a.ngroups;
-    const int tile = a.items[2 * base];
-    const int p = a.items[2 * base + 1];
+  {
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
@@ -693,6 +691,29 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
   }
 }
 
+// Work units from a longest-first queue. A unit carries its own directions
+// per wave, NDA or NDB: a split can give the longest pulsars fewer
+// directions per wave (more waves, shorter serial chains) and the others
+// more (fewer repeated base filters). NDA == NDB is a uniform split.
+template <int MODEL, int NDA, int NDB>
+__global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int u = __builtin_amdgcn_readfirstlane(v);
+    if (u >= a.n_units) break;
+    const int item = a.units[2 * u], code = a.units[2 * u + 1];
+    const int grp = code & 0xff;
+    const int tile = a.items[2 * item];
+    const int p = a.items[2 * item + 1];
+    if (NDA == NDB || (code >> 8) == NDA)
+      tangent_unit<MODEL, NDA>(a, lane, tile, p, grp);
+    else
+      tangent_unit<MODEL, NDB>(a, lane, tile, p, grp);
+  }
+}
+
 // Tangent sweep of model 4 (state [r, f, a, g, m], h = [1, 0, 1, 1, c] with
 // the chromatic factor c of each TOA): the same differentiated recursion
 // over five states. dF is diagonal, nonzero at a (red decay, its rate) and
@@ -706,19 +727,12 @@ __host__ __device__ constexpr int si5(int i, int j) {
 __device__ __forceinline__ constexpr bool h5(int i) { return i != 1; }
 
 template <int ND>
-__global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
+__device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, const int tile,
+                                              const int p, const int grp) {
   constexpr int NS = 5, NP = 15;
-  const int lane = threadIdx.x & (kWave - 1);
   const RecPtr rec = (RecPtr)a.rec;
   const ConstDPtr chrom = (ConstDPtr)a.chrom;
-  for (;;) {
-    int v = 0;
-    if (lane == 0) v = atomicAdd(a.counter, 1);
-    const int it = __builtin_amdgcn_readfirstlane(v);
-    if (it >= a.n_items * a.ngroups) break;
-    const int base = it / a.ngroups, grp = it - base * a.ngroups;
-    const int tile = a.items[2 * base];
-    const int p = a.items[2 * base + 1];
+  {
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
@@ -940,6 +954,26 @@ __global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
   }
 }
 
+// Work units of model 4, as k_tangent: each unit carries NDA or NDB.
+template <int NDA, int NDB>
+__global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int u = __builtin_amdgcn_readfirstlane(v);
+    if (u >= a.n_units) break;
+    const int item = a.units[2 * u], code = a.units[2 * u + 1];
+    const int grp = code & 0xff;
+    const int tile = a.items[2 * item];
+    const int p = a.items[2 * item + 1];
+    if (NDA == NDB || (code >> 8) == NDA)
+      tangent5_unit<NDA>(a, lane, tile, p, grp);
+    else
+      tangent5_unit<NDB>(a, lane, tile, p, grp);
+  }
+}
+
 // grad[s, c] from the per-pulsar parts, one thread per element (consecutive
 // threads on consecutive columns of a row, so the rows are written whole): a
 // pulsar's own parameters from its filter, the common ones summed over
@@ -988,7 +1022,33 @@ int grad_finish(argus_dataset* ds, Workspace* w, int64_t S, double* logl, double
   return ARGUS_OK;
 }
 
-int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nd, hipStream_t st) {
+// Work units of a split: every item (tile, pulsar) in the
+// longest-first order, cut into ndir / nd groups with nd = nda for pulsars
+// of at least thresh TOAs and ndb for the others.
+int tangent_units(argus_dataset* ds, Workspace* w, int nda, int ndb, int64_t thresh) {
+  if (w->units_nda == nda && w->units_ndb == ndb && w->units_thresh == thresh) return ARGUS_OK;
+  const int ndir = ds->model == 1 ? 2 : (ds->model == 4 ? 8 : 6);
+  std::vector<int32_t> u;
+  for (int i = 0; i < w->n_items; ++i) {
+    const int p = w->items_host[2 * i + 1];
+    const int nd = ds->counts[p] >= thresh ? nda : ndb;
+    for (int g = 0; g < ndir / nd; ++g) {
+      u.push_back(i);
+      u.push_back(g | nd << 8);
+    }
+  }
+  w->n_tan_units = (int)(u.size() / 2);
+  if (u.empty()) u.assign(2, 0);  // keep the buffer non-empty
+  const int rc = w->tan_units.upload(u.data(), u.size() * sizeof(int32_t));
+  if (rc) return rc;
+  w->units_nda = nda;
+  w->units_ndb = ndb;
+  w->units_thresh = thresh;
+  return ARGUS_OK;
+}
+
+int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nda, int ndb,
+                   int64_t thresh, hipStream_t st) {
   TanArgs a{};
   a.rec = ds->rec.as<TOARec>();
   a.chrom = ds->chrom.as<double>();
@@ -1006,28 +1066,46 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nd,
   a.P = ds->P;
   a.n_items = w->n_items;
   a.mc = ds->mc;
-  const int ndir = ds->model == 1 ? 2 : (ds->model == 4 ? 8 : 6);
-  a.ngroups = ndir / nd;
-  const int64_t waves = std::max<int64_t>(
-      4, std::min<int64_t>((int64_t)w->n_items * a.ngroups, 8LL * ds->n_cu));
+  int rc = tangent_units(ds, w, nda, ndb, thresh);
+  if (rc) return rc;
+  a.units = w->tan_units.as<int32_t>();
+  a.n_units = w->n_tan_units;
+  const int64_t waves = std::max<int64_t>(4, std::min<int64_t>(a.n_units, 8LL * ds->n_cu));
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  const int key = nda * 10 + ndb;
   if (ds->model == 4) {
-    if (nd == 4)
-      hipLaunchKernelGGL((k_tangent5<4>), grid, block, 0, st, a);
-    else if (nd == 2)
-      hipLaunchKernelGGL((k_tangent5<2>), grid, block, 0, st, a);
+    if (key == 44)
+      hipLaunchKernelGGL((k_tangent5<4, 4>), grid, block, 0, st, a);
+    else if (key == 22)
+      hipLaunchKernelGGL((k_tangent5<2, 2>), grid, block, 0, st, a);
+    else if (key == 11)
+      hipLaunchKernelGGL((k_tangent5<1, 1>), grid, block, 0, st, a);
+    else if (key == 12)
+      hipLaunchKernelGGL((k_tangent5<1, 2>), grid, block, 0, st, a);
+    else if (key == 14)
+      hipLaunchKernelGGL((k_tangent5<1, 4>), grid, block, 0, st, a);
+    else if (key == 24)
+      hipLaunchKernelGGL((k_tangent5<2, 4>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_tangent5<1>), grid, block, 0, st, a);
+      return fail(ARGUS_E_INVAL, "unsupported tangent split");
   } else if (ds->model == 1)
-    hipLaunchKernelGGL((k_tangent<1, 2>), grid, block, 0, st, a);
-  else if (nd == 6)
-    hipLaunchKernelGGL((k_tangent<2, 6>), grid, block, 0, st, a);
-  else if (nd == 3)
-    hipLaunchKernelGGL((k_tangent<2, 3>), grid, block, 0, st, a);
-  else if (nd == 2)
-    hipLaunchKernelGGL((k_tangent<2, 2>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_tangent<1, 2, 2>), grid, block, 0, st, a);
+  else if (key == 66)
+    hipLaunchKernelGGL((k_tangent<2, 6, 6>), grid, block, 0, st, a);
+  else if (key == 33)
+    hipLaunchKernelGGL((k_tangent<2, 3, 3>), grid, block, 0, st, a);
+  else if (key == 22)
+    hipLaunchKernelGGL((k_tangent<2, 2, 2>), grid, block, 0, st, a);
+  else if (key == 11)
+    hipLaunchKernelGGL((k_tangent<2, 1, 1>), grid, block, 0, st, a);
+  else if (key == 12)
+    hipLaunchKernelGGL((k_tangent<2, 1, 2>), grid, block, 0, st, a);
+  else if (key == 13)
+    hipLaunchKernelGGL((k_tangent<2, 1, 3>), grid, block, 0, st, a);
+  else if (key == 23)
+    hipLaunchKernelGGL((k_tangent<2, 2, 3>), grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL((k_tangent<2, 1>), grid, block, 0, st, a);
+    return fail(ARGUS_E_INVAL, "unsupported tangent split");
   HIPCHK(hipGetLastError());
   return ARGUS_OK;
 }
@@ -1036,7 +1114,8 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nd,
 
 // Tangent-mode gradient (the default): one streaming pass per direction
 // group; on the first call for a sample count the directions per wave are
-// chosen by timing (model 2: 6, 3, 2 or 1).
+// chosen by timing (model 2: 6, 3, 2 or 1 for every pulsar, or fewer for
+// the longest pulsars than for the others).
 int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl,
                     double* grad, int32_t* status, hipStream_t st) {
   int rc = ARGUS_OK;
@@ -1046,28 +1125,61 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
   if (w->gpart.p == nullptr &&
       (rc = w->gpart.alloc((size_t)ds->P * gstride * S * sizeof(double))))
     return rc;
-  if (w->tan_nd == 0) {
+  if (w->tan_nda == 0) {
+    // a forced split: "nd" (uniform) or "nda,ndb,thresh"
     const char* forced = std::getenv("ARGUS_TAN_ND");
-    int nd = forced ? std::atoi(forced) : 0;
-    if (ds->model == 1) nd = 2;
-    const bool ok = ds->model == 4 ? (nd == 1 || nd == 2 || nd == 4)
-                                   : (nd == 1 || nd == 2 || nd == 3 || nd == 6);
+    int fa = 0, fb = 0;
+    long long ft = 0;
+    const int nf = forced ? std::sscanf(forced, "%d,%d,%lld", &fa, &fb, &ft) : 0;
+    if (nf == 1) fb = fa;
+    if (ds->model == 1) fa = fb = 2;
+    const bool uni = fa == fb;
+    const int fk = fa * 10 + fb;
+    const bool ok = ds->model == 4
+                        ? (uni ? (fa == 1 || fa == 2 || fa == 4)
+                               : nf == 3 && ft >= 0 && (fk == 12 || fk == 14 || fk == 24))
+                        : (uni ? (fa == 1 || fa == 2 || fa == 3 || fa == 6)
+                               : nf == 3 && ft >= 0 && (fk == 12 || fk == 13 || fk == 23));
     if (ok) {
-      w->tan_nd = nd;
+      w->tan_nda = fa;
+      w->tan_ndb = fb;
+      w->tan_thresh = uni ? 0 : ft;
     } else {
+      // timed candidates: uniform splits, and (models 2, 4) mixed ones that
+      // give the pulsars of at least 1/2, 3/4 or 7/8 of the longest
+      // pulsar's TOAs fewer directions per wave
+      struct Cand {
+        int a, b;
+        int64_t t;
+      };
+      std::vector<Cand> cand;
+      std::vector<std::pair<int, int>> mixed;
+      if (ds->model == 4) {
+        for (int c : {4, 2, 1}) cand.push_back({c, c, 0});
+        mixed = {{1, 2}, {1, 4}, {2, 4}};
+      } else if (ds->model == 2) {
+        for (int c : {6, 3, 2, 1}) cand.push_back({c, c, 0});
+        mixed = {{1, 2}, {1, 3}, {2, 3}};
+      } else {
+        cand.push_back({2, 2, 0});
+      }
+      const int64_t nmax = ds->counts.empty()
+                               ? 0
+                               : *std::max_element(ds->counts.begin(), ds->counts.end());
+      for (int64_t t : {nmax / 2, (3 * nmax) / 4, (7 * nmax) / 8})
+        for (auto ab : mixed)
+          if (t > 0) cand.push_back({ab.first, ab.second, t});
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       float best = 1e30f;
-      int pick = 6;
+      Cand pick = cand[0];
       w->grad_log.clear();
-      const std::vector<int> splits =
-          ds->model == 4 ? std::vector<int>{4, 2, 1} : std::vector<int>{6, 3, 2, 1};
-      for (int c : splits) {
+      for (const Cand& c : cand) {
         float m = 1e30f;
         for (int rep = 0; rep < 3 && rc == ARGUS_OK; ++rep) {
           if (hipEventRecord(e0, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
-          if (!rc) rc = launch_tangent(ds, w, theta, c, st);
+          if (!rc) rc = launch_tangent(ds, w, theta, c.a, c.b, c.t, st);
           if (!rc) rc = grad_finish(ds, w, S, logl, grad, status, st);
           if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
           if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "sync");
@@ -1076,8 +1188,12 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
           if (rep > 0) m = std::min(m, ms);
         }
         if (rc) break;
-        char b[80];
-        std::snprintf(b, sizeof b, "tangent directions per wave %d: %.4f ms\n", c, m);
+        char b[128];
+        if (c.a == c.b)
+          std::snprintf(b, sizeof b, "tangent directions per wave %d: %.4f ms\n", c.a, m);
+        else
+          std::snprintf(b, sizeof b, "tangent directions per wave %d (>= %lld TOAs) / %d: %.4f ms\n",
+                        c.a, (long long)c.t, c.b, m);
         w->grad_log += b;
         if (m < best) {
           best = m;
@@ -1087,10 +1203,12 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
       if (rc) return rc;
-      w->tan_nd = pick;
+      w->tan_nda = pick.a;
+      w->tan_ndb = pick.b;
+      w->tan_thresh = pick.t;
     }
   }
-  if ((rc = launch_tangent(ds, w, theta, w->tan_nd, st))) return rc;
+  if ((rc = launch_tangent(ds, w, theta, w->tan_nda, w->tan_ndb, w->tan_thresh, st))) return rc;
   return grad_finish(ds, w, S, logl, grad, status, st);
 }
 
