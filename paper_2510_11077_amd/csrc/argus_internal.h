@@ -57,6 +57,29 @@ __device__ __forceinline__ TOARec load_rec(RecPtr r, int64_t k) {
   return x;
 }
 
+// A record as one 64-B vector (one scalar load of all 16 words). Handing the
+// whole vector to rec_keep at the top of the next step keeps all 16 SGPRs
+// live until then: otherwise the compiler may reuse the words the step does
+// not read while the load that writes them is still in flight, which forces
+// a wait for the load right after it is issued.
+typedef double RecVec __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(4))) const RecVec* RecVecPtr;
+__device__ __forceinline__ RecVec load_rec_v(RecVecPtr r, int k) { return r[k]; }
+__device__ __forceinline__ void rec_keep(const RecVec& v) { asm volatile("" ::"s"(v)); }
+__device__ __forceinline__ TOARec rec_fields(const RecVec& v) {
+  TOARec x;
+  x.dt = v[0];
+  x.h2 = v[1];
+  x.h3 = v[2];
+  x.phc = v[3];
+  x.qcu = v[4];
+  x.y = v[5];
+  x.s2 = v[6];
+  x.psr = 0;
+  x.pad = 0;
+  return x;
+}
+
 // exp(x) - 1 for the OU decays (x = -rate * dt <= 0 in every use). Range
 // reduction x = k ln2 + r, |r| <= ln2/2, with ln 2 split in two parts so that
 // k ln2_hi is exact (Cody & Waite 1980; the split of fdlibm); expm1(r) from

@@ -356,25 +356,33 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       const RecPtr rec = (RecPtr)a.rec;
       const ConstDPtr chrom = (ConstDPtr)a.chrom;
       const double ss2v = in_vgpr(ss2), c13 = in_vgpr(kExpm1Coef[11]);
-      // the next record, its chromatic factor and both decays are fetched
-      // one step ahead (index clamped; with twice the per-pulsar state of
-      // model 2 there are not enough SGPRs for a second record in flight)
-      TOARec rn{};
-      double cn = 0.0, emn = 0.0, emdn = 0.0;
+      // The record and chromatic factor of step k + 1 are fetched during
+      // step k; both decays of step k + 1 are computed during step k from
+      // its dt, which was fetched alone (8 B) during step k - 1, so no value
+      // is used in the step that fetches it (indices clamped).
+      const RecVecPtr recv = (RecVecPtr)a.rec;
+      const ConstDPtr dts = (ConstDPtr)a.rec;  // dt is the first of each record's 8 doubles
+      RecVec vn{};
+      double cn = 0.0, emn = 0.0, emdn = 0.0, dt2 = 0.0;
       if (kb < ke) {
-        rn = load_rec(rec, kb);
+        vn = load_rec_v(recv, kb);
         cn = chrom[kb];
-        emn = expm1_v(-gr * rn.dt, c13);
-        emdn = expm1_v(-gd * rn.dt, c13);
+        dt2 = dts[8 * (kb + 1 < ke ? kb + 1 : kb)];
+        emn = expm1_v(-gr * vn[0], c13);
+        emdn = expm1_v(-gd * vn[0], c13);
       }
       for (int k = kb; k < ke; ++k) {
-        const TOARec r = rn;
-        const double c = cn, em = emn, emd = emdn;
+        const RecVec v = vn;
+        const double c = cn, em = emn, emd = emdn, dt1 = dt2;
+        rec_keep(v);
+        sgpr_ready(dt1);
+        const TOARec r = rec_fields(v);
         const int kn = k + 1 < ke ? k + 1 : k;
-        rn = load_rec(rec, kn);
+        vn = load_rec_v(recv, kn);
         cn = chrom[kn];
-        emn = expm1_v(-gr * rn.dt, c13);
-        emdn = expm1_v(-gd * rn.dt, c13);
+        dt2 = dts[8 * (k < ke - 2 ? k + 2 : ke - 1)];
+        emn = expm1_v(-gr * dt1, c13);
+        emdn = expm1_v(-gd * dt1, c13);
         step5(f, r, c, em, emd, vr, vc, vd, efac2, equad2, ss2v);
       }
       st = f.st;
