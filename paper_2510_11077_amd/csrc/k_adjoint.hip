@@ -315,7 +315,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
-    const int64_t kb = a.off[p], N = a.off[p + 1] - kb;
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
     const int c1 = a.c1[p];
     double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
 
@@ -354,14 +355,29 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     int le = 0, stat = pnf ? kPNF : 0;
     int kc = 0;                 // position within the current segment
     double* ckw = ck;           // next level-1 checkpoint slot
-    for (int64_t k = 0; k < N; ++k) {
+    // gradient: the record of step k + 1 is fetched during step k (one 64-B
+    // vector, kept whole until the next step; index clamped); the smoothing
+    // variant has no SGPRs to spare for a record in flight
+    const RecVecPtr recv = (RecVecPtr)a.rec;
+    RecVec vn{};
+    if (!SMOOTH && N > 0) vn = load_rec_v(recv, kb);
+    for (int k = 0; k < N; ++k) {
+      TOARec r;
+      if (SMOOTH) {
+        r = load_rec(rec, kb + k);
+      } else {
+        const RecVec v = vn;
+        rec_keep(v);
+        vn = load_rec_v(recv, kb + (k + 1 < N ? k + 1 : k));
+        r = rec_fields(v);
+      }
       if (kc == 0) {
         put_state(ckw, lane, st);
         ckw += kFields * kWave;
       }
       kc = kc + 1 == c1 ? 0 : kc + 1;
       double S, e, inv;
-      fwd_step(st, load_rec(rec, kb + k), L, S, e, inv);
+      fwd_step(st, r, L, S, e, inv);
       const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
       if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
       quad = fma(e * e, inv, quad);
@@ -791,25 +807,35 @@ __device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, 
     double quad = 0.0, lm = 1.0;
     int le = 0, stat = pnf ? kPNF : 0;
 
-    // the next record, its chromatic factor and both decays one step ahead
-    // (index clamped); the top expm1 coefficient is held in a VGPR
+    // The record (one 64-B vector, kept whole until the next step) and the
+    // chromatic factor of step k + 1 are fetched during step k, and the dt of
+    // step k + 2 alone during step k, so both decays of step k + 1 are
+    // computed without waiting (indices clamped); the top expm1 coefficient
+    // is held in a VGPR
     const double c13 = in_vgpr(kExpm1Coef[11]);
-    TOARec rn{};
-    double cn = 0.0, emn = 0.0, emdn = 0.0;
+    const RecVecPtr recv = (RecVecPtr)a.rec;
+    const ConstDPtr dts = (ConstDPtr)a.rec;  // dt is the first of each record's 8 doubles
+    RecVec vn{};
+    double cn = 0.0, emn = 0.0, emdn = 0.0, dt2 = 0.0;
     if (N > 0) {
-      rn = load_rec(rec, kb);
+      vn = load_rec_v(recv, kb);
       cn = chrom[kb];
-      emn = expm1_v(-gr * rn.dt, c13);
-      emdn = expm1_v(-gd * rn.dt, c13);
+      dt2 = dts[8 * (kb + (N > 1 ? 1 : 0))];
+      emn = expm1_v(-gr * vn[0], c13);
+      emdn = expm1_v(-gd * vn[0], c13);
     }
     for (int k = 0; k < N; ++k) {
-      const TOARec r = rn;
-      const double c = cn, em = emn, emd = emdn;
+      const RecVec v = vn;
+      const double c = cn, em = emn, emd = emdn, dt1 = dt2;
+      rec_keep(v);
+      sgpr_ready(dt1);
+      const TOARec r = rec_fields(v);
       const int kn = kb + (k + 1 < N ? k + 1 : k);
-      rn = load_rec(rec, kn);
+      vn = load_rec_v(recv, kn);
       cn = chrom[kn];
-      emn = expm1_v(-gr * rn.dt, c13);
-      emdn = expm1_v(-gd * rn.dt, c13);
+      dt2 = dts[8 * (kb + (k < N - 2 ? k + 2 : N - 1))];
+      emn = expm1_v(-gr * dt1, c13);
+      emdn = expm1_v(-gd * dt1, c13);
       const double dt = r.dt;
       const double ph = 1.0 + em, phd = 1.0 + emd, phc = r.phc;
       const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
