@@ -206,8 +206,9 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
  * common ones) are NaN. Computed from the reverse sweep of the checkpointed
  * adjoint gradient, no matrix inverse: E[x|y] = x + P xb and Cov[x|y] = P +
  * P (2M - xb xb^T) P with (x, P) filtered and (xb, M) the adjoints of logL
- * with respect to them. Model 3 returns ARGUS_E_UNSUPPORTED; N*4*S above
- * 2^40 elements returns ARGUS_E_UNSUPPORTED. */
+ * with respect to them. Models 3 and 4 return ARGUS_E_UNSUPPORTED; N*4*S above
+ * 2^40 elements, or a pulsar with more than 33,554,431 TOAs, returns
+ * ARGUS_E_UNSUPPORTED. */
 int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
                  double* var, double* logl, int32_t* status, void* stream);
 

@@ -80,6 +80,39 @@ __device__ __forceinline__ TOARec rec_fields(const RecVec& v) {
   return x;
 }
 
+// One pulsar's TOA records read with vector (buffer) loads into VGPRs, for
+// kernels whose SGPRs cannot hold records in flight: the loads are issued
+// ahead of use and waited for in order. The descriptor covers the pulsar's
+// n records (n * 64 bytes must fit in 31 bits; the host checks); a read
+// beyond them returns zeros. Word 3 of the descriptor is the raw-buffer
+// format of the gfx9 family.
+struct RecBuf {
+  __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ RecBuf rec_buffer(const TOARec* first, int n) {
+  return RecBuf{__builtin_amdgcn_make_buffer_rsrc(const_cast<TOARec*>(first), (short)0, n * 64,
+                                                  0x00020000)};
+}
+__device__ __forceinline__ TOARec load_rec_vgpr(const RecBuf& b, int k) {
+  typedef double D2 __attribute__((ext_vector_type(2)));
+  const int o = k * 64;
+  const D2 a = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(b.r, o, 0, 0));
+  const D2 c = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(b.r, o + 16, 0, 0));
+  const D2 d = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(b.r, o + 32, 0, 0));
+  const double s2 = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, o + 48, 0, 0));
+  TOARec x;
+  x.dt = a[0];
+  x.h2 = a[1];
+  x.h3 = c[0];
+  x.phc = c[1];
+  x.qcu = d[0];
+  x.y = d[1];
+  x.s2 = s2;
+  x.psr = 0;
+  x.pad = 0;
+  return x;
+}
+
 // exp(x) - 1 for the OU decays (x = -rate * dt <= 0 in every use). Range
 // reduction x = k ln2 + r, |r| <= ln2/2, with ln 2 split in two parts so that
 // k ln2_hi is exact (Cody & Waite 1980; the split of fdlibm); expm1(r) from

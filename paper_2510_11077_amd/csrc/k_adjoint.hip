@@ -355,16 +355,21 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     int le = 0, stat = pnf ? kPNF : 0;
     int kc = 0;                 // position within the current segment
     double* ckw = ck;           // next level-1 checkpoint slot
-    // gradient: the record of step k + 1 is fetched during step k (one 64-B
-    // vector, kept whole until the next step; index clamped); the smoothing
-    // variant has no SGPRs to spare for a record in flight
+    // The record of step k + 1 is fetched during step k (index clamped):
+    // by the gradient variant as one 64-B scalar vector kept whole until the
+    // next step, by the smoothing variant, which has no SGPRs to spare, into
+    // VGPRs
     const RecVecPtr recv = (RecVecPtr)a.rec;
+    const RecBuf rb = rec_buffer(a.rec + kb, N);
     RecVec vn{};
+    TOARec rq{};
     if (!SMOOTH && N > 0) vn = load_rec_v(recv, kb);
+    if (SMOOTH && N > 0) rq = load_rec_vgpr(rb, 0);
     for (int k = 0; k < N; ++k) {
       TOARec r;
       if (SMOOTH) {
-        r = load_rec(rec, kb + k);
+        r = rq;
+        rq = load_rec_vgpr(rb, k + 1 < N ? k + 1 : k);
       } else {
         const RecVec v = vn;
         rec_keep(v);
@@ -400,30 +405,43 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
       const int64_t k0 = sg * c1;
       const int64_t k1 = k0 + c1 < N ? k0 + c1 : N;
       const int nsub = (int)((k1 - k0 + 3) / 4);
-      // recompute the segment to level-2 checkpoints every 4 TOAs
+      // recompute the segment to level-2 checkpoints every 4 TOAs; the four
+      // records of a piece are read together into VGPRs (one wait per piece)
       State cur = get_state(ck + sg * kFields * kWave, lane);
       for (int t = 0; t < nsub; ++t) {
         put_state(scr + (int64_t)t * kFields * kWave, lane, cur);
         if (t + 1 < nsub) {
-          const int64_t kk = kb + k0 + 4 * t;
+          const int kk = (int)k0 + 4 * t;  // a full piece: kk + 3 < k1
+          TOARec q[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) fwd_only(cur, load_rec(rec, kk + i), L);
+          for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, kk + i);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) fwd_only(cur, q[i], L);
         }
       }
       // reverse each 4-TOA piece, last first: the state before TOA i of the
       // piece is recomputed from the piece's checkpoint (0..3 steps), so
-      // only two states are live in registers
+      // only two states are live in registers; the piece's records are read
+      // once into VGPRs (index clamped to its last TOA) and the loops are
+      // unrolled so that they are addressed statically
       for (int t = nsub - 1; t >= 0; --t) {
-        const int64_t ks = k0 + 4 * t;
+        const int ks = (int)k0 + 4 * t;
         const int nt = (int)(k1 - ks < 4 ? k1 - ks : 4);
-        const int64_t kk = kb + ks;
+        TOARec q[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, ks + (i < nt ? i : nt - 1));
         const State s0 = get_state(scr + (int64_t)t * kFields * kWave, lane);
-        for (int i = nt - 1; i >= 0; --i) {
-          State cur = s0;
-          for (int j = 0; j < i; ++j) fwd_only(cur, load_rec(rec, kk + j), L);
-          rev_step(cur, load_rec(rec, kk + i), L, xb, M, G);
-          // (xb, M) are now the adjoints of the filtered state after TOA ks + i - 1
-          if (SMOOTH && valid && ks + i > 0) put_smooth(a, kk + i - 1, s, cur, xb, M, stat != 0);
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+          if (i < nt) {
+            State cur = s0;
+#pragma unroll
+            for (int j = 0; j < i; ++j) fwd_only(cur, q[j], L);
+            rev_step(cur, q[i], L, xb, M, G);
+            // (xb, M) are now the adjoints of the filtered state after TOA ks + i - 1
+            if (SMOOTH && valid && ks + i > 0)
+              put_smooth(a, kb + ks + i - 1, s, cur, xb, M, stat != 0);
+          }
         }
       }
     }
@@ -1245,6 +1263,11 @@ namespace {
 // the level-1 store and the per-wave level-2 scratch.
 int adjoint_setup(argus_dataset* ds, Workspace* w, int64_t S) {
   if (w->grad_ready) return ARGUS_OK;
+  // the reverse sweep reads a pulsar's records through one buffer
+  // descriptor, whose byte range is 31 bits
+  for (const int64_t n : ds->counts)
+    if (n > INT32_MAX / 64)
+      return fail(ARGUS_E_UNSUPPORTED, "the reverse sweep takes at most 33554431 TOAs per pulsar");
   const int64_t tiles = (S + kWave - 1) / kWave;
   std::vector<int32_t> c1(ds->P);
   std::vector<int64_t> base(ds->P);
