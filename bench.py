@@ -36,6 +36,10 @@ FLOP_PER_STEP_M1 = 47
 # and S with the chromatic row 32, reciprocal 1, gain + mean update + S K 20,
 # Joseph rank-2 update of 15 entries 90, quadratic form 3, log-det 1.
 FLOP_PER_STEP_M4 = 203
+# joint model, per TOA per sample: G and Sigma_B 1.3 k, elimination 1.4 k,
+# transition of P 1.2 k, rank-16 downdate 7.7 k (the FP64 MFMA part)
+FLOP_PER_TOA_JOINT = 11600
+FLOP_PER_TOA_JOINT_MFMA = 7700
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 
@@ -100,6 +104,12 @@ def surrogate_leg(A, pi, dev, stream, log):
                          "roofline": {"bound": "mfma", "achieved": flop / (ms * 1e-3) / 1e12,
                                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                                       "frac": flop / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}}
+    try:
+        bf, _ = A.mfma_rate(2)
+        out["eval_65536"]["roofline"]["attainable"] = bf
+        out["eval_65536"]["roofline"]["frac_attainable"] = flop / (ms * 1e-3) / 1e12 / bf
+    except A.ArgusError:
+        pass
     # accuracy on held-out posterior-bulk points
     ye, _ = ds5.loglike(tq, want_status=False)
     err = (yq - ye).abs().cpu().numpy()
@@ -317,10 +327,13 @@ def main():
             "flop_per_launch": flop,
         },
     }
-    # the published FP64 peak assumes the maximum engine clock; the FP64 FMA
-    # rate this device sustains with every SIMD busy, and its clock then
+    # the published peaks assume the maximum engine clock: the rates this
+    # device sustains with every CU busy (argus_fp64_rate, argus_mfma_rate),
+    # its clock then, and HBM bandwidth of a plain device copy
+    device = {}
     try:
         tf, mhz = A.fp64_rate(1)
+        device["fp64_vector_tflops"], device["fp64_vector_clock_mhz"] = tf, mhz
         res["roofline"]["attainable"] = tf
         res["roofline"]["frac_attainable"] = achieved / tf
         res["roofline"]["attainable_note"] = (
@@ -328,9 +341,24 @@ def main():
             "wave per SIMD); mean shader clock %.0f MHz against 2400 MHz for the published "
             "peak" % mhz)
         log("FP64 FMA rate under full load: %.1f TFLOP/s at %.0f MHz" % (tf, mhz))
+        for key, kind in (("fp64_mfma", 1), ("bf16_mfma", 2)):
+            tf, mhz = A.mfma_rate(kind)
+            device[key + "_tflops"], device[key + "_clock_mhz"] = tf, mhz
+            log("%s rate under full load: %.1f TFLOP/s at %.0f MHz" % (key, tf, mhz))
     except A.ArgusError as e:
         res["roofline"]["attainable"] = None
         res["roofline"]["attainable_note"] = "unavailable: %s" % e
+    if not args.copy_calib:  # (counter runs keep the calibration copy the only large one)
+        n_copy = 1 << 27  # 1 GiB of doubles
+        src = torch.ones(n_copy, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        ms_copy, _ = timed(lambda: dst.copy_(src), 10, 2, stream)
+        device["hbm_copy_GB_per_s"] = 2 * n_copy * 8 / (ms_copy * 1e-3) / 1e9
+        log("HBM copy: %.0f GB/s (read + write)" % device["hbm_copy_GB_per_s"])
+        del src, dst
+    device["published"] = {"fp64_vector_tflops": FP64_PEAK_TFLOPS, "fp64_mfma_tflops": 78.6,
+                           "bf16_mfma_tflops": BF16_PEAK_TFLOPS, "hbm_GB_per_s": 8000.0}
+    res["device"] = device
 
     extra = {}
     if not args.no_extra:
@@ -390,8 +418,11 @@ def main():
         s3 = torch.empty(S3, dtype=torch.int32, device=dev)
         ds3.loglike(t3, o3, s3)
         ms3, _ = timed(lambda: ds3.loglike(t3, o3, s3), 3, 1, stream)
-        extra["joint_hd_20psr_20000toa_256samples"] = {"ms_per_call": ms3,
-                                                        "evals_per_s": S3 / (ms3 * 1e-3)}
+        n3 = int(d3.n_toa) * S3
+        extra["joint_hd_20psr_20000toa_256samples"] = {
+            "ms_per_call": ms3, "evals_per_s": S3 / (ms3 * 1e-3),
+            "tflops_algorithmic": n3 * FLOP_PER_TOA_JOINT / (ms3 * 1e-3) / 1e12,
+            "mfma_tflops_algorithmic": n3 * FLOP_PER_TOA_JOINT_MFMA / (ms3 * 1e-3) / 1e12}
         log("joint HD: %.3f ms/call, %.4g evals/s" % (ms3, S3 / (ms3 * 1e-3)))
 
         # gradient (adjoint filter), 1024 samples of the 47-pulsar data

@@ -298,6 +298,15 @@ int argus_da_stage2(const int32_t* idx, const int32_t* count, int64_t cap,
  * arguments, ARGUS_E_HIP if the launch or a clock query fails. */
 int argus_fp64_rate(int32_t waves_per_simd, double* tflops, double* clock_mhz, void* stream);
 
+/* The same diagnostic for the matrix cores: kind 1 = v_mfma_f64_16x16x4f64
+ * (FP64, the joint model's downdate), kind 2 = v_mfma_f32_32x32x16_bf16
+ * (BF16 with FP32 accumulation, the surrogate), eight independent
+ * accumulators per wave. Allocates and synchronises the stream;
+ * -> ARGUS_E_INVAL for a bad kind or waves_per_simd, ARGUS_E_HIP if the
+ * launch or a clock query fails. */
+int argus_mfma_rate(int32_t kind, int32_t waves_per_simd, double* tflops, double* clock_mhz,
+                    void* stream);
+
 /* Human-readable launch configuration chosen for (ds, S), for reports. */
 int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len);
 

@@ -55,6 +55,8 @@ _lib.argus_hmc_step.argtypes = [_V, C.c_int64, C.c_int32, _V, _V, _V, _V, _V, _V
 _lib.argus_nuts_step.argtypes = [_V, C.c_int64, C.c_int32] + [_V] * 16
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
 _lib.argus_fp64_rate.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), _V]
+_lib.argus_mfma_rate.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), _V]
 _lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)]
 _lib.argus_mlp_destroy.argtypes = [_V]
 _lib.argus_mlp_n_params.argtypes = [_V, C.POINTER(C.c_int64)]
@@ -340,6 +342,16 @@ def fp64_rate(waves_per_simd: int = 1, stream=None):
     ceiling for FP64-VALU kernels, next to the published peak."""
     tf, mhz = C.c_double(), C.c_double()
     _check(_lib.argus_fp64_rate(int(waves_per_simd), C.byref(tf), C.byref(mhz), _stream(stream)))
+    return tf.value, mhz.value
+
+
+def mfma_rate(kind: int, waves_per_simd: int = 1, stream=None):
+    """Sustained matrix-core rate (TFLOP/s) and mean shader clock (MHz) with
+    every CU busy (argus_mfma_rate): kind 1 FP64 16x16x4, kind 2 BF16
+    32x32x16."""
+    tf, mhz = C.c_double(), C.c_double()
+    _check(_lib.argus_mfma_rate(int(kind), int(waves_per_simd), C.byref(tf), C.byref(mhz),
+                                _stream(stream)))
     return tf.value, mhz.value
 
 

@@ -624,8 +624,19 @@ extern "C" int argus_fp64_rate(int32_t waves_per_simd, double* tflops, double* c
   if (waves_per_simd < 1 || waves_per_simd > 4)
     return fail(ARGUS_E_INVAL, "waves_per_simd must be 1..4");
   // about 1 ms of FMAs at one wave per SIMD
-  return fp64_rate(waves_per_simd, 2000 / waves_per_simd, tflops, clock_mhz,
-                   (hipStream_t)stream);
+  return device_rate(0, waves_per_simd, 2000 / waves_per_simd, tflops, clock_mhz,
+                     (hipStream_t)stream);
+}
+
+extern "C" int argus_mfma_rate(int32_t kind, int32_t waves_per_simd, double* tflops,
+                               double* clock_mhz, void* stream) {
+  if (!tflops || !clock_mhz) return fail(ARGUS_E_INVAL, "tflops and clock_mhz are required");
+  if (kind != 1 && kind != 2) return fail(ARGUS_E_INVAL, "kind must be 1 (FP64) or 2 (BF16)");
+  if (waves_per_simd < 1 || waves_per_simd > 4)
+    return fail(ARGUS_E_INVAL, "waves_per_simd must be 1..4");
+  // about 1 ms of matrix instructions at one wave per SIMD
+  const int iters = (kind == 1 ? 4000 : 2000) / waves_per_simd;
+  return device_rate(kind, waves_per_simd, iters, tflops, clock_mhz, (hipStream_t)stream);
 }
 
 extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,

@@ -127,8 +127,8 @@ int nuts_step(argus_dataset* ds, int64_t S, int32_t max_depth, const double* eps
               const int32_t* dirs, const double* u_top, const double* u_sub, double* theta,
               double* logl, double* grad, int32_t* depth, int32_t* n_leapfrog,
               int32_t* divergent, double* accept_stat, hipStream_t st);
-int fp64_rate(int waves_per_simd, int iters, double* tflops, double* clock_mhz,
-              hipStream_t st);
+int device_rate(int kind, int waves_per_simd, int iters, double* tflops, double* clock_mhz,
+                hipStream_t st);
 int hmc_step(argus_dataset* ds, int64_t S, int32_t n_leapfrog, const double* eps,
              const double* m_inv, const double* lo, const double* hi, const double* z,
              const double* logu, double* theta, double* logl, double* grad,
