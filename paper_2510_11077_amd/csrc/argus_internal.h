@@ -150,6 +150,35 @@ __device__ __forceinline__ double expm1_v(double x, double c13) {
 }
 __device__ __forceinline__ double expm1_k(double x) { return expm1_v(x, kExpm1Coef[11]); }
 
+// The same with every coefficient held in VGPRs (for loops short of SGPRs):
+// the Horner steps then read no SGPR at all.
+struct Expm1Coef {
+  double c[12];
+};
+__device__ __forceinline__ Expm1Coef expm1_coef_vgpr() {
+  Expm1Coef k;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    k.c[i] = kExpm1Coef[i];
+    asm volatile("" : "+v"(k.c[i]));
+  }
+  return k;
+}
+__device__ __forceinline__ double expm1_c(double x, const Expm1Coef& k) {
+  const double kInvLn2 = 1.44269504088896338700;
+  const double kLn2Hi = 6.93147180369123816490e-01;
+  const double kLn2Lo = 1.90821492927058770002e-10;
+  const double kf = __builtin_rint(x * kInvLn2);
+  double r = __builtin_fma(-kf, kLn2Hi, x);
+  r = __builtin_fma(-kf, kLn2Lo, r);
+  double q = __builtin_fma(k.c[11], r, k.c[10]);
+#pragma unroll
+  for (int i = 9; i >= 0; --i) q = __builtin_fma(q, r, k.c[i]);
+  const double p = __builtin_fma(r * r, q, r);
+  const double t = __builtin_ldexp(1.0, (int)__builtin_fmax(kf, -1100.0));
+  return __builtin_fma(t, p, t - 1.0);
+}
+
 // A copy of a wave-uniform value held in a VGPR, so that FP64 operations
 // pairing it with a per-TOA SGPR operand need no register copy (a VOP3
 // instruction reads at most one SGPR).

@@ -408,7 +408,8 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       f.st = pnf ? kPNF : 0;
       const double ss2 = a.mc.ss2;
       const RecPtr rec = (RecPtr)a.rec;
-      const double ss2v = in_vgpr(ss2), c13 = in_vgpr(kExpm1Coef[11]);
+      const double ss2v = in_vgpr(ss2);
+      const Expm1Coef kc = expm1_coef_vgpr();
       // Two records in flight: step k waits for the record of step k + 1
       // (fetched during step k - 1), evaluates its red decay, and fetches
       // the record of step k + 2, so every scalar load has a whole step to
@@ -418,7 +419,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       if (kb < ke) {
         r1 = load_rec(rec, kb);
         r2 = load_rec(rec, kb + 1 < ke ? kb + 1 : kb);
-        em1 = expm1_v(-gr * r1.dt, c13);
+        em1 = expm1_c(-gr * r1.dt, kc);
       }
       for (int k = kb; k < ke; ++k) {
         const TOARec r = r1;
@@ -426,7 +427,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
         r1 = r2;
         sgpr_ready(r1.dt);
         r2 = load_rec(rec, k < ke - 2 ? k + 2 : ke - 1);
-        em1 = expm1_v(-gr * r1.dt, c13);
+        em1 = expm1_c(-gr * r1.dt, kc);
         step4(f, r, em, vr, vc, efac2, equad2, ss2v);
       }
       st = f.st;
