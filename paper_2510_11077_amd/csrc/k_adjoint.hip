@@ -838,7 +838,7 @@ __device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, 
     if (N > 0) {
       vn = load_rec_v(recv, kb);
       cn = chrom[kb];
-      dt2 = dts[8 * (kb + (N > 1 ? 1 : 0))];
+      dt2 = dts[8 * (int64_t)(kb + (N > 1 ? 1 : 0))];
       emn = expm1_v(-gr * vn[0], c13);
       emdn = expm1_v(-gd * vn[0], c13);
     }
@@ -851,7 +851,7 @@ __device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, 
       const int kn = kb + (k + 1 < N ? k + 1 : k);
       vn = load_rec_v(recv, kn);
       cn = chrom[kn];
-      dt2 = dts[8 * (kb + (k < N - 2 ? k + 2 : N - 1))];
+      dt2 = dts[8 * (int64_t)(kb + (k < N - 2 ? k + 2 : N - 1))];
       emn = expm1_v(-gr * dt1, c13);
       emdn = expm1_v(-gd * dt1, c13);
       const double dt = r.dt;

@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       if (kb < ke) {
         vn = load_rec_v(recv, kb);
         cn = chrom[kb];
-        dt2 = dts[8 * (kb + 1 < ke ? kb + 1 : kb)];
+        dt2 = dts[8 * (int64_t)(kb + 1 < ke ? kb + 1 : kb)];
         emn = expm1_v(-gr * vn[0], c13);
         emdn = expm1_v(-gd * vn[0], c13);
       }
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
         const int kn = k + 1 < ke ? k + 1 : k;
         vn = load_rec_v(recv, kn);
         cn = chrom[kn];
-        dt2 = dts[8 * (k < ke - 2 ? k + 2 : ke - 1)];
+        dt2 = dts[8 * (int64_t)(k < ke - 2 ? k + 2 : ke - 1)];
         emn = expm1_v(-gr * dt1, c13);
         emdn = expm1_v(-gd * dt1, c13);
         step5(f, r, c, em, emd, vr, vc, vd, efac2, equad2, ss2v);
