@@ -406,6 +406,25 @@ def main():
             "frac_fp64_peak": fl6 / (ms6d * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
         log("DM model: %.3f ms/call, %.4g evals/s, %.2f TFLOP/s (alg.)"
             % (ms6d, S6 / (ms6d * 1e-3), fl6 / (ms6d * 1e-3) / 1e12))
+        # smoothed r, f, a, g, m at every TOA for the first 1024 of those samples
+        try:
+            S6s = min(S6, 1024)
+            t6s = t6[:S6s].contiguous()
+            sm6 = torch.empty((d6.n_toa, 5, S6s), dtype=torch.float64, device=dev)
+            sv6 = torch.empty_like(sm6)
+            ds6.smooth(t6s, sm6, sv6)
+            ms6s, _ = timed(lambda: ds6.smooth(t6s, sm6, sv6), 5, 1, stream)
+            out6 = 2 * sm6.numel() * 8
+            extra["dm_smooth_47psr_1024samples"] = {
+                "ms_per_call": ms6s, "samples_per_s": S6s / (ms6s * 1e-3),
+                "toa_states_per_s": d6.n_toa * S6s / (ms6s * 1e-3),
+                "output_GB": out6 / 1e9,
+                "output_write_GB_per_s": out6 / (ms6s * 1e-3) / 1e9}
+            log("DM smooth: %.3f ms/call, %.1f GB/s of output"
+                % (ms6s, out6 / (ms6s * 1e-3) / 1e9))
+            del sm6, sv6
+        except A.ArgusError as e:
+            extra["dm_smooth_47psr_1024samples"] = "unavailable: %s" % e
         del ds6
 
         # joint 80-state HD model, 20 pulsars x 1000 TOAs, 256 samples

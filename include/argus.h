@@ -196,7 +196,8 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
  * components at t_k given all of its TOAs (paper: Summary and Statement of
  * Need: the filter tracks the realised, time-ordered noise; the fixed-interval
  * smoother completes it with the later data). Components c: r, f, a, g
- * (nc = 4) for model 2; r, f (nc = 2) for model 1.
+ * (nc = 4) for model 2; r, f (nc = 2) for model 1; r, f, a, g, m (nc = 5)
+ * for model 4.
  *   mean: dev [N*nc*S] FP64, element ((k*nc + c)*S + s), k the dataset's
  *         global TOA index (pulsar-major CSR order)
  *   var:  dev, same layout, or NULL for means only
@@ -206,9 +207,10 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
  * common ones) are NaN. Computed from the reverse sweep of the checkpointed
  * adjoint gradient, no matrix inverse: E[x|y] = x + P xb and Cov[x|y] = P +
  * P (2M - xb xb^T) P with (x, P) filtered and (xb, M) the adjoints of logL
- * with respect to them. Models 3 and 4 return ARGUS_E_UNSUPPORTED; N*4*S above
- * 2^40 elements, or a pulsar with more than 33,554,431 TOAs, returns
- * ARGUS_E_UNSUPPORTED. */
+ * with respect to them (model 4: the modified Bryson-Frazier recursion over
+ * the filtered states, the same moments). Model 3 returns
+ * ARGUS_E_UNSUPPORTED; N*nc*S above 2^40 elements, or a pulsar with more than
+ * 33,554,431 TOAs, returns ARGUS_E_UNSUPPORTED. */
 int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
                  double* var, double* logl, int32_t* status, void* stream);
 

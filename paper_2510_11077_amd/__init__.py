@@ -197,14 +197,14 @@ class Dataset:
         return out, grad, status
 
     def smooth(self, theta, mean=None, var=None, want_var=True, stream=None):
-        """Smoothed latent states (models 1, 2): posterior mean and variance
-        of each TOA's own pulsar state given all its TOAs, mean/var
-        [N, nc, S] float64 (nc = 2 for model 1, 4 for model 2: r, f, a, g),
-        plus logl [S] and status [S]."""
+        """Smoothed latent states (models 1, 2, 4): posterior mean and
+        variance of each TOA's own pulsar state given all its TOAs, mean/var
+        [N, nc, S] float64 (nc = 2 for model 1: r, f; 4 for model 2: r, f,
+        a, g; 5 for model 4: r, f, a, g, m), plus logl [S] and status [S]."""
         import torch
         tp = self._theta(theta)
         S = theta.shape[0]
-        nc = 2 if self.model == M1_SPIN else 4
+        nc = {M1_SPIN: 2, M4_PSR5_DM: 5}.get(self.model, 4)
         shape = (self.n_toa, nc, S)
         if mean is None:
             mean = torch.empty(shape, dtype=torch.float64, device=theta.device)

@@ -687,9 +687,10 @@ extern "C" int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, 
                             double* var, double* logl, int32_t* status, void* stream) {
   int rc = check_call(ds, theta, S, mean);
   if (rc || S == 0) return rc;
-  if (ds->model == ARGUS_M3_JOINT_HD || ds->model == ARGUS_M4_PSR5_DM)
-    return fail(ARGUS_E_UNSUPPORTED, "the smoother covers models 1 and 2");
-  if (ds->N > 0 && (uint64_t)ds->N * 4 * (uint64_t)S > ((uint64_t)1 << 40))
-    return fail(ARGUS_E_UNSUPPORTED, "N * S too large for one call");
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "the smoother covers models 1, 2 and 4");
+  const uint64_t nc = ds->model == ARGUS_M1_SPIN ? 2 : (ds->model == ARGUS_M4_PSR5_DM ? 5 : 4);
+  if (ds->N > 0 && (uint64_t)ds->N * nc * (uint64_t)S > ((uint64_t)1 << 40))
+    return fail(ARGUS_E_UNSUPPORTED, "N * nc * S too large for one call");
   return smooth_states(ds, theta, S, mean, var, logl, status, (hipStream_t)stream);
 }

@@ -65,6 +65,7 @@ constexpr int kFields = 14;  // x (4) + P (10)
 
 struct AdjArgs {
   const TOARec* rec;
+  const double* chrom;      // [N] chromatic factor per TOA (model 4)
   const int64_t* off;
   const double* theta;
   const int32_t* col;
@@ -1018,6 +1019,321 @@ __global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Smoother of model 4 (state [r, f, a, g, m], h = [1, 0, 1, 1, c]): the
+// forward filter with checkpoints as k_adjoint, and the backward recursion
+// of the modified Bryson-Frazier smoother on the filtered states (no
+// inverse). With (lt, Lt) the adjoint information of the filtered state
+// after TOA k (zero after the last TOA), the smoothed moments of TOA k are
+//   E = x+ - P+ lt,   Cov = P+ - P+ Lt P+,
+// the information moves back through the update of TOA k,
+//   lh = lt - h (e / S + K^T lt),
+//   Lh = Lt - h (Lt K)^T - (Lt K) h^T + h h^T (K^T Lt K + 1 / S),
+// and through its transition F_k to the filtered state after TOA k - 1,
+//   lt = F_k^T lh,   Lt = F_k^T Lh F_k.
+// The forward step is the model 4 filter step with the Joseph update in the
+// W = P- - K u^T, z = R K - W h, P+ = W + z K^T form (as the model 2
+// smoother). A saved state is 20 fields: x (5) and the lower triangle of P.
+constexpr int kF5 = 20;
+
+struct St5 {
+  double x[5];
+  double P[15];
+};
+struct Lane5 {
+  double gr, gd, vr, vd, vc, efac2, equad2, ss2;
+};
+
+__device__ __forceinline__ void put_st5(double* base, int lane, const St5& s) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) base[i * kWave + lane] = s.x[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) base[(5 + i) * kWave + lane] = s.P[i];
+}
+__device__ __forceinline__ St5 get_st5(const double* base, int lane) {
+  St5 s;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) s.x[i] = base[i * kWave + lane];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) s.P[i] = base[(5 + i) * kWave + lane];
+  return s;
+}
+
+// One filter step of TOA (record r, chromatic factor c) in place; returns
+// the gain, innovation variance and innovation.
+__device__ __forceinline__ void fwd5(St5& s, const TOARec& r, double c, const Lane5& L,
+                                     double K[5], double& S, double& e) {
+  constexpr int NS = 5, NP = 15;
+  const double dt = r.dt;
+  const double em = expm1_k(-L.gr * dt), emd = expm1_k(-L.gd * dt);
+  const double dg[NS] = {1.0, 1.0, 1.0 + em, r.phc, 1.0 + emd};  // diagonal part of F
+  double FP[NS][NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    FP[0][j] = fma(dt, s.P[si5(1, j)], s.P[si5(0, j)]);
+#pragma unroll
+    for (int i = 1; i < NS; ++i) FP[i][j] = dg[i] * s.P[si5(i, j)];
+  }
+  double xm[NS], Pm[NP];
+  xm[0] = fma(dt, s.x[1], s.x[0]);
+#pragma unroll
+  for (int i = 1; i < NS; ++i) xm[i] = dg[i] * s.x[i];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j)
+      Pm[si5(i, j)] = j == 0 ? fma(dt, FP[i][1], FP[i][0]) : dg[j] * FP[i][j];
+  Pm[si5(0, 0)] += L.ss2 * r.h3;
+  Pm[si5(1, 0)] += L.ss2 * r.h2;
+  Pm[si5(1, 1)] += L.ss2 * dt;
+  Pm[si5(2, 2)] = fma(L.vr, -em * (2.0 + em), Pm[si5(2, 2)]);
+  Pm[si5(3, 3)] = fma(L.vc, r.qcu, Pm[si5(3, 3)]);
+  Pm[si5(4, 4)] = fma(L.vd, -emd * (2.0 + emd), Pm[si5(4, 4)]);
+  const double hw[NS] = {1.0, 0.0, 1.0, 1.0, c};
+  double u[NS], hx = 0.0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < NS; ++l)
+      if (h5(l)) t = fma(hw[l], Pm[si5(i, l)], t);
+    u[i] = t;
+    if (h5(i)) hx = fma(hw[i], xm[i], hx);
+  }
+  double hu = 0.0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    if (h5(i)) hu = fma(hw[i], u[i], hu);
+  const double R = fma(L.efac2, r.s2, L.equad2);
+  S = hu + R;
+  e = r.y - hx;
+  const double inv = rcp_nr(S);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) K[i] = u[i] * inv;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) s.x[i] = fma(K[i], e, xm[i]);
+  // W = P- - K u^T (full), z = R K - W h, P+ = W + z K^T (entries i <= j)
+  double W[NS][NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = 0; j < NS; ++j) W[i][j] = fma(-K[i], u[j], Pm[si5(i, j)]);
+  double z[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double wh = 0.0;
+#pragma unroll
+    for (int l = 0; l < NS; ++l)
+      if (h5(l)) wh = fma(hw[l], W[i][l], wh);
+    z[i] = fma(R, K[i], -wh);
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = i; j < NS; ++j) s.P[si5(i, j)] = fma(z[i], K[j], W[i][j]);
+}
+
+// Smoothed mean and variance of TOA k from its filtered state and the
+// adjoint information (lt, Lt); NaN when the filter failed.
+__device__ __forceinline__ void put_smooth5(const AdjArgs& a, int64_t k, int64_t s,
+                                            const St5& f, const double lt[5],
+                                            const double Lt[15], bool bad) {
+  constexpr int NS = 5;
+  double* mo = a.smean + k * NS * a.S + s;
+  double* vo = a.svar ? a.svar + k * NS * a.S + s : nullptr;
+  const double nan = __builtin_nan("");
+#pragma unroll
+  for (int c = 0; c < NS; ++c) {
+    double m = f.x[c], v = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      m = fma(-f.P[si5(c, i)], lt[i], m);
+      double lp = 0.0;  // (Lt P+)_{i c}
+#pragma unroll
+      for (int j = 0; j < NS; ++j) lp = fma(Lt[si5(i, j)], f.P[si5(j, c)], lp);
+      v = fma(f.P[si5(c, i)], lp, v);
+    }
+    mo[c * a.S] = bad ? nan : m;
+    if (vo) vo[c * a.S] = bad ? nan : f.P[si5(c, c)] - v;
+  }
+}
+
+// The adjoint information moved back through the update of TOA k (gain K,
+// innovation variance S, innovation e, chromatic factor c) and through its
+// transition (record r) to the filtered state after TOA k - 1.
+__device__ __forceinline__ void bwd5(double lt[5], double Lt[15], const double K[5], double S,
+                                     double e, double c, const TOARec& r, const Lane5& L) {
+  constexpr int NS = 5, NP = 15;
+  const double hw[NS] = {1.0, 0.0, 1.0, 1.0, c};
+  const double inv = rcp_nr(S);
+  double ktl = 0.0, LK[NS], klk = 0.0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) ktl = fma(K[i], lt[i], ktl);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) t = fma(Lt[si5(i, j)], K[j], t);
+    LK[i] = t;
+    klk = fma(K[i], t, klk);
+  }
+  const double g = fma(e, inv, ktl), q = klk + inv;
+  double lh[NS], Lh[NP];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) lh[i] = h5(i) ? fma(-hw[i], g, lt[i]) : lt[i];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double v = Lt[si5(i, j)];
+      if (h5(i)) v = fma(-hw[i], LK[j], v);
+      if (h5(j)) v = fma(-LK[i], hw[j], v);
+      if (h5(i) && h5(j)) v = fma(hw[i] * hw[j], q, v);
+      Lh[si5(i, j)] = v;
+    }
+  // F = diag(1, 1, phi_r, phi_c, phi_d) + dt e_0 e_1^T for the interval
+  // ending at TOA k: lt = F^T lh, Lt = F^T Lh F
+  const double dt = r.dt;
+  const double dg[NS] = {1.0, 1.0, 1.0 + expm1_k(-L.gr * dt), r.phc, 1.0 + expm1_k(-L.gd * dt)};
+  lt[0] = lh[0];
+  lt[1] = fma(dt, lh[0], lh[1]);
+#pragma unroll
+  for (int i = 2; i < NS; ++i) lt[i] = dg[i] * lh[i];
+  double G[NS][NS];  // Lh F
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    G[i][0] = Lh[si5(i, 0)];
+    G[i][1] = fma(dt, Lh[si5(i, 0)], Lh[si5(i, 1)]);
+#pragma unroll
+    for (int k = 2; k < NS; ++k) G[i][k] = dg[k] * Lh[si5(i, k)];
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int k = 0; k <= i; ++k)
+      Lt[si5(i, k)] = i == 0 ? G[0][k] : (i == 1 ? fma(dt, G[0][k], G[1][k]) : dg[i] * G[i][k]);
+}
+
+__global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
+  constexpr int NS = 5, NP = 15;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gwave = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  double* scr = a.scratch + (int64_t)gwave * a.max_sub * kF5 * kWave;
+  const RecPtr rec = (RecPtr)a.rec;
+  const ConstDPtr chrom = (ConstDPtr)a.chrom;
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int it = __builtin_amdgcn_readfirstlane(v);
+    if (it >= a.n_items) break;
+    const int tile = a.items[2 * it];
+    const int p = a.items[2 * it + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+    const int c1 = a.c1[p];
+    double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kF5 * kWave;
+
+    const int c0 = 6 * p, cc = 6 * a.P;
+    const double t0 = prm(a, c0, s), t1 = prm(a, c0 + 1, s), t2 = prm(a, c0 + 2, s);
+    const double t3 = prm(a, c0 + 3, s), t4 = prm(a, c0 + 4, s), t5 = prm(a, c0 + 5, s);
+    const double t6 = prm(a, cc, s), t7 = prm(a, cc + 1, s);
+    const bool pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) &&
+                       finite_d(t4) && finite_d(t5) && finite_d(t6) && finite_d(t7));
+    Lane5 L;
+    L.gr = exp10(t1);
+    L.gd = exp10(t5);
+    const double sr = exp10(t0), sdm = exp10(t4), eq = exp10(t3);
+    L.vr = sr * sr / (2.0 * L.gr);
+    L.vd = sdm * sdm / (2.0 * L.gd);
+    const double gm1 = t7 - 1.0;
+    L.vc = exp(2.0 * kLn10 * t6 + (t7 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+           (12.0 * kPi * kPi * gm1);
+    L.efac2 = t2 * t2;
+    L.equad2 = eq * eq;
+    L.ss2 = a.mc.ss2;
+
+    // forward pass: log-likelihood and level-1 checkpoints (the state
+    // before the first TOA of each segment of c1 TOAs)
+    St5 st;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) st.x[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) st.P[i] = 0.0;
+    st.P[si5(0, 0)] = a.mc.s_r2;
+    st.P[si5(1, 1)] = a.mc.s_f2;
+    st.P[si5(2, 2)] = L.vr;
+    st.P[si5(3, 3)] = L.vc;
+    st.P[si5(4, 4)] = L.vd;
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+    for (int k = 0; k < N; ++k) {
+      if (k % c1 == 0) put_st5(ck + (int64_t)(k / c1) * kF5 * kWave, lane, st);
+      double K[NS], S, e;
+      fwd5(st, load_rec(rec, kb + k), chrom[kb + k], L, K, S, e);
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e * e, rcp_nr(S), quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    }
+    double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+    if (stat) ll = -INFINITY;
+
+    // backward pass over the segments, last first: recompute a segment to
+    // level-2 checkpoints every 4 TOAs, then take its 4-TOA pieces last
+    // first, each TOA's filtered state recomputed from its piece's checkpoint
+    double lt[NS], Lt[NP];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) lt[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) Lt[i] = 0.0;
+    const bool bad = stat != 0;
+    const int nseg = (N + c1 - 1) / c1;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int k0 = sg * c1;
+      const int k1 = k0 + c1 < N ? k0 + c1 : N;
+      const int nsub = (k1 - k0 + 3) / 4;
+      St5 cur = get_st5(ck + (int64_t)sg * kF5 * kWave, lane);
+      for (int t = 0; t < nsub; ++t) {
+        put_st5(scr + (int64_t)t * kF5 * kWave, lane, cur);
+        if (t + 1 < nsub) {
+          for (int i = 0; i < 4; ++i) {
+            double K[NS], S, e;
+            const int k = k0 + 4 * t + i;
+            fwd5(cur, load_rec(rec, kb + k), chrom[kb + k], L, K, S, e);
+          }
+        }
+      }
+      for (int t = nsub - 1; t >= 0; --t) {
+        const int ks = k0 + 4 * t;
+        const int nt = k1 - ks < 4 ? k1 - ks : 4;
+        const St5 s0 = get_st5(scr + (int64_t)t * kF5 * kWave, lane);
+        for (int i = nt - 1; i >= 0; --i) {
+          St5 c = s0;
+          double K[NS], S, e;
+          for (int j = 0; j < i; ++j) fwd5(c, load_rec(rec, kb + ks + j), chrom[kb + ks + j], L, K, S, e);
+          const int k = ks + i;
+          const TOARec r = load_rec(rec, kb + k);
+          const double ch = chrom[kb + k];
+          fwd5(c, r, ch, L, K, S, e);
+          if (valid) put_smooth5(a, kb + k, s, c, lt, Lt, bad);
+          bwd5(lt, Lt, K, S, e, ch, r, L);
+        }
+      }
+    }
+    if (valid) {
+      a.part[(int64_t)p * a.S + s] = ll;
+      a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+  }
+}
+
 // grad[s, c] from the per-pulsar parts, one thread per element (consecutive
 // threads on consecutive columns of a row, so the rows are written whole): a
 // pulsar's own parameters from its filter, the common ones summed over
@@ -1284,14 +1600,15 @@ int adjoint_setup(argus_dataset* ds, Workspace* w, int64_t S) {
   }
   w->tot_seg = tot;
   w->max_sub = cmax / 4;
+  const int fields = ds->model == 4 ? kF5 : kFields;  // doubles per saved state
   w->grad_waves = (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu);
   w->grad_waves = ((w->grad_waves + 3) / 4) * 4;
   int rc;
   if ((rc = w->c1.upload(c1.data(), c1.size() * sizeof(int32_t))) ||
       (rc = w->seg_base.upload(base.data(), base.size() * sizeof(int64_t))) ||
-      (rc = w->ckpt.alloc((size_t)std::max<int64_t>(tiles * tot, 1) * kFields * kWave *
+      (rc = w->ckpt.alloc((size_t)std::max<int64_t>(tiles * tot, 1) * fields * kWave *
                           sizeof(double))) ||
-      (rc = w->scratch.alloc((size_t)w->grad_waves * w->max_sub * kFields * kWave *
+      (rc = w->scratch.alloc((size_t)w->grad_waves * w->max_sub * fields * kWave *
                              sizeof(double))))
     return rc;
   w->grad_ready = true;
@@ -1301,6 +1618,7 @@ int adjoint_setup(argus_dataset* ds, Workspace* w, int64_t S) {
 AdjArgs adjoint_args(argus_dataset* ds, Workspace* w, const double* theta, int64_t S) {
   AdjArgs a{};
   a.rec = ds->rec.as<TOARec>();
+  a.chrom = ds->chrom.as<double>();
   a.off = ds->off.as<int64_t>();
   a.theta = theta;
   a.col = ds->col.as<int32_t>();
@@ -1320,7 +1638,7 @@ AdjArgs adjoint_args(argus_dataset* ds, Workspace* w, const double* theta, int64
   a.n_items = w->n_items;
   a.max_sub = w->max_sub;
   a.model = ds->model;
-  a.nc = ds->model == 1 ? 2 : 4;
+  a.nc = ds->model == 1 ? 2 : (ds->model == 4 ? 5 : 4);
   a.mc = ds->mc;
   return a;
 }
@@ -1356,7 +1674,10 @@ int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mea
   AdjArgs a = adjoint_args(ds, w, theta, S);
   a.smean = mean;
   a.svar = var;
-  hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+  if (ds->model == 4)
+    hipLaunchKernelGGL(k_smooth5, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
   HIPCHK(hipGetLastError());
   double* ll = logl ? logl : w->logl_tmp.as<double>();
   int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();

@@ -93,13 +93,6 @@ def test_dm_forced_layouts(argus, orc, cfg, monkeypatch):
     run(argus, orc, d, pi.sample_theta(d, 200, 15))
 
 
-def test_dm_smoother_unsupported(argus):
-    d = pi.make_pta_dm("t", n_psr=2, counts=[5, 6], seed=55)
-    ds = argus.Dataset(d)
-    with pytest.raises(argus.ArgusError, match="smoother"):
-        ds.smooth(dev(pi.sample_theta(d, 2, 1)))
-
-
 # ------------------------------------------------------------------ gradient
 def check_grad(g, gref, tol=1e-9):
     """As for the other models: ||g - g_ref||_inf <= tol max(||g_ref||_inf, 1)

@@ -1,7 +1,8 @@
 """Parity of the HIP smoother (argus_smooth: the reverse sweep of the
 checkpointed adjoint kernel writing E[x|y] = x + P xb and Cov[x|y] = P +
-P (2M - xb xb^T) P per TOA) with the oracle's Rauch-Tung-Striebel recursion,
-element by element, through the C ABI.
+P (2M - xb xb^T) P per TOA; for the DM model the modified Bryson-Frazier
+recursion over the filtered states) with the oracle's Rauch-Tung-Striebel
+recursion, element by element, through the C ABI.
 
 Tolerances: |mean_gpu - mean_ref| <= 1e-9 sd_ref and |var_gpu - var_ref| <=
 1e-8 var_ref, sd_ref = sqrt(var_ref). Both sides are fp64 but follow
@@ -164,7 +165,7 @@ def test_cfg4_full_batch_sampled(argus, orc):
 def test_joint_model_unsupported(argus):
     d = pi.make_pta("t", n_psr=2, counts=[5, 6], seed=35, model=pi.M_JOINT)
     ds = argus.Dataset(d)
-    with pytest.raises(argus.ArgusError, match="models 1 and 2"):
+    with pytest.raises(argus.ArgusError, match="models 1, 2 and 4"):
         ds.smooth(dev(pi.sample_theta(d, 2, 1)))
 
 
@@ -179,4 +180,30 @@ def test_spin_noise_after_a_long_gap(argus, orc):
     d = dataclasses.replace(d, t=d.t[keep], y=d.y[keep], sigma=d.sigma[keep],
                             off=np.array([0, keep.size], np.int64))
     th = np.array([[d.hi[0], 1.0], [d.hi[0] - 0.5, 0.9], [d.lo[0], 1.1]])
+    run(argus, orc, d, th)
+
+
+@pytest.mark.parametrize("S", [1, 70])
+def test_dm_model_ragged_tiles(argus, orc, S):
+    """Model 4 (state r, f, a, g, m; chromatic factor per TOA): empty,
+    one-TOA and ragged pulsars, partial tiles."""
+    d = pi.make_pta_dm("t", n_psr=6, counts=[1, 0, 37, 64, 130, 257], seed=61)
+    th = pi.sample_theta(d, S, 62)
+    m, v = run(argus, orc, d, th)
+    assert m.shape[2] == 5
+
+
+def test_dm_model_long_pulsar_near_truth(argus, orc):
+    """Several checkpoint segments and 4-TOA pieces, and posteriors much
+    tighter than the priors."""
+    d = pi.make_pta_dm("t", n_psr=2, counts=[1500, 333], seed=63)
+    th = pi.theta_near_truth(d, 64, 64, scale=0.05)
+    run(argus, orc, d, th)
+
+
+def test_dm_model_prior_corners(argus, orc):
+    d = pi.make_pta_dm("t", n_psr=3, counts=[40, 25, 60], seed=65)
+    lo, hi = d.lo[d.free], d.hi[d.free]
+    rng = np.random.default_rng(66)
+    th = np.where(rng.random((16, lo.size)) < 0.5, lo, hi)
     run(argus, orc, d, th)
