@@ -162,17 +162,25 @@ __global__ void k_out_eval(const __bf16* a3, int64_t Q, int width, const float* 
 // Fused inference for width W <= 256: one persistent block of W / 32 waves
 // per CU. Wave w owns output columns [32 w, 32 w + 32) of every hidden layer
 // and keeps those columns of W1, W2, W3 in registers as MFMA B fragments for
-// the whole launch; 64-row chunks of queries go through standardisation,
+// the whole launch; 128-row chunks of queries go through standardisation,
 // the three hidden layers (activations in LDS, BF16, ping-pong) and the FP32
 // output layer. Same rounding as the unfused path: inputs, weights and each
 // activation in BF16, FP32 accumulation, bias and SiLU in FP32.
+//
+// The SiLU epilogue (two transcendentals per element, each occupying the
+// SIMD four times as long as an FMA) costs more issue time than the MFMAs.
+// Within a layer a wave therefore runs the MFMA chain of 32-row block b + 1
+// interleaved with the epilogue of block b: the matrix core works through
+// the chain while the vector unit evaluates the activations, and only the
+// first chain and the last epilogue of a layer run alone.
+constexpr int kFusedRows = 64;
 struct FusedArgs {
   const double* theta;   // [Q x d_in]
   const double* lo;      // [d_in]
   const double* hi;
   const __bf16* W1;      // [W x kKin]
-  const __bf16* W2;      // [W x W] (out x in)
-  const __bf16* W3;
+  const __bf16* W2F;     // [W x W] in fragment order (frag_index)
+  const __bf16* W3F;
   const float* p32;      // packed FP32 parameters (biases, W4, b4)
   double* out;           // [Q]
   int64_t Q;
@@ -184,7 +192,8 @@ template <int W>
 __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
   constexpr int NW = W / 32;     // waves
   constexpr int KS = W / 16;     // K steps of a hidden layer
-  constexpr int R = 64;          // query rows per chunk
+  constexpr int R = kFusedRows;  // query rows per chunk
+  constexpr int RB = R / 32;      // 32-row MFMA blocks per chunk
   constexpr int LDA = W + 8;     // activation row stride (16-B pad: b128 reads spread over banks)
   constexpr int LDX = kKin + 8;
   __shared__ __bf16 s_x[R * LDX];
@@ -193,45 +202,7 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int ncol = 32 * w + (l & 31);     // B-fragment / accumulator column
   const int kh = 8 * (l >> 5);            // this lane's K half within a step
-  bf16x8 w1[2], w2[KS], w3[KS];
-#pragma unroll
-  for (int ks = 0; ks < 2; ++ks)
-    w1[ks] = *reinterpret_cast<const bf16x8*>(f.W1 + (size_t)ncol * kKin + 16 * ks + kh);
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    w2[ks] = *reinterpret_cast<const bf16x8*>(f.W2 + (size_t)ncol * W + 16 * ks + kh);
-    w3[ks] = *reinterpret_cast<const bf16x8*>(f.W3 + (size_t)ncol * W + 16 * ks + kh);
-  }
   const int d = f.d_in;
-  const float* b1 = f.p32 + (int64_t)W * d;
-  const float* b2 = b1 + W + (int64_t)W * W;
-  const float* b3 = b2 + W + (int64_t)W * W;
-  const float* W4 = b3 + W;
-  const float bias1 = b1[ncol], bias2 = b2[ncol], bias3 = b3[ncol], b4 = W4[W];
-
-  // one hidden layer: src rows (stride lds) x this wave's 32 columns -> dst;
-  // ksn carries the number of K steps as a type (2 for the input layer)
-  auto layer = [&](auto ksn, const __bf16* src, int lds, const bf16x8* wf, float bias,
-                   __bf16* dst) {
-    constexpr int KSN = decltype(ksn)::value;
-#pragma unroll
-    for (int rb = 0; rb < R / 32; ++rb) {
-      f32x16 acc = {};
-      const __bf16* ap = src + (rb * 32 + (l & 31)) * lds + kh;
-#pragma unroll
-      for (int ks = 0; ks < KSN; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap + 16 * ks);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wf[ks], acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = rb * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-        const float z = acc[r] + bias;
-        dst[row * LDA + ncol] = (__bf16)(z * sigm(z));
-      }
-    }
-  };
-
   // standardised inputs of a chunk (rows past Q are zero), loaded into
   // registers one chunk ahead
   constexpr int NT = NW * 64, PF = (R * kKin + NT - 1) / NT;
@@ -247,7 +218,67 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
       pf[j] = v;
     }
   };
+  // the first chunk's inputs before the weights, so that its wait does not
+  // also wait for the weight fragments
   fetch((int64_t)blockIdx.x * R);
+  bf16x8 w1[2], w2[KS], w3[KS];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+    w1[ks] = *reinterpret_cast<const bf16x8*>(f.W1 + (size_t)ncol * kKin + 16 * ks + kh);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    // 1 KB contiguous per wave and K step
+    const size_t fo = ((size_t)(w * KS + ks) * 64 + l) * 8;
+    w2[ks] = *reinterpret_cast<const bf16x8*>(f.W2F + fo);
+    w3[ks] = *reinterpret_cast<const bf16x8*>(f.W3F + fo);
+  }
+  const float* b1 = f.p32 + (int64_t)W * d;
+  const float* b2 = b1 + W + (int64_t)W * W;
+  const float* b3 = b2 + W + (int64_t)W * W;
+  const float* W4 = b3 + W;
+  const float bias1 = b1[ncol], bias2 = b2[ncol], bias3 = b3[ncol], b4 = W4[W];
+
+  // one hidden layer: src rows (stride lds) x this wave's 32 columns -> dst;
+  // ksn carries the number of K steps as a type (2 for the input layer).
+  // Accumulator element r of 32-row block rb is row rb*32 + 8(r/4) + 4(l/32)
+  // + r%4 of column ncol.
+  auto layer = [&](auto ksn, const __bf16* src, int lds, const bf16x8* wf, float bias,
+                   __bf16* dst) {
+    constexpr int KSN = decltype(ksn)::value;
+    const __bf16* ap0 = src + (l & 31) * lds + kh;
+    auto epi = [&](const f32x16& acc, int rb, int r) {
+      const int row = rb * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+      const float z = acc[r] + bias;
+      dst[row * LDA + ncol] = (__bf16)(z * sigm(z));
+    };
+    f32x16 cur = {};
+#pragma unroll
+    for (int ks = 0; ks < KSN; ++ks) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap0 + 16 * ks);
+      cur = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wf[ks], cur, 0, 0, 0);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      if (rb + 1 < RB) {
+        // chain of block rb + 1, one K step at a time, with the epilogue
+        // elements of block rb spread evenly between its MFMAs
+        f32x16 nxt = {};
+        const __bf16* ap = ap0 + (rb + 1) * 32 * lds;
+#pragma unroll
+        for (int ks = 0; ks < KSN; ++ks) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap + 16 * ks);
+          nxt = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wf[ks], nxt, 0, 0, 0);
+#pragma unroll
+          for (int r = ks * 16 / KSN; r < (ks + 1) * 16 / KSN; ++r) epi(cur, rb, r);
+        }
+        cur = nxt;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) epi(cur, rb, r);
+      }
+    }
+  };
+
   for (int64_t c = blockIdx.x; c * R < f.Q; c += gridDim.x) {
     const int64_t row0 = c * R;
 #pragma unroll
@@ -263,9 +294,10 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
     __syncthreads();
     layer(std::integral_constant<int, KS>{}, s_a[1], LDA, w3, bias3, s_a[0]);
     __syncthreads();
-    // output layer in FP32: wave w sums its 32 columns for row l
-    {
-      const __bf16* ar = s_a[0] + l * LDA + 32 * w;
+    // output layer in FP32: wave w sums its 32 columns for rows l + 64 h
+#pragma unroll
+    for (int hr = 0; hr < R / 64; ++hr) {
+      const __bf16* ar = s_a[0] + (l + 64 * hr) * LDA + 32 * w;
       float acc = 0.0f;
 #pragma unroll
       for (int j = 0; j < 32; j += 8) {
@@ -273,9 +305,10 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) acc = fmaf((float)v[i], W4[32 * w + j + i], acc);
       }
-      s_o[w][l] = acc;
+      s_o[w][l + 64 * hr] = acc;
     }
     __syncthreads();
+    static_assert(2 * W >= R, "one thread per output row");
     if (t < R && row0 + t < f.Q) {
       float o = 0.0f;
 #pragma unroll
@@ -367,6 +400,17 @@ __global__ void __launch_bounds__(256) k_head_grad(const float* dout, const floa
   }
 }
 
+// Fragment order of a [W x W] hidden weight (W a multiple of 32) for the
+// fused inference kernel, where wave w = n / 32 holds rows [32 w, 32 w + 32)
+// as B fragments of v_mfma_f32_32x32x16_bf16: lane n % 32 + 32 ((k % 16) / 8)
+// of K step k / 16 holds 8 consecutive k, so each wave reads 1 KB contiguous
+// per K step.
+constexpr int kFusedMaxWidth = 256;
+__device__ __forceinline__ int64_t frag_index(int64_t n, int64_t k, int64_t W) {
+  const int64_t w = n >> 5, c = n & 31, ks = k >> 4, h = (k >> 3) & 1, e = k & 7;
+  return (((w * (W >> 4) + ks) << 6) + c + 32 * h) * 8 + e;
+}
+
 struct AdamArgs {
   float* master;
   float* m;
@@ -375,6 +419,7 @@ struct AdamArgs {
   float* p32;             // the handle's FP32 copy (biases, output layer)
   __bf16 *w1, *w2, *w3;   // BF16 hidden weights [w x kKin], [w x w], [w x w]
   __bf16 *w2T, *w3T;      // transposed copies
+  __bf16 *w2F, *w3F;      // fragment-ordered copies for fused inference, or null
   int64_t n;
   int d_in, width;
   // 1 - beta is formed in double on the host: 1.0f - 0.999f is 1.3e-5 off
@@ -394,10 +439,12 @@ __device__ __forceinline__ void scatter_copy(const AdamArgs& a, int64_t i, float
     const int64_t n = (i - o2) / dW, k = (i - o2) % dW;
     a.w2[n * dW + k] = b;
     a.w2T[k * dW + n] = b;
+    if (a.w2F) a.w2F[frag_index(n, k, dW)] = b;
   } else if (i >= o3 && i < o3 + dW * dW) {
     const int64_t n = (i - o3) / dW, k = (i - o3) % dW;
     a.w3[n * dW + k] = b;
     a.w3T[k * dW + n] = b;
+    if (a.w3F) a.w3F[frag_index(n, k, dW)] = b;
   }
 }
 
@@ -527,7 +574,7 @@ struct argus_mlp {
   int d_in = 0, width = 0;
   int64_t n = 0, max_batch = 0;
   int device = 0, n_cu = 256;
-  argus::DevBuf p32, w1, w2, w3, w2T, w3T, lo, hi;
+  argus::DevBuf p32, w1, w2, w3, w2T, w3T, w2F, w3F, lo, hi;
   double mu = 0.0, sd = 1.0;
   bool loaded = false;
   // inference buffers (grown on demand)
@@ -695,6 +742,8 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
   a.w3 = h->w3.as<__bf16>();
   a.w2T = h->w2T.as<__bf16>();
   a.w3T = h->w3T.as<__bf16>();
+  a.w2F = h->w2F.p ? h->w2F.as<__bf16>() : nullptr;
+  a.w3F = h->w3F.p ? h->w3F.as<__bf16>() : nullptr;
   a.n = h->n;
   a.d_in = h->d_in;
   a.width = h->width;
@@ -713,11 +762,12 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
 }
 
 int eval_seq(argus_mlp* h, const double* theta, int64_t Q, double* logl_hat, hipStream_t st) {
-  if (h->width <= 256) {
+  if (h->width <= kFusedMaxWidth) {
     FusedArgs f{theta, h->lo.as<double>(), h->hi.as<double>(), h->w1.as<__bf16>(),
-                h->w2.as<__bf16>(), h->w3.as<__bf16>(), h->p32.as<float>(), logl_hat, Q,
+                h->w2F.as<__bf16>(), h->w3F.as<__bf16>(), h->p32.as<float>(), logl_hat, Q,
                 h->d_in, h->mu, h->sd};
-    const unsigned grid = (unsigned)std::min<int64_t>(h->n_cu, (Q + 63) / 64);
+    const unsigned grid =
+        (unsigned)std::min<int64_t>(h->n_cu, (Q + kFusedRows - 1) / kFusedRows);
     const dim3 block(h->width * 2);
     switch (h->width) {
       case 64: hipLaunchKernelGGL(k_mlp_fused<64>, dim3(grid), block, 0, st, f); break;
@@ -777,6 +827,9 @@ int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t
       (rc = h->x0.alloc(B * kKin * 2)) || (rc = h->x0T.alloc(B * kKin * 2)) ||
       (rc = h->t.alloc(B * 4)) || (rc = h->dout.alloc(B * 4)) || (rc = h->sq.alloc(B * 4)) ||
       (rc = h->g.alloc(h->n * 4)) || (rc = h->wpart.alloc(kWgradSplits * w * w * 4)))
+    return rc;
+  if (w <= kFusedMaxWidth &&
+      ((rc = h->w2F.alloc(w * w * 2)) || (rc = h->w3F.alloc(w * w * 2))))
     return rc;
   for (int l = 0; l < 3; ++l)
     if ((rc = h->z[l].alloc(B * w * 4)) || (rc = h->a[l].alloc(B * w * 2)) ||
