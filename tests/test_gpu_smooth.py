@@ -207,3 +207,20 @@ def test_dm_model_prior_corners(argus, orc):
     rng = np.random.default_rng(66)
     th = np.where(rng.random((16, lo.size)) < 0.5, lo, hi)
     run(argus, orc, d, th)
+
+
+def test_dm_full_batch_sampled(argus, orc):
+    """47 pulsars with DM variations (about 37k TOAs), 1024 samples, launched
+    as the benchmark launches it; the oracle checks three samples."""
+    import torch
+    d = pi.make_config("cfg2dm")
+    th = pi.sample_theta(d, 1024, pi.THETA_SEED["cfg2dm"])
+    ds = argus.Dataset(d)
+    m, v, ll, st = ds.smooth(dev(th))
+    assert bool((st == 0).all()) and bool(torch.isfinite(m).all()) and bool((v > 0).all())
+    idx = [0, 511, 1023]
+    m = m[:, :, idx].cpu().numpy().transpose(2, 0, 1)
+    v = v[:, :, idx].cpu().numpy().transpose(2, 0, 1)
+    rm, rv, rst = orc.smooth(d, d.to_canon(th[idx]))
+    assert (rst == 0).all()
+    check(m, v, rm, rv)

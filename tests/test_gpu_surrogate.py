@@ -65,6 +65,32 @@ def test_forward_matches_oracle(A, Q):
     assert np.median(err / scale) < 1e-3
 
 
+@pytest.mark.parametrize("width", [64, 192, 256])
+def test_forward_after_training_matches_oracle(A, width):
+    """Inference after Adam steps reads the fragment-ordered weight copies
+    that the step refreshes; the oracle runs on the step's FP32 master."""
+    import torch
+    from oracle import mlp
+    rng = np.random.default_rng(width)
+    lo, hi = np.full(D, -1.0), np.full(D, 2.0)
+    net = A.MLP(D, width, 256)
+    net.load(pi.mlp_weights(D, width, 7), lo, hi, 0.0, 1.0)
+    th = rng.uniform(lo, hi, size=(256, D))
+    target = rng.normal(size=256)
+    for _ in range(3):
+        net.train_step(dev(th), dev(target), 1e-2)
+    torch.cuda.synchronize()
+    flat = net.master.cpu().numpy().astype(np.float64)
+    q = rng.uniform(lo, hi, size=(333, D))
+    y = net.eval(dev(q)).cpu().numpy()
+    ref, cache = mlp.forward(flat, mlp.standardise_inputs(q, lo, hi), D, width, emulate=True)
+    p = mlp.unpack(flat, D, width)
+    scale = np.abs(cache["a3"] * p["W4"]).sum(1) + abs(p["b4"][0])
+    err = np.abs(y - ref)
+    assert (err <= 1e-2 * scale).all(), (err / scale).max()
+    assert np.median(err / scale) < 1e-3
+
+
 def test_gradient_matches_oracle(A):
     from oracle import mlp
     flat = rand_net(3)
