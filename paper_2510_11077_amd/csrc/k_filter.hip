@@ -449,13 +449,28 @@ __global__ void k_reduce(ReduceArgs a) {
   double acc = 0.0;
   int st = 0;
   bool pnf = false;
-  for (int p = 0; p < a.P; ++p) {
-    acc += a.part[(int64_t)p * a.S + s];
-    const int c = a.pstat[(int64_t)p * a.S + s];
-    if (c & kPNF)
-      pnf = true;
-    else if (c && !st)
-      st = c;
+  // pulsars in batches: a batch's loads are all issued before its sums, so
+  // a thread waits once per batch instead of once per pulsar; the sum is
+  // still taken in pulsar order
+  constexpr int kBatch = 16;
+  for (int p0 = 0; p0 < a.P; p0 += kBatch) {
+    double v[kBatch];
+    int c[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int p = p0 + j;
+      v[j] = p < a.P ? a.part[(int64_t)p * a.S + s] : 0.0;
+      c[j] = p < a.P ? a.pstat[(int64_t)p * a.S + s] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      if (p0 + j >= a.P) break;
+      acc += v[j];
+      if (c[j] & kPNF)
+        pnf = true;
+      else if (c[j] && !st)
+        st = c[j];
+    }
   }
   if (pnf) st = kNonFinite;
   a.logl[s] = st ? -INFINITY : acc;
