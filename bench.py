@@ -423,6 +423,19 @@ def main():
             log("DM smooth: %.3f ms/call, %.1f GB/s of output"
                 % (ms6s, out6 / (ms6s * 1e-3) / 1e9))
             del sm6, sv6
+            if not args.no_cpu:
+                import oracle
+                oracle.build()
+                n6 = 32
+                c6 = d6.to_canon(t6s[:n6].cpu().numpy())
+                t0 = time.perf_counter()
+                oracle.smooth(d6, c6, nthreads=oracle.default_threads())
+                w6 = time.perf_counter() - t0
+                leg6 = extra["dm_smooth_47psr_1024samples"]
+                leg6["cpu_oracle_samples_per_s"] = n6 / w6
+                leg6["cpu_oracle_sample"] = ("first %d samples, RTS on the dense Joseph-form "
+                                             "filter, %d threads" % (n6, oracle.default_threads()))
+                log("DM smooth cpu oracle: %.4g samples/s" % (n6 / w6))
         except A.ArgusError as e:
             extra["dm_smooth_47psr_1024samples"] = "unavailable: %s" % e
         del ds6
