@@ -224,3 +224,21 @@ def test_dm_full_batch_sampled(argus, orc):
     rm, rv, rst = orc.smooth(d, d.to_canon(th[idx]))
     assert (rst == 0).all()
     check(m, v, rm, rv)
+
+
+def test_dm_failures(argus, orc):
+    """Model 4: a non-finite DM parameter of one pulsar makes only that
+    pulsar's entries NaN; a non-finite common parameter makes all of them NaN;
+    the status words follow the oracle's."""
+    d = pi.make_pta_dm("t", n_psr=3, counts=[10, 12, 8], seed=67)
+    col = np.cumsum(d.free) - 1          # canonical index -> theta column
+    amp, rate = 6 * 1 + 4, 6 * 1 + 5     # pulsar 1's log10 sigma_dm, log10 gamma_dm
+    assert d.free[amp] and d.free[rate] and d.free[-1]
+    th = np.tile(d.truth, (4, 1))
+    th[1, col[amp]] = np.nan
+    th[2, col[rate]] = np.inf
+    th[3, col[-1]] = np.nan
+    m, v = run(argus, orc, d, th)
+    n0, n1 = 10, 12
+    assert np.isnan(m[1, n0:n0 + n1]).all() and not np.isnan(m[1, :n0]).any()
+    assert np.isnan(m[3]).all()
