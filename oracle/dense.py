@@ -135,7 +135,8 @@ def state_cross_cov(d, c):
     """Prior covariances of the latent state at every TOA with every TOA's
     residual: K [nc, N, N], K[m, k, j] = Cov(x_m(t_k) of TOA k's pulsar, y_j),
     and the prior variances V [nc, N] of those state components. Components
-    [r, f, a, g] (model 1: [r, f]); from the same covariance functions as
+    [r, f, a, g] (model 1: [r, f]; model 4: [r, f, a, g, m]); from the same
+    covariance functions as
     covariance(), with the spin ones differentiated in the first time:
       Cov(f(s), r(s')) = s_f^2 s' + sigma_s^2 (s <= s' ? s s' - s^2/2 : s'^2/2),
       Var r(s) = s_r^2 + s_f^2 s^2 + sigma_s^2 s^3/3,  Var f(s) = s_f^2 + sigma_s^2 s."""
@@ -155,15 +156,25 @@ def state_cross_cov(d, c):
     if d.model == 1:
         return np.stack([Kr * same, Kf * same]), np.stack([Vr, Vf])
     P = d.n_psr
+    k = 6 if d.model == 4 else 4
     tau = np.abs(tk - tj)
-    gr = 10.0 ** c[1:4 * P:4]
-    vr = 10.0 ** (2 * c[0:4 * P:4]) / (2 * gr)
+    gr = 10.0 ** c[1:k * P:k]
+    vr = 10.0 ** (2 * c[0:k * P:k]) / (2 * gr)
     Ka = vr[psr][:, None] * np.exp(-gr[psr][:, None] * tau) * same
     G = hd_closed_form(d.pos) if d.model == 3 else np.eye(P)
-    vc = common_var(c[4 * P], c[4 * P + 1], d.t_span)
+    vc = common_var(c[k * P], c[k * P + 1], d.t_span)
     Kg = vc * G[psr[:, None], psr[None, :]] * np.exp(-(2 * np.pi / d.t_span) * tau)
-    V = np.stack([Vr, Vf, vr[psr], vc * np.diag(G)[psr]])
-    return np.stack([Kr * same, Kf * same, Ka, Kg]), V
+    K = [Kr * same, Kf * same, Ka, Kg]
+    V = [Vr, Vf, vr[psr], vc * np.diag(G)[psr]]
+    if d.model == 4:
+        # DM delay m at the reference frequency: residual j sees ch_j m(t_j),
+        # so Cov(m(t_k), y_j) = ch_j v_d exp(-gamma_d |t_k - t_j|)
+        gd = 10.0 ** c[5:k * P:k]
+        vd = 10.0 ** (2 * c[4:k * P:k]) / (2 * gd)
+        ch = (1400.0 / np.asarray(d.freq, np.float64)) ** 2
+        K.append(vd[psr][:, None] * np.exp(-gd[psr][:, None] * tau) * ch[None, :] * same)
+        V.append(vd[psr])
+    return np.stack(K), np.stack(V)
 
 
 def smooth(d, c):
@@ -195,7 +206,8 @@ def noise_posterior(d, c):
         R = c[1] ** 2 * sig ** 2
     else:
         psr = np.repeat(np.arange(d.n_psr), np.diff(d.off))
-        R = c[4 * psr + 2] ** 2 * sig ** 2 + 10.0 ** (2 * c[4 * psr + 3])
+        k = 6 if d.model == 4 else 4
+        R = c[k * psr + 2] ** 2 * sig ** 2 + 10.0 ** (2 * c[k * psr + 3])
     cf = sla.cho_factor(Cm, lower=True)
     Ci = sla.cho_solve(cf, np.eye(y.size))
     return R * (Ci @ y), R - R * R * np.diag(Ci)

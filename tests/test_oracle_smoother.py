@@ -60,6 +60,22 @@ def test_smoother_equals_fp64_conditioning(oracle_mod, model):
         assert err_var(v[s], dv) < 1e-9
 
 
+def test_dm_smoother_equals_fp64_conditioning(oracle_mod):
+    """Model 4 (state r, f, a, g, m, each TOA seeing the DM delay through
+    its chromatic factor): the RTS smoother of the 5-state filter against
+    Gaussian conditioning with the dense DM covariance."""
+    from oracle import dense
+    d = pi.make_pta_dm("t", n_psr=3, counts=[40, 0, 60], seed=69)
+    c = d.to_canon(pi.sample_theta(d, 3, 12))
+    m, v, st = oracle_mod.smooth(d, c)
+    assert (st == 0).all() and m.shape[-1] == 5
+    for s in range(len(c)):
+        dm, dv = dense.smooth(d, c[s])
+        assert dm.shape[1] == 5
+        assert err_mean(m[s], dm, dv) < 1e-9
+        assert err_var(v[s], dv) < 1e-9
+
+
 @pytest.mark.parametrize("model", [1, 2, 3])
 def test_white_noise_posterior_identity(oracle_mod, model):
     """The white noise n_k = y_k - h.x_k has posterior mean R_k (C^-1 y)_k and
