@@ -62,6 +62,11 @@ def standardise_inputs(theta, lo, hi):
     return 2.0 * (np.asarray(theta, np.float64) - lo) / (hi - lo) - 1.0
 
 
+def affine_inputs(theta, center, T):
+    """General affine input map x = T (theta - center), one row per sample."""
+    return (np.asarray(theta, np.float64) - center) @ np.asarray(T, np.float64).T
+
+
 def silu(z):
     return z / (1.0 + np.exp(-z))
 

@@ -104,6 +104,79 @@ def test_emulated_forward_is_close_to_exact():
     assert not np.array_equal(a, b)
 
 
+def test_emulated_gradient_matches_autograd_of_the_rounding_model():
+    """The emulated backward pass places BF16 roundings where the kernels
+    store BF16 values: inputs, hidden weights and activations in the forward
+    pass, and the gradient with respect to each hidden pre-activation (dz,
+    the MFMA operand of the backward products). Independently: PyTorch
+    float64 autograd through the same forward, with torch's own bfloat16
+    conversion as a straight-through rounding on the forward values and a
+    rounding of the incoming gradient placed on each pre-activation. Any
+    other placement (no dz rounding, rounding da instead of dz, a rounded
+    output-layer gradient) fails this at the tolerance used."""
+    import torch
+
+    def rnd(x):
+        return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    class Fwd(torch.autograd.Function):  # rounds values, passes gradients
+        @staticmethod
+        def forward(ctx, x):
+            return rnd(x)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class Bwd(torch.autograd.Function):  # passes values, rounds gradients
+        @staticmethod
+        def forward(ctx, x):
+            return x.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return rnd(g)
+
+    flat = pi.mlp_weights(D_IN, W, 11)
+    flat[np.arange(flat.size) % 5 == 0] += 0.02
+    rng = np.random.default_rng(12)
+    B = 48
+    x = rng.uniform(-1, 1, size=(B, D_IN))
+    t = rng.normal(size=B)
+    loss, g = mlp.loss_and_grad(flat, x, t, D_IN, W, emulate=True)
+    p = {k: torch.tensor(v, requires_grad=True) for k, v in mlp.unpack(flat, D_IN, W).items()}
+    a = Fwd.apply(torch.tensor(x))
+    for l in (1, 2, 3):
+        z = Bwd.apply(a @ Fwd.apply(p["W%d" % l]).T + p["b%d" % l])
+        a = Fwd.apply(torch.nn.functional.silu(z))
+    out = a @ p["W4"] + p["b4"][0]
+    lt = ((out - torch.tensor(t)) ** 2).mean()
+    lt.backward()
+    gref = mlp.pack({k: v.grad.numpy() for k, v in p.items()}, D_IN, W)
+    assert abs(loss - lt.item()) <= 1e-14 * abs(loss)
+    # both sides round the same FP64 values; FP64 summation order differs
+    # only at ~1e-16, which can move a value across a BF16 rounding boundary
+    # in rare elements: compare with a bound far below one BF16 step
+    assert np.abs(g - gref).max() <= 1e-6 * np.abs(gref).max(), np.abs(g - gref).max()
+
+
+def test_affine_input_map():
+    """The box map is the diagonal case of the affine map; the whitening map
+    T = L^-1 (Sigma = L L^T) gives unit covariance."""
+    rng = np.random.default_rng(13)
+    lo, hi = rng.uniform(-5, 0, D_IN), rng.uniform(1, 6, D_IN)
+    th = rng.uniform(lo, hi, size=(200, D_IN))
+    T = np.diag(2.0 / (hi - lo))
+    assert np.allclose(mlp.affine_inputs(th, 0.5 * (lo + hi), T),
+                       mlp.standardise_inputs(th, lo, hi), rtol=0, atol=1e-14)
+    A = rng.normal(size=(D_IN, D_IN))
+    ens = rng.normal(size=(20000, D_IN)) @ A.T + 3.0
+    L = np.linalg.cholesky(np.cov(ens, rowvar=False))
+    u = mlp.affine_inputs(ens, ens.mean(0), np.linalg.inv(L))
+    assert np.allclose(np.cov(u, rowvar=False), np.eye(D_IN), atol=1e-10)
+    assert np.allclose(u.mean(0), 0.0, atol=1e-10)
+
+
 # ------------------------------------------------------------ sampler
 def test_delayed_acceptance_is_exact_with_a_wrong_surrogate():
     """2-D correlated Gaussian target; the surrogate has the wrong mean and
