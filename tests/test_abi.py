@@ -43,18 +43,30 @@ class Desc(C.Structure):
                 ("t", C.c_void_p), ("y", C.c_void_p), ("sigma", C.c_void_p),
                 ("pos", C.c_void_p), ("fixed", C.c_void_p), ("free_mask", C.c_void_p),
                 ("t_span", C.c_double), ("s_r", C.c_double), ("s_f", C.c_double),
-                ("sigma_s", C.c_double)]
+                ("sigma_s", C.c_double), ("freq", C.c_void_p)]
 
 
-def make(model=2, P=2, t=None, y=None, sig=None, pos=None, off=None, fixed=None):
+def test_descriptor_layout_matches_the_header():
+    """The struct above mirrors argus_dataset_desc field by field."""
+    txt = open(HDR).read()
+    body = re.search(r"typedef struct \{(.*?)\} argus_dataset_desc;", txt, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    # each declaration's names are the identifiers followed by "," or its end
+    names = [n for decl in body.split(";") for n in re.findall(r"(\w+)\s*(?:,|$)", decl.strip())]
+    assert names == [f for f, _ in Desc._fields_], names
+
+
+def make(model=2, P=2, t=None, y=None, sig=None, pos=None, off=None, fixed=None, freq=None):
     off = np.array([0, 3, 5] if off is None else off, np.int64)
     t = np.array([1.0, 2.0, 3.0, 1.5, 2.5] if t is None else t)
     y = np.zeros_like(t) if y is None else np.asarray(y, float)
     sig = np.full_like(t, 1e-7) if sig is None else np.asarray(sig, float)
-    keep = [off, t, y, sig, pos, fixed]
+    freq = None if freq is None else np.asarray(freq, float)
+    keep = [off, t, y, sig, pos, fixed, freq]
     d = Desc(model, P, off.ctypes.data, t.ctypes.data, y.ctypes.data, sig.ctypes.data,
              None if pos is None else pos.ctypes.data,
-             None if fixed is None else fixed.ctypes.data, None, 3e8, 1e-6, 1e-14, 1e-20)
+             None if fixed is None else fixed.ctypes.data, None, 3e8, 1e-6, 1e-14, 1e-20,
+             None if freq is None else freq.ctypes.data)
     return d, keep
 
 
@@ -68,6 +80,11 @@ def make(model=2, P=2, t=None, y=None, sig=None, pos=None, off=None, fixed=None)
     (dict(model=3), 1),                              # joint model needs positions
     (dict(model=1), 1),                              # spin model takes one pulsar
     (dict(model=7), 1),                              # unknown model
+    (dict(model=4), 1),                              # DM model needs radio frequencies
+    (dict(model=4, freq=[1400, 820, 0.0, 430, 2300]), 1),     # frequency must be > 0
+    (dict(model=4, freq=[1400, 820, -5.0, 430, 2300]), 1),    # negative frequency
+    (dict(model=4, freq=[1400, np.nan, 820, 430, 2300]), 1),  # frequency must be finite
+    (dict(model=4, freq=[1400, np.inf, 820, 430, 2300]), 1),
 ])
 def test_dataset_validation(case, code):
     L = lib()
