@@ -225,11 +225,13 @@ int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mea
  *   W1 [w x d] | b1 [w] | W2 [w x w] | b2 [w] | W3 [w x w] | b3 [w] |
  *   W4 [w] | b4 [1]          (n = w d + 2 w^2 + 4 w + 1)
  * The caller owns the master block and the Adam moments (device FP32); the
- * handle owns the BF16 copies and activation workspaces. Inputs are mapped
- * from the box [in_lo, in_hi] to [-1, 1] and rounded to BF16 (8 significant
- * bits), so the box should be the range of the training inputs rather than a
- * much wider prior box; the network predicts the standardised target
- * (logL - out_mu) / out_sd.
+ * handle owns the BF16 copies and activation workspaces. Inputs pass
+ * through an affine input map x = T (theta - c), evaluated in FP64 inside
+ * the kernels, then are rounded to BF16 (8 significant bits): the map should
+ * bring the region the network must resolve to about [-1, 1] in every
+ * direction (the box of the training inputs, or for correlated parameters a
+ * whitening of their covariance); the network predicts the standardised
+ * target (logL - out_mu) / out_sd.
  * ------------------------------------------------------------------- */
 typedef struct argus_mlp* argus_mlp_t;
 
@@ -240,9 +242,19 @@ int argus_mlp_destroy(argus_mlp_t h);
 int argus_mlp_n_params(argus_mlp_t h, int64_t* n);
 
 /* Takes the weights from master (dev [n]) into the handle's BF16/FP32
- * copies and sets the input box (host [d_in]) and target standardisation. */
+ * copies and sets the input map to the box map x = 2 (theta - in_lo) /
+ * (in_hi - in_lo) - 1 (in_lo, in_hi host [d_in], finite, in_hi > in_lo) and
+ * the target standardisation (out_sd > 0). Synchronises the stream. */
 int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo,
                    const double* in_hi, double out_mu, double out_sd, void* stream);
+
+/* The same with a general affine input map x = T (theta - center): center
+ * host [d_in], T host [d_in * d_in] row-major (x_k = sum_j T[k d_in + j]
+ * (theta_j - center_j)), all finite; argus_mlp_load is the diagonal case
+ * T = diag(2 / (in_hi - in_lo)), center = (in_lo + in_hi) / 2. Synchronises
+ * the stream. */
+int argus_mlp_load_affine(argus_mlp_t h, const float* master, const double* center,
+                          const double* T, double out_mu, double out_sd, void* stream);
 
 /* logl_hat (dev [Q]) for parameter rows theta (dev [Q*d_in] FP64), any Q. */
 int argus_surrogate_eval(argus_mlp_t h, const double* theta, int64_t Q,

@@ -61,6 +61,7 @@ _lib.argus_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(_V)
 _lib.argus_mlp_destroy.argtypes = [_V]
 _lib.argus_mlp_n_params.argtypes = [_V, C.POINTER(C.c_int64)]
 _lib.argus_mlp_load.argtypes = [_V, _V, _V, _V, C.c_double, C.c_double, _V]
+_lib.argus_mlp_load_affine.argtypes = [_V, _V, _V, _V, C.c_double, C.c_double, _V]
 _lib.argus_surrogate_eval.argtypes = [_V, _V, C.c_int64, _V, _V]
 _lib.argus_mlp_grad.argtypes = [_V, _V, _V, C.c_int64, _V, _V, _V]
 _lib.argus_surrogate_train_step.argtypes = [_V, _V, _V, _V, _V, _V, C.c_int64, C.c_float,
@@ -301,6 +302,23 @@ class MLP:
                                    self.in_hi.ctypes.data, self.out_mu, self.out_sd,
                                    _stream(stream)))
 
+    def load_affine(self, master, center, T, out_mu, out_sd, stream=None):
+        """Set the weights and the affine input map x = T (theta - center)
+        (T [d_in, d_in]) with the target standardisation."""
+        import torch
+        self.master.copy_(torch.as_tensor(master, dtype=torch.float32))
+        self.m.zero_()
+        self.v.zero_()
+        self.step = 0
+        self.in_center = np.ascontiguousarray(center, np.float64)
+        self.in_T = np.ascontiguousarray(T, np.float64)
+        if self.in_center.shape != (self.d_in,) or self.in_T.shape != (self.d_in, self.d_in):
+            raise ArgusError("center must be [d_in] and T [d_in, d_in]")
+        self.out_mu, self.out_sd = float(out_mu), float(out_sd)
+        _check(_lib.argus_mlp_load_affine(self._h, self.master.data_ptr(),
+                                          self.in_center.ctypes.data, self.in_T.ctypes.data,
+                                          self.out_mu, self.out_sd, _stream(stream)))
+
     def eval(self, theta, out=None, stream=None):
         import torch
         theta = theta.contiguous()
@@ -412,7 +430,9 @@ class DelayedAcceptance:
     def draws(self):
         import torch
         eps = torch.randn(self.theta.shape, dtype=torch.float64, device=self.theta.device,
-                          generator=self.gen) * self.scale
+                          generator=self.gen)
+        # per-parameter scales [d], or a matrix L [d, d]: proposal covariance L L^T
+        eps = eps @ self.scale.T if self.scale.dim() == 2 else eps * self.scale
         u = torch.rand((2, self.Q), dtype=torch.float64, device=self.theta.device,
                        generator=self.gen)
         return eps, torch.log(u[0]), torch.log(u[1])
@@ -442,6 +462,92 @@ class DelayedAcceptance:
         da_stage2(self.idx, self.count, cap, ll_prop, lh_prop, logu2, prop, self.theta, self.ll,
                   self.lh, self.acc)
         return n
+
+
+def pilot_posterior(ds, lo, hi, n_chains=4096, n_prior=65536, rounds=8, steps=40, keep=4,
+                    seed=0):
+    """Posterior draws without knowing the answer, by exact-likelihood
+    Metropolis on the batched filter: n_prior draws uniform in the prior box
+    [lo, hi] are evaluated in one batched call and the n_chains best start
+    the chains; each round of `steps` random-walk Metropolis steps proposes
+    from the Gaussian with covariance 2.38^2 / D times the ensemble's current
+    covariance (adaptive Metropolis, Haario, Saksman & Tamminen 2001; Roberts,
+    Gelman & Gilks 1997), a dense covariance that follows correlated
+    parameters. Returns (theta [n_chains, D] final states, logl [n_chains],
+    history [keep * steps * n_chains, D] states of the last `keep` rounds,
+    their logL, the proposal factor L [D, D] (proposal L z, z standard
+    normal), info). Sequencing only: every likelihood is argus_loglike."""
+    import torch
+    dev = "cuda"
+    f64 = torch.float64
+    lo_t = torch.as_tensor(lo, dtype=f64, device=dev)
+    hi_t = torch.as_tensor(hi, dtype=f64, device=dev)
+    D = lo_t.numel()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    pr = lo_t + (hi_t - lo_t) * torch.rand((n_prior, D), dtype=f64, device=dev, generator=gen)
+    lp, _ = ds.loglike(pr, want_status=False)
+    best = torch.topk(torch.nan_to_num(lp, nan=-np.inf), n_chains).indices
+    cur, llc = pr[best].contiguous(), lp[best].clone()
+    prop = torch.empty_like(cur)
+    llp = torch.empty_like(llc)
+    hist, hll, acc_log = [], [], []
+    for r in range(rounds):
+        C = torch.cov(cur.T) + torch.diag((hi_t - lo_t) ** 2 * 1e-14)
+        L = torch.linalg.cholesky(C) * (2.38 / np.sqrt(D))
+        n_acc = 0
+        for _ in range(steps):
+            z = torch.randn((n_chains, D), dtype=f64, device=dev, generator=gen)
+            torch.addmm(cur, z, L.T, out=prop)
+            ds.loglike(prop, out=llp, want_status=False)
+            lu = torch.log(torch.rand(n_chains, dtype=f64, device=dev, generator=gen))
+            ok = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu < llp - llc)
+            cur = torch.where(ok[:, None], prop, cur)
+            llc = torch.where(ok, llp, llc)
+            n_acc += int(ok.sum().item())
+            if r >= rounds - keep:
+                hist.append(cur)
+                hll.append(llc)
+        acc_log.append(n_acc / (steps * n_chains))
+    C = torch.cov(cur.T) + torch.diag((hi_t - lo_t) ** 2 * 1e-14)
+    L = torch.linalg.cholesky(C) * (2.38 / np.sqrt(D))
+    info = {"prior_draws": n_prior, "chains": n_chains, "rounds": rounds,
+            "steps_per_round": steps, "acceptance_per_round": acc_log}
+    return cur, llc, torch.cat(hist), torch.cat(hll), L, info
+
+
+def fit_surrogate(theta, logl, center, T, init_weights, width=256, batch=512, epochs=12,
+                  lr=1e-3, floor=15.0, seed=0):
+    """Trains the surrogate on exact (theta, logL) pairs with the library's
+    training step: targets below max(logL) - floor are raised to that level
+    (the network then only has to resolve the region a chain can move in;
+    delayed acceptance stays exact whatever the surrogate says), standardised
+    by their mean and standard deviation; input map x = T (theta - center);
+    starting from init_weights (packed FP32); Adam with cosine-decayed
+    learning rate over shuffled batches. Returns (net, info)."""
+    import time as _time
+    import torch
+    n = theta.shape[0]
+    y = torch.clamp(logl, min=float(logl.max().item()) - floor)
+    mu, sd = float(y.mean().item()), float(y.std().item())
+    net = MLP(theta.shape[1], width, batch)
+    net.load_affine(init_weights, center, T, mu, sd)
+    rng = np.random.default_rng(seed)
+    steps = 0
+    torch.cuda.synchronize()
+    t0 = _time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(n), device=theta.device)
+        lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / epochs))
+        for b in range(0, n - batch + 1, batch):
+            sel = perm[b:b + batch]
+            net.train_step(theta[sel], y[sel], lr_ep)
+            steps += 1
+    torch.cuda.synchronize()
+    info = {"samples": n, "epochs": epochs, "batch": batch, "steps": steps,
+            "seconds": _time.perf_counter() - t0, "floor": floor,
+            "final_loss": float(net.loss.item())}
+    return net, info
 
 
 class HMC:
@@ -537,7 +643,9 @@ def _make_loglike_fn():
     import torch
 
     class ArgusLogLike(torch.autograd.Function):
-        """logL(theta) with the adjoint-filter gradient as its backward."""
+        """logL(theta) with argus_loglike_grad's gradient as its backward
+        (the tangent sweep by default; the reverse-mode adjoint sweep with
+        ARGUS_GRAD=adjoint)."""
 
         @staticmethod
         def forward(ctx, theta, ds):

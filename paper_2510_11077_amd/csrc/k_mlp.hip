@@ -117,22 +117,29 @@ __global__ void __launch_bounds__(256) k_sum_parts(const float* part, int nsplit
   C[row * ldc + col] = acc;
 }
 
-// Inputs mapped from the prior box to [-1, 1], rounded to BF16, padded with
-// zero columns to kKin; optional transposed copy and standardised targets.
+// Inputs through the affine input map x = T (theta - c) (T row-major d x d;
+// the box map is T = diag(2 / (hi - lo)), c = (lo + hi) / 2), evaluated in
+// FP64 with the products summed in index order, rounded to FP32 and then to
+// BF16, padded with zero columns to kKin; optional transposed copy and
+// standardised targets.
 constexpr int kKin = 32;
 
-__global__ void k_prep(const double* theta, int64_t B, int d_in, const double* lo,
-                       const double* hi, __bf16* x0, __bf16* x0T, int ldT,
+__device__ __forceinline__ double map_input(const double* th_row, int d, int k, const double* c,
+                                            const double* T) {
+  double acc = 0.0;
+  for (int j = 0; j < d; ++j) acc = fma(T[k * d + j], th_row[j] - c[j], acc);
+  return acc;
+}
+
+__global__ void k_prep(const double* theta, int64_t B, int d_in, const double* c,
+                       const double* T, __bf16* x0, __bf16* x0T, int ldT,
                        const double* target, double mu, double sd, float* t) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= B * kKin) return;
   const int64_t m = i / kKin;
   const int k = (int)(i - m * kKin);
   float v = 0.0f;
-  if (k < d_in) {
-    const double u = 2.0 * (theta[m * d_in + k] - lo[k]) / (hi[k] - lo[k]) - 1.0;
-    v = (float)u;
-  }
+  if (k < d_in) v = (float)map_input(theta + m * d_in, d_in, k, c, T);
   const __bf16 b = (__bf16)v;
   x0[m * kKin + k] = b;
   if (x0T) x0T[(int64_t)k * ldT + m] = b;
@@ -176,8 +183,8 @@ __global__ void k_out_eval(const __bf16* a3, int64_t Q, int width, const float* 
 constexpr int kFusedRows = 64;
 struct FusedArgs {
   const double* theta;   // [Q x d_in]
-  const double* lo;      // [d_in]
-  const double* hi;
+  const double* c;       // [d_in] input map centre
+  const double* T;       // [d_in x d_in] input map matrix
   const __bf16* W1;      // [W x kKin]
   const __bf16* W2F;     // [W x W] in fragment order (frag_index)
   const __bf16* W3F;
@@ -214,7 +221,7 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
       const int m = i / kKin, k = i - m * kKin;
       float v = 0.0f;
       if (i < R * kKin && k < d && row0 + m < f.Q)
-        v = (float)(2.0 * (f.theta[(row0 + m) * d + k] - f.lo[k]) / (f.hi[k] - f.lo[k]) - 1.0);
+        v = (float)map_input(f.theta + (row0 + m) * d, d, k, f.c, f.T);
       pf[j] = v;
     }
   };
@@ -574,7 +581,8 @@ struct argus_mlp {
   int d_in = 0, width = 0;
   int64_t n = 0, max_batch = 0;
   int device = 0, n_cu = 256;
-  argus::DevBuf p32, w1, w2, w3, w2T, w3T, w2F, w3F, lo, hi;
+  argus::DevBuf p32, w1, w2, w3, w2T, w3T, w2F, w3F;
+  argus::DevBuf ic, iT;  // input map x = T (theta - c): c [d_in], T [d_in x d_in]
   double mu = 0.0, sd = 1.0;
   bool loaded = false;
   // inference buffers (grown on demand)
@@ -672,7 +680,7 @@ int mlp_backprop(argus_mlp* h, const double* theta, const double* target, int64_
   const int w = h->width, d = h->d_in;
   const int64_t ldT = h->max_batch;
   hipLaunchKernelGGL(k_prep, dim3(blocks(B * kKin, 256)), dim3(256), 0, st, theta, B, d,
-                     h->lo.as<double>(), h->hi.as<double>(), h->x0.as<__bf16>(),
+                     h->ic.as<double>(), h->iT.as<double>(), h->x0.as<__bf16>(),
                      h->x0T.as<__bf16>(), (int)ldT, target, h->mu, h->sd, h->t.as<float>());
   HIPCHK(hipGetLastError());
   __bf16* A[3] = {h->a[0].as<__bf16>(), h->a[1].as<__bf16>(), h->a[2].as<__bf16>()};
@@ -763,7 +771,7 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
 
 int eval_seq(argus_mlp* h, const double* theta, int64_t Q, double* logl_hat, hipStream_t st) {
   if (h->width <= kFusedMaxWidth) {
-    FusedArgs f{theta, h->lo.as<double>(), h->hi.as<double>(), h->w1.as<__bf16>(),
+    FusedArgs f{theta, h->ic.as<double>(), h->iT.as<double>(), h->w1.as<__bf16>(),
                 h->w2F.as<__bf16>(), h->w3F.as<__bf16>(), h->p32.as<float>(), logl_hat, Q,
                 h->d_in, h->mu, h->sd};
     const unsigned grid =
@@ -779,7 +787,7 @@ int eval_seq(argus_mlp* h, const double* theta, int64_t Q, double* logl_hat, hip
     return ARGUS_OK;
   }
   hipLaunchKernelGGL(k_prep, dim3(blocks(Q * kKin, 256)), dim3(256), 0, st, theta, Q, h->d_in,
-                     h->lo.as<double>(), h->hi.as<double>(), h->e_x0.as<__bf16>(), nullptr, 0,
+                     h->ic.as<double>(), h->iT.as<double>(), h->e_x0.as<__bf16>(), nullptr, 0,
                      nullptr, 0.0, 1.0, nullptr);
   HIPCHK(hipGetLastError());
   __bf16* A = h->e_a.as<__bf16>();
@@ -823,7 +831,7 @@ int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t
   if ((rc = h->p32.alloc(h->n * 4)) || (rc = h->w1.alloc(w * kKin * 2)) ||
       (rc = h->w2.alloc(w * w * 2)) || (rc = h->w3.alloc(w * w * 2)) ||
       (rc = h->w2T.alloc(w * w * 2)) || (rc = h->w3T.alloc(w * w * 2)) ||
-      (rc = h->lo.alloc(kKin * 8)) || (rc = h->hi.alloc(kKin * 8)) ||
+      (rc = h->ic.alloc(kKin * 8)) || (rc = h->iT.alloc(kKin * kKin * 8)) ||
       (rc = h->x0.alloc(B * kKin * 2)) || (rc = h->x0T.alloc(B * kKin * 2)) ||
       (rc = h->t.alloc(B * 4)) || (rc = h->dout.alloc(B * 4)) || (rc = h->sq.alloc(B * 4)) ||
       (rc = h->g.alloc(h->n * 4)) || (rc = h->wpart.alloc(kWgradSplits * w * w * 4)))
@@ -857,17 +865,21 @@ int argus_mlp_n_params(argus_mlp_t h, int64_t* n) {
   return ARGUS_OK;
 }
 
-int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo, const double* in_hi,
-                   double out_mu, double out_sd, void* stream) {
+int argus_mlp_load_affine(argus_mlp_t h, const float* master, const double* center,
+                          const double* T, double out_mu, double out_sd, void* stream) {
   int rc = check_mlp(h);
   if (rc) return rc;
-  if (!master || !in_lo || !in_hi) return fail(ARGUS_E_INVAL, "NULL argument");
-  if (!(out_sd > 0.0) || !std::isfinite(out_mu)) return fail(ARGUS_E_INVAL, "bad standardisation");
-  for (int k = 0; k < h->d_in; ++k)
-    if (!(in_hi[k] > in_lo[k])) return fail(ARGUS_E_INVAL, "input box must have hi > lo");
+  if (!master || !center || !T) return fail(ARGUS_E_INVAL, "NULL argument");
+  if (!(out_sd > 0.0) || !std::isfinite(out_sd) || !std::isfinite(out_mu))
+    return fail(ARGUS_E_INVAL, "bad standardisation");
+  const int d = h->d_in;
+  for (int k = 0; k < d; ++k)
+    if (!std::isfinite(center[k])) return fail(ARGUS_E_INVAL, "input map centre must be finite");
+  for (int k = 0; k < d * d; ++k)
+    if (!std::isfinite(T[k])) return fail(ARGUS_E_INVAL, "input map matrix must be finite");
   hipStream_t st = (hipStream_t)stream;
-  HIPCHK(hipMemcpyAsync(h->lo.p, in_lo, h->d_in * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(h->hi.p, in_hi, h->d_in * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->ic.p, center, d * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->iT.p, T, (size_t)d * d * 8, hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   h->mu = out_mu;
   h->sd = out_sd;
@@ -879,6 +891,22 @@ int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo, cons
     return rc;
   h->loaded = true;
   return ARGUS_OK;
+}
+
+int argus_mlp_load(argus_mlp_t h, const float* master, const double* in_lo, const double* in_hi,
+                   double out_mu, double out_sd, void* stream) {
+  int rc = check_mlp(h);
+  if (rc) return rc;
+  if (!master || !in_lo || !in_hi) return fail(ARGUS_E_INVAL, "NULL argument");
+  const int d = h->d_in;
+  std::vector<double> c(d), T((size_t)d * d, 0.0);
+  for (int k = 0; k < d; ++k) {
+    if (!(in_hi[k] > in_lo[k]) || !std::isfinite(in_hi[k] - in_lo[k]))
+      return fail(ARGUS_E_INVAL, "input box must be finite with hi > lo");
+    c[k] = 0.5 * (in_lo[k] + in_hi[k]);
+    T[(size_t)k * d + k] = 2.0 / (in_hi[k] - in_lo[k]);
+  }
+  return argus_mlp_load_affine(h, master, c.data(), T.data(), out_mu, out_sd, stream);
 }
 
 int argus_surrogate_eval(argus_mlp_t h, const double* theta, int64_t Q, double* logl_hat,

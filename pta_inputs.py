@@ -334,6 +334,23 @@ def theta_near_truth(d: PTAData, S: int, seed: int, scale=0.05) -> np.ndarray:
     return np.clip(tr + rng.uniform(-w, w, size=(S, tr.size)), lo, hi)
 
 
+def theta_from_ensemble(ens: np.ndarray, S: int, seed: int, lo, hi, widen=(1.0,)) -> np.ndarray:
+    """S parameter vectors from the Gaussian with the mean and covariance of
+    an ensemble of posterior draws `ens` [n, D] (a pilot sampler's chains),
+    in equal parts with the covariance scaled by each factor of `widen`
+    squared, clipped to the prior box [lo, hi]: training and starting points
+    where the posterior puts its mass."""
+    rng = np.random.default_rng(seed)
+    ens = np.asarray(ens, np.float64)
+    mu = ens.mean(0)
+    L = np.linalg.cholesky(np.cov(ens, rowvar=False) + 1e-30 * np.eye(ens.shape[1]))
+    parts = []
+    for i, w in enumerate(widen):
+        n = S // len(widen) + (1 if i < S % len(widen) else 0)
+        parts.append(mu + w * rng.standard_normal((n, mu.size)) @ L.T)
+    return np.clip(np.concatenate(parts), lo, hi)
+
+
 def mlp_weights(d_in: int, width: int, seed: int) -> np.ndarray:
     """Initial surrogate weights, packed as W1 [w, d], b1, W2 [w, w], b2,
     W3 [w, w], b3, W4 [w], b4: He-uniform weights U(-sqrt(6/fan_in), ...),

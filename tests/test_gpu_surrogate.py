@@ -47,7 +47,10 @@ def make(A, flat, lo, hi, mu=0.0, sd=1.0, max_batch=512):
     return net
 
 
-@pytest.mark.parametrize("Q", [1, 63, 1000])
+# 40,001 and 65,536 rows: more 64-row chunks than the launch has blocks (one
+# per CU), so each block walks several chunks (block-strided loop, next-chunk
+# register prefetch, LDS reuse across chunks) and the last chunk is ragged
+@pytest.mark.parametrize("Q", [1, 63, 1000, 40001, 65536])
 def test_forward_matches_oracle(A, Q):
     from oracle import mlp
     flat = rand_net(1)
@@ -65,8 +68,60 @@ def test_forward_matches_oracle(A, Q):
     assert np.median(err / scale) < 1e-3
 
 
-@pytest.mark.parametrize("width", [64, 192, 256])
-def test_forward_after_training_matches_oracle(A, width):
+def affine_map(seed):
+    """A whitening-like input map with strong off-diagonal terms."""
+    rng = np.random.default_rng(seed)
+    A_ = rng.normal(size=(D, D)) + 3.0 * np.eye(D)
+    center = rng.uniform(-1.0, 1.0, D)
+    return center, A_ / 8.0
+
+
+@pytest.mark.parametrize("Q", [333, 40001])
+def test_forward_affine_map_matches_oracle(A, Q):
+    """Inference through a general affine input map x = T (theta - c)."""
+    from oracle import mlp
+    flat = rand_net(21)
+    center, T = affine_map(22)
+    th = center + np.random.default_rng(23).normal(size=(Q, D))
+    mu, sd = -50.0, 3.0
+    net = A.MLP(D, W, 512)
+    net.load_affine(flat, center, T, mu, sd)
+    y = net.eval(dev(th)).cpu().numpy()
+    ref, cache = mlp.forward(flat, mlp.affine_inputs(th, center, T), D, W, emulate=True)
+    p = mlp.unpack(flat, D, W)
+    scale = np.abs(cache["a3"] * p["W4"]).sum(1) + abs(p["b4"][0])
+    err = np.abs((y - mu) / sd - ref)
+    assert (err <= 1e-2 * scale).all(), (err / scale).max()
+    assert np.median(err / scale) < 1e-3
+
+
+def test_gradient_affine_map_matches_oracle(A):
+    """The training path's input preparation through the same affine map."""
+    from oracle import mlp
+    flat = rand_net(24)
+    center, T = affine_map(25)
+    rng = np.random.default_rng(26)
+    B = 192
+    th = center + rng.normal(size=(B, D))
+    target = rng.normal(size=B)
+    net = A.MLP(D, W, 256)
+    net.load_affine(flat, center, T, 0.0, 1.0)
+    g, loss = net.grad(dev(th), dev(target))
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = mlp.loss_and_grad(flat, mlp.affine_inputs(th, center, T), target, D, W,
+                                   emulate=True)
+    assert abs(loss.item() - lref) <= 1e-2 * lref
+    o = 0
+    for name, shape in mlp.layout(D, W):
+        n = int(np.prod(shape))
+        a, b = g[o:o + n], gref[o:o + n]
+        assert (np.abs(a - b) <= 2e-2 * np.abs(b).max() + 1e-2 * np.abs(b)).all(), name
+        o += n
+
+
+@pytest.mark.parametrize("width,Q", [(64, 333), (192, 333), (256, 333), (64, 40001),
+                                     (256, 40001), (256, 65536)])
+def test_forward_after_training_matches_oracle(A, width, Q):
     """Inference after Adam steps reads the fragment-ordered weight copies
     that the step refreshes; the oracle runs on the step's FP32 master."""
     import torch
@@ -81,7 +136,7 @@ def test_forward_after_training_matches_oracle(A, width):
         net.train_step(dev(th), dev(target), 1e-2)
     torch.cuda.synchronize()
     flat = net.master.cpu().numpy().astype(np.float64)
-    q = rng.uniform(lo, hi, size=(333, D))
+    q = rng.uniform(lo, hi, size=(Q, D))
     y = net.eval(dev(q)).cpu().numpy()
     ref, cache = mlp.forward(flat, mlp.standardise_inputs(q, lo, hi), D, width, emulate=True)
     p = mlp.unpack(flat, D, width)
@@ -245,42 +300,69 @@ def test_da_chain_replays_exactly(A):
     assert np.allclose(sampler.ll.cpu().numpy(), llc, rtol=1e-12, atol=0)
 
 
-def test_trained_surrogate_saves_exact_evaluations(A):
-    """What the learned part gains: on the 10-parameter 10-pulsar workload,
-    a surrogate trained on exact-filter targets near the truth lets delayed
-    acceptance skip the exact evaluation of most proposals it rejects, while
-    making about as many accepted moves as plain exact-likelihood MH run on
-    the same proposals (the exactness of the DA chain itself is the replay
-    test above and the oracle's Gaussian test)."""
+@pytest.fixture(scope="module")
+def trained_cfg5(A):
+    """The 10-parameter 10-pulsar workload, its posterior found without the
+    truth (the best 4096 of 65,536 prior draws, then 8 rounds of 40 adaptive
+    Metropolis steps on the exact filter), and a surrogate trained on 262,144
+    exact-filter targets: pilot chain states and, for half of them, one
+    proposal step beyond (where delayed acceptance evaluates it), inputs
+    whitened by the pilot ensemble's covariance, targets more than 15 below
+    the best raised to that level, 50 epochs of batches of 512 (25,600
+    Adam steps: far fewer leave the posterior bulk resolved to only a few
+    tenths)."""
     import torch
     d = pi.make_config("cfg5")
     ds = A.Dataset(d)
     lo, hi = d.lo[d.free], d.hi[d.free]
-    th_tr = pi.theta_near_truth(d, 262144, 301, scale=0.01)
-    t_tr = dev(th_tr)
-    y_tr, _ = ds.loglike(t_tr)
-    y = y_tr.cpu().numpy()
-    net = A.MLP(10, 256, 2048)
-    net.load(pi.mlp_weights(10, 256, 2), th_tr.min(0), th_tr.max(0), float(y.mean()),
-             float(y.std()))
-    rng = np.random.default_rng(0)
-    epochs = 8
-    for ep in range(epochs):
-        perm = torch.as_tensor(rng.permutation(th_tr.shape[0]), device="cuda")
-        lr = 2e-3 * 0.5 * (1 + np.cos(np.pi * ep / epochs))
-        for b in range(0, th_tr.shape[0], 2048):
-            sel = perm[b:b + 2048]
-            net.train_step(t_tr[sel], y_tr[sel], lr)
-    # accuracy on held-out bulk points (the input box is the training
-    # inputs' range, so their BF16 inputs resolve the bulk)
-    t_ho = dev(pi.theta_near_truth(d, 4096, 402, scale=0.005))
-    err = (net.eval(t_ho) - ds.loglike(t_ho)[0]).abs().cpu().numpy()
-    print("held-out |dlogL|: median %.4f, within 0.1: %.4f" % (np.median(err), (err <= 0.1).mean()))
-    assert (err <= 0.1).mean() > 0.8  # 0.91 measured
+    cur, llc, hist, hll, Lp, info = A.pilot_posterior(ds, lo, hi, seed=1)
+    print("pilot acceptance per round:", np.round(info["acceptance_per_round"], 3))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(301)
+    n = 262144
+    th = hist[torch.randint(0, hist.shape[0], (n,), generator=gen, device="cuda")].clone()
+    th[n // 2:] += torch.randn((n - n // 2, th.shape[1]), dtype=torch.float64, device="cuda",
+                               generator=gen) @ Lp.T
+    th = torch.maximum(torch.minimum(th, dev(hi)), dev(lo)).contiguous()
+    y, _ = ds.loglike(th)
+    post = cur.cpu().numpy()
+    center = post.mean(0)
+    T = np.linalg.inv(np.linalg.cholesky(np.cov(post, rowvar=False))) / 5.0
+    net, tinfo = A.fit_surrogate(th, y, center, T, pi.mlp_weights(10, 256, 2), batch=512,
+                                 epochs=50, lr=1e-3, floor=15.0)
+    print("surrogate training:", tinfo)
+    return d, ds, net, cur, llc, Lp
+
+
+def exact_mh(ds, cur, llc, eps, lu, lo_t, hi_t):
+    """One random-walk Metropolis step of every chain on the exact filter."""
+    import torch
+    prop = (cur + eps).contiguous()
+    inb = ((prop >= lo_t) & (prop <= hi_t)).all(1)
+    llp, _ = ds.loglike(prop)
+    acc = inb & (lu < llp - llc)
+    return torch.where(acc[:, None], prop, cur), torch.where(acc, llp, llc), acc
+
+
+def test_trained_surrogate_saves_exact_evaluations(A, trained_cfg5):
+    """What the learned part gains: on the 10-parameter 10-pulsar workload,
+    a surrogate trained on exact-filter targets where the posterior lies lets
+    delayed acceptance skip the exact evaluation of most proposals it
+    rejects, while making about as many accepted moves as plain
+    exact-likelihood MH run on the same proposals (that the DA chain samples
+    the same posterior is test_da_and_exact_mh_agree_at_stationarity below;
+    its exactness decision by decision is the replay test above)."""
+    import torch
+    d, ds, net, post, llpost, Lp = trained_cfg5
+    lo, hi = d.lo[d.free], d.hi[d.free]
+    # accuracy on the pilot's final posterior states (not trained on)
+    err = (net.eval(post) - llpost).abs().cpu().numpy()
+    print("posterior states |dlogL|: median %.4f, within 0.1: %.4f"
+          % (np.median(err), (err <= 0.1).mean()))
+    assert (err <= 0.1).mean() > 0.8
     Q, T = 512, 40
-    th0 = dev(pi.theta_near_truth(d, Q, 401, scale=0.002))
-    step = (hi - lo) * 0.002
-    da = A.DelayedAcceptance(ds, net, th0, lo, hi, step, seed=5)
+    th0 = post[:Q].contiguous()
+    da = A.DelayedAcceptance(ds, net, th0, lo, hi, Lp, seed=5)
     cur = th0.clone()
     llc, _ = ds.loglike(cur)
     llc = llc.clone()
@@ -290,21 +372,82 @@ def test_trained_surrogate_saves_exact_evaluations(A):
     for _ in range(T):
         eps, lu1, lu2 = da.draws()
         da.step(eps, lu1, lu2)
-        prop = cur + eps
-        inb = ((prop >= lo_t) & (prop <= hi_t)).all(1)
-        llp, _ = ds.loglike(prop.contiguous())
+        cur, llc, acc = exact_mh(ds, cur, llc, eps, lu2, lo_t, hi_t)
         n_mh_exact += Q
-        acc = inb & (lu2 < llp - llc)
         mh_acc += acc.int()
-        cur = torch.where(acc[:, None], prop, cur)
-        llc = torch.where(acc, llp, llc)
     a_da, a_mh = int(da.acc.sum().item()), int(mh_acc.sum().item())
     print("exact evaluations DA %d vs MH %d; accepted moves DA %d vs MH %d"
           % (da.n_exact, n_mh_exact, a_da, a_mh))
     # accepted moves per exact evaluation: what the surrogate buys
-    assert da.n_exact < 0.8 * n_mh_exact
-    assert a_da / da.n_exact > a_mh / n_mh_exact
-    assert a_da > 0.5 * a_mh
+    assert da.n_exact < 0.5 * n_mh_exact
+    assert a_da / da.n_exact > 2.0 * a_mh / n_mh_exact
+    assert a_da > 0.7 * a_mh
     # an accurate surrogate: the exact filter confirms almost every move it passes
-    assert a_da / da.n_exact > 0.7  # 0.81 measured
+    assert a_da / da.n_exact > 0.7
     assert torch.isfinite(da.ll).all()
+    # the DA chain's own states (R17: posterior bulk): surrogate against exact
+    e_chain = (da.lh - da.ll).abs().cpu().numpy()
+    print("DA chain states |dlogL|: median %.4f, within 0.1: %.4f"
+          % (np.median(e_chain), (e_chain <= 0.1).mean()))
+    assert (e_chain <= 0.1).mean() > 0.8
+
+
+def test_da_and_exact_mh_agree_at_stationarity(A, trained_cfg5):
+    """Delayed acceptance samples the exact posterior (Christen & Fox 2005),
+    whatever the surrogate's error. 4096 chains start from the pilot's
+    posterior ensemble and take 400 exact random-walk Metropolis steps with
+    the pilot's proposal; from that common ensemble, 300 more steps
+    of delayed acceptance and, with independent random numbers, of exact
+    Metropolis give two ensembles of 4096 independent chains, each an i.i.d.
+    sample of the posterior. Per parameter: a two-sample Kolmogorov-Smirnov
+    test (p >= 1e-4 for each of the 10, a family-wise false-alarm rate of
+    1e-3) and the difference of the means within 5 standard errors. Power:
+    over the 300 steps the DA chains must move by at least one posterior
+    standard deviation (rms) in every parameter, so a sampler stuck near its
+    start does not pass by standing still. (Ensembles compared during the
+    transient from a start near the truth, as an earlier form of this test
+    did after 40 steps of a proposal 20 times narrower than the posterior,
+    differ because the two kernels relax at different rates, not because
+    their targets differ.)"""
+    import torch
+    from scipy.stats import ks_2samp
+    d, ds, net, post, llpost, Lp = trained_cfg5
+    lo, hi = d.lo[d.free], d.hi[d.free]
+    lo_t, hi_t = dev(lo), dev(hi)
+    Q, burn, T = 4096, 400, 300
+    Lt = Lp
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+
+    def mh_draws():
+        eps = torch.randn((Q, Lt.shape[0]), dtype=torch.float64, device="cuda",
+                          generator=gen) @ Lt.T
+        lu = torch.log(torch.rand(Q, dtype=torch.float64, device="cuda", generator=gen))
+        return eps, lu
+
+    cur = post[:Q].clone()
+    llc = ds.loglike(cur)[0].clone()
+    for _ in range(burn):
+        cur, llc, _ = exact_mh(ds, cur, llc, *mh_draws(), lo_t, hi_t)
+    e0 = cur.clone()
+    da = A.DelayedAcceptance(ds, net, e0, lo, hi, Lp, seed=12)
+    mh_acc = torch.zeros(Q, dtype=torch.int32, device="cuda")
+    for _ in range(T):
+        da.step()
+        cur, llc, acc = exact_mh(ds, cur, llc, *mh_draws(), lo_t, hi_t)
+        mh_acc += acc.int()
+    x_da, x_mh, x0 = da.theta.cpu().numpy(), cur.cpu().numpy(), e0.cpu().numpy()
+    assert np.isfinite(x_da).all() and torch.isfinite(da.ll).all()
+    sd = x_mh.std(0)
+    p = np.array([ks_2samp(x_da[:, j], x_mh[:, j]).pvalue for j in range(x_da.shape[1])])
+    z = (x_da.mean(0) - x_mh.mean(0)) / np.sqrt((x_da.var(0) + x_mh.var(0)) / Q)
+    move = np.sqrt(((x_da - x0) ** 2).mean(0)) / sd
+    print("KS p:", np.round(p, 4), "mean z:", np.round(z, 2))
+    print("DA rms move / sd:", np.round(move, 2), "accepted per chain DA %.1f MH %.1f"
+          % (da.acc.double().mean().item(), mh_acc.double().mean().item()))
+    pp = post.cpu().numpy()
+    print("pilot ensemble vs MH end, KS p:",
+          np.round([ks_2samp(pp[:, j], x_mh[:, j]).pvalue for j in range(x0.shape[1])], 4))
+    assert (p >= 1e-4).all(), p
+    assert (np.abs(z) <= 5.0).all(), z
+    assert (move >= 1.0).all(), move
