@@ -184,6 +184,7 @@ int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
   a.rec = ds->rec.as<TOARec>();
   a.chrom = ds->chrom.as<double>();
   a.off = ds->off.as<int64_t>();
+  a.maxdt = ds->maxdt.as<double>();
   a.theta = theta;
   a.col = ds->col.as<int32_t>();
   a.fixed = ds->fixed.as<double>();
@@ -191,6 +192,7 @@ int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
   a.items = (bal ? w->items_bal : w->items).as<int32_t>();
   a.bin_off = bal ? w->bin_off.as<int32_t>() : nullptr;
   a.counter = w->counter.as<int32_t>();
+  a.redo = w->redo.as<int32_t>();
   a.part = w->part.as<double>();
   a.pstat = w->pstat.as<int32_t>();
   a.S = w->S;
@@ -370,7 +372,8 @@ Workspace* get_workspace(argus_dataset* ds, int64_t S, int* rc) {
     w->n_bins = ds->n_cu;  // blocks
     if (bal.empty()) bal.assign(2, -1);  // keep the buffer non-empty
     if ((*rc = w->items_bal.upload(bal.data(), bal.size() * sizeof(int32_t))) ||
-        (*rc = w->bin_off.upload(boff.data(), boff.size() * sizeof(int32_t))))
+        (*rc = w->bin_off.upload(boff.data(), boff.size() * sizeof(int32_t))) ||
+        (*rc = w->redo.alloc((size_t)std::max(w->n_items, w->n_items_bal) * sizeof(int32_t))))
       return nullptr;
   }
   Workspace* raw = w.get();
@@ -470,9 +473,21 @@ int argus_dataset_create(const argus_dataset_desc* d, argus_dataset_t* out) {
     }
     if ((rc = ds->chrom.upload(ch.data(), ch.size() * sizeof(double)))) return rc;
   }
+  if (d->model != ARGUS_M3_JOINT_HD) {
+    std::vector<int32_t> po(ds->P);
+    std::iota(po.begin(), po.end(), 0);
+    std::stable_sort(po.begin(), po.end(),
+                     [&](int a, int b) { return ds->counts[a] > ds->counts[b]; });
+    if ((rc = ds->porder.upload(po.data(), po.size() * sizeof(int32_t)))) return rc;
+    std::vector<double> mdt(ds->P, 0.0);
+    for (int p = 0; p < ds->P; ++p)
+      for (int64_t k = d->toa_off[p]; k < d->toa_off[p + 1]; ++k)
+        mdt[p] = std::max(mdt[p], d->t[k] - (k > d->toa_off[p] ? d->t[k - 1] : 0.0));
+    if ((rc = ds->maxdt.upload(mdt.data(), mdt.size() * sizeof(double)))) return rc;
+  }
   StageArgs sa{ds->t.as<double>(), ds->y.as<double>(), ds->sig.as<double>(),
                dsrc.as<int64_t>(), dprev.as<int64_t>(), dpsr.as<int32_t>(),
-               ds->rec.as<TOARec>(), N, ds->mc.lam};
+               ds->rec.as<TOARec>(), N, ds->mc.lam, d->model == ARGUS_M3_JOINT_HD ? 1 : 0};
   HIPCHK(launch_stage(sa, 0));
   if (d->model == ARGUS_M3_JOINT_HD) {
     DevBuf dpos;

@@ -22,8 +22,11 @@ int fail(int code, const std::string& msg);
                            std::string(#x ": ") + hipGetErrorString(e_));  \
   } while (0)
 
-// Largest joint model: one workgroup thread per 4x4 covariance block,
-// P (P + 1) / 2 blocks <= 256 threads.
+// Largest joint model (one 16-wave workgroup per sample): the 4P-state
+// covariance, padded to 96 rows, fills the workgroup's LDS layout and the 48
+// rows of G each of the two elimination waves holds, and the transition of
+// the covariance gives each of its 384 lanes at most 3 of the 2 P (P + 1)
+// column segments, so P <= 22.
 constexpr int kJointMaxPsr = 22;
 
 // Owning device allocation.
@@ -56,6 +59,7 @@ struct TuneCfg {
 struct Workspace {
   int64_t S = 0;
   DevBuf part, pstat, logl_tmp, items, counter;
+  DevBuf redo;  // model 2: per-item flags of the fast form (max of both item counts)
   int n_items = 0;
   // the same items in one list per SIMD (4 per CU) with about equal TOA
   // steps per list
@@ -108,6 +112,8 @@ struct argus_dataset {
   argus::ModelConst mc{};
   argus::DevBuf rec, off, col, icol, fixed, hd, t, y, sig;  // icol: theta column -> canonical
   argus::DevBuf chrom;  // model 4: (nu_ref / nu)^2 per TOA
+  argus::DevBuf porder; // models 1, 2, 4: pulsars by TOA count, longest first
+  argus::DevBuf maxdt;  // models 1, 2, 4: largest TOA interval of each pulsar
   std::vector<int64_t> off_h, counts;
   std::map<int64_t, std::unique_ptr<argus::Workspace>> ws;
   hipStream_t cap_stream = nullptr;

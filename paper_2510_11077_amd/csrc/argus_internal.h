@@ -31,8 +31,8 @@ struct alignas(64) TOARec {
   double qcu;    // 1 - phc^2, common OU noise per unit variance
   double y;      // residual
   double s2;     // sigma_k^2
-  int32_t psr;   // pulsar of this TOA (model 3)
-  int32_t pad;
+  int32_t psr;   // merged stream (model 3): pulsar of this TOA; per-pulsar
+  int32_t pad;   // streams: these 8 bytes hold phc^2 instead (rec_phc2)
 };
 static_assert(sizeof(TOARec) == 64, "TOA record is one 64-B line");
 
@@ -222,7 +222,13 @@ struct FilterArgs {
   const double* theta;   // [S*D]
   const int32_t* col;    // [C] theta column of canonical param, or -1
   const double* fixed;   // [C]
-  const int32_t* items;  // [n_items*2] (sample tile, pulsar), longest first
+  const int32_t* items;  // [n_items*2] (sample tile, pulsar), longest first; or
+                         // NULL: item i is (i % tiles, porder[i / tiles])
+  const int32_t* porder; // [P] pulsars longest first (used when items is NULL)
+  int32_t tiles;         // ceil(S / 64) (used when items is NULL)
+  const double* maxdt;   // [P] largest TOA interval of each pulsar (model 2)
+  int32_t* redo;         // model 2: [n_items] 1 where the fast form left the
+                         // item to the general form, else 0
   // per-SIMD mode: items of SIMD j of block b are [bin_off[4b+j], bin_off[4b+j+1])
   const int32_t* bin_off;
   int32_t* counter;      // work-queue head (zero before launch)
@@ -258,6 +264,11 @@ struct PlainArgs {
   ModelConst mc;
 };
 
+// phc^2 of record k of a per-pulsar stream (the record's last 8 bytes)
+__device__ __forceinline__ double rec_phc2(RecPtr r, int64_t k) {
+  return ((ConstDPtr)r)[8 * k + 7];
+}
+
 struct StageArgs {
   const double* t;
   const double* y;
@@ -268,6 +279,8 @@ struct StageArgs {
   TOARec* rec;
   int64_t N;
   double lam;
+  int32_t merged;       // 1: merged stream (model 3) stores the pulsar index;
+                        // 0: per-pulsar streams store phc^2 in the last 8 bytes
 };
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t st);

@@ -140,6 +140,133 @@ __device__ __forceinline__ void step4(F4& f, const TOARec r, double em,
   acc_mul(f.L, S);
 }
 
+// ------------------------------------------------- model 2 step, fast form
+// The same recursion as step4 with fewer instructions for the common case:
+// no per-step failure classification and no per-step exponent extraction.
+// ln S is accumulated as a plain product of S over groups of kGroup steps,
+// its exponent extracted once per group (group_end), and every S compared
+// with 2^-120; a filter whose S ever falls below 2^-120 (including S <= 0), whose
+// product leaves the positive normal range, or whose result is not finite is
+// re-run by the caller with step4, whose per-step tests decide the status
+// word. The red-OU decay comes from expm1_fast, which needs |rate dt| <=
+// 1000 ln 2 (the caller checks every item against its pulsar's largest
+// interval). With S >= 2^-120 a group's partial products stay above
+// 2^-961, so no product passes through the subnormal range.
+constexpr int kGroup = 8;
+
+struct F4f {
+  double xr, xf, xa, xg;
+  double prr, prf, pff, pra, pfa, paa, prg, pfg, pag, pgg;
+  double quad, lm;
+  int le;
+};
+
+// Coefficients of H(u) = (expm1(u ln 2) - u ln 2) / u^2 on |u| <= 1/2,
+// highest degree first: its 10-term Chebyshev fit (expm1_coef.py beside this
+// file); the fit's own error contributes at most 3.7e-17 relative to expm1.
+__constant__ double kExpm1H[10] = {
+    0.000000000445410341058704017628, 0.00000000707097786650813855584,
+    0.000000101780672674494267932,    0.00000132154516332214343743,
+    0.0000152527338207958030237,      0.000154035304247765275866,
+    0.0013333558146423213121,         0.00961812910761866557058,
+    0.0555041086648215825683,         0.240226506959100761392};
+
+// the coefficients, ln 2 and the rounding constant 1.5 * 2^52, all in VGPRs
+// (an FP64 instruction reads at most one SGPR, and the step's other operands
+// are the record's SGPRs)
+struct Expm1H {
+  double c[10];
+  double ln2, magic;
+};
+__device__ __forceinline__ Expm1H expm1h_vgpr() {
+  Expm1H k;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    k.c[i] = kExpm1H[i];
+    asm volatile("" : "+v"(k.c[i]));
+  }
+  k.ln2 = in_vgpr(kLn2);
+  k.magic = in_vgpr(6755399441055744.0);
+  return k;
+}
+
+// expm1(-g dt) for gl = g / ln 2 with gl dt <= 1000 (and >= 0). Adding
+// 1.5 * 2^52 rounds -gl dt to the nearest integer k (ties to even), and the
+// low 32 bits of that sum are k itself; u = -gl dt - k is formed with one
+// rounding (exact product in the fma), |u| <= 1/2; expm1(u ln 2) =
+// u (ln 2 + u H(u)); expm1(-g dt) = 2^k expm1(u ln 2) + (2^k - 1).
+__device__ __forceinline__ double expm1_fast(double gl, double dt, const Expm1H& h) {
+  const double t = __builtin_fma(-gl, dt, h.magic);
+  const double kf = t - h.magic;
+  const double u = __builtin_fma(-gl, dt, -kf);
+  double q = __builtin_fma(h.c[0], u, h.c[1]);
+#pragma unroll
+  for (int i = 2; i < 10; ++i) q = __builtin_fma(q, u, h.c[i]);
+  const double p = u * __builtin_fma(q, u, h.ln2);
+  const int k = (int)(uint32_t)__builtin_bit_cast(uint64_t, t);
+  const double tk = __builtin_ldexp(1.0, k);
+  return __builtin_fma(tk, p, tk - 1.0);
+}
+
+__device__ __forceinline__ void step4_fast(F4f& f, double dt, double h2, double h3, double phc,
+                                           double qcu, double y, double s2, double phc2,
+                                           double em, double vr, double vr2, double vc,
+                                           double efac2, double equad2, double ss2, bool& ok) {
+  const double phr = 1.0 + em;
+  // vr (1 - phr^2) = -vr em (2 + em) = -em (vr em + 2 vr)
+  const double qr = -em * fma(vr, em, vr2);
+  const double qc = vc * qcu;
+  f.xr = fma(dt, f.xf, f.xr);
+  f.xa *= phr;
+  f.xg *= phc;
+  const double prf1 = fma(dt, f.pff, f.prf);
+  f.prr = fma(dt, f.prf + prf1, f.prr) + ss2 * h3;
+  f.prf = prf1 + ss2 * h2;
+  f.pff = f.pff + ss2 * dt;
+  f.pra = phr * fma(dt, f.pfa, f.pra);
+  f.pfa = phr * f.pfa;
+  f.paa = fma(phr * phr, f.paa, qr);
+  f.prg = phc * fma(dt, f.pfg, f.prg);
+  f.pfg = phc * f.pfg;
+  f.pag = (phr * phc) * f.pag;
+  f.pgg = fma(phc2, f.pgg, qc);
+  const double e = y - (f.xr + f.xa + f.xg);
+  const double ur = f.prr + f.pra + f.prg;
+  const double uf = f.prf + f.pfa + f.pfg;
+  const double ua = f.pra + f.paa + f.pag;
+  const double ug = f.prg + f.pag + f.pgg;
+  const double S = (ur + ua + ug) + fma(efac2, s2, equad2);
+  const double inv = rcp_nr(S);
+  const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
+  f.xr = fma(kr, e, f.xr);
+  f.xf = fma(kf, e, f.xf);
+  f.xa = fma(ka, e, f.xa);
+  f.xg = fma(kg, e, f.xg);
+  const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+  const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug);
+  JOSEPH(f.prr, kr, ur, dr, kr);
+  JOSEPH(f.prf, kr, uf, dr, kf);
+  JOSEPH(f.pff, kf, uf, df, kf);
+  JOSEPH(f.pra, kr, ua, dr, ka);
+  JOSEPH(f.pfa, kf, ua, df, ka);
+  JOSEPH(f.paa, ka, ua, da, ka);
+  JOSEPH(f.prg, kr, ug, dr, kg);
+  JOSEPH(f.pfg, kf, ug, df, kg);
+  JOSEPH(f.pag, ka, ug, da, kg);
+  JOSEPH(f.pgg, kg, ug, dg, kg);
+  f.quad = fma(e * e, inv, f.quad);
+  f.lm *= S;
+  ok = ok && S >= 0x1p-120;
+}
+
+// end of a group: the product must be a positive normal number; its
+// exponent moves to the integer accumulator
+__device__ __forceinline__ void group_end(F4f& f, bool& ok) {
+  ok = ok && __builtin_amdgcn_class(f.lm, 0x100);
+  f.le += __builtin_amdgcn_frexp_exp(f.lm);
+  f.lm = __builtin_amdgcn_frexp_mant(f.lm);
+}
+
 // ------------------------------------------------------------ model 4 step
 // The model 2 state plus m, the DM delay at the reference frequency (an OU
 // process), observed with the chromatic factor c = (nu_ref / nu)^2 of the
@@ -256,8 +383,12 @@ __device__ __forceinline__ double finish(double n, double quad,
   return st ? -INFINITY : ll;
 }
 
-// MAXT: launch bound (256, or 1024 for the one-block-per-CU layout)
-template <int MODEL, int MAXT>
+// MAXT: launch bound (256, or 1024 for the one-block-per-CU layout).
+// FAST (model 2): the fast loop only; an item it cannot decide is marked in
+// a.redo (one flag per item, written for every item) and left to the general
+// loop, which a second launch (FAST = false with a.redo set) runs on the
+// marked items only.
+template <int MODEL, int MAXT, bool FAST>
 __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wpb = blockDim.x / kWave;
@@ -280,9 +411,23 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
     q_hi = a.bin_off[4 * blockIdx.x + simd + 1];
   }
   int next = gwave;
+  // general form after the fast one (model 2): the marked items, found by
+  // reading the flags 64 at a time (one per lane) and walking the set bits
+  uint64_t rmask = 0;
+  int rbase = (gwave - nwaves) * kWave;
   for (;;) {
     int it;
-    if (a.dynamic == 1) {
+    if (MODEL == 2 && !FAST && a.redo) {
+      while (rmask == 0) {
+        rbase += nwaves * kWave;
+        if (rbase >= a.n_items) break;
+        const int idx = rbase + lane;
+        rmask = __builtin_amdgcn_ballot_w64(idx < a.n_items && a.redo[idx] != 0);
+      }
+      if (rmask == 0) break;
+      it = rbase + __builtin_ctzll(rmask);
+      rmask &= rmask - 1;
+    } else if (a.dynamic == 1) {
       int v = 0;
       if (lane == 0) v = atomicAdd(a.counter, 1);
       it = __builtin_amdgcn_readfirstlane(v);
@@ -303,8 +448,8 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       next += nwaves;
     }
     if (a.dynamic != 2 && it >= a.n_items) break;
-    const int tile = a.items[2 * it];
-    const int p = a.items[2 * it + 1];
+    const int tile = a.items ? a.items[2 * it] : it % a.tiles;
+    const int p = a.items ? a.items[2 * it + 1] : a.porder[it / a.tiles];
     const int64_t s_raw = (int64_t)tile * kWave + lane;
     const bool valid = s_raw < a.S;
     const int64_t s = valid ? s_raw : a.S - 1;
@@ -399,6 +544,68 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       const double vr = sr * sr / (2.0 * gr);
       const double vc = common_var(la, gc, a.mc);
       const double efac2 = efac * efac, equad2 = eq * eq;
+      const double ss2 = a.mc.ss2;
+      const RecPtr rec = (RecPtr)a.rec;
+      const double ss2v = in_vgpr(ss2);
+      // fast form unless a parameter is not finite or the red-OU exponent
+      // could leave expm1_fast's range on this pulsar
+      const double gl = gr * 1.44269504088896338700;
+      const bool fast_lane = !pnf && gl * a.maxdt[p] <= 1000.0;
+      bool done = false;
+      if (FAST && __builtin_amdgcn_ballot_w64(!fast_lane) == 0) {
+        const Expm1H hc = expm1h_vgpr();
+        const double vr2 = 2.0 * vr;
+        F4f g{};
+        g.prr = a.mc.s_r2;
+        g.pff = a.mc.s_f2;
+        g.paa = vr;
+        g.pgg = vc;
+        g.lm = 1.0;
+        bool ok = true;
+        // The record of step k + 1 is fetched during step k (as one 64-B
+        // scalar vector, its last double phc^2); the red decay of step k + 1
+        // is computed during step k from its dt, fetched alone during step
+        // k - 1 (indices clamped), so no value is used in the step that
+        // fetches it.
+        const RecVecPtr recv = (RecVecPtr)a.rec;
+        const ConstDPtr dts = (ConstDPtr)a.rec;  // dt: first double of each record
+        RecVec vn{};
+        double emn = 0.0, dt2 = 0.0;
+        if (kb < ke) {
+          vn = load_rec_v(recv, kb);
+          dt2 = dts[8 * (int64_t)(kb + 1 < ke ? kb + 1 : kb)];
+          emn = expm1_fast(gl, vn[0], hc);
+        }
+        auto one = [&](int k) {
+          const RecVec v = vn;
+          const double em = emn, dt1 = dt2;
+          rec_keep(v);
+          sgpr_ready(dt1);
+          vn = load_rec_v(recv, k + 1 < ke ? k + 1 : k);
+          dt2 = dts[8 * (int64_t)(k < ke - 2 ? k + 2 : ke - 1)];
+          emn = expm1_fast(gl, dt1, hc);
+          step4_fast(g, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], em, vr, vr2, vc, efac2,
+                     equad2, ss2v, ok);
+        };
+        int k = kb;
+        for (; k + kGroup <= ke; k += kGroup) {
+#pragma unroll 2
+          for (int j = 0; j < kGroup; ++j) one(k + j);
+          group_end(g, ok);
+        }
+        if (k < ke) {
+          for (; k < ke; ++k) one(k);
+          group_end(g, ok);
+        }
+        ll = -0.5 * ((double)(ke - kb) * kLn2Pi + (log(g.lm) + (double)g.le * kLn2) + g.quad);
+        st = 0;
+        const bool bad = !ok || !finite_d(ll);
+        done = __builtin_amdgcn_ballot_w64(bad) == 0;
+      }
+      if (FAST) {
+        if (lane == 0) a.redo[it] = done ? 0 : 1;
+        if (!done) continue;
+      } else {
       F4 f{};
       f.prr = a.mc.s_r2;
       f.pff = a.mc.s_f2;
@@ -406,9 +613,6 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       f.pgg = vc;
       f.L = {1.0, 0};
       f.st = pnf ? kPNF : 0;
-      const double ss2 = a.mc.ss2;
-      const RecPtr rec = (RecPtr)a.rec;
-      const double ss2v = in_vgpr(ss2);
       const Expm1Coef kc = expm1_coef_vgpr();
       // Two records in flight: step k waits for the record of step k + 1
       // (fetched during step k - 1), evaluates its red decay, and fetches
@@ -432,6 +636,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       }
       st = f.st;
       ll = finish((double)(ke - kb), f.quad, f.L, st);
+      }
     }
     if (valid) {
       a.part[(int64_t)p * a.S + s] = ll;
@@ -492,8 +697,13 @@ __global__ void k_stage(StageArgs a) {
   r.y = a.y[j];
   const double sg = a.sig[j];
   r.s2 = sg * sg;
-  r.psr = a.psr[k];
-  r.pad = 0;
+  if (a.merged) {
+    r.psr = a.psr[k];
+    r.pad = 0;
+  } else {
+    const double p2 = r.phc * r.phc;
+    __builtin_memcpy(&r.psr, &p2, sizeof p2);
+  }
   a.rec[k] = r;
 }
 
@@ -676,17 +886,33 @@ hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
                          hipStream_t st) {
   const bool big = block > 256;
   if (model == 4 && !big)
-    hipLaunchKernelGGL((k_filter<4, 256>), dim3(grid), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_filter<4, 256, false>), dim3(grid), dim3(block), 0, st, a);
   else if (model == 4)
-    hipLaunchKernelGGL((k_filter<4, 1024>), dim3(grid), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_filter<4, 1024, false>), dim3(grid), dim3(block), 0, st, a);
   else if (model == 1 && !big)
-    hipLaunchKernelGGL((k_filter<1, 256>), dim3(grid), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_filter<1, 256, false>), dim3(grid), dim3(block), 0, st, a);
   else if (model == 1)
-    hipLaunchKernelGGL((k_filter<1, 1024>), dim3(grid), dim3(block), 0, st, a);
-  else if (!big)
-    hipLaunchKernelGGL((k_filter<2, 256>), dim3(grid), dim3(block), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_filter<2, 1024>), dim3(grid), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((k_filter<1, 1024, false>), dim3(grid), dim3(block), 0, st, a);
+  else {
+    // model 2: the fast form over all items, then the general form over the
+    // items it marked (statically strided over a fixed grid of one-wave
+    // blocks; without marks every wave only reads the flags)
+    if (!big)
+      hipLaunchKernelGGL((k_filter<2, 256, true>), dim3(grid), dim3(block), 0, st, a);
+    else if (block <= 512)
+      hipLaunchKernelGGL((k_filter<2, 512, true>), dim3(grid), dim3(block), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_filter<2, 1024, true>), dim3(grid), dim3(block), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // (with per-SIMD lists, a.items and a.n_items are those lists, which is
+    // what the fast form's item indices refer to)
+    FilterArgs b = a;
+    b.dynamic = 0;
+    const int chunks = (b.n_items + kWave - 1) / kWave;
+    const int rg = chunks < 1 ? 1 : (chunks > 64 ? 64 : chunks);
+    hipLaunchKernelGGL((k_filter<2, 256, false>), dim3(rg), dim3(64), 0, st, b);
+  }
   return hipGetLastError();
 }
 

@@ -136,6 +136,30 @@ def test_status_flags(argus, orc):
     check(ll, st, ref, rst)
 
 
+def test_fast_form_hands_items_over_exactly(argus, orc):
+    """The batched 4-state filter runs a fast loop that leaves to the general
+    loop every (64-sample tile, pulsar) item in which some innovation
+    variance falls below 2^-120, a parameter is not finite, or the red-noise
+    rate times the pulsar's longest interval is too large for its expm1.
+    Here TOA errors of ~1e-25 s, no spin terms, and, in every third of the
+    first 128 samples, EQUAD, red and common amplitudes of 1e-40 keep S near
+    1e-50 in those samples, so some tiles mix handed-over and fast lanes and
+    others are fast throughout; a few samples carry huge rates. Every sample
+    matches the oracle."""
+    d = pi.make_pta("t", n_psr=3, counts=[300, 70, 129], seed=41)
+    d.sigma = d.sigma * 1e-18
+    d.s_r = d.s_f = d.sigma_s = 0.0
+    th = pi.sample_theta(d, 200, 42)
+    tiny = (np.arange(200) % 3 == 0) & (np.arange(200) < 128)
+    for p in range(3):
+        th[tiny, 4 * p] = -40.0      # log10 sigma_red
+        th[tiny, 4 * p + 3] = -40.0  # log10 EQUAD
+    th[tiny, -2] = -40.0             # log10 A
+    th[150:153, 1] = 4.0             # log10 gamma_red of pulsar 0: rate 1e4 / s
+    err = run(argus, orc, d, th)
+    print("max rel err %.2e" % err)
+
+
 def test_empty_batch_is_a_noop(argus):
     import torch
     d = pi.make_pta("t", n_psr=2, counts=[5, 6], seed=35)
