@@ -104,6 +104,24 @@ int argus_dataset_n_params(argus_dataset_t ds, int32_t* D);
 int argus_loglike(argus_dataset_t ds, const double* theta, int64_t S,
                   double* logl, int32_t* status, void* stream);
 
+/* argus_loglike for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Models 1, 2 and 4 (model 3 -> ARGUS_E_UNSUPPORTED); same arguments and
+ * outputs as argus_loglike, computed by the same filter and reduction
+ * kernels in one fixed launch layout (no autotuning, no graph, nothing
+ * synchronised). It allocates nothing: the per-(pulsar, sample) terms,
+ * status words and per-(64-sample tile, pulsar) flags live in a static 8 MiB
+ * device array of the library, one copy per device, held until the process
+ * ends, which limits S to round_up(8 P S, 256) + round_up(4 P S, 256) +
+ * 4 P ceil(S / 64) <= 8 MiB (47 pulsars: S <= 14,795; one pulsar:
+ * S <= 695,424); a larger S returns ARGUS_E_INVAL with the limit
+ * in argus_last_error(). Every call on a device shares that device's array:
+ * calls that overlap in time on one device (concurrent streams, threads)
+ * race and give wrong results. The first call on a device looks up the
+ * array's address (no allocation). */
+int argus_loglike_noalloc(argus_dataset_t ds, const double* theta, int64_t S,
+                          double* logl, int32_t* status, void* stream);
+
 /* Per-pulsar terms of logL (models 1, 2): terms dev [P*S], pulsar-major
  * (terms[p*S + s]); same kernel as argus_loglike, no graph. */
 int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S,

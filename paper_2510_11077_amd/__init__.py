@@ -46,7 +46,8 @@ _lib.argus_last_error.restype = C.c_char_p
 _lib.argus_dataset_create.argtypes = [C.POINTER(_Desc), C.POINTER(_V)]
 _lib.argus_dataset_destroy.argtypes = [_V]
 _lib.argus_dataset_n_params.argtypes = [_V, C.POINTER(C.c_int32)]
-for _n in ("argus_loglike", "argus_loglike_terms", "argus_loglike_plain"):
+for _n in ("argus_loglike", "argus_loglike_terms", "argus_loglike_plain",
+           "argus_loglike_noalloc"):
     getattr(_lib, _n).argtypes = [_V, _V, C.c_int64, _V, _V, _V]
 _lib.argus_loglike_grad.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V]
 _lib.argus_smooth.argtypes = [_V, _V, C.c_int64, _V, _V, _V, _V, _V]
@@ -163,6 +164,20 @@ class Dataset:
         out, status = self._outs(theta, out, status, want_status)
         _check(_lib.argus_loglike(self._h, tp, theta.shape[0], _dev_ptr(out, torch.float64, "out"),
                                   _dev_ptr(status, torch.int32, "status"), _stream(stream)))
+        return out, status
+
+    def loglike_noalloc(self, theta, out=None, status=None, want_status=True, stream=None):
+        """argus_loglike_noalloc: the same outputs as loglike, from a call that
+        allocates no device memory (models 1, 2, 4; S limited by the library's
+        static scratch). Callers must supply out/status to allocate nothing
+        on this side either."""
+        import torch
+        tp = self._theta(theta)
+        out, status = self._outs(theta, out, status, want_status)
+        _check(_lib.argus_loglike_noalloc(self._h, tp, theta.shape[0],
+                                          _dev_ptr(out, torch.float64, "out"),
+                                          _dev_ptr(status, torch.int32, "status"),
+                                          _stream(stream)))
         return out, status
 
     def loglike_terms(self, theta, stream=None):

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libargus.so")
-SOURCES = ["argus_api.cpp", "k_filter.hip", "k_scan.hip", "k_joint.hip", "k_adjoint.hip",
+SOURCES = ["argus_api.cpp", "argus_noalloc.cpp", "k_filter.hip", "k_scan.hip", "k_joint.hip", "k_adjoint.hip",
            "k_hmc.hip", "k_nuts.hip", "k_mlp.hip", "k_probe.hip"]
 ARCH = os.environ.get("ARGUS_ARCH", "gfx950")
 FLAGS = [
