@@ -87,10 +87,17 @@ typedef struct {
                                model 4 only, else NULL */
 } argus_dataset_desc;
 
-/* Copies the data to the device, orders the joint stream by (t, pulsar),
- * and precomputes per-TOA intervals, the common-process decay and (model 4)
- * the chromatic factors. C = 2 (model 1), 4P + 2 (models 2, 3) or 6P + 2
- * (model 4). Synchronises. Model 4 has the likelihood, its per-pulsar
+/* Builds the state-space model of a dataset (paper: Functionality,
+ * "State-space model construction": the noise processes of every pulsar,
+ * and for model 3 their Hellings-Downs coupling, compiled into one model;
+ * the TOA data enter as in Functionality, "Standardized Data Input", here
+ * as plain arrays): copies the data to the device, orders the joint stream
+ * by (t, pulsar), and precomputes per-TOA intervals, the common-process
+ * decay and (model 4) the chromatic factors. Validation failures (non-ascending or negative times, non-finite
+ * or non-positive errors, bad offsets, a missing position or frequency
+ * array) return ARGUS_E_INVAL before any device work; *out is NULL then.
+ * C = 2 (model 1), 4P + 2 (models 2, 3) or 6P + 2 (model 4) canonical
+ * parameters. Synchronises. Model 4 has the likelihood, its per-pulsar
  * terms, the gradient (tangent sweep) and the samplers; the plain baseline
  * and the smoother return ARGUS_E_UNSUPPORTED for it. */
 int argus_dataset_create(const argus_dataset_desc* desc, argus_dataset_t* out);
@@ -98,9 +105,13 @@ int argus_dataset_destroy(argus_dataset_t ds);
 /* D = number of free parameters (columns of theta). */
 int argus_dataset_n_params(argus_dataset_t ds, int32_t* D);
 
-/* logL for S parameter rows. theta: dev [S*D] row-major FP64; logl: dev [S];
- * status: dev [S] or NULL. Batched persistent kernel replayed from a captured
- * hipGraph; the first call for a new S autotunes (synchronises). */
+/* logL for S parameter rows (paper: Functionality, "Kalman filter
+ * likelihood evaluation": the Kalman filter's prediction-error
+ * decomposition over the time-ordered TOAs, O(N)). theta: dev [S*D]
+ * row-major FP64; logl: dev [S]; status: dev [S] or NULL. Batched
+ * persistent kernel replayed from a captured hipGraph; the first call for a
+ * new S autotunes (synchronises). S < 0, a NULL theta (D > 0) or a NULL
+ * logl return ARGUS_E_INVAL; S = 0 does nothing. */
 int argus_loglike(argus_dataset_t ds, const double* theta, int64_t S,
                   double* logl, int32_t* status, void* stream);
 
@@ -127,9 +138,12 @@ int argus_loglike_noalloc(argus_dataset_t ds, const double* theta, int64_t S,
 int argus_loglike_terms(argus_dataset_t ds, const double* theta, int64_t S,
                         double* terms, int32_t* status, void* stream);
 
-/* The plain per-sample GPU filter: one kernel launch per sample, one thread
- * per pulsar, per-TOA transcendentals and divisions, no precompute, no
- * persistence, no graph. Models 1, 2. Same outputs as argus_loglike. */
+/* The plain per-sample GPU filter (the same likelihood as argus_loglike,
+ * paper: Functionality, "Kalman filter likelihood evaluation", written the
+ * textbook way as a baseline): one kernel launch per sample, one thread per
+ * pulsar, dense 4 x 4 products, per-TOA transcendentals and divisions, no
+ * precompute, no persistence, no graph. Models 1, 2 (others:
+ * ARGUS_E_UNSUPPORTED). Same arguments and outputs as argus_loglike. */
 int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S,
                         double* logl, int32_t* status, void* stream);
 
@@ -342,7 +356,9 @@ int argus_mfma_rate(int32_t kind, int32_t waves_per_simd, double* tflops, double
 /* Human-readable launch configuration chosen for (ds, S), for reports. */
 int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len);
 
-/* Message for the last nonzero return on this thread. */
+/* Message for the last nonzero return on this thread (part of the error
+ * convention above, not of the method); valid until the thread's next call
+ * into the library. */
 const char* argus_last_error(void);
 
 #ifdef __cplusplus

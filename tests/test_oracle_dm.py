@@ -9,6 +9,7 @@ CPU only."""
 import dataclasses
 
 import numpy as np
+import pytest
 
 import pta_inputs as pi
 
@@ -31,14 +32,20 @@ def test_dm_filter_equals_dense_gaussian(oracle_mod):
     assert rel(ll, ref).max() < 1e-10
 
 
-def test_dm_gradient_equals_dense(oracle_mod):
+@pytest.mark.parametrize("seed", [4, 17])
+def test_dm_gradient_equals_dense(oracle_mod, seed):
+    """Per component, the criterion of the other models' gradient pin:
+    |g_j - g_dense,j| <= 1e-9 (|g_dense,j| + 1e-3 max|g_dense|), so a small
+    component such as a DM-rate derivative is held to the same relative
+    bar as the large ones (measured worst 2.2e-11)."""
     from oracle import dense
     d = small_dm(counts=(30, 20))
-    c = d.to_canon(pi.sample_theta(d, 2, 4))
+    c = d.to_canon(pi.sample_theta(d, 2, seed))
     g = oracle_mod.grad_cs(d, c)
     for s in range(2):
         ref = dense.grad(d, c[s])
-        assert np.max(np.abs(g[s] - ref)) <= 1e-7 * np.max(np.abs(ref))
+        scale = np.abs(ref).max()
+        assert (np.abs(g[s] - ref) / (np.abs(ref) + 1e-3 * scale)).max() < 1e-9
 
 
 def model2_view(d):

@@ -110,3 +110,43 @@ def test_accept_rule_edges():
     _, _, _, acc2, dh2 = hmc.transition(x0e, l0e, np.zeros_like(g0e) + 5.0, [0.1], [1.0], lo, hi,
                                         np.array([[3.0]]), np.array([-np.inf]), 2, f)
     assert not acc2[0] and np.isinf(dh2[0])
+
+
+def test_failed_density_mid_trajectory_rejects():
+    """A density that fails (is not finite) at an intermediate leapfrog
+    position rejects the transition even when the end point is fine, as a
+    filter failure part-way along a trajectory must: 1-D standard Gaussian,
+    a hole (l = -inf) around the second of four leapfrog positions. The
+    same draws without the hole are accepted (log u = -inf forces accept),
+    so the rejection is the hole's; a hole around the end point alone
+    rejects too."""
+    from oracle import hmc
+    base = hmc.gaussian_target([0.0], [[1.0]])
+    x0 = np.array([[-1.0]])
+    l0, g0 = base(x0)
+    z = np.array([[1.5]])
+    eps, L = 0.4, 4
+    # the positions the leapfrog visits from x0 with this momentum
+    xs, x, p, g = [], x0.copy(), z.copy(), g0.copy()
+    for _ in range(L):
+        p = p + 0.5 * eps * g
+        x = x + eps * p
+        xs.append(float(x[0, 0]))
+        _, g = base(x)
+        p = p + 0.5 * eps * g
+    assert len(set(np.round(xs, 6))) == L
+
+    def holed(center):
+        def f(xx):
+            l, gg = base(xx)
+            bad = np.abs(xx[:, 0] - center) < 1e-3
+            return np.where(bad, -np.inf, l), gg
+        return f
+
+    args = dict(eps=np.array([eps]), m_inv=np.array([1.0]), lo=np.array([-10.0]),
+                hi=np.array([10.0]), z=z, logu=np.array([-np.inf]), n_leapfrog=L)
+    t, l, g, acc, dh = hmc.transition(x0, l0, g0, logl_grad=base, **args)
+    assert acc[0] and t[0, 0] == xs[-1] and np.isfinite(dh[0])
+    for c in (xs[1], xs[-1]):
+        t, l, g, acc, dh = hmc.transition(x0, l0, g0, logl_grad=holed(c), **args)
+        assert not acc[0] and t[0, 0] == x0[0, 0] and l[0] == l0[0] and dh[0] == np.inf
