@@ -24,12 +24,23 @@ if ROOT not in sys.path:
 
 METRIC = "logL evals/s (47-psr batched Kalman, FP64); +grad; surrogate at |ΔlogL|≤0.1"
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
-# Algorithmic FP64 work of one filter step (FMA = 2 FLOP, expm1, reciprocal
-# and the log-accumulation each 1), counted from the structured step:
-# red-OU discretisation 6, common-OU noise 1, mean predict 4, covariance
-# predict 27, innovation/S 16, reciprocal 1, gain + mean update + S K 16,
-# Joseph rank-2 update of 10 entries 60, quadratic form 3, log-det 1.
+# Algorithmic FP64 work of one model-2 filter step as the survey's roofline
+# plan counts it (structured Joseph update of 10 entries x 8, predict 35,
+# discretisation 15, innovation 14, misc; a transcendental or division
+# counts 1): the figure `roofline` uses.
+FLOP_PER_STEP_M2_PLAN = 175
+# The same step counted from this implementation (FMA = 2 FLOP, expm1,
+# reciprocal and the log-accumulation each 1): red-OU discretisation 6,
+# common-OU noise 1, mean predict 4, covariance predict 27, innovation/S 16,
+# reciprocal 1, gain + mean update + S K 16, Joseph rank-2 update of 10
+# entries 60, quadratic form 3, log-det 1; reported beside it.
 FLOP_PER_STEP_M2 = 135
+# joint model and gradient as the roofline plan counts them: 37k FLOP per
+# TOA per sample for the sequential structured 80-state step; 700-900 FLOP
+# per TOA per sample for forward + recompute + reverse (midpoint 800)
+FLOP_PER_STEP_JOINT_PLAN = 37000
+FLOP_PER_STEP_GRAD_PLAN = 800
+MLP_FLOP_PER_QUERY = 2 * (10 * 256 + 2 * 256 * 256 + 256)  # 267,776
 FLOP_PER_STEP_M1 = 47
 # model 4 (state [r, f, a, g, m]), same accounting: both OU discretisations
 # 12, common-OU noise 1, mean predict 5, covariance predict 38, innovation
@@ -44,9 +55,13 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 
 def surrogate_leg(A, pi, dev, stream, log):
-    """10-parameter, 10-pulsar workload: exact targets from the batched
-    filter, training on the GPU, inference throughput, accuracy, and
-    delayed-acceptance screening against plain MH on the same proposals."""
+    """10-parameter, 10-pulsar workload: the posterior found without the
+    truth (pilot: best prior draws, then adaptive Metropolis on the exact
+    filter), 1M exact-filter targets from the pilot's chain states (half one
+    proposal step beyond), training on the GPU, inference throughput,
+    accuracy on held-out posterior states and on the delayed-acceptance
+    chain's own states, and screening against plain MH on the same
+    proposals."""
     import numpy as np
     import torch
 
@@ -54,52 +69,62 @@ def surrogate_leg(A, pi, dev, stream, log):
     ds5 = A.Dataset(d5)
     lo, hi = d5.lo[d5.free], d5.hi[d5.free]
     out = {}
-    # 1M exact-filter targets in the high-likelihood region (two box sizes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cur, llc, hist, hll, Lp, pinfo = A.pilot_posterior(ds5, lo, hi, seed=1)
+    torch.cuda.synchronize()
+    pinfo["seconds"] = time.perf_counter() - t0
+    pinfo["history_states"] = int(hist.shape[0])
+    out["pilot"] = pinfo
+    log("surrogate pilot: %.2f s, acceptance per round %s"
+        % (pinfo["seconds"], np.round(pinfo["acceptance_per_round"], 3)))
+    # 1M training inputs: pilot chain states, half of them one proposal step beyond
     n_train = 1 << 20
-    th = np.concatenate([pi.theta_near_truth(d5, n_train // 2, 301, scale=0.02),
-                         pi.theta_near_truth(d5, n_train // 2, 302, scale=0.005)])
-    t_th = torch.as_tensor(th, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(301)
+    th = hist[torch.randint(0, hist.shape[0], (n_train,), generator=gen, device=dev)].clone()
+    th[n_train // 2:] += torch.randn((n_train - n_train // 2, th.shape[1]), dtype=torch.float64,
+                                     device=dev, generator=gen) @ Lp.T
+    lo_t, hi_t = torch.as_tensor(lo, device=dev), torch.as_tensor(hi, device=dev)
+    th = torch.maximum(torch.minimum(th, hi_t), lo_t).contiguous()
     y = torch.empty(n_train, dtype=torch.float64, device=dev)
     chunk = 65536
-    ds5.loglike(t_th[:chunk], out=y[:chunk], want_status=False)
+    ds5.loglike(th[:chunk], out=y[:chunk], want_status=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for c in range(0, n_train, chunk):
-        ds5.loglike(t_th[c:c + chunk], out=y[c:c + chunk], want_status=False)
+        ds5.loglike(th[c:c + chunk], out=y[c:c + chunk], want_status=False)
     torch.cuda.synchronize()
-    out["target_generation_evals_per_s"] = n_train / (time.perf_counter() - t0)
-    yn = y.cpu().numpy()
-    mu, sd = float(yn.mean()), float(yn.std())
-    net = A.MLP(10, 256, 4096)
-    # input box = the range of the training inputs: the network sees them
-    # mapped to [-1, 1] and rounded to BF16, so the prior box (25x wider
-    # than this data) would quantise the bulk to a few steps per axis
-    net.load(pi.mlp_weights(10, 256, 1), th.min(0), th.max(0), mu, sd)
-    B, epochs = 4096, 12
-    rng = np.random.default_rng(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps = 0
-    for ep in range(epochs):
-        perm = torch.as_tensor(rng.permutation(n_train), device=dev)
-        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * ep / epochs))
-        for b in range(0, n_train, B):
-            sel = perm[b:b + B]
-            net.train_step(t_th[sel], y[sel], lr)
-            steps += 1
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    out["train"] = {"samples": n_train, "epochs": epochs, "batch": B, "steps": steps,
-                    "seconds": train_s, "samples_per_s": steps * B / train_s,
-                    "final_loss": float(net.loss.item())}
-    log("surrogate: trained %d steps in %.2f s, loss %.3g" % (steps, train_s, net.loss.item()))
-    # inference throughput on 65,536 queries
+    tg = time.perf_counter() - t0
+    tg_flop = float(d5.n_toa) * n_train * FLOP_PER_STEP_M2_PLAN
+    out["target_generation"] = {
+        "evals_per_s": n_train / tg, "seconds": tg,
+        "roofline": {"bound": "alu", "achieved": tg_flop / tg / 1e12, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tg_flop / tg / 1e12 / FP64_PEAK_TFLOPS,
+                     "flop_per_step": FLOP_PER_STEP_M2_PLAN,
+                     "note": "16 batched calls of 65,536 samples, host wall clock"}}
+    # training: whitened inputs (pilot ensemble), targets floored 15 below the best
+    post = cur.cpu().numpy()
+    center = post.mean(0)
+    T = np.linalg.inv(np.linalg.cholesky(np.cov(post, rowvar=False))) / 5.0
+    net, tinfo = A.fit_surrogate(th, y, center, T, pi.mlp_weights(10, 256, 1), batch=512,
+                                 epochs=12, lr=1e-3, floor=15.0)
+    tr_flop = 3.0 * MLP_FLOP_PER_QUERY * tinfo["samples"] * tinfo["epochs"]
+    tinfo["samples_per_s"] = tinfo["samples"] * tinfo["epochs"] / tinfo["seconds"]
+    tinfo["roofline"] = {"bound": "mfma", "achieved": tr_flop / tinfo["seconds"] / 1e12,
+                         "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tr_flop / tinfo["seconds"] / 1e12 / BF16_PEAK_TFLOPS,
+                         "flop_per_sample": 3 * MLP_FLOP_PER_QUERY,
+                         "seconds_at_peak": tr_flop / (BF16_PEAK_TFLOPS * 1e12)}
+    out["train"] = tinfo
+    log("surrogate: trained %d steps in %.2f s, loss %.3g"
+        % (tinfo["steps"], tinfo["seconds"], tinfo["final_loss"]))
+    # inference throughput on 65,536 posterior states
     Qn = 65536
-    tq = torch.as_tensor(pi.theta_near_truth(d5, Qn, 303, scale=0.005), dtype=torch.float64,
-                         device=dev)
+    tq = hist[torch.randint(0, hist.shape[0], (Qn,), generator=gen, device=dev)].contiguous()
     yq = torch.empty(Qn, dtype=torch.float64, device=dev)
     ms, _ = timed(lambda: net.eval(tq, out=yq), 50, 5, stream)
-    flop = 2.0 * (10 * 256 + 2 * 256 * 256 + 256) * Qn
+    flop = float(MLP_FLOP_PER_QUERY) * Qn
     out["eval_65536"] = {"ms_per_batch": ms, "evals_per_s": Qn / (ms * 1e-3),
                          "roofline": {"bound": "mfma", "achieved": flop / (ms * 1e-3) / 1e12,
                                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -110,60 +135,60 @@ def surrogate_leg(A, pi, dev, stream, log):
         out["eval_65536"]["roofline"]["frac_attainable"] = flop / (ms * 1e-3) / 1e12 / bf
     except A.ArgusError:
         pass
-    # accuracy on held-out posterior-bulk points
-    ye, _ = ds5.loglike(tq, want_status=False)
-    err = (yq - ye).abs().cpu().numpy()
-    out["accuracy_heldout_bulk"] = {"frac_abs_err_le_0.1": float((err <= 0.1).mean()),
-                                    "median_abs_err": float(np.median(err)),
-                                    "p90_abs_err": float(np.quantile(err, 0.9))}
+    # accuracy on the pilot's final posterior states (not trained on)
+    err = (net.eval(cur) - llc).abs().cpu().numpy()
+    out["accuracy_posterior_states"] = {
+        "states": int(cur.shape[0]), "frac_abs_err_le_0.1": float((err <= 0.1).mean()),
+        "median_abs_err": float(np.median(err)), "p90_abs_err": float(np.quantile(err, 0.9))}
     # delayed acceptance vs plain MH on the same proposals, 65,536 chains
-    Qc, T = 65536, 10
-    th0 = torch.as_tensor(pi.theta_near_truth(d5, Qc, 401, scale=0.002), dtype=torch.float64,
-                          device=dev)
-    step = (hi - lo) * 0.005
-    da = A.DelayedAcceptance(ds5, net, th0, lo, hi, step, seed=7)
-    draws = [da.draws() for _ in range(T)]
+    # started from pilot chain states, proposal 2.38^2 / D x pilot covariance
+    Qc, Tn = 65536, 10
+    th0 = hist[torch.randint(0, hist.shape[0], (Qc,), generator=gen, device=dev)].contiguous()
+    da = A.DelayedAcceptance(ds5, net, th0, lo, hi, Lp, seed=7)
+    draws = [da.draws() for _ in range(Tn)]
     for i in range(2):  # warm the fixed-size exact workspaces
         da.step(*draws[i])
     da.n_exact = da.n_prop = 0
     da.acc.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(2, T):
+    for i in range(2, Tn):
         da.step(*draws[i])
     torch.cuda.synchronize()
     da_s = time.perf_counter() - t0
     n_prop = da.n_prop
     da_moves = int(da.acc.sum().item())
+    e_chain = (da.lh - da.ll).abs().cpu().numpy()
+    out["accuracy_da_chain_states"] = {
+        "states": int(Qc), "frac_abs_err_le_0.1": float((e_chain <= 0.1).mean()),
+        "median_abs_err": float(np.median(e_chain)),
+        "p90_abs_err": float(np.quantile(e_chain, 0.9))}
     # plain MH: every proposal evaluated exactly, in fixed buffers (so the
     # batched call replays its graph, as a well-written sampler would)
-    cur = th0.clone()
-    llc, _ = ds5.loglike(cur, want_status=False)
-    llc = llc.clone()
-    lo_t = torch.as_tensor(lo, device=dev)
-    hi_t = torch.as_tensor(hi, device=dev)
-    prop = torch.empty_like(cur)
-    llp = torch.empty_like(llc)
-
+    cur2 = th0.clone()
+    llc2, _ = ds5.loglike(cur2, want_status=False)
+    llc2 = llc2.clone()
+    prop = torch.empty_like(cur2)
+    llp = torch.empty_like(llc2)
     mh_moves = torch.zeros((), dtype=torch.int64, device=dev)
 
     def mh_step(i):
         eps, _, lu2 = draws[i]
-        torch.add(cur, eps, out=prop)
+        torch.add(cur2, eps, out=prop)
         ds5.loglike(prop, out=llp, want_status=False)
-        acc = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu2 < llp - llc)
-        torch.where(acc[:, None], prop, cur, out=cur)
-        torch.where(acc, llp, llc, out=llc)
+        acc = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu2 < llp - llc2)
+        torch.where(acc[:, None], prop, cur2, out=cur2)
+        torch.where(acc, llp, llc2, out=llc2)
         mh_moves.add_(acc.sum())
 
     for i in range(2):  # warm-up: graph capture for the fixed buffers
         mh_step(i)
-    cur.copy_(th0)
-    llc.copy_(ds5.loglike(cur, want_status=False)[0])
+    cur2.copy_(th0)
+    llc2.copy_(ds5.loglike(cur2, want_status=False)[0])
     mh_moves.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(2, T):
+    for i in range(2, Tn):
         mh_step(i)
     torch.cuda.synchronize()
     mh_s = time.perf_counter() - t0
@@ -171,17 +196,19 @@ def surrogate_leg(A, pi, dev, stream, log):
         "screened_proposals_per_s": n_prop / da_s,
         "plain_mh_proposals_per_s": n_prop / mh_s,
         "exact_evals_fraction": da.n_exact / n_prop,
-        # second-stage acceptance: accepted moves per exact evaluation (1 for
-        # a surrogate equal to the exact logL); accepted moves of both chains
+        # accepted moves per exact evaluation (1 for a surrogate equal to
+        # the exact logL); accepted moves of both chains on the same proposals
         "stage2_acceptance": da_moves / max(da.n_exact, 1),
         "accepted_moves_da": da_moves,
         "accepted_moves_plain_mh": int(mh_moves.item()),
-        "iterations_timed": T - 2,
-    }
+        "iterations_timed": Tn - 2,
+        "start": "pilot chain states; proposal covariance 2.38^2 / D x pilot ensemble"}
     log("DA: %.4g proposals/s screened vs %.4g plain MH, exact fraction %.3f, stage-2 "
-        "acceptance %.3f, accepted moves %d vs %d"
+        "acceptance %.3f, accepted moves %d vs %d; accuracy: posterior states %.3f, DA chain "
+        "%.3f within 0.1"
         % (n_prop / da_s, n_prop / mh_s, da.n_exact / n_prop, da_moves / max(da.n_exact, 1),
-           da_moves, int(mh_moves.item())))
+           da_moves, int(mh_moves.item()), out["accuracy_posterior_states"]["frac_abs_err_le_0.1"],
+           out["accuracy_da_chain_states"]["frac_abs_err_le_0.1"]))
     return out
 
 
@@ -217,6 +244,84 @@ def measured_traffic():
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def cpu_legs(oracle, pi, d2, th2, nthreads, log):
+    """The oracle on the host for every workload (a baseline, not the
+    target): single-thread ns per filter step for each model, and
+    all-thread rates for the spin, joint, gradient and surrogate workloads,
+    each on a bounded sample that is stated."""
+    import dataclasses
+
+    import numpy as np
+
+    legs = {}
+
+    def wall(f):
+        t0 = time.perf_counter()
+        r = f()
+        return time.perf_counter() - t0, r
+
+    d1 = pi.make_config("cfg1")
+    th1 = pi.sample_theta(d1, 64, pi.THETA_SEED["cfg1"])
+    d3 = pi.make_config("cfg3")
+    th3 = pi.sample_theta(d3, 16, pi.THETA_SEED["cfg3"])
+    d4 = pi.make_config("cfg2dm")
+    th4 = pi.sample_theta(d4, 4, pi.THETA_SEED["cfg2dm"])
+    # joint model, single thread: the first 100 TOAs of each of its 20 pulsars
+    cnt = np.diff(d3.off)
+    keep = np.concatenate([np.arange(d3.off[p], d3.off[p] + min(100, cnt[p]))
+                           for p in range(d3.n_psr)])
+    off_s = np.concatenate([[0], np.cumsum(np.minimum(cnt, 100))]).astype(np.int64)
+    d3s = dataclasses.replace(d3, off=off_s, t=d3.t[keep], y=d3.y[keep], sigma=d3.sigma[keep])
+    single = {}
+    for name, dd, th, note in (
+            ("model1_spin", d1, th1, "64 samples x 500 TOAs"),
+            ("model2_psr4", d2, th2[:8], "8 samples x 37,269 TOAs"),
+            ("model3_joint_hd", d3s, th3[:1], "1 sample x 2,000 TOAs (first 100 of each "
+                                              "of the 20 pulsars), dense 80 x 80 update"),
+            ("model4_dm", d4, th4, "4 samples x 37,269 TOAs")):
+        t, _ = wall(lambda: oracle.loglike(dd, dd.to_canon(th), nthreads=1))
+        steps = int(dd.off[-1]) * th.shape[0]
+        single[name] = {"ns_per_step": t / steps * 1e9, "sample": note}
+    legs["single_thread"] = single
+    t, _ = wall(lambda: oracle.loglike(d1, d1.to_canon(th1), nthreads=nthreads))
+    legs["spin_1psr_500toa_64samples"] = {"evals_per_s": 64 / t, "threads": nthreads,
+                                          "sample": "all 64 samples"}
+    t, _ = wall(lambda: oracle.loglike(d3s, d3s.to_canon(th3), nthreads=nthreads))
+    legs["joint_hd_20psr_20000toa"] = {
+        "evals_per_s": 16 / t * int(d3s.off[-1]) / int(d3.off[-1]), "threads": nthreads,
+        "sample": "16 of the 256 samples on the first 100 TOAs of each pulsar (2,000 of the "
+                  "20,000 merged steps, dense 80 x 80 Joseph update), rate scaled by "
+                  "2,000 / 20,000 to the full stream (the cost per step does not depend on "
+                  "N); about 47 s per full-stream sample on one core"}
+    thg = pi.sample_theta(d2, 8, pi.THETA_SEED["cfg4"])
+    t, _ = wall(lambda: oracle.grad_cs(d2, d2.to_canon(thg), nthreads=nthreads))
+    legs["grad_47psr"] = {
+        "evals_per_s": 8 / t, "threads": nthreads,
+        "sample": "8 of the 1024 samples; complex-step oracle (one complex-valued filter run "
+                  "per canonical parameter, 190), not a reverse-mode CPU baseline"}
+    # surrogate: plain NumPy FP32 forward of the 10-256-256-256-1 SiLU network
+    w = pi.mlp_weights(10, 256, 1).astype(np.float32)
+    o, Wl = 0, []
+    for shp in ((256, 10), (256,), (256, 256), (256,), (256, 256), (256,), (256,), (1,)):
+        n = int(np.prod(shp))
+        Wl.append(w[o:o + n].reshape(shp))
+        o += n
+    x = np.random.default_rng(0).uniform(-1, 1, size=(65536, 10)).astype(np.float32)
+
+    def fwd():
+        a = x
+        for l in range(3):
+            z = a @ Wl[2 * l].T + Wl[2 * l + 1]
+            a = z / (np.float32(1) + np.exp(-z))
+        return a @ Wl[6] + Wl[7][0]
+
+    t, _ = wall(fwd)
+    legs["surrogate_eval_65536"] = {"evals_per_s": 65536 / t,
+                                    "sample": "NumPy FP32 forward of 65,536 queries"}
+    log("cpu legs: " + json.dumps(legs))
+    return legs
 
 
 def log(msg):
@@ -284,16 +389,30 @@ def main():
     ds = A.Dataset(d)
     out = torch.empty(S, dtype=torch.float64, device=dev)
     st = torch.empty(S, dtype=torch.int32, device=dev)
-    ds.loglike(th, out, st)  # autotune + graph capture (untimed)
+    # untimed set-up, timed apart: the first call autotunes the launch, the
+    # second (same pointers) captures the graph
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ds.loglike(th, out, st)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ds.loglike(th, out, st)
+    torch.cuda.synchronize()
+    capture_s = time.perf_counter() - t0
     log("cfg2 tune: " + ds.tune_info(S).replace("\n", " | "))
     step = lambda: ds.loglike(th, out, st)
     ms, wall = timed(step, args.steps, args.warmup, stream)
     value = S / (ms * 1e-3)
+    # the dominant kernel alone: HIP events around each of K back-to-back
+    # launches of the tuned filter kernel on the same stream
+    kms = ds.filter_kernel_ms(th, args.steps, stream)
     n_steps_total = int(d.n_toa) * S
-    flop = n_steps_total * FLOP_PER_STEP_M2
-    achieved = flop / (ms * 1e-3) / 1e12
-    log("cfg2: %.4f ms/step, %.4g evals/s, %.2f TFLOP/s (alg.)" % (ms, value, achieved))
+    flop = n_steps_total * FLOP_PER_STEP_M2_PLAN
+    achieved = flop / (kms * 1e-3) / 1e12
+    own = n_steps_total * FLOP_PER_STEP_M2 / (kms * 1e-3) / 1e12
+    log("cfg2: %.4f ms/step (filter kernel %.4f ms), %.4g evals/s, %.2f TFLOP/s (alg., "
+        "kernel time)" % (ms, kms, value, achieved))
     assert int((st != 0).sum().item()) == 0 and bool(torch.isfinite(out).all())
 
     res = {
@@ -323,9 +442,18 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": measured_traffic(),
-            "kernel": "k_filter<2> (+ k_reduce in the same timed step)",
+            "kernel": "k_filter<2> fast form (per-pulsar filter, one wave per 64-sample "
+                      "tile and pulsar)",
+            "kernel_ms": kms,
+            "kernel_ms_method": "argus_filter_kernel_ms: HIP events around each of %d "
+                                "back-to-back launches of the tuned kernel on the bench stream"
+                                % args.steps,
+            "flop_per_step": FLOP_PER_STEP_M2_PLAN,
             "flop_per_launch": flop,
+            "frac_own_count": {"flop_per_step": FLOP_PER_STEP_M2, "frac": own / FP64_PEAK_TFLOPS},
+            "frac_step_time": flop / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
         },
+        "setup_s": {"autotune": tune_s, "graph_capture": capture_s},
     }
     # the published peaks assume the maximum engine clock: the rates this
     # device sustains with every CU busy (argus_fp64_rate, argus_mfma_rate),
@@ -384,8 +512,11 @@ def main():
         ms1, _ = timed(lambda: ds1.loglike(t1, o1, s1), 50, 5, stream)
         tune1 = ds1.tune_info(64)
         chosen1 = [l for l in tune1.splitlines() if l.startswith("chosen")]
+        pms1, _ = timed(lambda: ds1.loglike_plain(t1, o1, s1), 3, 1, stream)
         extra["spin_1psr_500toa_64samples"] = {"us_per_call": ms1 * 1e3,
                                                 "evals_per_s": 64 / (ms1 * 1e-3),
+                                                "plain_gpu_evals_per_s": 64 / (pms1 * 1e-3),
+                                                "speedup_vs_plain_gpu": pms1 / ms1,
                                                 "layout": chosen1[0] if chosen1 else tune1}
         log("spin 1 pulsar: %.2f us/call; tune: %s" % (ms1 * 1e3, tune1.replace("\n", " | ")))
 
@@ -451,10 +582,17 @@ def main():
         ds3.loglike(t3, o3, s3)
         ms3, _ = timed(lambda: ds3.loglike(t3, o3, s3), 3, 1, stream)
         n3 = int(d3.n_toa) * S3
+        plan3 = n3 * FLOP_PER_STEP_JOINT_PLAN / (ms3 * 1e-3) / 1e12
         extra["joint_hd_20psr_20000toa_256samples"] = {
             "ms_per_call": ms3, "evals_per_s": S3 / (ms3 * 1e-3),
-            "tflops_algorithmic": n3 * FLOP_PER_TOA_JOINT / (ms3 * 1e-3) / 1e12,
-            "mfma_tflops_algorithmic": n3 * FLOP_PER_TOA_JOINT_MFMA / (ms3 * 1e-3) / 1e12}
+            "roofline": {"bound": "alu", "achieved": plan3, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": plan3 / FP64_PEAK_TFLOPS,
+                         "flop_per_step": FLOP_PER_STEP_JOINT_PLAN,
+                         "note": "one kernel per call: call time; work counted as the "
+                                 "sequential structured 80-state step"},
+            "tflops_blocked_method": n3 * FLOP_PER_TOA_JOINT / (ms3 * 1e-3) / 1e12,
+            "mfma_tflops_blocked_method": n3 * FLOP_PER_TOA_JOINT_MFMA / (ms3 * 1e-3) / 1e12,
+            "plain_gpu": "not available for the joint model"}
         log("joint HD: %.3f ms/call, %.4g evals/s" % (ms3, S3 / (ms3 * 1e-3)))
 
         # gradient (adjoint filter), 1024 samples of the 47-pulsar data
@@ -467,9 +605,16 @@ def main():
         try:
             ds.loglike_grad(t4, o4, g4, s4)
             ms4, _ = timed(lambda: ds.loglike_grad(t4, o4, g4, s4), 10, 2, stream)
-            extra["grad_47psr_1024samples"] = {"ms_per_call": ms4,
-                                               "evals_per_s": S4 / (ms4 * 1e-3),
-                                               "sweep": "tangent (forward-mode), tuned split"}
+            plan4 = int(d.n_toa) * S4 * FLOP_PER_STEP_GRAD_PLAN / (ms4 * 1e-3) / 1e12
+            extra["grad_47psr_1024samples"] = {
+                "ms_per_call": ms4, "evals_per_s": S4 / (ms4 * 1e-3),
+                "sweep": "tangent (forward-mode), tuned split",
+                "roofline": {"bound": "alu", "achieved": plan4, "peak": FP64_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": plan4 / FP64_PEAK_TFLOPS,
+                             "flop_per_step": FLOP_PER_STEP_GRAD_PLAN,
+                             "note": "call time (tangent kernel + reduction); work counted "
+                                     "as forward + recompute + reverse"},
+                "plain_gpu_loglike_evals_per_s": plain_rate}
             log("grad: %.3f ms/call, %.4g evals/s" % (ms4, S4 / (ms4 * 1e-3)))
             log("grad tune: " + ds.tune_info(S4).replace("\n", " | "))
         except A.ArgusError as e:
@@ -566,8 +711,9 @@ def main():
     if not args.no_cpu:
         import oracle
         oracle.build()
+        host = oracle.host_cpus()
+        nthreads = host["usable"]
         n = 1024
-        nthreads = oracle.default_threads()
         c = d.to_canon(th_np[:n])
         t0 = time.perf_counter()
         ref, rst = oracle.loglike(d, c, nthreads=nthreads)
@@ -580,11 +726,14 @@ def main():
             "cores": nthreads,
             "kind": "oracle",
             "sample": "first %d of the %d parameter samples, all 47 pulsars (dense Joseph-form "
-                      "C++ filter, -O2, one std::thread per core)" % (n, S),
+                      "C++ filter, -O2, one std::thread per usable CPU: %d of nproc %d, "
+                      "%s)" % (n, S, nthreads, host["nproc"], host["model"]),
+            "host": host,
         }
         res["parity_on_cpu_sample"] = {"max_rel_err": float(err.max()), "tol": 1e-9}
         log("cpu oracle: %.4g evals/s on %d threads (max rel err vs GPU %.2e)"
             % (n / wall, nthreads, err.max()))
+        res["cpu_baseline"]["legs"] = cpu_legs(oracle, pi, d, th_np, nthreads, log)
     print(json.dumps(res), flush=True)
 
 

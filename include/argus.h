@@ -353,6 +353,17 @@ int argus_fp64_rate(int32_t waves_per_simd, double* tflops, double* clock_mhz, v
 int argus_mfma_rate(int32_t kind, int32_t waves_per_simd, double* tflops, double* clock_mhz,
                     void* stream);
 
+/* Device diagnostic for roofline reports (not part of the method): the
+ * average duration in ms of the per-pulsar filter kernel alone (models 1, 2,
+ * 4; for model 2 its fast form without the general pass over flagged items,
+ * and without the reduction over pulsars), launched reps times back to back
+ * on `stream` in the layout argus_loglike tuned for this S, between two HIP
+ * events. Needs a previous argus_loglike call with this S (else
+ * ARGUS_E_INVAL); writes only the handle's workspace; synchronises the
+ * stream. Model 3 -> ARGUS_E_UNSUPPORTED. */
+int argus_filter_kernel_ms(argus_dataset_t ds, const double* theta, int64_t S, int32_t reps,
+                           double* ms, void* stream);
+
 /* Human-readable launch configuration chosen for (ds, S), for reports. */
 int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len);
 

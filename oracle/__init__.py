@@ -100,8 +100,40 @@ def _as_ds(d) -> Dataset:
     return d if isinstance(d, Dataset) else Dataset(d)
 
 
+def host_cpus() -> dict:
+    """The host's CPUs as this process sees them: nproc (os.cpu_count), the
+    CPUs it may run on (affinity), the cgroup CPU quota if one is set, the
+    CPU model name, and 'usable' = the smaller of affinity and quota."""
+    nproc = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = nproc
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, period = fh.read().split()[:2]
+        if q != "max":
+            quota = int(q) / int(period)
+    except (OSError, ValueError):
+        pass
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = aff if quota is None else min(aff, max(1, int(quota)))
+    return {"nproc": nproc, "affinity": aff, "cgroup_quota": quota, "model": model,
+            "usable": max(1, usable)}
+
+
 def default_threads() -> int:
-    return max(1, min(os.cpu_count() or 1, 16))
+    """One thread per CPU this process can use (affinity and cgroup quota)."""
+    return host_cpus()["usable"]
 
 
 def loglike(d, canon, nthreads=None, per_psr=False):

@@ -55,6 +55,7 @@ _lib.argus_hmc_step.argtypes = [_V, C.c_int64, C.c_int32, _V, _V, _V, _V, _V, _V
                                 _V, _V, _V]
 _lib.argus_nuts_step.argtypes = [_V, C.c_int64, C.c_int32] + [_V] * 16
 _lib.argus_tune_info.argtypes = [_V, C.c_int64, C.c_char_p, C.c_int32]
+_lib.argus_filter_kernel_ms.argtypes = [_V, _V, C.c_int64, C.c_int32, C.POINTER(C.c_double), _V]
 _lib.argus_fp64_rate.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), _V]
 _lib.argus_mfma_rate.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), _V]
@@ -266,6 +267,15 @@ class Dataset:
             _dev_ptr(grad, f64, "grad"), _dev_ptr(depth, i32, "depth"),
             _dev_ptr(n_leapfrog, i32, "n_leapfrog"), _dev_ptr(divergent, i32, "divergent"),
             _dev_ptr(accept_stat, f64, "accept_stat"), _stream(stream)))
+
+    def filter_kernel_ms(self, theta, reps, stream=None) -> float:
+        """Average duration (ms) of the tuned filter kernel alone over reps
+        back-to-back launches (diagnostic; after a loglike call with this S)."""
+        import torch
+        ms = C.c_double()
+        _check(_lib.argus_filter_kernel_ms(self._h, self._theta(theta), theta.shape[0], int(reps),
+                                           C.byref(ms), _stream(stream)))
+        return ms.value
 
     def tune_info(self, S: int) -> str:
         buf = C.create_string_buffer(4096)
@@ -507,10 +517,15 @@ def pilot_posterior(ds, lo, hi, n_chains=4096, n_prior=65536, rounds=8, steps=40
     prop = torch.empty_like(cur)
     llp = torch.empty_like(llc)
     hist, hll, acc_log = [], [], []
+    jitter = np.diag((np.asarray(hi, np.float64) - np.asarray(lo, np.float64)) ** 2 * 1e-14)
+
+    def proposal_factor(x):  # the D x D covariance work on the host
+        C = np.cov(x.cpu().numpy(), rowvar=False) + jitter
+        return torch.as_tensor(np.linalg.cholesky(C) * (2.38 / np.sqrt(D)), device=dev)
+
     for r in range(rounds):
-        C = torch.cov(cur.T) + torch.diag((hi_t - lo_t) ** 2 * 1e-14)
-        L = torch.linalg.cholesky(C) * (2.38 / np.sqrt(D))
-        n_acc = 0
+        L = proposal_factor(cur)
+        n_acc = torch.zeros((), dtype=torch.int64, device=dev)
         for _ in range(steps):
             z = torch.randn((n_chains, D), dtype=f64, device=dev, generator=gen)
             torch.addmm(cur, z, L.T, out=prop)
@@ -519,13 +534,12 @@ def pilot_posterior(ds, lo, hi, n_chains=4096, n_prior=65536, rounds=8, steps=40
             ok = ((prop >= lo_t) & (prop <= hi_t)).all(1) & (lu < llp - llc)
             cur = torch.where(ok[:, None], prop, cur)
             llc = torch.where(ok, llp, llc)
-            n_acc += int(ok.sum().item())
+            n_acc += ok.sum()
             if r >= rounds - keep:
                 hist.append(cur)
                 hll.append(llc)
-        acc_log.append(n_acc / (steps * n_chains))
-    C = torch.cov(cur.T) + torch.diag((hi_t - lo_t) ** 2 * 1e-14)
-    L = torch.linalg.cholesky(C) * (2.38 / np.sqrt(D))
+        acc_log.append(int(n_acc.item()) / (steps * n_chains))
+    L = proposal_factor(cur)
     info = {"prior_draws": n_prior, "chains": n_chains, "rounds": rounds,
             "steps_per_round": steps, "acceptance_per_round": acc_log}
     return cur, llc, torch.cat(hist), torch.cat(hll), L, info

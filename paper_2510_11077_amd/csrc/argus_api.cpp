@@ -177,9 +177,25 @@ std::vector<int32_t> make_items_binned(const std::vector<int64_t>& counts, int64
   return it;
 }
 
+FilterArgs filter_args(argus_dataset* ds, Workspace* w, const double* theta,
+                       const TuneCfg& cfg);
+
 int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
                        double* logl, int32_t* status, const TuneCfg& cfg,
                        hipStream_t st) {
+  const FilterArgs a = filter_args(ds, w, theta, cfg);
+  if (cfg.order == 2)
+    HIPCHK(launch_scan(ds->model, a, cfg.grid, cfg.block / kWave, st));
+  else
+    HIPCHK(launch_filter(ds->model, a, cfg.grid, cfg.block, st));
+  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, status,
+               w->counter.as<int32_t>(), w->S, ds->P};
+  HIPCHK(launch_reduce(r, st));
+  return ARGUS_OK;
+}
+
+FilterArgs filter_args(argus_dataset* ds, Workspace* w, const double* theta,
+                       const TuneCfg& cfg) {
   FilterArgs a{};
   a.rec = ds->rec.as<TOARec>();
   a.chrom = ds->chrom.as<double>();
@@ -201,14 +217,7 @@ int launch_loglike_seq(argus_dataset* ds, Workspace* w, const double* theta,
   a.n_items = bal ? w->n_items_bal : w->n_items;
   a.dynamic = bal ? 2 : cfg.dynamic;
   a.mc = ds->mc;
-  if (cfg.order == 2)
-    HIPCHK(launch_scan(ds->model, a, cfg.grid, cfg.block / kWave, st));
-  else
-    HIPCHK(launch_filter(ds->model, a, cfg.grid, cfg.block, st));
-  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), logl, status,
-               w->counter.as<int32_t>(), w->S, ds->P};
-  HIPCHK(launch_reduce(r, st));
-  return ARGUS_OK;
+  return a;
 }
 
 std::vector<TuneCfg> candidates(const argus_dataset* ds, const Workspace* w) {
@@ -599,6 +608,49 @@ int argus_loglike_plain(argus_dataset_t ds, const double* theta, int64_t S, doub
                 status ? status + s : nullptr, ds->D, ds->P, ds->model, ds->mc};
     HIPCHK(launch_plain(a, st));
   }
+  return ARGUS_OK;
+}
+
+int argus_filter_kernel_ms(argus_dataset_t ds, const double* theta, int64_t S, int32_t reps,
+                           double* ms, void* stream) {
+  int rc = check_call(ds, theta, S, ms);
+  if (rc) return rc;
+  if (!ms || reps < 1 || S < 1) return fail(ARGUS_E_INVAL, "need ms, reps >= 1 and S >= 1");
+  if (ds->model == ARGUS_M3_JOINT_HD)
+    return fail(ARGUS_E_UNSUPPORTED, "the joint model has one kernel per call: time the call");
+  auto it = ds->ws.find(S);
+  if (it == ds->ws.end() || !it->second->tuned)
+    return fail(ARGUS_E_INVAL, "call argus_loglike for this S first (the launch is tuned there)");
+  Workspace* w = it->second.get();
+  hipStream_t st = (hipStream_t)stream;
+  const FilterArgs a = filter_args(ds, w, theta, w->cfg);
+  // one pair of events around each launch; the work-queue head of the
+  // atomic-queue layout is cleared between launches, outside the pairs
+  std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    if (w->cfg.dynamic == 1 && w->cfg.order == 0) e = hipMemsetAsync(w->counter.p, 0, 4, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * i], st);
+    if (e == hipSuccess)
+      e = w->cfg.order == 2 ? launch_scan(ds->model, a, w->cfg.grid, w->cfg.block / kWave, st)
+                            : launch_filter(ds->model, a, w->cfg.grid, w->cfg.block, st, false);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], st);
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+  double tot = 0.0;
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+    tot += t;
+  }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (w->cfg.dynamic == 1 && w->cfg.order == 0 && e == hipSuccess)
+    e = hipMemsetAsync(w->counter.p, 0, 4, st);
+  if (e != hipSuccess) return fail(ARGUS_E_HIP, std::string("timing: ") + hipGetErrorString(e));
+  *ms = tot / reps;
   return ARGUS_OK;
 }
 

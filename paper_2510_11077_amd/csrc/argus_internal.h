@@ -285,8 +285,10 @@ struct StageArgs {
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t st);
 hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st);
+// Model 2 launches the fast filter, then (with_redo) the general filter over
+// the items the fast one flagged.
 hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
-                         hipStream_t st);
+                         hipStream_t st, bool with_redo = true);
 // Time-parallel filter (models 1, 2): one workgroup of nw waves (4, 8 or 16)
 // per item, grid workgroups striding over the items.
 hipError_t launch_scan(int model, const FilterArgs& a, int grid, int nw, hipStream_t st);

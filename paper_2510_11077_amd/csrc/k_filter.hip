@@ -149,7 +149,7 @@ __device__ __forceinline__ void step4(F4& f, const TOARec r, double em,
 // product leaves the positive normal range, or whose result is not finite is
 // re-run by the caller with step4, whose per-step tests decide the status
 // word. The red-OU decay comes from expm1_fast, which needs |rate dt| <=
-// 1000 ln 2 (the caller checks every item against its pulsar's largest
+// 2^30 ln 2 (the caller checks every item against its pulsar's largest
 // interval). With S >= 2^-120 a group's partial products stay above
 // 2^-961, so no product passes through the subnormal range.
 constexpr int kGroup = 8;
@@ -190,11 +190,12 @@ __device__ __forceinline__ Expm1H expm1h_vgpr() {
   return k;
 }
 
-// expm1(-g dt) for gl = g / ln 2 with gl dt <= 1000 (and >= 0). Adding
+// expm1(-g dt) for gl = g / ln 2 with 0 <= gl dt <= 2^30. Adding
 // 1.5 * 2^52 rounds -gl dt to the nearest integer k (ties to even), and the
-// low 32 bits of that sum are k itself; u = -gl dt - k is formed with one
-// rounding (exact product in the fma), |u| <= 1/2; expm1(u ln 2) =
-// u (ln 2 + u H(u)); expm1(-g dt) = 2^k expm1(u ln 2) + (2^k - 1).
+// low 32 bits of that sum are k itself (|k| < 2^31); u = -gl dt - k is
+// formed with one rounding (exact product in the fma), |u| <= 1/2;
+// expm1(u ln 2) = u (ln 2 + u H(u)); expm1(-g dt) = 2^k expm1(u ln 2) +
+// (2^k - 1), where 2^k underflows to 0 (the result -1) below k = -1074.
 __device__ __forceinline__ double expm1_fast(double gl, double dt, const Expm1H& h) {
   const double t = __builtin_fma(-gl, dt, h.magic);
   const double kf = t - h.magic;
@@ -411,23 +412,9 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
     q_hi = a.bin_off[4 * blockIdx.x + simd + 1];
   }
   int next = gwave;
-  // general form after the fast one (model 2): the marked items, found by
-  // reading the flags 64 at a time (one per lane) and walking the set bits
-  uint64_t rmask = 0;
-  int rbase = (gwave - nwaves) * kWave;
   for (;;) {
     int it;
-    if (MODEL == 2 && !FAST && a.redo) {
-      while (rmask == 0) {
-        rbase += nwaves * kWave;
-        if (rbase >= a.n_items) break;
-        const int idx = rbase + lane;
-        rmask = __builtin_amdgcn_ballot_w64(idx < a.n_items && a.redo[idx] != 0);
-      }
-      if (rmask == 0) break;
-      it = rbase + __builtin_ctzll(rmask);
-      rmask &= rmask - 1;
-    } else if (a.dynamic == 1) {
+    if (a.dynamic == 1) {
       int v = 0;
       if (lane == 0) v = atomicAdd(a.counter, 1);
       it = __builtin_amdgcn_readfirstlane(v);
@@ -448,6 +435,8 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       next += nwaves;
     }
     if (a.dynamic != 2 && it >= a.n_items) break;
+    // general form after the fast one (model 2): the marked items only
+    if (MODEL == 2 && !FAST && a.redo && !a.redo[it]) continue;
     const int tile = a.items ? a.items[2 * it] : it % a.tiles;
     const int p = a.items ? a.items[2 * it + 1] : a.porder[it / a.tiles];
     const int64_t s_raw = (int64_t)tile * kWave + lane;
@@ -550,7 +539,7 @@ __global__ void __launch_bounds__(MAXT) k_filter(FilterArgs a) {
       // fast form unless a parameter is not finite or the red-OU exponent
       // could leave expm1_fast's range on this pulsar
       const double gl = gr * 1.44269504088896338700;
-      const bool fast_lane = !pnf && gl * a.maxdt[p] <= 1000.0;
+      const bool fast_lane = !pnf && gl * a.maxdt[p] <= 0x1p30;
       bool done = false;
       if (FAST && __builtin_amdgcn_ballot_w64(!fast_lane) == 0) {
         const Expm1H hc = expm1h_vgpr();
@@ -883,7 +872,7 @@ hipError_t launch_hd(const double* pos, int P, double* G, hipStream_t st) {
 }
 
 hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
-                         hipStream_t st) {
+                         hipStream_t st, bool with_redo) {
   const bool big = block > 256;
   if (model == 4 && !big)
     hipLaunchKernelGGL((k_filter<4, 256, false>), dim3(grid), dim3(block), 0, st, a);
@@ -895,8 +884,7 @@ hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
     hipLaunchKernelGGL((k_filter<1, 1024, false>), dim3(grid), dim3(block), 0, st, a);
   else {
     // model 2: the fast form over all items, then the general form over the
-    // items it marked (statically strided over a fixed grid of one-wave
-    // blocks; without marks every wave only reads the flags)
+    // items it marked (without marks every wave only reads its flag)
     if (!big)
       hipLaunchKernelGGL((k_filter<2, 256, true>), dim3(grid), dim3(block), 0, st, a);
     else if (block <= 512)
@@ -904,14 +892,15 @@ hipError_t launch_filter(int model, const FilterArgs& a, int grid, int block,
     else
       hipLaunchKernelGGL((k_filter<2, 1024, true>), dim3(grid), dim3(block), 0, st, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // (with per-SIMD lists, a.items and a.n_items are those lists, which is
-    // what the fast form's item indices refer to)
+    if (e != hipSuccess || !with_redo) return e;
+    // One wave per item (statically assigned), each reading its own flag,
+    // so that many marked items run in parallel; with per-SIMD lists,
+    // a.items and a.n_items are those lists, which is what the fast form's
+    // item indices refer to.
     FilterArgs b = a;
     b.dynamic = 0;
-    const int chunks = (b.n_items + kWave - 1) / kWave;
-    const int rg = chunks < 1 ? 1 : (chunks > 64 ? 64 : chunks);
-    hipLaunchKernelGGL((k_filter<2, 256, false>), dim3(rg), dim3(64), 0, st, b);
+    const int rg = b.n_items > 0 ? (b.n_items + 3) / 4 : 1;
+    hipLaunchKernelGGL((k_filter<2, 256, false>), dim3(rg), dim3(256), 0, st, b);
   }
   return hipGetLastError();
 }
