@@ -499,40 +499,77 @@ struct DA1Args {
   int32_t* flag1;       // [Q] stage-1 decision
 };
 
-__global__ void k_da1_count(DA1Args a) {
-  __shared__ int s_cnt;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
+// Stage-1 compaction in three launches with no serial loop: per block, the
+// survivors' count from one ballot per wave; one block scans the block
+// counts (in chunks of 1024 with a carry); per block, each survivor's slot
+// is the block's offset plus the survivors in earlier waves of the block
+// plus those in lower lanes of its own wave (mbcnt). The order of the
+// survivors is their chain order.
+constexpr int kScanWaves = kScanBlock / 64;
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_da1_count(DA1Args a) {
+  __shared__ int s_cnt[kScanWaves];
   const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
   int ok = 0;
   if (i < a.Q) {
     ok = stage1_ok(i, a.theta_prop, a.d, a.lo, a.hi, a.lh_cur, a.lh_prop, a.logu1);
     a.flag1[i] = ok;
   }
-  if (ok) atomicAdd(&s_cnt, 1);  // integer count: order-independent
+  const uint64_t m = __builtin_amdgcn_ballot_w64(ok != 0);
+  if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = __builtin_popcountll(m);
   __syncthreads();
-  if (threadIdx.x == 0) a.block_cnt[blockIdx.x] = s_cnt;
-}
-
-__global__ void k_da1_scan(DA1Args a, int nblocks) {
-  if (threadIdx.x != 0) return;
-  int acc = 0;
-  for (int b = 0; b < nblocks; ++b) {
-    a.block_off[b] = acc;
-    acc += a.block_cnt[b];
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int w = 0; w < kScanWaves; ++w) c += s_cnt[w];
+    a.block_cnt[blockIdx.x] = c;
   }
-  *a.count = acc;
 }
 
-__global__ void k_da1_write(DA1Args a) {
-  __shared__ int s_flag[kScanBlock];
-  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-  s_flag[threadIdx.x] = i < a.Q ? a.flag1[i] : 0;
+// exclusive prefix of the block counts, one block of 1024 threads
+__global__ void __launch_bounds__(1024) k_da1_scan(DA1Args a, int nblocks) {
+  __shared__ int s_w[16];
+  __shared__ int s_carry;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) s_carry = 0;
   __syncthreads();
-  if (i >= a.Q || !s_flag[threadIdx.x]) return;
-  int before = 0;
-  for (int j = 0; j < (int)threadIdx.x; ++j) before += s_flag[j];
-  a.idx[a.block_off[blockIdx.x] + before] = (int32_t)i;
+  for (int base = 0; base < nblocks; base += 1024) {
+    const int b = base + t;
+    const int v = b < nblocks ? a.block_cnt[b] : 0;
+    int x = v;  // inclusive scan within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int before = s_carry;
+    for (int q = 0; q < w; ++q) before += s_w[q];
+    if (b < nblocks) a.block_off[b] = before + x - v;
+    __syncthreads();
+    if (t == 1023) s_carry = before + x;
+    __syncthreads();
+  }
+  if (t == 0) *a.count = s_carry;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_da1_write(DA1Args a) {
+  __shared__ int s_cnt[kScanWaves];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  const int ok = i < a.Q ? a.flag1[i] : 0;
+  const uint64_t m = __builtin_amdgcn_ballot_w64(ok != 0);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_cnt[w] = __builtin_popcountll(m);
+  __syncthreads();
+  if (!ok) return;
+  int before = a.block_off[blockIdx.x] + lanes_below(m);
+  for (int q = 0; q < w; ++q) before += s_cnt[q];
+  a.idx[before] = (int32_t)i;
 }
 
 __global__ void k_gather_rows(const double* src, const int32_t* idx, const int32_t* count,
@@ -994,7 +1031,7 @@ int argus_da_stage1(const double* theta_prop, const double* lo, const double* hi
   hipStream_t st = (hipStream_t)stream;
   const int nb = (int)blocks(Q, kScanBlock);
   if (Q == 0) {
-    hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(64), 0, st,
+    hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(1024), 0, st,
                        DA1Args{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d,
                                nullptr, nullptr, nullptr, count, nullptr},
                        0);
@@ -1008,7 +1045,7 @@ int argus_da_stage1(const double* theta_prop, const double* lo, const double* hi
             work + Q, work + Q + nb, idx, count, work};
   hipLaunchKernelGGL(k_da1_count, dim3(nb), dim3(kScanBlock), 0, st, a);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(64), 0, st, a, nb);
+  hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(1024), 0, st, a, nb);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_da1_write, dim3(nb), dim3(kScanBlock), 0, st, a);
   HIPCHK(hipGetLastError());

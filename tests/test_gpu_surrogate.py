@@ -258,6 +258,28 @@ def test_stage1_compaction_and_stage2(A):
     assert np.array_equal(llc.cpu().numpy(), exp_ll) and np.array_equal(lhc.cpu().numpy(), exp_lh)
 
 
+@pytest.mark.parametrize("Q", [1, 255, 257, 65536, 300001])
+def test_stage1_compaction_sizes(A, Q):
+    """Survivor indices in chain order and their count, for sizes around the
+    256-chain block and beyond 1024 blocks (the scan's carry across chunks)."""
+    import torch
+    rng = np.random.default_rng(Q)
+    d = 2
+    lo, hi = np.zeros(d), np.ones(d)
+    prop = rng.uniform(-0.05, 1.05, size=(Q, d))
+    lh_cur, lh_prop = rng.normal(size=Q), rng.normal(size=Q)
+    lu1 = np.log(rng.uniform(size=Q))
+    keep = np.all((prop >= lo) & (prop <= hi), axis=1) & (lu1 < lh_prop - lh_cur)
+    idx = torch.full((Q,), -1, dtype=torch.int32, device="cuda")
+    count = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    work = torch.empty(A.da_work_size(Q), dtype=torch.int32, device="cuda")
+    A.da_stage1(dev(prop), dev(lo), dev(hi), dev(lh_cur), dev(lh_prop), dev(lu1), idx, count, work)
+    n = count.item()
+    ref = np.nonzero(keep)[0]
+    assert n == ref.size
+    assert np.array_equal(idx.cpu().numpy()[:n], ref)
+
+
 def test_da_chain_replays_exactly(A):
     """Three DA iterations of 256 chains on a 2-pulsar dataset: every chain
     state equals the per-chain reference decisions (oracle logL at the
