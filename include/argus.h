@@ -306,6 +306,18 @@ int argus_surrogate_train_step(argus_mlp_t h, float* master, float* adam_m,
                                const double* target, int64_t B, float lr,
                                int64_t step, float* loss_out, void* stream);
 
+/* n_batches training steps in one call (width <= 256, else
+ * ARGUS_E_UNSUPPORTED): batch b takes rows order[b*B .. (b+1)*B) (dev int32,
+ * each in [0, N)) of theta (dev [N*d_in]) and target (dev [N]) and makes
+ * the step of argus_surrogate_train_step numbered step0 + b + 1 (Adam's bias
+ * correction); loss_out dev [n_batches] (each batch's loss before its
+ * update) or NULL. An epoch is one call with a permutation of the training
+ * rows as order; nothing is gathered or copied on the host. */
+int argus_surrogate_train_epoch(argus_mlp_t h, float* master, float* adam_m, float* adam_v,
+                                const double* theta, const double* target,
+                                const int32_t* order, int64_t n_batches, int64_t B, float lr,
+                                int64_t step0, float* loss_out, void* stream);
+
 /* Delayed acceptance, stage 1 for Q chains with symmetric proposals: chain i
  * survives when theta_prop[i] lies in [lo, hi] (dev [d]) and
  * logu1[i] < lh_prop[i] - lh_cur[i] (surrogate values). Survivor indices go

@@ -68,6 +68,8 @@ _lib.argus_surrogate_eval.argtypes = [_V, _V, C.c_int64, _V, _V]
 _lib.argus_mlp_grad.argtypes = [_V, _V, _V, C.c_int64, _V, _V, _V]
 _lib.argus_surrogate_train_step.argtypes = [_V, _V, _V, _V, _V, _V, C.c_int64, C.c_float,
                                             C.c_int64, _V, _V]
+_lib.argus_surrogate_train_epoch.argtypes = [_V, _V, _V, _V, _V, _V, _V, C.c_int64, C.c_int64,
+                                             C.c_float, C.c_int64, _V, _V]
 _lib.argus_da_stage1.argtypes = [_V, _V, _V, _V, _V, _V, C.c_int64, C.c_int32, _V, _V, _V, _V]
 _lib.argus_da_work_size.argtypes = [C.c_int64]
 _lib.argus_da_work_size.restype = C.c_int64
@@ -361,6 +363,21 @@ class MLP:
                                    g.data_ptr(), self.loss.data_ptr(), _stream(stream)))
         return g, self.loss
 
+    def train_epoch(self, theta, target, order, batch, lr, losses=None, stream=None):
+        """len(order) // batch training steps in one library call; batch b
+        uses rows order[b*batch:(b+1)*batch] of theta [N, d] / target [N]
+        (device, float64); order: device int32. losses: optional device
+        float32 [n_batches] for each batch's loss."""
+        import torch
+        n_batches = order.numel() // batch
+        _check(_lib.argus_surrogate_train_epoch(
+            self._h, self.master.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+            _dev_ptr(theta, torch.float64, "theta"), _dev_ptr(target, torch.float64, "target"),
+            _dev_ptr(order, torch.int32, "order"), n_batches, batch, float(lr), self.step,
+            _dev_ptr(losses, torch.float32, "losses"), _stream(stream)))
+        self.step += n_batches
+        return n_batches
+
     def train_step(self, theta, target, lr, stream=None):
         import torch
         self.step += 1
@@ -562,20 +579,20 @@ def fit_surrogate(theta, logl, center, T, init_weights, width=256, batch=512, ep
     net = MLP(theta.shape[1], width, batch)
     net.load_affine(init_weights, center, T, mu, sd)
     rng = np.random.default_rng(seed)
+    perms = [torch.as_tensor(rng.permutation(n).astype(np.int32), device=theta.device)
+             for _ in range(epochs)]
+    losses = torch.empty(n // batch, dtype=torch.float32, device=theta.device)
+    theta = theta.contiguous()
     steps = 0
     torch.cuda.synchronize()
     t0 = _time.perf_counter()
     for ep in range(epochs):
-        perm = torch.as_tensor(rng.permutation(n), device=theta.device)
         lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / epochs))
-        for b in range(0, n - batch + 1, batch):
-            sel = perm[b:b + batch]
-            net.train_step(theta[sel], y[sel], lr_ep)
-            steps += 1
+        steps += net.train_epoch(theta, y, perms[ep], batch, lr_ep, losses)
     torch.cuda.synchronize()
     info = {"samples": n, "epochs": epochs, "batch": batch, "steps": steps,
             "seconds": _time.perf_counter() - t0, "floor": floor,
-            "final_loss": float(net.loss.item())}
+            "final_loss": float(losses[-1].item())}
     return net, info
 
 

@@ -206,28 +206,31 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
   __shared__ __bf16 s_x[R * LDX];
   __shared__ __bf16 s_a[2][R * LDA];
   __shared__ float s_o[NW][R];
+  __shared__ double s_th[R * kKin];   // a chunk's theta rows minus c, d per row
+  __shared__ double s_T[kKin * kKin];  // input map matrix (d x d)
+  __shared__ double s_c[kKin];         // input map centre
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int ncol = 32 * w + (l & 31);     // B-fragment / accumulator column
   const int kh = 8 * (l >> 5);            // this lane's K half within a step
   const int d = f.d_in;
-  // standardised inputs of a chunk (rows past Q are zero), loaded into
-  // registers one chunk ahead
+  // a chunk's theta rows (R x d doubles, contiguous) loaded into registers
+  // one chunk ahead, flat and coalesced (rows past Q read as zero)
   constexpr int NT = NW * 64, PF = (R * kKin + NT - 1) / NT;
-  float pf[PF];
+  double pf[PF];
   auto fetch = [&](int64_t row0) {
+    const int64_t base = row0 * d;
+    const int64_t end = (row0 + R < f.Q ? row0 + R : f.Q) * d;
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int i = t + j * NT;
-      const int m = i / kKin, k = i - m * kKin;
-      float v = 0.0f;
-      if (i < R * kKin && k < d && row0 + m < f.Q)
-        v = (float)map_input(f.theta + (row0 + m) * d, d, k, f.c, f.T);
-      pf[j] = v;
+      pf[j] = (i < R * d && base + i < end) ? f.theta[base + i] : 0.0;
     }
   };
   // the first chunk's inputs before the weights, so that its wait does not
   // also wait for the weight fragments
   fetch((int64_t)blockIdx.x * R);
+  for (int i = t; i < d * d; i += NT) s_T[i] = f.T[i];
+  if (t < d) s_c[t] = f.c[t];
   bf16x8 w1[2], w2[KS], w3[KS];
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks)
@@ -286,14 +289,30 @@ __global__ void __launch_bounds__(W * 2) k_mlp_fused(FusedArgs f) {
     }
   };
 
+  __syncthreads();  // s_T, s_c
   for (int64_t c = blockIdx.x; c * R < f.Q; c += gridDim.x) {
     const int64_t row0 = c * R;
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int i = t + j * NT;
-      if (i < R * kKin) s_x[(i / kKin) * LDX + i % kKin] = (__bf16)pf[j];
+      if (i < R * d) s_th[i] = pf[j] - s_c[i % d];
     }
     fetch(row0 + (int64_t)gridDim.x * R);
+    __syncthreads();
+    // mapped inputs x = T (theta - c) in FP64, summed in index order, then
+    // FP32 and BF16 (as map_input); a thread's column k = t mod kKin is the
+    // same for all of its elements
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int i = t + j * NT;
+      const int m = i / kKin, k = i - m * kKin;
+      if (i < R * kKin) {
+        double acc = 0.0;
+        if (k < d)
+          for (int jj = 0; jj < d; ++jj) acc = fma(s_T[k * d + jj], s_th[m * d + jj], acc);
+        s_x[m * LDX + k] = (__bf16)(float)acc;
+      }
+    }
     __syncthreads();
     layer(std::integral_constant<int, 2>{}, s_x, LDX, w1, bias1, s_a[0]);
     __syncthreads();
@@ -426,7 +445,8 @@ struct AdamArgs {
   float* p32;             // the handle's FP32 copy (biases, output layer)
   __bf16 *w1, *w2, *w3;   // BF16 hidden weights [w x kKin], [w x w], [w x w]
   __bf16 *w2T, *w3T;      // transposed copies
-  __bf16 *w2F, *w3F;      // fragment-ordered copies for fused inference, or null
+  __bf16 *w2F, *w3F;      // fragment-ordered copies for the fused kernels, or null
+  __bf16 *w2TF, *w3TF;    // fragment-ordered copies of the transposes (fused training), or null
   int64_t n;
   int d_in, width;
   // 1 - beta is formed in double on the host: 1.0f - 0.999f is 1.3e-5 off
@@ -447,11 +467,13 @@ __device__ __forceinline__ void scatter_copy(const AdamArgs& a, int64_t i, float
     a.w2[n * dW + k] = b;
     a.w2T[k * dW + n] = b;
     if (a.w2F) a.w2F[frag_index(n, k, dW)] = b;
+    if (a.w2TF) a.w2TF[frag_index(k, n, dW)] = b;
   } else if (i >= o3 && i < o3 + dW * dW) {
     const int64_t n = (i - o3) / dW, k = (i - o3) % dW;
     a.w3[n * dW + k] = b;
     a.w3T[k * dW + n] = b;
     if (a.w3F) a.w3F[frag_index(n, k, dW)] = b;
+    if (a.w3TF) a.w3TF[frag_index(k, n, dW)] = b;
   }
 }
 
@@ -469,6 +491,501 @@ __global__ void k_adam(AdamArgs a) {
     a.master[i] = w;
   }
   scatter_copy(a, i, w);
+}
+
+// ------------------------------------------------------ fused training
+// Training step for W <= 256 in two launches, with the arithmetic of the
+// general path (the same BF16 roundings: inputs, hidden weights, hidden
+// activations and the pre-activation gradients dz; FP32 accumulation;
+// biases, output layer and optimiser state in FP32):
+//
+// k_train_rows: one workgroup of W/32 waves per 32-row chunk of the batch.
+// Rows are gathered through an index list (a shuffled epoch reads the
+// training set in place), mapped to inputs, and taken through the three
+// hidden layers (wave w owns output columns [32 w, 32 w + 32); the B
+// fragments of each layer are loaded into registers one layer ahead, so the
+// chain of a chunk waits on global memory once, in its input stage), keeping
+// SiLU'(z) of every element in registers; then the output layer, the
+// residual, dz of the last layer, and two backward-data products
+// (dz_l W_l, B fragments from the transposed copies) down to dz_1. The
+// chunk writes its inputs, a_1, a_2 and dz_1..3 transposed (rows of the
+// weight-gradient products, 16-B stores), and per-chunk partial sums of
+// dz_l (bias gradients), dout a_3 (output weights), dout and the squared
+// residual.
+//
+// The transposed activations (rows: units of a layer; columns: batch rows)
+// pass between the two kernels in K-step fragment order: element (n, m) of
+// an NR-row matrix sits at
+//   ((m / 32) (NR / 32) + n / 32) 1024 + ((m / 16) % 2) 512
+//     + (n % 32 + 32 ((m / 8) % 2)) 8 + m % 8,
+// so that the MFMA operand of 32 rows and one K step (16 batch rows) is one
+// 1-KB run, lane l reading 16 B at l * 16 B, and each 32-row chunk of the
+// batch is one contiguous block.
+//
+// k_train_update: one block per 32 x 32 tile of dW_l = dz_l^T a_{l-1} over
+// the whole batch (its eight waves split the batch rows, partial tiles added
+// in wave order), and one lane per remaining parameter, whose block's eight
+// waves split the chunk partials (sums added in wave order); each
+// parameter's gradient is formed by exactly one lane, which then applies
+// Adam and refreshes the handle's FP32 and BF16 copies (row-major,
+// transposed, fragment order).
+constexpr int kTrainRows = 32;
+struct TrainRowsArgs {
+  const double* theta;   // [N x d] training inputs
+  const double* target;  // [N]
+  const int32_t* idx;    // [B] rows of this batch, or null for rows 0..B-1
+  int d;
+  const double* c;       // input map centre [d]
+  const double* T;       // input map matrix [d x d]
+  double mu, sd;
+  const __bf16* W1;      // [W x kKin]
+  const __bf16* W2F;     // fragment order
+  const __bf16* W3F;
+  const __bf16* W2TF;    // the transposes W2^T, W3^T in fragment order
+  const __bf16* W3TF;
+  const float* p32;      // biases, W4, b4
+  float inv_b;           // 1 / B
+  __bf16* x0T;           // [kKin x B], K-step fragment order
+  __bf16* a1T;           // [W x B], K-step fragment order
+  __bf16* a2T;
+  __bf16* dz1T;
+  __bf16* dz2T;
+  __bf16* dz3T;
+  float* part;           // [chunks x (4 W + 2)]
+};
+
+template <int W>
+__global__ void __launch_bounds__(W * 2) k_train_rows(TrainRowsArgs f) {
+  constexpr int NW = W / 32, KS = W / 16, R = kTrainRows;
+  constexpr int LDA = W + 8, LDX = kKin + 8, NT = NW * 64, NP = 4 * W + 2;
+  __shared__ __bf16 s_x[R * LDX];
+  __shared__ __bf16 s_a[2][R * LDA];
+  __shared__ float s_o[NW][R];
+  __shared__ double s_th[R * kKin];
+  __shared__ double s_T[kKin * kKin];
+  __shared__ double s_c[kKin];
+  __shared__ float s_w4[W + 1];  // output weights, then the output bias
+  __shared__ float s_t[R], s_dout[R], s_sq[R];
+  __shared__ float s_ds1[16 * NT];  // SiLU'(z_1), element r of thread t at r NT + t
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int ncol = 32 * w + (l & 31), kh = 8 * (l >> 5);
+  const int d = f.d;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  float* part = f.part + (int64_t)blockIdx.x * NP;
+  const float* b1 = f.p32 + (int64_t)W * d;
+  const float* b2 = b1 + W + (int64_t)W * W;
+  const float* b3 = b2 + W + (int64_t)W * W;
+  const float* W4 = b3 + W;
+
+  // Weight fragments are loaded ahead into two register sets: fb holds W1,
+  // then W3, then W2^T (loaded once the last layer's SiLU' is used up), fa
+  // holds W2, then W3^T, all in fragment order (one 1-KB run per wave and
+  // K step). W1 and this lane's biases are loaded with the inputs, W2 while
+  // the inputs are mapped.
+  bf16x8 fa[KS], fb[KS];
+  float bias1, bias2, bias3;
+
+  // inputs, standardised targets and output weights of the chunk: every
+  // load is issued (row numbers first, then the rows) before any LDS store,
+  // with out-of-range slots reading element 0 and storing nothing
+  constexpr int NI = (R * kKin + NT - 1) / NT, NTI = (kKin * kKin + NT - 1) / NT;
+  {
+    int64_t src[NI], trow;
+    const int tr = t < R ? t : 0;
+    if (f.idx) {
+#pragma unroll
+      for (int it = 0; it < NI; ++it) {
+        const int i = t + it * NT;
+        src[it] = f.idx[row0 + (i < R * d ? i / d : 0)];
+      }
+      trow = f.idx[row0 + tr];
+    } else {
+#pragma unroll
+      for (int it = 0; it < NI; ++it) {
+        const int i = t + it * NT;
+        src[it] = row0 + (i < R * d ? i / d : 0);
+      }
+      trow = row0 + tr;
+    }
+    double tv[NTI];
+#pragma unroll
+    for (int it = 0; it < NTI; ++it) {
+      const int i = t + it * NT;
+      tv[it] = f.T[i < d * d ? i : 0];
+    }
+    const double cv = f.c[t < d ? t : 0];
+    const float w4v = W4[t <= W ? t : W];  // NT = 2 W threads cover W4 and b4
+    double thv[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int i = t + it * NT, m = i < R * d ? i / d : 0, j = i < R * d ? i - m * d : 0;
+      thv[it] = f.theta[src[it] * d + j];
+    }
+    const double tg = f.target[trow];
+    // after the input loads, so that waiting for those does not wait for these
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+      fb[ks] = *reinterpret_cast<const bf16x8*>(f.W1 + (size_t)ncol * kKin + 16 * ks + kh);
+    bias1 = b1[ncol];
+    bias2 = b2[ncol];
+    bias3 = b3[ncol];
+#pragma unroll
+    for (int it = 0; it < NTI; ++it)
+      if (t + it * NT < d * d) s_T[t + it * NT] = tv[it];
+    if (t < d) s_c[t] = cv;
+    if (t <= W) s_w4[t] = w4v;
+    if (t < R) s_t[t] = (float)((tg - f.mu) / f.sd);
+#pragma unroll
+    for (int it = 0; it < NI; ++it)
+      if (t + it * NT < R * d) s_th[t + it * NT] = thv[it];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      fa[ks] = *reinterpret_cast<const bf16x8*>(f.W2F + ((size_t)(w * KS + ks) * 64 + l) * 8);
+  }
+  __syncthreads();
+  // x = T (theta - c) for the R x d inputs (four terms' operands read
+  // ahead, terms added in order), zeros in columns d .. kKin - 1
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
+    const int i = t + it * NT;
+    if (i < R * d) {
+      const int m = i / d, k = i - m * d;
+      const double* Tk = s_T + k * d;
+      const double* th = s_th + m * d;
+      double acc = 0.0;
+      int jj = 0;
+      for (; jj + 4 <= d; jj += 4) {
+        double tq[4], xq[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          tq[e] = Tk[jj + e];
+          xq[e] = th[jj + e] - s_c[jj + e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = fma(tq[e], xq[e], acc);
+      }
+      for (; jj < d; ++jj) acc = fma(Tk[jj], th[jj] - s_c[jj], acc);
+      s_x[m * LDX + k] = (__bf16)(float)acc;
+    }
+  }
+  for (int i = t; i < R * (kKin - d); i += NT) {
+    const int m = i / (kKin - d);
+    s_x[m * LDX + d + (i - m * (kKin - d))] = (__bf16)0.0f;
+  }
+  __syncthreads();
+
+  // columns [0, ncols) of the chunk's R x ld LDS matrix into dstT, in
+  // K-step fragment order: each thread gathers 8 consecutive rows of one
+  // column into one 16-B unit, and consecutive threads write consecutive
+  // units
+  auto store_T = [&](const __bf16* src, int ld, int ncols, __bf16* dstT) {
+    __bf16* base = dstT + (int64_t)blockIdx.x * ncols * R;
+    for (int i = t; i < ncols * (R / 8); i += NT) {
+      const int ln = i & 63, s16 = (i >> 6) & 1, nb = i >> 7;
+      const int n = 32 * nb + (ln & 31), m8 = 16 * s16 + 8 * (ln >> 5);
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = src[(m8 + e) * ld + n];
+      *reinterpret_cast<bf16x8*>(base + (int64_t)i * 8) = v;
+    }
+  };
+  // per-column sums over the chunk's rows of an R x LDA LDS matrix (rows in order)
+  auto col_sums = [&](const __bf16* src, float* out) {
+    for (int n = t; n < W; n += NT) {
+      float acc = 0.0f;
+#pragma unroll 8
+      for (int m = 0; m < R; ++m) acc += (float)src[m * LDA + n];
+      out[n] = acc;
+    }
+  };
+  // The chunk's rows (src, stride lds) times this wave's 32 columns of Y
+  // (B fragments bf[ks]). Element r is row 8(r/4) + 4(l/32) + r%4, column ncol.
+  auto product = [&](auto ksn, const __bf16* src, int lds, const bf16x8* bf) {
+    constexpr int KSN = decltype(ksn)::value;
+    const __bf16* ap = src + (l & 31) * lds + kh;
+    f32x16 a = {};
+#pragma unroll
+    for (int ks = 0; ks < KSN; ++ks)
+      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8*>(ap + 16 * ks),
+                                                  bf[ks], a, 0, 0, 0);
+    return a;
+  };
+  auto row_of = [&](int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); };
+  // a = bf16(SiLU(z)) into dst and SiLU'(z) into dsl, z = acc + bias
+  auto silu_out = [&](const f32x16& acc, float bias, __bf16* dst, f32x16& dsl) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float z = acc[r] + bias, sg = sigm(z);
+      dst[row_of(r) * LDA + ncol] = (__bf16)(z * sg);
+      dsl[r] = sg * (1.0f + z * (1.0f - sg));
+    }
+  };
+
+  f32x16 ds[3];  // SiLU'(z_l) of this lane's elements (that of layer 1 kept in LDS)
+  f32x16 acc;
+  // ---- layer 1
+  acc = product(std::integral_constant<int, 2>{}, s_x, LDX, fb);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+    fb[ks] = *reinterpret_cast<const bf16x8*>(f.W3F + ((size_t)(w * KS + ks) * 64 + l) * 8);
+  silu_out(acc, bias1, s_a[0], ds[0]);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) s_ds1[r * NT + t] = ds[0][r];
+  store_T(s_x, LDX, kKin, f.x0T);
+  __syncthreads();
+  // ---- layer 2
+  acc = product(std::integral_constant<int, KS>{}, s_a[0], LDA, fa);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+    fa[ks] = *reinterpret_cast<const bf16x8*>(f.W3TF + ((size_t)(w * KS + ks) * 64 + l) * 8);
+  silu_out(acc, bias2, s_a[1], ds[1]);
+  store_T(s_a[0], LDA, W, f.a1T);
+  __syncthreads();
+  // ---- layer 3
+  acc = product(std::integral_constant<int, KS>{}, s_a[1], LDA, fb);
+  silu_out(acc, bias3, s_a[0], ds[2]);
+  store_T(s_a[1], LDA, W, f.a2T);
+  __syncthreads();
+  // a_3 is in s_a[0]. ---- output layer: wave w sums its 32 columns, 16 per lane half
+  {
+    const int c0 = 32 * w + 16 * (l >> 5);
+    const __bf16* ar = s_a[0] + (l & 31) * LDA + c0;
+    float o = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; j += 8) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(ar + j);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) o = fmaf((float)v[e], s_w4[c0 + j + e], o);
+    }
+    o += __shfl_xor(o, 32);
+    if (l < 32) s_o[w][l] = o;
+  }
+  __syncthreads();
+  if (t < R) {
+    float o = 0.0f;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) o += s_o[ww][t];
+    const float res = o + s_w4[W] - s_t[t];
+    s_dout[t] = 2.0f * res * f.inv_b;
+    s_sq[t] = res * res;
+  }
+  __syncthreads();
+  // output-layer partials: dout a_3 per column, dout and squared residual
+  for (int n = t; n < W; n += NT) {
+    float acc1 = 0.0f;
+#pragma unroll 8
+    for (int m = 0; m < R; ++m) acc1 = fmaf(s_dout[m], (float)s_a[0][m * LDA + n], acc1);
+    part[3 * W + n] = acc1;
+  }
+  if (t == 0) {
+    float sd = 0.0f, sq = 0.0f;
+#pragma unroll 8
+    for (int m = 0; m < R; ++m) {
+      sd += s_dout[m];
+      sq += s_sq[m];
+    }
+    part[4 * W] = sd;
+    part[4 * W + 1] = sq;
+  }
+  // ---- dz_3 = bf16(dout W4 SiLU'(z_3)) into s_a[1]
+  {
+    const float w4 = s_w4[ncol];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = row_of(r);
+      s_a[1][row * LDA + ncol] = (__bf16)(s_dout[row] * w4 * ds[2][r]);
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+    fb[ks] = *reinterpret_cast<const bf16x8*>(f.W2TF + ((size_t)(w * KS + ks) * 64 + l) * 8);
+  __syncthreads();
+  // ---- backward-data products: dz_L = bf16((dz_{L+1} W_{L+1}) SiLU'(z_L)),
+  // dz_3 in s_a[1] -> dz_2 in s_a[0] (W3^T in fa) -> dz_1 in s_a[1] (W2^T in fb)
+  col_sums(s_a[1], part + 2 * W);
+  store_T(s_a[1], LDA, W, f.dz3T);
+  acc = product(std::integral_constant<int, KS>{}, s_a[1], LDA, fa);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) s_a[0][row_of(r) * LDA + ncol] = (__bf16)(acc[r] * ds[1][r]);
+  __syncthreads();
+  col_sums(s_a[0], part + W);
+  store_T(s_a[0], LDA, W, f.dz2T);
+  acc = product(std::integral_constant<int, KS>{}, s_a[0], LDA, fb);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) s_a[1][row_of(r) * LDA + ncol] = (__bf16)(acc[r] * s_ds1[r * NT + t]);
+  __syncthreads();
+  col_sums(s_a[1], part);
+  store_T(s_a[1], LDA, W, f.dz1T);
+}
+
+struct TrainUpdArgs {
+  const __bf16* x0T;
+  const __bf16* a1T;
+  const __bf16* a2T;
+  const __bf16* dz1T;
+  const __bf16* dz2T;
+  const __bf16* dz3T;
+  const float* part;
+  int chunks;
+  int64_t B;
+  float inv_b;
+  float* g;       // [n] gradient (packed)
+  float* loss;    // [1] mean squared residual, or null
+  AdamArgs adam;  // do_update 0: gradient only, copies untouched
+};
+
+// Adam on parameter i from its gradient gv and loaded state (m0, v0, w0):
+// stores the new moments and master weight and refreshes the copies.
+__device__ __forceinline__ void adam_store(const AdamArgs& a, int64_t i, float gv, float m0,
+                                           float v0, float w0) {
+  const float m = a.b1 * m0 + a.omb1 * gv;
+  const float v = a.b2 * v0 + a.omb2 * gv * gv;
+  a.m[i] = m;
+  a.v[i] = v;
+  const float w = w0 - a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+  a.master[i] = w;
+  scatter_copy(a, i, w);
+}
+
+// k_train_update: one block of 8 waves per 32 x 32 weight-gradient tile.
+// The batch's K steps (16 rows each) are cut into groups of 4; wave q sums
+// groups [q G/8, (q+1) G/8) with up to 16 K steps of loads issued together
+// (each a 1-KB run of the fragment-ordered activations), so that all the
+// blocks together keep the whole operand traffic in flight. The eight
+// partial tiles meet in LDS, where each of the 512 threads adds two elements
+// in wave order and applies the update; blocks after the tiles take the
+// remaining parameters and the loss, 64 at a time.
+template <int W>
+__global__ void __launch_bounds__(512) k_train_update(TrainUpdArgs u) {
+  constexpr int NTL = W / 32, NP = 4 * W + 2;
+  __shared__ float s_tile[8][32 * 33];
+  const int l = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int d = u.adam.d_in;
+  const int64_t oW2 = (int64_t)W * d + W, oW3 = oW2 + (int64_t)W * W + W;
+  const int tiles_big = NTL * NTL, tiles = 2 * tiles_big + NTL;
+  const int unit = blockIdx.x;
+  if (unit < tiles) {
+    // dW[n][k] = sum over the batch of dzT[n][m] aT[k][m]
+    int layer, tile;
+    if (unit < tiles_big) {
+      layer = 3;
+      tile = unit;
+    } else if (unit < 2 * tiles_big) {
+      layer = 2;
+      tile = unit - tiles_big;
+    } else {
+      layer = 1;
+      tile = unit - 2 * tiles_big;
+    }
+    const int nt_k = layer == 1 ? 1 : NTL;
+    const int nb = tile / nt_k, kb = tile % nt_k;
+    const __bf16* X = layer == 3 ? u.dz3T : (layer == 2 ? u.dz2T : u.dz1T);
+    const __bf16* Y = layer == 3 ? u.a2T : (layer == 2 ? u.a1T : u.x0T);
+    const int ynb = layer == 1 ? kKin / 32 : NTL;  // 32-row blocks of Y
+    // K step g (chunk g / 2, half g % 2) of row block b of a matrix with nbk
+    // row blocks starts at ((g / 2) nbk + b) 1024 + (g % 2) 512 elements
+    const __bf16* xp = X + (int64_t)nb * 1024 + l * 8;
+    const __bf16* yp = Y + (int64_t)kb * 1024 + l * 8;
+    const int64_t xstep = (int64_t)NTL * 1024, ystep = (int64_t)ynb * 1024;
+    const int64_t G = u.B / 64, g0 = G * q / 8, g1 = G * (q + 1) / 8;
+    f32x16 acc = {};
+    for (int64_t g = g0; g < g1; g += 4) {
+      const int ng = (int)(g1 - g < 4 ? g1 - g : 4);
+      bf16x8 xa[16], yb[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if ((e >> 2) < ng) {
+          const int64_t st = 4 * g + e, c = st >> 1, h = st & 1;
+          xa[e] = *reinterpret_cast<const bf16x8*>(xp + c * xstep + h * 512);
+          yb[e] = *reinterpret_cast<const bf16x8*>(yp + c * ystep + h * 512);
+        }
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if ((e >> 2) < ng) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[e], yb[e], acc, 0, 0, 0);
+    }
+    // the eight partial tiles meet in LDS; each thread then forms two of the
+    // tile's gradients (partials added in wave order) and updates them
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      s_tile[q][(8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * 33 + (l & 31)] = acc[r];
+    __syncthreads();
+    const int kin = layer == 1 ? d : W;
+    const int64_t off = layer == 3 ? oW3 : (layer == 2 ? oW2 : 0);
+    const int n0 = 32 * nb, k0 = 32 * kb;
+    const int kl = threadIdx.x & 31, nl = threadIdx.x >> 5;  // elements (nl, kl), (nl + 16, kl)
+    if (k0 + kl >= kin) return;
+    float gv[2];
+    int64_t ix[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = (nl + 16 * h) * 33 + kl;
+      float sum = s_tile[0][e];
+#pragma unroll
+      for (int qq = 1; qq < 8; ++qq) sum += s_tile[qq][e];
+      gv[h] = sum;
+      ix[h] = off + (int64_t)(n0 + nl + 16 * h) * kin + k0 + kl;
+    }
+    const AdamArgs& a = u.adam;
+    if (a.do_update) {
+      float mo[2], vo[2], wo[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        mo[h] = a.m[ix[h]];
+        vo[h] = a.v[ix[h]];
+        wo[h] = a.master[ix[h]];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        u.g[ix[h]] = gv[h];
+        adam_store(a, ix[h], gv[h], mo[h], vo[h], wo[h]);
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) u.g[ix[h]] = gv[h];
+    }
+    return;
+  }
+  const int tiles_end = tiles;
+  // the remaining parameters and the loss, 64 per block (one per lane): the
+  // eight waves sum consecutive ranges of the chunk partials, in chunk order,
+  // and wave 0 adds the eight sums in wave order
+  __shared__ float s_vp[8][64];
+  const int j = (unit - tiles_end) * 64 + l;
+  const bool live = j <= 4 * W || (j == 4 * W + 1 && u.loss);
+  const int c0 = u.chunks * q / 8, c1 = u.chunks * (q + 1) / 8;
+  float acc = 0.0f;
+  if (live) {
+    int c = c0;
+    for (; c + 16 <= c1; c += 16) {
+      float v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = u.part[(int64_t)(c + e) * NP + j];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc += v[e];
+    }
+    for (; c < c1; ++c) acc += u.part[(int64_t)c * NP + j];
+  }
+  s_vp[q][l] = acc;
+  __syncthreads();
+  if (q > 0 || !live) return;
+#pragma unroll
+  for (int qq = 1; qq < 8; ++qq) acc += s_vp[qq][l];
+  if (j == 4 * W + 1) {
+    *u.loss = acc * u.inv_b;
+    return;
+  }
+  int64_t i;
+  if (j < W)
+    i = (int64_t)W * d + j;                      // b1
+  else if (j < 2 * W)
+    i = oW2 + (int64_t)W * W + (j - W);          // b2
+  else if (j < 3 * W)
+    i = oW3 + (int64_t)W * W + (j - 2 * W);      // b3
+  else
+    i = oW3 + (int64_t)W * W + W + (j - 3 * W);  // W4, then b4
+  u.g[i] = acc;
+  const AdamArgs& a = u.adam;
+  if (a.do_update) adam_store(a, i, acc, a.m[i], a.v[i], a.master[i]);
 }
 
 // ------------------------------------------------- delayed acceptance
@@ -618,7 +1135,7 @@ struct argus_mlp {
   int d_in = 0, width = 0;
   int64_t n = 0, max_batch = 0;
   int device = 0, n_cu = 256;
-  argus::DevBuf p32, w1, w2, w3, w2T, w3T, w2F, w3F;
+  argus::DevBuf p32, w1, w2, w3, w2T, w3T, w2F, w3F, w2TF, w3TF;
   argus::DevBuf ic, iT;  // input map x = T (theta - c): c [d_in], T [d_in x d_in]
   double mu = 0.0, sd = 1.0;
   bool loaded = false;
@@ -639,6 +1156,7 @@ struct argus_mlp {
   // training buffers
   argus::DevBuf x0, x0T, z[3], a[3], aT[3], dz[3], dzT[3], t, dout, sq, g;
   argus::DevBuf wpart;  // split-K partial weight gradients
+  argus::DevBuf tpart;  // fused training: per-chunk partial sums [max_batch/32 x (4 w + 2)]
 };
 
 namespace argus {
@@ -774,8 +1292,8 @@ int mlp_backprop(argus_mlp* h, const double* theta, const double* target, int64_
   return ARGUS_OK;
 }
 
-int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float lr,
-            int64_t step, hipStream_t st) {
+AdamArgs adam_args(argus_mlp* h, float* master, float* m, float* v, bool update, float lr,
+                   int64_t step) {
   AdamArgs a{};
   a.master = master;
   a.m = m;
@@ -789,6 +1307,8 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
   a.w3T = h->w3T.as<__bf16>();
   a.w2F = h->w2F.p ? h->w2F.as<__bf16>() : nullptr;
   a.w3F = h->w3F.p ? h->w3F.as<__bf16>() : nullptr;
+  a.w2TF = h->w2TF.p ? h->w2TF.as<__bf16>() : nullptr;
+  a.w3TF = h->w3TF.p ? h->w3TF.as<__bf16>() : nullptr;
   a.n = h->n;
   a.d_in = h->d_in;
   a.width = h->width;
@@ -801,7 +1321,79 @@ int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float 
   a.c1 = update ? (float)(1.0 / (1.0 - std::pow(0.9, (double)step))) : 1.0f;
   a.c2 = update ? (float)(1.0 / (1.0 - std::pow(0.999, (double)step))) : 1.0f;
   a.do_update = update ? 1 : 0;
+  return a;
+}
+
+// Adam on the handle's gradient buffer (update), or only the copies from
+// master (no update)
+int refresh(argus_mlp* h, float* master, float* m, float* v, bool update, float lr,
+            int64_t step, hipStream_t st) {
+  const AdamArgs a = adam_args(h, master, m, v, update, lr, step);
   hipLaunchKernelGGL(k_adam, dim3(blocks(h->n, 256)), dim3(256), 0, st, a);
+  HIPCHK(hipGetLastError());
+  return ARGUS_OK;
+}
+
+// One fused training step (width <= 256): rows of theta/target through idx
+// (or 0..B-1), gradient into gout, loss into loss (or null), Adam when update.
+int train_fused(argus_mlp* h, const double* theta, const double* target, const int32_t* idx,
+                int64_t B, float* master, float* m, float* v, bool update, float lr,
+                int64_t step, float* gout, float* loss, hipStream_t st) {
+  const int w = h->width;
+  TrainRowsArgs f{};
+  f.theta = theta;
+  f.target = target;
+  f.idx = idx;
+  f.d = h->d_in;
+  f.c = h->ic.as<double>();
+  f.T = h->iT.as<double>();
+  f.mu = h->mu;
+  f.sd = h->sd;
+  f.W1 = h->w1.as<__bf16>();
+  f.W2F = h->w2F.as<__bf16>();
+  f.W3F = h->w3F.as<__bf16>();
+  f.W2TF = h->w2TF.as<__bf16>();
+  f.W3TF = h->w3TF.as<__bf16>();
+  f.p32 = h->p32.as<float>();
+  f.inv_b = (float)(1.0 / (double)B);
+  f.x0T = h->x0T.as<__bf16>();
+  f.a1T = h->aT[0].as<__bf16>();
+  f.a2T = h->aT[1].as<__bf16>();
+  f.dz1T = h->dzT[0].as<__bf16>();
+  f.dz2T = h->dzT[1].as<__bf16>();
+  f.dz3T = h->dzT[2].as<__bf16>();
+  f.part = h->tpart.as<float>();
+  const dim3 rows_grid((unsigned)(B / kTrainRows)), rows_block(2 * w);
+  switch (w) {
+    case 64: hipLaunchKernelGGL(k_train_rows<64>, rows_grid, rows_block, 0, st, f); break;
+    case 128: hipLaunchKernelGGL(k_train_rows<128>, rows_grid, rows_block, 0, st, f); break;
+    case 192: hipLaunchKernelGGL(k_train_rows<192>, rows_grid, rows_block, 0, st, f); break;
+    default: hipLaunchKernelGGL(k_train_rows<256>, rows_grid, rows_block, 0, st, f); break;
+  }
+  HIPCHK(hipGetLastError());
+  TrainUpdArgs u{};
+  u.x0T = f.x0T;
+  u.a1T = f.a1T;
+  u.a2T = f.a2T;
+  u.dz1T = f.dz1T;
+  u.dz2T = f.dz2T;
+  u.dz3T = f.dz3T;
+  u.part = f.part;
+  u.chunks = (int)(B / kTrainRows);
+  u.B = B;
+  u.inv_b = f.inv_b;
+  u.g = gout;
+  u.loss = loss;
+  u.adam = adam_args(h, master, m, v, update, lr, step);
+  const int nt = w / 32;
+  const int units = 2 * nt * nt + nt + (4 * w + 2 + 63) / 64;
+  const dim3 upd_grid((unsigned)units), upd_block(512);
+  switch (w) {
+    case 64: hipLaunchKernelGGL(k_train_update<64>, upd_grid, upd_block, 0, st, u); break;
+    case 128: hipLaunchKernelGGL(k_train_update<128>, upd_grid, upd_block, 0, st, u); break;
+    case 192: hipLaunchKernelGGL(k_train_update<192>, upd_grid, upd_block, 0, st, u); break;
+    default: hipLaunchKernelGGL(k_train_update<256>, upd_grid, upd_block, 0, st, u); break;
+  }
   HIPCHK(hipGetLastError());
   return ARGUS_OK;
 }
@@ -871,10 +1463,12 @@ int argus_mlp_create(int32_t d_in, int32_t width, int64_t max_batch, argus_mlp_t
       (rc = h->ic.alloc(kKin * 8)) || (rc = h->iT.alloc(kKin * kKin * 8)) ||
       (rc = h->x0.alloc(B * kKin * 2)) || (rc = h->x0T.alloc(B * kKin * 2)) ||
       (rc = h->t.alloc(B * 4)) || (rc = h->dout.alloc(B * 4)) || (rc = h->sq.alloc(B * 4)) ||
-      (rc = h->g.alloc(h->n * 4)) || (rc = h->wpart.alloc(kWgradSplits * w * w * 4)))
+      (rc = h->g.alloc(h->n * 4)) || (rc = h->wpart.alloc(kWgradSplits * w * w * 4)) ||
+      (rc = h->tpart.alloc((B / kTrainRows) * (4 * w + 2) * 4)))
     return rc;
   if (w <= kFusedMaxWidth &&
-      ((rc = h->w2F.alloc(w * w * 2)) || (rc = h->w3F.alloc(w * w * 2))))
+      ((rc = h->w2F.alloc(w * w * 2)) || (rc = h->w3F.alloc(w * w * 2)) ||
+       (rc = h->w2TF.alloc(w * w * 2)) || (rc = h->w3TF.alloc(w * w * 2))))
     return rc;
   for (int l = 0; l < 3; ++l)
     if ((rc = h->z[l].alloc(B * w * 4)) || (rc = h->a[l].alloc(B * w * 2)) ||
@@ -1006,6 +1600,9 @@ int argus_mlp_grad(argus_mlp_t h, const double* theta, const double* target, int
     return fail(ARGUS_E_INVAL, "batch must be a multiple of 64 and <= max_batch");
   if (!theta || !target || !loss_out) return fail(ARGUS_E_INVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
+  if (h->width <= kFusedMaxWidth)
+    return train_fused(h, theta, target, nullptr, B, nullptr, nullptr, nullptr, false, 0.f, 0,
+                       grad_out ? grad_out : h->g.as<float>(), loss_out, st);
   if ((rc = mlp_backprop(h, theta, target, B, loss_out, st))) return rc;
   if (grad_out)
     HIPCHK(hipMemcpyAsync(grad_out, h->g.p, h->n * 4, hipMemcpyDeviceToDevice, st));
@@ -1019,8 +1616,39 @@ int argus_surrogate_train_step(argus_mlp_t h, float* master, float* adam_m, floa
   if (rc) return rc;
   if (!master || !adam_m || !adam_v) return fail(ARGUS_E_INVAL, "NULL argument");
   if (step < 1) return fail(ARGUS_E_INVAL, "step counts from 1");
+  if (h->width <= kFusedMaxWidth) {
+    if (!h->loaded) return fail(ARGUS_E_INVAL, "weights not loaded");
+    if (B < 64 || B % 64 || B > h->max_batch)
+      return fail(ARGUS_E_INVAL, "batch must be a multiple of 64 and <= max_batch");
+    if (!theta || !target || !loss_out) return fail(ARGUS_E_INVAL, "NULL argument");
+    return train_fused(h, theta, target, nullptr, B, master, adam_m, adam_v, true, lr, step,
+                       h->g.as<float>(), loss_out, (hipStream_t)stream);
+  }
   if ((rc = argus_mlp_grad(h, theta, target, B, nullptr, loss_out, stream))) return rc;
   return refresh(h, master, adam_m, adam_v, true, lr, step, (hipStream_t)stream);
+}
+
+int argus_surrogate_train_epoch(argus_mlp_t h, float* master, float* adam_m, float* adam_v,
+                                const double* theta, const double* target,
+                                const int32_t* order, int64_t n_batches, int64_t B, float lr,
+                                int64_t step0, float* loss_out, void* stream) {
+  int rc = check_mlp(h);
+  if (rc) return rc;
+  if (h->width > kFusedMaxWidth)
+    return fail(ARGUS_E_UNSUPPORTED, "the epoch entry point covers widths up to 256");
+  if (!h->loaded) return fail(ARGUS_E_INVAL, "weights not loaded");
+  if (!master || !adam_m || !adam_v || !theta || !target || !order)
+    return fail(ARGUS_E_INVAL, "NULL argument");
+  if (B < 64 || B % 64 || B > h->max_batch)
+    return fail(ARGUS_E_INVAL, "batch must be a multiple of 64 and <= max_batch");
+  if (n_batches < 0 || step0 < 0) return fail(ARGUS_E_INVAL, "bad counts");
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t b = 0; b < n_batches; ++b)
+    if ((rc = train_fused(h, theta, target, order + b * B, B, master, adam_m, adam_v, true, lr,
+                          step0 + b + 1, h->g.as<float>(), loss_out ? loss_out + b : nullptr,
+                          st)))
+      return rc;
+  return ARGUS_OK;
 }
 
 int argus_da_stage1(const double* theta_prop, const double* lo, const double* hi,

@@ -169,6 +169,63 @@ def test_gradient_matches_oracle(A):
         o += n
 
 
+@pytest.mark.parametrize("width,B", [(128, 320), (64, 64), (192, 192), (320, 128)])
+def test_gradient_other_widths_matches_oracle(A, width, B):
+    """The fused training kernels at other widths and batch sizes (several
+    32-row chunks, per-chunk partial sums combined in order), and the
+    general path above width 256."""
+    from oracle import mlp
+    rng = np.random.default_rng(width + B)
+    flat = pi.mlp_weights(D, width, 13)
+    lo, hi = np.zeros(D), np.ones(D)
+    th = rng.uniform(0, 1, size=(B, D))
+    target = rng.normal(size=B)
+    net = A.MLP(D, width, 512)
+    net.load(flat, lo, hi, 0.0, 1.0)
+    g, loss = net.grad(dev(th), dev(target))
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = mlp.loss_and_grad(flat, mlp.standardise_inputs(th, lo, hi), target, D, width,
+                                   emulate=True)
+    assert abs(loss.item() - lref) <= 1e-2 * lref
+    o = 0
+    for name, shape in mlp.layout(D, width):
+        n = int(np.prod(shape))
+        a, b = g[o:o + n], gref[o:o + n]
+        assert (np.abs(a - b) <= 2e-2 * np.abs(b).max() + 1e-2 * np.abs(b)).all(), name
+        o += n
+
+
+def test_epoch_call_equals_single_steps(A):
+    """argus_surrogate_train_epoch (rows gathered through an index list on
+    the device) makes exactly the steps of argus_surrogate_train_step on the
+    same rows, bit for bit."""
+    import torch
+    rng = np.random.default_rng(31)
+    N, B, nb = 1000, 128, 5
+    th = dev(rng.uniform(0, 1, size=(N, D)))
+    y = dev(rng.normal(size=N))
+    order = torch.as_tensor(rng.permutation(N)[:B * nb].astype(np.int32), device="cuda")
+    lo, hi = np.zeros(D), np.ones(D)
+    nets = []
+    for _ in range(2):
+        net = A.MLP(D, W, 512)
+        net.load(pi.mlp_weights(D, W, 17), lo, hi, 0.1, 1.3)
+        nets.append(net)
+    losses = torch.empty(nb, dtype=torch.float32, device="cuda")
+    nets[0].train_epoch(th, y, order, B, 1e-3, losses)
+    step_losses = []
+    for b in range(nb):
+        sel = order[b * B:(b + 1) * B].long()
+        step_losses.append(nets[1].train_step(th[sel].contiguous(), y[sel].contiguous(),
+                                              1e-3).item())
+    torch.cuda.synchronize()
+    assert torch.equal(nets[0].master, nets[1].master)
+    assert torch.equal(nets[0].m, nets[1].m) and torch.equal(nets[0].v, nets[1].v)
+    assert np.array_equal(losses.cpu().numpy(), np.array(step_losses, np.float32))
+    q = dev(rng.uniform(0, 1, size=(300, D)))
+    assert torch.equal(nets[0].eval(q), nets[1].eval(q))
+
+
 def test_adam_step_matches_oracle(A):
     import torch
     from oracle import mlp
