@@ -1010,18 +1010,18 @@ struct DA1Args {
   int64_t Q;
   int d;
   int32_t* block_cnt;   // [nblocks]
-  int32_t* block_off;   // [nblocks]
   int32_t* idx;         // [Q] compacted survivors
   int32_t* count;       // [1]
   int32_t* flag1;       // [Q] stage-1 decision
 };
 
-// Stage-1 compaction in three launches with no serial loop: per block, the
-// survivors' count from one ballot per wave; one block scans the block
-// counts (in chunks of 1024 with a carry); per block, each survivor's slot
-// is the block's offset plus the survivors in earlier waves of the block
-// plus those in lower lanes of its own wave (mbcnt). The order of the
-// survivors is their chain order.
+// Stage-1 compaction in two launches: per block, the survivors' count from
+// one ballot per wave; then per block, its offset as the sum of the earlier
+// blocks' counts (all threads of the block share the loads; an integer sum,
+// so its order does not matter), and each survivor's slot is that offset
+// plus the survivors in earlier waves of the block plus those in lower
+// lanes of its own wave (mbcnt). The last block also writes the total. The
+// order of the survivors is their chain order.
 constexpr int kScanWaves = kScanBlock / 64;
 
 __device__ __forceinline__ int lanes_below(uint64_t m) {
@@ -1047,47 +1047,36 @@ __global__ void __launch_bounds__(kScanBlock) k_da1_count(DA1Args a) {
   }
 }
 
-// exclusive prefix of the block counts, one block of 1024 threads
-__global__ void __launch_bounds__(1024) k_da1_scan(DA1Args a, int nblocks) {
-  __shared__ int s_w[16];
-  __shared__ int s_carry;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  if (t == 0) s_carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nblocks; base += 1024) {
-    const int b = base + t;
-    const int v = b < nblocks ? a.block_cnt[b] : 0;
-    int x = v;  // inclusive scan within the wave
+__global__ void __launch_bounds__(kScanBlock) k_da1_write(DA1Args a, int nblocks) {
+  __shared__ int s_cnt[kScanWaves], s_part[kScanWaves];
+  const int t = threadIdx.x, w = t >> 6;
+  int part = 0;
+  for (int b = t; b < (int)blockIdx.x; b += kScanBlock) part += a.block_cnt[b];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) s_w[w] = x;
-    __syncthreads();
-    int before = s_carry;
-    for (int q = 0; q < w; ++q) before += s_w[q];
-    if (b < nblocks) a.block_off[b] = before + x - v;
-    __syncthreads();
-    if (t == 1023) s_carry = before + x;
-    __syncthreads();
-  }
-  if (t == 0) *a.count = s_carry;
-}
-
-__global__ void __launch_bounds__(kScanBlock) k_da1_write(DA1Args a) {
-  __shared__ int s_cnt[kScanWaves];
-  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + t;
   const int ok = i < a.Q ? a.flag1[i] : 0;
   const uint64_t m = __builtin_amdgcn_ballot_w64(ok != 0);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) s_cnt[w] = __builtin_popcountll(m);
+  if ((t & 63) == 0) {
+    s_part[w] = part;
+    s_cnt[w] = __builtin_popcountll(m);
+  }
   __syncthreads();
+  int off = 0;
+#pragma unroll
+  for (int q = 0; q < kScanWaves; ++q) off += s_part[q];
+  if ((int)blockIdx.x == nblocks - 1 && t == 0) {
+    int tot = off;
+    for (int q = 0; q < kScanWaves; ++q) tot += s_cnt[q];
+    *a.count = tot;
+  }
   if (!ok) return;
-  int before = a.block_off[blockIdx.x] + lanes_below(m);
+  int before = off + lanes_below(m);
   for (int q = 0; q < w; ++q) before += s_cnt[q];
   a.idx[before] = (int32_t)i;
 }
+
+__global__ void k_da1_none(int32_t* count) { *count = 0; }
 
 __global__ void k_gather_rows(const double* src, const int32_t* idx, const int32_t* count,
                               int64_t cap, int d, double* dst) {
@@ -1659,23 +1648,18 @@ int argus_da_stage1(const double* theta_prop, const double* lo, const double* hi
   hipStream_t st = (hipStream_t)stream;
   const int nb = (int)blocks(Q, kScanBlock);
   if (Q == 0) {
-    hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(1024), 0, st,
-                       DA1Args{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d,
-                               nullptr, nullptr, nullptr, count, nullptr},
-                       0);
+    hipLaunchKernelGGL(k_da1_none, dim3(1), dim3(1), 0, st, count);
     HIPCHK(hipGetLastError());
     return ARGUS_OK;
   }
   if (!theta_prop || !lo || !hi || !lh_cur || !lh_prop || !logu1 || !idx || !work)
     return fail(ARGUS_E_INVAL, "NULL argument");
-  // work = [stage-1 flags (Q) | per-block counts (nb) | per-block offsets (nb)]
+  // work = [stage-1 flags (Q) | per-block counts (nb) | (unused, nb)]
   DA1Args a{theta_prop, lo, hi, lh_cur, lh_prop, logu1, Q, d,
-            work + Q, work + Q + nb, idx, count, work};
+            work + Q, idx, count, work};
   hipLaunchKernelGGL(k_da1_count, dim3(nb), dim3(kScanBlock), 0, st, a);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_da1_scan, dim3(1), dim3(1024), 0, st, a, nb);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_da1_write, dim3(nb), dim3(kScanBlock), 0, st, a);
+  hipLaunchKernelGGL(k_da1_write, dim3(nb), dim3(kScanBlock), 0, st, a, nb);
   HIPCHK(hipGetLastError());
   return ARGUS_OK;
 }
