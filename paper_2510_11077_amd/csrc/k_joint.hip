@@ -33,20 +33,23 @@
 // overlaps across waves) per parameter sample; P0 (full n x n, FP64) and the
 // block's work arrays live in LDS (~145 KB). Per block of kB TOAs, three
 // barriers:
-//   A  all waves: G (n x kB) and the lower triangle of Sigma_B from the 4x4
-//      pulsar blocks of P0.
+//   A  all waves: G (n x kB) and the full Sigma_B from the 4x4 pulsar
+//      blocks of P0, and the last column of every elimination row (the
+//      negated predicted mean of a state row, the residual of a TOA row),
+//      so that the elimination waves load their rows without divergence.
 //   C  waves 0-1: the elimination in registers. Lanes 0-15 of each wave hold
 //      the rows of Sigma_B with the residual, lanes 16-63 hold 48 rows of G
 //      with the predicted mean; pivot, innovation and the
 //      pivot column reach every lane by v_readlane, so the whole
 //      factorisation runs without LDS round trips or barriers.
-//      Waves on the other two SIMDs: P0 <- A_end P0 A_end^T + Qacc_end on
-//      the lower triangle (4-row column segments, consecutive lanes on
-//      consecutive columns), the log-likelihood ledger of the previous block
-//      (pivots and innovations left in LDS by the elimination), the per-TOA
-//      constants of the block after next (elapsed times, decays) from records
-//      staged in LDS with the global loads of the records of the block after
-//      that, and the noise part of the next block's Sigma_B.
+//      Waves 5, 9, 13 (beside wave 1): the noise part of the next block's
+//      Sigma_B. Waves on the other two SIMDs: P0 <- A_end P0 A_end^T +
+//      Qacc_end on the lower triangle (4-row column segments, consecutive
+//      lanes on consecutive columns), the log-likelihood ledger of the
+//      previous block (pivots and innovations left in LDS by the
+//      elimination), the per-TOA constants of the block after next (elapsed
+//      times, decays) from records staged in LDS with the global loads of the
+//      records of the block after that.
 //   D  all waves: P -= U M^T on MFMA tiles (lower tiles, mirrored).
 // The final block is padded to kB with identity rows of Sigma_B, zero
 // residuals and zero columns of G: their pivots are exactly 1 and their
@@ -75,13 +78,15 @@ static_assert(2 * kGRows >= kNPad, "two elimination waves cover every row");
 static_assert(kGRows % 4 == 0, "a pulsar's four rows stay in one wave");
 static_assert(kThreads / 16 * 2 >= kNPad * kB / 16, "phase A covers G in two passes");
 
-// Work of phase C by wave (SIMD = wave % 4): the elimination owns SIMDs 0
-// and 1 (its waves 0, 1; the other waves there stay idle in C so as not to
-// take its issue slots); SIMDs 2 and 3 take the rest.
+// Work of phase C by wave (SIMD = wave % 4): the elimination on waves 0 and
+// 1 (SIMDs 0 and 1; waves 4, 8, 12 beside wave 0 stay idle in C so as not to
+// take its issue slots, the longer of the two); the noise part of the next
+// block's Sigma_B on waves 5, 9, 13 beside wave 1; SIMDs 2 and 3 take the
+// rest.
 constexpr int kWLedger = 2;      // ledger of the previous block
 constexpr int kWToa = 3;         // per-TOA constants two blocks ahead, records
 __device__ __forceinline__ int pairs_slot(int w) {      // -1: not a pairs wave
-  return w == 7 ? 0 : w == 11 ? 1 : w == 15 ? 2 : -1;
+  return w == 5 ? 0 : w == 9 ? 1 : w == 13 ? 2 : -1;
 }
 constexpr int kTfWaves = 6;      // transform: waves 6, 10, 14 and 7, 11, 15
 constexpr int kTfRounds = 3;     // units per lane (2 P (P + 1) <= kTfRounds * 384)
@@ -174,11 +179,13 @@ __device__ __forceinline__ double decay_ratio(double ek, double iej, double ej, 
 
 __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   __shared__ double sP[kNPad * kLdP];      // covariance at the block start
-  __shared__ double sG[kNPad * kLdB];      // G = Cov(x_end, y_block)
+  // rows of the elimination: G = Cov(x_end, y_block) (rows 0 .. kNPad - 1,
+  // zero past n) and the full symmetric Sigma_B (rows kNPad .. kNPad + kB - 1)
+  __shared__ double sG[(kNPad + kB) * kLdB];
+  __shared__ double s_slot[kNPad + kB];    // their last column: -predicted mean, residual
   __shared__ double sU[(kNPad + kB) * kLdB];  // eliminated columns u_k
   __shared__ double sM[(kNPad + kB) * kLdB];  // u_k / S_k
   // (rows kNPad.. take the stores of the Sigma_B lanes, which are not read)
-  __shared__ double sS[kB * kLdB];         // Sigma_B, lower triangle
   __shared__ double sx[2][kNPad + kB];     // mean, double-buffered by block
   __shared__ double s_rec[kNBuf][kB][8];   // staged TOA records
   __shared__ double s_led[2][kB][2];       // pivots S_k and innovations e_k
@@ -201,7 +208,7 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   const double* recd = reinterpret_cast<const double*>(a.rec);
 
   for (int i = tid; i < kNPad * kLdP; i += kThreads) sP[i] = 0.0;
-  for (int i = tid; i < kNPad * kLdB; i += kThreads) sG[i] = 0.0;
+  for (int i = tid; i < (kNPad + kB) * kLdB; i += kThreads) sG[i] = 0.0;
   for (int i = tid; i < (kNPad + kB) * kLdB; i += kThreads) sU[i] = sM[i] = 0.0;
   for (int i = tid; i < 2 * (kNPad + kB); i += kThreads) (&sx[0][0])[i] = 0.0;
   for (int i = tid; i < P * P; i += kThreads) s_hd[i] = a.hd[i];
@@ -263,6 +270,10 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   }
   int sk = 0, sj = 0;  // phase A: Sigma_B entry of threads kSig0 .. kSig0 + kPairs
   constexpr int kSig0 = kThreads / 2;
+  // phase A: the elimination rows' last column by threads kSlot0 .. (they
+  // have no G entry in the second pass)
+  constexpr int kSlot0 = 3 * kThreads / 4;
+  static_assert(kThreads - kSlot0 >= kNPad + kB && 16 * 3 + 64 >= kNPad, "slot threads");
   if (tid >= kSig0 && tid < kSig0 + kPairs) pair_of(tid - kSig0, sk, sj);
   int pk = 0, pj = 0;  // pairs waves: one noise pair per lane
   const int pe = psl >= 0 ? lane + kWave * psl : kPairs;
@@ -471,35 +482,41 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
         w[c] = r[0] + t1 * r[1] + g1 * r[2] + c1 * r[3];
       }
       const double v = w[0] + t2 * w[1] + g2 * w[2] + c2 * w[3];
-      sS[sk * kLdB + sj] = sk < nb ? sn + v : sn;
+      const double val = sk < nb ? sn + v : sn;
+      sG[(kNPad + sk) * kLdB + sj] = val;
+      sG[(kNPad + sj) * kLdB + sk] = val;
+    }
+    // the last column of every elimination row: the negated predicted mean
+    // of the state rows, the residual of the TOA rows
+    if (tid >= kSlot0 && tid < kSlot0 + kNPad + kB) {
+      const int row = tid - kSlot0;
+      const double* x0 = sx[xb];
+      double sl = 0.0;
+      if (row >= kNPad) {
+        const int k = row - kNPad;
+        if (k < nb) {
+          const double* xp = x0 + 4 * bc.p[k];
+          sl = bc.y[k] - (xp[0] + bc.tau[k] * xp[1] + bc.eg[k] * xp[2] + bc.ec[k] * xp[3]);
+        }
+      } else if (row < n) {
+        const int q = row >> 2, c = row & 3;
+        const int r1 = c == 0 ? row + 1 : row;
+        const double mA = c == 2 ? bc.eqe[q] : (c == 3 ? ec_e : 1.0);
+        const double mB = c == 0 ? tau_e : 0.0;
+        sl = -fma(mB, x0[r1], mA * x0[row]);
+      }
+      s_slot[row] = sl;
     }
     __syncthreads();
     // ---- C.
-    const double* x0 = sx[xb];
     if (wave < 2) {
-      // load: Sigma_B row + residual (lanes < kB) or a row of G + predicted
-      // mean, stored negated so that both kinds of row eliminate alike
-      double v[kB], slot;
+      // load a row of Sigma_B (lanes < kB) or of G with its last column
+      double v[kB];
       const bool sig = lane < kB;
       const int row = sig ? kNPad + lane : kGRows * wave + lane - kB;
-      if (sig) {
-        const int k = lane;
 #pragma unroll
-        for (int j = 0; j < kB; ++j) v[j] = sS[(j <= k ? k * kLdB + j : j * kLdB + k)];
-        const int pk2 = bc.p[k < nb ? k : 0];
-        const double* xp = x0 + 4 * pk2;
-        const double r = bc.y[k] - (xp[0] + bc.tau[k] * xp[1] + bc.eg[k] * xp[2] + bc.ec[k] * xp[3]);
-        slot = k < nb ? r : 0.0;
-      } else {
-        const bool live = row < n;
-        const int q = live ? row >> 2 : 0, c = row & 3;
-        const int r1 = c == 0 ? row + 1 : row;
-        const double mA = !live ? 0.0 : c == 2 ? bc.eqe[q] : (c == 3 ? ec_e : 1.0);
-        const double mB = live && c == 0 ? tau_e : 0.0;
-#pragma unroll
-        for (int j = 0; j < kB; ++j) v[j] = sG[(live ? row : 0) * kLdB + j] * (live ? 1.0 : 0.0);
-        slot = -fma(mB, x0[r1], mA * x0[row]);
-      }
+      for (int j = 0; j < kB; ++j) v[j] = sG[row * kLdB + j];
+      double slot = s_slot[row];
       // elimination in TOA order
       double dk = 1.0, ek = 0.0;
 #pragma unroll
@@ -542,8 +559,9 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
         s_rec[cb][lane >> 2][2 * (lane & 3)] = r0;
         s_rec[cb][lane >> 2][2 * (lane & 3) + 1] = r1;
       }
+    } else if (psl >= 0) {
+      if (k0 + kB < N) pairs_part((int)((b + 1) % kNBuf));
     } else if (tsl >= 0) {
-      if (psl >= 0 && k0 + kB < N) pairs_part((int)((b + 1) % kNBuf));
       // P0 <- A_end P0 A_end^T + Qacc_end on the lower triangle of 4x4
       // pulsar blocks (the downdate below rewrites the upper triangle from
       // the lower); consecutive lanes take consecutive columns, the column
