@@ -604,7 +604,7 @@ def main():
             "plain_gpu": "not available for the joint model"}
         log("joint HD: %.3f ms/call, %.4g evals/s" % (ms3, S3 / (ms3 * 1e-3)))
 
-        # gradient (adjoint filter), 1024 samples of the 47-pulsar data
+        # gradient (tuned tangent sweep), 1024 samples of the 47-pulsar data
         S4 = pi.N_SAMPLES["cfg4"]
         t4 = torch.as_tensor(pi.sample_theta(d, S4, pi.THETA_SEED["cfg4"]), dtype=torch.float64,
                              device=dev)
@@ -617,7 +617,9 @@ def main():
             plan4 = int(d.n_toa) * S4 * FLOP_PER_STEP_GRAD_PLAN / (ms4 * 1e-3) / 1e12
             extra["grad_47psr_1024samples"] = {
                 "ms_per_call": ms4, "evals_per_s": S4 / (ms4 * 1e-3),
-                "sweep": "tangent (forward-mode), tuned split",
+                "sweep": "tangent (forward-mode): " + next(
+                    (ln.split(": ", 1)[1] for ln in ds.tune_info(S4).split("\n")
+                     if ln.startswith("gradient:")), "tuned split"),
                 "roofline": {"bound": "alu", "achieved": plan4, "peak": FP64_PEAK_TFLOPS,
                              "unit": "TFLOP/s", "frac": plan4 / FP64_PEAK_TFLOPS,
                              "flop_per_step": FLOP_PER_STEP_GRAD_PLAN,

@@ -669,7 +669,12 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
     s = b + w->tune_log;
   }
   if (w && w->tan_nda) {
-    if (w->tan_nda == w->tan_ndb)
+    if (w->tan_thresh < 0)
+      std::snprintf(b, sizeof b,
+                    "gradient: tangent sweep, producer/consumer form (one base-filter wave, "
+                    "%d waves of %d directions per item)\n",
+                    6 / w->tan_nda, w->tan_nda);
+    else if (w->tan_nda == w->tan_ndb)
       std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nda);
     else
       std::snprintf(b, sizeof b,

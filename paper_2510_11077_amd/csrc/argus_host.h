@@ -86,8 +86,9 @@ struct Workspace {
   int max_sub = 0, grad_waves = 0;
   bool grad_ready = false;
   // tangent-mode gradient: directions per wave, tan_nda for pulsars of at
-  // least tan_thresh TOAs and tan_ndb for the others (0 = not tuned yet),
-  // and the work units of the split they were built for
+  // least tan_thresh TOAs and tan_ndb for the others (0 = not tuned yet;
+  // tan_thresh < 0: the producer/consumer form of model 2), and the work
+  // units of the split they were built for
   int tan_nda = 0, tan_ndb = 0;
   int64_t tan_thresh = 0;
   DevBuf tan_units;

@@ -749,6 +749,240 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
   }
 }
 
+// Producer/consumer form of the model-2 tangent sweep: one workgroup of
+// 1 + 6 / NDC waves per (64-sample tile, pulsar) item. Wave 0 runs the base
+// filter once and hands, for every TOA, what the differentiated step needs
+// from it (the red decay, the previous posterior's xa and a column, the
+// gain, the innovation and 1/S: kPcVals values per lane) to the other waves
+// through a double-buffered ring in LDS of kPcSteps TOAs per buffer; wave w
+// carries directions NDC (w - 1) .. NDC w - 1 of the pulsar's six. The base
+// filter then runs once per item instead of once per direction group, and
+// the serial chain of a TOA is the longer of the base step and an
+// NDC-direction tangent step instead of their sum. Barrier b of the item
+// separates the producer's writes of block b from the consumers' reads of
+// it (in the next round) and their reads of block b - 1 from the producer's
+// rewrite of that buffer; all four waves execute nblk + 1 barriers. The
+// arithmetic of each step is that of tangent_unit.
+constexpr int kPcSteps = 4;
+constexpr int kPcVals = 12;
+
+template <int NDC>
+__global__ void __launch_bounds__(kWave * (1 + 6 / NDC)) k_tangent_pc(TanArgs a) {
+  __shared__ double s_ring[2 * kPcSteps * kPcVals * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const RecPtr rec = (RecPtr)a.rec;
+  const int item = blockIdx.x;
+  const int tile = a.items[2 * item], p = a.items[2 * item + 1];
+  const int64_t s_raw = (int64_t)tile * kWave + lane;
+  const bool valid = s_raw < a.S;
+  const int64_t s = valid ? s_raw : a.S - 1;
+  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+  const int nblk = (N + kPcSteps - 1) / kPcSteps;
+  double* ring = s_ring + lane;  // value v of step j of buffer b at ((b kPcSteps + j) kPcVals + v) kWave
+
+  const int c0 = 4 * p, cc = 4 * a.P;
+  const double t0 = tprm(a, c0, s), t1 = tprm(a, c0 + 1, s), t2 = tprm(a, c0 + 2, s);
+  const double t3 = tprm(a, c0 + 3, s), t4 = tprm(a, cc, s), t5 = tprm(a, cc + 1, s);
+  const double gr = exp10(t1);
+  const double sr = exp10(t0), eq = exp10(t3);
+  const double vr = sr * sr / (2.0 * gr);
+  const double gm1 = t5 - 1.0;
+  const double vc = exp(2.0 * kLn10 * t4 + (t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+                    (12.0 * kPi * kPi * gm1);
+
+  if (wave == 0) {
+    // ---- the base filter (the base part of tangent_unit, model 2)
+    const bool pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) &&
+                       finite_d(t4) && finite_d(t5));
+    const double efac2 = t2 * t2, equad2 = eq * eq;
+    const double ss2 = in_vgpr(a.mc.ss2);
+    State st{0.0, 0.0, 0.0, 0.0,
+             Cov4{a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, 0.0, vr, 0.0, 0.0, 0.0, vc}};
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+    const double c13 = in_vgpr(kExpm1Coef[11]);
+    TOARec r1{}, r2{};
+    double em1 = 0.0;
+    if (N > 0) {
+      r1 = load_rec(rec, kb);
+      r2 = load_rec(rec, kb + (N > 1 ? 1 : 0));
+      em1 = expm1_v(-gr * r1.dt, c13);
+    }
+    for (int blk = 0; blk <= nblk; ++blk) {
+      double* rb = ring + (blk & 1) * kPcSteps * kPcVals * kWave;
+      for (int j = 0; j < kPcSteps && blk < nblk; ++j) {
+        const int k = blk * kPcSteps + j;
+        if (k >= N) break;
+        const TOARec r = r1;
+        const double em = em1;
+        r1 = r2;
+        sgpr_ready(r1.dt);
+        r2 = load_rec(rec, kb + (k < N - 2 ? k + 2 : N - 1));
+        em1 = expm1_v(-gr * r1.dt, c13);
+        const double dt = r.dt, phc = r.phc;
+        const double ph = 1.0 + em, qfac = -em * (2.0 + em);
+        const Cov4& Q0 = st.P;
+        double* rv = rb + j * kPcVals * kWave;
+        rv[0 * kWave] = em;
+        rv[1 * kWave] = st.xa;
+        rv[2 * kWave] = Q0.ra;
+        rv[3 * kWave] = Q0.fa;
+        rv[4 * kWave] = Q0.aa;
+        rv[5 * kWave] = Q0.ag;
+        Cov4 Pm;
+        const double prf1 = fma(dt, Q0.ff, Q0.rf);
+        Pm.rr = fma(dt, Q0.rf + prf1, Q0.rr) + ss2 * r.h3;
+        Pm.rf = prf1 + ss2 * r.h2;
+        Pm.ff = Q0.ff + ss2 * dt;
+        Pm.ra = ph * fma(dt, Q0.fa, Q0.ra);
+        Pm.fa = ph * Q0.fa;
+        Pm.aa = fma(ph * ph, Q0.aa, vr * qfac);
+        Pm.rg = phc * fma(dt, Q0.fg, Q0.rg);
+        Pm.fg = phc * Q0.fg;
+        Pm.ag = (ph * phc) * Q0.ag;
+        Pm.gg = fma(phc * phc, Q0.gg, vc * r.qcu);
+        const double xr = fma(dt, st.xf, st.xr), xf = st.xf, xa = ph * st.xa, xg = phc * st.xg;
+        const double e = r.y - (xr + xa + xg);
+        const double ur = Pm.rr + Pm.ra + Pm.rg, uf = Pm.rf + Pm.fa + Pm.fg;
+        const double ua = Pm.ra + Pm.aa + Pm.ag, ug = Pm.rg + Pm.ag + Pm.gg;
+        const double S = (ur + ua + ug) + fma(efac2, r.s2, equad2);
+        const double inv = rcp_nr(S);
+        const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
+        const double ei = e * inv;
+        rv[6 * kWave] = kr;
+        rv[7 * kWave] = kf;
+        rv[8 * kWave] = ka;
+        rv[9 * kWave] = kg;
+        rv[10 * kWave] = e;
+        rv[11 * kWave] = inv;
+        st.xr = fma(kr, e, xr);
+        st.xf = fma(kf, e, xf);
+        st.xa = fma(ka, e, xa);
+        st.xg = fma(kg, e, xg);
+        const double dr = fma(S, kr, -ur), df = fma(S, kf, -uf);
+        const double da = fma(S, ka, -ua), dg = fma(S, kg, -ug);
+        JOSEPH(Pm.rr, kr, ur, dr, kr);
+        JOSEPH(Pm.rf, kr, uf, dr, kf);
+        JOSEPH(Pm.ff, kf, uf, df, kf);
+        JOSEPH(Pm.ra, kr, ua, dr, ka);
+        JOSEPH(Pm.fa, kf, ua, df, ka);
+        JOSEPH(Pm.aa, ka, ua, da, ka);
+        JOSEPH(Pm.rg, kr, ug, dr, kg);
+        JOSEPH(Pm.fg, kf, ug, df, kg);
+        JOSEPH(Pm.ag, ka, ug, da, kg);
+        JOSEPH(Pm.gg, kg, ug, dg, kg);
+        st.P = Pm;
+        const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+        if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+        quad = fma(e, ei, quad);
+        const double pm = lm * S;
+        lm = __builtin_amdgcn_frexp_mant(pm);
+        le += __builtin_amdgcn_frexp_exp(pm);
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+      if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+      a.part[(int64_t)p * a.S + s] = stat ? -INFINITY : ll;
+      a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+  } else {
+    // ---- NDC directions per wave (the tangent part of tangent_unit)
+    constexpr int ND = NDC;
+    const int grp = wave - 1;
+    const double equad2 = eq * eq;
+    double sv[ND], sg[ND], sc[ND], sr2[ND], sq2[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const int dir = grp * ND + j;
+      sv[j] = dir == 0 ? 2.0 * kLn10 * vr : (dir == 1 ? -kLn10 * vr : 0.0);
+      sg[j] = dir == 1 ? kLn10 * gr : 0.0;
+      sr2[j] = dir == 2 ? 2.0 * t2 : 0.0;
+      sq2[j] = dir == 3 ? 2.0 * kLn10 * equad2 : 0.0;
+      sc[j] = dir == 4 ? 2.0 * kLn10 * vc
+                       : (dir == 5 ? vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / gm1) : 0.0);
+    }
+    Tan tg[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      tg[j] = Tan{0.0, 0.0, 0.0, 0.0, Cov4{0, 0, 0, 0, 0, sv[j], 0, 0, 0, sc[j]}, 0.0};
+    for (int blk = 0; blk <= nblk; ++blk) {
+      const double* rb = ring + ((blk - 1) & 1) * kPcSteps * kPcVals * kWave;
+#pragma unroll 1
+      for (int jj = 0; jj < kPcSteps && blk > 0; ++jj) {
+        const int k = (blk - 1) * kPcSteps + jj;
+        if (k >= N) break;
+        const TOARec r = load_rec(rec, kb + k);
+        const double* rv = rb + jj * kPcVals * kWave;
+        const double em = rv[0 * kWave], xa0 = rv[1 * kWave];
+        const double qra = rv[2 * kWave], qfa = rv[3 * kWave], qaa = rv[4 * kWave],
+                     qag = rv[5 * kWave];
+        const double kr = rv[6 * kWave], kf = rv[7 * kWave], ka = rv[8 * kWave],
+                     kg = rv[9 * kWave];
+        const double e = rv[10 * kWave], inv = rv[11 * kWave];
+        const double dt = r.dt, phc = r.phc;
+        const double ph = 1.0 + em, qfac = -em * (2.0 + em);
+        const double fpra = fma(dt, qfa, qra), fpfa = qfa, fpaa = ph * qaa, fpga = phc * qag;
+        const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+          Tan& d = tg[j];
+          const double dph = -dt * ph * sg[j];
+          const double dqa = fma(sv[j], qfac, -2.0 * vr * ph * dph);
+          const double dxr = fma(dt, d.xf, d.xr), dxf = d.xf;
+          const double dxa = fma(ph, d.xa, dph * xa0), dxg = phc * d.xg;
+          const Cov4& D0 = d.P;
+          Cov4 Dm;
+          const double drf1 = fma(dt, D0.ff, D0.rf);
+          Dm.rr = fma(dt, D0.rf + drf1, D0.rr);
+          Dm.rf = drf1;
+          Dm.ff = D0.ff;
+          Dm.ra = fma(ph, fma(dt, D0.fa, D0.ra), dph * fpra);
+          Dm.fa = fma(ph, D0.fa, dph * fpfa);
+          Dm.aa = fma(ph * ph, D0.aa, fma(2.0 * dph, fpaa, dqa));
+          Dm.rg = phc * fma(dt, D0.fg, D0.rg);
+          Dm.fg = phc * D0.fg;
+          Dm.ag = fma(ph * phc, D0.ag, dph * fpga);
+          Dm.gg = fma(phc * phc, D0.gg, sc[j] * r.qcu);
+          const double de = -(dxr + dxa + dxg);
+          const double dur = Dm.rr + Dm.ra + Dm.rg, duf = Dm.rf + Dm.fa + Dm.fg;
+          const double dua = Dm.ra + Dm.aa + Dm.ag, dug = Dm.rg + Dm.ag + Dm.gg;
+          const double dS = (dur + dua + dug) + fma(sr2[j], r.s2, sq2[j]);
+          const double dkr = (dur - kr * dS) * inv, dkf = (duf - kf * dS) * inv;
+          const double dka = (dua - ka * dS) * inv, dkg = (dug - kg * dS) * inv;
+          d.xr = fma(dkr, e, fma(kr, de, dxr));
+          d.xf = fma(dkf, e, fma(kf, de, dxf));
+          d.xa = fma(dka, e, fma(ka, de, dxa));
+          d.xg = fma(dkg, e, fma(kg, de, dxg));
+#define TAN_UPD(dp, ki, dui, kj, duj) dp = fma(dS * (ki), kj, fma(-(dui), kj, fma(-(ki), duj, dp)))
+          TAN_UPD(Dm.rr, kr, dur, kr, dur);
+          TAN_UPD(Dm.rf, kr, dur, kf, duf);
+          TAN_UPD(Dm.ff, kf, duf, kf, duf);
+          TAN_UPD(Dm.ra, kr, dur, ka, dua);
+          TAN_UPD(Dm.fa, kf, duf, ka, dua);
+          TAN_UPD(Dm.aa, ka, dua, ka, dua);
+          TAN_UPD(Dm.rg, kr, dur, kg, dug);
+          TAN_UPD(Dm.fg, kf, duf, kg, dug);
+          TAN_UPD(Dm.ag, ka, dua, kg, dug);
+          TAN_UPD(Dm.gg, kg, dug, kg, dug);
+#undef TAN_UPD
+          d.P = Dm;
+          d.dl = fma(-0.5, fma(dS, hS, 2.0 * ei * de), d.dl);
+        }
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      double* g = a.gpart + (int64_t)p * 6 * a.S + s;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) g[(int64_t)(grp * ND + j) * a.S] = tg[j].dl;
+    }
+  }
+}
+
 // Tangent sweep of model 4 (state [r, f, a, g, m], h = [1, 0, 1, 1, c] with
 // the chromatic factor c of each TOA): the same differentiated recursion
 // over five states. dF is diagonal, nonzero at a (red decay, its rate) and
@@ -1426,6 +1660,18 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nda
   a.P = ds->P;
   a.n_items = w->n_items;
   a.mc = ds->mc;
+  if (thresh < 0) {
+    // the producer/consumer form (model 2): one workgroup of 1 + 6 / nda
+    // waves per item
+    if (ds->model != 2 || (nda != 1 && nda != 2))
+      return fail(ARGUS_E_INVAL, "unsupported tangent split");
+    if (nda == 2)
+      hipLaunchKernelGGL(k_tangent_pc<2>, dim3((unsigned)w->n_items), dim3(4 * kWave), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_tangent_pc<1>, dim3((unsigned)w->n_items), dim3(7 * kWave), 0, st, a);
+    HIPCHK(hipGetLastError());
+    return ARGUS_OK;
+  }
   int rc = tangent_units(ds, w, nda, ndb, thresh);
   if (rc) return rc;
   a.units = w->tan_units.as<int32_t>();
@@ -1486,11 +1732,14 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
       (rc = w->gpart.alloc((size_t)ds->P * gstride * S * sizeof(double))))
     return rc;
   if (w->tan_nda == 0) {
-    // a forced split: "nd" (uniform) or "nda,ndb,thresh"
+    // a forced split: "nd" (uniform), "nda,ndb,thresh", or "pc" / "pc1"
+    // (model 2: the producer/consumer form with 2 / 1 directions per wave)
     const char* forced = std::getenv("ARGUS_TAN_ND");
     int fa = 0, fb = 0;
     long long ft = 0;
-    const int nf = forced ? std::sscanf(forced, "%d,%d,%lld", &fa, &fb, &ft) : 0;
+    const bool fpc = forced && ds->model == 2 &&
+                     (std::strcmp(forced, "pc") == 0 || std::strcmp(forced, "pc1") == 0);
+    const int nf = forced && !fpc ? std::sscanf(forced, "%d,%d,%lld", &fa, &fb, &ft) : 0;
     if (nf == 1) fb = fa;
     if (ds->model == 1) fa = fb = 2;
     const bool uni = fa == fb;
@@ -1500,7 +1749,10 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
                                : nf == 3 && ft >= 0 && (fk == 12 || fk == 14 || fk == 24))
                         : (uni ? (fa == 1 || fa == 2 || fa == 3 || fa == 6)
                                : nf == 3 && ft >= 0 && (fk == 12 || fk == 13 || fk == 23));
-    if (ok) {
+    if (fpc) {
+      w->tan_nda = w->tan_ndb = std::strcmp(forced, "pc1") == 0 ? 1 : 2;
+      w->tan_thresh = -1;
+    } else if (ok) {
       w->tan_nda = fa;
       w->tan_ndb = fb;
       w->tan_thresh = uni ? 0 : ft;
@@ -1529,6 +1781,8 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
       for (int64_t t : {nmax / 2, (3 * nmax) / 4, (7 * nmax) / 8})
         for (auto ab : mixed)
           if (t > 0) cand.push_back({ab.first, ab.second, t});
+      if (ds->model == 2)  // producer/consumer forms
+        for (int c : {2, 1}) cand.push_back({c, c, -1});
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
@@ -1549,7 +1803,10 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
         }
         if (rc) break;
         char b[128];
-        if (c.a == c.b)
+        if (c.t < 0)
+          std::snprintf(b, sizeof b, "tangent producer/consumer (base wave + %d x %d directions): %.4f ms\n",
+                        6 / c.a, c.a, m);
+        else if (c.a == c.b)
           std::snprintf(b, sizeof b, "tangent directions per wave %d: %.4f ms\n", c.a, m);
         else
           std::snprintf(b, sizeof b, "tangent directions per wave %d (>= %lld TOAs) / %d: %.4f ms\n",

@@ -158,11 +158,15 @@ def test_grad_repeatable(argus):
     assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
 
 
-@pytest.mark.parametrize("nd", ["1", "2", "3", "6", "1,2,90", "1,3,90", "2,3,3", "1,3,261"])
+@pytest.mark.parametrize("nd", ["1", "2", "3", "6", "1,2,90", "1,3,90", "2,3,3", "1,3,261", "pc", "pc1"])
 def test_tangent_direction_splits(argus, orc, nd, sweep, monkeypatch):
     """The tangent sweep with each split of the six directions over waves:
     uniform, and mixed (fewer directions per wave for pulsars of at least the
-    threshold's TOAs; "1,3,261" puts every pulsar in the second group)."""
+    threshold's TOAs; "1,3,261" puts every pulsar in the second group); "pc"
+    and "pc1" are the producer/consumer forms (the base filter on one wave,
+    its per-TOA values handed through LDS to three waves of two directions,
+    or six of one), here with a pulsar of no TOAs and one of fewer TOAs than
+    a hand-over block."""
     if sweep != "tangent":
         pytest.skip("tangent sweep only")
     monkeypatch.setenv("ARGUS_TAN_ND", nd)
