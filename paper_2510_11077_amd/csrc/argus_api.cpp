@@ -673,7 +673,7 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
       std::snprintf(b, sizeof b,
                     "gradient: tangent sweep, producer/consumer form (one base-filter wave, "
                     "%d waves of %d directions per item)\n",
-                    6 / w->tan_nda, w->tan_nda);
+                    (ds->model == ARGUS_M4_PSR5_DM ? 8 : 6) / w->tan_nda, w->tan_nda);
     else if (w->tan_nda == w->tan_ndb)
       std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nda);
     else

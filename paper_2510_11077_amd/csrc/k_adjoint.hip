@@ -1234,6 +1234,302 @@ __device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, 
 }
 
 // Work units of model 4, as k_tangent: each unit carries NDA or NDB.
+// Producer/consumer form of the model-4 tangent sweep, as k_tangent_pc: one
+// workgroup of 1 + 8 / NDC waves per item; wave 0 runs the 5-state base
+// filter once and hands per TOA the red and DM decays, the previous
+// posterior's a and m states, the a and m columns of F P, the gain, the
+// innovation and 1/S (kPc5Vals values per lane) through a double-buffered
+// LDS ring of kPc5Steps TOAs per buffer to waves of NDC directions each.
+// The arithmetic of each step is that of tangent5_unit.
+constexpr int kPc5Steps = 2;
+constexpr int kPc5Vals = 21;
+
+template <int NDC>
+__global__ void __launch_bounds__(kWave * (1 + 8 / NDC)) k_tangent5_pc(TanArgs a) {
+  constexpr int NS = 5, NP = 15;
+  __shared__ double s_ring[2 * kPc5Steps * kPc5Vals * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const RecPtr rec = (RecPtr)a.rec;
+  const ConstDPtr chrom = (ConstDPtr)a.chrom;
+  const int item = blockIdx.x;
+  const int tile = a.items[2 * item], p = a.items[2 * item + 1];
+  const int64_t s_raw = (int64_t)tile * kWave + lane;
+  const bool valid = s_raw < a.S;
+  const int64_t s = valid ? s_raw : a.S - 1;
+  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+  const int nblk = (N + kPc5Steps - 1) / kPc5Steps;
+  double* ring = s_ring + lane;  // value v of step j of buffer b at ((b kPc5Steps + j) kPc5Vals + v) kWave
+
+  const int c0 = 6 * p, cc = 6 * a.P;
+  const double t0 = tprm(a, c0, s), t1 = tprm(a, c0 + 1, s), t2 = tprm(a, c0 + 2, s);
+  const double t3 = tprm(a, c0 + 3, s), t4 = tprm(a, c0 + 4, s), t5 = tprm(a, c0 + 5, s);
+  const double t6 = tprm(a, cc, s), t7 = tprm(a, cc + 1, s);
+  const double gr = exp10(t1), sr = exp10(t0), eq = exp10(t3);
+  const double gd = exp10(t5), sdm = exp10(t4);
+  const double vr = sr * sr / (2.0 * gr), vd = sdm * sdm / (2.0 * gd);
+  const double gm1 = t7 - 1.0;
+  const double vc = exp(2.0 * kLn10 * t6 + (t7 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+                    (12.0 * kPi * kPi * gm1);
+  const double equad2 = eq * eq;
+
+  if (wave == 0) {
+    // ---- the base filter (the base part of tangent5_unit)
+    const bool pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) &&
+                       finite_d(t4) && finite_d(t5) && finite_d(t6) && finite_d(t7));
+    const double efac2 = t2 * t2, ss2 = a.mc.ss2;
+    double x[NS] = {0.0, 0.0, 0.0, 0.0, 0.0}, P[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[i] = 0.0;
+    P[si5(0, 0)] = a.mc.s_r2;
+    P[si5(1, 1)] = a.mc.s_f2;
+    P[si5(2, 2)] = vr;
+    P[si5(3, 3)] = vc;
+    P[si5(4, 4)] = vd;
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+    const double c13 = in_vgpr(kExpm1Coef[11]);
+    const RecVecPtr recv = (RecVecPtr)a.rec;
+    const ConstDPtr dts = (ConstDPtr)a.rec;
+    RecVec vn{};
+    double cn = 0.0, emn = 0.0, emdn = 0.0, dt2 = 0.0;
+    if (N > 0) {
+      vn = load_rec_v(recv, kb);
+      cn = chrom[kb];
+      dt2 = dts[8 * (int64_t)(kb + (N > 1 ? 1 : 0))];
+      emn = expm1_v(-gr * vn[0], c13);
+      emdn = expm1_v(-gd * vn[0], c13);
+    }
+    for (int blk = 0; blk <= nblk; ++blk) {
+      double* rb = ring + (blk & 1) * kPc5Steps * kPc5Vals * kWave;
+      for (int jj = 0; jj < kPc5Steps && blk < nblk; ++jj) {
+        const int k = blk * kPc5Steps + jj;
+        if (k >= N) break;
+        const RecVec v = vn;
+        const double c = cn, em = emn, emd = emdn, dt1 = dt2;
+        rec_keep(v);
+        sgpr_ready(dt1);
+        const TOARec r = rec_fields(v);
+        const int kn = kb + (k + 1 < N ? k + 1 : k);
+        vn = load_rec_v(recv, kn);
+        cn = chrom[kn];
+        dt2 = dts[8 * (int64_t)(kb + (k < N - 2 ? k + 2 : N - 1))];
+        emn = expm1_v(-gr * dt1, c13);
+        emdn = expm1_v(-gd * dt1, c13);
+        const double dt = r.dt;
+        const double ph = 1.0 + em, phd = 1.0 + emd, phc = r.phc;
+        const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
+        const double dg[NS] = {1.0, 1.0, ph, phc, phd};
+        double FP[NS][NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          FP[0][j] = fma(dt, P[si5(1, j)], P[si5(0, j)]);
+#pragma unroll
+          for (int i = 1; i < NS; ++i) FP[i][j] = dg[i] * P[si5(i, j)];
+        }
+        double* rv = rb + jj * kPc5Vals * kWave;
+        rv[0 * kWave] = em;
+        rv[1 * kWave] = emd;
+        rv[2 * kWave] = x[2];
+        rv[3 * kWave] = x[4];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          rv[(4 + i) * kWave] = FP[i][2];
+          rv[(9 + i) * kWave] = FP[i][4];
+        }
+        double xm[NS], Pm[NP];
+        xm[0] = fma(dt, x[1], x[0]);
+#pragma unroll
+        for (int i = 1; i < NS; ++i) xm[i] = dg[i] * x[i];
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j)
+            Pm[si5(i, j)] = j == 0 ? fma(dt, FP[i][1], FP[i][0]) : dg[j] * FP[i][j];
+        Pm[si5(0, 0)] += ss2 * r.h3;
+        Pm[si5(1, 0)] += ss2 * r.h2;
+        Pm[si5(1, 1)] += ss2 * dt;
+        Pm[si5(2, 2)] = fma(vr, qf, Pm[si5(2, 2)]);
+        Pm[si5(3, 3)] = fma(vc, r.qcu, Pm[si5(3, 3)]);
+        Pm[si5(4, 4)] = fma(vd, qfd, Pm[si5(4, 4)]);
+        const double hw[NS] = {1.0, 0.0, 1.0, 1.0, c};
+        double u[NS], hx = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          double t = 0.0;
+#pragma unroll
+          for (int l = 0; l < NS; ++l)
+            if (h5(l)) t = fma(hw[l], Pm[si5(i, l)], t);
+          u[i] = t;
+          if (h5(i)) hx = fma(hw[i], xm[i], hx);
+        }
+        double hu = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+          if (h5(i)) hu = fma(hw[i], u[i], hu);
+        const double S = hu + fma(efac2, r.s2, equad2);
+        const double e = r.y - hx;
+        const double inv = rcp_nr(S);
+        double K[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          K[i] = u[i] * inv;
+          rv[(14 + i) * kWave] = K[i];
+        }
+        rv[19 * kWave] = e;
+        rv[20 * kWave] = inv;
+        const double ei = e * inv;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) x[i] = fma(K[i], e, xm[i]);
+        double dd[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) dd[i] = fma(S, K[i], -u[i]);
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+          for (int q = 0; q <= i; ++q)
+            P[si5(i, q)] = fma(dd[i], K[q], fma(-K[i], u[q], Pm[si5(i, q)]));
+        const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+        if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+        quad = fma(e, ei, quad);
+        const double pm = lm * S;
+        lm = __builtin_amdgcn_frexp_mant(pm);
+        le += __builtin_amdgcn_frexp_exp(pm);
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+      if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+      a.part[(int64_t)p * a.S + s] = stat ? -INFINITY : ll;
+      a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+  } else {
+    // ---- NDC directions per wave (the tangent part of tangent5_unit)
+    constexpr int ND = NDC;
+    const int grp = wave - 1;
+    double sv[ND], sg[ND], sc[ND], sd[ND], sgd[ND], sr2[ND], sq2[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const int dir = grp * ND + j;
+      sv[j] = dir == 0 ? 2.0 * kLn10 * vr : (dir == 1 ? -kLn10 * vr : 0.0);
+      sg[j] = dir == 1 ? kLn10 * gr : 0.0;
+      sr2[j] = dir == 2 ? 2.0 * t2 : 0.0;
+      sq2[j] = dir == 3 ? 2.0 * kLn10 * equad2 : 0.0;
+      sd[j] = dir == 4 ? 2.0 * kLn10 * vd : (dir == 5 ? -kLn10 * vd : 0.0);
+      sgd[j] = dir == 5 ? kLn10 * gd : 0.0;
+      sc[j] = dir == 6 ? 2.0 * kLn10 * vc
+                       : (dir == 7 ? vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / gm1) : 0.0);
+    }
+    double dx[ND][NS], dP[ND][NP], dl[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) dx[j][i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) dP[j][i] = 0.0;
+      dP[j][si5(2, 2)] = sv[j];
+      dP[j][si5(3, 3)] = sc[j];
+      dP[j][si5(4, 4)] = sd[j];
+      dl[j] = 0.0;
+    }
+    for (int blk = 0; blk <= nblk; ++blk) {
+      const double* rb = ring + ((blk - 1) & 1) * kPc5Steps * kPc5Vals * kWave;
+#pragma unroll 1
+      for (int jj = 0; jj < kPc5Steps && blk > 0; ++jj) {
+        const int k = (blk - 1) * kPc5Steps + jj;
+        if (k >= N) break;
+        const TOARec r = load_rec(rec, kb + k);
+        const double c = chrom[kb + k];
+        const double* rv = rb + jj * kPc5Vals * kWave;
+        const double em = rv[0 * kWave], emd = rv[1 * kWave];
+        const double x2 = rv[2 * kWave], x4 = rv[3 * kWave];
+        double FP2[NS], FP4[NS], K[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          FP2[i] = rv[(4 + i) * kWave];
+          FP4[i] = rv[(9 + i) * kWave];
+          K[i] = rv[(14 + i) * kWave];
+        }
+        const double e = rv[19 * kWave], inv = rv[20 * kWave];
+        const double dt = r.dt;
+        const double ph = 1.0 + em, phd = 1.0 + emd, phc = r.phc;
+        const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
+        const double dg[NS] = {1.0, 1.0, ph, phc, phd};
+        const double hw[NS] = {1.0, 0.0, 1.0, 1.0, c};
+        const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);
+        // column i of F P for i = 2, 4 (the only ones the tangent takes)
+        auto fpc = [&](int row, int col) { return col == 2 ? FP2[row] : FP4[row]; };
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+          const double dph = -dt * ph * sg[j], dphd = -dt * phd * sgd[j];
+          const double ddg[NS] = {0.0, 0.0, dph, 0.0, dphd};
+          double ddx[NS];
+          ddx[0] = fma(dt, dx[j][1], dx[j][0]);
+          ddx[1] = dx[j][1];
+          ddx[2] = fma(ph, dx[j][2], dph * x2);
+          ddx[3] = phc * dx[j][3];
+          ddx[4] = fma(phd, dx[j][4], dphd * x4);
+          double FD[NS][NS];
+#pragma unroll
+          for (int q = 0; q < NS; ++q) {
+            FD[0][q] = fma(dt, dP[j][si5(1, q)], dP[j][si5(0, q)]);
+#pragma unroll
+            for (int i = 1; i < NS; ++i) FD[i][q] = dg[i] * dP[j][si5(i, q)];
+          }
+          double D[NP];
+#pragma unroll
+          for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int q = 0; q <= i; ++q) {
+              double t = q == 0 ? fma(dt, FD[i][1], FD[i][0]) : dg[q] * FD[i][q];
+              if (i == 2 || i == 4) t = fma(ddg[i], fpc(q, i), t);
+              if (q == 2 || q == 4) t = fma(ddg[q], fpc(i, q), t);
+              D[si5(i, q)] = t;
+            }
+          D[si5(2, 2)] += fma(sv[j], qf, -2.0 * vr * ph * dph);
+          D[si5(3, 3)] = fma(sc[j], r.qcu, D[si5(3, 3)]);
+          D[si5(4, 4)] += fma(sd[j], qfd, -2.0 * vd * phd * dphd);
+          double du[NS], de = 0.0;
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = 0; l < NS; ++l)
+              if (h5(l)) t = fma(hw[l], D[si5(i, l)], t);
+            du[i] = t;
+            if (h5(i)) de = fma(-hw[i], ddx[i], de);
+          }
+          double hdu = 0.0;
+#pragma unroll
+          for (int i = 0; i < NS; ++i)
+            if (h5(i)) hdu = fma(hw[i], du[i], hdu);
+          const double dS = hdu + fma(sr2[j], r.s2, sq2[j]);
+#pragma unroll
+          for (int i = 0; i < NS; ++i) {
+            const double dk = fma(-K[i], dS, du[i]) * inv;
+            dx[j][i] = fma(dk, e, fma(K[i], de, ddx[i]));
+          }
+#pragma unroll
+          for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int q = 0; q <= i; ++q)
+              dP[j][si5(i, q)] =
+                  fma(dS * K[i], K[q], fma(-du[i], K[q], fma(-K[i], du[q], D[si5(i, q)])));
+          dl[j] = fma(-0.5, fma(dS, hS, 2.0 * ei * de), dl[j]);
+        }
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      double* g = a.gpart + (int64_t)p * 8 * a.S + s;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) g[(int64_t)(grp * ND + j) * a.S] = dl[j];
+    }
+  }
+}
+
 template <int NDA, int NDB>
 __global__ void __launch_bounds__(256) k_tangent5(TanArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -1661,14 +1957,19 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nda
   a.n_items = w->n_items;
   a.mc = ds->mc;
   if (thresh < 0) {
-    // the producer/consumer form (model 2): one workgroup of 1 + 6 / nda
-    // waves per item
-    if (ds->model != 2 || (nda != 1 && nda != 2))
-      return fail(ARGUS_E_INVAL, "unsupported tangent split");
-    if (nda == 2)
-      hipLaunchKernelGGL(k_tangent_pc<2>, dim3((unsigned)w->n_items), dim3(4 * kWave), 0, st, a);
+    // the producer/consumer forms: one workgroup of 1 + ndir / nda waves per
+    // item (model 2: 6 directions, model 4: 8)
+    const dim3 grid((unsigned)w->n_items);
+    if (ds->model == 2 && nda == 2)
+      hipLaunchKernelGGL(k_tangent_pc<2>, grid, dim3(4 * kWave), 0, st, a);
+    else if (ds->model == 2 && nda == 1)
+      hipLaunchKernelGGL(k_tangent_pc<1>, grid, dim3(7 * kWave), 0, st, a);
+    else if (ds->model == 4 && nda == 2)
+      hipLaunchKernelGGL(k_tangent5_pc<2>, grid, dim3(5 * kWave), 0, st, a);
+    else if (ds->model == 4 && nda == 1)
+      hipLaunchKernelGGL(k_tangent5_pc<1>, grid, dim3(9 * kWave), 0, st, a);
     else
-      hipLaunchKernelGGL(k_tangent_pc<1>, dim3((unsigned)w->n_items), dim3(7 * kWave), 0, st, a);
+      return fail(ARGUS_E_INVAL, "unsupported tangent split");
     HIPCHK(hipGetLastError());
     return ARGUS_OK;
   }
@@ -1733,11 +2034,12 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
     return rc;
   if (w->tan_nda == 0) {
     // a forced split: "nd" (uniform), "nda,ndb,thresh", or "pc" / "pc1"
-    // (model 2: the producer/consumer form with 2 / 1 directions per wave)
+    // (models 2, 4: the producer/consumer form with 2 / 1 directions per
+    // wave)
     const char* forced = std::getenv("ARGUS_TAN_ND");
     int fa = 0, fb = 0;
     long long ft = 0;
-    const bool fpc = forced && ds->model == 2 &&
+    const bool fpc = forced && (ds->model == 2 || ds->model == 4) &&
                      (std::strcmp(forced, "pc") == 0 || std::strcmp(forced, "pc1") == 0);
     const int nf = forced && !fpc ? std::sscanf(forced, "%d,%d,%lld", &fa, &fb, &ft) : 0;
     if (nf == 1) fb = fa;
@@ -1781,7 +2083,7 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
       for (int64_t t : {nmax / 2, (3 * nmax) / 4, (7 * nmax) / 8})
         for (auto ab : mixed)
           if (t > 0) cand.push_back({ab.first, ab.second, t});
-      if (ds->model == 2)  // producer/consumer forms
+      if (ds->model == 2 || ds->model == 4)  // producer/consumer forms
         for (int c : {2, 1}) cand.push_back({c, c, -1});
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
@@ -1805,7 +2107,7 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
         char b[128];
         if (c.t < 0)
           std::snprintf(b, sizeof b, "tangent producer/consumer (base wave + %d x %d directions): %.4f ms\n",
-                        6 / c.a, c.a, m);
+                        (ds->model == 4 ? 8 : 6) / c.a, c.a, m);
         else if (c.a == c.b)
           std::snprintf(b, sizeof b, "tangent directions per wave %d: %.4f ms\n", c.a, m);
         else

@@ -104,12 +104,14 @@ def check_grad(g, gref, tol=1e-9):
         assert (d <= tol * (np.abs(gref[s]) + 1e-3 * inf)).all(), s
 
 
-@pytest.mark.parametrize("nd", ["", "1", "2", "4", "1,2,37", "1,4,37", "2,4,7"])
+@pytest.mark.parametrize("nd", ["", "1", "2", "4", "1,2,37", "1,4,37", "2,4,7", "pc", "pc1"])
 def test_dm_gradient(argus, orc, nd, monkeypatch):
     """The model-4 tangent sweep (eight directions per pulsar, split over
     8 / nd waves; "a,b,t": a per wave for pulsars of at least t TOAs, b for
-    the others; "" lets the first call choose) against the oracle's
-    complex-step derivative, ragged pulsars and tiles."""
+    the others; "pc" / "pc1": the base filter on one wave handing its
+    per-TOA values to four waves of two directions or eight of one; "" lets
+    the first call choose) against the oracle's complex-step derivative,
+    ragged pulsars and tiles."""
     if nd:
         monkeypatch.setenv("ARGUS_TAN_ND", nd)
     else:
