@@ -698,8 +698,12 @@ def main():
                    "toa_states_per_s": d.n_toa * S4 / (ms5 * 1e-3),
                    "output_GB": out_bytes / 1e9,
                    "output_write_GB_per_s": out_bytes / (ms5 * 1e-3) / 1e9}
-            log("smooth: %.3f ms/call, %.4g TOA-states/s, %.1f GB/s of output"
-                % (ms5, leg["toa_states_per_s"], leg["output_write_GB_per_s"]))
+            leg["form"] = next((ln.split(": ", 1)[1] for ln in ds.tune_info(S4).split("\n")
+                                if ln.startswith("smoother:")), "")
+            log("smooth: %.3f ms/call, %.4g TOA-states/s, %.1f GB/s of output (%s)"
+                % (ms5, leg["toa_states_per_s"], leg["output_write_GB_per_s"], leg["form"]))
+            log("smooth tune: " + " | ".join(ln.strip() for ln in ds.tune_info(S4).split("\n")
+                                             if ln.strip().startswith("smoother")))
             if not args.no_cpu:
                 import oracle
                 oracle.build()

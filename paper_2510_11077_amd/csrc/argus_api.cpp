@@ -683,6 +683,15 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
                     w->tan_nda, (long long)w->tan_thresh, w->tan_ndb);
     s += b + w->grad_log;
   }
+  if (w && w->smooth_k) {
+    if (w->smooth_k == 1)
+      std::snprintf(b, sizeof b, "smoother: one wave per item\n");
+    else
+      std::snprintf(b, sizeof b,
+                    "smoother: time-parallel form, the longest pulsars in %d chunks\n",
+                    w->smooth_k);
+    s += b + w->smooth_log;
+  }
   std::snprintf(buf, len, "%s", s.c_str());
   return ARGUS_OK;
 }

@@ -82,6 +82,7 @@ struct Workspace {
   // gradient workspace: level-1 checkpoints, per-wave level-2 scratch,
   // per-pulsar gradient parts
   DevBuf ckpt, scratch, gpart, c1, seg_base, stat_tmp;
+  std::vector<int32_t> c1_host;
   int64_t tot_seg = 0;
   int max_sub = 0, grad_waves = 0;
   bool grad_ready = false;
@@ -96,6 +97,14 @@ struct Workspace {
   int64_t units_thresh = -1;
   std::vector<int32_t> items_host;  // the items, as uploaded
   std::string grad_log;
+  // smoother of models 1, 2: 1 = one wave per item, K > 1 = the
+  // time-parallel form with chunks of about 1 / K of the longest pulsar
+  // (0 = not tuned yet); the per-item chunk counts and slots, the (item,
+  // chunk) units and the chunk count they were built for, chunk summaries,
+  // hand-over states and the reverse waves' level-2 scratch
+  int smooth_k = 0, tp_built_k = 0, n_tp_units = 0, tp_waves = 0;
+  DevBuf tp_item, tp_units, tp_sum, tp_adj, tp_scr;
+  std::string smooth_log;
   // HMC: proposal position, momentum, gradient, logL, initial energy, flags
   DevBuf hmc_x, hmc_p, hmc_g, hmc_l, hmc_h0, hmc_ok;
   // NUTS: trajectory, cursor and subtree-stack buffers for depth <= nuts_md

@@ -2,10 +2,10 @@
 // adjoint (reverse-mode) Kalman sweep. The paper's samplers consume the
 // likelihood and its gradient (Functionality, "Sampler Integration"); here
 // the gradient is the exact derivative of the same recursion. The same
-// sweep, with the adjoints of each filtered state turned into that state's
-// posterior given all TOAs, is the fixed-interval smoother of the latent
-// noise (the filter tracking the realised noise: Summary, Statement of
-// Need).
+// checkpointed pass, carrying the information pair of the modified
+// Bryson-Frazier recursion backwards instead of the adjoints, is the
+// fixed-interval smoother of the latent noise (the filter tracking the
+// realised noise: Summary, Statement of Need).
 //
 // Per TOA the forward map is (x, P) -> (x+, P+) with
 //   x- = F x, P- = F P F^T + Q, e = y - h.x-, u = P- h, S = h.u + R,
@@ -79,10 +79,14 @@ struct AdjArgs {
   double* part;             // [P*S] log-likelihood terms
   int32_t* pstat;           // [P*S]
   double* gpart;            // [P * 6 * S] per-pulsar parameter gradients
+  const int32_t* tp_item;   // time-parallel smoother: per item its chunk count and first slot
+  const int32_t* tp_units;  // (item, chunk) units, longest chunk first
+  double* tpsum;            // [slots * 30 * 64] chunk summaries
+  double* tpadj;            // [slots * 14 * 64] adjoints after each chunk / the final state
   double* smean;            // smoothing: [N * nc * S] posterior means
   double* svar;             // smoothing: [N * nc * S] posterior variances, or null
   int64_t S, tot_seg;
-  int32_t D, P, n_items, max_sub, model, nc;
+  int32_t D, P, n_items, max_sub, model, nc, n_units;
   ModelConst mc;
 };
 
@@ -133,10 +137,11 @@ __device__ __forceinline__ Pred predict(const State& s, const TOARec& r, const L
 
 #define JOSEPH(pij, ki, uj, di, kj) pij = fma(di, kj, fma(-(ki), uj, pij))
 
-// One forward step in place; returns S and e.
+// One forward step in place; returns S, e, 1/S, the gain k and the red decay.
 __device__ __forceinline__ void fwd_step(State& s, const TOARec& r, const LaneP& L, double& S,
-                                         double& e, double& inv) {
+                                         double& e, double& inv, double kk[4], double& phr) {
   const Pred p = predict(s, r, L);
+  phr = p.ph;
   e = r.y - (p.xr + p.xa + p.xg);
   const double ur = p.P.rr + p.P.ra + p.P.rg;
   const double uf = p.P.rf + p.P.fa + p.P.fg;
@@ -146,6 +151,10 @@ __device__ __forceinline__ void fwd_step(State& s, const TOARec& r, const LaneP&
   S = (ur + ua + ug) + R;
   inv = rcp_nr(S);
   const double kr = ur * inv, kf = uf * inv, ka = ua * inv, kg = ug * inv;
+  kk[0] = kr;
+  kk[1] = kf;
+  kk[2] = ka;
+  kk[3] = kg;
   s.xr = fma(kr, e, p.xr);
   s.xf = fma(kf, e, p.xf);
   s.xa = fma(ka, e, p.xa);
@@ -176,6 +185,12 @@ __device__ __forceinline__ void fwd_step(State& s, const TOARec& r, const LaneP&
   s.P.fg = fma(zf, kg, wfg);
   s.P.ag = fma(za, kg, wag);
   s.P.gg = fma(zg, kg, wgg);
+}
+
+__device__ __forceinline__ void fwd_step(State& s, const TOARec& r, const LaneP& L, double& S,
+                                         double& e, double& inv) {
+  double kk[4], ph;
+  fwd_step(s, r, L, S, e, inv, kk, ph);
 }
 
 __device__ __forceinline__ void fwd_only(State& s, const TOARec& r, const LaneP& L) {
@@ -248,30 +263,76 @@ __device__ __forceinline__ void rev_step(const State& sp, const TOARec& r, const
   M.gg = (phc * phc) * Mm.gg;
 }
 
-// Smoothed moments at one TOA from the filtered state f after it and the
-// adjoints (xb, M) of that state, i.e. the derivatives of the total
-// log-likelihood with respect to the filtered mean and covariance. For a
-// Gaussian N(x; m, P) that the later data reweight, d log Z / dm = P^-1 (mu - m)
-// and d log Z / dP = 1/2 P^-1 (Sigma + (mu - m)(mu - m)^T - P) P^-1, so
-//   E[x | y] = x + P xb,   Cov[x | y] = P + P (2 M - xb xb^T) P
-// (the Bryson-Frazier form of the fixed-interval smoother; no inverse).
-// Writes the first nc components of the mean and the variance diagonal
-// at entry ((k * nc + c) * S + s); NaN when the filter failed.
+// Smoother: the modified Bryson-Frazier recursion. With the information
+// vector lam and matrix Lam of the filtered state after a TOA (zero after
+// the last TOA), the smoothed moments there are
+//   E[x | y] = x - P lam,   Cov[x | y] = P - P Lam P,
+// and TOA k maps the pair after it to the pair after TOA k - 1 by
+//   lam <- F^T (C^T lam - h e / S),   Lam <- F^T (C^T Lam C + h h^T / S) F,
+//   C = I - K h^T,  C^T Lam C = Lam - h g^T - g h^T + (K.g) h h^T,  g = Lam K.
+// (In terms of the adjoints of the gradient sweep, lam = -xb and
+// Lam = xb xb^T - 2 M; carrying the pair itself keeps the smoothed
+// covariance free of the cancellation between xb xb^T and 2 M.)
+// sp = filtered state after TOA k - 1, r = TOA k.
+__device__ __forceinline__ void rev_bf(const State& sp, const TOARec& r, const LaneP& L,
+                                       double lam[4], Cov4& Lm) {
+  const Pred p = predict(sp, r, L);
+  const double dt = r.dt, phc = r.phc, ph = p.ph;
+  const double e = r.y - (p.xr + p.xa + p.xg);
+  const double u[4] = {p.P.rr + p.P.ra + p.P.rg, p.P.rf + p.P.fa + p.P.fg,
+                       p.P.ra + p.P.aa + p.P.ag, p.P.rg + p.P.ag + p.P.gg};
+  const double S = (u[0] + u[2] + u[3]) + fma(L.efac2, r.s2, L.equad2);
+  const double inv = rcp_nr(S);
+  const double K[4] = {u[0] * inv, u[1] * inv, u[2] * inv, u[3] * inv};
+  // C^T lam - h e / S  (h = [1, 0, 1, 1])
+  const double hl = fma(K[0], lam[0], fma(K[1], lam[1], fma(K[2], lam[2], K[3] * lam[3]))) +
+                    e * inv;
+  const double t0 = lam[0] - hl, t1 = lam[1], t2 = lam[2] - hl, t3 = lam[3] - hl;
+  // g = Lam K, C^T Lam C + h h^T / S
+  const double g[4] = {Lm.rr * K[0] + Lm.rf * K[1] + Lm.ra * K[2] + Lm.rg * K[3],
+                       Lm.rf * K[0] + Lm.ff * K[1] + Lm.fa * K[2] + Lm.fg * K[3],
+                       Lm.ra * K[0] + Lm.fa * K[1] + Lm.aa * K[2] + Lm.ag * K[3],
+                       Lm.rg * K[0] + Lm.fg * K[1] + Lm.ag * K[2] + Lm.gg * K[3]};
+  const double c = fma(K[0], g[0], fma(K[1], g[1], fma(K[2], g[2], K[3] * g[3]))) + inv;
+  Cov4 X;
+  X.rr = Lm.rr - 2.0 * g[0] + c;
+  X.rf = Lm.rf - g[1];
+  X.ff = Lm.ff;
+  X.ra = Lm.ra - g[2] - g[0] + c;
+  X.fa = Lm.fa - g[1];
+  X.aa = Lm.aa - 2.0 * g[2] + c;
+  X.rg = Lm.rg - g[3] - g[0] + c;
+  X.fg = Lm.fg - g[1];
+  X.ag = Lm.ag - g[3] - g[2] + c;
+  X.gg = Lm.gg - 2.0 * g[3] + c;
+  // through F: lam = F^T t, Lam = F^T X F
+  lam[0] = t0;
+  lam[1] = fma(dt, t0, t1);
+  lam[2] = ph * t2;
+  lam[3] = phc * t3;
+  Lm.rr = X.rr;
+  Lm.rf = fma(dt, X.rr, X.rf);
+  Lm.ff = fma(dt, fma(dt, X.rr, 2.0 * X.rf), X.ff);
+  Lm.ra = ph * X.ra;
+  Lm.fa = ph * fma(dt, X.ra, X.fa);
+  Lm.rg = phc * X.rg;
+  Lm.fg = phc * fma(dt, X.rg, X.fg);
+  Lm.aa = (ph * ph) * X.aa;
+  Lm.ag = (ph * phc) * X.ag;
+  Lm.gg = (phc * phc) * X.gg;
+}
+
+// Smoothed moments at TOA k from the filtered state f after it and the
+// information pair there: the first nc components of the mean and the
+// variance diagonal at entry ((k * nc + c) * S + s); NaN when the filter
+// failed.
 __device__ __forceinline__ void put_smooth(const AdjArgs& a, int64_t k, int64_t s,
-                                           const State& f, const double xb[4], const Cov4& M,
+                                           const State& f, const double lam[4], const Cov4& Lm,
                                            bool bad) {
   const double P[4][4] = {{f.P.rr, f.P.rf, f.P.ra, f.P.rg},
                           {f.P.rf, f.P.ff, f.P.fa, f.P.fg},
                           {f.P.ra, f.P.fa, f.P.aa, f.P.ag},
                           {f.P.rg, f.P.fg, f.P.ag, f.P.gg}};
-  const double B[4][4] = {{2.0 * M.rr - xb[0] * xb[0], 2.0 * M.rf - xb[0] * xb[1],
-                           2.0 * M.ra - xb[0] * xb[2], 2.0 * M.rg - xb[0] * xb[3]},
-                          {2.0 * M.rf - xb[1] * xb[0], 2.0 * M.ff - xb[1] * xb[1],
-                           2.0 * M.fa - xb[1] * xb[2], 2.0 * M.fg - xb[1] * xb[3]},
-                          {2.0 * M.ra - xb[2] * xb[0], 2.0 * M.fa - xb[2] * xb[1],
-                           2.0 * M.aa - xb[2] * xb[2], 2.0 * M.ag - xb[2] * xb[3]},
-                          {2.0 * M.rg - xb[3] * xb[0], 2.0 * M.fg - xb[3] * xb[1],
-                           2.0 * M.ag - xb[3] * xb[2], 2.0 * M.gg - xb[3] * xb[3]}};
   const double x[4] = {f.xr, f.xf, f.xa, f.xg};
   double* mo = a.smean + k * a.nc * a.S + s;
   double* vo = a.svar ? a.svar + k * a.nc * a.S + s : nullptr;
@@ -279,23 +340,141 @@ __device__ __forceinline__ void put_smooth(const AdjArgs& a, int64_t k, int64_t 
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (c >= a.nc) break;
-    double m = x[c], v = 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      m = fma(P[c][i], xb[i], m);
-      double bp = 0.0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bp = fma(B[i][j], P[j][c], bp);
-      v = fma(P[c][i], bp, v);
-    }
+    // w = row c of P: mean x_c - w.lam, variance P_cc - w^T Lam w
+    const double* w = P[c];
+    const double m = x[c] - fma(w[0], lam[0], fma(w[1], lam[1], fma(w[2], lam[2], w[3] * lam[3])));
+    const double q = fma(w[0], fma(Lm.rr, w[0], 2.0 * fma(Lm.rf, w[1], fma(Lm.ra, w[2], Lm.rg * w[3]))),
+                     fma(w[1], fma(Lm.ff, w[1], 2.0 * fma(Lm.fa, w[2], Lm.fg * w[3])),
+                         fma(w[2], fma(Lm.aa, w[2], 2.0 * Lm.ag * w[3]), Lm.gg * w[3] * w[3])));
     mo[c * a.S] = bad ? nan : m;
-    if (vo) vo[c * a.S] = bad ? nan : P[c][c] + v;
+    if (vo) vo[c * a.S] = bad ? nan : P[c][c] - q;
   }
 }
 
 __device__ __forceinline__ double prm(const AdjArgs& a, int c, int64_t s) {
   const int j = a.col[c];
   return j >= 0 ? a.theta[s * a.D + j] : a.fixed[c];
+}
+
+// This lane's filter parameters for pulsar p (models 1, 2), the parameters
+// the gradient's chain rule needs (model 1: t1 = EFAC; model 2: t1 =
+// log10 gamma_red, t2 = EFAC, t5 = gamma), and whether one is not finite.
+struct LaneTheta {
+  LaneP L;
+  double t1, t2, t5;
+  bool pnf;
+};
+__device__ __forceinline__ LaneTheta lane_theta(const AdjArgs& a, int p, int64_t s) {
+  LaneTheta o;
+  if (a.model == 1) {
+    const double t0 = prm(a, 0, s);  // log10 sigma_s
+    o.t1 = prm(a, 1, s);             // EFAC
+    o.pnf = !(finite_d(t0) && finite_d(o.t1));
+    const double ss = exp10(t0);
+    o.L = LaneP{1.0, 0.0, 0.0, o.t1 * o.t1, 0.0, ss * ss};
+    o.t2 = 0.0;
+    o.t5 = 2.0;
+  } else {
+    const int c0 = 4 * p, cc = 4 * a.P;
+    const double t0 = prm(a, c0, s);
+    o.t1 = prm(a, c0 + 1, s);
+    o.t2 = prm(a, c0 + 2, s);
+    const double t3 = prm(a, c0 + 3, s);
+    const double t4 = prm(a, cc, s);
+    o.t5 = prm(a, cc + 1, s);
+    o.pnf = !(finite_d(t0) && finite_d(o.t1) && finite_d(o.t2) && finite_d(t3) &&
+              finite_d(t4) && finite_d(o.t5));
+    const double gr = exp10(o.t1), sr = exp10(t0), eq = exp10(t3);
+    const double gm1 = o.t5 - 1.0;
+    const double vc = exp(2.0 * kLn10 * t4 + (o.t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+                      (12.0 * kPi * kPi * gm1);
+    o.L = LaneP{gr, sr * sr / (2.0 * gr), vc, o.t2 * o.t2, eq * eq, a.mc.ss2};
+  }
+  return o;
+}
+
+// What the reverse sweep carries and does per TOA. The gradient: the
+// adjoints (xb, M) of the filtered state and the parameter gradient.
+struct GradSweep {
+  double xb[4];
+  Cov4 M;
+  Grad G;
+  __device__ __forceinline__ void step(const State& sp, const TOARec& r, const LaneP& L) {
+    rev_step(sp, r, L, xb, M, G);
+  }
+  __device__ __forceinline__ void emit(int, const State&) {}
+};
+// The smoother: the information pair (lam, Lam) of the filtered state, and
+// the smoothed moments of each TOA k (within pulsar stream kb..) written out.
+struct SmoothSweep {
+  const AdjArgs* a;
+  int kb;
+  int64_t s;
+  bool valid, bad;
+  double lam[4];
+  Cov4 Lm;
+  __device__ __forceinline__ void step(const State& sp, const TOARec& r, const LaneP& L) {
+    rev_bf(sp, r, L, lam, Lm);
+  }
+  __device__ __forceinline__ void emit(int k, const State& f) {
+    if (valid) put_smooth(*a, (int64_t)kb + k, s, f, lam, Lm, bad);
+  }
+};
+
+// The reverse sweep over level-1 segments sg_hi - 1 down to sg_lo of a
+// pulsar's stream (ck: its level-1 checkpoints; scr: this wave's level-2
+// scratch). sw holds what is carried after the last TOA of segment
+// sg_hi - 1 and on return holds it before the first TOA of segment sg_lo;
+// sw.emit(k, f) is called, with the filtered state f after TOA k, for every
+// TOA k >= klo of the range except the last one.
+template <class Sweep>
+__device__ __forceinline__ void reverse_segments(const RecBuf& rb, const double* ck, double* scr,
+                                                 const LaneP& L, int N, int c1, int sg_lo,
+                                                 int sg_hi, int klo, Sweep& sw) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t sg = sg_hi - 1; sg >= sg_lo; --sg) {
+    const int64_t k0 = sg * c1;
+    const int64_t k1 = k0 + c1 < N ? k0 + c1 : N;
+    const int nsub = (int)((k1 - k0 + 3) / 4);
+    // recompute the segment to level-2 checkpoints every 4 TOAs; the four
+    // records of a piece are read together into VGPRs (one wait per piece)
+    State cur = get_state(ck + sg * kFields * kWave, lane);
+    for (int t = 0; t < nsub; ++t) {
+      put_state(scr + (int64_t)t * kFields * kWave, lane, cur);
+      if (t + 1 < nsub) {
+        const int kk = (int)k0 + 4 * t;  // a full piece: kk + 3 < k1
+        TOARec q[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, kk + i);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fwd_only(cur, q[i], L);
+      }
+    }
+    // reverse each 4-TOA piece, last first: the state before TOA i of the
+    // piece is recomputed from the piece's checkpoint (0..3 steps), so
+    // only two states are live in registers; the piece's records are read
+    // once into VGPRs (index clamped to its last TOA) and the loops are
+    // unrolled so that they are addressed statically
+    for (int t = nsub - 1; t >= 0; --t) {
+      const int ks = (int)k0 + 4 * t;
+      const int nt = (int)(k1 - ks < 4 ? k1 - ks : 4);
+      TOARec q[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, ks + (i < nt ? i : nt - 1));
+      const State s0 = get_state(scr + (int64_t)t * kFields * kWave, lane);
+#pragma unroll
+      for (int i = 3; i >= 0; --i) {
+        if (i < nt) {
+          State cur = s0;
+#pragma unroll
+          for (int j = 0; j < i; ++j) fwd_only(cur, q[j], L);
+          sw.step(cur, q[i], L);
+          // sw now holds the pair of the filtered state after TOA ks + i - 1
+          if (ks + i > klo) sw.emit(ks + i - 1, cur);
+        }
+      }
+    }
+  }
 }
 
 // SMOOTH: write the smoothed moments of every TOA instead of the gradient.
@@ -322,32 +501,10 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
 
     // parameters of this lane's filter
-    LaneP L;
-    double t0, t1, t2, t3, t4 = 0.0, t5 = 2.0;
-    bool pnf;
-    if (a.model == 1) {
-      t0 = prm(a, 0, s);  // log10 sigma_s
-      t1 = prm(a, 1, s);  // EFAC
-      pnf = !(finite_d(t0) && finite_d(t1));
-      const double ss = exp10(t0);
-      L = LaneP{1.0, 0.0, 0.0, t1 * t1, 0.0, ss * ss};
-      t2 = t3 = 0.0;
-    } else {
-      const int c0 = 4 * p, cc = 4 * a.P;
-      t0 = prm(a, c0, s);
-      t1 = prm(a, c0 + 1, s);
-      t2 = prm(a, c0 + 2, s);
-      t3 = prm(a, c0 + 3, s);
-      t4 = prm(a, cc, s);
-      t5 = prm(a, cc + 1, s);
-      pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) && finite_d(t4) &&
-              finite_d(t5));
-      const double gr = exp10(t1), sr = exp10(t0), eq = exp10(t3);
-      const double gm1 = t5 - 1.0;
-      const double vc = exp(2.0 * kLn10 * t4 + (t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
-                        (12.0 * kPi * kPi * gm1);
-      L = LaneP{gr, sr * sr / (2.0 * gr), vc, t2 * t2, eq * eq, a.mc.ss2};
-    }
+    const LaneTheta th = lane_theta(a, p, s);
+    const LaneP L = th.L;
+    const double t1 = th.t1, t2 = th.t2, t5 = th.t5;
+    const bool pnf = th.pnf;
 
     // ---------------- forward pass: log-likelihood + level-1 checkpoints
     State st{0.0, 0.0, 0.0, 0.0,
@@ -395,66 +552,27 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
     if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
     if (stat) ll = -INFINITY;
 
-    // ---------------- reverse sweep
-    double xb[4] = {0.0, 0.0, 0.0, 0.0};
-    Cov4 M{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    Grad G{0, 0, 0, 0, 0, 0};
-    // the last TOA's smoothed moments are its filtered ones
-    if (SMOOTH && valid && N > 0) put_smooth(a, kb + N - 1, s, st, xb, M, stat != 0);
-    const int64_t nseg = (N + c1 - 1) / c1;
-    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-      const int64_t k0 = sg * c1;
-      const int64_t k1 = k0 + c1 < N ? k0 + c1 : N;
-      const int nsub = (int)((k1 - k0 + 3) / 4);
-      // recompute the segment to level-2 checkpoints every 4 TOAs; the four
-      // records of a piece are read together into VGPRs (one wait per piece)
-      State cur = get_state(ck + sg * kFields * kWave, lane);
-      for (int t = 0; t < nsub; ++t) {
-        put_state(scr + (int64_t)t * kFields * kWave, lane, cur);
-        if (t + 1 < nsub) {
-          const int kk = (int)k0 + 4 * t;  // a full piece: kk + 3 < k1
-          TOARec q[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, kk + i);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) fwd_only(cur, q[i], L);
-        }
-      }
-      // reverse each 4-TOA piece, last first: the state before TOA i of the
-      // piece is recomputed from the piece's checkpoint (0..3 steps), so
-      // only two states are live in registers; the piece's records are read
-      // once into VGPRs (index clamped to its last TOA) and the loops are
-      // unrolled so that they are addressed statically
-      for (int t = nsub - 1; t >= 0; --t) {
-        const int ks = (int)k0 + 4 * t;
-        const int nt = (int)(k1 - ks < 4 ? k1 - ks : 4);
-        TOARec q[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, ks + (i < nt ? i : nt - 1));
-        const State s0 = get_state(scr + (int64_t)t * kFields * kWave, lane);
-#pragma unroll
-        for (int i = 3; i >= 0; --i) {
-          if (i < nt) {
-            State cur = s0;
-#pragma unroll
-            for (int j = 0; j < i; ++j) fwd_only(cur, q[j], L);
-            rev_step(cur, q[i], L, xb, M, G);
-            // (xb, M) are now the adjoints of the filtered state after TOA ks + i - 1
-            if (SMOOTH && valid && ks + i > 0)
-              put_smooth(a, kb + ks + i - 1, s, cur, xb, M, stat != 0);
-          }
-        }
-      }
-    }
-    // the prior P0 = diag(s_r^2, s_f^2, v_r, v_c)
-    G.v += M.aa;
-    G.vc += M.gg;
-
     if (valid) {
       a.part[(int64_t)p * a.S + s] = ll;
       a.pstat[(int64_t)p * a.S + s] = stat;
     }
-    if (valid && !SMOOTH) {
+    // ---------------- reverse sweep
+    const int nseg = (N + c1 - 1) / c1;
+    if constexpr (SMOOTH) {
+      SmoothSweep sw{&a, kb, s, valid, stat != 0, {0.0, 0.0, 0.0, 0.0},
+                     Cov4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+      // the last TOA's smoothed moments are its filtered ones
+      if (N > 0) sw.emit(N - 1, st);
+      reverse_segments(rb, ck, scr, L, N, c1, 0, nseg, 0, sw);
+    } else {
+      GradSweep sw{{0.0, 0.0, 0.0, 0.0}, Cov4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+                   Grad{0, 0, 0, 0, 0, 0}};
+      reverse_segments(rb, ck, scr, L, N, c1, 0, nseg, 0, sw);
+      Grad& G = sw.G;
+      // the prior P0 = diag(s_r^2, s_f^2, v_r, v_c)
+      G.v += sw.M.aa;
+      G.vc += sw.M.gg;
+      if (!valid) continue;
       double* g = a.gpart + (int64_t)p * 6 * a.S + s;
       if (a.model == 1) {
         g[0] = G.ss2 * 2.0 * kLn10 * L.ss2;  // log10 sigma_s
@@ -468,6 +586,231 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
         g[5 * a.S] = G.vc * L.vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / (t5 - 1.0));  // gamma
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time-parallel form of the smoother (models 1, 2). In the modified
+// Bryson-Frazier recursion (rev_bf) TOA k maps the information pair after
+// it to the pair after TOA k - 1 by
+//   lam <- A^T lam - F^T h e / S,   Lam <- A^T Lam A + (F^T h)(F^T h)^T / S,
+//   A = (I - K h^T) F,
+// affine in lam and a congruence plus a constant in Lam. A run of TOAs
+// therefore maps the pair after its last TOA to the pair before its first by
+//   lam <- U lam + phi,   Lam <- U Lam U^T + Om,   U = A_1^T ... A_n^T,
+// and (U, phi, Om) accumulate along the forward pass: per TOA,
+//   V = U F^T, v = V h, phi -= v e / S, Om += v v^T / S, U = V - v K^T.
+// An item (64-sample tile, pulsar) is split into nch chunks of whole level-1
+// segments (chunk c: segments c nseg / nch .. (c + 1) nseg / nch - 1).
+// k_smooth_fwd (one wave per item) runs the forward filter over the whole
+// stream (log-likelihood, level-1 checkpoints, the summaries of chunks
+// 1 .. nch - 1), chains the summaries from the last chunk back (the pair
+// after the last TOA is zero) and stores the pair after the last TOA of
+// every chunk but the last, and the final filtered state in the last
+// chunk's place. k_smooth_rev then runs the checkpointed reverse sweep of
+// every (item, chunk) unit independently, longest chunks first. An item's
+// serial chain drops from a forward and a reverse pass over its N TOAs to a
+// forward pass over N and a reverse pass over about N / nch.
+constexpr int kSum = 30;  // a chunk summary: U (16, row major), phi (4), Om (10)
+
+__host__ __device__ constexpr int si4(int i, int j) {
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+__global__ void __launch_bounds__(256) k_smooth_fwd(AdjArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int it = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  if (it >= a.n_items) return;
+  const int tile = a.items[2 * it];
+  const int p = a.items[2 * it + 1];
+  const int64_t s_raw = (int64_t)tile * kWave + lane;
+  const bool valid = s_raw < a.S;
+  const int64_t s = valid ? s_raw : a.S - 1;
+  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+  const int c1 = a.c1[p];
+  const int nseg = (N + c1 - 1) / c1;
+  const int nch = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it]);
+  const int64_t base = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it + 1]);
+  double* ckw = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
+  const LaneTheta th = lane_theta(a, p, s);
+  const LaneP L = th.L;
+  const RecBuf rb = rec_buffer(a.rec + kb, N);
+
+  State st{0.0, 0.0, 0.0, 0.0,
+           Cov4{a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, 0.0, L.vr, 0.0, 0.0, 0.0, L.vc}};
+  double quad = 0.0, lm = 1.0;
+  int le = 0, stat = th.pnf ? kPNF : 0;
+  int kc = 0;  // position within the current level-1 segment
+  TOARec rq{};
+  if (N > 0) rq = load_rec_vgpr(rb, 0);
+  double U[4][4], phi[4], Om[10];
+  // one TOA: checkpoint, filter step and log-likelihood terms, and with
+  // ACC the chunk summary
+  auto step = [&](int k, auto acc) {
+    const TOARec r = rq;
+    rq = load_rec_vgpr(rb, k + 1 < N ? k + 1 : k);
+    if (kc == 0) {
+      put_state(ckw, lane, st);
+      ckw += kFields * kWave;
+    }
+    kc = kc + 1 == c1 ? 0 : kc + 1;
+    double S, e, inv, kk[4], ph;
+    fwd_step(st, r, L, S, e, inv, kk, ph);
+    const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+    if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+    quad = fma(e * e, inv, quad);
+    const double pm = lm * S;
+    lm = __builtin_amdgcn_frexp_mant(pm);
+    le += __builtin_amdgcn_frexp_exp(pm);
+    if constexpr (decltype(acc)::value) {
+      const double dt = r.dt, phc = r.phc, ei = -e * inv;
+      double V[4][4], v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        V[i][0] = fma(dt, U[i][1], U[i][0]);
+        V[i][1] = U[i][1];
+        V[i][2] = ph * U[i][2];
+        V[i][3] = phc * U[i][3];
+        v[i] = V[i][0] + V[i][2] + V[i][3];
+        phi[i] = fma(v[i], ei, phi[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double vs = v[i] * inv;
+#pragma unroll
+        for (int c = 0; c <= i; ++c) Om[si4(i, c)] = fma(vs, v[c], Om[si4(i, c)]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) U[i][c] = fma(-v[i], kk[c], V[i][c]);
+      }
+    }
+  };
+  const std::integral_constant<bool, false> no_acc;
+  const std::integral_constant<bool, true> with_acc;
+  // chunk 0 needs no summary
+  int k = 0;
+  const int e0 = (nseg / nch) * c1 < N ? (nseg / nch) * c1 : N;
+  for (; k < e0; ++k) step(k, no_acc);
+  for (int c = 1; c < nch; ++c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) U[i][q] = i == q ? 1.0 : 0.0;
+      phi[i] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 10; ++i) Om[i] = 0.0;
+    const int sh = (c + 1) * nseg / nch;
+    const int ec = sh * c1 < N ? sh * c1 : N;
+    for (; k < ec; ++k) step(k, with_acc);
+    double* o = a.tpsum + (base + c) * kSum * kWave + lane;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) o[i * kWave] = U[i / 4][i % 4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[(16 + i) * kWave] = phi[i];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) o[(20 + i) * kWave] = Om[i];
+  }
+  double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+  if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+  if (stat) ll = -INFINITY;
+  if (valid) {
+    a.part[(int64_t)p * a.S + s] = ll;
+    a.pstat[(int64_t)p * a.S + s] = stat;
+  }
+  // the final filtered state, in the last chunk's place
+  put_state(a.tpadj + (base + nch - 1) * kFields * kWave, lane, st);
+  // chain the summaries from the last chunk back; the pair after the last
+  // TOA of chunk c - 1 goes to chunk c - 1's place (lam, then Lam in the
+  // order of a covariance)
+  double lam[4] = {0.0, 0.0, 0.0, 0.0}, Lam[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) Lam[i] = 0.0;
+  for (int c = nch - 1; c >= 1; --c) {
+    const double* o = a.tpsum + (base + c) * kSum * kWave + lane;
+    double Uc[4][4], T[4][4], nl[4];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Uc[i / 4][i % 4] = o[i * kWave];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double acc = o[(16 + i) * kWave];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc = fma(Uc[i][q], lam[q], acc);
+        double tq = 0.0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) tq = fma(Uc[i][l], Lam[si4(l, q)], tq);
+        T[i][q] = tq;
+      }
+      nl[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      lam[i] = nl[i];
+#pragma unroll
+      for (int q = 0; q <= i; ++q) {
+        double acc = o[(20 + si4(i, q)) * kWave];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) acc = fma(T[i][l], Uc[q][l], acc);
+        Lam[si4(i, q)] = acc;
+      }
+    }
+    put_state(a.tpadj + (base + c - 1) * kFields * kWave, lane,
+              State{lam[0], lam[1], lam[2], lam[3],
+                    Cov4{Lam[0], Lam[1], Lam[2], Lam[3], Lam[4], Lam[5], Lam[6], Lam[7], Lam[8],
+                         Lam[9]}});
+  }
+}
+
+// Reverse sweep of the time-parallel smoother: one (item, chunk) unit per
+// wave from a queue ordered longest chunk first; two waves per SIMD.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_smooth_rev(AdjArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gwave = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  double* scr = a.scratch + (int64_t)gwave * a.max_sub * kFields * kWave;
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int u = __builtin_amdgcn_readfirstlane(v);
+    if (u >= a.n_units) break;
+    const int it = a.tp_units[2 * u];
+    const int c = a.tp_units[2 * u + 1];
+    const int tile = a.items[2 * it];
+    const int p = a.items[2 * it + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+    const int c1 = a.c1[p];
+    const int nseg = (N + c1 - 1) / c1;
+    const int nch = a.tp_item[2 * it];
+    const int64_t base = a.tp_item[2 * it + 1];
+    const int sg_lo = c * nseg / nch, sg_hi = (c + 1) * nseg / nch;
+    const int k0 = sg_lo * c1, k1 = sg_hi * c1 < N ? sg_hi * c1 : N;
+    const double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
+    const LaneP L = lane_theta(a, p, s).L;
+    const RecBuf rb = rec_buffer(a.rec + kb, N);
+    const bool bad = a.pstat[(int64_t)p * a.S + s] != 0;
+    SmoothSweep sw{&a, kb, s, valid, bad, {0.0, 0.0, 0.0, 0.0},
+                   Cov4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    State fend;  // the filtered state after this chunk's last TOA
+    const State slot = get_state(a.tpadj + (base + c) * kFields * kWave, lane);
+    if (c == nch - 1) {
+      fend = slot;
+    } else {
+      sw.lam[0] = slot.xr;
+      sw.lam[1] = slot.xf;
+      sw.lam[2] = slot.xa;
+      sw.lam[3] = slot.xg;
+      sw.Lm = slot.P;
+      fend = get_state(ck + (int64_t)sg_hi * kFields * kWave, lane);
+    }
+    if (k1 > k0) sw.emit(k1 - 1, fend);
+    reverse_segments(rb, ck, scr, L, N, c1, sg_lo, sg_hi, k0, sw);
   }
 }
 
@@ -2159,6 +2502,7 @@ int adjoint_setup(argus_dataset* ds, Workspace* w, int64_t S) {
   }
   w->tot_seg = tot;
   w->max_sub = cmax / 4;
+  w->c1_host = c1;
   const int fields = ds->model == 4 ? kF5 : kFields;  // doubles per saved state
   w->grad_waves = (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu);
   w->grad_waves = ((w->grad_waves + 3) / 4) * 4;
@@ -2222,8 +2566,104 @@ int grad_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl
   return grad_finish(ds, w, S, logl, grad, status, st);
 }
 
+namespace {
+
+// Chunks of the time-parallel smoother for K chunks of the longest pulsar:
+// a pulsar of N TOAs gets ceil(N / ceil(N_max / K)) chunks (at most one per
+// level-1 segment); per item its chunk count and first slot, and the (item,
+// chunk) units ordered by chunk length, longest first. Buffers grow to fit.
+int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
+  if (w->tp_built_k == K) return ARGUS_OK;
+  const int64_t nmax =
+      ds->counts.empty() ? 1 : std::max<int64_t>(1, *std::max_element(ds->counts.begin(),
+                                                                       ds->counts.end()));
+  const int64_t lc = (nmax + K - 1) / K;
+  std::vector<int32_t> item(2 * (size_t)w->n_items);
+  std::vector<std::pair<int64_t, int64_t>> units;  // (-chunk length, item * 65536 + chunk)
+  int64_t slots = 0;
+  for (int i = 0; i < w->n_items; ++i) {
+    const int p = w->items_host[2 * i + 1];
+    const int64_t n = ds->counts[p];
+    const int64_t c1 = w->c1_host[p];
+    const int64_t nseg = (n + c1 - 1) / c1;
+    int64_t nch = (n + lc - 1) / lc;
+    nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max<int64_t>(nseg, 1)));
+    nch = std::min<int64_t>(nch, 65535);
+    item[2 * i] = (int32_t)nch;
+    item[2 * i + 1] = (int32_t)slots;
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t lo = std::min(n, (c * nseg / nch) * c1);
+      const int64_t hi = std::min(n, ((c + 1) * nseg / nch) * c1);
+      units.push_back({-(hi - lo), (int64_t)i * 65536 + c});
+    }
+    slots += nch;
+  }
+  if (slots > INT32_MAX) return fail(ARGUS_E_UNSUPPORTED, "time-parallel smoother: too many chunks");
+  std::stable_sort(units.begin(), units.end(),
+                   [](const auto& x, const auto& y) { return x.first < y.first; });
+  std::vector<int32_t> uh(2 * units.size());
+  for (size_t u = 0; u < units.size(); ++u) {
+    uh[2 * u] = (int32_t)(units[u].second / 65536);
+    uh[2 * u + 1] = (int32_t)(units[u].second % 65536);
+  }
+  const int waves = (int)std::min<int64_t>((int64_t)units.size(), 8LL * ds->n_cu);
+  w->tp_waves = ((std::max(waves, 1) + 3) / 4) * 4;
+  const size_t need_sum = (size_t)std::max<int64_t>(slots, 1) * kSum * kWave * sizeof(double);
+  const size_t need_adj = (size_t)std::max<int64_t>(slots, 1) * kFields * kWave * sizeof(double);
+  const size_t need_scr = (size_t)w->tp_waves * w->max_sub * kFields * kWave * sizeof(double);
+  int rc;
+  if ((rc = w->tp_item.upload(item.data(), item.size() * sizeof(int32_t))) ||
+      (rc = w->tp_units.upload(uh.data(), uh.size() * sizeof(int32_t))))
+    return rc;
+  if (w->tp_sum.bytes < need_sum && (rc = w->tp_sum.alloc(need_sum))) return rc;
+  if (w->tp_adj.bytes < need_adj && (rc = w->tp_adj.alloc(need_adj))) return rc;
+  if (w->tp_scr.bytes < need_scr && (rc = w->tp_scr.alloc(need_scr))) return rc;
+  w->n_tp_units = (int)units.size();
+  w->tp_built_k = K;
+  return ARGUS_OK;
+}
+
+// One smoother launch of the given form (1: one wave per item; K > 1: the
+// time-parallel form, the longest pulsars in K chunks) and the reduction of
+// the log-likelihood terms.
+int smooth_once(argus_dataset* ds, Workspace* w, const AdjArgs& a, int nw, int64_t S,
+                double* logl, int32_t* status, hipStream_t st) {
+  int rc;
+  if (ds->model == 4) {
+    hipLaunchKernelGGL(k_smooth5, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+    HIPCHK(hipGetLastError());
+  } else if (nw == 1) {
+    hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+    HIPCHK(hipGetLastError());
+  } else {
+    if ((rc = smooth_tp_setup(ds, w, nw))) return rc;
+    AdjArgs b = a;
+    b.tp_item = w->tp_item.as<int32_t>();
+    b.tp_units = w->tp_units.as<int32_t>();
+    b.tpsum = w->tp_sum.as<double>();
+    b.tpadj = w->tp_adj.as<double>();
+    b.scratch = w->tp_scr.as<double>();
+    b.n_units = w->n_tp_units;
+    hipLaunchKernelGGL(k_smooth_fwd, dim3((w->n_items + 3) / 4), dim3(256), 0, st, b);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_smooth_rev, dim3(w->tp_waves / 4), dim3(256), 0, st, b);
+    HIPCHK(hipGetLastError());
+  }
+  double* ll = logl ? logl : w->logl_tmp.as<double>();
+  int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();
+  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), ll, stat, w->counter.as<int32_t>(),
+               S, ds->P};
+  HIPCHK(launch_reduce(r, st));
+  return ARGUS_OK;
+}
+
+}  // namespace
+
 // Smoothed latent states: the adjoint sweep with the per-TOA moments written
-// in place of the gradient.
+// in place of the gradient. For models 1 and 2 the first call per sample
+// count times the one-wave-per-item sweep against the time-parallel form
+// with the longest pulsars in 2, 4, 8 and 16 chunks and keeps the fastest;
+// ARGUS_SMOOTH = seq | tp2 | tp4 | tp8 | tp16 forces a form.
 int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mean, double* var,
                   double* logl, int32_t* status, hipStream_t st) {
   int rc = ARGUS_OK;
@@ -2233,17 +2673,53 @@ int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mea
   AdjArgs a = adjoint_args(ds, w, theta, S);
   a.smean = mean;
   a.svar = var;
-  if (ds->model == 4)
-    hipLaunchKernelGGL(k_smooth5, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
-  HIPCHK(hipGetLastError());
-  double* ll = logl ? logl : w->logl_tmp.as<double>();
-  int32_t* stat = status ? status : w->stat_tmp.as<int32_t>();
-  ReduceArgs r{w->part.as<double>(), w->pstat.as<int32_t>(), ll, stat, w->counter.as<int32_t>(),
-               S, ds->P};
-  HIPCHK(launch_reduce(r, st));
-  return ARGUS_OK;
+  if (ds->model == 4) return smooth_once(ds, w, a, 1, S, logl, status, st);
+  const char* force = std::getenv("ARGUS_SMOOTH");
+  int forced = 0;
+  if (force && *force) {
+    if (!std::strcmp(force, "seq")) forced = 1;
+    else if (!std::strcmp(force, "tp2")) forced = 2;
+    else if (!std::strcmp(force, "tp4")) forced = 4;
+    else if (!std::strcmp(force, "tp8")) forced = 8;
+    else if (!std::strcmp(force, "tp16")) forced = 16;
+    else return fail(ARGUS_E_INVAL, "ARGUS_SMOOTH: seq, tp2, tp4, tp8 or tp16");
+  }
+  if (forced) return smooth_once(ds, w, a, forced, S, logl, status, st);
+  if (!w->smooth_k) {
+    const std::vector<int> cand = {1, 2, 4, 8, 16};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int pick = 1;
+    w->smooth_log.clear();
+    for (int nw : cand) {
+      float m = 1e30f;
+      for (int rep = 0; rep < 2 && rc == ARGUS_OK; ++rep) {
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
+        if (!rc) rc = smooth_once(ds, w, a, nw, S, logl, status, st);
+        if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = fail(ARGUS_E_HIP, "event");
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "sync");
+        float ms = 0;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "t");
+        if (!rc) m = std::min(m, ms);
+      }
+      if (rc) break;
+      char line[96];
+      std::snprintf(line, sizeof line, "  smoother %s%d: %.3f ms\n", nw == 1 ? "seq" : "tp", nw,
+                    m);
+      w->smooth_log += line;
+      if (m < best) {
+        best = m;
+        pick = nw;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    w->smooth_k = pick;
+  }
+  return smooth_once(ds, w, a, w->smooth_k, S, logl, status, st);
 }
 
 }  // namespace argus
