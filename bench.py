@@ -559,9 +559,12 @@ def main():
                 "ms_per_call": ms6s, "samples_per_s": S6s / (ms6s * 1e-3),
                 "toa_states_per_s": d6.n_toa * S6s / (ms6s * 1e-3),
                 "output_GB": out6 / 1e9,
-                "output_write_GB_per_s": out6 / (ms6s * 1e-3) / 1e9}
-            log("DM smooth: %.3f ms/call, %.1f GB/s of output"
-                % (ms6s, out6 / (ms6s * 1e-3) / 1e9))
+                "output_write_GB_per_s": out6 / (ms6s * 1e-3) / 1e9,
+                "form": next((ln.split(": ", 1)[1] for ln in ds6.tune_info(S6s).split("\n")
+                              if ln.startswith("smoother:")), "")}
+            log("DM smooth: %.3f ms/call, %.1f GB/s of output (%s)"
+                % (ms6s, out6 / (ms6s * 1e-3) / 1e9,
+                   extra["dm_smooth_47psr_1024samples"]["form"]))
             del sm6, sv6
             if not args.no_cpu:
                 import oracle

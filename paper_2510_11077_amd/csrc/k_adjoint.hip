@@ -2087,6 +2087,29 @@ __device__ __forceinline__ void bwd5(double lt[5], double Lt[15], const double K
       Lt[si5(i, k)] = i == 0 ? G[0][k] : (i == 1 ? fma(dt, G[0][k], G[1][k]) : dg[i] * G[i][k]);
 }
 
+// This lane's model-4 parameters for pulsar p, and whether one is not finite.
+__device__ __forceinline__ Lane5 lane5(const AdjArgs& a, int p, int64_t s, bool& pnf) {
+  const int c0 = 6 * p, cc = 6 * a.P;
+  const double t0 = prm(a, c0, s), t1 = prm(a, c0 + 1, s), t2 = prm(a, c0 + 2, s);
+  const double t3 = prm(a, c0 + 3, s), t4 = prm(a, c0 + 4, s), t5 = prm(a, c0 + 5, s);
+  const double t6 = prm(a, cc, s), t7 = prm(a, cc + 1, s);
+  pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) && finite_d(t4) &&
+          finite_d(t5) && finite_d(t6) && finite_d(t7));
+  Lane5 L;
+  L.gr = exp10(t1);
+  L.gd = exp10(t5);
+  const double sr = exp10(t0), sdm = exp10(t4), eq = exp10(t3);
+  L.vr = sr * sr / (2.0 * L.gr);
+  L.vd = sdm * sdm / (2.0 * L.gd);
+  const double gm1 = t7 - 1.0;
+  L.vc = exp(2.0 * kLn10 * t6 + (t7 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+         (12.0 * kPi * kPi * gm1);
+  L.efac2 = t2 * t2;
+  L.equad2 = eq * eq;
+  L.ss2 = a.mc.ss2;
+  return L;
+}
+
 __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
   constexpr int NS = 5, NP = 15;
   const int lane = threadIdx.x & (kWave - 1);
@@ -2110,24 +2133,8 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
     const int c1 = a.c1[p];
     double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kF5 * kWave;
 
-    const int c0 = 6 * p, cc = 6 * a.P;
-    const double t0 = prm(a, c0, s), t1 = prm(a, c0 + 1, s), t2 = prm(a, c0 + 2, s);
-    const double t3 = prm(a, c0 + 3, s), t4 = prm(a, c0 + 4, s), t5 = prm(a, c0 + 5, s);
-    const double t6 = prm(a, cc, s), t7 = prm(a, cc + 1, s);
-    const bool pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) &&
-                       finite_d(t4) && finite_d(t5) && finite_d(t6) && finite_d(t7));
-    Lane5 L;
-    L.gr = exp10(t1);
-    L.gd = exp10(t5);
-    const double sr = exp10(t0), sdm = exp10(t4), eq = exp10(t3);
-    L.vr = sr * sr / (2.0 * L.gr);
-    L.vd = sdm * sdm / (2.0 * L.gd);
-    const double gm1 = t7 - 1.0;
-    L.vc = exp(2.0 * kLn10 * t6 + (t7 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
-           (12.0 * kPi * kPi * gm1);
-    L.efac2 = t2 * t2;
-    L.equad2 = eq * eq;
-    L.ss2 = a.mc.ss2;
+    bool pnf;
+    const Lane5 L = lane5(a, p, s, pnf);
 
     // forward pass: log-likelihood and level-1 checkpoints (the state
     // before the first TOA of each segment of c1 TOAs)
@@ -2203,6 +2210,245 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
     if (valid) {
       a.part[(int64_t)p * a.S + s] = ll;
       a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+  }
+}
+
+// Time-parallel form of the model-4 smoother, as k_smooth_fwd / k_smooth_rev
+// for models 1 and 2: the summary of a chunk is U (5 x 5, row major), phi (5)
+// and Om (15) with F = diag(1, 1, phi_r, phi_c, phi_d) + dt e_0 e_1^T and
+// h = [1, 0, 1, 1, c] per TOA; a chunk's place holds the pair (lt, Lt) after
+// its last TOA as a saved state's 20 fields (the last chunk starts from zero
+// and, like k_smooth5, recomputes each TOA's filtered state itself).
+constexpr int kSum5 = 45;
+
+__global__ void __launch_bounds__(256) k_smooth5_fwd(AdjArgs a) {
+  constexpr int NS = 5, NP = 15;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int it = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  if (it >= a.n_items) return;
+  const RecPtr rec = (RecPtr)a.rec;
+  const ConstDPtr chrom = (ConstDPtr)a.chrom;
+  const int tile = a.items[2 * it];
+  const int p = a.items[2 * it + 1];
+  const int64_t s_raw = (int64_t)tile * kWave + lane;
+  const bool valid = s_raw < a.S;
+  const int64_t s = valid ? s_raw : a.S - 1;
+  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+  const int c1 = a.c1[p];
+  const int nseg = (N + c1 - 1) / c1;
+  const int nch = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it]);
+  const int64_t base = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it + 1]);
+  double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kF5 * kWave;
+  bool pnf;
+  const Lane5 L = lane5(a, p, s, pnf);
+
+  St5 st;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) st.x[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) st.P[i] = 0.0;
+  st.P[si5(0, 0)] = a.mc.s_r2;
+  st.P[si5(1, 1)] = a.mc.s_f2;
+  st.P[si5(2, 2)] = L.vr;
+  st.P[si5(3, 3)] = L.vc;
+  st.P[si5(4, 4)] = L.vd;
+  double quad = 0.0, lm = 1.0;
+  int le = 0, stat = pnf ? kPNF : 0;
+  double U[NS][NS], phi[NS], Om[NP];
+  // one TOA: checkpoint, filter step and log-likelihood terms, and with
+  // ACC the chunk summary
+  auto step = [&](int k, auto acc) {
+    if (k % c1 == 0) put_st5(ck + (int64_t)(k / c1) * kF5 * kWave, lane, st);
+    const TOARec r = load_rec(rec, kb + k);
+    const double ch = chrom[kb + k];
+    double K[NS], S, e;
+    fwd5(st, r, ch, L, K, S, e);
+    const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+    if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+    const double inv = rcp_nr(S);
+    quad = fma(e * e, inv, quad);
+    const double pm = lm * S;
+    lm = __builtin_amdgcn_frexp_mant(pm);
+    le += __builtin_amdgcn_frexp_exp(pm);
+    if constexpr (decltype(acc)::value) {
+      const double dt = r.dt, ei = -e * inv;
+      const double dg[NS] = {1.0, 1.0, 1.0 + expm1_k(-L.gr * dt), r.phc,
+                             1.0 + expm1_k(-L.gd * dt)};
+      double V[NS][NS], v[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        V[i][0] = fma(dt, U[i][1], U[i][0]);
+        V[i][1] = U[i][1];
+#pragma unroll
+        for (int j = 2; j < NS; ++j) V[i][j] = dg[j] * U[i][j];
+        v[i] = fma(ch, V[i][4], V[i][0] + V[i][2] + V[i][3]);
+        phi[i] = fma(v[i], ei, phi[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const double vs = v[i] * inv;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) Om[si5(i, j)] = fma(vs, v[j], Om[si5(i, j)]);
+#pragma unroll
+        for (int j = 0; j < NS; ++j) U[i][j] = fma(-v[i], K[j], V[i][j]);
+      }
+    }
+  };
+  const std::integral_constant<bool, false> no_acc;
+  const std::integral_constant<bool, true> with_acc;
+  int k = 0;
+  const int e0 = (nseg / nch) * c1 < N ? (nseg / nch) * c1 : N;
+  for (; k < e0; ++k) step(k, no_acc);
+  for (int c = 1; c < nch; ++c) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) U[i][q] = i == q ? 1.0 : 0.0;
+      phi[i] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) Om[i] = 0.0;
+    const int sh = (c + 1) * nseg / nch;
+    const int ec = sh * c1 < N ? sh * c1 : N;
+    for (; k < ec; ++k) step(k, with_acc);
+    double* o = a.tpsum + (base + c) * kSum5 * kWave + lane;
+#pragma unroll
+    for (int i = 0; i < NS * NS; ++i) o[i * kWave] = U[i / NS][i % NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) o[(NS * NS + i) * kWave] = phi[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) o[(30 + i) * kWave] = Om[i];
+  }
+  double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+  if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+  if (stat) ll = -INFINITY;
+  if (valid) {
+    a.part[(int64_t)p * a.S + s] = ll;
+    a.pstat[(int64_t)p * a.S + s] = stat;
+  }
+  // chain the summaries from the last chunk back
+  St5 pr;  // (lt, Lt) in a saved state's fields
+#pragma unroll
+  for (int i = 0; i < NS; ++i) pr.x[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) pr.P[i] = 0.0;
+  for (int c = nch - 1; c >= 1; --c) {
+    const double* o = a.tpsum + (base + c) * kSum5 * kWave + lane;
+    double Uc[NS][NS], T[NS][NS], nl[NS];
+#pragma unroll
+    for (int i = 0; i < NS * NS; ++i) Uc[i / NS][i % NS] = o[i * kWave];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      double acc = o[(NS * NS + i) * kWave];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        acc = fma(Uc[i][q], pr.x[q], acc);
+        double tq = 0.0;
+#pragma unroll
+        for (int l = 0; l < NS; ++l) tq = fma(Uc[i][l], pr.P[si5(l, q)], tq);
+        T[i][q] = tq;
+      }
+      nl[i] = acc;
+    }
+    double nL[NP];
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int q = 0; q <= i; ++q) {
+        double acc = o[(30 + si5(i, q)) * kWave];
+#pragma unroll
+        for (int l = 0; l < NS; ++l) acc = fma(T[i][l], Uc[q][l], acc);
+        nL[si5(i, q)] = acc;
+      }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) pr.x[i] = nl[i];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) pr.P[i] = nL[i];
+    put_st5(a.tpadj + (base + c - 1) * kF5 * kWave, lane, pr);
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_smooth5_rev(AdjArgs a) {
+  constexpr int NS = 5, NP = 15;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int gwave = __builtin_amdgcn_readfirstlane(
+      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  double* scr = a.scratch + (int64_t)gwave * a.max_sub * kF5 * kWave;
+  const RecPtr rec = (RecPtr)a.rec;
+  const ConstDPtr chrom = (ConstDPtr)a.chrom;
+  for (;;) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(a.counter, 1);
+    const int u = __builtin_amdgcn_readfirstlane(v);
+    if (u >= a.n_units) break;
+    const int it = a.tp_units[2 * u];
+    const int cch = a.tp_units[2 * u + 1];
+    const int tile = a.items[2 * it];
+    const int p = a.items[2 * it + 1];
+    const int64_t s_raw = (int64_t)tile * kWave + lane;
+    const bool valid = s_raw < a.S;
+    const int64_t s = valid ? s_raw : a.S - 1;
+    const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+    const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+    const int c1 = a.c1[p];
+    const int nseg = (N + c1 - 1) / c1;
+    const int nch = a.tp_item[2 * it];
+    const int64_t base = a.tp_item[2 * it + 1];
+    const int sg_lo = cch * nseg / nch, sg_hi = (cch + 1) * nseg / nch;
+    const double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kF5 * kWave;
+    bool pnf;
+    const Lane5 L = lane5(a, p, s, pnf);
+    const bool bad = a.pstat[(int64_t)p * a.S + s] != 0;
+    double lt[NS], Lt[NP];
+    if (cch == nch - 1) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) lt[i] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) Lt[i] = 0.0;
+    } else {
+      const St5 pr = get_st5(a.tpadj + (base + cch) * kF5 * kWave, lane);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) lt[i] = pr.x[i];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) Lt[i] = pr.P[i];
+    }
+    // the backward pass of k_smooth5 over this chunk's segments
+    for (int sg = sg_hi - 1; sg >= sg_lo; --sg) {
+      const int k0 = sg * c1;
+      const int k1 = k0 + c1 < N ? k0 + c1 : N;
+      const int nsub = (k1 - k0 + 3) / 4;
+      St5 cur = get_st5(ck + (int64_t)sg * kF5 * kWave, lane);
+      for (int t = 0; t < nsub; ++t) {
+        put_st5(scr + (int64_t)t * kF5 * kWave, lane, cur);
+        if (t + 1 < nsub) {
+          for (int i = 0; i < 4; ++i) {
+            double K[NS], S, e;
+            const int k = k0 + 4 * t + i;
+            fwd5(cur, load_rec(rec, kb + k), chrom[kb + k], L, K, S, e);
+          }
+        }
+      }
+      for (int t = nsub - 1; t >= 0; --t) {
+        const int ks = k0 + 4 * t;
+        const int nt = k1 - ks < 4 ? k1 - ks : 4;
+        const St5 s0 = get_st5(scr + (int64_t)t * kF5 * kWave, lane);
+        for (int i = nt - 1; i >= 0; --i) {
+          St5 c = s0;
+          double K[NS], S, e;
+          for (int j = 0; j < i; ++j)
+            fwd5(c, load_rec(rec, kb + ks + j), chrom[kb + ks + j], L, K, S, e);
+          const int k = ks + i;
+          const TOARec r = load_rec(rec, kb + k);
+          const double ch = chrom[kb + k];
+          fwd5(c, r, ch, L, K, S, e);
+          if (valid) put_smooth5(a, kb + k, s, c, lt, Lt, bad);
+          bwd5(lt, Lt, K, S, e, ch, r, L);
+        }
+      }
     }
   }
 }
@@ -2608,9 +2854,13 @@ int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
   }
   const int waves = (int)std::min<int64_t>((int64_t)units.size(), 8LL * ds->n_cu);
   w->tp_waves = ((std::max(waves, 1) + 3) / 4) * 4;
-  const size_t need_sum = (size_t)std::max<int64_t>(slots, 1) * kSum * kWave * sizeof(double);
-  const size_t need_adj = (size_t)std::max<int64_t>(slots, 1) * kFields * kWave * sizeof(double);
-  const size_t need_scr = (size_t)w->tp_waves * w->max_sub * kFields * kWave * sizeof(double);
+  const bool m4 = ds->model == 4;
+  const size_t need_sum =
+      (size_t)std::max<int64_t>(slots, 1) * (m4 ? kSum5 : kSum) * kWave * sizeof(double);
+  const size_t need_adj =
+      (size_t)std::max<int64_t>(slots, 1) * (m4 ? kF5 : kFields) * kWave * sizeof(double);
+  const size_t need_scr =
+      (size_t)w->tp_waves * w->max_sub * (m4 ? kF5 : kFields) * kWave * sizeof(double);
   int rc;
   if ((rc = w->tp_item.upload(item.data(), item.size() * sizeof(int32_t))) ||
       (rc = w->tp_units.upload(uh.data(), uh.size() * sizeof(int32_t))))
@@ -2629,11 +2879,11 @@ int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
 int smooth_once(argus_dataset* ds, Workspace* w, const AdjArgs& a, int nw, int64_t S,
                 double* logl, int32_t* status, hipStream_t st) {
   int rc;
-  if (ds->model == 4) {
-    hipLaunchKernelGGL(k_smooth5, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
-    HIPCHK(hipGetLastError());
-  } else if (nw == 1) {
-    hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+  if (nw == 1) {
+    if (ds->model == 4)
+      hipLaunchKernelGGL(k_smooth5, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_adjoint<true>, dim3(w->grad_waves / 4), dim3(256), 0, st, a);
     HIPCHK(hipGetLastError());
   } else {
     if ((rc = smooth_tp_setup(ds, w, nw))) return rc;
@@ -2644,9 +2894,15 @@ int smooth_once(argus_dataset* ds, Workspace* w, const AdjArgs& a, int nw, int64
     b.tpadj = w->tp_adj.as<double>();
     b.scratch = w->tp_scr.as<double>();
     b.n_units = w->n_tp_units;
-    hipLaunchKernelGGL(k_smooth_fwd, dim3((w->n_items + 3) / 4), dim3(256), 0, st, b);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_smooth_rev, dim3(w->tp_waves / 4), dim3(256), 0, st, b);
+    if (ds->model == 4) {
+      hipLaunchKernelGGL(k_smooth5_fwd, dim3((w->n_items + 3) / 4), dim3(256), 0, st, b);
+      HIPCHK(hipGetLastError());
+      hipLaunchKernelGGL(k_smooth5_rev, dim3(w->tp_waves / 4), dim3(256), 0, st, b);
+    } else {
+      hipLaunchKernelGGL(k_smooth_fwd, dim3((w->n_items + 3) / 4), dim3(256), 0, st, b);
+      HIPCHK(hipGetLastError());
+      hipLaunchKernelGGL(k_smooth_rev, dim3(w->tp_waves / 4), dim3(256), 0, st, b);
+    }
     HIPCHK(hipGetLastError());
   }
   double* ll = logl ? logl : w->logl_tmp.as<double>();
@@ -2659,9 +2915,9 @@ int smooth_once(argus_dataset* ds, Workspace* w, const AdjArgs& a, int nw, int64
 
 }  // namespace
 
-// Smoothed latent states: the adjoint sweep with the per-TOA moments written
-// in place of the gradient. For models 1 and 2 the first call per sample
-// count times the one-wave-per-item sweep against the time-parallel form
+// Smoothed latent states: the filter pass with checkpoints and the
+// Bryson-Frazier recursion back over it. The first call per sample count
+// times the one-wave-per-item sweep against the time-parallel form
 // with the longest pulsars in 2, 4, 8 and 16 chunks and keeps the fastest;
 // ARGUS_SMOOTH = seq | tp2 | tp4 | tp8 | tp16 forces a form.
 int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mean, double* var,
@@ -2673,7 +2929,6 @@ int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mea
   AdjArgs a = adjoint_args(ds, w, theta, S);
   a.smean = mean;
   a.svar = var;
-  if (ds->model == 4) return smooth_once(ds, w, a, 1, S, logl, status, st);
   const char* force = std::getenv("ARGUS_SMOOTH");
   int forced = 0;
   if (force && *force) {

@@ -37,8 +37,8 @@ def argus():
 
 @pytest.fixture(params=["auto", "seq", "tp2", "tp4", "tp16"])
 def form(request, monkeypatch):
-    """Smoother form of models 1 and 2: the tuner's choice, the one-wave-per-
-    item sweep, or the time-parallel form with the longest pulsar in 2, 4 or
+    """Smoother form: the tuner's choice, the one-wave-per-item sweep, or the
+    time-parallel form with the longest pulsar in 2, 4 or
     16 chunks (shorter pulsars in proportionally fewer, at most one per
     level-1 segment)."""
     if request.param == "auto":
@@ -199,7 +199,7 @@ def test_spin_noise_after_a_long_gap(argus, orc, form):
 
 
 @pytest.mark.parametrize("S", [1, 70])
-def test_dm_model_ragged_tiles(argus, orc, S):
+def test_dm_model_ragged_tiles(argus, orc, form, S):
     """Model 4 (state r, f, a, g, m; chromatic factor per TOA): empty,
     one-TOA and ragged pulsars, partial tiles."""
     d = pi.make_pta_dm("t", n_psr=6, counts=[1, 0, 37, 64, 130, 257], seed=61)
@@ -208,7 +208,7 @@ def test_dm_model_ragged_tiles(argus, orc, S):
     assert m.shape[2] == 5
 
 
-def test_dm_model_long_pulsar_near_truth(argus, orc):
+def test_dm_model_long_pulsar_near_truth(argus, orc, form):
     """Several checkpoint segments and 4-TOA pieces, and posteriors much
     tighter than the priors."""
     d = pi.make_pta_dm("t", n_psr=2, counts=[1500, 333], seed=63)
@@ -216,7 +216,7 @@ def test_dm_model_long_pulsar_near_truth(argus, orc):
     run(argus, orc, d, th)
 
 
-def test_dm_model_prior_corners(argus, orc):
+def test_dm_model_prior_corners(argus, orc, form):
     d = pi.make_pta_dm("t", n_psr=3, counts=[40, 25, 60], seed=65)
     lo, hi = d.lo[d.free], d.hi[d.free]
     rng = np.random.default_rng(66)
@@ -224,7 +224,7 @@ def test_dm_model_prior_corners(argus, orc):
     run(argus, orc, d, th)
 
 
-def test_dm_full_batch_sampled(argus, orc):
+def test_dm_full_batch_sampled(argus, orc, form):
     """47 pulsars with DM variations (about 37k TOAs), 1024 samples, launched
     as the benchmark launches it; the oracle checks three samples."""
     import torch
@@ -241,7 +241,7 @@ def test_dm_full_batch_sampled(argus, orc):
     check(m, v, rm, rv)
 
 
-def test_dm_failures(argus, orc):
+def test_dm_failures(argus, orc, form):
     """Model 4: a non-finite DM parameter of one pulsar makes only that
     pulsar's entries NaN; a non-finite common parameter makes all of them NaN;
     the status words follow the oracle's."""
