@@ -365,32 +365,42 @@ struct LaneTheta {
   bool pnf;
 };
 __device__ __forceinline__ LaneTheta lane_theta(const AdjArgs& a, int p, int64_t s) {
-  LaneTheta o;
+  // scalar locals in both branches (an aggregate assigned in each branch
+  // would be merged through private memory)
+  double gr, vr, vc, efac2, equad2, ss2, t1, t2, t5;
+  bool pnf;
   if (a.model == 1) {
     const double t0 = prm(a, 0, s);  // log10 sigma_s
-    o.t1 = prm(a, 1, s);             // EFAC
-    o.pnf = !(finite_d(t0) && finite_d(o.t1));
+    t1 = prm(a, 1, s);               // EFAC
+    pnf = !(finite_d(t0) && finite_d(t1));
     const double ss = exp10(t0);
-    o.L = LaneP{1.0, 0.0, 0.0, o.t1 * o.t1, 0.0, ss * ss};
-    o.t2 = 0.0;
-    o.t5 = 2.0;
+    gr = 1.0;
+    vr = vc = equad2 = 0.0;
+    efac2 = t1 * t1;
+    ss2 = ss * ss;
+    t2 = 0.0;
+    t5 = 2.0;
   } else {
     const int c0 = 4 * p, cc = 4 * a.P;
     const double t0 = prm(a, c0, s);
-    o.t1 = prm(a, c0 + 1, s);
-    o.t2 = prm(a, c0 + 2, s);
+    t1 = prm(a, c0 + 1, s);
+    t2 = prm(a, c0 + 2, s);
     const double t3 = prm(a, c0 + 3, s);
     const double t4 = prm(a, cc, s);
-    o.t5 = prm(a, cc + 1, s);
-    o.pnf = !(finite_d(t0) && finite_d(o.t1) && finite_d(o.t2) && finite_d(t3) &&
-              finite_d(t4) && finite_d(o.t5));
-    const double gr = exp10(o.t1), sr = exp10(t0), eq = exp10(t3);
-    const double gm1 = o.t5 - 1.0;
-    const double vc = exp(2.0 * kLn10 * t4 + (o.t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
-                      (12.0 * kPi * kPi * gm1);
-    o.L = LaneP{gr, sr * sr / (2.0 * gr), vc, o.t2 * o.t2, eq * eq, a.mc.ss2};
+    t5 = prm(a, cc + 1, s);
+    pnf = !(finite_d(t0) && finite_d(t1) && finite_d(t2) && finite_d(t3) && finite_d(t4) &&
+            finite_d(t5));
+    gr = exp10(t1);
+    const double sr = exp10(t0), eq = exp10(t3);
+    const double gm1 = t5 - 1.0;
+    vc = exp(2.0 * kLn10 * t4 + (t5 - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+         (12.0 * kPi * kPi * gm1);
+    vr = sr * sr / (2.0 * gr);
+    efac2 = t2 * t2;
+    equad2 = eq * eq;
+    ss2 = a.mc.ss2;
   }
-  return o;
+  return LaneTheta{LaneP{gr, vr, vc, efac2, equad2, ss2}, t1, t2, t5, pnf};
 }
 
 // What the reverse sweep carries and does per TOA. The gradient: the
@@ -602,11 +612,11 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
 //   V = U F^T, v = V h, phi -= v e / S, Om += v v^T / S, U = V - v K^T.
 // An item (64-sample tile, pulsar) is split into nch chunks of whole level-1
 // segments (chunk c: segments c nseg / nch .. (c + 1) nseg / nch - 1).
-// k_smooth_fwd (one wave per item) runs the forward filter over the whole
-// stream (log-likelihood, level-1 checkpoints, the summaries of chunks
-// 1 .. nch - 1), chains the summaries from the last chunk back (the pair
-// after the last TOA is zero) and stores the pair after the last TOA of
-// every chunk but the last, and the final filtered state in the last
+// k_smooth_fwd_pc (one workgroup per item) runs the forward filter over the
+// whole stream (log-likelihood, level-1 checkpoints, the summaries of
+// chunks 1 .. nch - 1), chains the summaries from the last chunk back (the
+// pair after the last TOA is zero) and stores the pair after the last TOA
+// of every chunk but the last, and the final filtered state in the last
 // chunk's place. k_smooth_rev then runs the checkpointed reverse sweep of
 // every (item, chunk) unit independently, longest chunks first. An item's
 // serial chain drops from a forward and a reverse pass over its N TOAs to a
@@ -617,113 +627,11 @@ __host__ __device__ constexpr int si4(int i, int j) {
   return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
 }
 
-__global__ void __launch_bounds__(256) k_smooth_fwd(AdjArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int it = __builtin_amdgcn_readfirstlane(
-      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
-  if (it >= a.n_items) return;
-  const int tile = a.items[2 * it];
-  const int p = a.items[2 * it + 1];
-  const int64_t s_raw = (int64_t)tile * kWave + lane;
-  const bool valid = s_raw < a.S;
-  const int64_t s = valid ? s_raw : a.S - 1;
-  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
-  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
-  const int c1 = a.c1[p];
-  const int nseg = (N + c1 - 1) / c1;
-  const int nch = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it]);
-  const int64_t base = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it + 1]);
-  double* ckw = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
-  const LaneTheta th = lane_theta(a, p, s);
-  const LaneP L = th.L;
-  const RecBuf rb = rec_buffer(a.rec + kb, N);
-
-  State st{0.0, 0.0, 0.0, 0.0,
-           Cov4{a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, 0.0, L.vr, 0.0, 0.0, 0.0, L.vc}};
-  double quad = 0.0, lm = 1.0;
-  int le = 0, stat = th.pnf ? kPNF : 0;
-  int kc = 0;  // position within the current level-1 segment
-  TOARec rq{};
-  if (N > 0) rq = load_rec_vgpr(rb, 0);
-  double U[4][4], phi[4], Om[10];
-  // one TOA: checkpoint, filter step and log-likelihood terms, and with
-  // ACC the chunk summary
-  auto step = [&](int k, auto acc) {
-    const TOARec r = rq;
-    rq = load_rec_vgpr(rb, k + 1 < N ? k + 1 : k);
-    if (kc == 0) {
-      put_state(ckw, lane, st);
-      ckw += kFields * kWave;
-    }
-    kc = kc + 1 == c1 ? 0 : kc + 1;
-    double S, e, inv, kk[4], ph;
-    fwd_step(st, r, L, S, e, inv, kk, ph);
-    const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
-    if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
-    quad = fma(e * e, inv, quad);
-    const double pm = lm * S;
-    lm = __builtin_amdgcn_frexp_mant(pm);
-    le += __builtin_amdgcn_frexp_exp(pm);
-    if constexpr (decltype(acc)::value) {
-      const double dt = r.dt, phc = r.phc, ei = -e * inv;
-      double V[4][4], v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        V[i][0] = fma(dt, U[i][1], U[i][0]);
-        V[i][1] = U[i][1];
-        V[i][2] = ph * U[i][2];
-        V[i][3] = phc * U[i][3];
-        v[i] = V[i][0] + V[i][2] + V[i][3];
-        phi[i] = fma(v[i], ei, phi[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double vs = v[i] * inv;
-#pragma unroll
-        for (int c = 0; c <= i; ++c) Om[si4(i, c)] = fma(vs, v[c], Om[si4(i, c)]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) U[i][c] = fma(-v[i], kk[c], V[i][c]);
-      }
-    }
-  };
-  const std::integral_constant<bool, false> no_acc;
-  const std::integral_constant<bool, true> with_acc;
-  // chunk 0 needs no summary
-  int k = 0;
-  const int e0 = (nseg / nch) * c1 < N ? (nseg / nch) * c1 : N;
-  for (; k < e0; ++k) step(k, no_acc);
-  for (int c = 1; c < nch; ++c) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) U[i][q] = i == q ? 1.0 : 0.0;
-      phi[i] = 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < 10; ++i) Om[i] = 0.0;
-    const int sh = (c + 1) * nseg / nch;
-    const int ec = sh * c1 < N ? sh * c1 : N;
-    for (; k < ec; ++k) step(k, with_acc);
-    double* o = a.tpsum + (base + c) * kSum * kWave + lane;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) o[i * kWave] = U[i / 4][i % 4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[(16 + i) * kWave] = phi[i];
-#pragma unroll
-    for (int i = 0; i < 10; ++i) o[(20 + i) * kWave] = Om[i];
-  }
-  double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
-  if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
-  if (stat) ll = -INFINITY;
-  if (valid) {
-    a.part[(int64_t)p * a.S + s] = ll;
-    a.pstat[(int64_t)p * a.S + s] = stat;
-  }
-  // the final filtered state, in the last chunk's place
-  put_state(a.tpadj + (base + nch - 1) * kFields * kWave, lane, st);
-  // chain the summaries from the last chunk back; the pair after the last
-  // TOA of chunk c - 1 goes to chunk c - 1's place (lam, then Lam in the
-  // order of a covariance)
+// The chain of the chunk summaries of one item, from the last chunk back:
+// the pair after the last TOA of chunk c - 1 goes to chunk c - 1's place
+// (lam, then Lam in the order of a covariance); the pair after the last TOA
+// is zero. The summaries are this wave's own writes.
+__device__ __forceinline__ void smooth_chain(const AdjArgs& a, int64_t base, int nch, int lane) {
   double lam[4] = {0.0, 0.0, 0.0, 0.0}, Lam[10];
 #pragma unroll
   for (int i = 0; i < 10; ++i) Lam[i] = 0.0;
@@ -760,6 +668,179 @@ __global__ void __launch_bounds__(256) k_smooth_fwd(AdjArgs a) {
               State{lam[0], lam[1], lam[2], lam[3],
                     Cov4{Lam[0], Lam[1], Lam[2], Lam[3], Lam[4], Lam[5], Lam[6], Lam[7], Lam[8],
                          Lam[9]}});
+  }
+}
+
+// Forward pass of the time-parallel smoother: one workgroup of two waves per
+// item. Wave 0 runs the filter (log-likelihood, level-1 checkpoints, final
+// state) and hands, per TOA, the gain, e, 1/S, the red decay, dt and the
+// common decay (kSmVals values per lane) to wave 1 through a double-buffered
+// LDS ring of kSmSteps TOAs per buffer; wave 1 accumulates the chunk
+// summaries one block behind and chains them. Barrier b separates wave 0's
+// writes of block b from wave 1's reads of it and wave 1's reads of block
+// b - 1 from wave 0's rewrite of that buffer; both waves execute nblk + 1
+// barriers. The filter's serial chain carries no summary arithmetic, which
+// lets its blocks be straight-line code (with the summaries inline, the
+// scheduler's overlap of four steps ran out of registers).
+constexpr int kSmSteps = 4, kSmVals = 9;
+
+__global__ void __launch_bounds__(2 * kWave) k_smooth_fwd_pc(AdjArgs a) {
+  __shared__ double s_ring[2 * kSmSteps * kSmVals * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int it = blockIdx.x;
+  const int tile = a.items[2 * it];
+  const int p = a.items[2 * it + 1];
+  const int64_t s_raw = (int64_t)tile * kWave + lane;
+  const bool valid = s_raw < a.S;
+  const int64_t s = valid ? s_raw : a.S - 1;
+  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+  const int c1 = a.c1[p];
+  const int nseg = (N + c1 - 1) / c1;
+  const int nch = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it]);
+  const int64_t base = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it + 1]);
+  const int nblk = (N + kSmSteps - 1) / kSmSteps;
+  double* ring = s_ring + lane;  // value v of step j of buffer b at ((b kSmSteps + j) kSmVals + v) kWave
+
+  if (wave == 0) {
+    double* ckw = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kFields * kWave;
+    const LaneTheta th = lane_theta(a, p, s);
+    const LaneP L = th.L;
+    const RecBuf rb = rec_buffer(a.rec + kb, N);
+    State st{0.0, 0.0, 0.0, 0.0,
+             Cov4{a.mc.s_r2, 0.0, a.mc.s_f2, 0.0, 0.0, L.vr, 0.0, 0.0, 0.0, L.vc}};
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = th.pnf ? kPNF : 0;
+    // one TOA: filter step, hand-over values, log-likelihood terms
+    auto step = [&](const TOARec& r, double* rv) {
+      double S, e, inv, kk[4], ph;
+      fwd_step(st, r, L, S, e, inv, kk, ph);
+      rv[0 * kWave] = kk[0];
+      rv[1 * kWave] = kk[1];
+      rv[2 * kWave] = kk[2];
+      rv[3 * kWave] = kk[3];
+      rv[4 * kWave] = e;
+      rv[5 * kWave] = inv;
+      rv[6 * kWave] = ph;
+      rv[7 * kWave] = r.dt;
+      rv[8 * kWave] = r.phc;
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e * e, inv, quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    };
+    // the records of block blk + 1 are fetched while block blk is filtered
+    // (indices clamped to the last TOA); a full block is straight-line code,
+    // so the steps' record-only work (the decays) overlaps the previous
+    // step's chain. Level-1 segments start at block starts (c1 is a
+    // multiple of kSmSteps).
+    TOARec q[kSmSteps], qn[kSmSteps];
+#pragma unroll
+    for (int j = 0; j < kSmSteps; ++j) q[j] = load_rec_vgpr(rb, j < N ? j : (N > 0 ? N - 1 : 0));
+    for (int blk = 0; blk <= nblk; ++blk) {
+      double* rbuf = ring + (blk & 1) * kSmSteps * kSmVals * kWave;
+      if (blk < nblk) {
+        const int k0 = blk * kSmSteps;
+#pragma unroll
+        for (int j = 0; j < kSmSteps; ++j) {
+          const int kn = k0 + kSmSteps + j;
+          qn[j] = load_rec_vgpr(rb, kn < N ? kn : N - 1);
+        }
+        if (k0 % c1 == 0) put_state(ckw + (int64_t)(k0 / c1) * kFields * kWave, lane, st);
+        if (k0 + kSmSteps <= N) {
+#pragma unroll
+          for (int j = 0; j < kSmSteps; ++j) step(q[j], rbuf + j * kSmVals * kWave);
+        } else {
+          for (int j = 0; j < N - k0; ++j) {
+            // the tail: at most kSmSteps - 1 steps, records selected by index
+            const TOARec r = j == 0 ? q[0] : (j == 1 ? q[1] : q[2]);
+            step(r, rbuf + j * kSmVals * kWave);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kSmSteps; ++j) q[j] = qn[j];
+      }
+      __syncthreads();
+    }
+    double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+    if (stat) ll = -INFINITY;
+    if (valid) {
+      a.part[(int64_t)p * a.S + s] = ll;
+      a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+    put_state(a.tpadj + (base + nch - 1) * kFields * kWave, lane, st);
+  } else {
+    // chunk summaries, one block behind the filter
+    double U[4][4], phi[4], Om[10];
+    auto reset = [&]() {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U[i][q] = i == q ? 1.0 : 0.0;
+        phi[i] = 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 10; ++i) Om[i] = 0.0;
+    };
+    reset();
+    int c = 0;  // chunk of the next TOA and its end
+    int ec = (nseg / nch) * c1 < N ? (nseg / nch) * c1 : N;
+    for (int blk = 0; blk <= nblk; ++blk) {
+      if (blk > 0) {
+        const double* rbuf = ring + ((blk - 1) & 1) * kSmSteps * kSmVals * kWave;
+#pragma unroll 1
+        for (int j = 0; j < kSmSteps; ++j) {
+          const int k = (blk - 1) * kSmSteps + j;
+          if (k >= N) break;
+          if (c > 0) {
+            const double* rv = rbuf + j * kSmVals * kWave;
+            const double kk[4] = {rv[0 * kWave], rv[1 * kWave], rv[2 * kWave], rv[3 * kWave]};
+            const double e = rv[4 * kWave], inv = rv[5 * kWave], ph = rv[6 * kWave];
+            const double dt = rv[7 * kWave], phc = rv[8 * kWave];
+            const double ei = -e * inv;
+            double V[4][4], v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              V[i][0] = fma(dt, U[i][1], U[i][0]);
+              V[i][1] = U[i][1];
+              V[i][2] = ph * U[i][2];
+              V[i][3] = phc * U[i][3];
+              v[i] = V[i][0] + V[i][2] + V[i][3];
+              phi[i] = fma(v[i], ei, phi[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double vs = v[i] * inv;
+#pragma unroll
+              for (int q = 0; q <= i; ++q) Om[si4(i, q)] = fma(vs, v[q], Om[si4(i, q)]);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) U[i][q] = fma(-v[i], kk[q], V[i][q]);
+            }
+          }
+          if (k + 1 == ec) {
+            if (c > 0) {
+              double* o = a.tpsum + (base + c) * kSum * kWave + lane;
+#pragma unroll
+              for (int i = 0; i < 16; ++i) o[i * kWave] = U[i / 4][i % 4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) o[(16 + i) * kWave] = phi[i];
+#pragma unroll
+              for (int i = 0; i < 10; ++i) o[(20 + i) * kWave] = Om[i];
+            }
+            reset();
+            ++c;
+            const int sh = (c + 1) * nseg / nch;
+            ec = sh * c1 < N ? sh * c1 : N;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    smooth_chain(a, base, nch, lane);
   }
 }
 
@@ -1935,11 +2016,14 @@ __device__ __forceinline__ St5 get_st5(const double* base, int lane) {
 // One filter step of TOA (record r, chromatic factor c) in place; returns
 // the gain, innovation variance and innovation.
 __device__ __forceinline__ void fwd5(St5& s, const TOARec& r, double c, const Lane5& L,
-                                     double K[5], double& S, double& e) {
+                                     double K[5], double& S, double& e, double& phr,
+                                     double& phd) {
   constexpr int NS = 5, NP = 15;
   const double dt = r.dt;
   const double em = expm1_k(-L.gr * dt), emd = expm1_k(-L.gd * dt);
   const double dg[NS] = {1.0, 1.0, 1.0 + em, r.phc, 1.0 + emd};  // diagonal part of F
+  phr = dg[2];
+  phd = dg[4];
   double FP[NS][NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
@@ -2004,6 +2088,11 @@ __device__ __forceinline__ void fwd5(St5& s, const TOARec& r, double c, const La
   for (int i = 0; i < NS; ++i)
 #pragma unroll
     for (int j = i; j < NS; ++j) s.P[si5(i, j)] = fma(z[i], K[j], W[i][j]);
+}
+__device__ __forceinline__ void fwd5(St5& s, const TOARec& r, double c, const Lane5& L,
+                                     double K[5], double& S, double& e) {
+  double phr, phd;
+  fwd5(s, r, c, L, K, S, e, phr, phd);
 }
 
 // Smoothed mean and variance of TOA k from its filtered state and the
@@ -2087,6 +2176,72 @@ __device__ __forceinline__ void bwd5(double lt[5], double Lt[15], const double K
       Lt[si5(i, k)] = i == 0 ? G[0][k] : (i == 1 ? fma(dt, G[0][k], G[1][k]) : dg[i] * G[i][k]);
 }
 
+// The model-4 backward pass over level-1 segments sg_hi - 1 down to sg_lo
+// (ck: the level-1 checkpoints; scr: this wave's level-2 scratch), from the
+// pair (lt, Lt) after the last TOA of segment sg_hi - 1: each segment is
+// recomputed to level-2 checkpoints every 4 TOAs, then its 4-TOA pieces are
+// taken last first, each TOA's filtered state recomputed from its piece's
+// checkpoint and its smoothed moments written. A piece's records and
+// chromatic factors are read once into VGPRs (index clamped to its last
+// TOA), so the unrolled loops address them statically.
+__device__ __forceinline__ void reverse5(const AdjArgs& a, const RecBuf& rb,
+                                         const double* chr, const double* ck, double* scr,
+                                         const Lane5& L, int kb, int N, int c1, int sg_lo,
+                                         int sg_hi, int64_t s, bool valid, bool bad, double lt[5],
+                                         double Lt[15]) {
+  constexpr int NS = 5;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int sg = sg_hi - 1; sg >= sg_lo; --sg) {
+    const int k0 = sg * c1;
+    const int k1 = k0 + c1 < N ? k0 + c1 : N;
+    const int nsub = (k1 - k0 + 3) / 4;
+    St5 cur = get_st5(ck + (int64_t)sg * kF5 * kWave, lane);
+    for (int t = 0; t < nsub; ++t) {
+      put_st5(scr + (int64_t)t * kF5 * kWave, lane, cur);
+      if (t + 1 < nsub) {
+        const int kk = k0 + 4 * t;  // a full piece
+        TOARec q[4];
+        double cq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          q[i] = load_rec_vgpr(rb, kk + i);
+          cq[i] = chr[kk + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double K[NS], S, e;
+          fwd5(cur, q[i], cq[i], L, K, S, e);
+        }
+      }
+    }
+    for (int t = nsub - 1; t >= 0; --t) {
+      const int ks = k0 + 4 * t;
+      const int nt = k1 - ks < 4 ? k1 - ks : 4;
+      TOARec q[4];
+      double cq[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = ks + (i < nt ? i : nt - 1);
+        q[i] = load_rec_vgpr(rb, k);
+        cq[i] = chr[k];
+      }
+      const St5 s0 = get_st5(scr + (int64_t)t * kF5 * kWave, lane);
+#pragma unroll
+      for (int i = 3; i >= 0; --i) {
+        if (i < nt) {
+          St5 c = s0;
+          double K[NS], S, e;
+#pragma unroll
+          for (int j = 0; j < i; ++j) fwd5(c, q[j], cq[j], L, K, S, e);
+          fwd5(c, q[i], cq[i], L, K, S, e);
+          if (valid) put_smooth5(a, kb + ks + i, s, c, lt, Lt, bad);
+          bwd5(lt, Lt, K, S, e, cq[i], q[i], L);
+        }
+      }
+    }
+  }
+}
+
 // This lane's model-4 parameters for pulsar p, and whether one is not finite.
 __device__ __forceinline__ Lane5 lane5(const AdjArgs& a, int p, int64_t s, bool& pnf) {
   const int c0 = 6 * p, cc = 6 * a.P;
@@ -2110,14 +2265,27 @@ __device__ __forceinline__ Lane5 lane5(const AdjArgs& a, int p, int64_t s, bool&
   return L;
 }
 
+// The prior state of model 4: zero mean, P0 = diag(s_r^2, s_f^2, v_r, v_c, v_d).
+__device__ __forceinline__ St5 prior5(const AdjArgs& a, const Lane5& L) {
+  St5 st;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) st.x[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 15; ++i) st.P[i] = 0.0;
+  st.P[si5(0, 0)] = a.mc.s_r2;
+  st.P[si5(1, 1)] = a.mc.s_f2;
+  st.P[si5(2, 2)] = L.vr;
+  st.P[si5(3, 3)] = L.vc;
+  st.P[si5(4, 4)] = L.vd;
+  return st;
+}
+
 __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
   constexpr int NS = 5, NP = 15;
   const int lane = threadIdx.x & (kWave - 1);
   const int gwave = __builtin_amdgcn_readfirstlane(
       (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
   double* scr = a.scratch + (int64_t)gwave * a.max_sub * kF5 * kWave;
-  const RecPtr rec = (RecPtr)a.rec;
-  const ConstDPtr chrom = (ConstDPtr)a.chrom;
   for (;;) {
     int v = 0;
     if (lane == 0) v = atomicAdd(a.counter, 1);
@@ -2137,23 +2305,28 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
     const Lane5 L = lane5(a, p, s, pnf);
 
     // forward pass: log-likelihood and level-1 checkpoints (the state
-    // before the first TOA of each segment of c1 TOAs)
-    St5 st;
-#pragma unroll
-    for (int i = 0; i < NS; ++i) st.x[i] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) st.P[i] = 0.0;
-    st.P[si5(0, 0)] = a.mc.s_r2;
-    st.P[si5(1, 1)] = a.mc.s_f2;
-    st.P[si5(2, 2)] = L.vr;
-    st.P[si5(3, 3)] = L.vc;
-    st.P[si5(4, 4)] = L.vd;
+    // before the first TOA of each segment of c1 TOAs); the record and
+    // chromatic factor of TOA k + 1 are fetched during step k
+    const RecBuf rb = rec_buffer(a.rec + kb, N);
+    const double* chr = a.chrom + kb;
+    St5 st = prior5(a, L);
     double quad = 0.0, lm = 1.0;
     int le = 0, stat = pnf ? kPNF : 0;
+    TOARec rq{};
+    double cqn = 0.0;
+    if (N > 0) {
+      rq = load_rec_vgpr(rb, 0);
+      cqn = chr[0];
+    }
     for (int k = 0; k < N; ++k) {
+      const TOARec r = rq;
+      const double ch = cqn;
+      const int kn = k + 1 < N ? k + 1 : k;
+      rq = load_rec_vgpr(rb, kn);
+      cqn = chr[kn];
       if (k % c1 == 0) put_st5(ck + (int64_t)(k / c1) * kF5 * kWave, lane, st);
       double K[NS], S, e;
-      fwd5(st, load_rec(rec, kb + k), chrom[kb + k], L, K, S, e);
+      fwd5(st, r, ch, L, K, S, e);
       const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
       if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
       quad = fma(e * e, rcp_nr(S), quad);
@@ -2165,48 +2338,14 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
     if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
     if (stat) ll = -INFINITY;
 
-    // backward pass over the segments, last first: recompute a segment to
-    // level-2 checkpoints every 4 TOAs, then take its 4-TOA pieces last
-    // first, each TOA's filtered state recomputed from its piece's checkpoint
+    // backward pass over all segments from a zero pair
     double lt[NS], Lt[NP];
 #pragma unroll
     for (int i = 0; i < NS; ++i) lt[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) Lt[i] = 0.0;
-    const bool bad = stat != 0;
-    const int nseg = (N + c1 - 1) / c1;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
-      const int k0 = sg * c1;
-      const int k1 = k0 + c1 < N ? k0 + c1 : N;
-      const int nsub = (k1 - k0 + 3) / 4;
-      St5 cur = get_st5(ck + (int64_t)sg * kF5 * kWave, lane);
-      for (int t = 0; t < nsub; ++t) {
-        put_st5(scr + (int64_t)t * kF5 * kWave, lane, cur);
-        if (t + 1 < nsub) {
-          for (int i = 0; i < 4; ++i) {
-            double K[NS], S, e;
-            const int k = k0 + 4 * t + i;
-            fwd5(cur, load_rec(rec, kb + k), chrom[kb + k], L, K, S, e);
-          }
-        }
-      }
-      for (int t = nsub - 1; t >= 0; --t) {
-        const int ks = k0 + 4 * t;
-        const int nt = k1 - ks < 4 ? k1 - ks : 4;
-        const St5 s0 = get_st5(scr + (int64_t)t * kF5 * kWave, lane);
-        for (int i = nt - 1; i >= 0; --i) {
-          St5 c = s0;
-          double K[NS], S, e;
-          for (int j = 0; j < i; ++j) fwd5(c, load_rec(rec, kb + ks + j), chrom[kb + ks + j], L, K, S, e);
-          const int k = ks + i;
-          const TOARec r = load_rec(rec, kb + k);
-          const double ch = chrom[kb + k];
-          fwd5(c, r, ch, L, K, S, e);
-          if (valid) put_smooth5(a, kb + k, s, c, lt, Lt, bad);
-          bwd5(lt, Lt, K, S, e, ch, r, L);
-        }
-      }
-    }
+    reverse5(a, rb, chr, ck, scr, L, kb, N, c1, 0, (N + c1 - 1) / c1, s, valid, stat != 0, lt,
+             Lt);
     if (valid) {
       a.part[(int64_t)p * a.S + s] = ll;
       a.pstat[(int64_t)p * a.S + s] = stat;
@@ -2214,7 +2353,7 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
   }
 }
 
-// Time-parallel form of the model-4 smoother, as k_smooth_fwd / k_smooth_rev
+// Time-parallel form of the model-4 smoother, as k_smooth_fwd_pc / k_smooth_rev
 // for models 1 and 2: the summary of a chunk is U (5 x 5, row major), phi (5)
 // and Om (15) with F = diag(1, 1, phi_r, phi_c, phi_d) + dt e_0 e_1^T and
 // h = [1, 0, 1, 1, c] per TOA; a chunk's place holds the pair (lt, Lt) after
@@ -2222,114 +2361,12 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
 // and, like k_smooth5, recomputes each TOA's filtered state itself).
 constexpr int kSum5 = 45;
 
-__global__ void __launch_bounds__(256) k_smooth5_fwd(AdjArgs a) {
+// The chain of one item's model-4 chunk summaries from the last chunk back,
+// as smooth_chain; the pair (lt, Lt) after the last TOA of chunk c - 1 goes
+// to chunk c - 1's place in a saved state's fields.
+__device__ __forceinline__ void smooth5_chain(const AdjArgs& a, int64_t base, int nch,
+                                              int lane) {
   constexpr int NS = 5, NP = 15;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int it = __builtin_amdgcn_readfirstlane(
-      (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
-  if (it >= a.n_items) return;
-  const RecPtr rec = (RecPtr)a.rec;
-  const ConstDPtr chrom = (ConstDPtr)a.chrom;
-  const int tile = a.items[2 * it];
-  const int p = a.items[2 * it + 1];
-  const int64_t s_raw = (int64_t)tile * kWave + lane;
-  const bool valid = s_raw < a.S;
-  const int64_t s = valid ? s_raw : a.S - 1;
-  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
-  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
-  const int c1 = a.c1[p];
-  const int nseg = (N + c1 - 1) / c1;
-  const int nch = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it]);
-  const int64_t base = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it + 1]);
-  double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kF5 * kWave;
-  bool pnf;
-  const Lane5 L = lane5(a, p, s, pnf);
-
-  St5 st;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) st.x[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < NP; ++i) st.P[i] = 0.0;
-  st.P[si5(0, 0)] = a.mc.s_r2;
-  st.P[si5(1, 1)] = a.mc.s_f2;
-  st.P[si5(2, 2)] = L.vr;
-  st.P[si5(3, 3)] = L.vc;
-  st.P[si5(4, 4)] = L.vd;
-  double quad = 0.0, lm = 1.0;
-  int le = 0, stat = pnf ? kPNF : 0;
-  double U[NS][NS], phi[NS], Om[NP];
-  // one TOA: checkpoint, filter step and log-likelihood terms, and with
-  // ACC the chunk summary
-  auto step = [&](int k, auto acc) {
-    if (k % c1 == 0) put_st5(ck + (int64_t)(k / c1) * kF5 * kWave, lane, st);
-    const TOARec r = load_rec(rec, kb + k);
-    const double ch = chrom[kb + k];
-    double K[NS], S, e;
-    fwd5(st, r, ch, L, K, S, e);
-    const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
-    if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
-    const double inv = rcp_nr(S);
-    quad = fma(e * e, inv, quad);
-    const double pm = lm * S;
-    lm = __builtin_amdgcn_frexp_mant(pm);
-    le += __builtin_amdgcn_frexp_exp(pm);
-    if constexpr (decltype(acc)::value) {
-      const double dt = r.dt, ei = -e * inv;
-      const double dg[NS] = {1.0, 1.0, 1.0 + expm1_k(-L.gr * dt), r.phc,
-                             1.0 + expm1_k(-L.gd * dt)};
-      double V[NS][NS], v[NS];
-#pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        V[i][0] = fma(dt, U[i][1], U[i][0]);
-        V[i][1] = U[i][1];
-#pragma unroll
-        for (int j = 2; j < NS; ++j) V[i][j] = dg[j] * U[i][j];
-        v[i] = fma(ch, V[i][4], V[i][0] + V[i][2] + V[i][3]);
-        phi[i] = fma(v[i], ei, phi[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        const double vs = v[i] * inv;
-#pragma unroll
-        for (int j = 0; j <= i; ++j) Om[si5(i, j)] = fma(vs, v[j], Om[si5(i, j)]);
-#pragma unroll
-        for (int j = 0; j < NS; ++j) U[i][j] = fma(-v[i], K[j], V[i][j]);
-      }
-    }
-  };
-  const std::integral_constant<bool, false> no_acc;
-  const std::integral_constant<bool, true> with_acc;
-  int k = 0;
-  const int e0 = (nseg / nch) * c1 < N ? (nseg / nch) * c1 : N;
-  for (; k < e0; ++k) step(k, no_acc);
-  for (int c = 1; c < nch; ++c) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-#pragma unroll
-      for (int q = 0; q < NS; ++q) U[i][q] = i == q ? 1.0 : 0.0;
-      phi[i] = 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < NP; ++i) Om[i] = 0.0;
-    const int sh = (c + 1) * nseg / nch;
-    const int ec = sh * c1 < N ? sh * c1 : N;
-    for (; k < ec; ++k) step(k, with_acc);
-    double* o = a.tpsum + (base + c) * kSum5 * kWave + lane;
-#pragma unroll
-    for (int i = 0; i < NS * NS; ++i) o[i * kWave] = U[i / NS][i % NS];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) o[(NS * NS + i) * kWave] = phi[i];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) o[(30 + i) * kWave] = Om[i];
-  }
-  double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
-  if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
-  if (stat) ll = -INFINITY;
-  if (valid) {
-    a.part[(int64_t)p * a.S + s] = ll;
-    a.pstat[(int64_t)p * a.S + s] = stat;
-  }
-  // chain the summaries from the last chunk back
   St5 pr;  // (lt, Lt) in a saved state's fields
 #pragma unroll
   for (int i = 0; i < NS; ++i) pr.x[i] = 0.0;
@@ -2371,15 +2408,184 @@ __global__ void __launch_bounds__(256) k_smooth5_fwd(AdjArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_smooth5_rev(AdjArgs a) {
+// Forward pass of the model-4 time-parallel smoother, as k_smooth_fwd_pc:
+// wave 0 filters (blocks of kSmSteps TOAs, full blocks straight-line) and
+// hands per TOA the gain, e, 1/S, dt, the three decays and the chromatic
+// factor (kSm5Vals values) to wave 1, which accumulates the chunk summaries
+// one block behind and chains them.
+constexpr int kSm5Vals = 12;
+
+__global__ void __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(2)))
+k_smooth5_fwd_pc(AdjArgs a) {
+  constexpr int NS = 5, NP = 15;
+  __shared__ double s_ring[2 * kSmSteps * kSm5Vals * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int it = blockIdx.x;
+  const int tile = a.items[2 * it];
+  const int p = a.items[2 * it + 1];
+  const int64_t s_raw = (int64_t)tile * kWave + lane;
+  const bool valid = s_raw < a.S;
+  const int64_t s = valid ? s_raw : a.S - 1;
+  const int kb = __builtin_amdgcn_readfirstlane((int)a.off[p]);
+  const int N = __builtin_amdgcn_readfirstlane((int)a.off[p + 1]) - kb;
+  const int c1 = a.c1[p];
+  const int nseg = (N + c1 - 1) / c1;
+  const int nch = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it]);
+  const int64_t base = __builtin_amdgcn_readfirstlane(a.tp_item[2 * it + 1]);
+  const int nblk = (N + kSmSteps - 1) / kSmSteps;
+  double* ring = s_ring + lane;  // value v of step j of buffer b at ((b kSmSteps + j) kSm5Vals + v) kWave
+
+  if (wave == 0) {
+    double* ck = a.ckpt + ((int64_t)tile * a.tot_seg + a.seg_base[p]) * kF5 * kWave;
+    bool pnf;
+    const Lane5 L = lane5(a, p, s, pnf);
+    const RecBuf rb = rec_buffer(a.rec + kb, N);
+    const double* chr = a.chrom + kb;
+    St5 st = prior5(a, L);
+    double quad = 0.0, lm = 1.0;
+    int le = 0, stat = pnf ? kPNF : 0;
+    auto step = [&](const TOARec& r, double ch, double* rv) {
+      double K[NS], S, e, phr, phd;
+      fwd5(st, r, ch, L, K, S, e, phr, phd);
+      const double inv = rcp_nr(S);
+#pragma unroll
+      for (int i = 0; i < NS; ++i) rv[i * kWave] = K[i];
+      rv[5 * kWave] = e;
+      rv[6 * kWave] = inv;
+      rv[7 * kWave] = r.dt;
+      rv[8 * kWave] = phr;
+      rv[9 * kWave] = r.phc;
+      rv[10 * kWave] = phd;
+      rv[11 * kWave] = ch;
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && stat == 0) stat = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e * e, inv, quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    };
+    for (int blk = 0; blk <= nblk; ++blk) {
+      double* rbuf = ring + (blk & 1) * kSmSteps * kSm5Vals * kWave;
+      if (blk < nblk) {
+        // the block's records and chromatic factors, read together (index
+        // clamped to the last TOA); a full block is straight-line code, two
+        // steps at a time (four at once need more registers than two waves
+        // per SIMD leave)
+        const int k0 = blk * kSmSteps;
+        TOARec q[kSmSteps];
+        double cq[kSmSteps];
+#pragma unroll
+        for (int j = 0; j < kSmSteps; ++j) {
+          const int k = k0 + j < N ? k0 + j : N - 1;
+          q[j] = load_rec_vgpr(rb, k);
+          cq[j] = chr[k];
+        }
+        if (k0 % c1 == 0) put_st5(ck + (int64_t)(k0 / c1) * kF5 * kWave, lane, st);
+        if (k0 + kSmSteps <= N) {
+#pragma unroll
+          for (int j = 0; j < kSmSteps; ++j) {
+            step(q[j], cq[j], rbuf + j * kSm5Vals * kWave);
+            if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
+          for (int j = 0; j < N - k0; ++j) {
+            const TOARec r = j == 0 ? q[0] : (j == 1 ? q[1] : q[2]);
+            const double ch = j == 0 ? cq[0] : (j == 1 ? cq[1] : cq[2]);
+            step(r, ch, rbuf + j * kSm5Vals * kWave);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    if (stat == 0 && !finite_d(ll)) stat = kNonFinite;
+    if (stat) ll = -INFINITY;
+    if (valid) {
+      a.part[(int64_t)p * a.S + s] = ll;
+      a.pstat[(int64_t)p * a.S + s] = stat;
+    }
+  } else {
+    double U[NS][NS], phi[NS], Om[NP];
+    auto reset = [&]() {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) U[i][q] = i == q ? 1.0 : 0.0;
+        phi[i] = 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < NP; ++i) Om[i] = 0.0;
+    };
+    reset();
+    int c = 0;  // chunk of the next TOA and its end
+    int ec = (nseg / nch) * c1 < N ? (nseg / nch) * c1 : N;
+    for (int blk = 0; blk <= nblk; ++blk) {
+      if (blk > 0) {
+        const double* rbuf = ring + ((blk - 1) & 1) * kSmSteps * kSm5Vals * kWave;
+#pragma unroll 1
+        for (int j = 0; j < kSmSteps; ++j) {
+          const int k = (blk - 1) * kSmSteps + j;
+          if (k >= N) break;
+          if (c > 0) {
+            const double* rv = rbuf + j * kSm5Vals * kWave;
+            double K[NS];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) K[i] = rv[i * kWave];
+            const double e = rv[5 * kWave], inv = rv[6 * kWave], dt = rv[7 * kWave];
+            const double dg[NS] = {1.0, 1.0, rv[8 * kWave], rv[9 * kWave], rv[10 * kWave]};
+            const double ch = rv[11 * kWave];
+            const double ei = -e * inv;
+            double V[NS][NS], v[NS];
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+              V[i][0] = fma(dt, U[i][1], U[i][0]);
+              V[i][1] = U[i][1];
+#pragma unroll
+              for (int q = 2; q < NS; ++q) V[i][q] = dg[q] * U[i][q];
+              v[i] = fma(ch, V[i][4], V[i][0] + V[i][2] + V[i][3]);
+              phi[i] = fma(v[i], ei, phi[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+              const double vs = v[i] * inv;
+#pragma unroll
+              for (int q = 0; q <= i; ++q) Om[si5(i, q)] = fma(vs, v[q], Om[si5(i, q)]);
+#pragma unroll
+              for (int q = 0; q < NS; ++q) U[i][q] = fma(-v[i], K[q], V[i][q]);
+            }
+          }
+          if (k + 1 == ec) {
+            if (c > 0) {
+              double* o = a.tpsum + (base + c) * kSum5 * kWave + lane;
+#pragma unroll
+              for (int i = 0; i < NS * NS; ++i) o[i * kWave] = U[i / NS][i % NS];
+#pragma unroll
+              for (int i = 0; i < NS; ++i) o[(NS * NS + i) * kWave] = phi[i];
+#pragma unroll
+              for (int i = 0; i < NP; ++i) o[(30 + i) * kWave] = Om[i];
+            }
+            reset();
+            ++c;
+            const int sh = (c + 1) * nseg / nch;
+            ec = sh * c1 < N ? sh * c1 : N;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    smooth5_chain(a, base, nch, lane);
+  }
+}
+
+// One wave per SIMD: at two, the piece's records in VGPRs no longer fit
+// without spills (measured slower).
+__global__ void __launch_bounds__(256) k_smooth5_rev(AdjArgs a) {
   constexpr int NS = 5, NP = 15;
   const int lane = threadIdx.x & (kWave - 1);
   const int gwave = __builtin_amdgcn_readfirstlane(
       (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
   double* scr = a.scratch + (int64_t)gwave * a.max_sub * kF5 * kWave;
-  const RecPtr rec = (RecPtr)a.rec;
-  const ConstDPtr chrom = (ConstDPtr)a.chrom;
   for (;;) {
     int v = 0;
     if (lane == 0) v = atomicAdd(a.counter, 1);
@@ -2416,40 +2622,8 @@ k_smooth5_rev(AdjArgs a) {
 #pragma unroll
       for (int i = 0; i < NP; ++i) Lt[i] = pr.P[i];
     }
-    // the backward pass of k_smooth5 over this chunk's segments
-    for (int sg = sg_hi - 1; sg >= sg_lo; --sg) {
-      const int k0 = sg * c1;
-      const int k1 = k0 + c1 < N ? k0 + c1 : N;
-      const int nsub = (k1 - k0 + 3) / 4;
-      St5 cur = get_st5(ck + (int64_t)sg * kF5 * kWave, lane);
-      for (int t = 0; t < nsub; ++t) {
-        put_st5(scr + (int64_t)t * kF5 * kWave, lane, cur);
-        if (t + 1 < nsub) {
-          for (int i = 0; i < 4; ++i) {
-            double K[NS], S, e;
-            const int k = k0 + 4 * t + i;
-            fwd5(cur, load_rec(rec, kb + k), chrom[kb + k], L, K, S, e);
-          }
-        }
-      }
-      for (int t = nsub - 1; t >= 0; --t) {
-        const int ks = k0 + 4 * t;
-        const int nt = k1 - ks < 4 ? k1 - ks : 4;
-        const St5 s0 = get_st5(scr + (int64_t)t * kF5 * kWave, lane);
-        for (int i = nt - 1; i >= 0; --i) {
-          St5 c = s0;
-          double K[NS], S, e;
-          for (int j = 0; j < i; ++j)
-            fwd5(c, load_rec(rec, kb + ks + j), chrom[kb + ks + j], L, K, S, e);
-          const int k = ks + i;
-          const TOARec r = load_rec(rec, kb + k);
-          const double ch = chrom[kb + k];
-          fwd5(c, r, ch, L, K, S, e);
-          if (valid) put_smooth5(a, kb + k, s, c, lt, Lt, bad);
-          bwd5(lt, Lt, K, S, e, ch, r, L);
-        }
-      }
-    }
+    reverse5(a, rec_buffer(a.rec + kb, N), a.chrom + kb, ck, scr, L, kb, N, c1, sg_lo, sg_hi, s,
+             valid, bad, lt, Lt);
   }
 }
 
@@ -2852,7 +3026,9 @@ int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
     uh[2 * u] = (int32_t)(units[u].second / 65536);
     uh[2 * u + 1] = (int32_t)(units[u].second % 65536);
   }
-  const int waves = (int)std::min<int64_t>((int64_t)units.size(), 8LL * ds->n_cu);
+  // resident reverse waves: two per SIMD for models 1 and 2, one for model 4
+  const int waves = (int)std::min<int64_t>((int64_t)units.size(),
+                                           (ds->model == 4 ? 4LL : 8LL) * ds->n_cu);
   w->tp_waves = ((std::max(waves, 1) + 3) / 4) * 4;
   const bool m4 = ds->model == 4;
   const size_t need_sum =
@@ -2895,11 +3071,11 @@ int smooth_once(argus_dataset* ds, Workspace* w, const AdjArgs& a, int nw, int64
     b.scratch = w->tp_scr.as<double>();
     b.n_units = w->n_tp_units;
     if (ds->model == 4) {
-      hipLaunchKernelGGL(k_smooth5_fwd, dim3((w->n_items + 3) / 4), dim3(256), 0, st, b);
+      hipLaunchKernelGGL(k_smooth5_fwd_pc, dim3(w->n_items), dim3(2 * kWave), 0, st, b);
       HIPCHK(hipGetLastError());
       hipLaunchKernelGGL(k_smooth5_rev, dim3(w->tp_waves / 4), dim3(256), 0, st, b);
     } else {
-      hipLaunchKernelGGL(k_smooth_fwd, dim3((w->n_items + 3) / 4), dim3(256), 0, st, b);
+      hipLaunchKernelGGL(k_smooth_fwd_pc, dim3(w->n_items), dim3(2 * kWave), 0, st, b);
       HIPCHK(hipGetLastError());
       hipLaunchKernelGGL(k_smooth_rev, dim3(w->tp_waves / 4), dim3(256), 0, st, b);
     }
