@@ -82,7 +82,6 @@ struct Workspace {
   // gradient workspace: level-1 checkpoints, per-wave level-2 scratch,
   // per-pulsar gradient parts
   DevBuf ckpt, scratch, gpart, c1, seg_base, stat_tmp;
-  std::vector<int32_t> c1_host;
   int64_t tot_seg = 0;
   int max_sub = 0, grad_waves = 0;
   bool grad_ready = false;
@@ -104,6 +103,10 @@ struct Workspace {
   // hand-over states and the reverse waves' level-2 scratch
   int smooth_k = 0, tp_built_k = 0, n_tp_units = 0, tp_waves = 0;
   DevBuf tp_item, tp_units, tp_sum, tp_adj, tp_scr;
+  // its checkpoints: the filtered state before every fourth TOA (per-pulsar
+  // stride 4, segment bases, the store)
+  DevBuf tp_c1, tp_seg, tp_ck;
+  int64_t tp_tot_seg = 0;
   std::string smooth_log;
   // HMC: proposal position, momentum, gradient, logL, initial energy, flags
   DevBuf hmc_x, hmc_p, hmc_g, hmc_l, hmc_h0, hmc_ok;

@@ -437,14 +437,41 @@ struct SmoothSweep {
 // sg_hi - 1 and on return holds it before the first TOA of segment sg_lo;
 // sw.emit(k, f) is called, with the filtered state f after TOA k, for every
 // TOA k >= klo of the range except the last one.
-template <class Sweep>
+// PIECES: every segment is one piece (level-1 stride 4): no level-2 pass.
+template <bool PIECES, class Sweep>
 __device__ __forceinline__ void reverse_segments(const RecBuf& rb, const double* ck, double* scr,
                                                  const LaneP& L, int N, int c1, int sg_lo,
                                                  int sg_hi, int klo, Sweep& sw) {
   const int lane = threadIdx.x & (kWave - 1);
+  // reverse one 4-TOA piece starting at TOA ks from the state s0 before it:
+  // the state before TOA i of the piece is recomputed from s0 (0..3 steps),
+  // so only two states are live in registers; the piece's records are read
+  // once into VGPRs (index clamped to its last TOA) and the loops are
+  // unrolled so that they are addressed statically
+  auto piece = [&](int ks, int nt, const State& s0) {
+    TOARec q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, ks + (i < nt ? i : nt - 1));
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      if (i < nt) {
+        State cur = s0;
+#pragma unroll
+        for (int j = 0; j < i; ++j) fwd_only(cur, q[j], L);
+        sw.step(cur, q[i], L);
+        // sw now holds the pair of the filtered state after TOA ks + i - 1
+        if (ks + i > klo) sw.emit(ks + i - 1, cur);
+      }
+    }
+  };
   for (int64_t sg = sg_hi - 1; sg >= sg_lo; --sg) {
     const int64_t k0 = sg * c1;
     const int64_t k1 = k0 + c1 < N ? k0 + c1 : N;
+    if constexpr (PIECES) {
+      // the piece starts from its level-1 checkpoint itself
+      piece((int)k0, (int)(k1 - k0), get_state(ck + sg * kFields * kWave, lane));
+      continue;
+    }
     const int nsub = (int)((k1 - k0 + 3) / 4);
     // recompute the segment to level-2 checkpoints every 4 TOAs; the four
     // records of a piece are read together into VGPRs (one wait per piece)
@@ -460,29 +487,10 @@ __device__ __forceinline__ void reverse_segments(const RecBuf& rb, const double*
         for (int i = 0; i < 4; ++i) fwd_only(cur, q[i], L);
       }
     }
-    // reverse each 4-TOA piece, last first: the state before TOA i of the
-    // piece is recomputed from the piece's checkpoint (0..3 steps), so
-    // only two states are live in registers; the piece's records are read
-    // once into VGPRs (index clamped to its last TOA) and the loops are
-    // unrolled so that they are addressed statically
+    // the pieces, last first
     for (int t = nsub - 1; t >= 0; --t) {
       const int ks = (int)k0 + 4 * t;
-      const int nt = (int)(k1 - ks < 4 ? k1 - ks : 4);
-      TOARec q[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) q[i] = load_rec_vgpr(rb, ks + (i < nt ? i : nt - 1));
-      const State s0 = get_state(scr + (int64_t)t * kFields * kWave, lane);
-#pragma unroll
-      for (int i = 3; i >= 0; --i) {
-        if (i < nt) {
-          State cur = s0;
-#pragma unroll
-          for (int j = 0; j < i; ++j) fwd_only(cur, q[j], L);
-          sw.step(cur, q[i], L);
-          // sw now holds the pair of the filtered state after TOA ks + i - 1
-          if (ks + i > klo) sw.emit(ks + i - 1, cur);
-        }
-      }
+      piece(ks, (int)(k1 - ks < 4 ? k1 - ks : 4), get_state(scr + (int64_t)t * kFields * kWave, lane));
     }
   }
 }
@@ -573,11 +581,11 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
                      Cov4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
       // the last TOA's smoothed moments are its filtered ones
       if (N > 0) sw.emit(N - 1, st);
-      reverse_segments(rb, ck, scr, L, N, c1, 0, nseg, 0, sw);
+      reverse_segments<false>(rb, ck, scr, L, N, c1, 0, nseg, 0, sw);
     } else {
       GradSweep sw{{0.0, 0.0, 0.0, 0.0}, Cov4{0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
                    Grad{0, 0, 0, 0, 0, 0}};
-      reverse_segments(rb, ck, scr, L, N, c1, 0, nseg, 0, sw);
+      reverse_segments<false>(rb, ck, scr, L, N, c1, 0, nseg, 0, sw);
       Grad& G = sw.G;
       // the prior P0 = diag(s_r^2, s_f^2, v_r, v_c)
       G.v += sw.M.aa;
@@ -620,7 +628,11 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
 // chunk's place. k_smooth_rev then runs the checkpointed reverse sweep of
 // every (item, chunk) unit independently, longest chunks first. An item's
 // serial chain drops from a forward and a reverse pass over its N TOAs to a
-// forward pass over N and a reverse pass over about N / nch.
+// forward pass over N and a reverse pass over about N / nch. This form keeps
+// a checkpoint before every fourth TOA (the level-1 stride is 4, a segment is
+// one reverse piece), so the reverse sweep recomputes no segment and needs no
+// level-2 scratch; the store takes 448 B per four TOAs and sample (model 4:
+// 640 B).
 constexpr int kSum = 30;  // a chunk summary: U (16, row major), phi (4), Om (10)
 
 __host__ __device__ constexpr int si4(int i, int j) {
@@ -891,7 +903,7 @@ k_smooth_rev(AdjArgs a) {
       fend = get_state(ck + (int64_t)sg_hi * kFields * kWave, lane);
     }
     if (k1 > k0) sw.emit(k1 - 1, fend);
-    reverse_segments(rb, ck, scr, L, N, c1, sg_lo, sg_hi, k0, sw);
+    reverse_segments<true>(rb, ck, scr, L, N, c1, sg_lo, sg_hi, k0, sw);
   }
 }
 
@@ -2183,7 +2195,9 @@ __device__ __forceinline__ void bwd5(double lt[5], double Lt[15], const double K
 // taken last first, each TOA's filtered state recomputed from its piece's
 // checkpoint and its smoothed moments written. A piece's records and
 // chromatic factors are read once into VGPRs (index clamped to its last
-// TOA), so the unrolled loops address them statically.
+// TOA), so the unrolled loops address them statically. PIECES: every
+// segment is one piece (level-1 stride 4): no level-2 pass.
+template <bool PIECES>
 __device__ __forceinline__ void reverse5(const AdjArgs& a, const RecBuf& rb,
                                          const double* chr, const double* ck, double* scr,
                                          const Lane5& L, int kb, int N, int c1, int sg_lo,
@@ -2191,9 +2205,37 @@ __device__ __forceinline__ void reverse5(const AdjArgs& a, const RecBuf& rb,
                                          double Lt[15]) {
   constexpr int NS = 5;
   const int lane = threadIdx.x & (kWave - 1);
+  // one 4-TOA piece starting at TOA ks from the state s0 before it
+  auto piece = [&](int ks, int nt, const St5& s0) {
+    TOARec q[4];
+    double cq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = ks + (i < nt ? i : nt - 1);
+      q[i] = load_rec_vgpr(rb, k);
+      cq[i] = chr[k];
+    }
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      if (i < nt) {
+        St5 c = s0;
+        double K[NS], S, e;
+#pragma unroll
+        for (int j = 0; j < i; ++j) fwd5(c, q[j], cq[j], L, K, S, e);
+        fwd5(c, q[i], cq[i], L, K, S, e);
+        if (valid) put_smooth5(a, kb + ks + i, s, c, lt, Lt, bad);
+        bwd5(lt, Lt, K, S, e, cq[i], q[i], L);
+      }
+    }
+  };
   for (int sg = sg_hi - 1; sg >= sg_lo; --sg) {
     const int k0 = sg * c1;
     const int k1 = k0 + c1 < N ? k0 + c1 : N;
+    if constexpr (PIECES) {
+      // the piece starts from its level-1 checkpoint itself
+      piece(k0, k1 - k0, get_st5(ck + (int64_t)sg * kF5 * kWave, lane));
+      continue;
+    }
     const int nsub = (k1 - k0 + 3) / 4;
     St5 cur = get_st5(ck + (int64_t)sg * kF5 * kWave, lane);
     for (int t = 0; t < nsub; ++t) {
@@ -2216,28 +2258,7 @@ __device__ __forceinline__ void reverse5(const AdjArgs& a, const RecBuf& rb,
     }
     for (int t = nsub - 1; t >= 0; --t) {
       const int ks = k0 + 4 * t;
-      const int nt = k1 - ks < 4 ? k1 - ks : 4;
-      TOARec q[4];
-      double cq[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = ks + (i < nt ? i : nt - 1);
-        q[i] = load_rec_vgpr(rb, k);
-        cq[i] = chr[k];
-      }
-      const St5 s0 = get_st5(scr + (int64_t)t * kF5 * kWave, lane);
-#pragma unroll
-      for (int i = 3; i >= 0; --i) {
-        if (i < nt) {
-          St5 c = s0;
-          double K[NS], S, e;
-#pragma unroll
-          for (int j = 0; j < i; ++j) fwd5(c, q[j], cq[j], L, K, S, e);
-          fwd5(c, q[i], cq[i], L, K, S, e);
-          if (valid) put_smooth5(a, kb + ks + i, s, c, lt, Lt, bad);
-          bwd5(lt, Lt, K, S, e, cq[i], q[i], L);
-        }
-      }
+      piece(ks, k1 - ks < 4 ? k1 - ks : 4, get_st5(scr + (int64_t)t * kF5 * kWave, lane));
     }
   }
 }
@@ -2344,7 +2365,7 @@ __global__ void __launch_bounds__(256) k_smooth5(AdjArgs a) {
     for (int i = 0; i < NS; ++i) lt[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < NP; ++i) Lt[i] = 0.0;
-    reverse5(a, rb, chr, ck, scr, L, kb, N, c1, 0, (N + c1 - 1) / c1, s, valid, stat != 0, lt,
+    reverse5<false>(a, rb, chr, ck, scr, L, kb, N, c1, 0, (N + c1 - 1) / c1, s, valid, stat != 0, lt,
              Lt);
     if (valid) {
       a.part[(int64_t)p * a.S + s] = ll;
@@ -2622,7 +2643,7 @@ __global__ void __launch_bounds__(256) k_smooth5_rev(AdjArgs a) {
 #pragma unroll
       for (int i = 0; i < NP; ++i) Lt[i] = pr.P[i];
     }
-    reverse5(a, rec_buffer(a.rec + kb, N), a.chrom + kb, ck, scr, L, kb, N, c1, sg_lo, sg_hi, s,
+    reverse5<true>(a, rec_buffer(a.rec + kb, N), a.chrom + kb, ck, scr, L, kb, N, c1, sg_lo, sg_hi, s,
              valid, bad, lt, Lt);
   }
 }
@@ -2922,7 +2943,6 @@ int adjoint_setup(argus_dataset* ds, Workspace* w, int64_t S) {
   }
   w->tot_seg = tot;
   w->max_sub = cmax / 4;
-  w->c1_host = c1;
   const int fields = ds->model == 4 ? kF5 : kFields;  // doubles per saved state
   w->grad_waves = (int)std::min<int64_t>(w->n_items, 8LL * ds->n_cu);
   w->grad_waves = ((w->grad_waves + 3) / 4) * 4;
@@ -2994,6 +3014,28 @@ namespace {
 // chunk) units ordered by chunk length, longest first. Buffers grow to fit.
 int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
   if (w->tp_built_k == K) return ARGUS_OK;
+  const bool m4 = ds->model == 4;
+  const int fields = m4 ? kF5 : kFields;
+  int rc;
+  if (w->tp_ck.p == nullptr) {
+    // the checkpoint layout of the time-parallel form: the state before
+    // every fourth TOA, so that the reverse sweep recomputes at most three
+    // steps per TOA and no segment
+    std::vector<int32_t> c1(ds->P, 4);
+    std::vector<int64_t> seg(ds->P);
+    int64_t tot = 0;
+    for (int p = 0; p < ds->P; ++p) {
+      seg[p] = tot;
+      tot += (ds->counts[p] + 3) / 4;
+    }
+    const int64_t tiles = (w->S + kWave - 1) / kWave;
+    if ((rc = w->tp_c1.upload(c1.data(), c1.size() * sizeof(int32_t))) ||
+        (rc = w->tp_seg.upload(seg.data(), seg.size() * sizeof(int64_t))) ||
+        (rc = w->tp_ck.alloc((size_t)std::max<int64_t>(tiles * tot, 1) * fields * kWave *
+                             sizeof(double))))
+      return rc;
+    w->tp_tot_seg = tot;
+  }
   const int64_t nmax =
       ds->counts.empty() ? 1 : std::max<int64_t>(1, *std::max_element(ds->counts.begin(),
                                                                        ds->counts.end()));
@@ -3004,7 +3046,7 @@ int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
   for (int i = 0; i < w->n_items; ++i) {
     const int p = w->items_host[2 * i + 1];
     const int64_t n = ds->counts[p];
-    const int64_t c1 = w->c1_host[p];
+    const int64_t c1 = 4;
     const int64_t nseg = (n + c1 - 1) / c1;
     int64_t nch = (n + lc - 1) / lc;
     nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max<int64_t>(nseg, 1)));
@@ -3030,14 +3072,12 @@ int smooth_tp_setup(argus_dataset* ds, Workspace* w, int K) {
   const int waves = (int)std::min<int64_t>((int64_t)units.size(),
                                            (ds->model == 4 ? 4LL : 8LL) * ds->n_cu);
   w->tp_waves = ((std::max(waves, 1) + 3) / 4) * 4;
-  const bool m4 = ds->model == 4;
   const size_t need_sum =
       (size_t)std::max<int64_t>(slots, 1) * (m4 ? kSum5 : kSum) * kWave * sizeof(double);
   const size_t need_adj =
       (size_t)std::max<int64_t>(slots, 1) * (m4 ? kF5 : kFields) * kWave * sizeof(double);
-  const size_t need_scr =
-      (size_t)w->tp_waves * w->max_sub * (m4 ? kF5 : kFields) * kWave * sizeof(double);
-  int rc;
+  // level-2 scratch of one state per wave (segments of one piece need none)
+  const size_t need_scr = (size_t)w->tp_waves * fields * kWave * sizeof(double);
   if ((rc = w->tp_item.upload(item.data(), item.size() * sizeof(int32_t))) ||
       (rc = w->tp_units.upload(uh.data(), uh.size() * sizeof(int32_t))))
     return rc;
@@ -3070,6 +3110,11 @@ int smooth_once(argus_dataset* ds, Workspace* w, const AdjArgs& a, int nw, int64
     b.tpadj = w->tp_adj.as<double>();
     b.scratch = w->tp_scr.as<double>();
     b.n_units = w->n_tp_units;
+    b.ckpt = w->tp_ck.as<double>();
+    b.c1 = w->tp_c1.as<int32_t>();
+    b.seg_base = w->tp_seg.as<int64_t>();
+    b.tot_seg = w->tp_tot_seg;
+    b.max_sub = 1;
     if (ds->model == 4) {
       hipLaunchKernelGGL(k_smooth5_fwd_pc, dim3(w->n_items), dim3(2 * kWave), 0, st, b);
       HIPCHK(hipGetLastError());
