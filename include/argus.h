@@ -223,7 +223,7 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
                     int32_t* depth, int32_t* n_leapfrog, int32_t* divergent,
                     double* accept_stat, void* stream);
 
-/* Smoothed latent states (models 1, 2): for every TOA k of every pulsar and
+/* Smoothed latent states (models 1, 2, 4): for every TOA k of every pulsar and
  * every sample s, the posterior mean and variance of that pulsar's state
  * components at t_k given all of its TOAs (paper: Summary and Statement of
  * Need: the filter tracks the realised, time-ordered noise; the fixed-interval
@@ -236,13 +236,18 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
  *   logl, status: dev [S] or NULL, as argus_loglike
  * The entries of a pulsar whose filter fails for a sample (innovation
  * variance not positive, or a non-finite parameter among its own and the
- * common ones) are NaN. Computed from the reverse sweep of the checkpointed
- * adjoint gradient, no matrix inverse: E[x|y] = x + P xb and Cov[x|y] = P +
- * P (2M - xb xb^T) P with (x, P) filtered and (xb, M) the adjoints of logL
- * with respect to them (model 4: the modified Bryson-Frazier recursion over
- * the filtered states, the same moments). Model 3 returns
- * ARGUS_E_UNSUPPORTED; N*nc*S above 2^40 elements, or a pulsar with more than
- * 33,554,431 TOAs, returns ARGUS_E_UNSUPPORTED. */
+ * common ones) are NaN. Computed without a matrix inverse by the modified
+ * Bryson-Frazier recursion over the checkpointed filter: E[x|y] = x - P lam
+ * and Cov[x|y] = P - P Lam P with (x, P) filtered and (lam, Lam) the
+ * information of the later TOAs about that state. The first call per sample
+ * count times one wave per (64-sample tile, pulsar) against a time-parallel
+ * form (each pulsar's stream in chunks reversed at once from chained chunk
+ * summaries) and keeps the faster; the environment variable ARGUS_SMOOTH =
+ * seq | tp2 | tp4 | tp8 | tp16 forces a form (any other value:
+ * ARGUS_E_INVAL). The time-parallel form keeps a checkpoint before every
+ * fourth TOA (448 B per four TOAs and sample; model 4: 640 B). Model 3
+ * returns ARGUS_E_UNSUPPORTED; N*nc*S above 2^40 elements, or a pulsar with
+ * more than 33,554,431 TOAs, returns ARGUS_E_UNSUPPORTED. */
 int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,
                  double* var, double* logl, int32_t* status, void* stream);
 
