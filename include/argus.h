@@ -69,7 +69,7 @@ typedef struct argus_dataset* argus_dataset_t;
 
 typedef struct {
   int32_t model;            /* ARGUS_M1_SPIN / ARGUS_M2_PSR4 / ARGUS_M3_JOINT_HD */
-  int32_t n_psr;            /* P >= 1 (model 1: P == 1; model 3: P <= 22) */
+  int32_t n_psr;            /* P >= 1 (model 1: P == 1; model 3: P <= 63) */
   const int64_t* toa_off;   /* host [P+1] CSR offsets into t/y/sigma, off[0]=0 */
   const double* t;          /* host [N] s since the epoch t0 = 0; strictly
                                ascending within a pulsar, >= 0 */

@@ -22,12 +22,16 @@ int fail(int code, const std::string& msg);
                            std::string(#x ": ") + hipGetErrorString(e_));  \
   } while (0)
 
-// Largest joint model (one 16-wave workgroup per sample): the 4P-state
-// covariance, padded to 96 rows, fills the workgroup's LDS layout and the 48
-// rows of G each of the two elimination waves holds, and the transition of
-// the covariance gives each of its 384 lanes at most 3 of the 2 P (P + 1)
-// column segments, so P <= 22.
-constexpr int kJointMaxPsr = 22;
+// Joint model sizes. The blocked kernel (one 16-wave workgroup per sample)
+// keeps the 4P-state covariance, padded to 96 rows, in the workgroup's LDS
+// with 48 rows of G on each of its two elimination waves, and the
+// transition of the covariance gives each of its 384 lanes at most 3 of the
+// 2 P (P + 1) column segments, so P <= 22. Above that the sequential kernel
+// spreads the covariance's P (P + 1) / 2 lower 4x4 pulsar blocks over the
+// registers of one workgroup, at most 2048 blocks (512 threads, 4 each):
+// P <= 63.
+constexpr int kJointBlockedMaxPsr = 22;
+constexpr int kJointMaxPsr = 63;
 
 // Owning device allocation.
 struct DevBuf {

@@ -699,14 +699,16 @@ __global__ void k_stage(StageArgs a) {
 // Hellings & Downs (1983) correlation with the pulsar term on the diagonal:
 // G_ab = 3/2 x ln x - x/4 + 1/2 + delta_ab/2, x = (1 - cos zeta_ab)/2.
 __global__ void k_hd(const double* pos, int P, double* G) {
-  const int a = blockIdx.x, b = threadIdx.x;
-  if (a >= P || b >= P) return;
-  const double c = pos[3 * a] * pos[3 * b] + pos[3 * a + 1] * pos[3 * b + 1] +
-                   pos[3 * a + 2] * pos[3 * b + 2];
-  double x = a == b ? 0.0 : 0.5 * (1.0 - c);
-  x = x < 0.0 ? 0.0 : x;
-  const double xl = x > 0.0 ? x * log(x) : 0.0;
-  G[a * P + b] = 1.5 * xl - 0.25 * x + 0.5 + (a == b ? 0.5 : 0.0);
+  const int a = blockIdx.x;
+  if (a >= P) return;
+  for (int b = threadIdx.x; b < P; b += blockDim.x) {
+    const double c = pos[3 * a] * pos[3 * b] + pos[3 * a + 1] * pos[3 * b + 1] +
+                     pos[3 * a + 2] * pos[3 * b + 2];
+    double x = a == b ? 0.0 : 0.5 * (1.0 - c);
+    x = x < 0.0 ? 0.0 : x;
+    const double xl = x > 0.0 ? x * log(x) : 0.0;
+    G[a * P + b] = 1.5 * xl - 0.25 * x + 0.5 + (a == b ? 0.5 : 0.0);
+  }
 }
 
 // ------------------------------------------------ plain per-sample baseline

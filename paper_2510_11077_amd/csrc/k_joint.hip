@@ -57,6 +57,9 @@
 // loop keeps a fixed trip count.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
+
 #include "argus_host.h"
 #include "argus_internal.h"
 
@@ -66,7 +69,7 @@ namespace {
 
 constexpr int kWaves = 16;                               // 4 per SIMD
 constexpr int kThreads = kWaves * kWave;
-constexpr int kMaxP = kJointMaxPsr;
+constexpr int kMaxP = kJointBlockedMaxPsr;
 constexpr int kB = 16;                                   // TOAs per block
 constexpr int kNPad = ((4 * kMaxP + 15) / 16) * 16;     // padded state dim
 constexpr int kLdP = kNPad + 2;                          // P row: 16-B aligned
@@ -636,6 +639,224 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sequential joint filter for arrays beyond the blocked kernel's LDS layout
+// (P > 22): the same recursion one TOA at a time, one workgroup of NT
+// threads per sample. The covariance's lower 4x4 pulsar blocks (a >= b) are
+// spread over the threads' registers: blocks t + NT j, j < NR, of the lower
+// triangle (row order) belong to thread t, and no thread touches another's
+// entries. One block per thread in 1024 threads up to 44 pulsars, two in
+// 768 (three waves per SIMD leave 168 registers) up to 54, four in 512 (256
+// registers) up to 63; more blocks per thread spill. Per TOA of pulsar q (record: dt, the spin-noise moments, common
+// decay and noise fraction, residual, white variance):
+//   A  every block: X <- F_a X F_b^T + Q_ab with F_p = [[1, dt, 0, 0],
+//      [0, 1, 0, 0], [0, 0, phi_p, 0], [0, 0, 0, phi_c]], Q_aa the pulsar's
+//      spin and red noise, and Gamma_ab v_c (1 - phi_c^2) on the g-g entry
+//      of every block; the blocks of column q (or row q, transposed) write
+//      u = P- h_q to LDS; thread p < P predicts pulsar p's mean (kept in its
+//      registers) and pulsar q's thread writes h_q . x-.
+//   B  S = h_q . u + R, e = y - h_q . x-, K = u / S; every block takes the
+//      Joseph update in the W = P- - K u^T, z = R K - W h, P+ = W + z K^T
+//      form, row by row; thread p < P updates its mean and forms pulsar p's
+//      decays of the next TOA; thread 0 adds the log-likelihood terms.
+// Two barriers per TOA.
+__device__ __forceinline__ void lower_block(int e, int& r, int& c) {
+  r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  r += (r + 1) * (r + 2) / 2 <= e ? 1 : 0;
+  r -= r * (r + 1) / 2 > e ? 1 : 0;
+  c = e - r * (r + 1) / 2;
+}
+
+struct SeqTOA {
+  double dt, h2, h3, phc, qc;  // interval, spin moments, common decay, common noise
+  int q;
+};
+
+// phase A on one block (rows of pulsar pa, columns of pulsar pb)
+__device__ __forceinline__ void seq_predict(double (&M)[4][4], int pa, int pb, double gam,
+                                            const SeqTOA& o, double ss2, const double* s_ph,
+                                            const double* s_qa, double* s_u) {
+  const double fa = s_ph[pa], fb = s_ph[pb];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    M[0][c] = fma(o.dt, M[1][c], M[0][c]);
+    M[2][c] *= fa;
+    M[3][c] *= o.phc;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    M[i][0] = fma(o.dt, M[i][1], M[i][0]);
+    M[i][2] *= fb;
+    M[i][3] *= o.phc;
+  }
+  if (pa == pb) {
+    M[0][0] = fma(ss2, o.h3, M[0][0]);
+    M[0][1] = fma(ss2, o.h2, M[0][1]);
+    M[1][0] = fma(ss2, o.h2, M[1][0]);
+    M[1][1] = fma(ss2, o.dt, M[1][1]);
+    M[2][2] += s_qa[pa];
+  }
+  M[3][3] = fma(gam, o.qc, M[3][3]);
+  if (pb == o.q) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_u[4 * pa + i] = M[i][0] + M[i][2] + M[i][3];
+  } else if (pa == o.q) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s_u[4 * pb + c] = M[0][c] + M[2][c] + M[3][c];
+  }
+}
+
+// phase B on one block, a row at a time (few values live)
+__device__ __forceinline__ void seq_update(double (&M)[4][4], int pa, int pb, double inv,
+                                           double R, double hu, const double* s_u) {
+  double uj[4], Kj[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    uj[c] = s_u[4 * pb + c];
+    Kj[c] = uj[c] * inv;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double ui = s_u[4 * pa + i], Ki = ui * inv;
+    // z = R K - W h with W h = u - K (h . u)
+    const double zi = fma(R, Ki, -fma(-Ki, hu, ui));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M[i][c] = fma(zi, Kj[c], fma(-Ki, uj[c], M[i][c]));
+  }
+}
+
+template <int NT, int NR>
+__global__ void __launch_bounds__(NT) k_joint_seq(JointArgs a) {
+  __shared__ double s_u[4 * kJointMaxPsr];
+  __shared__ double s_ph[kJointMaxPsr], s_qa[kJointMaxPsr];  // red decay and noise of a TOA
+  __shared__ double s_vr[kJointMaxPsr], s_gr[kJointMaxPsr], s_ef2[kJointMaxPsr],
+      s_eq2[kJointMaxPsr];
+  __shared__ double s_hx, s_vc;
+  __shared__ int s_pnf;
+  const int tid = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const int P = a.P;
+  const int nb = P * (P + 1) / 2;
+  const int64_t N = a.N;
+  const double ss2 = a.mc.ss2;
+  const RecPtr rec = (RecPtr)a.rec;
+
+  if (tid == 0) {
+    const double la = prm(a, 4 * P, s), gc = prm(a, 4 * P + 1, s);
+    const double gm1 = gc - 1.0;
+    s_vc = exp(2.0 * kLn10 * la + (gc - 3.0) * a.mc.log_fyr + gm1 * a.mc.log_T) /
+           (12.0 * kPi * kPi * gm1);
+    s_pnf = (finite_d(la) && finite_d(gc)) ? 0 : 1;
+  }
+  __syncthreads();
+  if (tid < P) {
+    const int q = tid;
+    const double lsr = prm(a, 4 * q, s), lgr = prm(a, 4 * q + 1, s);
+    const double ef = prm(a, 4 * q + 2, s), leq = prm(a, 4 * q + 3, s);
+    if (!(finite_d(lsr) && finite_d(lgr) && finite_d(ef) && finite_d(leq)))
+      atomicOr(&s_pnf, 1);
+    const double gr = exp10(lgr);
+    const double sr = exp10(lsr), eq = exp10(leq);
+    s_vr[q] = sr * sr / (2.0 * gr);
+    s_gr[q] = gr;
+    s_ef2[q] = ef * ef;
+    s_eq2[q] = eq * eq;
+    // decays of the first TOA
+    const double dt0 = N > 0 ? rec[0].dt : 0.0;
+    const double em = expm1_k(-gr * dt0);
+    s_ph[q] = 1.0 + em;
+    s_qa[q] = s_vr[q] * (-em * (2.0 + em));
+  }
+  __syncthreads();
+  const double vc = s_vc;
+
+  // this thread's blocks: rows of pulsar ba[j], columns of pulsar bb[j];
+  // the prior: diag(s_r^2, s_f^2, v_r) per pulsar, Gamma v_c on g-g
+  int ba[NR], bb[NR];
+  double gam[NR];
+  double X[NR][4][4];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int e = tid + NT * j;
+    int r = -1, c = -1;
+    if (e < nb) lower_block(e, r, c);
+    ba[j] = r;
+    bb[j] = c;
+    gam[j] = e < nb ? a.hd[r * P + c] : 0.0;
+    double (&M)[4][4] = X[j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) M[i][cc] = 0.0;
+    if (e < nb) {
+      if (r == c) {
+        M[0][0] = a.mc.s_r2;
+        M[1][1] = a.mc.s_f2;
+        M[2][2] = s_vr[r];
+      }
+      M[3][3] = gam[j] * vc;
+    }
+  }
+  // the mean of pulsar tid (tid < P)
+  double xm[4] = {0.0, 0.0, 0.0, 0.0};
+  const double gr_own = tid < P ? s_gr[tid] : 0.0, vr_own = tid < P ? s_vr[tid] : 0.0;
+
+  double quad = 0.0, lm = 1.0;
+  int le = 0, st = 0;
+  for (int64_t k = 0; k < N; ++k) {
+    const TOARec r = load_rec(rec, k);
+    const SeqTOA o{r.dt, r.h2, r.h3, r.phc, vc * r.qcu, __builtin_amdgcn_readfirstlane(r.psr)};
+    // ---- A. predict every block, u = P- h_q, predicted mean
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+      if (ba[j] >= 0) seq_predict(X[j], ba[j], bb[j], gam[j], o, ss2, s_ph, s_qa, s_u);
+    if (tid < P) {
+      xm[0] = fma(o.dt, xm[1], xm[0]);
+      xm[2] *= s_ph[tid];
+      xm[3] *= o.phc;
+      if (tid == o.q) s_hx = xm[0] + xm[2] + xm[3];
+    }
+    __syncthreads();
+    // ---- B. innovation, gain, Joseph update of every block
+    const int q = o.q;
+    const double hu = s_u[4 * q] + s_u[4 * q + 2] + s_u[4 * q + 3];
+    const double R = fma(s_ef2[q], r.s2, s_eq2[q]);
+    const double S = hu + R;
+    const double e = r.y - s_hx;
+    const double inv = rcp_nr(S);
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+      if (ba[j] >= 0) seq_update(X[j], ba[j], bb[j], inv, R, hu, s_u);
+    if (tid < P) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xm[i] = fma(s_u[4 * tid + i] * inv, e, xm[i]);
+    }
+    if (tid == 0) {
+      const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
+      if (!good && st == 0) st = (!finite_d(S) || !finite_d(e)) ? kNonFinite : kNonPD;
+      quad = fma(e * e, inv, quad);
+      const double pm = lm * S;
+      lm = __builtin_amdgcn_frexp_mant(pm);
+      le += __builtin_amdgcn_frexp_exp(pm);
+    }
+    // the decays of the next TOA: phase A, their only reader, ran before the
+    // first barrier of this TOA and runs again after the next one
+    if (tid < P && k + 1 < N) {
+      const double em = expm1_k(-gr_own * rec[k + 1].dt);
+      s_ph[tid] = 1.0 + em;
+      s_qa[tid] = vr_own * (-em * (2.0 + em));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (s_pnf) st = kNonFinite;
+    double ll = -0.5 * ((double)N * kLn2Pi + (log(lm) + (double)le * kLn2) + quad);
+    if (st == 0 && !finite_d(ll)) st = kNonFinite;
+    a.logl[s] = st ? -INFINITY : ll;
+    if (a.status) a.status[s] = st;
+  }
+}
+
 }  // namespace
 
 int joint_loglike(argus_dataset* ds, const double* theta, int64_t S, double* logl,
@@ -653,7 +874,21 @@ int joint_loglike(argus_dataset* ds, const double* theta, int64_t S, double* log
   a.D = ds->D;
   a.P = ds->P;
   a.mc = ds->mc;
-  hipLaunchKernelGGL(k_joint, dim3((unsigned)S), dim3(kThreads), 0, st, a);
+  const char* force = std::getenv("ARGUS_JOINT");
+  const bool seq = ds->P > kJointBlockedMaxPsr || (force && !std::strcmp(force, "seq"));
+  if (!seq) {
+    hipLaunchKernelGGL(k_joint, dim3((unsigned)S), dim3(kThreads), 0, st, a);
+  } else {
+    // threads and blocks per thread
+    const int nb = ds->P * (ds->P + 1) / 2;
+    const dim3 g((unsigned)S);
+    if (nb <= 1024)
+      hipLaunchKernelGGL((k_joint_seq<1024, 1>), g, dim3(1024), 0, st, a);
+    else if (nb <= 2 * 768)
+      hipLaunchKernelGGL((k_joint_seq<768, 2>), g, dim3(768), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_joint_seq<512, 4>), g, dim3(512), 0, st, a);
+  }
   HIPCHK(hipGetLastError());
   return ARGUS_OK;
 }

@@ -99,7 +99,7 @@ def test_dataset_validation(case, code):
 
 def test_joint_model_size_limit():
     L = lib()
-    P = 23
+    P = 64  # one more than the sequential joint kernel holds
     off = np.arange(P + 1, dtype=np.int64)
     t = np.ones(P)
     pos = np.tile([0, 0, 1.0], (P, 1))

@@ -198,19 +198,31 @@ def test_free_mask_subset(argus, orc):
 
 
 # ------------------------------------------------------------ joint model
-def test_joint_small(argus, orc):
+@pytest.fixture(params=["blocked", "seq"])
+def joint_form(request, monkeypatch):
+    """The joint model's kernel: the blocked one (the default up to 22
+    pulsars) or the sequential one (the default above), forced through
+    ARGUS_JOINT=seq."""
+    if request.param == "seq":
+        monkeypatch.setenv("ARGUS_JOINT", "seq")
+    else:
+        monkeypatch.delenv("ARGUS_JOINT", raising=False)
+    return request.param
+
+
+def test_joint_small(argus, orc, joint_form):
     d = pi.make_pta("t", n_psr=3, counts=[30, 1, 45], seed=37, model=pi.M_JOINT)
     th = pi.sample_theta(d, 6, 9)
     run(argus, orc, d, th)
 
 
-def test_joint_tied_toas(argus, orc):
+def test_joint_tied_toas(argus, orc, joint_form):
     d = pi.make_pta("t", n_psr=2, counts=[15, 15], seed=38, model=pi.M_JOINT)
     d.t[15:] = d.t[:15]
     run(argus, orc, d, pi.sample_theta(d, 4, 10))
 
 
-def test_joint_twenty_pulsars(argus, orc):
+def test_joint_twenty_pulsars(argus, orc, joint_form):
     d = pi.make_pta("t", n_psr=20, counts=np.full(20, 40), seed=39, model=pi.M_JOINT)
     th = pi.sample_theta(d, 6, 11)
     run(argus, orc, d, th)
@@ -231,7 +243,7 @@ def test_joint_cfg3_sampled(argus, orc):
 
 
 @pytest.mark.parametrize("counts", [[1], [9, 8], [5, 0, 12], [3] * 22])
-def test_joint_block_edges(argus, orc, counts):
+def test_joint_block_edges(argus, orc, counts, joint_form):
     """Stream lengths around the 16-TOA block size, an empty pulsar, and the
     largest supported joint model (22 pulsars, padded MFMA tiles)."""
     d = pi.make_pta("t", n_psr=len(counts), counts=counts, seed=40 + len(counts),
@@ -239,7 +251,7 @@ def test_joint_block_edges(argus, orc, counts):
     run(argus, orc, d, pi.sample_theta(d, 5, 12))
 
 
-def test_joint_prior_corners_and_flags(argus, orc):
+def test_joint_prior_corners_and_flags(argus, orc, joint_form):
     d = pi.make_pta("t", n_psr=4, counts=[20, 35, 3, 50], seed=47, model=pi.M_JOINT)
     lo, hi = d.lo, d.hi
     th = np.array([lo, hi, np.where(np.arange(lo.size) % 2, lo, hi), d.truth, d.truth])
@@ -258,6 +270,19 @@ def test_joint_prior_corners_and_flags(argus, orc):
     ref, rst = orc.loglike(dz, z)
     assert rst[0] == 1
     check(ll, st, ref, rst)
+
+
+@pytest.mark.parametrize("P, per", [(23, 4), (45, 3), (55, 3), (63, 2)])
+def test_joint_beyond_blocked_limit(argus, orc, P, per):
+    """Arrays larger than the blocked kernel's LDS layout take the sequential
+    kernel: one covariance block per thread up to 44 pulsars (23), two (45),
+    four (55, and 63, the largest supported array); ragged TOA counts, and
+    the oracle's dense 4P-state Joseph-form filter on every sample."""
+    counts = np.full(P, per)
+    counts[::3] += 1
+    counts[1::5] = 1
+    d = pi.make_pta("t", n_psr=P, counts=counts, seed=60 + P, model=pi.M_JOINT)
+    run(argus, orc, d, pi.sample_theta(d, 3, 13 + P))
 
 
 @pytest.mark.parametrize("cfg", ["64,7,0", "256,3,0", "1024,1,0,1", "256,1,0,1", "64,1,0,1",
