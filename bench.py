@@ -529,6 +529,28 @@ def main():
                                                 "layout": chosen1[0] if chosen1 else tune1}
         log("spin 1 pulsar: %.2f us/call; tune: %s" % (ms1 * 1e3, tune1.replace("\n", " | ")))
 
+        # the cost's growth with the number of TOAs (the paper: O(N) per
+        # likelihood): the same 47 pulsars with every TOA count scaled by f
+        # (cadence over the same span), the same 4096 samples
+        sweep = []
+        for f in (0.25, 0.5, 1.0, 2.0):
+            cnt = np.maximum(1, np.rint(np.diff(d.off) * f)).astype(np.int64)
+            df = pi.make_pta("cfg2", counts=cnt)
+            dsf = A.Dataset(df)
+            dsf.loglike(th, out, st)
+            msf, _ = timed(lambda: dsf.loglike(th, out, st), 10, 2, stream)
+            sweep.append({"scale": f, "n_toa": int(df.n_toa), "longest_pulsar": int(cnt.max()),
+                          "ms_per_call": msf,
+                          "ns_per_toa_and_sample": msf * 1e6 / (df.n_toa * S)})
+            del dsf
+        slope = float(np.polyfit(np.log([p["n_toa"] for p in sweep]),
+                                 np.log([p["ms_per_call"] for p in sweep]), 1)[0])
+        extra["n_sweep_47psr_4096samples"] = {
+            "points": sweep, "loglog_slope": slope,
+            "note": "time per call against the total TOA count; slope 1 = O(N)"}
+        log("N sweep: " + ", ".join("%d TOAs %.3f ms" % (p["n_toa"], p["ms_per_call"])
+                                    for p in sweep) + "; log-log slope %.3f" % slope)
+
         # 47 pulsars with DM variations in four radio bands, 4096 samples
         d6 = pi.make_config("cfg2dm")
         S6 = pi.N_SAMPLES["cfg2dm"]
@@ -606,6 +628,21 @@ def main():
             "mfma_tflops_blocked_method": n3 * FLOP_PER_TOA_JOINT_MFMA / (ms3 * 1e-3) / 1e12,
             "plain_gpu": "not available for the joint model"}
         log("joint HD: %.3f ms/call, %.4g evals/s" % (ms3, S3 / (ms3 * 1e-3)))
+        del ds3
+        # the joint model beyond the blocked kernel: all 47 pulsars x 400 TOAs
+        # (the sequential kernel, covariance blocks in registers), 256 samples
+        d3b = pi.make_pta("cfg3", n_psr=47, counts=np.full(47, 400), model=pi.M_JOINT)
+        t3b = torch.as_tensor(pi.sample_theta(d3b, S3, pi.THETA_SEED["cfg3"]),
+                              dtype=torch.float64, device=dev)
+        ds3b = A.Dataset(d3b)
+        ds3b.loglike(t3b, o3, s3)
+        ms3b, _ = timed(lambda: ds3b.loglike(t3b, o3, s3), 3, 1, stream)
+        extra["joint_hd_47psr_18800toa_256samples"] = {
+            "ms_per_call": ms3b, "evals_per_s": S3 / (ms3b * 1e-3),
+            "us_per_toa": ms3b * 1e3 / d3b.n_toa,
+            "kernel": "sequential joint filter (188 states; 2 covariance blocks per thread)"}
+        log("joint HD 47 pulsars: %.3f ms/call" % ms3b)
+        del ds3b
 
         # gradient (tuned tangent sweep), 1024 samples of the 47-pulsar data
         S4 = pi.N_SAMPLES["cfg4"]
