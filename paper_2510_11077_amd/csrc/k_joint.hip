@@ -658,8 +658,11 @@ __global__ void __launch_bounds__(kThreads) k_joint(JointArgs a) {
 //   B  S = h_q . u + R, e = y - h_q . x-, K = u / S; every block takes the
 //      Joseph update in the W = P- - K u^T, z = R K - W h, P+ = W + z K^T
 //      form, row by row; thread p < P updates its mean and forms pulsar p's
-//      decays of the next TOA; thread 0 adds the log-likelihood terms.
-// Two barriers per TOA.
+//      decays of the TOA after next; thread 0 adds the log-likelihood terms.
+// One barrier per TOA, between A and B: u and h_q . x- alternate between two
+// LDS buffers (B of TOA k reads one while A of TOA k + 1 writes the other),
+// and the decays, written two TOAs ahead into one of three buffers, are read
+// only after the barrier that follows their writing.
 __device__ __forceinline__ void lower_block(int e, int& r, int& c) {
   r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
   r += (r + 1) * (r + 2) / 2 <= e ? 1 : 0;
@@ -727,11 +730,11 @@ __device__ __forceinline__ void seq_update(double (&M)[4][4], int pa, int pb, do
 
 template <int NT, int NR>
 __global__ void __launch_bounds__(NT) k_joint_seq(JointArgs a) {
-  __shared__ double s_u[4 * kJointMaxPsr];
-  __shared__ double s_ph[kJointMaxPsr], s_qa[kJointMaxPsr];  // red decay and noise of a TOA
+  __shared__ double s_u[2][4 * kJointMaxPsr];
+  __shared__ double s_ph[3][kJointMaxPsr], s_qa[3][kJointMaxPsr];  // red decay, noise by TOA
   __shared__ double s_vr[kJointMaxPsr], s_gr[kJointMaxPsr], s_ef2[kJointMaxPsr],
       s_eq2[kJointMaxPsr];
-  __shared__ double s_hx, s_vc;
+  __shared__ double s_hx[2], s_vc;
   __shared__ int s_pnf;
   const int tid = threadIdx.x;
   const int64_t s = blockIdx.x;
@@ -761,11 +764,13 @@ __global__ void __launch_bounds__(NT) k_joint_seq(JointArgs a) {
     s_gr[q] = gr;
     s_ef2[q] = ef * ef;
     s_eq2[q] = eq * eq;
-    // decays of the first TOA
-    const double dt0 = N > 0 ? rec[0].dt : 0.0;
-    const double em = expm1_k(-gr * dt0);
-    s_ph[q] = 1.0 + em;
-    s_qa[q] = s_vr[q] * (-em * (2.0 + em));
+    // decays of the first two TOAs
+    for (int k = 0; k < 2; ++k) {
+      const double dtk = k < N ? rec[k].dt : 0.0;
+      const double em = expm1_k(-gr * dtk);
+      s_ph[k][q] = 1.0 + em;
+      s_qa[k][q] = s_vr[q] * (-em * (2.0 + em));
+    }
   }
   __syncthreads();
   const double vc = s_vc;
@@ -806,30 +811,32 @@ __global__ void __launch_bounds__(NT) k_joint_seq(JointArgs a) {
   for (int64_t k = 0; k < N; ++k) {
     const TOARec r = load_rec(rec, k);
     const SeqTOA o{r.dt, r.h2, r.h3, r.phc, vc * r.qcu, __builtin_amdgcn_readfirstlane(r.psr)};
+    const int ub = (int)(k & 1), db = (int)(k % 3);
+    double* su = s_u[ub];
     // ---- A. predict every block, u = P- h_q, predicted mean
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-      if (ba[j] >= 0) seq_predict(X[j], ba[j], bb[j], gam[j], o, ss2, s_ph, s_qa, s_u);
+      if (ba[j] >= 0) seq_predict(X[j], ba[j], bb[j], gam[j], o, ss2, s_ph[db], s_qa[db], su);
     if (tid < P) {
       xm[0] = fma(o.dt, xm[1], xm[0]);
-      xm[2] *= s_ph[tid];
+      xm[2] *= s_ph[db][tid];
       xm[3] *= o.phc;
-      if (tid == o.q) s_hx = xm[0] + xm[2] + xm[3];
+      if (tid == o.q) s_hx[ub] = xm[0] + xm[2] + xm[3];
     }
     __syncthreads();
     // ---- B. innovation, gain, Joseph update of every block
     const int q = o.q;
-    const double hu = s_u[4 * q] + s_u[4 * q + 2] + s_u[4 * q + 3];
+    const double hu = su[4 * q] + su[4 * q + 2] + su[4 * q + 3];
     const double R = fma(s_ef2[q], r.s2, s_eq2[q]);
     const double S = hu + R;
-    const double e = r.y - s_hx;
+    const double e = r.y - s_hx[ub];
     const double inv = rcp_nr(S);
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-      if (ba[j] >= 0) seq_update(X[j], ba[j], bb[j], inv, R, hu, s_u);
+      if (ba[j] >= 0) seq_update(X[j], ba[j], bb[j], inv, R, hu, su);
     if (tid < P) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) xm[i] = fma(s_u[4 * tid + i] * inv, e, xm[i]);
+      for (int i = 0; i < 4; ++i) xm[i] = fma(su[4 * tid + i] * inv, e, xm[i]);
     }
     if (tid == 0) {
       const bool good = __builtin_amdgcn_class(S, 0x180) & finite_d(e);
@@ -839,14 +846,14 @@ __global__ void __launch_bounds__(NT) k_joint_seq(JointArgs a) {
       lm = __builtin_amdgcn_frexp_mant(pm);
       le += __builtin_amdgcn_frexp_exp(pm);
     }
-    // the decays of the next TOA: phase A, their only reader, ran before the
-    // first barrier of this TOA and runs again after the next one
-    if (tid < P && k + 1 < N) {
-      const double em = expm1_k(-gr_own * rec[k + 1].dt);
-      s_ph[tid] = 1.0 + em;
-      s_qa[tid] = vr_own * (-em * (2.0 + em));
+    // the decays of the TOA after next, into the buffer that TOA k - 1 used:
+    // its readers (phase A of k - 1) are behind this TOA's barrier, and the
+    // TOA after next reads it after the next TOA's barrier
+    if (tid < P && k + 2 < N) {
+      const double em = expm1_k(-gr_own * rec[k + 2].dt);
+      s_ph[(k + 2) % 3][tid] = 1.0 + em;
+      s_qa[(k + 2) % 3][tid] = vr_own * (-em * (2.0 + em));
     }
-    __syncthreads();
   }
   if (tid == 0) {
     if (s_pnf) st = kNonFinite;
