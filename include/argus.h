@@ -242,7 +242,8 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
  * information of the later TOAs about that state. The first call per sample
  * count times one wave per (64-sample tile, pulsar) against a time-parallel
  * form (each pulsar's stream in chunks reversed at once from chained chunk
- * summaries) and keeps the faster; the environment variable ARGUS_SMOOTH =
+ * summaries; skipped when its checkpoint store does not fit in device
+ * memory) and keeps the faster; the environment variable ARGUS_SMOOTH =
  * seq | tp2 | tp4 | tp8 | tp16 forces a form (any other value:
  * ARGUS_E_INVAL). The time-parallel form keeps a checkpoint before every
  * fourth TOA (448 B per four TOAs and sample; model 4: 640 B). Model 3

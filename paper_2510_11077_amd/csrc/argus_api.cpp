@@ -41,6 +41,7 @@ int DevBuf::alloc(size_t nbytes) {
   hipError_t e = hipMalloc(&p, nbytes);
   if (e != hipSuccess) {
     p = nullptr;
+    (void)hipGetLastError();  // a later launch check must not see this failure
     return fail(ARGUS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
   bytes = nbytes;

@@ -3180,6 +3180,19 @@ int smooth_states(argus_dataset* ds, const double* theta, int64_t S, double* mea
         if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(ARGUS_E_HIP, "t");
         if (!rc) m = std::min(m, ms);
       }
+      if (rc == ARGUS_E_NOMEM && nw > 1) {
+        // the time-parallel form's checkpoint store did not fit: drop the
+        // form (its buffers too) and keep timing the others
+        w->tp_ck.release();
+        w->tp_sum.release();
+        w->tp_adj.release();
+        w->tp_built_k = 0;
+        char line[96];
+        std::snprintf(line, sizeof line, "  smoother tp%d: not enough device memory\n", nw);
+        w->smooth_log += line;
+        rc = ARGUS_OK;
+        continue;
+      }
       if (rc) break;
       char line[96];
       std::snprintf(line, sizeof line, "  smoother %s%d: %.3f ms\n", nw == 1 ? "seq" : "tp", nw,
