@@ -246,7 +246,7 @@ int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const doub
  * memory) and keeps the faster; the environment variable ARGUS_SMOOTH =
  * seq | tp2 | tp4 | tp8 | tp16 forces a form (any other value:
  * ARGUS_E_INVAL). The time-parallel form keeps a checkpoint before every
- * fourth TOA (448 B per four TOAs and sample; model 4: 640 B). Model 3
+ * fourth TOA (112 B per four TOAs and sample; model 4: 160 B). Model 3
  * returns ARGUS_E_UNSUPPORTED; N*nc*S above 2^40 elements, or a pulsar with
  * more than 33,554,431 TOAs, returns ARGUS_E_UNSUPPORTED. */
 int argus_smooth(argus_dataset_t ds, const double* theta, int64_t S, double* mean,

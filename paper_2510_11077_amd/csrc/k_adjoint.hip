@@ -631,8 +631,8 @@ __global__ void __launch_bounds__(256) k_adjoint(AdjArgs a) {
 // forward pass over N and a reverse pass over about N / nch. This form keeps
 // a checkpoint before every fourth TOA (the level-1 stride is 4, a segment is
 // one reverse piece), so the reverse sweep recomputes no segment and needs no
-// level-2 scratch; the store takes 448 B per four TOAs and sample (model 4:
-// 640 B).
+// level-2 scratch; the store takes 112 B per four TOAs and sample (model 4:
+// 160 B).
 constexpr int kSum = 30;  // a chunk summary: U (16, row major), phi (4), Om (10)
 
 __host__ __device__ constexpr int si4(int i, int j) {

@@ -242,6 +242,25 @@ def test_joint_cfg3_sampled(argus, orc):
     assert np.isfinite(ll.cpu().numpy()).all()
 
 
+def test_joint_cfg3_blocked_against_sequential(argus, monkeypatch):
+    """Full cfg3 (20 pulsars x 1000 TOAs, 256 samples): the blocked kernel
+    (16-TOA elimination, MFMA downdate) against the sequential kernel (one
+    TOA at a time; its own parity with the oracle is tested above) on every
+    sample. The two are different fp64 algebra for the same recursion; the
+    bound is the oracle tolerance of this module."""
+    import torch
+    d = pi.make_config("cfg3")
+    th = dev(pi.sample_theta(d, pi.N_SAMPLES["cfg3"], pi.THETA_SEED["cfg3"]))
+    ds = argus.Dataset(d)
+    monkeypatch.delenv("ARGUS_JOINT", raising=False)
+    ll_b, st_b = ds.loglike(th)
+    ll_b, st_b = ll_b.clone(), st_b.clone()
+    monkeypatch.setenv("ARGUS_JOINT", "seq")
+    ll_s, st_s = ds.loglike(th)
+    assert torch.equal(st_b, st_s) and bool((st_b == 0).all())
+    check(ll_b.cpu().numpy(), st_b.cpu().numpy(), ll_s.cpu().numpy(), st_s.cpu().numpy())
+
+
 @pytest.mark.parametrize("counts", [[1], [9, 8], [5, 0, 12], [3] * 22])
 def test_joint_block_edges(argus, orc, counts, joint_form):
     """Stream lengths around the 16-TOA block size, an empty pulsar, and the
