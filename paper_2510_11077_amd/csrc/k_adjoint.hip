@@ -1202,6 +1202,158 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
 constexpr int kPcSteps = 4;
 constexpr int kPcVals = 12;
 
+// What a consumer wave of k_tangent_pc needs from its workgroup.
+struct TanPcCtx {
+  const TanArgs* a;
+  const double* ring;
+  int N, nblk, kb, p;
+  int64_t s;
+  bool valid;
+  double vr, gr, vc, t2, equad2, gm1;
+};
+
+// The per-TOA values shared by a consumer's directions.
+struct TanPcTOA {
+  double dt, phc, qcu, s2, ph, ph2, qfac, xa0, fpra, fpfa, fpaa, fpga;
+  double kr, kf, ka, kg, e, inv, ei, hS;
+};
+
+// One TOA of model-2 tangent direction DIR (0 log10 sigma_red, 1
+// log10 gamma_red, 2 EFAC, 3 log10 EQUAD, 4 log10 A, 5 gamma) with its
+// source src (the derivative of the red variance, of the white variance's
+// EFAC or EQUAD part, or of the common variance) and, for DIR 1, srate (of
+// the red rate). Terms whose source is zero for DIR are left out at compile
+// time: they add exact zeros, so the results equal those of the generic
+// step (tangent_unit).
+template <int DIR>
+__device__ __forceinline__ void tan_dir_step(Tan& d, double src, double srate,
+                                             const TanPcTOA& c, double vr) {
+  constexpr bool HV = DIR <= 1, HG = DIR == 1, HR = DIR == 2, HQ = DIR == 3, HC = DIR >= 4;
+  const double dt = c.dt, ph = c.ph, phc = c.phc;
+  const double dph = HG ? -dt * ph * srate : 0.0;
+  const double dxr = fma(dt, d.xf, d.xr), dxf = d.xf;
+  const double dxa = HG ? fma(ph, d.xa, dph * c.xa0) : ph * d.xa, dxg = phc * d.xg;
+  const Cov4& D0 = d.P;
+  Cov4 Dm;
+  const double drf1 = fma(dt, D0.ff, D0.rf);
+  Dm.rr = fma(dt, D0.rf + drf1, D0.rr);
+  Dm.rf = drf1;
+  Dm.ff = D0.ff;
+  const double ra0 = fma(dt, D0.fa, D0.ra);
+  Dm.ra = HG ? fma(ph, ra0, dph * c.fpra) : ph * ra0;
+  Dm.fa = HG ? fma(ph, D0.fa, dph * c.fpfa) : ph * D0.fa;
+  if constexpr (HG) {
+    const double dqa = fma(src, c.qfac, -2.0 * vr * ph * dph);
+    Dm.aa = fma(c.ph2, D0.aa, fma(2.0 * dph, c.fpaa, dqa));
+  } else if constexpr (HV) {
+    Dm.aa = fma(c.ph2, D0.aa, src * c.qfac);
+  } else {
+    Dm.aa = c.ph2 * D0.aa;
+  }
+  Dm.rg = phc * fma(dt, D0.fg, D0.rg);
+  Dm.fg = phc * D0.fg;
+  Dm.ag = HG ? fma(ph * phc, D0.ag, dph * c.fpga) : (ph * phc) * D0.ag;
+  Dm.gg = HC ? fma(phc * phc, D0.gg, src * c.qcu) : (phc * phc) * D0.gg;
+  const double de = -(dxr + dxa + dxg);
+  const double dur = Dm.rr + Dm.ra + Dm.rg, duf = Dm.rf + Dm.fa + Dm.fg;
+  const double dua = Dm.ra + Dm.aa + Dm.ag, dug = Dm.rg + Dm.ag + Dm.gg;
+  double dS = (dur + dua + dug);
+  if constexpr (HR) dS += src * c.s2;
+  if constexpr (HQ) dS += src;
+  const double inv = c.inv, kr = c.kr, kf = c.kf, ka = c.ka, kg = c.kg, e = c.e;
+  const double dkr = (dur - kr * dS) * inv, dkf = (duf - kf * dS) * inv;
+  const double dka = (dua - ka * dS) * inv, dkg = (dug - kg * dS) * inv;
+  d.xr = fma(dkr, e, fma(kr, de, dxr));
+  d.xf = fma(dkf, e, fma(kf, de, dxf));
+  d.xa = fma(dka, e, fma(ka, de, dxa));
+  d.xg = fma(dkg, e, fma(kg, de, dxg));
+#define TAN_UPD(dp, ki, dui, kj, duj) dp = fma(dS * (ki), kj, fma(-(dui), kj, fma(-(ki), duj, dp)))
+  TAN_UPD(Dm.rr, kr, dur, kr, dur);
+  TAN_UPD(Dm.rf, kr, dur, kf, duf);
+  TAN_UPD(Dm.ff, kf, duf, kf, duf);
+  TAN_UPD(Dm.ra, kr, dur, ka, dua);
+  TAN_UPD(Dm.fa, kf, duf, ka, dua);
+  TAN_UPD(Dm.aa, ka, dua, ka, dua);
+  TAN_UPD(Dm.rg, kr, dur, kg, dug);
+  TAN_UPD(Dm.fg, kf, duf, kg, dug);
+  TAN_UPD(Dm.ag, ka, dua, kg, dug);
+  TAN_UPD(Dm.gg, kg, dug, kg, dug);
+#undef TAN_UPD
+  d.P = Dm;
+  d.dl = fma(-0.5, fma(dS, c.hS, 2.0 * c.ei * de), d.dl);
+}
+
+// The source of direction DIR for this lane (see tan_dir_step) and, for the
+// red rate, its second source.
+template <int DIR>
+__device__ __forceinline__ double tan_src(const TanPcCtx& c) {
+  if constexpr (DIR == 0) return 2.0 * kLn10 * c.vr;
+  if constexpr (DIR == 1) return -kLn10 * c.vr;
+  if constexpr (DIR == 2) return 2.0 * c.t2;
+  if constexpr (DIR == 3) return 2.0 * kLn10 * c.equad2;
+  if constexpr (DIR == 4) return 2.0 * kLn10 * c.vc;
+  return c.vc * (c.a->mc.log_fyr + c.a->mc.log_T - 1.0 / c.gm1);
+}
+
+// A consumer wave of k_tangent_pc carrying directions D0 and D1 (D1 < 0:
+// D0 alone), one ring block behind the base filter wave.
+template <int D0, int D1>
+__device__ __forceinline__ void tangent_pc_consumer(const TanPcCtx& c) {
+  const TanArgs& a = *c.a;
+  const RecPtr rec = (RecPtr)a.rec;
+  const double src0 = tan_src<D0>(c), srate0 = D0 == 1 ? kLn10 * c.gr : 0.0;
+  const double src1 = tan_src<(D1 < 0 ? 0 : D1)>(c), srate1 = D1 == 1 ? kLn10 * c.gr : 0.0;
+  // the prior's derivative: the red variance (directions 0, 1) and the
+  // common variance (4, 5) of P0
+  auto prior = [](int dir, double src) {
+    const double v = dir <= 1 ? src : 0.0, cc = dir >= 4 ? src : 0.0;
+    return Tan{0.0, 0.0, 0.0, 0.0, Cov4{0, 0, 0, 0, 0, v, 0, 0, 0, cc}, 0.0};
+  };
+  Tan t0 = prior(D0, src0), t1 = prior(D1, src1);
+  for (int blk = 0; blk <= c.nblk; ++blk) {
+    const double* rb = c.ring + ((blk - 1) & 1) * kPcSteps * kPcVals * kWave;
+#pragma unroll 1
+    for (int jj = 0; jj < kPcSteps && blk > 0; ++jj) {
+      const int k = (blk - 1) * kPcSteps + jj;
+      if (k >= c.N) break;
+      const TOARec r = load_rec(rec, c.kb + k);
+      const double* rv = rb + jj * kPcVals * kWave;
+      TanPcTOA o;
+      const double em = rv[0 * kWave];
+      o.xa0 = rv[1 * kWave];
+      const double qra = rv[2 * kWave], qfa = rv[3 * kWave], qaa = rv[4 * kWave],
+                   qag = rv[5 * kWave];
+      o.kr = rv[6 * kWave];
+      o.kf = rv[7 * kWave];
+      o.ka = rv[8 * kWave];
+      o.kg = rv[9 * kWave];
+      o.e = rv[10 * kWave];
+      o.inv = rv[11 * kWave];
+      o.dt = r.dt;
+      o.phc = r.phc;
+      o.qcu = r.qcu;
+      o.s2 = r.s2;
+      o.ph = 1.0 + em;
+      o.ph2 = o.ph * o.ph;
+      o.qfac = -em * (2.0 + em);
+      o.fpra = fma(o.dt, qfa, qra);
+      o.fpfa = qfa;
+      o.fpaa = o.ph * qaa;
+      o.fpga = o.phc * qag;
+      o.ei = o.e * o.inv;
+      o.hS = o.inv * fma(-o.e, o.ei, 1.0);
+      tan_dir_step<D0>(t0, src0, srate0, o, c.vr);
+      if constexpr (D1 >= 0) tan_dir_step<(D1 < 0 ? 0 : D1)>(t1, src1, srate1, o, c.vr);
+    }
+    __syncthreads();
+  }
+  if (c.valid) {
+    double* g = a.gpart + (int64_t)c.p * 6 * a.S + c.s;
+    g[(int64_t)D0 * a.S] = t0.dl;
+    if constexpr (D1 >= 0) g[(int64_t)D1 * a.S] = t1.dl;
+  }
+}
+
 template <int NDC>
 __global__ void __launch_bounds__(kWave * (1 + 6 / NDC)) k_tangent_pc(TanArgs a) {
   __shared__ double s_ring[2 * kPcSteps * kPcVals * kWave];
@@ -1326,95 +1478,23 @@ __global__ void __launch_bounds__(kWave * (1 + 6 / NDC)) k_tangent_pc(TanArgs a)
       a.pstat[(int64_t)p * a.S + s] = stat;
     }
   } else {
-    // ---- NDC directions per wave (the tangent part of tangent_unit)
-    constexpr int ND = NDC;
+    // ---- NDC directions per wave (the tangent part of tangent_unit), each
+    // wave's directions fixed at compile time
+    const TanPcCtx c{&a, ring, N, nblk, kb, p, s, valid, vr, gr, vc, t2, eq * eq, gm1};
     const int grp = wave - 1;
-    const double equad2 = eq * eq;
-    double sv[ND], sg[ND], sc[ND], sr2[ND], sq2[ND];
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      const int dir = grp * ND + j;
-      sv[j] = dir == 0 ? 2.0 * kLn10 * vr : (dir == 1 ? -kLn10 * vr : 0.0);
-      sg[j] = dir == 1 ? kLn10 * gr : 0.0;
-      sr2[j] = dir == 2 ? 2.0 * t2 : 0.0;
-      sq2[j] = dir == 3 ? 2.0 * kLn10 * equad2 : 0.0;
-      sc[j] = dir == 4 ? 2.0 * kLn10 * vc
-                       : (dir == 5 ? vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / gm1) : 0.0);
-    }
-    Tan tg[ND];
-#pragma unroll
-    for (int j = 0; j < ND; ++j)
-      tg[j] = Tan{0.0, 0.0, 0.0, 0.0, Cov4{0, 0, 0, 0, 0, sv[j], 0, 0, 0, sc[j]}, 0.0};
-    for (int blk = 0; blk <= nblk; ++blk) {
-      const double* rb = ring + ((blk - 1) & 1) * kPcSteps * kPcVals * kWave;
-#pragma unroll 1
-      for (int jj = 0; jj < kPcSteps && blk > 0; ++jj) {
-        const int k = (blk - 1) * kPcSteps + jj;
-        if (k >= N) break;
-        const TOARec r = load_rec(rec, kb + k);
-        const double* rv = rb + jj * kPcVals * kWave;
-        const double em = rv[0 * kWave], xa0 = rv[1 * kWave];
-        const double qra = rv[2 * kWave], qfa = rv[3 * kWave], qaa = rv[4 * kWave],
-                     qag = rv[5 * kWave];
-        const double kr = rv[6 * kWave], kf = rv[7 * kWave], ka = rv[8 * kWave],
-                     kg = rv[9 * kWave];
-        const double e = rv[10 * kWave], inv = rv[11 * kWave];
-        const double dt = r.dt, phc = r.phc;
-        const double ph = 1.0 + em, qfac = -em * (2.0 + em);
-        const double fpra = fma(dt, qfa, qra), fpfa = qfa, fpaa = ph * qaa, fpga = phc * qag;
-        const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-          Tan& d = tg[j];
-          const double dph = -dt * ph * sg[j];
-          const double dqa = fma(sv[j], qfac, -2.0 * vr * ph * dph);
-          const double dxr = fma(dt, d.xf, d.xr), dxf = d.xf;
-          const double dxa = fma(ph, d.xa, dph * xa0), dxg = phc * d.xg;
-          const Cov4& D0 = d.P;
-          Cov4 Dm;
-          const double drf1 = fma(dt, D0.ff, D0.rf);
-          Dm.rr = fma(dt, D0.rf + drf1, D0.rr);
-          Dm.rf = drf1;
-          Dm.ff = D0.ff;
-          Dm.ra = fma(ph, fma(dt, D0.fa, D0.ra), dph * fpra);
-          Dm.fa = fma(ph, D0.fa, dph * fpfa);
-          Dm.aa = fma(ph * ph, D0.aa, fma(2.0 * dph, fpaa, dqa));
-          Dm.rg = phc * fma(dt, D0.fg, D0.rg);
-          Dm.fg = phc * D0.fg;
-          Dm.ag = fma(ph * phc, D0.ag, dph * fpga);
-          Dm.gg = fma(phc * phc, D0.gg, sc[j] * r.qcu);
-          const double de = -(dxr + dxa + dxg);
-          const double dur = Dm.rr + Dm.ra + Dm.rg, duf = Dm.rf + Dm.fa + Dm.fg;
-          const double dua = Dm.ra + Dm.aa + Dm.ag, dug = Dm.rg + Dm.ag + Dm.gg;
-          const double dS = (dur + dua + dug) + fma(sr2[j], r.s2, sq2[j]);
-          const double dkr = (dur - kr * dS) * inv, dkf = (duf - kf * dS) * inv;
-          const double dka = (dua - ka * dS) * inv, dkg = (dug - kg * dS) * inv;
-          d.xr = fma(dkr, e, fma(kr, de, dxr));
-          d.xf = fma(dkf, e, fma(kf, de, dxf));
-          d.xa = fma(dka, e, fma(ka, de, dxa));
-          d.xg = fma(dkg, e, fma(kg, de, dxg));
-#define TAN_UPD(dp, ki, dui, kj, duj) dp = fma(dS * (ki), kj, fma(-(dui), kj, fma(-(ki), duj, dp)))
-          TAN_UPD(Dm.rr, kr, dur, kr, dur);
-          TAN_UPD(Dm.rf, kr, dur, kf, duf);
-          TAN_UPD(Dm.ff, kf, duf, kf, duf);
-          TAN_UPD(Dm.ra, kr, dur, ka, dua);
-          TAN_UPD(Dm.fa, kf, duf, ka, dua);
-          TAN_UPD(Dm.aa, ka, dua, ka, dua);
-          TAN_UPD(Dm.rg, kr, dur, kg, dug);
-          TAN_UPD(Dm.fg, kf, duf, kg, dug);
-          TAN_UPD(Dm.ag, ka, dua, kg, dug);
-          TAN_UPD(Dm.gg, kg, dug, kg, dug);
-#undef TAN_UPD
-          d.P = Dm;
-          d.dl = fma(-0.5, fma(dS, hS, 2.0 * ei * de), d.dl);
-        }
+    if constexpr (NDC == 2) {
+      if (grp == 0) tangent_pc_consumer<0, 1>(c);
+      else if (grp == 1) tangent_pc_consumer<2, 3>(c);
+      else tangent_pc_consumer<4, 5>(c);
+    } else {
+      switch (grp) {
+        case 0: tangent_pc_consumer<0, -1>(c); break;
+        case 1: tangent_pc_consumer<1, -1>(c); break;
+        case 2: tangent_pc_consumer<2, -1>(c); break;
+        case 3: tangent_pc_consumer<3, -1>(c); break;
+        case 4: tangent_pc_consumer<4, -1>(c); break;
+        default: tangent_pc_consumer<5, -1>(c); break;
       }
-      __syncthreads();
-    }
-    if (valid) {
-      double* g = a.gpart + (int64_t)p * 6 * a.S + s;
-#pragma unroll
-      for (int j = 0; j < ND; ++j) g[(int64_t)(grp * ND + j) * a.S] = tg[j].dl;
     }
   }
 }
