@@ -1186,19 +1186,20 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
 }
 
 // Producer/consumer form of the model-2 tangent sweep: one workgroup of
-// 1 + 6 / NDC waves per (64-sample tile, pulsar) item. Wave 0 runs the base
-// filter once and hands, for every TOA, what the differentiated step needs
-// from it (the red decay, the previous posterior's xa and a column, the
-// gain, the innovation and 1/S: kPcVals values per lane) to the other waves
-// through a double-buffered ring in LDS of kPcSteps TOAs per buffer; wave w
-// carries directions NDC (w - 1) .. NDC w - 1 of the pulsar's six. The base
-// filter then runs once per item instead of once per direction group, and
-// the serial chain of a TOA is the longer of the base step and an
-// NDC-direction tangent step instead of their sum. Barrier b of the item
-// separates the producer's writes of block b from the consumers' reads of
-// it (in the next round) and their reads of block b - 1 from the producer's
-// rewrite of that buffer; all four waves execute nblk + 1 barriers. The
-// arithmetic of each step is that of tangent_unit.
+// 1 + ceil(5 / NDC) waves per (64-sample tile, pulsar) item. Wave 0 runs the
+// base filter once and hands, for every TOA, what the differentiated step
+// needs from it (the red decay, the previous posterior's xa and a column,
+// the gain, the innovation and 1/S: kPcVals values per lane) to the other
+// waves through a double-buffered ring in LDS of kPcSteps TOAs per buffer;
+// wave w carries directions NDC (w - 1) .. NDC w - 1 of five: the pulsar's
+// four and the common variance, from which the log10 A and gamma
+// derivatives both follow. The base filter then runs once per item instead
+// of once per direction group, and the serial chain of a TOA is the longer
+// of the base step and an NDC-direction tangent step instead of their sum.
+// Barrier b of the item separates the producer's writes of block b from the
+// consumers' reads of it (in the next round) and their reads of block b - 1
+// from the producer's rewrite of that buffer; every wave executes nblk + 1
+// barriers. The arithmetic of each step is that of tangent_unit.
 constexpr int kPcSteps = 4;
 constexpr int kPcVals = 12;
 
@@ -1219,12 +1220,13 @@ struct TanPcTOA {
 };
 
 // One TOA of model-2 tangent direction DIR (0 log10 sigma_red, 1
-// log10 gamma_red, 2 EFAC, 3 log10 EQUAD, 4 log10 A, 5 gamma) with its
-// source src (the derivative of the red variance, of the white variance's
-// EFAC or EQUAD part, or of the common variance) and, for DIR 1, srate (of
-// the red rate). Terms whose source is zero for DIR are left out at compile
-// time: they add exact zeros, so the results equal those of the generic
-// step (tangent_unit).
+// log10 gamma_red, 2 EFAC, 3 log10 EQUAD, 4 ln of the common variance) with
+// its source src (the derivative of the red variance, of the white
+// variance's EFAC or EQUAD part, or of the common variance) and, for DIR 1,
+// srate (of the red rate). Terms whose source is zero for DIR are left out
+// at compile time: they add exact zeros. log10 A and gamma enter the filter
+// only through the common variance, so both of their derivatives are
+// multiples of direction 4's (see tangent_pc_consumer).
 template <int DIR>
 __device__ __forceinline__ void tan_dir_step(Tan& d, double src, double srate,
                                              const TanPcTOA& c, double vr) {
@@ -1291,8 +1293,7 @@ __device__ __forceinline__ double tan_src(const TanPcCtx& c) {
   if constexpr (DIR == 1) return -kLn10 * c.vr;
   if constexpr (DIR == 2) return 2.0 * c.t2;
   if constexpr (DIR == 3) return 2.0 * kLn10 * c.equad2;
-  if constexpr (DIR == 4) return 2.0 * kLn10 * c.vc;
-  return c.vc * (c.a->mc.log_fyr + c.a->mc.log_T - 1.0 / c.gm1);
+  return c.vc;
 }
 
 // A consumer wave of k_tangent_pc carrying directions D0 and D1 (D1 < 0:
@@ -1304,7 +1305,7 @@ __device__ __forceinline__ void tangent_pc_consumer(const TanPcCtx& c) {
   const double src0 = tan_src<D0>(c), srate0 = D0 == 1 ? kLn10 * c.gr : 0.0;
   const double src1 = tan_src<(D1 < 0 ? 0 : D1)>(c), srate1 = D1 == 1 ? kLn10 * c.gr : 0.0;
   // the prior's derivative: the red variance (directions 0, 1) and the
-  // common variance (4, 5) of P0
+  // common variance (4) of P0
   auto prior = [](int dir, double src) {
     const double v = dir <= 1 ? src : 0.0, cc = dir >= 4 ? src : 0.0;
     return Tan{0.0, 0.0, 0.0, 0.0, Cov4{0, 0, 0, 0, 0, v, 0, 0, 0, cc}, 0.0};
@@ -1349,13 +1350,21 @@ __device__ __forceinline__ void tangent_pc_consumer(const TanPcCtx& c) {
   }
   if (c.valid) {
     double* g = a.gpart + (int64_t)c.p * 6 * a.S + c.s;
-    g[(int64_t)D0 * a.S] = t0.dl;
+    if constexpr (D0 == 4) {
+      // v_c = A^2 f_yr^(gamma - 3) T^(gamma - 1) / (12 pi^2 (gamma - 1)):
+      // d ln v_c / d log10 A = 2 ln 10, d ln v_c / d gamma =
+      // ln f_yr + ln T - 1 / (gamma - 1)
+      g[4 * a.S] = 2.0 * kLn10 * t0.dl;
+      g[5 * a.S] = (a.mc.log_fyr + a.mc.log_T - 1.0 / c.gm1) * t0.dl;
+    } else {
+      g[(int64_t)D0 * a.S] = t0.dl;
+    }
     if constexpr (D1 >= 0) g[(int64_t)D1 * a.S] = t1.dl;
   }
 }
 
 template <int NDC>
-__global__ void __launch_bounds__(kWave * (1 + 6 / NDC)) k_tangent_pc(TanArgs a) {
+__global__ void __launch_bounds__(kWave * (NDC == 2 ? 4 : 6)) k_tangent_pc(TanArgs a) {
   __shared__ double s_ring[2 * kPcSteps * kPcVals * kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1485,15 +1494,14 @@ __global__ void __launch_bounds__(kWave * (1 + 6 / NDC)) k_tangent_pc(TanArgs a)
     if constexpr (NDC == 2) {
       if (grp == 0) tangent_pc_consumer<0, 1>(c);
       else if (grp == 1) tangent_pc_consumer<2, 3>(c);
-      else tangent_pc_consumer<4, 5>(c);
+      else tangent_pc_consumer<4, -1>(c);
     } else {
       switch (grp) {
         case 0: tangent_pc_consumer<0, -1>(c); break;
         case 1: tangent_pc_consumer<1, -1>(c); break;
         case 2: tangent_pc_consumer<2, -1>(c); break;
         case 3: tangent_pc_consumer<3, -1>(c); break;
-        case 4: tangent_pc_consumer<4, -1>(c); break;
-        default: tangent_pc_consumer<5, -1>(c); break;
+        default: tangent_pc_consumer<4, -1>(c); break;
       }
     }
   }
@@ -2821,13 +2829,13 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nda
   a.n_items = w->n_items;
   a.mc = ds->mc;
   if (thresh < 0) {
-    // the producer/consumer forms: one workgroup of 1 + ndir / nda waves per
-    // item (model 2: 6 directions, model 4: 8)
+    // the producer/consumer forms: one workgroup of 1 + ceil(ndir / nda)
+    // waves per item (model 2: 5 directions, model 4: 8)
     const dim3 grid((unsigned)w->n_items);
     if (ds->model == 2 && nda == 2)
       hipLaunchKernelGGL(k_tangent_pc<2>, grid, dim3(4 * kWave), 0, st, a);
     else if (ds->model == 2 && nda == 1)
-      hipLaunchKernelGGL(k_tangent_pc<1>, grid, dim3(7 * kWave), 0, st, a);
+      hipLaunchKernelGGL(k_tangent_pc<1>, grid, dim3(6 * kWave), 0, st, a);
     else if (ds->model == 4 && nda == 2)
       hipLaunchKernelGGL(k_tangent5_pc<2>, grid, dim3(5 * kWave), 0, st, a);
     else if (ds->model == 4 && nda == 1)
