@@ -1199,7 +1199,8 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
 // Barrier b of the item separates the producer's writes of block b from the
 // consumers' reads of it (in the next round) and their reads of block b - 1
 // from the producer's rewrite of that buffer; every wave executes nblk + 1
-// barriers. The arithmetic of each step is that of tangent_unit.
+// barriers. Each step differentiates the base step as tangent_unit does,
+// with the update written in fewer operations (tan_dir_step).
 constexpr int kPcSteps = 4;
 constexpr int kPcVals = 12;
 
@@ -1262,27 +1263,32 @@ __device__ __forceinline__ void tan_dir_step(Tan& d, double src, double srate,
   double dS = (dur + dua + dug);
   if constexpr (HR) dS += src * c.s2;
   if constexpr (HQ) dS += src;
-  const double inv = c.inv, kr = c.kr, kf = c.kf, ka = c.ka, kg = c.kg, e = c.e;
-  const double dkr = (dur - kr * dS) * inv, dkf = (duf - kf * dS) * inv;
-  const double dka = (dua - ka * dS) * inv, dkg = (dug - kg * dS) * inv;
-  d.xr = fma(dkr, e, fma(kr, de, dxr));
-  d.xf = fma(dkf, e, fma(kf, de, dxf));
-  d.xa = fma(dka, e, fma(ka, de, dxa));
-  d.xg = fma(dkg, e, fma(kg, de, dxg));
-#define TAN_UPD(dp, ki, dui, kj, duj) dp = fma(dS * (ki), kj, fma(-(dui), kj, fma(-(ki), duj, dp)))
-  TAN_UPD(Dm.rr, kr, dur, kr, dur);
-  TAN_UPD(Dm.rf, kr, dur, kf, duf);
-  TAN_UPD(Dm.ff, kf, duf, kf, duf);
-  TAN_UPD(Dm.ra, kr, dur, ka, dua);
-  TAN_UPD(Dm.fa, kf, duf, ka, dua);
-  TAN_UPD(Dm.aa, ka, dua, ka, dua);
-  TAN_UPD(Dm.rg, kr, dur, kg, dug);
-  TAN_UPD(Dm.fg, kf, duf, kg, dug);
-  TAN_UPD(Dm.ag, ka, dua, kg, dug);
-  TAN_UPD(Dm.gg, kg, dug, kg, dug);
+  const double kr = c.kr, kf = c.kf, ka = c.ka, kg = c.kg, ei = c.ei;
+  // x+ = x- + k e with k = u / S, so dx+ = dx- + du e / S + k (de - dS e / S)
+  const double z = fma(-dS, ei, de);
+  d.xr = fma(dur, ei, fma(kr, z, dxr));
+  d.xf = fma(duf, ei, fma(kf, z, dxf));
+  d.xa = fma(dua, ei, fma(ka, z, dxa));
+  d.xg = fma(dug, ei, fma(kg, z, dxg));
+  // P+ = P- - u u^T / S, so dP+ = dP- - du k^T - k du^T + dS k k^T, which is
+  // dP- - w k^T - k w^T with w = du - dS k / 2
+  const double hd = -0.5 * dS;
+  const double wr = fma(hd, kr, dur), wf = fma(hd, kf, duf);
+  const double wa = fma(hd, ka, dua), wg = fma(hd, kg, dug);
+#define TAN_UPD(dp, ki, wi, kj, wj) dp = fma(-(wi), kj, fma(-(ki), wj, dp))
+  TAN_UPD(Dm.rr, kr, wr, kr, wr);
+  TAN_UPD(Dm.rf, kr, wr, kf, wf);
+  TAN_UPD(Dm.ff, kf, wf, kf, wf);
+  TAN_UPD(Dm.ra, kr, wr, ka, wa);
+  TAN_UPD(Dm.fa, kf, wf, ka, wa);
+  TAN_UPD(Dm.aa, ka, wa, ka, wa);
+  TAN_UPD(Dm.rg, kr, wr, kg, wg);
+  TAN_UPD(Dm.fg, kf, wf, kg, wg);
+  TAN_UPD(Dm.ag, ka, wa, kg, wg);
+  TAN_UPD(Dm.gg, kg, wg, kg, wg);
 #undef TAN_UPD
   d.P = Dm;
-  d.dl = fma(-0.5, fma(dS, c.hS, 2.0 * c.ei * de), d.dl);
+  d.dl = fma(-0.5, fma(dS, c.hS, 2.0 * ei * de), d.dl);
 }
 
 // The source of direction DIR for this lane (see tan_dir_step) and, for the
@@ -1350,16 +1356,19 @@ __device__ __forceinline__ void tangent_pc_consumer(const TanPcCtx& c) {
   }
   if (c.valid) {
     double* g = a.gpart + (int64_t)c.p * 6 * a.S + c.s;
-    if constexpr (D0 == 4) {
-      // v_c = A^2 f_yr^(gamma - 3) T^(gamma - 1) / (12 pi^2 (gamma - 1)):
-      // d ln v_c / d log10 A = 2 ln 10, d ln v_c / d gamma =
-      // ln f_yr + ln T - 1 / (gamma - 1)
-      g[4 * a.S] = 2.0 * kLn10 * t0.dl;
-      g[5 * a.S] = (a.mc.log_fyr + a.mc.log_T - 1.0 / c.gm1) * t0.dl;
-    } else {
-      g[(int64_t)D0 * a.S] = t0.dl;
-    }
-    if constexpr (D1 >= 0) g[(int64_t)D1 * a.S] = t1.dl;
+    auto put = [&](int dir, double dl) {
+      if (dir == 4) {
+        // v_c = A^2 f_yr^(gamma - 3) T^(gamma - 1) / (12 pi^2 (gamma - 1)):
+        // d ln v_c / d log10 A = 2 ln 10, d ln v_c / d gamma =
+        // ln f_yr + ln T - 1 / (gamma - 1)
+        g[4 * a.S] = 2.0 * kLn10 * dl;
+        g[5 * a.S] = (a.mc.log_fyr + a.mc.log_T - 1.0 / c.gm1) * dl;
+      } else {
+        g[(int64_t)dir * a.S] = dl;
+      }
+    };
+    put(D0, t0.dl);
+    if constexpr (D1 >= 0) put(D1, t1.dl);
   }
 }
 
@@ -1492,9 +1501,11 @@ __global__ void __launch_bounds__(kWave * (NDC == 2 ? 4 : 6)) k_tangent_pc(TanAr
     const TanPcCtx c{&a, ring, N, nblk, kb, p, s, valid, vr, gr, vc, t2, eq * eq, gm1};
     const int grp = wave - 1;
     if constexpr (NDC == 2) {
-      if (grp == 0) tangent_pc_consumer<0, 1>(c);
-      else if (grp == 1) tangent_pc_consumer<2, 3>(c);
-      else tangent_pc_consumer<4, -1>(c);
+      // the red rate's direction costs most (its decay derivative), so it
+      // runs alone and the others pair up
+      if (grp == 0) tangent_pc_consumer<1, -1>(c);
+      else if (grp == 1) tangent_pc_consumer<0, 4>(c);
+      else tangent_pc_consumer<2, 3>(c);
     } else {
       switch (grp) {
         case 0: tangent_pc_consumer<0, -1>(c); break;

@@ -164,9 +164,10 @@ def test_tangent_direction_splits(argus, orc, nd, sweep, monkeypatch):
     uniform, and mixed (fewer directions per wave for pulsars of at least the
     threshold's TOAs; "1,3,261" puts every pulsar in the second group); "pc"
     and "pc1" are the producer/consumer forms (the base filter on one wave,
-    its per-TOA values handed through LDS to three waves of two directions,
-    or six of one), here with a pulsar of no TOAs and one of fewer TOAs than
-    a hand-over block."""
+    its per-TOA values handed through LDS to three waves (the red rate alone,
+    two pairs of directions; the common variance's tangent gives both log10 A
+    and gamma) or five of one), here with a pulsar of no TOAs and one of fewer
+    TOAs than a hand-over block."""
     if sweep != "tangent":
         pytest.skip("tangent sweep only")
     monkeypatch.setenv("ARGUS_TAN_ND", nd)
