@@ -1191,9 +1191,10 @@ __global__ void __launch_bounds__(256) k_tangent(TanArgs a) {
 // needs from it (the red decay, the previous posterior's xa and a column,
 // the gain, the innovation and 1/S: kPcVals values per lane) to the other
 // waves through a double-buffered ring in LDS of kPcSteps TOAs per buffer;
-// wave w carries directions NDC (w - 1) .. NDC w - 1 of five: the pulsar's
-// four and the common variance, from which the log10 A and gamma
-// derivatives both follow. The base filter then runs once per item instead
+// the other waves carry NDC each of five directions: the pulsar's four and
+// the common variance, from which the log10 A and gamma derivatives both
+// follow (NDC = 2: the red rate alone, then (log10 sigma_red, common
+// variance) and (EFAC, EQUAD)). The base filter then runs once per item instead
 // of once per direction group, and the serial chain of a TOA is the longer
 // of the base step and an NDC-direction tangent step instead of their sum.
 // Barrier b of the item separates the producer's writes of block b from the
