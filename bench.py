@@ -532,17 +532,22 @@ def main():
         # the cost's growth with the number of TOAs (the paper: O(N) per
         # likelihood): the same 47 pulsars with every TOA count scaled by f
         # (cadence over the same span), the same 4096 samples
+        # (own output buffers: the headline's `out` is checked against the
+        # oracle at the end)
         sweep = []
+        osw = torch.empty_like(out)
+        ssw = torch.empty_like(st)
         for f in (0.25, 0.5, 1.0, 2.0):
             cnt = np.maximum(1, np.rint(np.diff(d.off) * f)).astype(np.int64)
             df = pi.make_pta("cfg2", counts=cnt)
             dsf = A.Dataset(df)
-            dsf.loglike(th, out, st)
-            msf, _ = timed(lambda: dsf.loglike(th, out, st), 10, 2, stream)
+            dsf.loglike(th, osw, ssw)
+            msf, _ = timed(lambda: dsf.loglike(th, osw, ssw), 10, 2, stream)
             sweep.append({"scale": f, "n_toa": int(df.n_toa), "longest_pulsar": int(cnt.max()),
                           "ms_per_call": msf,
                           "ns_per_toa_and_sample": msf * 1e6 / (df.n_toa * S)})
             del dsf
+        del osw, ssw
         slope = float(np.polyfit(np.log([p["n_toa"] for p in sweep]),
                                  np.log([p["ms_per_call"] for p in sweep]), 1)[0])
         extra["n_sweep_47psr_4096samples"] = {
