@@ -1769,19 +1769,210 @@ __device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, 
   }
 }
 
+// What a consumer wave of k_tangent5_pc needs from its workgroup.
+struct Tan5PcCtx {
+  const TanArgs* a;
+  const double* ring;
+  int N, nblk, kb, p;
+  int64_t s;
+  bool valid;
+  double vr, gr, vd, gd, vc, t2, equad2, gm1;
+};
+
+// One model-4 direction's tangent: x (5), P (lower triangle, 15) and logL.
+struct Tan5 {
+  double x[5], P[15], dl;
+};
+
+// One TOA of model-4 tangent direction DIR (0 log10 sigma_red, 1
+// log10 gamma_red, 2 EFAC, 3 log10 EQUAD, 4 log10 sigma_dm, 5 log10 gamma_dm,
+// 6 ln of the common variance) with its source src and, for the two rate
+// directions, srate. Terms whose source is zero for DIR are left out at
+// compile time. The update is the derivative of the base step written as in
+// tan_dir_step: dx+ = dx- + du e / S + K (de - dS e / S) and
+// dP+ = dP- - w K^T - K w^T with w = du - dS K / 2.
+template <int DIR>
+__device__ __forceinline__ void tan5_dir_step(Tan5& d, double src, double srate, double dt,
+                                              double ph, double phd, double phc, double qf,
+                                              double qfd, double qcu, double s2, double x2,
+                                              double x4, const double (&FP2)[5],
+                                              const double (&FP4)[5], const double (&K)[5],
+                                              const double (&hw)[5], double ei, double hS,
+                                              double vr, double vd) {
+  constexpr int NS = 5, NP = 15;
+  constexpr bool HV = DIR <= 1, HG = DIR == 1, HR = DIR == 2, HQ = DIR == 3;
+  constexpr bool HD = DIR == 4 || DIR == 5, HGD = DIR == 5, HC = DIR == 6;
+  const double dph = HG ? -dt * ph * srate : 0.0, dphd = HGD ? -dt * phd * srate : 0.0;
+  const double dg[NS] = {1.0, 1.0, ph, phc, phd};
+  double ddx[NS];
+  ddx[0] = fma(dt, d.x[1], d.x[0]);
+  ddx[1] = d.x[1];
+  ddx[2] = HG ? fma(ph, d.x[2], dph * x2) : ph * d.x[2];
+  ddx[3] = phc * d.x[3];
+  ddx[4] = HGD ? fma(phd, d.x[4], dphd * x4) : phd * d.x[4];
+  double FD[NS][NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    FD[0][q] = fma(dt, d.P[si5(1, q)], d.P[si5(0, q)]);
+#pragma unroll
+    for (int i = 1; i < NS; ++i) FD[i][q] = dg[i] * d.P[si5(i, q)];
+  }
+  // column i of F P for i = 2, 4 (the only ones a rate direction takes)
+  auto fpc = [&](int row, int col) { return col == 2 ? FP2[row] : FP4[row]; };
+  double D[NP];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int q = 0; q <= i; ++q) {
+      double t = q == 0 ? fma(dt, FD[i][1], FD[i][0]) : dg[q] * FD[i][q];
+      if (HG && i == 2) t = fma(dph, fpc(q, 2), t);
+      if (HGD && i == 4) t = fma(dphd, fpc(q, 4), t);
+      if (HG && q == 2) t = fma(dph, fpc(i, 2), t);
+      if (HGD && q == 4) t = fma(dphd, fpc(i, 4), t);
+      D[si5(i, q)] = t;
+    }
+  if constexpr (HG) D[si5(2, 2)] += fma(src, qf, -2.0 * vr * ph * dph);
+  else if constexpr (HV) D[si5(2, 2)] = fma(src, qf, D[si5(2, 2)]);
+  if constexpr (HC) D[si5(3, 3)] = fma(src, qcu, D[si5(3, 3)]);
+  if constexpr (HGD) D[si5(4, 4)] += fma(src, qfd, -2.0 * vd * phd * dphd);
+  else if constexpr (HD) D[si5(4, 4)] = fma(src, qfd, D[si5(4, 4)]);
+  double du[NS], de = 0.0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < NS; ++l)
+      if (h5(l)) t = fma(hw[l], D[si5(i, l)], t);
+    du[i] = t;
+    if (h5(i)) de = fma(-hw[i], ddx[i], de);
+  }
+  double dS = 0.0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    if (h5(i)) dS = fma(hw[i], du[i], dS);
+  if constexpr (HR) dS = fma(src, s2, dS);
+  if constexpr (HQ) dS += src;
+  const double z = fma(-dS, ei, de), hd = -0.5 * dS;
+  double w[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    d.x[i] = fma(du[i], ei, fma(K[i], z, ddx[i]));
+    w[i] = fma(hd, K[i], du[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int q = 0; q <= i; ++q)
+      d.P[si5(i, q)] = fma(-w[i], K[q], fma(-K[i], w[q], D[si5(i, q)]));
+  d.dl = fma(-0.5, fma(dS, hS, 2.0 * ei * de), d.dl);
+}
+
+// The source of model-4 direction DIR for this lane and, for the two rate
+// directions, the rate's own source.
+template <int DIR>
+__device__ __forceinline__ double tan5_src(const Tan5PcCtx& c) {
+  if constexpr (DIR == 0) return 2.0 * kLn10 * c.vr;
+  if constexpr (DIR == 1) return -kLn10 * c.vr;
+  if constexpr (DIR == 2) return 2.0 * c.t2;
+  if constexpr (DIR == 3) return 2.0 * kLn10 * c.equad2;
+  if constexpr (DIR == 4) return 2.0 * kLn10 * c.vd;
+  if constexpr (DIR == 5) return -kLn10 * c.vd;
+  return c.vc;
+}
+template <int DIR>
+__device__ __forceinline__ double tan5_srate(const Tan5PcCtx& c) {
+  if constexpr (DIR == 1) return kLn10 * c.gr;
+  if constexpr (DIR == 5) return kLn10 * c.gd;
+  return 0.0;
+}
+
+constexpr int kPc5Steps = 2;
+constexpr int kPc5Vals = 21;
+
+// A consumer wave of k_tangent5_pc carrying directions D0 and D1 (D1 < 0:
+// D0 alone), one ring block behind the base filter wave.
+template <int D0, int D1>
+__device__ __forceinline__ void tangent5_pc_consumer(const Tan5PcCtx& c) {
+  constexpr int NS = 5;
+  constexpr int E1 = D1 < 0 ? 0 : D1;
+  const TanArgs& a = *c.a;
+  const RecPtr rec = (RecPtr)a.rec;
+  const ConstDPtr chrom = (ConstDPtr)a.chrom;
+  const double src0 = tan5_src<D0>(c), srate0 = tan5_srate<D0>(c);
+  const double src1 = tan5_src<E1>(c), srate1 = tan5_srate<E1>(c);
+  // the prior's derivative: the red (0, 1), common (6) or DM (4, 5) variance
+  auto prior = [](int dir, double src) {
+    Tan5 t;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) t.x[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 15; ++i) t.P[i] = 0.0;
+    t.P[si5(2, 2)] = dir <= 1 ? src : 0.0;
+    t.P[si5(3, 3)] = dir == 6 ? src : 0.0;
+    t.P[si5(4, 4)] = dir == 4 || dir == 5 ? src : 0.0;
+    t.dl = 0.0;
+    return t;
+  };
+  Tan5 t0 = prior(D0, src0), t1 = prior(E1, src1);
+  for (int blk = 0; blk <= c.nblk; ++blk) {
+    const double* rb = c.ring + ((blk - 1) & 1) * kPc5Steps * kPc5Vals * kWave;
+#pragma unroll 1
+    for (int jj = 0; jj < kPc5Steps && blk > 0; ++jj) {
+      const int k = (blk - 1) * kPc5Steps + jj;
+      if (k >= c.N) break;
+      const TOARec r = load_rec(rec, c.kb + k);
+      const double cf = chrom[c.kb + k];
+      const double* rv = rb + jj * kPc5Vals * kWave;
+      const double em = rv[0 * kWave], emd = rv[1 * kWave];
+      const double x2 = rv[2 * kWave], x4 = rv[3 * kWave];
+      double FP2[NS], FP4[NS], K[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        FP2[i] = rv[(4 + i) * kWave];
+        FP4[i] = rv[(9 + i) * kWave];
+        K[i] = rv[(14 + i) * kWave];
+      }
+      const double e = rv[19 * kWave], inv = rv[20 * kWave];
+      const double ph = 1.0 + em, phd = 1.0 + emd;
+      const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
+      const double hw[NS] = {1.0, 0.0, 1.0, 1.0, cf};
+      const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);
+      tan5_dir_step<D0>(t0, src0, srate0, r.dt, ph, phd, r.phc, qf, qfd, r.qcu, r.s2, x2, x4,
+                        FP2, FP4, K, hw, ei, hS, c.vr, c.vd);
+      if constexpr (D1 >= 0)
+        tan5_dir_step<E1>(t1, src1, srate1, r.dt, ph, phd, r.phc, qf, qfd, r.qcu, r.s2, x2, x4,
+                          FP2, FP4, K, hw, ei, hS, c.vr, c.vd);
+    }
+    __syncthreads();
+  }
+  if (c.valid) {
+    double* g = a.gpart + (int64_t)c.p * 8 * a.S + c.s;
+    auto put = [&](int dir, double dl) {
+      if (dir == 6) {
+        // log10 A and gamma enter only through v_c (as in model 2)
+        g[6 * a.S] = 2.0 * kLn10 * dl;
+        g[7 * a.S] = (a.mc.log_fyr + a.mc.log_T - 1.0 / c.gm1) * dl;
+      } else {
+        g[(int64_t)dir * a.S] = dl;
+      }
+    };
+    put(D0, t0.dl);
+    if constexpr (D1 >= 0) put(D1, t1.dl);
+  }
+}
+
 // Work units of model 4, as k_tangent: each unit carries NDA or NDB.
 // Producer/consumer form of the model-4 tangent sweep, as k_tangent_pc: one
-// workgroup of 1 + 8 / NDC waves per item; wave 0 runs the 5-state base
+// workgroup of 1 + ceil(7 / NDC) waves per item; wave 0 runs the 5-state base
 // filter once and hands per TOA the red and DM decays, the previous
 // posterior's a and m states, the a and m columns of F P, the gain, the
 // innovation and 1/S (kPc5Vals values per lane) through a double-buffered
 // LDS ring of kPc5Steps TOAs per buffer to waves of NDC directions each.
-// The arithmetic of each step is that of tangent5_unit.
-constexpr int kPc5Steps = 2;
-constexpr int kPc5Vals = 21;
+// Each consumer step differentiates the base step (tan5_dir_step).
 
 template <int NDC>
-__global__ void __launch_bounds__(kWave * (1 + 8 / NDC)) k_tangent5_pc(TanArgs a) {
+__global__ void __launch_bounds__(kWave * (NDC == 2 ? 5 : 8))
+__attribute__((amdgpu_waves_per_eu(NDC == 2 ? 3 : 1))) k_tangent5_pc(TanArgs a) {
   constexpr int NS = 5, NP = 15;
   __shared__ double s_ring[2 * kPc5Steps * kPc5Vals * kWave];
   const int lane = threadIdx.x & (kWave - 1);
@@ -1942,126 +2133,28 @@ __global__ void __launch_bounds__(kWave * (1 + 8 / NDC)) k_tangent5_pc(TanArgs a
       a.pstat[(int64_t)p * a.S + s] = stat;
     }
   } else {
-    // ---- NDC directions per wave (the tangent part of tangent5_unit)
-    constexpr int ND = NDC;
+    // ---- NDC directions per wave, fixed at compile time: seven
+    // directions (log10 A and gamma both from the common variance's)
+    const Tan5PcCtx cx{&a, ring, N, nblk, kb, p, s, valid, vr, gr, vd, gd, vc, t2, equad2, gm1};
     const int grp = wave - 1;
-    double sv[ND], sg[ND], sc[ND], sd[ND], sgd[ND], sr2[ND], sq2[ND];
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      const int dir = grp * ND + j;
-      sv[j] = dir == 0 ? 2.0 * kLn10 * vr : (dir == 1 ? -kLn10 * vr : 0.0);
-      sg[j] = dir == 1 ? kLn10 * gr : 0.0;
-      sr2[j] = dir == 2 ? 2.0 * t2 : 0.0;
-      sq2[j] = dir == 3 ? 2.0 * kLn10 * equad2 : 0.0;
-      sd[j] = dir == 4 ? 2.0 * kLn10 * vd : (dir == 5 ? -kLn10 * vd : 0.0);
-      sgd[j] = dir == 5 ? kLn10 * gd : 0.0;
-      sc[j] = dir == 6 ? 2.0 * kLn10 * vc
-                       : (dir == 7 ? vc * (a.mc.log_fyr + a.mc.log_T - 1.0 / gm1) : 0.0);
-    }
-    double dx[ND][NS], dP[ND][NP], dl[ND];
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) dx[j][i] = 0.0;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) dP[j][i] = 0.0;
-      dP[j][si5(2, 2)] = sv[j];
-      dP[j][si5(3, 3)] = sc[j];
-      dP[j][si5(4, 4)] = sd[j];
-      dl[j] = 0.0;
-    }
-    for (int blk = 0; blk <= nblk; ++blk) {
-      const double* rb = ring + ((blk - 1) & 1) * kPc5Steps * kPc5Vals * kWave;
-#pragma unroll 1
-      for (int jj = 0; jj < kPc5Steps && blk > 0; ++jj) {
-        const int k = (blk - 1) * kPc5Steps + jj;
-        if (k >= N) break;
-        const TOARec r = load_rec(rec, kb + k);
-        const double c = chrom[kb + k];
-        const double* rv = rb + jj * kPc5Vals * kWave;
-        const double em = rv[0 * kWave], emd = rv[1 * kWave];
-        const double x2 = rv[2 * kWave], x4 = rv[3 * kWave];
-        double FP2[NS], FP4[NS], K[NS];
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          FP2[i] = rv[(4 + i) * kWave];
-          FP4[i] = rv[(9 + i) * kWave];
-          K[i] = rv[(14 + i) * kWave];
-        }
-        const double e = rv[19 * kWave], inv = rv[20 * kWave];
-        const double dt = r.dt;
-        const double ph = 1.0 + em, phd = 1.0 + emd, phc = r.phc;
-        const double qf = -em * (2.0 + em), qfd = -emd * (2.0 + emd);
-        const double dg[NS] = {1.0, 1.0, ph, phc, phd};
-        const double hw[NS] = {1.0, 0.0, 1.0, 1.0, c};
-        const double ei = e * inv, hS = inv * fma(-e, ei, 1.0);
-        // column i of F P for i = 2, 4 (the only ones the tangent takes)
-        auto fpc = [&](int row, int col) { return col == 2 ? FP2[row] : FP4[row]; };
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-          const double dph = -dt * ph * sg[j], dphd = -dt * phd * sgd[j];
-          const double ddg[NS] = {0.0, 0.0, dph, 0.0, dphd};
-          double ddx[NS];
-          ddx[0] = fma(dt, dx[j][1], dx[j][0]);
-          ddx[1] = dx[j][1];
-          ddx[2] = fma(ph, dx[j][2], dph * x2);
-          ddx[3] = phc * dx[j][3];
-          ddx[4] = fma(phd, dx[j][4], dphd * x4);
-          double FD[NS][NS];
-#pragma unroll
-          for (int q = 0; q < NS; ++q) {
-            FD[0][q] = fma(dt, dP[j][si5(1, q)], dP[j][si5(0, q)]);
-#pragma unroll
-            for (int i = 1; i < NS; ++i) FD[i][q] = dg[i] * dP[j][si5(i, q)];
-          }
-          double D[NP];
-#pragma unroll
-          for (int i = 0; i < NS; ++i)
-#pragma unroll
-            for (int q = 0; q <= i; ++q) {
-              double t = q == 0 ? fma(dt, FD[i][1], FD[i][0]) : dg[q] * FD[i][q];
-              if (i == 2 || i == 4) t = fma(ddg[i], fpc(q, i), t);
-              if (q == 2 || q == 4) t = fma(ddg[q], fpc(i, q), t);
-              D[si5(i, q)] = t;
-            }
-          D[si5(2, 2)] += fma(sv[j], qf, -2.0 * vr * ph * dph);
-          D[si5(3, 3)] = fma(sc[j], r.qcu, D[si5(3, 3)]);
-          D[si5(4, 4)] += fma(sd[j], qfd, -2.0 * vd * phd * dphd);
-          double du[NS], de = 0.0;
-#pragma unroll
-          for (int i = 0; i < NS; ++i) {
-            double t = 0.0;
-#pragma unroll
-            for (int l = 0; l < NS; ++l)
-              if (h5(l)) t = fma(hw[l], D[si5(i, l)], t);
-            du[i] = t;
-            if (h5(i)) de = fma(-hw[i], ddx[i], de);
-          }
-          double hdu = 0.0;
-#pragma unroll
-          for (int i = 0; i < NS; ++i)
-            if (h5(i)) hdu = fma(hw[i], du[i], hdu);
-          const double dS = hdu + fma(sr2[j], r.s2, sq2[j]);
-#pragma unroll
-          for (int i = 0; i < NS; ++i) {
-            const double dk = fma(-K[i], dS, du[i]) * inv;
-            dx[j][i] = fma(dk, e, fma(K[i], de, ddx[i]));
-          }
-#pragma unroll
-          for (int i = 0; i < NS; ++i)
-#pragma unroll
-            for (int q = 0; q <= i; ++q)
-              dP[j][si5(i, q)] =
-                  fma(dS * K[i], K[q], fma(-du[i], K[q], fma(-K[i], du[q], D[si5(i, q)])));
-          dl[j] = fma(-0.5, fma(dS, hS, 2.0 * ei * de), dl[j]);
-        }
+    if constexpr (NDC == 2) {
+      // each rate direction (the costliest) pairs with a white-noise one
+      switch (grp) {
+        case 0: tangent5_pc_consumer<1, 2>(cx); break;
+        case 1: tangent5_pc_consumer<5, 3>(cx); break;
+        case 2: tangent5_pc_consumer<0, 4>(cx); break;
+        default: tangent5_pc_consumer<6, -1>(cx); break;
       }
-      __syncthreads();
-    }
-    if (valid) {
-      double* g = a.gpart + (int64_t)p * 8 * a.S + s;
-#pragma unroll
-      for (int j = 0; j < ND; ++j) g[(int64_t)(grp * ND + j) * a.S] = dl[j];
+    } else {
+      switch (grp) {
+        case 0: tangent5_pc_consumer<0, -1>(cx); break;
+        case 1: tangent5_pc_consumer<1, -1>(cx); break;
+        case 2: tangent5_pc_consumer<2, -1>(cx); break;
+        case 3: tangent5_pc_consumer<3, -1>(cx); break;
+        case 4: tangent5_pc_consumer<4, -1>(cx); break;
+        case 5: tangent5_pc_consumer<5, -1>(cx); break;
+        default: tangent5_pc_consumer<6, -1>(cx); break;
+      }
     }
   }
 }
@@ -2842,7 +2935,7 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nda
   a.mc = ds->mc;
   if (thresh < 0) {
     // the producer/consumer forms: one workgroup of 1 + ceil(ndir / nda)
-    // waves per item (model 2: 5 directions, model 4: 8)
+    // waves per item (model 2: 5 directions, model 4: 7)
     const dim3 grid((unsigned)w->n_items);
     if (ds->model == 2 && nda == 2)
       hipLaunchKernelGGL(k_tangent_pc<2>, grid, dim3(4 * kWave), 0, st, a);
@@ -2851,7 +2944,7 @@ int launch_tangent(argus_dataset* ds, Workspace* w, const double* theta, int nda
     else if (ds->model == 4 && nda == 2)
       hipLaunchKernelGGL(k_tangent5_pc<2>, grid, dim3(5 * kWave), 0, st, a);
     else if (ds->model == 4 && nda == 1)
-      hipLaunchKernelGGL(k_tangent5_pc<1>, grid, dim3(9 * kWave), 0, st, a);
+      hipLaunchKernelGGL(k_tangent5_pc<1>, grid, dim3(8 * kWave), 0, st, a);
     else
       return fail(ARGUS_E_INVAL, "unsupported tangent split");
     HIPCHK(hipGetLastError());

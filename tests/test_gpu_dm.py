@@ -109,9 +109,10 @@ def test_dm_gradient(argus, orc, nd, monkeypatch):
     """The model-4 tangent sweep (eight directions per pulsar, split over
     8 / nd waves; "a,b,t": a per wave for pulsars of at least t TOAs, b for
     the others; "pc" / "pc1": the base filter on one wave handing its
-    per-TOA values to four waves of two directions or eight of one; "" lets
-    the first call choose) against the oracle's complex-step derivative,
-    ragged pulsars and tiles."""
+    per-TOA values to four waves (three of two directions, one of the common
+    variance, whose tangent gives both log10 A and gamma) or seven of one;
+    "" lets the first call choose) against the oracle's complex-step
+    derivative, ragged pulsars and tiles."""
     if nd:
         monkeypatch.setenv("ARGUS_TAN_ND", nd)
     else:
