@@ -128,6 +128,24 @@ def test_dm_gradient(argus, orc, nd, monkeypatch):
     assert (np.abs(ll.cpu().numpy() - ref) <= TOL * np.maximum(np.abs(ref), 1)).all()
 
 
+def test_dm_gradient_full_data_sampled(argus, orc, monkeypatch):
+    """The DM gradient on all 47 pulsars (37,269 TOAs in four bands) at 1024
+    samples, the gradient benchmark's batch, in the launch the first call
+    tunes (the producer/consumer form there); the oracle's complex-step
+    derivative checks 8 rows spread over the batch."""
+    monkeypatch.delenv("ARGUS_TAN_ND", raising=False)
+    d = pi.make_config("cfg2dm")
+    th = pi.sample_theta(d, 1024, pi.THETA_SEED["cfg2dm"])
+    ds = argus.Dataset(d)
+    ll, g, st = ds.loglike_grad(dev(th))
+    assert (st.cpu().numpy() == 0).all()
+    rows = np.arange(0, 1024, 128)
+    check_grad(g.cpu().numpy()[rows], orc.grad_cs(d, d.to_canon(th[rows]), which=d.free_idx))
+    ref, _ = orc.loglike(d, d.to_canon(th[rows]))
+    got = ll.cpu().numpy()[rows]
+    assert (np.abs(got - ref) <= TOL * np.maximum(np.abs(ref), 1)).all()
+
+
 def test_dm_gradient_long_pulsar_and_free_mask(argus, orc):
     d = pi.make_pta_dm("t", n_psr=2, counts=[2000, 333], seed=57)
     d.free = np.zeros(d.truth.size, bool)
