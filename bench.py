@@ -608,6 +608,24 @@ def main():
                 log("DM smooth cpu oracle: %.4g samples/s" % (n6 / w6))
         except A.ArgusError as e:
             extra["dm_smooth_47psr_1024samples"] = "unavailable: %s" % e
+        # the DM model's gradient (tuned tangent sweep) at 1024 samples
+        try:
+            S6g = min(S6, 1024)
+            t6g = t6[:S6g].contiguous()
+            o6g = torch.empty(S6g, dtype=torch.float64, device=dev)
+            g6g = torch.empty_like(t6g)
+            s6g = torch.empty(S6g, dtype=torch.int32, device=dev)
+            ds6.loglike_grad(t6g, o6g, g6g, s6g)
+            ms6g, _ = timed(lambda: ds6.loglike_grad(t6g, o6g, g6g, s6g), 10, 2, stream)
+            extra["dm_grad_47psr_1024samples"] = {
+                "ms_per_call": ms6g, "evals_per_s": S6g / (ms6g * 1e-3),
+                "sweep": "tangent (forward-mode): " + next(
+                    (ln.split(": ", 1)[1] for ln in ds6.tune_info(S6g).split("\n")
+                     if ln.startswith("gradient:")), "tuned split")}
+            log("DM grad: %.3f ms/call (%s)" % (ms6g, extra["dm_grad_47psr_1024samples"]["sweep"]))
+            del t6g, o6g, g6g, s6g
+        except A.ArgusError as e:
+            extra["dm_grad_47psr_1024samples"] = "unavailable: %s" % e
         del ds6
 
         # joint 80-state HD model, 20 pulsars x 1000 TOAs, 256 samples

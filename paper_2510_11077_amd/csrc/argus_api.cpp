@@ -671,10 +671,8 @@ int argus_tune_info(argus_dataset_t ds, int64_t S, char* buf, int32_t len) {
   }
   if (w && w->tan_nda) {
     if (w->tan_thresh < 0)
-      std::snprintf(b, sizeof b,
-                    "gradient: tangent sweep, producer/consumer form (one base-filter wave, "
-                    "%d waves of %d directions per item)\n",
-                    (ds->model == ARGUS_M4_PSR5_DM ? 8 : 6) / w->tan_nda, w->tan_nda);
+      std::snprintf(b, sizeof b, "gradient: tangent sweep, producer/consumer form (%s per item)\n",
+                    tangent_pc_layout(ds->model, w->tan_nda));
     else if (w->tan_nda == w->tan_ndb)
       std::snprintf(b, sizeof b, "gradient: tangent sweep, %d directions per wave\n", w->tan_nda);
     else

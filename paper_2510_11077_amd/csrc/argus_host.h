@@ -33,6 +33,18 @@ int fail(int code, const std::string& msg);
 constexpr int kJointBlockedMaxPsr = 22;
 constexpr int kJointMaxPsr = 63;
 
+// The wave layout of the producer/consumer tangent sweep (k_tangent_pc,
+// k_tangent5_pc) for tuning logs: one base-filter wave, then the direction
+// waves (model 2: five directions, model 4: seven; log10 A and gamma both
+// come from the common variance's tangent).
+inline const char* tangent_pc_layout(int model, int nda) {
+  if (model == 4)
+    return nda == 2 ? "base wave + 3 waves of 2 directions + the common variance's wave"
+                    : "base wave + 7 waves of 1 direction";
+  return nda == 2 ? "base wave + the red rate's wave + 2 waves of 2 directions"
+                  : "base wave + 5 waves of 1 direction";
+}
+
 // Owning device allocation.
 struct DevBuf {
   void* p = nullptr;

@@ -3081,10 +3081,10 @@ int tangent_loglike(argus_dataset* ds, const double* theta, int64_t S, double* l
           if (rep > 0) m = std::min(m, ms);
         }
         if (rc) break;
-        char b[128];
+        char b[160];
         if (c.t < 0)
-          std::snprintf(b, sizeof b, "tangent producer/consumer (base wave + %d x %d directions): %.4f ms\n",
-                        (ds->model == 4 ? 8 : 6) / c.a, c.a, m);
+          std::snprintf(b, sizeof b, "tangent producer/consumer (%s): %.4f ms\n",
+                        tangent_pc_layout(ds->model, c.a), m);
         else if (c.a == c.b)
           std::snprintf(b, sizeof b, "tangent directions per wave %d: %.4f ms\n", c.a, m);
         else
