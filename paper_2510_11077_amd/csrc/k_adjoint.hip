@@ -1102,23 +1102,27 @@ __device__ __forceinline__ void tangent_unit(const TanArgs& a, const int lane, c
         const double dur = Dm.rr + Dm.ra + Dm.rg, duf = Dm.rf + Dm.fa + Dm.fg;
         const double dua = Dm.ra + Dm.aa + Dm.ag, dug = Dm.rg + Dm.ag + Dm.gg;
         const double dS = (dur + dua + dug) + fma(sr2[j], r.s2, sq2[j]);
-        const double dkr = (dur - kr * dS) * inv, dkf = (duf - kf * dS) * inv;
-        const double dka = (dua - ka * dS) * inv, dkg = (dug - kg * dS) * inv;
-        d.xr = fma(dkr, e, fma(kr, de, dxr));
-        d.xf = fma(dkf, e, fma(kf, de, dxf));
-        d.xa = fma(dka, e, fma(ka, de, dxa));
-        d.xg = fma(dkg, e, fma(kg, de, dxg));
-#define TAN_UPD(dp, ki, dui, kj, duj) dp = fma(dS * (ki), kj, fma(-(dui), kj, fma(-(ki), duj, dp)))
-        TAN_UPD(Dm.rr, kr, dur, kr, dur);
-        TAN_UPD(Dm.rf, kr, dur, kf, duf);
-        TAN_UPD(Dm.ff, kf, duf, kf, duf);
-        TAN_UPD(Dm.ra, kr, dur, ka, dua);
-        TAN_UPD(Dm.fa, kf, duf, ka, dua);
-        TAN_UPD(Dm.aa, ka, dua, ka, dua);
-        TAN_UPD(Dm.rg, kr, dur, kg, dug);
-        TAN_UPD(Dm.fg, kf, duf, kg, dug);
-        TAN_UPD(Dm.ag, ka, dua, kg, dug);
-        TAN_UPD(Dm.gg, kg, dug, kg, dug);
+        // x+ = x- + K e and P+ = P- - u u^T / S differentiated with no dK:
+        // dx+ = dx- + du e / S + K (de - dS e / S), dP+ = dP- - w K^T - K w^T
+        // with w = du - dS K / 2
+        const double z = fma(-dS, ei, de), hd = -0.5 * dS;
+        d.xr = fma(dur, ei, fma(kr, z, dxr));
+        d.xf = fma(duf, ei, fma(kf, z, dxf));
+        d.xa = fma(dua, ei, fma(ka, z, dxa));
+        d.xg = fma(dug, ei, fma(kg, z, dxg));
+        const double wr = fma(hd, kr, dur), wf = fma(hd, kf, duf);
+        const double wa = fma(hd, ka, dua), wg = fma(hd, kg, dug);
+#define TAN_UPD(dp, ki, wi, kj, wj) dp = fma(-(wi), kj, fma(-(ki), wj, dp))
+        TAN_UPD(Dm.rr, kr, wr, kr, wr);
+        TAN_UPD(Dm.rf, kr, wr, kf, wf);
+        TAN_UPD(Dm.ff, kf, wf, kf, wf);
+        TAN_UPD(Dm.ra, kr, wr, ka, wa);
+        TAN_UPD(Dm.fa, kf, wf, ka, wa);
+        TAN_UPD(Dm.aa, ka, wa, ka, wa);
+        TAN_UPD(Dm.rg, kr, wr, kg, wg);
+        TAN_UPD(Dm.fg, kf, wf, kg, wg);
+        TAN_UPD(Dm.ag, ka, wa, kg, wg);
+        TAN_UPD(Dm.gg, kg, wg, kg, wg);
 #undef TAN_UPD
         d.P = Dm;
         d.dl = fma(-0.5, fma(dS, hS, 2.0 * ei * de), d.dl);
@@ -1724,17 +1728,20 @@ __device__ __forceinline__ void tangent5_unit(const TanArgs& a, const int lane, 
         for (int i = 0; i < NS; ++i)
           if (h5(i)) hdu = fma(hw[i], du[i], hdu);
         const double dS = hdu + fma(sr2[j], r.s2, sq2[j]);
+        // no dK: dx+ = dx- + du e / S + K (de - dS e / S) and
+        // dP+ = dP- - w K^T - K w^T with w = du - dS K / 2
+        const double z = fma(-dS, ei, de), hd = -0.5 * dS;
+        double w[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-          const double dk = fma(-K[i], dS, du[i]) * inv;
-          dx[j][i] = fma(dk, e, fma(K[i], de, ddx[i]));
+          dx[j][i] = fma(du[i], ei, fma(K[i], z, ddx[i]));
+          w[i] = fma(hd, K[i], du[i]);
         }
 #pragma unroll
         for (int i = 0; i < NS; ++i)
 #pragma unroll
           for (int q = 0; q <= i; ++q)
-            dP[j][si5(i, q)] =
-                fma(dS * K[i], K[q], fma(-du[i], K[q], fma(-K[i], du[q], D[si5(i, q)])));
+            dP[j][si5(i, q)] = fma(-w[i], K[q], fma(-K[i], w[q], D[si5(i, q)]));
         dl[j] = fma(-0.5, fma(dS, hS, 2.0 * ei * de), dl[j]);
       }
       // base update (the likelihood kernel's Joseph form)
