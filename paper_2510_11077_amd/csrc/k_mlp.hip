@@ -888,20 +888,51 @@ __global__ void __launch_bounds__(512) k_train_update(TrainUpdArgs u) {
     const __bf16* yp = Y + (int64_t)kb * 1024 + l * 8;
     const int64_t xstep = (int64_t)NTL * 1024, ystep = (int64_t)ynb * 1024;
     const int64_t G = u.B / 64, g0 = G * q / 8, g1 = G * (q + 1) / 8;
+    // this thread's two parameters' Adam state, read now so that its latency
+    // hides behind the products
+    const int kin = layer == 1 ? d : W;
+    const int64_t off = layer == 3 ? oW3 : (layer == 2 ? oW2 : 0);
+    const int n0 = 32 * nb, k0 = 32 * kb;
+    const int kl = threadIdx.x & 31, nl = threadIdx.x >> 5;  // elements (nl, kl), (nl + 16, kl)
+    const bool own = k0 + kl < kin;
+    int64_t ix[2];
+    float mo[2] = {0.0f, 0.0f}, vo[2] = {0.0f, 0.0f}, wo[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      ix[h] = off + (int64_t)(n0 + nl + 16 * h) * kin + k0 + kl;
+      if (own && u.adam.do_update) {
+        mo[h] = u.adam.m[ix[h]];
+        vo[h] = u.adam.v[ix[h]];
+        wo[h] = u.adam.master[ix[h]];
+      }
+    }
+    // the K steps in groups of up to 16, software-pipelined: each operand
+    // register is refilled with the next group's step as soon as its MFMA
+    // has been issued, so that 16 steps' loads stay in flight
     f32x16 acc = {};
+    bf16x8 xa[16], yb[16];
+    auto load = [&](int64_t g, int ng, int e) {
+      if ((e >> 2) < ng) {
+        const int64_t st = 4 * g + e, c = st >> 1, h = st & 1;
+        xa[e] = *reinterpret_cast<const bf16x8*>(xp + c * xstep + h * 512);
+        yb[e] = *reinterpret_cast<const bf16x8*>(yp + c * ystep + h * 512);
+      }
+    };
+    if (g0 < g1) {
+      const int ng0 = (int)(g1 - g0 < 4 ? g1 - g0 : 4);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) load(g0, ng0, e);
+    }
     for (int64_t g = g0; g < g1; g += 4) {
       const int ng = (int)(g1 - g < 4 ? g1 - g : 4);
-      bf16x8 xa[16], yb[16];
+      const int64_t gn = g + 4;
+      const int ngn = gn < g1 ? (int)(g1 - gn < 4 ? g1 - gn : 4) : 0;
 #pragma unroll
       for (int e = 0; e < 16; ++e)
         if ((e >> 2) < ng) {
-          const int64_t st = 4 * g + e, c = st >> 1, h = st & 1;
-          xa[e] = *reinterpret_cast<const bf16x8*>(xp + c * xstep + h * 512);
-          yb[e] = *reinterpret_cast<const bf16x8*>(yp + c * ystep + h * 512);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[e], yb[e], acc, 0, 0, 0);
+          load(gn, ngn, e);
         }
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-        if ((e >> 2) < ng) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[e], yb[e], acc, 0, 0, 0);
     }
     // the eight partial tiles meet in LDS; each thread then forms two of the
     // tile's gradients (partials added in wave order) and updates them
@@ -909,13 +940,8 @@ __global__ void __launch_bounds__(512) k_train_update(TrainUpdArgs u) {
     for (int r = 0; r < 16; ++r)
       s_tile[q][(8 * (r >> 2) + 4 * (l >> 5) + (r & 3)) * 33 + (l & 31)] = acc[r];
     __syncthreads();
-    const int kin = layer == 1 ? d : W;
-    const int64_t off = layer == 3 ? oW3 : (layer == 2 ? oW2 : 0);
-    const int n0 = 32 * nb, k0 = 32 * kb;
-    const int kl = threadIdx.x & 31, nl = threadIdx.x >> 5;  // elements (nl, kl), (nl + 16, kl)
-    if (k0 + kl >= kin) return;
+    if (!own) return;
     float gv[2];
-    int64_t ix[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = (nl + 16 * h) * 33 + kl;
@@ -923,17 +949,9 @@ __global__ void __launch_bounds__(512) k_train_update(TrainUpdArgs u) {
 #pragma unroll
       for (int qq = 1; qq < 8; ++qq) sum += s_tile[qq][e];
       gv[h] = sum;
-      ix[h] = off + (int64_t)(n0 + nl + 16 * h) * kin + k0 + kl;
     }
     const AdamArgs& a = u.adam;
     if (a.do_update) {
-      float mo[2], vo[2], wo[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        mo[h] = a.m[ix[h]];
-        vo[h] = a.v[ix[h]];
-        wo[h] = a.master[ix[h]];
-      }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         u.g[ix[h]] = gv[h];
