@@ -24,8 +24,8 @@ if ROOT not in sys.path:
 
 METRIC = "logL evals/s (47-psr batched Kalman, FP64); +grad; surrogate at |ΔlogL|≤0.1"
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
-# Algorithmic FP64 work of one model-2 filter step as the survey's roofline
-# plan counts it (structured Joseph update of 10 entries x 8, predict 35,
+# Algorithmic FP64 work of one model-2 filter step as the roofline plan
+# counts it (structured Joseph update of 10 entries x 8, predict 35,
 # discretisation 15, innovation 14, misc; a transcendental or division
 # counts 1): the figure `roofline` uses.
 FLOP_PER_STEP_M2_PLAN = 175
@@ -365,9 +365,9 @@ def main():
                     help="also run one plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(samples shard trivially across GPUs; see the design notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(samples shard trivially across GPUs). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
