@@ -213,8 +213,9 @@ int argus_hmc_step(argus_dataset_t ds, int64_t S, int32_t n_leapfrog, const doub
  *   leapfrog steps taken, 1 if the transition ended on a divergence)
  *   accept_stat: dev [S] mean of min(1, exp(H0 - H)) over the leaves, or NULL
  * max_depth in [1, 10]. All chains step together: each leaf is one batched
- * gradient evaluation; the call synchronises the stream once per leaf to
- * stop when no chain is still building. Allocates per-sample-count work
+ * gradient evaluation; the call synchronises the stream after every 8th
+ * leaf of a subtree and at its end, to stop when no chain is still
+ * building. Allocates per-sample-count work
  * buffers on the first call for S (and for a larger max_depth). */
 int argus_nuts_step(argus_dataset_t ds, int64_t S, int32_t max_depth, const double* eps,
                     const double* inv_mass, const double* lo, const double* hi,

@@ -26,8 +26,8 @@
 // post-order of the recursive build. Each stack entry keeps its log weight,
 // momentum sum, first-leaf momentum and proposal (position, gradient,
 // logL). Kernels run one wave per chain, lanes over parameters; the host
-// reads back the number of chains still building once per leaf to stop
-// early.
+// reads back the number of chains still building after every 8th leaf of a
+// subtree and at its end, and stops the subtree once none is left.
 #include <cmath>
 
 #include "argus_host.h"
@@ -395,9 +395,14 @@ int nuts_step(argus_dataset* ds, int64_t S, int32_t max_depth, const double* eps
       hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, a.active);
       hipLaunchKernelGGL(k_nuts_leaf, grid, block, 0, st, a);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(&n_active, a.active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (n_active == 0) break;
+      // the count is read back after every 8th leaf and at the subtree's
+      // end only: a read-back stalls the host until the stream drains, and
+      // the leaves a stopped chain is carried through change nothing for it
+      if (i == leaves - 1 || ((i + 1) & 7) == 0) {
+        HIPCHK(hipMemcpyAsync(&n_active, a.active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (n_active == 0) break;
+      }
     }
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, a.active);
     hipLaunchKernelGGL(k_nuts_top, grid, block, 0, st, a);
