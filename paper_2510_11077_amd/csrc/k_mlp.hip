@@ -1017,10 +1017,16 @@ __device__ __forceinline__ bool stage1_ok(int64_t i, const double* theta_prop, i
                                           const double* lo, const double* hi,
                                           const double* lh_cur, const double* lh_prop,
                                           const double* logu1) {
+  // every test evaluated without an early exit, so that all the row's loads
+  // are in flight together (a NaN fails both comparisons, as before)
   const double* t = theta_prop + i * d;
-  for (int k = 0; k < d; ++k)
-    if (!(t[k] >= lo[k] && t[k] <= hi[k])) return false;
-  return logu1[i] < lh_prop[i] - lh_cur[i];
+  bool in = logu1[i] < lh_prop[i] - lh_cur[i];
+#pragma unroll 4
+  for (int k = 0; k < d; ++k) {
+    const double x = t[k];
+    in = in & (x >= lo[k]) & (x <= hi[k]);
+  }
+  return in;
 }
 
 struct DA1Args {
