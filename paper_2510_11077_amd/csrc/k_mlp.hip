@@ -1133,7 +1133,19 @@ __global__ void k_da2(DA2Args a) {
   const int64_t i = a.idx[j];
   const double la = (a.ll_prop[j] - a.ll_cur[i]) - (a.lh_prop[i] - a.lh_cur[i]);
   if (a.logu2[i] < la) {
-    for (int k = 0; k < a.d; ++k) a.theta_cur[i * a.d + k] = a.theta_prop[i * a.d + k];
+    // the row in chunks of 8: all of a chunk's loads, then its stores (an
+    // element-wise copy would wait for each store before the next load)
+    const double* src = a.theta_prop + i * a.d;
+    double* dst = a.theta_cur + i * a.d;
+    for (int k0 = 0; k0 < a.d; k0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < a.d) v[q] = src[k0 + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < a.d) dst[k0 + q] = v[q];
+    }
     a.ll_cur[i] = a.ll_prop[j];
     a.lh_cur[i] = a.lh_prop[i];
     a.acc[i] += 1;
