@@ -328,6 +328,30 @@ def test_power_law_variance(oracle_mod, la, g):
         assert abs(np.sqrt(v) - 1.0e-7) / 1e-7 < 0.01
 
 
+@pytest.mark.parametrize("model", [2, 4])
+def test_common_amplitude_and_index_act_through_the_variance(oracle_mod, model):
+    """log10 A and gamma of the common process enter the model only through
+    its variance v_c = A^2 f_yr^(gamma - 3) T^(gamma - 1) / (12 pi^2 (gamma - 1))
+    (the power-law common process of the Statement of Need, mapped as in
+    reading R5), so dlogL/dgamma = dlogL/dlog10A (ln f_yr + ln T -
+    1 / (gamma - 1)) / (2 ln 10) for every sample: the identity by which the
+    GPU tangent sweeps take both derivatives from one tangent. Checked on the
+    oracle's complex-step derivatives, which take the two separately."""
+    if model == 2:
+        d = small_pta(counts=(40, 25, 33))
+        per = 4
+    else:
+        d = pi.make_pta_dm("t4", n_psr=3, counts=[40, 25, 33], seed=8)
+        per = 6
+    c = d.to_canon(moderate_theta(d, 3, 23))
+    ia, ig = per * d.n_psr, per * d.n_psr + 1
+    g = oracle_mod.grad_cs(d, c, which=[ia, ig])
+    gam = c[:, ig]
+    fac = (np.log(1.0 / pi.YEAR) + np.log(d.t_span) - 1.0 / (gam - 1.0)) / (2.0 * np.log(10.0))
+    assert np.all(np.abs(g[:, 0]) > 0)
+    assert np.allclose(g[:, 1], g[:, 0] * fac, rtol=1e-9, atol=0)
+
+
 # ---------------------------------------------------- 6. gradient
 @pytest.mark.parametrize("model", [1, 2, 3])
 def test_complex_step_gradient_vs_dense(oracle_mod, model):
